@@ -1,0 +1,132 @@
+"""Pins for the oracle's multigrid pieces (Sec. 6 transfers and level
+operators; Sec. 7 Chebyshev smoother, eigenvalue estimate, PCG)."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spl
+
+import workloads as W
+from oracle import fe, gmg, rng
+
+
+@pytest.mark.parametrize("dim,p", [(2, 1), (2, 3), (3, 2), (2, 4)])
+def test_prolongation_reproduces_coarse_polynomials(dim, p):
+    c, f = fe.Mesh(dim, 2, p), fe.Mesh(dim, 4, p)
+    P = gmg.prolongation(c, f)
+    I = gmg.interpolation(f, c)
+    r = np.random.default_rng(0)
+    coef = r.standard_normal((dim,) + (p + 1,) * dim)
+    def field(X):
+        out = np.zeros((X.shape[0], dim))
+        for comp in range(dim):
+            for idx in np.ndindex(*coef.shape[1:]):
+                out[:, comp] += coef[(comp,) + idx] * np.prod([X[:, k] ** idx[k] for k in range(dim)], axis=0)
+        return np.ascontiguousarray(out.T.reshape(-1))
+    uc, uf = field(c.node_coords()), field(f.node_coords())
+    np.testing.assert_allclose(P @ uc, uf, atol=1e-12)
+    np.testing.assert_allclose(I @ uf, uc, atol=1e-12)
+    np.testing.assert_allclose((I @ P).toarray(), np.eye(c.n_dofs), atol=1e-13)
+
+
+@pytest.mark.parametrize("dim,p", [(2, 2), (3, 1), (3, 2), (2, 3)])
+def test_galerkin_identity_affine_homogeneous(dim, p):
+    """P^T K_f P = K_c when u is affine and the body homogeneous: the coarse
+    space is contained in the fine one and q = p+1 integrates the (polynomial)
+    integrands exactly."""
+    c, f = fe.Mesh(dim, 1 if dim == 3 else 2, p), fe.Mesh(dim, 2 if dim == 3 else 4, p)
+    mat = fe.Material([1.1], [1.6])
+    F0 = np.eye(dim) + 0.15 * np.random.default_rng(2).standard_normal((dim, dim))
+    def affine(m):
+        X = m.node_coords()
+        return np.ascontiguousarray((X @ (F0 - np.eye(dim)).T).T.reshape(-1))
+    Kc = fe.tangent_matrix(c, mat, affine(c)).toarray()
+    Kf = fe.tangent_matrix(f, mat, affine(f))
+    P = gmg.prolongation(c, f)
+    np.testing.assert_allclose((P.T @ Kf @ P).toarray(), Kc, atol=1e-12 * abs(Kc).max())
+
+
+def test_chebyshev_error_polynomial():
+    """On a diagonal system D^-1 A = diag(t) with x0 = 0 and f = A e, the
+    error after one degree-k application is T_k((theta - t)/delta) /
+    T_k(theta/delta) e."""
+    t = np.linspace(0.05, 2.0, 40)
+    e = np.random.default_rng(1).standard_normal(40)
+    dvals = np.linspace(1.0, 3.0, 40)
+    A = t * dvals
+    lo, hi = 0.6, 2.1
+    for k in (1, 2, 3, 4, 6):
+        x = gmg.chebyshev(lambda v: A * v, 1.0 / dvals, A * e, np.zeros(40), lo, hi, k)
+        theta, delta = 0.5 * (hi + lo), 0.5 * (hi - lo)
+        Tk = np.polynomial.chebyshev.Chebyshev.basis(k)
+        want = Tk((theta - t) / delta) / Tk(theta / delta) * e
+        np.testing.assert_allclose(e - x, want, atol=1e-12)
+
+
+def test_lanczos_estimate_vs_dense_eigensolver():
+    mu, lam = W.two_phase_material()
+    m = fe.Mesh(3, 3, 2)
+    mat = fe.Material(mu, lam, W.spheres(2, 3))
+    cons = m.constrained(W.clamp_bottom_top(3))
+    u = W.sine_field(3, m.L, 4, 0.02, kmax=1)
+    A = fe.constrain_matrix(fe.tangent_matrix(m, mat, u), cons)
+    dinv = 1.0 / A.diagonal()
+    est, its = gmg.lanczos_lambda_max(lambda v: A @ v, dinv, gmg.eig_start_vector(m.n_dofs, cons), 30)
+    s = np.sqrt(dinv)
+    true = np.linalg.eigvalsh(s[:, None] * A.toarray() * s[None, :]).max()
+    assert its == 30
+    assert est <= true * (1 + 1e-12)
+    assert est >= true * (1 - 1e-3)
+
+
+def test_splitmix64_published_vectors():
+    """SplitMix64 seeded with 1234567: first outputs as published with the
+    reference implementation (xoshiro/splitmix64.c test vector)."""
+    z = rng.splitmix64(1234567, 5)
+    assert [int(v) for v in z] == [6457827717110365317, 3203168211198807973, 9817491932198370423,
+                                    4593380528125082431, 16408922859458223821]
+
+
+def test_pcg_with_vcycle_matches_direct_solve():
+    mu, lam = W.two_phase_material()
+    mat = fe.Material(mu, lam, W.spheres(3, 3))
+    H = gmg.Hierarchy(3, 2, 2, 2, mat, W.clamp_bottom_top(3))
+    u = W.sine_field(3, H.meshes[-1].L, 4, 0.01, kmax=1)
+    u[H.cons[-1]] = 0.0
+    H.set_deformation(u)
+    b = W.normal_vector(H.meshes[-1].n_dofs, 5)
+    b[H.cons[-1]] = 0.0
+    x, it, rel = gmg.pcg(lambda v: H.A[-1] @ v, b, H.vcycle, 1e-10, 200)
+    xd = spl.spsolve(H.A[-1].tocsc(), b)
+    assert rel <= 1e-10
+    assert np.linalg.norm(x - xd) <= 1e-8 * np.linalg.norm(xd)
+    assert np.all(x[H.cons[-1]] == 0)
+
+
+def test_vcycle_is_symmetric_and_h_independent():
+    """The V-cycle is a symmetric preconditioner, and for a homogeneous body
+    the PCG iteration count does not grow under refinement (Sec. 6)."""
+    mat = fe.Material([1.0], [1.5])
+    counts = []
+    for nl in (2, 3):
+        H = gmg.Hierarchy(3, 2, 2, nl, mat, W.clamp_bottom_top(3))
+        H.set_deformation(np.zeros(H.meshes[-1].n_dofs))
+        n = H.meshes[-1].n_dofs
+        a, b = W.normal_vector(n, 1), W.normal_vector(n, 2)
+        a[H.cons[-1]] = 0
+        b[H.cons[-1]] = 0
+        assert abs(a @ H.vcycle(b) - b @ H.vcycle(a)) <= 1e-10 * abs(a @ H.vcycle(b))
+        _, it, rel = gmg.pcg(lambda v, H=H: H.A[-1] @ v, b, H.vcycle, 1e-8, 100)
+        counts.append(it)
+    assert counts[1] <= counts[0] + 1
+    assert counts[1] <= 15
+
+
+def test_level_displacements_are_nodal_interpolants():
+    mat = fe.Material([1.0], [1.5])
+    H = gmg.Hierarchy(2, 2, 2, 3, mat)
+    X = H.meshes[-1].node_coords()
+    u = np.ascontiguousarray(np.stack([np.sin(3 * X[:, 0]) * X[:, 1], X[:, 0] ** 2], 0).reshape(-1))
+    us = H.level_displacements(u)
+    for l in range(3):
+        Xl = H.meshes[l].node_coords()
+        want = np.ascontiguousarray(np.stack([np.sin(3 * Xl[:, 0]) * Xl[:, 1], Xl[:, 0] ** 2], 0).reshape(-1))
+        np.testing.assert_allclose(us[l], want, atol=1e-14)   # p = 2 nodes nest: injection

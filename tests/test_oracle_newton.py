@@ -1,0 +1,36 @@
+"""End-to-end pin of the oracle Newton + GMG-CG (Sec. 3, Sec. 6, Sec. 7):
+uniaxial stretch of a homogeneous cube on rollers has the affine exact
+solution F = diag(s, s, 1 + delta) with mu s^2 = mu - 2 lambda ln(s^2 (1 + delta))
+(lateral Kirchhoff stress tau = mu b - c1 I vanishes), which lies in the
+finite-element space, so the discrete solution equals it."""
+import numpy as np
+import pytest
+from scipy.optimize import brentq
+
+import workloads as W
+from oracle import fe, gmg, newton
+
+
+@pytest.mark.parametrize("dim,p,delta", [(3, 2, 0.1), (2, 3, -0.15), (3, 1, 0.08)])
+def test_uniaxial_stretch_closed_form(dim, p, delta):
+    mu, lam = 1.0, 1.5
+    mat = fe.Material([mu], [lam])
+    ax = dim - 1
+    mask = W.face_bits(dim, ax, 0, [ax]) | W.face_bits(dim, ax, 1, [ax])
+    for a in range(dim - 1):
+        mask |= W.face_bits(dim, a, 0, [a])
+    vals = np.zeros((2 * dim, dim))
+    vals[2 * ax + 1][ax] = delta
+    H = gmg.Hierarchy(dim, 1, p, 2, mat, mask)
+    u, recs = newton.solve(H, vals, n_steps=2)
+    s = brentq(lambda s: mu * s * s - (mu - 2 * lam * np.log(s ** (dim - 1) * (1 + delta))), 0.5, 1.5)
+    m = H.meshes[-1]
+    X = m.node_coords()
+    want = X * np.array([s - 1] * (dim - 1) + [delta])
+    np.testing.assert_allclose(u.reshape(dim, -1).T, want, atol=1e-9)
+    # reaction on the moving face: sum of unconstrained residual = P_zz * area
+    R = fe.residual(m, mat, u).reshape(dim, -1).T
+    top = np.abs(X[:, ax] - 1.0) < 1e-12
+    Pzz = (mu * (1 + delta) ** 2 - (mu - 2 * lam * np.log(s ** (dim - 1) * (1 + delta)))) / (1 + delta)
+    assert abs(R[top, ax].sum() - Pzz) < 1e-9
+    assert all(r["cg_rel"] <= 1e-8 for r in recs)
