@@ -1,0 +1,187 @@
+"""Benchmark of the matrix-free finite-strain tangent on one MI355X.
+
+Workload (the configuration the headline metric is quoted on): 3-D unit cube,
+32^3 Q2 cells (823,875 DoFs), (p+1)^3 Gauss points, compressible Neo-Hookean
+matrix (mu = 1, nu = 0.3) with 20 seeded spheres 100x stiffer, seeded smooth
+displacement of amplitude 0.1, x ~ N(0, 1).  A step is one tangent vmult
+(gather -> sum factorisation -> quadrature-point stage -> transposed sum
+factorisation -> atomic scatter) with the inputs resident in HBM.  Every
+quadrature-point policy is timed in FP64 and FP32; the best FP64 one is the
+headline value.  The roofline object describes the cell kernel of the
+headline variant, timed with HIP events on the library's stream; cpu_baseline
+times the CPU oracle on a bounded sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu]
+"""
+import argparse
+import json
+import os
+import resource
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "tangent vmult DoFs/s (FP64/FP32, Q2 3D); GMG-CG Newton-step time at 1e-8"
+HBM_PEAK_GBS = 8000.0
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
+POLICIES = {0: "recompute", 1: "cache_F", 2: "cache_T2"}
+
+# Algorithmic flop counts: minimal sum factorisation of one
+# d-component field, 4 d^2 n^(d+1), plus the quadrature-point algebra per point.
+QP_FLOPS_3D = {0: 313, 1: 307, 2: 188}
+QP_FLOPS_2D = {0: 118, 1: 116, 2: 78}
+CACHE_WORDS = {3: {0: 0, 1: 9, 2: 16}, 2: {0: 0, 1: 4, 2: 8}}
+
+
+def algorithmic_cost(dim, degree, n_cells, n_dofs, policy, word):
+    n = degree + 1
+    ncells = n_cells ** dim
+    nq = n ** dim
+    fields = 3 if policy == 0 else 2      # forward x (+ forward u), backward
+    sf = 4 * dim * dim * n ** (dim + 1)
+    qpf = (QP_FLOPS_3D if dim == 3 else QP_FLOPS_2D)[policy]
+    flops = ncells * (fields * sf + nq * qpf)
+    nbytes = 2 * word * n_dofs                        # x read once, y written once
+    if policy == 0:
+        nbytes += 8 * n_dofs if word == 8 else 4 * n_dofs   # displacement
+    nbytes += CACHE_WORDS[dim][policy] * nq * ncells * word
+    nbytes += 4 * ncells * ((nq + 31) // 32)          # material bits
+    return flops, nbytes
+
+
+def roofline(dim, degree, n_cells, n_dofs, policy, dtype, kernel_ms):
+    word = 8 if dtype == "f64" else 4
+    flops, nbytes = algorithmic_cost(dim, degree, n_cells, n_dofs, policy, word)
+    t_hbm = nbytes / (HBM_PEAK_GBS * 1e9)
+    t_alu = flops / (PEAK_TFLOPS[dtype] * 1e12)
+    s = kernel_ms * 1e-3
+    if t_hbm >= t_alu:
+        ach = nbytes / s / 1e9
+        return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                "traffic": None, "alg_bytes": nbytes, "alg_flops": flops}
+    ach = flops / s / 1e12
+    return {"bound": "alu", "achieved": ach, "peak": PEAK_TFLOPS[dtype], "unit": "TFLOP/s",
+            "frac": ach / PEAK_TFLOPS[dtype], "traffic": None, "alg_bytes": nbytes, "alg_flops": flops}
+
+
+def time_vmult(P, x, y, steps, warmup, cold=False, flush=None):
+    import torch
+    for _ in range(warmup):
+        P.tangent_vmult(x, y)
+    torch.cuda.synchronize()
+    P.timer_enable(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        if cold:
+            flush.add_(1.0)
+        P.tangent_vmult(x, y)
+    e1.record()
+    torch.cuda.synchronize()
+    kms, nl = P.timer_read()
+    P.timer_enable(False)
+    return e0.elapsed_time(e1) / steps, kms / max(nl, 1)
+
+
+def cpu_baseline(w, n_sample_cells=32768):
+    """Oracle element-by-element tangent apply over a sample of the cells."""
+    from oracle import fe
+    mesh = fe.Mesh(w["dim"], w["n_cells"], w["degree"])
+    mat = fe.Material(w["mu"], w["lam"], w["inclusions"])
+    rng = np.random.default_rng(0)
+    cells = np.sort(rng.choice(mesh.n_cells, n_sample_cells, replace=False))
+    r0 = resource.getrusage(resource.RUSAGE_SELF)
+    t0 = time.perf_counter()
+    fe.vmult_ebe(mesh, mat, w["u"], w["x"], cells=cells)
+    wall = time.perf_counter() - t0
+    r1 = resource.getrusage(resource.RUSAGE_SELF)
+    cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
+    dofs_equiv = mesh.n_dofs * n_sample_cells / mesh.n_cells
+    return {"value": dofs_equiv / wall, "unit": "DoF/s", "cores": round(cpu / wall, 1), "kind": "oracle",
+            "sample": f"oracle element-by-element FP64 tangent apply on {n_sample_cells} of {mesh.n_cells} "
+                      f"cells ({wall:.1f} s wall), scaled to DoFs of the full mesh",
+            "host_threads_available": os.cpu_count()}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--policies", default="0,1,2")
+    a = ap.parse_args(argv)
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding)",
+              file=sys.stderr)
+        return 2
+
+    import torch
+
+    import workloads as W
+    from paper_1904_13131_amd import Problem
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    w = W.config2()
+    dim, nc, deg = w["dim"], w["n_cells"], w["degree"]
+    u = torch.as_tensor(w["u"], device="cuda")
+    x64 = torch.as_tensor(w["x"], device="cuda")
+    x32 = x64.float()
+    flush = torch.zeros(128 * 1024 * 1024, dtype=torch.float32, device="cuda")   # 512 MB > MALL
+    res = {}
+    n_dofs = None
+    for pol in [int(p) for p in a.policies.split(",")]:
+        P = Problem(dim, nc, deg, mu=tuple(w["mu"]), lam=tuple(w["lam"]), inclusions=w["inclusions"], qp_policy=pol)
+        P.set_deformation(u)
+        n_dofs = P.n_dofs()
+        for dt, x in (("f64", x64), ("f32", x32)):
+            y = torch.empty_like(x)
+            ms, kms = time_vmult(P, x, y, a.steps, a.warmup)
+            _, kms_cold = time_vmult(P, x, y, max(5, a.steps // 5), 1, cold=True, flush=flush)
+            res[(pol, dt)] = dict(ms_per_step=ms, kernel_ms=kms, kernel_ms_cold=kms_cold,
+                                  dofs_per_s=n_dofs / (ms * 1e-3), kernel_dofs_per_s=n_dofs / (kms * 1e-3))
+            print(f"[bench] {POLICIES[pol]:9s} {dt}: {ms * 1e3:8.1f} us/vmult, kernel {kms * 1e3:8.1f} us "
+                  f"(cold {kms_cold * 1e3:8.1f} us), {n_dofs / (ms * 1e-3):.3e} DoF/s", file=sys.stderr, flush=True)
+        del P
+        torch.cuda.empty_cache()
+    best = max((k for k in res if k[1] == "f64"), key=lambda k: res[k]["dofs_per_s"])
+    best32 = max((k for k in res if k[1] == "f32"), key=lambda k: res[k]["dofs_per_s"])
+    r = res[best]
+    out = {
+        "metric": METRIC,
+        "value": r["dofs_per_s"],
+        "unit": "DoF/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "3-D unit cube 32^3 Q2 (823,875 DoFs), 27 Gauss points per cell, Neo-Hookean "
+                               "matrix mu=1 nu=0.3 with 20 seeded spheres (r 0.05-0.12, 100x stiffer), smooth "
+                               "seeded displacement amplitude 0.1; one FP64 tangent vmult per step",
+                   "n_dofs": n_dofs, "cells": nc ** dim, "degree": deg, "qp_policy": POLICIES[best[0]],
+                   "scatter": "atomic"},
+        "roofline": roofline(dim, deg, nc, n_dofs, best[0], "f64", r["kernel_ms"]),
+        "fp32": {"value": res[best32]["dofs_per_s"], "unit": "DoF/s", "qp_policy": POLICIES[best32[0]],
+                 "roofline": roofline(dim, deg, nc, n_dofs, best32[0], "f32", res[best32]["kernel_ms"])},
+        "variants": {f"{POLICIES[k[0]]}/{k[1]}": {kk: (round(v, 6) if isinstance(v, float) else v)
+                                                 for kk, v in res[k].items()} for k in res},
+    }
+    out["roofline"]["kernel_ms"] = r["kernel_ms"]
+    out["roofline"]["kernel_ms_cold"] = r["kernel_ms_cold"]
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

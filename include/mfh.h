@@ -1,0 +1,239 @@
+/*
+ * mfh.h -- C ABI of the MI355X matrix-free finite-strain hyperelasticity library.
+ *
+ * The library applies the Newton tangent of a compressible Neo-Hookean body
+ * without assembling it (the matrix-free vmult of Sec. 5, built on the
+ * linearisation of Sec. 2.2 and the material law of Sec. 2.3), evaluates the
+ * residual of the weak form (Sec. 2.1, Sec. 3), and solves the Newton system
+ * with a CG preconditioned by the geometric multigrid V-cycle of Sec. 6 whose
+ * level operators are linearised about the displacement interpolated onto each
+ * level.  Smoother and solver settings follow Sec. 7: Chebyshev of degree 4
+ * on the operator diagonal, two pre- and two post-smoothing steps, the
+ * interval [0.6, 1.2] x lambda_max, lambda_max from 30 CG iterations.
+ *
+ * Geometry and numbering.  The body is the unit box [0,1]^dim (dim = 2 is
+ * plane strain) split into n_cells^dim equal cells; the displacement is a
+ * continuous vector Lagrange field of degree p (Gauss-Lobatto-Legendre
+ * support points) integrated with the (p+1)^dim Gauss rule (Tables 1-2).  The
+ * lattice has L = p*n_cells + 1 nodes per direction; every vector is
+ * component-blocked with the first lattice index fastest (the tensor
+ * multi-index of Sec. 5):  dof = c * L^dim + i + L * (j + L * k).
+ *
+ * Ownership and memory.  All vector arguments are DEVICE pointers owned by
+ * the caller; the library never frees them.  Every device buffer the library
+ * uses lives in the caller-supplied workspace passed to mfh_create (size from
+ * mfh_workspace_size); after mfh_create returns the library allocates no
+ * device memory.  Host arrays inside mfh_desc are copied at mfh_create.
+ *
+ * Streams and synchronisation.  Work is enqueued on the HIP stream given to
+ * mfh_create (NULL = the null stream).  Calls documented as "async" return
+ * after enqueueing; calls that return host scalars synchronise the stream.
+ *
+ * Errors.  Every call returns an mfh_status; nothing throws or exits.  After
+ * an error, mfh_last_error(problem) (or mfh_last_error(NULL) for failures
+ * before a problem exists) gives a message.  A problem stays usable after any
+ * error other than MFH_ERR_HIP.  A problem is not thread-safe.
+ *
+ * Dirichlet conditions fix whole components on whole faces.  Bit
+ * ((2*axis + side) * dim + comp) of dirichlet_mask fixes component comp on the
+ * face x_axis = side.  Operators carry identity rows and columns on
+ * constrained DoFs:  tangent_vmult returns K_c x with
+ * K_c = (I - C) K (I - C) + C (C = indicator of constrained DoFs); residual
+ * returns zero on constrained rows; cg_solve expects b = 0 on constrained
+ * rows and returns x = 0 there.
+ */
+#ifndef MFH_H
+#define MFH_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MFH_OK = 0,
+  MFH_ERR_INVALID_ARG = -1,   /* bad descriptor, level, dtype, pointer, or call order   */
+  MFH_ERR_HIP = -2,           /* a HIP runtime call failed; the problem is unusable      */
+  MFH_ERR_WORKSPACE = -3,     /* workspace smaller than mfh_workspace_size reported      */
+  MFH_ERR_INVERTED = -4,      /* a quadrature point has J = det F <= 0 (Sec. 2.1)       */
+  MFH_ERR_NOT_CONVERGED = -5, /* CG / Newton hit its iteration limit; outputs still set */
+  MFH_ERR_BREAKDOWN = -6,     /* CG: p^T A p <= 0 or a NaN appeared                     */
+  MFH_ERR_NOT_SPD = -7        /* coarse-level factorisation met a non-positive pivot    */
+} mfh_status;
+
+enum { MFH_F64 = 0, MFH_F32 = 1 };
+
+/* Quadrature-point policies of the tangent vmult (Sec. 5, Algorithms 1-2):
+ *  RECOMPUTE  re-evaluates Grad u, F, J, F^-1, ln J and the stresses at every
+ *             quadrature point from the displacement (the recompute end of
+ *             the caching trade-off; Algorithm 1 without its scalar cache);
+ *  CACHE_F    reads the cached deformation gradient F and recomputes the rest;
+ *  CACHE_T2   reads cached F^-1, the second Piola-Kirchhoff stress S and
+ *             c1 = mu - 2 lambda ln J: the referential counterpart of
+ *             Algorithm 2's cached tau/J, c1, c2.                               */
+enum { MFH_QP_RECOMPUTE = 0, MFH_QP_CACHE_F = 1, MFH_QP_CACHE_T2 = 2 };
+
+/* Scatter of cell results into the output vector: ATOMIC (hardware float
+ * atomics; summation order varies run to run) or COLOR (2^dim launches over
+ * cells of equal coordinate parity, plain read-modify-write, deterministic). */
+enum { MFH_SCATTER_ATOMIC = 0, MFH_SCATTER_COLOR = 1 };
+
+typedef struct mfh_problem mfh_problem;
+
+typedef struct {
+  int dim;                   /* 2 or 3                                                   */
+  int n_cells;               /* cells per direction on the finest level (>= 1)            */
+  int degree;                /* polynomial degree p, 1..4                                */
+  int n_levels;              /* multigrid levels >= 1; n_cells % 2^(n_levels-1) == 0      */
+  int n_materials;           /* 1 or 2 (material 0 = matrix)                             */
+  const double* mu;          /* host [n_materials] shear moduli, > 0                     */
+  const double* lambda;      /* host [n_materials] parameter lambda of the energy         */
+  int n_inclusions;          /* >= 0                                                     */
+  const double* inclusions;  /* host [n_inclusions][dim + 2]: centre, radius, material id;
+                                a quadrature point X is in an inclusion when
+                                |X - centre|^2 <= radius^2 (later rows win)               */
+  unsigned dirichlet_mask;   /* face-component bits, see above                           */
+  int qp_policy;             /* MFH_QP_*                                                  */
+  int scatter;               /* MFH_SCATTER_*                                              */
+  int vcycle_dtype;          /* MFH_F32: mixed precision V-cycle; MFH_F64: all FP64        */
+  int cheb_degree;           /* Chebyshev degree (paper: 4), 1..16                       */
+  int n_smooth;              /* Chebyshev applications pre and post (paper: 2), 1..8      */
+  int eig_iters;             /* CG iterations for lambda_max (paper: 30), 1..200          */
+  double cheb_lo, cheb_hi;   /* smoother interval factors (paper: 0.6, 1.2)              */
+} mfh_desc;
+
+/* Fills *desc with the paper's solver settings (degree 4, 2 steps, 30
+ * iterations, [0.6, 1.2]), RECOMPUTE, ATOMIC, F32 V-cycle; geometry fields
+ * are zeroed and must be set by the caller. */
+void mfh_desc_defaults(mfh_desc* desc);
+
+/* Device bytes the problem needs.  Errors: MFH_ERR_INVALID_ARG. */
+mfh_status mfh_workspace_size(const mfh_desc* desc, size_t* bytes);
+
+/* Creates a problem inside `workspace` (device, >= mfh_workspace_size bytes,
+ * 256-byte aligned, owned by the caller and kept alive until mfh_destroy).
+ * `hip_stream` is a hipStream_t or NULL.  Builds the level lattices, 1-D
+ * tables, per-quadrature-point material ids, transfer tables and Dirichlet
+ * masks.  Synchronises.  Errors: INVALID_ARG, WORKSPACE, HIP. */
+mfh_status mfh_create(const mfh_desc* desc, void* workspace, size_t bytes,
+                      void* hip_stream, mfh_problem** out);
+
+/* Releases host state (never the workspace).  NULL is accepted. */
+mfh_status mfh_destroy(mfh_problem* problem);
+
+/* Number of DoFs of level `level` (0 = coarsest, n_levels-1 = finest). */
+mfh_status mfh_n_dofs(const mfh_problem* problem, int level, long long* n);
+
+/* Linearisation point (Sec. 6): copies the finest-level displacement u
+ * (device FP64, n_dofs), interpolates it at the support points of every
+ * coarser level, and builds each level operator's quadrature data.  Writes
+ * the smallest J over all levels to *min_J_host (may be NULL).  The
+ * preconditioner data (operator diagonals, Chebyshev intervals with
+ * lambda_max from eig_iters CG iterations, FP64 coarse-level inverse) are
+ * built on the first V-cycle / CG / Chebyshev / diagonal query that follows.
+ * Synchronises.  Errors: INVALID_ARG, INVERTED (min J <= 0; the problem then
+ * has no valid linearisation point until the next successful call), HIP. */
+mfh_status mfh_set_deformation(mfh_problem* problem, const double* u_dev, double* min_J_host);
+
+/* y = K_c x on `level` in precision `dtype` (MFH_F64: double*, MFH_F32:
+ * float*), linearised about the level displacement of the last
+ * mfh_set_deformation (eq. mf_vmult / eq. algebraic_tangent).  x and y are
+ * device vectors of n_dofs(level) entries and must not overlap.  Async.
+ * Errors: INVALID_ARG (also when no deformation was set), HIP. */
+mfh_status mfh_tangent_vmult(mfh_problem* problem, int level, int dtype,
+                             const void* x_dev, void* y_dev);
+
+/* r = residual of the weak form at displacement u on the finest level
+ * (eq. linear_system, volume term; FP64), zero on constrained rows.  u is any
+ * device FP64 displacement (not necessarily the linearisation point).  Async.
+ * Errors: INVALID_ARG, HIP. */
+mfh_status mfh_residual(mfh_problem* problem, const double* u_dev, double* r_dev);
+
+/* z = one multigrid V-cycle applied to r on the finest level (Sec. 6, Sec. 7),
+ * FP64 in and out; the cycle itself runs in vcycle_dtype, the coarse solve in
+ * FP64.  The V-cycle, CG and Newton entry points need a coarsest level of at
+ * most 20000 DoFs (the dense direct solve); larger coarsest levels give
+ * INVALID_ARG there while operator application keeps working.  The first
+ * call after set_deformation builds the preconditioner data and synchronises;
+ * later calls are async.  Errors: INVALID_ARG, NOT_SPD (coarse-level tangent
+ * not positive definite), BREAKDOWN (eigenvalue estimate), HIP. */
+mfh_status mfh_gmg_vcycle(mfh_problem* problem, const double* r_dev, double* z_dev);
+
+/* Solves K_c x = b on the finest level with FP64 CG preconditioned by the
+ * V-cycle, x0 = 0, until |r|_2 <= rtol |b|_2 or max_it iterations.  Writes the
+ * iteration count and the final relative residual (recomputed explicitly as
+ * |b - K_c x| / |b|) to the host pointers (may be NULL).  Synchronises.
+ * Errors: INVALID_ARG, NOT_CONVERGED, BREAKDOWN, NOT_SPD, HIP. */
+mfh_status mfh_cg_solve(mfh_problem* problem, const double* b_dev, double* x_dev,
+                        double rtol, int max_it, int* iters_host, double* relres_host);
+
+/* Message for the last error of `problem` (or of the calling thread's last
+ * failed mfh_create / mfh_workspace_size when problem is NULL). */
+const char* mfh_last_error(const mfh_problem* problem);
+
+/* ---- Newton load stepping (Sec. 3 Newton-Raphson, Sec. 7 tolerances) ---- */
+
+typedef struct {
+  int load_step, newton_iter, cg_iters;
+  double residual_norm;      /* |rhs| of this Newton step (free rows)                   */
+  double residual_after;     /* |R(u)| on free rows after the update                    */
+  double du_norm;            /* |du|_2                                                  */
+  double cg_relres;
+  double min_J;
+  double setup_ms, residual_ms, solve_ms;   /* host wall time of each phase         */
+} mfh_newton_record;
+
+/* Sets u on constrained DoFs to scale * face_values[2*axis + side][comp]
+ * (host array of 2*dim*dim doubles; where faces meet, the later face in
+ * axis-major order wins).  Async.  Errors: INVALID_ARG, HIP. */
+mfh_status mfh_apply_dirichlet(mfh_problem* problem, double* u_dev,
+                               const double* face_values, double scale);
+
+/* Full Newton solve under displacement control.  The prescribed values
+ * (as for mfh_apply_dirichlet) are applied in n_steps equal increments; the
+ * first Newton step of each increment carries it linearly
+ * (K_c d = -(R(u) + K(u) dg), u <- u + dg + d), later steps solve
+ * K_c du = -R(u).  A step converges when |du| <= du_tol and
+ * |R| <= r_tol or |R| <= r_tol |R0| (R0: first right-hand side of the step).
+ * u (device FP64) is the initial state and receives the solution.  Up to
+ * max_records records are written to the host array; *n_records receives the
+ * number of Newton steps taken.  Synchronises.
+ * Errors: INVALID_ARG, INVERTED, NOT_CONVERGED, BREAKDOWN, NOT_SPD, HIP. */
+mfh_status mfh_newton_solve(mfh_problem* problem, double* u_dev, const double* face_values,
+                            int n_steps, double cg_rtol, int cg_max_it, double du_tol,
+                            double r_tol, int max_newton,
+                            mfh_newton_record* records, int max_records, int* n_records);
+
+/* ---- Access to multigrid pieces, for verification against a reference ---- */
+
+/* Copies the FP64 level displacement of the last set_deformation. Sync. */
+mfh_status mfh_level_displacement(mfh_problem* problem, int level, double* u_dev);
+/* Copies the FP64 operator diagonal of `level` (1 on constrained DoFs). Sync. */
+mfh_status mfh_level_diagonal(mfh_problem* problem, int level, double* d_dev);
+/* lambda_max estimate of D^-1 A on `level` >= 1 (host). */
+mfh_status mfh_level_lambda_max(mfh_problem* problem, int level, double* lam_host);
+/* y_fine = P x_coarse (coarse level = level-1, fine = level, 1 <= level),
+ * constrained fine entries zeroed; dtype as for tangent_vmult.  Async. */
+mfh_status mfh_prolongate(mfh_problem* problem, int level, int dtype, const void* x_dev, void* y_dev);
+/* y_coarse = P^T x_fine, constrained coarse entries zeroed.  Async. */
+mfh_status mfh_restrict(mfh_problem* problem, int level, int dtype, const void* x_dev, void* y_dev);
+/* One degree-cheb_degree Chebyshev application on `level` >= 1 in the
+ * V-cycle's precision (vcycle_dtype): x <- x + p(D^-1 A)(D^-1 (f - A x)).  Async. */
+mfh_status mfh_chebyshev(mfh_problem* problem, int level, const void* f_dev, void* x_dev);
+
+/* ---- Kernel timers (measurement of the operator kernel) ---- */
+
+/* enable != 0: from now on every cell-kernel launch of mfh_tangent_vmult is
+ * bracketed by HIP events on the problem's stream (the output fill is not
+ * included); enable == 0 stops recording.  Either call resets the totals. */
+mfh_status mfh_timer_enable(mfh_problem* problem, int enable);
+/* Synchronises and returns the summed duration (ms) and the number of the
+ * timed cell-kernel launches since the last mfh_timer_enable. */
+mfh_status mfh_timer_read(mfh_problem* problem, double* total_ms, long long* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MFH_H */

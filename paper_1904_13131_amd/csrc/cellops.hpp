@@ -1,0 +1,960 @@
+// Cell kernels of the matrix-free operator: gather -> sum factorisation ->
+// quadrature-point stage -> transposed sum factorisation -> scatter.
+//
+// Sec. 5 evaluates eq. (mf_vmult) cell by cell with sum factorisation: every
+// reference derivative at the tensor-product Gauss points is a sequence of
+// 1-D contractions with the tables S (values) and D (derivatives), and the
+// test-function side is the same sequence transposed.
+//
+// Thread layout (one block = kBlock threads = CPB cells x NP pencils):
+//   thread t handles cell t % CPB (consecutive lanes -> neighbouring cells, so
+//   the lattice gathers coalesce) and pencil t / CPB.  A pencil is a line of
+//   n = p+1 points; 3-D cells have n^2 pencils, 2-D cells n.  The 1-D
+//   contraction along a pencil runs in registers; pencils are re-oriented
+//   between the x, y and z sweeps through LDS (layout [array][point][cell],
+//   cell fastest, so a wave's LDS accesses are consecutive words).  After the
+//   forward sweeps each thread owns the Gauss points of one z-line (2-D:
+//   y-line) of its cell with all d x d reference derivatives in registers; the
+//   quadrature-point stage runs there, and the transposed sweeps return the
+//   test-function contributions to the thread's x-line of nodes, which are
+//   scattered into the output with hardware float atomics (or plain
+//   read-modify-write inside one colour of cells).
+#pragma once
+
+#include "common.hpp"
+
+namespace mfh {
+
+enum { POL_R = 0, POL_CF = 1, POL_C2 = 2 };
+
+// Cache words per quadrature point.
+template <int DIM, int POL>
+struct CacheWords {
+  static constexpr int value = POL == POL_CF ? DIM * DIM
+                              : POL == POL_C2 ? DIM * DIM + DIM * (DIM + 1) / 2 + 1
+                              : 0;
+};
+
+template <int DIM, int N1>
+struct Geo {
+  static constexpr int NP = DIM == 3 ? N1 * N1 : N1;   // pencils per cell
+  static constexpr int NV = NP * N1;                   // points per cell
+  static constexpr int CPB = kBlock / NP;              // cells per block
+  static constexpr int NARR = DIM == 3 ? 3 : 2;        // LDS arrays per component
+};
+
+template <int DIM, int N1, typename T>
+struct SumFact {
+  using G = Geo<DIM, N1>;
+  static constexpr int NV = G::NV, CPB = G::CPB;
+
+  __device__ static __forceinline__ int pt(int x, int y, int z) { return x + N1 * (y + N1 * z); }
+  __device__ static __forceinline__ T& at(T* lds, int arr, int p, int cl) {
+    return lds[(arr * NV + p) * CPB + cl];
+  }
+
+  // Nodal values v[c][a] on the thread's x-line -> reference gradients
+  // g[c][I][q] (I = derivative direction) at the Gauss points of the thread's
+  // final line (3-D: z-line (qx,qy) = (pen%n, pen/n); 2-D: y-line qx = pen).
+  template <int NC>
+  __device__ static void forward(const T (&v)[NC][N1], T (&g)[NC][DIM][N1], T* lds,
+                                 int pen, int cl, bool act, const Tables<T>& tb) {
+    if constexpr (DIM == 3) {
+      const int p0 = pen % N1, p1 = pen / N1;
+      if (act) {   // x-sweep: line (b, c) = (p0, p1)
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+          for (int q = 0; q < N1; ++q) {
+            T s = 0, d = 0;
+#pragma unroll
+            for (int a = 0; a < N1; ++a) {
+              s += tb.S[q][a] * v[c][a];
+              d += tb.D[q][a] * v[c][a];
+            }
+            at(lds, 3 * c + 0, pt(q, p0, p1), cl) = s;
+            at(lds, 3 * c + 1, pt(q, p0, p1), cl) = d;
+          }
+      }
+      __syncthreads();
+      if (act) {   // y-sweep: line (qx, c) = (p0, p1)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          T s[N1], d[N1];
+#pragma unroll
+          for (int b = 0; b < N1; ++b) {
+            s[b] = at(lds, 3 * c + 0, pt(p0, b, p1), cl);
+            d[b] = at(lds, 3 * c + 1, pt(p0, b, p1), cl);
+          }
+#pragma unroll
+          for (int q = 0; q < N1; ++q) {
+            T ss = 0, sd = 0, ds = 0;
+#pragma unroll
+            for (int b = 0; b < N1; ++b) {
+              ss += tb.S[q][b] * s[b];
+              sd += tb.D[q][b] * s[b];
+              ds += tb.S[q][b] * d[b];
+            }
+            at(lds, 3 * c + 0, pt(p0, q, p1), cl) = ss;   // S_y S_x
+            at(lds, 3 * c + 1, pt(p0, q, p1), cl) = sd;   // D_y S_x
+            at(lds, 3 * c + 2, pt(p0, q, p1), cl) = ds;   // S_y D_x
+          }
+        }
+      }
+      __syncthreads();
+      if (act) {   // z-sweep: line (qx, qy) = (p0, p1)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          T ss[N1], sd[N1], ds[N1];
+#pragma unroll
+          for (int k = 0; k < N1; ++k) {
+            ss[k] = at(lds, 3 * c + 0, pt(p0, p1, k), cl);
+            sd[k] = at(lds, 3 * c + 1, pt(p0, p1, k), cl);
+            ds[k] = at(lds, 3 * c + 2, pt(p0, p1, k), cl);
+          }
+#pragma unroll
+          for (int q = 0; q < N1; ++q) {
+            T gx = 0, gy = 0, gz = 0;
+#pragma unroll
+            for (int k = 0; k < N1; ++k) {
+              gx += tb.S[q][k] * ds[k];
+              gy += tb.S[q][k] * sd[k];
+              gz += tb.D[q][k] * ss[k];
+            }
+            g[c][0][q] = gx;
+            g[c][1][q] = gy;
+            g[c][2][q] = gz;
+          }
+        }
+      }
+      __syncthreads();
+    } else {
+      const int b = pen;
+      if (act) {   // x-sweep: line b
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+          for (int q = 0; q < N1; ++q) {
+            T s = 0, d = 0;
+#pragma unroll
+            for (int a = 0; a < N1; ++a) {
+              s += tb.S[q][a] * v[c][a];
+              d += tb.D[q][a] * v[c][a];
+            }
+            at(lds, 2 * c + 0, pt(q, b, 0), cl) = s;
+            at(lds, 2 * c + 1, pt(q, b, 0), cl) = d;
+          }
+      }
+      __syncthreads();
+      if (act) {   // y-sweep: line qx = pen
+        const int qx = pen;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          T s[N1], d[N1];
+#pragma unroll
+          for (int j = 0; j < N1; ++j) {
+            s[j] = at(lds, 2 * c + 0, pt(qx, j, 0), cl);
+            d[j] = at(lds, 2 * c + 1, pt(qx, j, 0), cl);
+          }
+#pragma unroll
+          for (int q = 0; q < N1; ++q) {
+            T gx = 0, gy = 0;
+#pragma unroll
+            for (int j = 0; j < N1; ++j) {
+              gx += tb.S[q][j] * d[j];
+              gy += tb.D[q][j] * s[j];
+            }
+            g[c][0][q] = gx;
+            g[c][1][q] = gy;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+
+  // Transposed sweeps: quadrature values P[c][I][q] on the thread's final line
+  // (weights already applied) -> out[c][a] = sum_q sum_I dphi_a/dxi_I(q) P[c][I][q]
+  // on the thread's x-line of nodes.
+  template <int NC>
+  __device__ static void backward(const T (&P)[NC][DIM][N1], T (&out)[NC][N1], T* lds,
+                                  int pen, int cl, bool act, const Tables<T>& tb) {
+    if constexpr (DIM == 3) {
+      const int p0 = pen % N1, p1 = pen / N1;
+      if (act) {   // z: line (qx, qy)
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+          for (int k = 0; k < N1; ++k) {
+            T z0 = 0, z1 = 0, z2 = 0;
+#pragma unroll
+            for (int q = 0; q < N1; ++q) {
+              z0 += tb.S[q][k] * P[c][0][q];
+              z1 += tb.S[q][k] * P[c][1][q];
+              z2 += tb.D[q][k] * P[c][2][q];
+            }
+            at(lds, 3 * c + 0, pt(p0, p1, k), cl) = z0;
+            at(lds, 3 * c + 1, pt(p0, p1, k), cl) = z1;
+            at(lds, 3 * c + 2, pt(p0, p1, k), cl) = z2;
+          }
+      }
+      __syncthreads();
+      if (act) {   // y: line (qx, c)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          T z0[N1], z1[N1], z2[N1];
+#pragma unroll
+          for (int q = 0; q < N1; ++q) {
+            z0[q] = at(lds, 3 * c + 0, pt(p0, q, p1), cl);
+            z1[q] = at(lds, 3 * c + 1, pt(p0, q, p1), cl);
+            z2[q] = at(lds, 3 * c + 2, pt(p0, q, p1), cl);
+          }
+#pragma unroll
+          for (int b = 0; b < N1; ++b) {
+            T yd = 0, ys = 0;
+#pragma unroll
+            for (int q = 0; q < N1; ++q) {
+              yd += tb.S[q][b] * z0[q];
+              ys += tb.D[q][b] * z1[q] + tb.S[q][b] * z2[q];
+            }
+            at(lds, 3 * c + 0, pt(p0, b, p1), cl) = yd;   // still needs D_x
+            at(lds, 3 * c + 1, pt(p0, b, p1), cl) = ys;   // still needs S_x
+          }
+        }
+      }
+      __syncthreads();
+      if (act) {   // x: line (b, c)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          T yd[N1], ys[N1];
+#pragma unroll
+          for (int q = 0; q < N1; ++q) {
+            yd[q] = at(lds, 3 * c + 0, pt(q, p0, p1), cl);
+            ys[q] = at(lds, 3 * c + 1, pt(q, p0, p1), cl);
+          }
+#pragma unroll
+          for (int a = 0; a < N1; ++a) {
+            T s = 0;
+#pragma unroll
+            for (int q = 0; q < N1; ++q) s += tb.D[q][a] * yd[q] + tb.S[q][a] * ys[q];
+            out[c][a] = s;
+          }
+        }
+      }
+      __syncthreads();
+    } else {
+      if (act) {   // y: line qx = pen
+        const int qx = pen;
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+          for (int j = 0; j < N1; ++j) {
+            T yd = 0, ys = 0;
+#pragma unroll
+            for (int q = 0; q < N1; ++q) {
+              yd += tb.S[q][j] * P[c][0][q];
+              ys += tb.D[q][j] * P[c][1][q];
+            }
+            at(lds, 2 * c + 0, pt(qx, j, 0), cl) = yd;
+            at(lds, 2 * c + 1, pt(qx, j, 0), cl) = ys;
+          }
+      }
+      __syncthreads();
+      if (act) {   // x: line b = pen
+        const int b = pen;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          T yd[N1], ys[N1];
+#pragma unroll
+          for (int q = 0; q < N1; ++q) {
+            yd[q] = at(lds, 2 * c + 0, pt(q, b, 0), cl);
+            ys[q] = at(lds, 2 * c + 1, pt(q, b, 0), cl);
+          }
+#pragma unroll
+          for (int a = 0; a < N1; ++a) {
+            T s = 0;
+#pragma unroll
+            for (int q = 0; q < N1; ++q) s += tb.D[q][a] * yd[q] + tb.S[q][a] * ys[q];
+            out[c][a] = s;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Per-thread cell geometry.
+template <int DIM, int N1>
+struct CellPos {
+  long long e;          // linear cell index on the level
+  int i0, j0, k0;       // lattice origin of the thread's x-line of nodes
+  unsigned fjk;         // faces touched by the line's (j, k)
+  bool first_i, last_i; // the cell touches x = 0 / x = 1
+  long long base;       // node index of the line's first node
+
+  template <typename T>
+  __device__ void init(const CellArgs<T>& a, long long lin, int pen) {
+    constexpr int P = N1 - 1;
+    int ex, ey, ez;
+    if (a.color < 0) {
+      e = lin;
+      ex = (int)(lin % a.N);
+      const long long r = lin / a.N;
+      ey = (int)(r % a.N);
+      ez = (int)(r / a.N);
+    } else {
+      const int cx = a.color & 1, cy = (a.color >> 1) & 1, cz = (a.color >> 2) & 1;
+      const int nx = (a.N - cx + 1) / 2, ny = (a.N - cy + 1) / 2;
+      const int ix = (int)(lin % nx);
+      const long long r = lin / nx;
+      const int iy = (int)(r % ny), iz = (int)(r / ny);
+      ex = 2 * ix + cx;
+      ey = 2 * iy + cy;
+      ez = DIM == 3 ? 2 * iz + cz : 0;
+      e = ex + (long long)a.N * (ey + (long long)a.N * ez);
+    }
+    const int b = DIM == 3 ? pen % N1 : pen;
+    const int c = DIM == 3 ? pen / N1 : 0;
+    i0 = ex * P;
+    j0 = ey * P + b;
+    k0 = DIM == 3 ? ez * P + c : 0;
+    fjk = node_faces(1, j0, k0, a.L, DIM);     // i = 1 is never a face node
+    first_i = (ex == 0);
+    last_i = (ex == a.N - 1);
+    base = i0 + (long long)a.L * (j0 + (long long)a.L * k0);
+  }
+
+  __device__ __forceinline__ unsigned faces(int a_, int L) const {
+    unsigned f = fjk;
+    if (a_ == 0 && first_i) f |= 1u;
+    if (a_ == N1 - 1 && last_i) f |= 2u;
+    return f;
+  }
+};
+
+template <int DIM, int N1, typename T>
+__device__ __forceinline__ void gather(const T* __restrict__ src, const CellArgs<T>& a,
+                                       const CellPos<DIM, N1>& cp, bool act, bool masked,
+                                       T (&v)[DIM][N1]) {
+#pragma unroll
+  for (int c = 0; c < DIM; ++c)
+#pragma unroll
+    for (int k = 0; k < N1; ++k) {
+      T val = 0;
+      if (act) {
+        val = src[c * a.nn + cp.base + k];
+        if (masked && a.mask_in && (cp.faces(k, a.L) & a.fmask[c])) val = 0;
+      }
+      v[c][k] = val;
+    }
+}
+
+template <int DIM, int N1, typename T>
+__device__ __forceinline__ void scatter(T* __restrict__ dst, const CellArgs<T>& a,
+                                        const CellPos<DIM, N1>& cp, bool act,
+                                        const T (&v)[DIM][N1]) {
+  if (!act) return;
+#pragma unroll
+  for (int c = 0; c < DIM; ++c)
+#pragma unroll
+    for (int k = 0; k < N1; ++k) {
+      if (cp.faces(k, a.L) & a.fmask[c]) continue;
+      T* p = dst + c * a.nn + cp.base + k;
+      if (a.color < 0)
+        atomic_add(p, v[c][k]);
+      else
+        *p += v[c][k];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Quadrature-point algebra (Sec. 2.3).  All gradients are physical (1/h
+// applied).  Referential route used by the device:
+//   F = I + Grad u, J = det F, c1 = mu - 2 lambda ln J,
+//   S = mu I - c1 C^-1   (C^-1 = F^-1 F^-T),
+//   g = Grad x F^-1 (spatial gradient of the trial field),
+//   sigma = 2 c1 sym(g) + 2 lambda tr(g) I        (J c : sym g, Sec. 2.3)
+//   P_x = sigma F^-T + Grad x S                    (tangent, eq. tangent
+//                                                   pulled back: g tau F^-T = Grad x S)
+// and the residual stress P = mu F - c1 F^-T (= tau F^-T with tau = mu b - c1 I).
+
+template <typename T> __device__ __forceinline__ T log1p_t(T x);
+template <> __device__ __forceinline__ double log1p_t<double>(double x) { return log1p(x); }
+template <> __device__ __forceinline__ float log1p_t<float>(float x) { return log1pf(x); }
+
+// J - 1 of F = I + H without cancellation: tr H + second invariant + det H.
+template <int DIM, typename T>
+__device__ __forceinline__ T det_minus_one(const T (&H)[DIM][DIM]) {
+  if constexpr (DIM == 3) {
+    const T tr = H[0][0] + H[1][1] + H[2][2];
+    const T i2 = H[0][0] * H[1][1] - H[0][1] * H[1][0] + H[0][0] * H[2][2] - H[0][2] * H[2][0]
+               + H[1][1] * H[2][2] - H[1][2] * H[2][1];
+    const T dt = H[0][0] * (H[1][1] * H[2][2] - H[1][2] * H[2][1])
+               - H[0][1] * (H[1][0] * H[2][2] - H[1][2] * H[2][0])
+               + H[0][2] * (H[1][0] * H[2][1] - H[1][1] * H[2][0]);
+    return tr + i2 + dt;
+  } else {
+    return H[0][0] + H[1][1] + (H[0][0] * H[1][1] - H[0][1] * H[1][0]);
+  }
+}
+
+// F = I + H; returns J and writes F^-1 (Fi[I][j]).
+template <int DIM, typename T>
+__device__ __forceinline__ T kinematics(const T (&H)[DIM][DIM], T (&F)[DIM][DIM], T (&Fi)[DIM][DIM], T& jm1) {
+#pragma unroll
+  for (int i = 0; i < DIM; ++i)
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) F[i][j] = H[i][j] + (i == j ? T(1) : T(0));
+  jm1 = det_minus_one<DIM, T>(H);
+  const T J = T(1) + jm1;
+  const T r = T(1) / J;
+  if constexpr (DIM == 3) {
+    Fi[0][0] = (F[1][1] * F[2][2] - F[1][2] * F[2][1]) * r;
+    Fi[0][1] = (F[0][2] * F[2][1] - F[0][1] * F[2][2]) * r;
+    Fi[0][2] = (F[0][1] * F[1][2] - F[0][2] * F[1][1]) * r;
+    Fi[1][0] = (F[1][2] * F[2][0] - F[1][0] * F[2][2]) * r;
+    Fi[1][1] = (F[0][0] * F[2][2] - F[0][2] * F[2][0]) * r;
+    Fi[1][2] = (F[0][2] * F[1][0] - F[0][0] * F[1][2]) * r;
+    Fi[2][0] = (F[1][0] * F[2][1] - F[1][1] * F[2][0]) * r;
+    Fi[2][1] = (F[0][1] * F[2][0] - F[0][0] * F[2][1]) * r;
+    Fi[2][2] = (F[0][0] * F[1][1] - F[0][1] * F[1][0]) * r;
+  } else {
+    Fi[0][0] = F[1][1] * r;
+    Fi[0][1] = -F[0][1] * r;
+    Fi[1][0] = -F[1][0] * r;
+    Fi[1][1] = F[0][0] * r;
+  }
+  return J;
+}
+
+// S = mu I - c1 F^-1 F^-T, symmetric.
+template <int DIM, typename T>
+__device__ __forceinline__ void pk2(const T (&Fi)[DIM][DIM], T mu, T c1, T (&S)[DIM][DIM]) {
+#pragma unroll
+  for (int I = 0; I < DIM; ++I)
+#pragma unroll
+    for (int J = I; J < DIM; ++J) {
+      T ci = 0;
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) ci += Fi[I][k] * Fi[J][k];
+      const T s = (I == J ? mu : T(0)) - c1 * ci;
+      S[I][J] = s;
+      S[J][I] = s;
+    }
+}
+
+// Tangent action at one quadrature point: Hx (physical Grad x) -> P_x * wt, in place.
+template <int DIM, typename T>
+__device__ __forceinline__ void tangent_qp(T (&Hx)[DIM][DIM], const T (&Fi)[DIM][DIM],
+                                           const T (&S)[DIM][DIM], T c1, T lam, T wt) {
+  T g[DIM][DIM];
+#pragma unroll
+  for (int i = 0; i < DIM; ++i)
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) {
+      T s = 0;
+#pragma unroll
+      for (int I = 0; I < DIM; ++I) s += Hx[i][I] * Fi[I][j];
+      g[i][j] = s;
+    }
+  T tr = 0;
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) tr += g[i][i];
+  T sig[DIM][DIM];
+#pragma unroll
+  for (int i = 0; i < DIM; ++i)
+#pragma unroll
+    for (int j = i; j < DIM; ++j) {
+      const T s = c1 * (g[i][j] + g[j][i]) + (i == j ? T(2) * lam * tr : T(0));
+      sig[i][j] = s;
+      sig[j][i] = s;
+    }
+  T P[DIM][DIM];
+#pragma unroll
+  for (int i = 0; i < DIM; ++i)
+#pragma unroll
+    for (int I = 0; I < DIM; ++I) {
+      T s = 0;
+#pragma unroll
+      for (int j = 0; j < DIM; ++j) s += sig[i][j] * Fi[I][j];
+#pragma unroll
+      for (int J = 0; J < DIM; ++J) s += Hx[i][J] * S[J][I];
+      P[i][I] = s;
+    }
+#pragma unroll
+  for (int i = 0; i < DIM; ++i)
+#pragma unroll
+    for (int I = 0; I < DIM; ++I) Hx[i][I] = P[i][I] * wt;
+}
+
+template <int DIM, int N1, typename T>
+__device__ __forceinline__ T qp_weight(const Tables<T>& tb, int p0, int p1, int q) {
+  if constexpr (DIM == 3)
+    return tb.w[p0] * tb.w[p1] * tb.w[q];
+  else
+    return tb.w[p0] * tb.w[q];
+}
+
+template <int DIM, int N1>
+__device__ __forceinline__ int qp_index(int p0, int p1, int q) {
+  return DIM == 3 ? p0 + N1 * (p1 + N1 * q) : p0 + N1 * q;
+}
+
+template <typename T>
+__device__ __forceinline__ int material_of(const CellArgs<T>& a, long long e, int qp) {
+  return (a.matbits[e * a.nwords + (qp >> 5)] >> (qp & 31)) & 1u;
+}
+
+// ---------------------------------------------------------------------------
+// Tangent vmult: y += K x over the cells of this launch (y pre-filled).
+template <int DIM, int P, typename T, int POL>
+__global__ void __launch_bounds__(kBlock) k_tangent(CellArgs<T> a) {
+  constexpr int N1 = P + 1;
+  using G = Geo<DIM, N1>;
+  using SF = SumFact<DIM, N1, T>;
+  constexpr int NW = CacheWords<DIM, POL>::value;
+  __shared__ T lds[DIM * G::NARR * G::NV * G::CPB];
+
+  const int t = threadIdx.x;
+  const int cl = t % G::CPB, pen = t / G::CPB;
+  const long long blk = a.color < 0 ? xcd_block(blockIdx.x, gridDim.x) : (long long)blockIdx.x;
+  const long long lin = blk * G::CPB + cl;
+  const bool act = pen < G::NP && lin < a.nlaunch;
+  CellPos<DIM, N1> cp;
+  cp.init(a, act ? lin : 0, act ? pen : 0);
+  const int p0 = DIM == 3 ? pen % N1 : pen;
+  const int p1 = DIM == 3 ? pen / N1 : 0;
+
+  T gx[DIM][DIM][N1];
+  {
+    T v[DIM][N1];
+    gather<DIM, N1, T>(a.x, a, cp, act, true, v);
+    SF::template forward<DIM>(v, gx, lds, pen, cl, act, a.tb);
+  }
+  T gu[DIM][DIM][N1];
+  if constexpr (POL == POL_R) {
+    T v[DIM][N1];
+    gather<DIM, N1, T>(a.u, a, cp, act, false, v);
+    SF::template forward<DIM>(v, gu, lds, pen, cl, act, a.tb);
+  }
+
+  if (act) {
+#pragma unroll
+    for (int q = 0; q < N1; ++q) {
+      const int qp = qp_index<DIM, N1>(p0, p1, q);
+      const int mid = material_of(a, cp.e, qp);
+      const T mu = mid ? a.mu[1] : a.mu[0];
+      const T lam = mid ? a.lam[1] : a.lam[0];
+      const T wt = qp_weight<DIM, N1, T>(a.tb, p0, p1, q) * a.wscale;
+      T Hx[DIM][DIM];
+#pragma unroll
+      for (int i = 0; i < DIM; ++i)
+#pragma unroll
+        for (int I = 0; I < DIM; ++I) Hx[i][I] = gx[i][I][q] * a.invh;
+      T Fi[DIM][DIM], S[DIM][DIM], c1;
+      if constexpr (POL == POL_R || POL == POL_CF) {
+        T H[DIM][DIM];
+        if constexpr (POL == POL_R) {
+#pragma unroll
+          for (int i = 0; i < DIM; ++i)
+#pragma unroll
+            for (int I = 0; I < DIM; ++I) H[i][I] = gu[i][I][q] * a.invh;
+        } else {
+          const T* cq = a.cache + (long long)qp * a.ncells + cp.e;
+          const long long stride = (long long)G::NV * a.ncells;
+#pragma unroll
+          for (int i = 0; i < DIM; ++i)
+#pragma unroll
+            for (int I = 0; I < DIM; ++I) H[i][I] = cq[(i * DIM + I) * stride] - (i == I ? T(1) : T(0));
+        }
+        T F[DIM][DIM], jm1;
+        kinematics<DIM, T>(H, F, Fi, jm1);
+        c1 = mu - T(2) * lam * log1p_t<T>(jm1);
+        pk2<DIM, T>(Fi, mu, c1, S);
+      } else {
+        const T* cq = a.cache + (long long)qp * a.ncells + cp.e;
+        const long long stride = (long long)G::NV * a.ncells;
+        int w = 0;
+#pragma unroll
+        for (int I = 0; I < DIM; ++I)
+#pragma unroll
+          for (int j = 0; j < DIM; ++j) Fi[I][j] = cq[(w++) * stride];
+#pragma unroll
+        for (int I = 0; I < DIM; ++I)
+#pragma unroll
+          for (int J = I; J < DIM; ++J) {
+            const T s = cq[(w++) * stride];
+            S[I][J] = s;
+            S[J][I] = s;
+          }
+        c1 = cq[w * stride];
+      }
+      tangent_qp<DIM, T>(Hx, Fi, S, c1, lam, wt);
+#pragma unroll
+      for (int i = 0; i < DIM; ++i)
+#pragma unroll
+        for (int I = 0; I < DIM; ++I) gx[i][I][q] = Hx[i][I];
+    }
+  }
+  (void)NW;
+
+  T out[DIM][N1];
+  SF::template backward<DIM>(gx, out, lds, pen, cl, act, a.tb);
+  scatter<DIM, N1, T>(a.y, a, cp, act, out);
+}
+
+// Residual of the weak form: y += sum_q w P(F) : Grad N (FP64).
+template <int DIM, int P>
+__global__ void __launch_bounds__(kBlock) k_residual(CellArgs<double> a) {
+  using T = double;
+  constexpr int N1 = P + 1;
+  using G = Geo<DIM, N1>;
+  using SF = SumFact<DIM, N1, T>;
+  __shared__ T lds[DIM * G::NARR * G::NV * G::CPB];
+  const int t = threadIdx.x;
+  const int cl = t % G::CPB, pen = t / G::CPB;
+  const long long blk = a.color < 0 ? xcd_block(blockIdx.x, gridDim.x) : (long long)blockIdx.x;
+  const long long lin = blk * G::CPB + cl;
+  const bool act = pen < G::NP && lin < a.nlaunch;
+  CellPos<DIM, N1> cp;
+  cp.init(a, act ? lin : 0, act ? pen : 0);
+  const int p0 = DIM == 3 ? pen % N1 : pen;
+  const int p1 = DIM == 3 ? pen / N1 : 0;
+
+  T gu[DIM][DIM][N1];
+  {
+    T v[DIM][N1];
+    gather<DIM, N1, T>(a.u, a, cp, act, false, v);
+    SF::template forward<DIM>(v, gu, lds, pen, cl, act, a.tb);
+  }
+  if (act) {
+#pragma unroll
+    for (int q = 0; q < N1; ++q) {
+      const int qp = qp_index<DIM, N1>(p0, p1, q);
+      const int mid = material_of(a, cp.e, qp);
+      const T mu = mid ? a.mu[1] : a.mu[0];
+      const T lam = mid ? a.lam[1] : a.lam[0];
+      const T wt = qp_weight<DIM, N1, T>(a.tb, p0, p1, q) * a.wscale;
+      T H[DIM][DIM], F[DIM][DIM], Fi[DIM][DIM], jm1;
+#pragma unroll
+      for (int i = 0; i < DIM; ++i)
+#pragma unroll
+        for (int I = 0; I < DIM; ++I) H[i][I] = gu[i][I][q] * a.invh;
+      kinematics<DIM, T>(H, F, Fi, jm1);
+      const T c1 = mu - T(2) * lam * log1p_t<T>(jm1);
+#pragma unroll
+      for (int i = 0; i < DIM; ++i)
+#pragma unroll
+        for (int I = 0; I < DIM; ++I) gu[i][I][q] = (mu * F[i][I] - c1 * Fi[I][i]) * wt;
+    }
+  }
+  T out[DIM][N1];
+  SF::template backward<DIM>(gu, out, lds, pen, cl, act, a.tb);
+  scatter<DIM, N1, T>(a.y, a, cp, act, out);
+}
+
+// Quadrature data of a level: min J per block, and the policy cache
+// (CF: F;  C2: F^-1, S (upper triangle, row major), c1) in precision T.
+// The displacement is read in FP64 and everything is evaluated in FP64.
+template <int DIM, int P, typename T, int POL>
+__global__ void __launch_bounds__(kBlock) k_qpdata(CellArgs<double> a, T* __restrict__ cache) {
+  using D = double;
+  constexpr int N1 = P + 1;
+  using G = Geo<DIM, N1>;
+  using SF = SumFact<DIM, N1, D>;
+  __shared__ D lds[DIM * G::NARR * G::NV * G::CPB];
+  __shared__ D red[kBlock];
+  const int t = threadIdx.x;
+  const int cl = t % G::CPB, pen = t / G::CPB;
+  const long long lin = (long long)blockIdx.x * G::CPB + cl;
+  const bool act = pen < G::NP && lin < a.nlaunch;
+  CellPos<DIM, N1> cp;
+  cp.init(a, act ? lin : 0, act ? pen : 0);
+  const int p0 = DIM == 3 ? pen % N1 : pen;
+  const int p1 = DIM == 3 ? pen / N1 : 0;
+  D gu[DIM][DIM][N1];
+  {
+    D v[DIM][N1];
+    gather<DIM, N1, D>(a.u, a, cp, act, false, v);
+    SF::template forward<DIM>(v, gu, lds, pen, cl, act, a.tb);
+  }
+  D jmin = 1e300;
+  if (act) {
+#pragma unroll
+    for (int q = 0; q < N1; ++q) {
+      const int qp = qp_index<DIM, N1>(p0, p1, q);
+      const int mid = material_of(a, cp.e, qp);
+      const D mu = mid ? a.mu[1] : a.mu[0];
+      const D lam = mid ? a.lam[1] : a.lam[0];
+      D H[DIM][DIM], F[DIM][DIM], Fi[DIM][DIM], jm1;
+#pragma unroll
+      for (int i = 0; i < DIM; ++i)
+#pragma unroll
+        for (int I = 0; I < DIM; ++I) H[i][I] = gu[i][I][q] * a.invh;
+      const D J = kinematics<DIM, D>(H, F, Fi, jm1);
+      jmin = J < jmin ? J : jmin;
+      if constexpr (POL != POL_R) {
+        T* cq = cache + (long long)qp * a.ncells + cp.e;
+        const long long stride = (long long)G::NV * a.ncells;
+        if constexpr (POL == POL_CF) {
+#pragma unroll
+          for (int i = 0; i < DIM; ++i)
+#pragma unroll
+            for (int I = 0; I < DIM; ++I) cq[(i * DIM + I) * stride] = (T)F[i][I];
+        } else {
+          const D c1 = mu - 2.0 * lam * log1p(jm1);
+          D S[DIM][DIM];
+          pk2<DIM, D>(Fi, mu, c1, S);
+          int w = 0;
+#pragma unroll
+          for (int I = 0; I < DIM; ++I)
+#pragma unroll
+            for (int j = 0; j < DIM; ++j) cq[(w++) * stride] = (T)Fi[I][j];
+#pragma unroll
+          for (int I = 0; I < DIM; ++I)
+#pragma unroll
+            for (int J = I; J < DIM; ++J) cq[(w++) * stride] = (T)S[I][J];
+          cq[w * stride] = (T)c1;
+        }
+      }
+    }
+  }
+  red[t] = jmin;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if (t < s) red[t] = red[t] < red[t + s] ? red[t] : red[t + s];
+    __syncthreads();
+  }
+  if (t == 0) a.blockmin[blockIdx.x] = red[0];
+}
+
+// Operator diagonal (FP64).  For DoF (node a, component al) of a cell the
+// tangent entry reduces, with v = F^-T Grad N_a, to
+//   sum_q w_q |cell| [ (c1 + 2 lambda) v_al^2 + mu |Grad N_a|^2 ]
+// (material part 2 c1 sym g : sym g + 2 lambda tr(g)^2 plus geometric part
+// v . tau v with tau = mu b - c1 I).  One thread per (cell, node); the cell's
+// displacement and per-qp data are staged in LDS.
+template <int DIM, int P>
+__global__ void __launch_bounds__(kBlock) k_diag(CellArgs<double> a) {
+  using D = double;
+  constexpr int N1 = P + 1;
+  constexpr int NV = DIM == 3 ? N1 * N1 * N1 : N1 * N1;
+  constexpr int CPB = kBlock / NV;
+  constexpr int NQD = DIM * DIM + 2;   // F^-1, c1 + 2 lambda, mu
+  __shared__ D su[CPB][DIM][NV];
+  __shared__ D sq[CPB][NV][NQD];
+  const int t = threadIdx.x;
+  const int cl = t / NV, loc = t % NV;
+  const long long e = (long long)blockIdx.x * CPB + cl;
+  const bool act = cl < CPB && e < a.ncells;
+  int ex = 0, ey = 0, ez = 0;
+  if (act) {
+    ex = (int)(e % a.N);
+    ey = (int)((e / a.N) % a.N);
+    ez = DIM == 3 ? (int)(e / ((long long)a.N * a.N)) : 0;
+  }
+  const int ax = loc % N1, ay = (loc / N1) % N1, az = DIM == 3 ? loc / (N1 * N1) : 0;
+  const int I = ex * P + ax, J = ey * P + ay, K = ez * P + az;
+  const long long node = I + (long long)a.L * (J + (long long)a.L * K);
+  if (act) {
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) su[cl][c][loc] = a.u[c * a.nn + node];
+  }
+  __syncthreads();
+  if (act) {   // quadrature point qp = loc: Grad u by direct summation over the cell's nodes
+    const int qx = ax, qy = ay, qz = az;
+    D H[DIM][DIM] = {};
+    for (int b = 0; b < NV; ++b) {
+      const int bx = b % N1, by = (b / N1) % N1, bz = DIM == 3 ? b / (N1 * N1) : 0;
+      D gr[DIM];
+      if constexpr (DIM == 3) {
+        gr[0] = a.tb.D[qx][bx] * a.tb.S[qy][by] * a.tb.S[qz][bz];
+        gr[1] = a.tb.S[qx][bx] * a.tb.D[qy][by] * a.tb.S[qz][bz];
+        gr[2] = a.tb.S[qx][bx] * a.tb.S[qy][by] * a.tb.D[qz][bz];
+      } else {
+        gr[0] = a.tb.D[qx][bx] * a.tb.S[qy][by];
+        gr[1] = a.tb.S[qx][bx] * a.tb.D[qy][by];
+      }
+#pragma unroll
+      for (int c = 0; c < DIM; ++c)
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) H[c][d] += su[cl][c][b] * gr[d] * a.invh;
+    }
+    D F[DIM][DIM], Fi[DIM][DIM], jm1;
+    kinematics<DIM, D>(H, F, Fi, jm1);
+    const int mid = material_of(a, e, loc);
+    const D mu = mid ? a.mu[1] : a.mu[0];
+    const D lam = mid ? a.lam[1] : a.lam[0];
+    const D c1 = mu - 2.0 * lam * log1p(jm1);
+    int w = 0;
+#pragma unroll
+    for (int i = 0; i < DIM; ++i)
+#pragma unroll
+      for (int j = 0; j < DIM; ++j) sq[cl][loc][w++] = Fi[i][j];
+    sq[cl][loc][w++] = c1 + 2.0 * lam;
+    sq[cl][loc][w] = mu;
+  }
+  __syncthreads();
+  if (!act) return;
+  D acc[DIM] = {};
+  for (int q = 0; q < NV; ++q) {
+    const int qx = q % N1, qy = (q / N1) % N1, qz = DIM == 3 ? q / (N1 * N1) : 0;
+    D gr[DIM], wq;
+    if constexpr (DIM == 3) {
+      gr[0] = a.tb.D[qx][ax] * a.tb.S[qy][ay] * a.tb.S[qz][az] * a.invh;
+      gr[1] = a.tb.S[qx][ax] * a.tb.D[qy][ay] * a.tb.S[qz][az] * a.invh;
+      gr[2] = a.tb.S[qx][ax] * a.tb.S[qy][ay] * a.tb.D[qz][az] * a.invh;
+      wq = a.tb.w[qx] * a.tb.w[qy] * a.tb.w[qz];
+    } else {
+      gr[0] = a.tb.D[qx][ax] * a.tb.S[qy][ay] * a.invh;
+      gr[1] = a.tb.S[qx][ax] * a.tb.D[qy][ay] * a.invh;
+      wq = a.tb.w[qx] * a.tb.w[qy];
+    }
+    wq *= a.wscale / a.invh;   // w_q h^d
+    const D* s = sq[cl][q];
+    D gg = 0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) gg += gr[d] * gr[d];
+#pragma unroll
+    for (int al = 0; al < DIM; ++al) {
+      D v = 0;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) v += gr[d] * s[d * DIM + al];
+      acc[al] += wq * (s[DIM * DIM] * v * v + s[DIM * DIM + 1] * gg);
+    }
+  }
+  const unsigned f = node_faces(I, J, K, a.L, DIM);
+#pragma unroll
+  for (int al = 0; al < DIM; ++al)
+    if (!(f & a.fmask[al])) atomic_add(a.y + al * a.nn + node, acc[al]);
+}
+
+// Dense coarse-level tangent over free DoFs (FP64), one block per cell and one
+// thread per cell node a.  With v = F^-T Grad N (spatial gradient of a shape
+// function) the tangent entry of eq. (algebraic_tangent) between DoFs (a, i)
+// and (b, k) is, for this material law,
+//   sum_q w_q |cell| [ c1 v_a,k v_b,i + 2 lambda v_a,i v_b,k + mu delta_ik Grad N_a . Grad N_b ]
+// (material part with J c = 2 c1 Ssym + 2 lambda I (x) I, geometric part with
+// tau = mu b - c1 I).  Entries are added atomically into K[fi * nf + fj],
+// fi / fj the free indices of the two DoFs (fmap = -1 on constrained DoFs).
+template <int DIM, int P>
+__global__ void __launch_bounds__(kBlock) k_coarse_assemble(CellArgs<double> a, const int* __restrict__ fmap,
+                                                             long long nf, double* __restrict__ K) {
+  using D = double;
+  constexpr int N1 = P + 1;
+  constexpr int NV = DIM == 3 ? N1 * N1 * N1 : N1 * N1;
+  constexpr int NQD = DIM * DIM + 3;   // F^-1, c1, 2 lambda, mu
+  __shared__ D su[DIM][NV];
+  __shared__ D sq[NV][NQD];
+  const long long e = blockIdx.x;
+  const int t = threadIdx.x;
+  const bool act = t < NV;
+  const int ex = (int)(e % a.N), ey = (int)((e / a.N) % a.N);
+  const int ez = DIM == 3 ? (int)(e / ((long long)a.N * a.N)) : 0;
+  const int ax = t % N1, ay = (t / N1) % N1, az = DIM == 3 ? t / (N1 * N1) : 0;
+  const long long node = (ex * P + ax) + (long long)a.L * ((ey * P + ay) + (long long)a.L * (ez * P + az));
+  if (act) {
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) su[c][t] = a.u[c * a.nn + node];
+  }
+  __syncthreads();
+  if (act) {   // quadrature data at qp t
+    D H[DIM][DIM] = {};
+    for (int b = 0; b < NV; ++b) {
+      const int bx = b % N1, by = (b / N1) % N1, bz = DIM == 3 ? b / (N1 * N1) : 0;
+      D gr[DIM];
+      if constexpr (DIM == 3) {
+        gr[0] = a.tb.D[ax][bx] * a.tb.S[ay][by] * a.tb.S[az][bz];
+        gr[1] = a.tb.S[ax][bx] * a.tb.D[ay][by] * a.tb.S[az][bz];
+        gr[2] = a.tb.S[ax][bx] * a.tb.S[ay][by] * a.tb.D[az][bz];
+      } else {
+        gr[0] = a.tb.D[ax][bx] * a.tb.S[ay][by];
+        gr[1] = a.tb.S[ax][bx] * a.tb.D[ay][by];
+      }
+#pragma unroll
+      for (int c = 0; c < DIM; ++c)
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) H[c][d] += su[c][b] * gr[d] * a.invh;
+    }
+    D F[DIM][DIM], Fi[DIM][DIM], jm1;
+    kinematics<DIM, D>(H, F, Fi, jm1);
+    const int mid = material_of(a, e, t);
+    const D mu = mid ? a.mu[1] : a.mu[0];
+    const D lam = mid ? a.lam[1] : a.lam[0];
+    int w = 0;
+#pragma unroll
+    for (int i = 0; i < DIM; ++i)
+#pragma unroll
+      for (int j = 0; j < DIM; ++j) sq[t][w++] = Fi[i][j];
+    sq[t][w++] = mu - 2.0 * lam * log1p(jm1);
+    sq[t][w++] = 2.0 * lam;
+    sq[t][w] = mu;
+  }
+  __syncthreads();
+  if (!act) return;
+  int fi[DIM];
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) fi[i] = fmap[i * a.nn + node];
+  const D hd = a.wscale / a.invh;   // h^d
+  for (int b = 0; b < NV; ++b) {
+    const int bx = b % N1, by = (b / N1) % N1, bz = DIM == 3 ? b / (N1 * N1) : 0;
+    D acc[DIM][DIM] = {};
+    for (int q = 0; q < NV; ++q) {
+      const int qx = q % N1, qy = (q / N1) % N1, qz = DIM == 3 ? q / (N1 * N1) : 0;
+      D ga[DIM], gb[DIM], wq;
+      if constexpr (DIM == 3) {
+        ga[0] = a.tb.D[qx][ax] * a.tb.S[qy][ay] * a.tb.S[qz][az];
+        ga[1] = a.tb.S[qx][ax] * a.tb.D[qy][ay] * a.tb.S[qz][az];
+        ga[2] = a.tb.S[qx][ax] * a.tb.S[qy][ay] * a.tb.D[qz][az];
+        gb[0] = a.tb.D[qx][bx] * a.tb.S[qy][by] * a.tb.S[qz][bz];
+        gb[1] = a.tb.S[qx][bx] * a.tb.D[qy][by] * a.tb.S[qz][bz];
+        gb[2] = a.tb.S[qx][bx] * a.tb.S[qy][by] * a.tb.D[qz][bz];
+        wq = a.tb.w[qx] * a.tb.w[qy] * a.tb.w[qz] * hd;
+      } else {
+        ga[0] = a.tb.D[qx][ax] * a.tb.S[qy][ay];
+        ga[1] = a.tb.S[qx][ax] * a.tb.D[qy][ay];
+        gb[0] = a.tb.D[qx][bx] * a.tb.S[qy][by];
+        gb[1] = a.tb.S[qx][bx] * a.tb.D[qy][by];
+        wq = a.tb.w[qx] * a.tb.w[qy] * hd;
+      }
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        ga[d] *= a.invh;
+        gb[d] *= a.invh;
+      }
+      const D* s = sq[q];
+      D va[DIM], vb[DIM], gg = 0;
+#pragma unroll
+      for (int j = 0; j < DIM; ++j) {
+        D sa = 0, sb = 0;
+#pragma unroll
+        for (int I = 0; I < DIM; ++I) {
+          sa += ga[I] * s[I * DIM + j];
+          sb += gb[I] * s[I * DIM + j];
+        }
+        va[j] = sa;
+        vb[j] = sb;
+        gg += ga[j] * gb[j];
+      }
+      const D c1 = s[DIM * DIM], l2 = s[DIM * DIM + 1], mu = s[DIM * DIM + 2];
+#pragma unroll
+      for (int i = 0; i < DIM; ++i)
+#pragma unroll
+        for (int k = 0; k < DIM; ++k)
+          acc[i][k] += wq * (c1 * va[k] * vb[i] + l2 * va[i] * vb[k] + (i == k ? mu * gg : 0.0));
+    }
+    const long long nodeb = (ex * P + bx) + (long long)a.L * ((ey * P + by) + (long long)a.L * (ez * P + bz));
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      const int fj = fmap[k * a.nn + nodeb];
+      if (fj < 0) continue;
+#pragma unroll
+      for (int i = 0; i < DIM; ++i)
+        if (fi[i] >= 0) atomic_add(K + (long long)fi[i] * nf + fj, acc[i][k]);
+    }
+  }
+}
+
+}  // namespace mfh

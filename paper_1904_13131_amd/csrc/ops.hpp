@@ -1,0 +1,37 @@
+// Launch table of the cell kernels, one entry per (dim, degree).
+#pragma once
+
+#include "common.hpp"
+
+namespace mfh {
+
+struct OpFns {
+  // tangent vmult per policy (0 R, 1 CF, 2 C2)
+  void (*tangent_d[3])(const CellArgs<double>&, unsigned grid, hipStream_t);
+  void (*tangent_f[3])(const CellArgs<float>&, unsigned grid, hipStream_t);
+  void (*residual)(const CellArgs<double>&, unsigned grid, hipStream_t);
+  // quadrature data (min J and the policy cache in double / float)
+  void (*qpdata_d[3])(const CellArgs<double>&, double* cache, unsigned grid, hipStream_t);
+  void (*qpdata_f[3])(const CellArgs<double>&, float* cache, unsigned grid, hipStream_t);
+  void (*diag)(const CellArgs<double>&, unsigned grid, hipStream_t);
+  void (*coarse_assemble)(const CellArgs<double>&, const int* fmap, long long nf, double* K,
+                          unsigned grid, hipStream_t);
+  int cpb;        // cells per block of the pencil kernels
+  int cpb_diag;   // cells per block of the diagonal kernel
+  int cache_words[3];
+};
+
+const OpFns* op_fns(int dim, int degree);
+
+#define MFH_DECLARE_OPS(D, P) const OpFns* op_fns_##D##_##P();
+MFH_DECLARE_OPS(2, 1)
+MFH_DECLARE_OPS(2, 2)
+MFH_DECLARE_OPS(2, 3)
+MFH_DECLARE_OPS(2, 4)
+MFH_DECLARE_OPS(3, 1)
+MFH_DECLARE_OPS(3, 2)
+MFH_DECLARE_OPS(3, 3)
+MFH_DECLARE_OPS(3, 4)
+#undef MFH_DECLARE_OPS
+
+}  // namespace mfh

@@ -1,0 +1,1174 @@
+// Host orchestration of the mfh library: levels, workspace layout,
+// set_deformation, operator application, V-cycle, CG, Newton, and the C ABI.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/mfh.h"
+#include "ops.hpp"
+#include "tables.hpp"
+#include "vec.hpp"
+
+namespace mfh {
+
+const OpFns* op_fns(int dim, int degree) {
+  if (dim == 2) {
+    switch (degree) {
+      case 1: return op_fns_2_1();
+      case 2: return op_fns_2_2();
+      case 3: return op_fns_2_3();
+      case 4: return op_fns_2_4();
+    }
+  } else if (dim == 3) {
+    switch (degree) {
+      case 1: return op_fns_3_1();
+      case 2: return op_fns_3_2();
+      case 3: return op_fns_3_3();
+      case 4: return op_fns_3_4();
+    }
+  }
+  return nullptr;
+}
+
+struct Error : std::runtime_error {
+  mfh_status st;
+  Error(mfh_status s, const std::string& m) : std::runtime_error(m), st(s) {}
+};
+
+#define HIPCHECK(expr)                                                                        \
+  do {                                                                                        \
+    hipError_t _e = (expr);                                                                   \
+    if (_e != hipSuccess)                                                                     \
+      throw Error(MFH_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(_e));           \
+  } while (0)
+
+static void check_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw Error(MFH_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Bump allocator over the caller's workspace; with base == nullptr it only measures.
+struct Bump {
+  char* base = nullptr;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t n) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += n * sizeof(T) + 8;   // +8: never hand out zero-size slots at the same address
+    return p;
+  }
+};
+
+struct DevBand {
+  int nout = 0, nin = 0, K = 0;
+  int* start = nullptr;
+  double* v64 = nullptr;
+  float* v32 = nullptr;
+  BandHost host;
+  template <typename T>
+  Band<T> get() const;
+};
+template <>
+Band<double> DevBand::get<double>() const { return {nout, nin, K, start, v64}; }
+template <>
+Band<float> DevBand::get<float>() const { return {nout, nin, K, start, v32}; }
+
+struct Level {
+  int N = 0, L = 0;
+  long long nn = 0, ndofs = 0, ncells = 0;
+  double h = 0;
+  Lattice lt{};
+  int nwords = 0;
+  uint32_t* bits = nullptr;
+  double* u64 = nullptr;
+  float* u32 = nullptr;
+  double* cache64 = nullptr;
+  float* cache32 = nullptr;
+  double* diag64 = nullptr;
+  void* dinv = nullptr;        // vcycle dtype
+  void *vb = nullptr, *vx = nullptr, *vt = nullptr, *vd = nullptr;   // vcycle dtype
+  double lam_max = 0;
+  std::vector<double> cd, cr;  // Chebyshev step coefficients
+  DevBand P1, R1, I1;          // transfers from level-1 into this level (l >= 1)
+};
+
+}  // namespace mfh
+
+struct mfh_problem {
+  mfh_desc d{};
+  std::vector<double> mu, lam, incl;
+  hipStream_t stream = nullptr;
+  const mfh::OpFns* ops = nullptr;
+  mfh::Tables<double> tb64{};
+  mfh::Tables<float> tb32{};
+  std::vector<mfh::Level> lv;
+  int nq = 0;                        // quadrature points per cell
+  // shared buffers
+  double* incl_dev = nullptr;
+  double* sc = nullptr;              // device scalars
+  double* part = nullptr;            // reduction partials
+  double* minj = nullptr;            // per level min J
+  double* hist = nullptr;            // Lanczos alpha/beta history (2 * eig_iters)
+  char* tmpA = nullptr;
+  char* tmpB = nullptr;
+  double *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_Ap = nullptr;
+  double *nw_R = nullptr, *nw_dg = nullptr, *nw_b = nullptr, *nw_du = nullptr;
+  // coarse level
+  long long nf = 0;
+  int* fmap = nullptr;               // dof -> free index or -1
+  int* dof_of = nullptr;             // free index -> dof
+  double* Kinv = nullptr;
+  double *gj_P = nullptr, *gj_C = nullptr, *gj_R = nullptr, *crf = nullptr, *czf = nullptr;
+  int* flag = nullptr;
+  std::vector<int> h_fmap, h_dof_of;
+  bool deformed = false;
+  bool precond_ready = false;        // diagonals, lambda_max, coarse inverse built
+  bool has_coarse = false;           // coarse level small enough for the dense direct solve
+  std::string err;
+  // kernel timers
+  bool timing = false;
+  std::vector<hipEvent_t> ev;        // pairs (start, stop)
+  size_t ev_used = 0;
+  ~mfh_problem() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  }
+};
+
+namespace mfh {
+
+namespace {
+
+thread_local std::string g_err;
+
+using Clock = std::chrono::steady_clock;
+double ms_since(Clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
+}
+
+void validate(const mfh_desc* d) {
+  auto bad = [](const std::string& m) { throw Error(MFH_ERR_INVALID_ARG, m); };
+  if (!d) bad("descriptor is NULL");
+  if (d->dim != 2 && d->dim != 3) bad("dim must be 2 or 3");
+  if (d->degree < 1 || d->degree > kMaxDeg) bad("degree must be 1..4");
+  if (d->n_cells < 1) bad("n_cells must be >= 1");
+  if (d->n_levels < 1 || d->n_levels > 12) bad("n_levels must be 1..12");
+  if (d->n_cells % (1 << (d->n_levels - 1)) != 0) bad("n_cells must be divisible by 2^(n_levels-1)");
+  if (d->n_materials < 1 || d->n_materials > 2) bad("n_materials must be 1 or 2");
+  if (!d->mu || !d->lambda) bad("mu/lambda arrays are NULL");
+  for (int m = 0; m < d->n_materials; ++m)
+    if (!(d->mu[m] > 0) || !std::isfinite(d->lambda[m])) bad("material parameters must have mu > 0 and finite lambda");
+  if (d->n_inclusions < 0 || (d->n_inclusions > 0 && !d->inclusions)) bad("inclusions array is NULL");
+  for (int s = 0; s < d->n_inclusions; ++s) {
+    const double id = d->inclusions[s * (d->dim + 2) + d->dim + 1];
+    if (id != 0.0 && (id != 1.0 || d->n_materials < 2)) bad("inclusion material id must be 0 or 1 (< n_materials)");
+  }
+  if (d->dirichlet_mask >> (2 * d->dim * d->dim)) bad("dirichlet_mask has bits beyond 2*dim*dim");
+  if (d->qp_policy < 0 || d->qp_policy > 2) bad("qp_policy must be 0..2");
+  if (d->scatter != MFH_SCATTER_ATOMIC && d->scatter != MFH_SCATTER_COLOR) bad("bad scatter mode");
+  if (d->vcycle_dtype != MFH_F32 && d->vcycle_dtype != MFH_F64) bad("bad vcycle_dtype");
+  if (d->cheb_degree < 1 || d->cheb_degree > 16) bad("cheb_degree must be 1..16");
+  if (d->n_smooth < 1 || d->n_smooth > 8) bad("n_smooth must be 1..8");
+  if (d->eig_iters < 1 || d->eig_iters > 200) bad("eig_iters must be 1..200");
+  if (!(d->cheb_lo > 0) || !(d->cheb_hi > d->cheb_lo)) bad("need 0 < cheb_lo < cheb_hi");
+}
+
+// Largest coarse level that gets the dense FP64 direct solve; problems with a
+// larger coarsest level support operator application but no V-cycle / CG.
+constexpr long long kMaxCoarseDofs = 20000;
+
+// Host-side level geometry, transfer tables and coarse-level maps.
+void build_host(mfh_problem* P) {
+  const mfh_desc& d = P->d;
+  P->ops = op_fns(d.dim, d.degree);
+  if (!P->ops) throw Error(MFH_ERR_INVALID_ARG, "no kernels for this (dim, degree)");
+  P->tb64 = make_tables(d.degree);
+  P->tb32 = to_float(P->tb64);
+  const int n1 = d.degree + 1;
+  P->nq = d.dim == 3 ? n1 * n1 * n1 : n1 * n1;
+  P->lv.assign(d.n_levels, Level());
+  for (int l = 0; l < d.n_levels; ++l) {
+    Level& v = P->lv[l];
+    v.N = d.n_cells >> (d.n_levels - 1 - l);
+    v.L = d.degree * v.N + 1;
+    v.nn = d.dim == 3 ? (long long)v.L * v.L * v.L : (long long)v.L * v.L;
+    v.ndofs = d.dim * v.nn;
+    v.ncells = d.dim == 3 ? (long long)v.N * v.N * v.N : (long long)v.N * v.N;
+    v.h = 1.0 / v.N;
+    v.nwords = (P->nq + 31) / 32;
+    v.lt.L = v.L;
+    v.lt.dim = d.dim;
+    v.lt.nn = v.nn;
+    for (int c = 0; c < 3; ++c) {
+      unsigned fm = 0;
+      if (c < d.dim)
+        for (int f = 0; f < 2 * d.dim; ++f)
+          if ((d.dirichlet_mask >> (f * d.dim + c)) & 1u) fm |= 1u << f;
+      v.lt.fmask[c] = fm;
+    }
+    if (l >= 1) {
+      const Level& c = P->lv[l - 1];
+      const std::vector<double> Xf = lattice_coords(v.N, d.degree);
+      const std::vector<double> Xc = lattice_coords(c.N, d.degree);
+      const std::vector<double> P1 = eval_global_1d(c.N, d.degree, Xf);   // Lf x Lc
+      std::vector<double> R1((size_t)c.L * v.L);
+      for (int i = 0; i < v.L; ++i)
+        for (int j = 0; j < c.L; ++j) R1[(size_t)j * v.L + i] = P1[(size_t)i * c.L + j];
+      const std::vector<double> I1 = eval_global_1d(v.N, d.degree, Xc);   // Lc x Lf
+      v.P1.host = make_band(P1, v.L, c.L);
+      v.R1.host = make_band(R1, c.L, v.L);
+      v.I1.host = make_band(I1, c.L, v.L);
+      for (DevBand* b : {&v.P1, &v.R1, &v.I1}) {
+        b->nout = b->host.nout;
+        b->nin = b->host.nin;
+        b->K = b->host.K;
+      }
+    }
+  }
+  // coarse-level free DoFs
+  Level& c = P->lv[0];
+  P->h_fmap.assign(c.ndofs, -1);
+  P->h_dof_of.clear();
+  P->has_coarse = c.ndofs <= kMaxCoarseDofs;
+  for (long long dof = 0; P->has_coarse && dof < c.ndofs; ++dof) {
+    const int comp = (int)(dof / c.nn);
+    long long n = dof - comp * c.nn;
+    const int i = (int)(n % c.L);
+    n /= c.L;
+    const int j = (int)(n % c.L);
+    const int k = (int)(n / c.L);
+    unsigned f = 0;
+    f |= (i == 0) ? 1u : 0u;
+    f |= (i == c.L - 1) ? 2u : 0u;
+    f |= (j == 0) ? 4u : 0u;
+    f |= (j == c.L - 1) ? 8u : 0u;
+    if (d.dim == 3) {
+      f |= (k == 0) ? 16u : 0u;
+      f |= (k == c.L - 1) ? 32u : 0u;
+    }
+    if (!(f & c.lt.fmask[comp])) {
+      P->h_fmap[dof] = (int)P->h_dof_of.size();
+      P->h_dof_of.push_back((int)dof);
+    }
+  }
+  P->nf = (long long)P->h_dof_of.size();
+}
+
+// Assigns every device buffer; returns the bytes used.
+size_t layout(mfh_problem* P, char* base) {
+  const mfh_desc& d = P->d;
+  Bump b;
+  b.base = base;
+  const size_t vs = d.vcycle_dtype == MFH_F32 ? sizeof(float) : sizeof(double);
+  const int nw = P->ops->cache_words[d.qp_policy];
+  for (size_t l = 0; l < P->lv.size(); ++l) {
+    Level& v = P->lv[l];
+    v.bits = b.take<uint32_t>((size_t)v.ncells * v.nwords);
+    v.u64 = b.take<double>(v.ndofs);
+    v.u32 = b.take<float>(v.ndofs);
+    v.cache64 = nw ? b.take<double>((size_t)nw * P->nq * v.ncells) : nullptr;
+    v.cache32 = nw ? b.take<float>((size_t)nw * P->nq * v.ncells) : nullptr;
+    v.diag64 = b.take<double>(v.ndofs);
+    v.dinv = b.take<char>(vs * v.ndofs);
+    v.vb = b.take<char>(vs * v.ndofs);
+    v.vx = b.take<char>(vs * v.ndofs);
+    v.vt = b.take<char>(vs * v.ndofs);
+    v.vd = b.take<char>(vs * v.ndofs);
+    for (DevBand* db : {&v.P1, &v.R1, &v.I1}) {
+      if (!db->nout) continue;
+      db->start = b.take<int>(db->nout);
+      db->v64 = b.take<double>((size_t)db->nout * db->K);
+      db->v32 = b.take<float>((size_t)db->nout * db->K);
+    }
+  }
+  const Level& top = P->lv.back();
+  P->incl_dev = b.take<double>((size_t)std::max(1, d.n_inclusions) * (d.dim + 2));
+  P->sc = b.take<double>(SC_COUNT);
+  P->part = b.take<double>((size_t)std::max<long long>(kRedBlocks, top.ncells / P->ops->cpb + 16));
+  P->minj = b.take<double>(P->lv.size());
+  P->hist = b.take<double>(2 * (size_t)d.eig_iters + 2);
+  // transfer intermediates: dim * Lf^(dim-1) * Lc entries of up to 8 bytes
+  size_t tmp = 8;
+  for (size_t l = 1; l < P->lv.size(); ++l) {
+    const size_t Lf = P->lv[l].L, Lc = P->lv[l - 1].L;
+    const size_t sz = d.dim * (d.dim == 3 ? Lf * Lf * Lc : Lf * Lc);
+    tmp = std::max(tmp, sz);
+  }
+  P->tmpA = b.take<char>(tmp * 8);
+  P->tmpB = b.take<char>(tmp * 8);
+  P->cg_r = b.take<double>(top.ndofs);
+  P->cg_z = b.take<double>(top.ndofs);
+  P->cg_p = b.take<double>(top.ndofs);
+  P->cg_Ap = b.take<double>(top.ndofs);
+  P->nw_R = b.take<double>(top.ndofs);
+  P->nw_dg = b.take<double>(top.ndofs);
+  P->nw_b = b.take<double>(top.ndofs);
+  P->nw_du = b.take<double>(top.ndofs);
+  const Level& c = P->lv[0];
+  P->fmap = b.take<int>(P->has_coarse ? c.ndofs : 1);
+  P->dof_of = b.take<int>(std::max<long long>(1, P->nf));
+  P->Kinv = b.take<double>((size_t)P->nf * P->nf);
+  P->gj_P = b.take<double>(64 * 64);
+  P->gj_C = b.take<double>((size_t)P->nf * 64);
+  P->gj_R = b.take<double>((size_t)P->nf * 64);
+  P->crf = b.take<double>(std::max<long long>(1, P->nf));
+  P->czf = b.take<double>(std::max<long long>(1, P->nf));
+  P->flag = b.take<int>(1);
+  return b.off + 256;
+}
+
+template <typename T>
+CellArgs<T> cell_args(const mfh_problem* P, const Level& v, const T* u, const T* cache, const T* x, T* y);
+
+template <typename T>
+void fill_common(const mfh_problem* P, const Level& v, CellArgs<T>& a) {
+  a.N = v.N;
+  a.L = v.L;
+  a.nn = v.nn;
+  a.ncells = v.ncells;
+  a.nlaunch = v.ncells;
+  a.color = -1;
+  for (int c = 0; c < 3; ++c) a.fmask[c] = v.lt.fmask[c];
+  a.invh = (T)(1.0 / v.h);
+  a.wscale = (T)std::pow(v.h, P->d.dim - 1);
+  for (int m = 0; m < 2; ++m) {
+    const int mm = m < P->d.n_materials ? m : 0;
+    a.mu[m] = (T)P->mu[mm];
+    a.lam[m] = (T)P->lam[mm];
+  }
+  a.matbits = v.bits;
+  a.nwords = v.nwords;
+  a.blockmin = P->part;
+  a.mask_in = 1;
+}
+
+template <>
+CellArgs<double> cell_args<double>(const mfh_problem* P, const Level& v, const double* u, const double* cache,
+                                   const double* x, double* y) {
+  CellArgs<double> a{};
+  a.tb = P->tb64;
+  fill_common(P, v, a);
+  a.u = u;
+  a.cache = cache;
+  a.x = x;
+  a.y = y;
+  return a;
+}
+template <>
+CellArgs<float> cell_args<float>(const mfh_problem* P, const Level& v, const float* u, const float* cache,
+                                 const float* x, float* y) {
+  CellArgs<float> a{};
+  a.tb = P->tb32;
+  fill_common(P, v, a);
+  a.u = u;
+  a.cache = cache;
+  a.x = x;
+  a.y = y;
+  return a;
+}
+
+template <typename T>
+struct Sel;
+template <>
+struct Sel<double> {
+  static const double* u(const Level& v) { return v.u64; }
+  static const double* cache(const Level& v) { return v.cache64; }
+  static void run(const OpFns* o, int pol, const CellArgs<double>& a, unsigned g, hipStream_t s) {
+    o->tangent_d[pol](a, g, s);
+  }
+  static Band<double> band(const DevBand& b) { return b.get<double>(); }
+};
+template <>
+struct Sel<float> {
+  static const float* u(const Level& v) { return v.u32; }
+  static const float* cache(const Level& v) { return v.cache32; }
+  static void run(const OpFns* o, int pol, const CellArgs<float>& a, unsigned g, hipStream_t s) {
+    o->tangent_f[pol](a, g, s);
+  }
+  static Band<float> band(const DevBand& b) { return b.get<float>(); }
+};
+
+long long color_count(int N, int dim, int color) {
+  long long c = 1;
+  for (int ax = 0; ax < dim; ++ax) {
+    const int bit = (color >> ax) & 1;
+    c *= (N - bit + 1) / 2;
+  }
+  return c;
+}
+
+void timer_mark(mfh_problem* P) {
+  if (!P->timing) return;
+  if (P->ev_used == P->ev.size()) {
+    hipEvent_t e;
+    HIPCHECK(hipEventCreate(&e));
+    P->ev.push_back(e);
+  }
+  HIPCHECK(hipEventRecord(P->ev[P->ev_used++], P->stream));
+}
+
+// y = K_c x (mask_in = 1) or y = (I - C) K x with constrained rows zero (mask_in = 0).
+template <typename T>
+void vmult(mfh_problem* P, int l, const T* x, T* y, int mask_in = 1) {
+  const Level& v = P->lv[l];
+  fill_dirichlet<T>(y, mask_in ? x : nullptr, v.ndofs, v.lt, P->stream);
+  CellArgs<T> a = cell_args<T>(P, v, Sel<T>::u(v), Sel<T>::cache(v), x, y);
+  a.mask_in = mask_in;
+  const int cpb = P->ops->cpb;
+  timer_mark(P);
+  if (P->d.scatter == MFH_SCATTER_ATOMIC) {
+    Sel<T>::run(P->ops, P->d.qp_policy, a, (unsigned)((v.ncells + cpb - 1) / cpb), P->stream);
+  } else {
+    for (int color = 0; color < (1 << P->d.dim); ++color) {
+      a.color = color;
+      a.nlaunch = color_count(v.N, P->d.dim, color);
+      if (!a.nlaunch) continue;
+      Sel<T>::run(P->ops, P->d.qp_policy, a, (unsigned)((a.nlaunch + cpb - 1) / cpb), P->stream);
+    }
+  }
+  timer_mark(P);
+}
+
+void residual(mfh_problem* P, const double* u, double* r) {
+  const Level& v = P->lv.back();
+  fill_dirichlet<double>(r, nullptr, v.ndofs, v.lt, P->stream);
+  CellArgs<double> a = cell_args<double>(P, v, u, nullptr, nullptr, r);
+  const int cpb = P->ops->cpb;
+  if (P->d.scatter == MFH_SCATTER_ATOMIC) {
+    P->ops->residual(a, (unsigned)((v.ncells + cpb - 1) / cpb), P->stream);
+  } else {
+    for (int color = 0; color < (1 << P->d.dim); ++color) {
+      a.color = color;
+      a.nlaunch = color_count(v.N, P->d.dim, color);
+      if (!a.nlaunch) continue;
+      P->ops->residual(a, (unsigned)((a.nlaunch + cpb - 1) / cpb), P->stream);
+    }
+  }
+}
+
+// Applies the three (two) 1-D sweeps of a tensor-product transfer.
+template <typename T>
+void transfer(mfh_problem* P, const DevBand& band, int Lin, int Lout, const T* in, T* out, bool add, bool mask,
+              const Lattice& out_lt) {
+  const int dim = P->d.dim;
+  SweepArgs<T> a{};
+  a.band = Sel<T>::band(band);
+  a.comps = dim;
+  a.add = 0;
+  a.mask = 0;
+  int n[3] = {Lin, Lin, dim == 3 ? Lin : 1};
+  const T* src = in;
+  T* bufs[2] = {reinterpret_cast<T*>(P->tmpA), reinterpret_cast<T*>(P->tmpB)};
+  for (int ax = 0; ax < dim; ++ax) {
+    const bool last = ax == dim - 1;
+    a.axis = ax;
+    a.n[0] = n[0];
+    a.n[1] = n[1];
+    a.n[2] = n[2];
+    a.in_cs = (long long)n[0] * n[1] * n[2];
+    int m[3] = {n[0], n[1], n[2]};
+    m[ax] = Lout;
+    a.out_cs = (long long)m[0] * m[1] * m[2];
+    T* dst = last ? out : bufs[ax & 1];
+    if (last) {
+      a.add = add ? 1 : 0;
+      a.mask = mask ? 1 : 0;
+      a.lt = out_lt;
+    }
+    sweep<T>(src, dst, a, P->stream);
+    src = dst;
+    n[0] = m[0];
+    n[1] = m[1];
+    n[2] = m[2];
+  }
+}
+
+template <typename T>
+void prolongate(mfh_problem* P, int l, const T* xc, T* yf, bool add) {
+  const Level& f = P->lv[l];
+  const Level& c = P->lv[l - 1];
+  transfer<T>(P, f.P1, c.L, f.L, xc, yf, add, true, f.lt);
+}
+
+template <typename T>
+void restrict_(mfh_problem* P, int l, const T* xf, T* yc) {
+  const Level& f = P->lv[l];
+  const Level& c = P->lv[l - 1];
+  transfer<T>(P, f.R1, f.L, c.L, xf, yc, false, true, c.lt);
+}
+
+// ---- smoother, V-cycle ---------------------------------------------------------------
+
+template <typename T>
+void cheb_apply(mfh_problem* P, int l, const T* f, T* x, bool xzero) {
+  Level& v = P->lv[l];
+  T* t = static_cast<T*>(v.vt);
+  T* dvec = static_cast<T*>(v.vd);
+  const T* dinv = static_cast<const T*>(v.dinv);
+  for (int j = 0; j < P->d.cheb_degree; ++j) {
+    const bool first_zero = (j == 0 && xzero);
+    const T* tt = nullptr;
+    if (!first_zero) {
+      vmult<T>(P, l, x, t);
+      tt = t;
+    }
+    cheb_step<T>(f, tt, dinv, dvec, x, (T)v.cd[j], (T)v.cr[j], first_zero ? 1 : 0, v.ndofs, P->stream);
+  }
+}
+
+template <typename T>
+void smooth(mfh_problem* P, int l, const T* f, T* x, bool xzero) {
+  for (int s = 0; s < P->d.n_smooth; ++s) cheb_apply<T>(P, l, f, x, xzero && s == 0);
+}
+
+template <typename T>
+void coarse_solve(mfh_problem* P, const T* b, T* x) {
+  const Level& c = P->lv[0];
+  fill<T>(x, T(0), c.ndofs, P->stream);
+  if (P->nf) coarse_apply<T>(P->Kinv, P->nf, P->dof_of, b, P->crf, P->czf, x, P->stream);
+}
+
+template <typename T>
+void vcycle_level(mfh_problem* P, int l, const T* b, T* x) {
+  if (l == 0) {
+    coarse_solve<T>(P, b, x);
+    return;
+  }
+  Level& v = P->lv[l];
+  Level& c = P->lv[l - 1];
+  T* t = static_cast<T*>(v.vt);
+  smooth<T>(P, l, b, x, true);
+  vmult<T>(P, l, x, t);
+  lincomb3<T>(t, T(1), b, T(-1), t, T(0), nullptr, v.ndofs, P->stream);
+  restrict_<T>(P, l, t, static_cast<T*>(c.vb));
+  vcycle_level<T>(P, l - 1, static_cast<T*>(c.vb), static_cast<T*>(c.vx));
+  prolongate<T>(P, l, static_cast<T*>(c.vx), x, true);
+  smooth<T>(P, l, b, x, false);
+}
+
+void vcycle(mfh_problem* P, const double* r, double* z) {
+  const int top = (int)P->lv.size() - 1;
+  Level& v = P->lv[top];
+  if (P->d.vcycle_dtype == MFH_F32) {
+    cast<double, float>(r, static_cast<float*>(v.vb), v.ndofs, P->stream);
+    vcycle_level<float>(P, top, static_cast<float*>(v.vb), static_cast<float*>(v.vx));
+    cast<float, double>(static_cast<float*>(v.vx), z, v.ndofs, P->stream);
+  } else {
+    vcycle_level<double>(P, top, r, z);
+  }
+}
+
+double read_scalar(mfh_problem* P, const double* dev) {
+  double h = 0;
+  HIPCHECK(hipMemcpyAsync(&h, dev, sizeof(double), hipMemcpyDeviceToHost, P->stream));
+  HIPCHECK(hipStreamSynchronize(P->stream));
+  return h;
+}
+
+// Largest eigenvalue of D^-1 A on level l from eig_iters Jacobi-PCG steps
+// (CG-Lanczos relation), in the V-cycle precision.
+template <typename T>
+double lambda_max(mfh_problem* P, int l) {
+  Level& v = P->lv[l];
+  const long long n = v.ndofs;
+  T* r = static_cast<T*>(v.vb);
+  T* z = static_cast<T*>(v.vx);
+  T* p = static_cast<T*>(v.vd);
+  T* Ap = static_cast<T*>(v.vt);
+  const T* dinv = static_cast<const T*>(v.dinv);
+  splitmix_uniform<T>(r, n, 0x5EEDull, P->stream);
+  zero_constrained<T>(r, n, v.lt, P->stream);
+  cheb_step<T>(r, nullptr, dinv, z, p, T(0), T(1), 1, n, P->stream);   // z = D^-1 r, p = z
+  dot<T, T>(r, z, n, P->part, P->sc + SC_RZ, P->stream);
+  const int it = P->d.eig_iters;
+  for (int j = 0; j < it; ++j) {
+    vmult<T>(P, l, p, Ap);
+    dot<T, T>(p, Ap, n, P->part, P->sc + SC_PAP, P->stream);
+    scalar_div(P->sc, SC_ALPHA, SC_RZ, SC_PAP, -1, -1, P->hist, j, P->stream);
+    lanczos_update<T>(r, z, Ap, dinv, n, P->sc, P->part, P->stream);
+    scalar_div(P->sc, SC_BETA, SC_RZNEW, SC_RZ, SC_RZ, SC_RZNEW, P->hist, it + j, P->stream);
+    cg_pupdate<T>(p, z, n, P->sc, P->stream);
+  }
+  std::vector<double> h(2 * it);
+  HIPCHECK(hipMemcpyAsync(h.data(), P->hist, sizeof(double) * 2 * it, hipMemcpyDeviceToHost, P->stream));
+  HIPCHECK(hipStreamSynchronize(P->stream));
+  std::vector<double> al, be;
+  for (int j = 0; j < it; ++j) {
+    const double a = h[j], bta = h[it + j];
+    if (!(a > 0) || !std::isfinite(a)) break;
+    al.push_back(a);
+    be.push_back(bta);
+    if (!(bta > 0) || !std::isfinite(bta)) break;
+  }
+  const int m = (int)al.size();
+  if (m == 0) throw Error(MFH_ERR_BREAKDOWN, "eigenvalue estimate: CG broke down on level " + std::to_string(l));
+  std::vector<double> dg(m), off(m > 1 ? m - 1 : 0);
+  for (int j = 0; j < m; ++j) {
+    dg[j] = 1.0 / al[j] + (j > 0 ? be[j - 1] / al[j - 1] : 0.0);
+    if (j + 1 < m) off[j] = std::sqrt(be[j]) / al[j];
+  }
+  return tridiag_max_eig(dg, off);
+}
+
+void set_cheb_coeffs(mfh_problem* P, Level& v) {
+  const double lo = P->d.cheb_lo * v.lam_max, hi = P->d.cheb_hi * v.lam_max;
+  const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+  v.cd.assign(P->d.cheb_degree, 0.0);
+  v.cr.assign(P->d.cheb_degree, 0.0);
+  double rho = 1.0 / sigma;
+  v.cr[0] = 1.0 / theta;
+  for (int j = 1; j < P->d.cheb_degree; ++j) {
+    const double rn = 1.0 / (2.0 * sigma - rho);
+    v.cd[j] = rn * rho;
+    v.cr[j] = 2.0 * rn / delta;
+    rho = rn;
+  }
+}
+
+void interpolate_down(mfh_problem* P, int l) {
+  const Level& f = P->lv[l];
+  const Level& c = P->lv[l - 1];
+  transfer<double>(P, f.I1, f.L, c.L, f.u64, c.u64, false, false, c.lt);
+}
+
+// Builds every level operator about u (Sec. 6).  Returns min J over all levels.
+double set_deformation(mfh_problem* P, const double* u) {
+  const mfh_desc& d = P->d;
+  const int nl = (int)P->lv.size();
+  hipStream_t s = P->stream;
+  Level& top = P->lv.back();
+  HIPCHECK(hipMemcpyAsync(top.u64, u, sizeof(double) * top.ndofs, hipMemcpyDeviceToDevice, s));
+  for (int l = nl - 1; l >= 1; --l) interpolate_down(P, l);
+  const int pol = d.qp_policy;
+  const int cpb = P->ops->cpb;
+  for (int l = 0; l < nl; ++l) {
+    Level& v = P->lv[l];
+    cast<double, float>(v.u64, v.u32, v.ndofs, s);
+    CellArgs<double> a = cell_args<double>(P, v, v.u64, nullptr, nullptr, nullptr);
+    const unsigned g = (unsigned)((v.ncells + cpb - 1) / cpb);
+    P->ops->qpdata_d[pol](a, v.cache64, g, s);
+    if (pol != MFH_QP_RECOMPUTE) P->ops->qpdata_f[pol](a, v.cache32, g, s);
+    min_reduce(P->part, (int)g, P->minj + l, s);
+  }
+  check_launch("quadrature data");
+  std::vector<double> mj(nl);
+  HIPCHECK(hipMemcpyAsync(mj.data(), P->minj, sizeof(double) * nl, hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  double minJ = 1e300;
+  for (double m : mj) minJ = std::fmin(minJ, m);
+  if (!(minJ > 0)) {
+    P->deformed = false;
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "deformation inverts a quadrature point: min J = %.6g", minJ);
+    throw Error(MFH_ERR_INVERTED, buf);
+  }
+  P->deformed = true;
+  P->precond_ready = false;
+  HIPCHECK(hipStreamSynchronize(s));
+  return minJ;
+}
+
+// Preconditioner data about the current linearisation point: operator
+// diagonals, Chebyshev intervals (lambda_max) and the coarse inverse.  Built on
+// the first solver call after every set_deformation.
+void setup_precond(mfh_problem* P) {
+  if (P->precond_ready) return;
+  const mfh_desc& d = P->d;
+  const int nl = (int)P->lv.size();
+  hipStream_t s = P->stream;
+  // diagonals and smoother intervals
+  for (int l = 0; l < nl; ++l) {
+    Level& v = P->lv[l];
+    fill<double>(v.diag64, 0.0, v.ndofs, s);
+    CellArgs<double> a = cell_args<double>(P, v, v.u64, nullptr, nullptr, v.diag64);
+    P->ops->diag(a, (unsigned)((v.ncells + P->ops->cpb_diag - 1) / P->ops->cpb_diag), s);
+    set_constrained<double>(v.diag64, 1.0, v.ndofs, v.lt, s);
+    if (d.vcycle_dtype == MFH_F32)
+      reciprocal<float>(v.diag64, static_cast<float*>(v.dinv), v.ndofs, s);
+    else
+      reciprocal<double>(v.diag64, static_cast<double*>(v.dinv), v.ndofs, s);
+  }
+  check_launch("diagonal");
+  for (int l = 1; l < nl; ++l) {
+    Level& v = P->lv[l];
+    v.lam_max = d.vcycle_dtype == MFH_F32 ? lambda_max<float>(P, l) : lambda_max<double>(P, l);
+    set_cheb_coeffs(P, v);
+  }
+  // coarse level: dense FP64 tangent on free DoFs, inverted in place
+  Level& c = P->lv[0];
+  const long long nf = P->nf;
+  if (nf) {
+    fill<double>(P->Kinv, 0.0, nf * nf, s);
+    CellArgs<double> a = cell_args<double>(P, c, c.u64, nullptr, nullptr, nullptr);
+    P->ops->coarse_assemble(a, P->fmap, nf, P->Kinv, (unsigned)c.ncells, s);
+    fill<int>(P->flag, 0, 1, s);
+    for (long long k0 = 0; k0 < nf; k0 += 64) {
+      const int nb = (int)std::min<long long>(64, nf - k0);
+      gj_pivot(P->Kinv, nf, k0, nb, P->gj_P, P->flag, s);
+      gj_panels(P->Kinv, nf, k0, nb, P->gj_P, P->gj_C, P->gj_R, s);
+      gj_update(P->Kinv, nf, k0, nb, P->gj_C, P->gj_R, s);
+      gj_finish(P->Kinv, nf, k0, nb, P->gj_C, P->gj_R, P->gj_P, s);
+    }
+    check_launch("coarse inverse");
+    int flag = 0;
+    HIPCHECK(hipMemcpyAsync(&flag, P->flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    if (flag) throw Error(MFH_ERR_NOT_SPD, "coarse-level tangent is not positive definite");
+  }
+  HIPCHECK(hipStreamSynchronize(s));
+  P->precond_ready = true;
+}
+
+struct CgResult {
+  int iters = 0;
+  double relres = 0;
+  mfh_status st = MFH_OK;
+};
+
+CgResult cg_solve(mfh_problem* P, const double* b, double* x, double rtol, int max_it) {
+  Level& v = P->lv.back();
+  const long long n = v.ndofs;
+  hipStream_t s = P->stream;
+  double* r = P->cg_r;
+  double* z = P->cg_z;
+  double* p = P->cg_p;
+  double* Ap = P->cg_Ap;
+  CgResult res;
+  fill<double>(x, 0.0, n, s);
+  HIPCHECK(hipMemcpyAsync(r, b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  dot<double, double>(b, b, n, P->part, P->sc + SC_BB, s);
+  const double bb = read_scalar(P, P->sc + SC_BB);
+  if (!std::isfinite(bb)) {
+    res.st = MFH_ERR_BREAKDOWN;
+    res.relres = NAN;
+    return res;
+  }
+  if (bb == 0.0) return res;
+  vcycle(P, r, z);
+  HIPCHECK(hipMemcpyAsync(p, z, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  dot<double, double>(r, z, n, P->part, P->sc + SC_RZ, s);
+  res.st = MFH_ERR_NOT_CONVERGED;
+  for (int it = 1; it <= max_it; ++it) {
+    vmult<double>(P, (int)P->lv.size() - 1, p, Ap);
+    dot<double, double>(p, Ap, n, P->part, P->sc + SC_PAP, s);
+    scalar_div(P->sc, SC_ALPHA, SC_RZ, SC_PAP, -1, -1, nullptr, 0, s);
+    cg_update<double>(x, r, p, Ap, n, P->sc, P->part, s);
+    double h[SC_COUNT];
+    HIPCHECK(hipMemcpyAsync(h, P->sc, sizeof(double) * SC_COUNT, hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    res.iters = it;
+    const double pAp = h[SC_PAP], rr = h[SC_RR];
+    if (!(pAp > 0) || !std::isfinite(rr)) {
+      res.st = MFH_ERR_BREAKDOWN;
+      break;
+    }
+    res.relres = std::sqrt(rr / bb);
+    if (res.relres <= rtol) {
+      res.st = MFH_OK;
+      break;
+    }
+    if (it == max_it) break;
+    vcycle(P, r, z);
+    dot<double, double>(r, z, n, P->part, P->sc + SC_RZNEW, s);
+    scalar_div(P->sc, SC_BETA, SC_RZNEW, SC_RZ, SC_RZ, SC_RZNEW, nullptr, 0, s);
+    cg_pupdate<double>(p, z, n, P->sc, s);
+  }
+  // explicit final residual |b - K_c x| / |b|
+  vmult<double>(P, (int)P->lv.size() - 1, x, Ap);
+  lincomb3<double>(r, 1.0, b, -1.0, Ap, 0.0, nullptr, n, s);
+  dot<double, double>(r, r, n, P->part, P->sc + SC_TMP, s);
+  const double rr = read_scalar(P, P->sc + SC_TMP);
+  if (res.st != MFH_ERR_BREAKDOWN) res.relres = std::sqrt(rr / bb);
+  check_launch("cg");
+  return res;
+}
+
+double norm2(mfh_problem* P, const double* v, long long n) {
+  dot<double, double>(v, v, n, P->part, P->sc + SC_TMP, P->stream);
+  return std::sqrt(read_scalar(P, P->sc + SC_TMP));
+}
+
+template <typename F>
+mfh_status guarded(mfh_problem* P, F&& f) {
+  try {
+    f();
+    if (P) P->err.clear();
+    return MFH_OK;
+  } catch (const Error& e) {
+    if (P)
+      P->err = e.what();
+    else
+      g_err = e.what();
+    return e.st;
+  } catch (const std::exception& e) {
+    if (P)
+      P->err = e.what();
+    else
+      g_err = e.what();
+    return MFH_ERR_INVALID_ARG;
+  }
+}
+
+void need(bool c, const char* m) {
+  if (!c) throw Error(MFH_ERR_INVALID_ARG, m);
+}
+
+void check_level(const mfh_problem* P, int level) {
+  need(level >= 0 && level < (int)P->lv.size(), "level out of range");
+}
+
+}  // namespace
+}  // namespace mfh
+
+using namespace mfh;
+
+extern "C" {
+
+void mfh_desc_defaults(mfh_desc* d) {
+  if (!d) return;
+  std::memset(d, 0, sizeof(*d));
+  d->n_levels = 1;
+  d->n_materials = 1;
+  d->qp_policy = MFH_QP_RECOMPUTE;
+  d->scatter = MFH_SCATTER_ATOMIC;
+  d->vcycle_dtype = MFH_F32;
+  d->cheb_degree = 4;
+  d->n_smooth = 2;
+  d->eig_iters = 30;
+  d->cheb_lo = 0.6;
+  d->cheb_hi = 1.2;
+}
+
+mfh_status mfh_workspace_size(const mfh_desc* desc, size_t* bytes) {
+  return guarded(nullptr, [&] {
+    validate(desc);
+    need(bytes != nullptr, "bytes is NULL");
+    mfh_problem tmp;
+    tmp.d = *desc;
+    build_host(&tmp);
+    *bytes = layout(&tmp, nullptr);
+  });
+}
+
+mfh_status mfh_create(const mfh_desc* desc, void* ws, size_t bytes, void* stream, mfh_problem** out) {
+  std::unique_ptr<mfh_problem> P(new mfh_problem());
+  mfh_status st = guarded(nullptr, [&] {
+    validate(desc);
+    need(out != nullptr, "out is NULL");
+    need(ws != nullptr, "workspace is NULL");
+    need((reinterpret_cast<uintptr_t>(ws) & 255) == 0, "workspace must be 256-byte aligned");
+    P->d = *desc;
+    P->mu.assign(desc->mu, desc->mu + desc->n_materials);
+    P->lam.assign(desc->lambda, desc->lambda + desc->n_materials);
+    P->incl.assign(desc->inclusions, desc->inclusions + (size_t)desc->n_inclusions * (desc->dim + 2));
+    P->stream = static_cast<hipStream_t>(stream);
+    build_host(P.get());
+    const size_t need_bytes = layout(P.get(), nullptr);
+    if (bytes < need_bytes)
+      throw Error(MFH_ERR_WORKSPACE, "workspace too small: need " + std::to_string(need_bytes) + " bytes");
+    layout(P.get(), static_cast<char*>(ws));
+    hipStream_t s = P->stream;
+    if (!P->incl.empty())
+      HIPCHECK(hipMemcpyAsync(P->incl_dev, P->incl.data(), sizeof(double) * P->incl.size(), hipMemcpyHostToDevice, s));
+    for (Level& v : P->lv) {
+      material_bits(v.bits, v.ncells, v.N, desc->dim, desc->degree + 1, P->tb64, v.h, P->incl_dev,
+                    desc->n_inclusions, v.nwords, s);
+      for (DevBand* db : {&v.P1, &v.R1, &v.I1}) {
+        if (!db->nout) continue;
+        std::vector<float> v32(db->host.vals.begin(), db->host.vals.end());
+        HIPCHECK(hipMemcpyAsync(db->start, db->host.start.data(), sizeof(int) * db->nout, hipMemcpyHostToDevice, s));
+        HIPCHECK(hipMemcpyAsync(db->v64, db->host.vals.data(), sizeof(double) * db->host.vals.size(),
+                                hipMemcpyHostToDevice, s));
+        HIPCHECK(hipMemcpyAsync(db->v32, v32.data(), sizeof(float) * v32.size(), hipMemcpyHostToDevice, s));
+        HIPCHECK(hipStreamSynchronize(s));
+      }
+    }
+    const Level& c = P->lv[0];
+    if (P->has_coarse)
+      HIPCHECK(hipMemcpyAsync(P->fmap, P->h_fmap.data(), sizeof(int) * c.ndofs, hipMemcpyHostToDevice, s));
+    if (P->nf)
+      HIPCHECK(hipMemcpyAsync(P->dof_of, P->h_dof_of.data(), sizeof(int) * P->nf, hipMemcpyHostToDevice, s));
+    check_launch("create");
+    HIPCHECK(hipStreamSynchronize(s));
+    *out = P.release();
+  });
+  return st;
+}
+
+mfh_status mfh_destroy(mfh_problem* P) {
+  delete P;
+  return MFH_OK;
+}
+
+mfh_status mfh_n_dofs(const mfh_problem* P, int level, long long* n) {
+  return guarded(const_cast<mfh_problem*>(P), [&] {
+    need(P && n, "NULL argument");
+    check_level(P, level);
+    *n = P->lv[level].ndofs;
+  });
+}
+
+mfh_status mfh_set_deformation(mfh_problem* P, const double* u, double* min_J) {
+  if (!P) return MFH_ERR_INVALID_ARG;
+  return guarded(P, [&] {
+    need(u != nullptr, "u is NULL");
+    const double mj = set_deformation(P, u);
+    if (min_J) *min_J = mj;
+  });
+}
+
+mfh_status mfh_tangent_vmult(mfh_problem* P, int level, int dtype, const void* x, void* y) {
+  if (!P) return MFH_ERR_INVALID_ARG;
+  return guarded(P, [&] {
+    check_level(P, level);
+    need(x && y, "x/y is NULL");
+    need(x != y, "x and y must not overlap");
+    need(P->deformed, "set_deformation has not succeeded yet");
+    if (dtype == MFH_F64)
+      vmult<double>(P, level, static_cast<const double*>(x), static_cast<double*>(y));
+    else if (dtype == MFH_F32)
+      vmult<float>(P, level, static_cast<const float*>(x), static_cast<float*>(y));
+    else
+      need(false, "dtype must be MFH_F64 or MFH_F32");
+    check_launch("tangent_vmult");
+  });
+}
+
+mfh_status mfh_residual(mfh_problem* P, const double* u, double* r) {
+  if (!P) return MFH_ERR_INVALID_ARG;
+  return guarded(P, [&] {
+    need(u && r, "u/r is NULL");
+    need(u != r, "u and r must not overlap");
+    residual(P, u, r);
+    check_launch("residual");
+  });
+}
+
+mfh_status mfh_gmg_vcycle(mfh_problem* P, const double* r, double* z) {
+  if (!P) return MFH_ERR_INVALID_ARG;
+  return guarded(P, [&] {
+    need(r && z, "r/z is NULL");
+    need(r != z, "r and z must not overlap");
+    need(P->deformed, "set_deformation has not succeeded yet");
+    need(P->has_coarse, "coarsest level too large for the direct solve: use more levels");
+    setup_precond(P);
+    vcycle(P, r, z);
+    check_launch("gmg_vcycle");
+  });
+}
+
+mfh_status mfh_cg_solve(mfh_problem* P, const double* b, double* x, double rtol, int max_it, int* iters,
+                        double* relres) {
+  if (!P) return MFH_ERR_INVALID_ARG;
+  mfh_status st = MFH_OK;
+  mfh_status g = guarded(P, [&] {
+    need(b && x, "b/x is NULL");
+    need(b != x, "b and x must not overlap");
+    need(max_it >= 1 && rtol >= 0, "need max_it >= 1 and rtol >= 0");
+    need(P->deformed, "set_deformation has not succeeded yet");
+    need(P->has_coarse, "coarsest level too large for the direct solve: use more levels");
+    setup_precond(P);
+    CgResult r = cg_solve(P, b, x, rtol, max_it);
+    if (iters) *iters = r.iters;
+    if (relres) *relres = r.relres;
+    st = r.st;
+    if (st == MFH_ERR_NOT_CONVERGED) throw Error(st, "CG did not reach the tolerance within max_it iterations");
+    if (st == MFH_ERR_BREAKDOWN) throw Error(st, "CG breakdown (p^T A p <= 0 or NaN)");
+  });
+  return g;
+}
+
+const char* mfh_last_error(const mfh_problem* P) { return P ? P->err.c_str() : g_err.c_str(); }
+
+mfh_status mfh_apply_dirichlet(mfh_problem* P, double* u, const double* fv, double scale) {
+  if (!P) return MFH_ERR_INVALID_ARG;
+  return guarded(P, [&] {
+    need(u && fv, "NULL argument");
+    const Level& v = P->lv.back();
+    set_dirichlet(u, v.lt, fv, scale, v.ndofs, P->stream);
+    check_launch("apply_dirichlet");
+  });
+}
+
+mfh_status mfh_newton_solve(mfh_problem* P, double* u, const double* fv, int n_steps, double cg_rtol, int cg_max_it,
+                            double du_tol, double r_tol, int max_newton, mfh_newton_record* rec, int max_rec,
+                            int* n_rec) {
+  if (!P) return MFH_ERR_INVALID_ARG;
+  int nrec = 0;
+  mfh_status st = guarded(P, [&] {
+    need(u && fv, "NULL argument");
+    need(n_steps >= 1 && cg_max_it >= 1 && max_newton >= 1, "bad iteration limits");
+    need(P->has_coarse, "coarsest level too large for the direct solve: use more levels");
+    const Level& v = P->lv.back();
+    const long long n = v.ndofs;
+    hipStream_t s = P->stream;
+    const int top = (int)P->lv.size() - 1;
+    for (int step = 1; step <= n_steps; ++step) {
+      const double scale = (double)step / n_steps;
+      dirichlet_delta(u, P->nw_dg, v.lt, fv, scale, n, s);
+      double R0 = -1;
+      bool conv = false;
+      bool have_R = false;
+      for (int it = 0; it < max_newton; ++it) {
+        mfh_newton_record r{};
+        r.load_step = step;
+        r.newton_iter = it;
+        auto t0 = Clock::now();
+        if (!have_R) residual(P, u, P->nw_R);
+        HIPCHECK(hipStreamSynchronize(s));
+        r.residual_ms = ms_since(t0);
+        t0 = Clock::now();
+        r.min_J = set_deformation(P, u);
+        setup_precond(P);
+        r.setup_ms = ms_since(t0);
+        t0 = Clock::now();
+        if (it == 0) {
+          vmult<double>(P, top, P->nw_dg, P->nw_b, 0);   // (I - C) K dg
+          lincomb3<double>(P->nw_b, -1.0, P->nw_R, -1.0, P->nw_b, 0.0, nullptr, n, s);
+        } else {
+          lincomb3<double>(P->nw_b, -1.0, P->nw_R, 0.0, nullptr, 0.0, nullptr, n, s);
+        }
+        r.residual_norm = norm2(P, P->nw_b, n);
+        if (R0 < 0) R0 = r.residual_norm;
+        CgResult cr = cg_solve(P, P->nw_b, P->nw_du, cg_rtol, cg_max_it);
+        r.cg_iters = cr.iters;
+        r.cg_relres = cr.relres;
+        if (cr.st == MFH_ERR_BREAKDOWN) throw Error(cr.st, "CG breakdown inside Newton");
+        if (it == 0) axpby<double>(P->nw_du, P->nw_dg, 1.0, 1.0, n, s);
+        axpby<double>(u, P->nw_du, 1.0, 1.0, n, s);
+        r.solve_ms = ms_since(t0);
+        r.du_norm = norm2(P, P->nw_du, n);
+        t0 = Clock::now();
+        residual(P, u, P->nw_R);
+        have_R = true;
+        r.residual_after = norm2(P, P->nw_R, n);
+        r.residual_ms += ms_since(t0);
+        if (rec && nrec < max_rec) rec[nrec] = r;
+        ++nrec;
+        if (cr.st == MFH_ERR_NOT_CONVERGED) throw Error(cr.st, "CG did not converge inside Newton");
+        if (r.du_norm <= du_tol && (r.residual_after <= r_tol || r.residual_after <= r_tol * R0)) {
+          conv = true;
+          break;
+        }
+      }
+      if (!conv) throw Error(MFH_ERR_NOT_CONVERGED, "Newton did not converge in load step " + std::to_string(step));
+    }
+  });
+  if (n_rec) *n_rec = nrec;
+  return st;
+}
+
+mfh_status mfh_level_displacement(mfh_problem* P, int level, double* u) {
+  if (!P) return MFH_ERR_INVALID_ARG;
+  return guarded(P, [&] {
+    check_level(P, level);
+    need(u != nullptr, "u is NULL");
+    need(P->deformed, "set_deformation has not succeeded yet");
+    const Level& v = P->lv[level];
+    HIPCHECK(hipMemcpyAsync(u, v.u64, sizeof(double) * v.ndofs, hipMemcpyDeviceToDevice, P->stream));
+    HIPCHECK(hipStreamSynchronize(P->stream));
+  });
+}
+
+mfh_status mfh_level_diagonal(mfh_problem* P, int level, double* dg) {
+  if (!P) return MFH_ERR_INVALID_ARG;
+  return guarded(P, [&] {
+    check_level(P, level);
+    need(dg != nullptr, "d is NULL");
+    need(P->deformed, "set_deformation has not succeeded yet");
+    setup_precond(P);
+    const Level& v = P->lv[level];
+    HIPCHECK(hipMemcpyAsync(dg, v.diag64, sizeof(double) * v.ndofs, hipMemcpyDeviceToDevice, P->stream));
+    HIPCHECK(hipStreamSynchronize(P->stream));
+  });
+}
+
+mfh_status mfh_level_lambda_max(mfh_problem* P, int level, double* lam) {
+  if (!P) return MFH_ERR_INVALID_ARG;
+  return guarded(P, [&] {
+    need(level >= 1 && level < (int)P->lv.size(), "level must be 1..n_levels-1");
+    need(lam != nullptr, "lam is NULL");
+    need(P->deformed, "set_deformation has not succeeded yet");
+    setup_precond(P);
+    *lam = P->lv[level].lam_max;
+  });
+}
+
+mfh_status mfh_prolongate(mfh_problem* P, int level, int dtype, const void* x, void* y) {
+  if (!P) return MFH_ERR_INVALID_ARG;
+  return guarded(P, [&] {
+    need(level >= 1 && level < (int)P->lv.size(), "level must be 1..n_levels-1");
+    need(x && y && x != y, "bad x/y");
+    if (dtype == MFH_F64)
+      prolongate<double>(P, level, static_cast<const double*>(x), static_cast<double*>(y), false);
+    else if (dtype == MFH_F32)
+      prolongate<float>(P, level, static_cast<const float*>(x), static_cast<float*>(y), false);
+    else
+      need(false, "bad dtype");
+    check_launch("prolongate");
+  });
+}
+
+mfh_status mfh_restrict(mfh_problem* P, int level, int dtype, const void* x, void* y) {
+  if (!P) return MFH_ERR_INVALID_ARG;
+  return guarded(P, [&] {
+    need(level >= 1 && level < (int)P->lv.size(), "level must be 1..n_levels-1");
+    need(x && y && x != y, "bad x/y");
+    if (dtype == MFH_F64)
+      restrict_<double>(P, level, static_cast<const double*>(x), static_cast<double*>(y));
+    else if (dtype == MFH_F32)
+      restrict_<float>(P, level, static_cast<const float*>(x), static_cast<float*>(y));
+    else
+      need(false, "bad dtype");
+    check_launch("restrict");
+  });
+}
+
+mfh_status mfh_chebyshev(mfh_problem* P, int level, const void* f, void* x) {
+  if (!P) return MFH_ERR_INVALID_ARG;
+  return guarded(P, [&] {
+    need(level >= 1 && level < (int)P->lv.size(), "level must be 1..n_levels-1");
+    need(f && x && f != x, "bad f/x");
+    need(P->deformed, "set_deformation has not succeeded yet");
+    setup_precond(P);
+    if (P->d.vcycle_dtype == MFH_F32)
+      cheb_apply<float>(P, level, static_cast<const float*>(f), static_cast<float*>(x), false);
+    else
+      cheb_apply<double>(P, level, static_cast<const double*>(f), static_cast<double*>(x), false);
+    check_launch("chebyshev");
+  });
+}
+
+mfh_status mfh_timer_enable(mfh_problem* P, int enable) {
+  if (!P) return MFH_ERR_INVALID_ARG;
+  return guarded(P, [&] {
+    HIPCHECK(hipStreamSynchronize(P->stream));
+    P->ev_used = 0;
+    P->timing = enable != 0;
+  });
+}
+
+mfh_status mfh_timer_read(mfh_problem* P, double* total_ms, long long* launches) {
+  if (!P) return MFH_ERR_INVALID_ARG;
+  return guarded(P, [&] {
+    need(total_ms && launches, "NULL argument");
+    HIPCHECK(hipStreamSynchronize(P->stream));
+    double t = 0;
+    for (size_t i = 0; i + 1 < P->ev_used; i += 2) {
+      float ms = 0;
+      HIPCHECK(hipEventElapsedTime(&ms, P->ev[i], P->ev[i + 1]));
+      t += ms;
+    }
+    *total_ms = t;
+    *launches = (long long)(P->ev_used / 2);
+  });
+}
+
+}  // extern "C"

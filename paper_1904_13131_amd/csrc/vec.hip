@@ -1,0 +1,595 @@
+// Vector, transfer and coarse-solve kernels.
+#include "vec.hpp"
+
+namespace mfh {
+
+namespace {
+
+constexpr int kVB = 256;
+
+inline unsigned grid_for(long long n, long long cap = 16384) {
+  long long g = (n + kVB - 1) / kVB;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+inline unsigned red_grid(long long n) { return grid_for(n, kRedBlocks); }
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int s = kVB / 2; s > 0; s >>= 1) {
+    if (t < s) sh[t] += sh[t + s];
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+template <typename T>
+__global__ void k_fill_dirichlet(T* __restrict__ y, const T* __restrict__ x, long long n, Lattice lt) {
+  for (long long i = blockIdx.x * (long long)kVB + threadIdx.x; i < n; i += (long long)gridDim.x * kVB)
+    y[i] = (x != nullptr && constrained_dof(lt, i)) ? x[i] : T(0);
+}
+
+template <typename T>
+__global__ void k_zero_constrained(T* __restrict__ v, long long n, Lattice lt) {
+  for (long long i = blockIdx.x * (long long)kVB + threadIdx.x; i < n; i += (long long)gridDim.x * kVB)
+    if (constrained_dof(lt, i)) v[i] = T(0);
+}
+
+template <typename T>
+__global__ void k_fill(T* __restrict__ v, T val, long long n) {
+  for (long long i = blockIdx.x * (long long)kVB + threadIdx.x; i < n; i += (long long)gridDim.x * kVB) v[i] = val;
+}
+
+template <typename TI, typename TO>
+__global__ void k_cast(const TI* __restrict__ in, TO* __restrict__ out, long long n) {
+  for (long long i = blockIdx.x * (long long)kVB + threadIdx.x; i < n; i += (long long)gridDim.x * kVB)
+    out[i] = (TO)in[i];
+}
+
+template <typename TA, typename TB>
+__global__ void k_dot_part(const TA* __restrict__ a, const TB* __restrict__ b, long long n, double* part) {
+  __shared__ double sh[kVB];
+  double acc = 0;
+  for (long long i = blockIdx.x * (long long)kVB + threadIdx.x; i < n; i += (long long)gridDim.x * kVB)
+    acc += (double)a[i] * (double)b[i];
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void k_sum_final(const double* __restrict__ part, int np, double* out) {
+  __shared__ double sh[kVB];
+  double acc = 0;
+  for (int i = threadIdx.x; i < np; i += kVB) acc += part[i];
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) *out = s;
+}
+
+__global__ void k_min_final(const double* __restrict__ part, int np, double* out) {
+  __shared__ double sh[kVB];
+  double m = 1e300;
+  for (int i = threadIdx.x; i < np; i += kVB) m = part[i] < m ? part[i] : m;
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = kVB / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] = sh[threadIdx.x + s] < sh[threadIdx.x] ? sh[threadIdx.x + s] : sh[threadIdx.x];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sh[0];
+}
+
+__global__ void k_set_scalar(double* p, double v) { *p = v; }
+
+__global__ void k_scalar_div(double* sc, int dst, int num, int den, int copy_to, int copy_from, double* hist,
+                             int hidx) {
+  const double v = sc[num] / sc[den];
+  sc[dst] = v;
+  if (hist) hist[hidx] = v;
+  if (copy_to >= 0) sc[copy_to] = sc[copy_from];
+}
+
+template <typename T>
+__global__ void k_cg_update(T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p, const T* __restrict__ Ap,
+                            long long n, const double* __restrict__ sc, double* part) {
+  __shared__ double sh[kVB];
+  const T alpha = (T)sc[SC_ALPHA];
+  double acc = 0;
+  for (long long i = blockIdx.x * (long long)kVB + threadIdx.x; i < n; i += (long long)gridDim.x * kVB) {
+    x[i] += alpha * p[i];
+    const T ri = r[i] - alpha * Ap[i];
+    r[i] = ri;
+    acc += (double)ri * (double)ri;
+  }
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+template <typename T>
+__global__ void k_lanczos_update(T* __restrict__ r, T* __restrict__ z, const T* __restrict__ Ap,
+                                 const T* __restrict__ dinv, long long n, const double* __restrict__ sc,
+                                 double* part) {
+  __shared__ double sh[kVB];
+  const T alpha = (T)sc[SC_ALPHA];
+  double acc = 0;
+  for (long long i = blockIdx.x * (long long)kVB + threadIdx.x; i < n; i += (long long)gridDim.x * kVB) {
+    const T ri = r[i] - alpha * Ap[i];
+    const T zi = dinv[i] * ri;
+    r[i] = ri;
+    z[i] = zi;
+    acc += (double)ri * (double)zi;
+  }
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+template <typename T>
+__global__ void k_cg_pupdate(T* __restrict__ p, const T* __restrict__ z, long long n, const double* __restrict__ sc) {
+  const T beta = (T)sc[SC_BETA];
+  for (long long i = blockIdx.x * (long long)kVB + threadIdx.x; i < n; i += (long long)gridDim.x * kVB)
+    p[i] = z[i] + beta * p[i];
+}
+
+template <typename T>
+__global__ void k_axpby(T* __restrict__ y, const T* __restrict__ x, T a, T b, long long n) {
+  for (long long i = blockIdx.x * (long long)kVB + threadIdx.x; i < n; i += (long long)gridDim.x * kVB)
+    y[i] = a * x[i] + b * y[i];
+}
+
+template <typename T>
+__global__ void k_lincomb3(T* __restrict__ z, T a, const T* __restrict__ x, T b, const T* __restrict__ y, T c,
+                           const T* __restrict__ w, long long n) {
+  for (long long i = blockIdx.x * (long long)kVB + threadIdx.x; i < n; i += (long long)gridDim.x * kVB) {
+    T v = 0;
+    if (x) v += a * x[i];
+    if (y) v += b * y[i];
+    if (w) v += c * w[i];
+    z[i] = v;
+  }
+}
+
+template <typename T>
+__global__ void k_cheb(const T* __restrict__ f, const T* __restrict__ t, const T* __restrict__ dinv, T* __restrict__ d,
+                       T* __restrict__ x, T cd, T cr, int xzero, long long n) {
+  for (long long i = blockIdx.x * (long long)kVB + threadIdx.x; i < n; i += (long long)gridDim.x * kVB) {
+    const T r = t ? f[i] - t[i] : f[i];
+    const T di = (cd != T(0) ? cd * d[i] : T(0)) + cr * dinv[i] * r;
+    d[i] = di;
+    x[i] = xzero ? di : x[i] + di;
+  }
+}
+
+template <typename T>
+__global__ void k_set_constrained(T* __restrict__ v, T val, long long n, Lattice lt) {
+  for (long long i = blockIdx.x * (long long)kVB + threadIdx.x; i < n; i += (long long)gridDim.x * kVB)
+    if (constrained_dof(lt, i)) v[i] = val;
+}
+
+template <typename T>
+__global__ void k_splitmix(T* __restrict__ v, long long n, unsigned long long seed) {
+  for (long long i = blockIdx.x * (long long)kVB + threadIdx.x; i < n; i += (long long)gridDim.x * kVB) {
+    unsigned long long z = seed + (unsigned long long)(i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z = z ^ (z >> 31);
+    v[i] = (T)((double)(z >> 11) * 0x1p-52 - 1.0);
+  }
+}
+
+template <typename TO>
+__global__ void k_reciprocal(const double* __restrict__ in, TO* __restrict__ out, long long n) {
+  for (long long i = blockIdx.x * (long long)kVB + threadIdx.x; i < n; i += (long long)gridDim.x * kVB)
+    out[i] = (TO)(1.0 / in[i]);
+}
+
+template <typename T>
+__global__ void k_sweep(const T* __restrict__ in, T* __restrict__ out, SweepArgs<T> a) {
+  int m[3] = {a.n[0], a.n[1], a.n[2]};
+  m[a.axis] = a.band.nout;
+  const long long per = (long long)m[0] * m[1] * m[2];
+  const long long total = per * a.comps;
+  for (long long g = blockIdx.x * (long long)kVB + threadIdx.x; g < total; g += (long long)gridDim.x * kVB) {
+    const int c = (int)(g / per);
+    long long r = g - c * per;
+    int idx[3];
+    idx[0] = (int)(r % m[0]);
+    r /= m[0];
+    idx[1] = (int)(r % m[1]);
+    idx[2] = (int)(r / m[1]);
+    const int o = idx[a.axis];
+    const int st = a.band.start[o];
+    long long stride = 1;
+    for (int k = 0; k < a.axis; ++k) stride *= a.n[k];
+    idx[a.axis] = st;
+    const long long ib = c * a.in_cs + idx[0] + (long long)a.n[0] * (idx[1] + (long long)a.n[1] * idx[2]);
+    const T* v = a.band.vals + (long long)o * a.band.K;
+    T s = 0;
+    for (int k = 0; k < a.band.K; ++k) s += v[k] * in[ib + k * stride];
+    idx[a.axis] = o;
+    const long long ob = c * a.out_cs + idx[0] + (long long)m[0] * (idx[1] + (long long)m[1] * idx[2]);
+    if (a.mask && constrained_dof(a.lt, c * a.lt.nn + (ob - c * a.out_cs))) s = T(0);
+    out[ob] = a.add ? out[ob] + s : s;
+  }
+}
+
+struct FaceVals {
+  double v[6][3];
+};
+
+__device__ __forceinline__ int last_face(const Lattice& lt, long long dof, int& comp) {
+  comp = (int)(dof / lt.nn);
+  long long n = dof - comp * lt.nn;
+  const int i = (int)(n % lt.L);
+  n /= lt.L;
+  const int j = (int)(n % lt.L);
+  const int k = (int)(n / lt.L);
+  int f = -1;
+  const int lat[3] = {i, j, k};
+  for (int ax = 0; ax < lt.dim; ++ax)
+    for (int side = 0; side < 2; ++side) {
+      const int ff = 2 * ax + side;
+      if (lat[ax] == (side ? lt.L - 1 : 0) && ((lt.fmask[comp] >> ff) & 1u)) f = ff;
+    }
+  return f;
+}
+
+__global__ void k_set_dirichlet(double* __restrict__ u, Lattice lt, FaceVals fv, double scale, long long n) {
+  for (long long i = blockIdx.x * (long long)kVB + threadIdx.x; i < n; i += (long long)gridDim.x * kVB) {
+    int c;
+    const int f = last_face(lt, i, c);
+    if (f >= 0) u[i] = scale * fv.v[f][c];
+  }
+}
+
+__global__ void k_dirichlet_delta(const double* __restrict__ u, double* __restrict__ dg, Lattice lt, FaceVals fv,
+                                  double scale, long long n) {
+  for (long long i = blockIdx.x * (long long)kVB + threadIdx.x; i < n; i += (long long)gridDim.x * kVB) {
+    int c;
+    const int f = last_face(lt, i, c);
+    dg[i] = f >= 0 ? scale * fv.v[f][c] - u[i] : 0.0;
+  }
+}
+
+__global__ void k_material_bits(uint32_t* __restrict__ bits, long long ncells, int N, int dim, int n1,
+                                Tables<double> tb, double h, const double* __restrict__ incl, int nincl, int nwords) {
+  const int nq = dim == 3 ? n1 * n1 * n1 : n1 * n1;
+  const long long total = ncells * nwords;
+  for (long long g = blockIdx.x * (long long)kVB + threadIdx.x; g < total; g += (long long)gridDim.x * kVB) {
+    const long long e = g / nwords;
+    const int w = (int)(g - e * nwords);
+    const int ex = (int)(e % N), ey = (int)((e / N) % N), ez = dim == 3 ? (int)(e / ((long long)N * N)) : 0;
+    uint32_t word = 0;
+    for (int b = 0; b < 32; ++b) {
+      const int q = w * 32 + b;
+      if (q >= nq) break;
+      const int qx = q % n1, qy = (q / n1) % n1, qz = q / (n1 * n1);
+      double X[3] = {h * (ex + tb.xg[qx]), h * (ey + tb.xg[qy]), dim == 3 ? h * (ez + tb.xg[qz]) : 0.0};
+      int id = 0;
+      for (int s = 0; s < nincl; ++s) {
+        const double* row = incl + (long long)s * (dim + 2);
+        double d2 = 0;
+        for (int k = 0; k < dim; ++k) d2 += (X[k] - row[k]) * (X[k] - row[k]);
+        if (d2 <= row[dim] * row[dim]) id = (int)row[dim + 1];
+      }
+      if (id) word |= 1u << b;
+    }
+    bits[g] = word;
+  }
+}
+
+// ---- coarse solve -----------------------------------------------------------------
+
+constexpr int kGJ = 64;
+
+__global__ void k_gj_pivot(double* __restrict__ A, long long n, long long k0, int nb, double* __restrict__ Pinv,
+                           int* flag) {
+  __shared__ double M[kGJ][kGJ + 1];
+  __shared__ double colk[kGJ], rowk[kGJ];
+  const int t = threadIdx.x;
+  for (int e = t; e < nb * nb; e += blockDim.x) {
+    const int i = e / nb, j = e % nb;
+    M[i][j] = A[(k0 + i) * n + k0 + j];
+  }
+  __syncthreads();
+  for (int k = 0; k < nb; ++k) {
+    if (t < nb) {
+      colk[t] = M[t][k];
+      rowk[t] = M[k][t];
+    }
+    __syncthreads();
+    const double p = rowk[k];
+    if (t == 0 && !(p > 0.0)) *flag = 1;
+    const double pinv = 1.0 / p;
+    for (int e = t; e < nb * nb; e += blockDim.x) {
+      const int i = e / nb, j = e % nb;
+      if (i == k && j == k)
+        M[i][j] = pinv;
+      else if (i == k)
+        M[i][j] = rowk[j] * pinv;
+      else if (j == k)
+        M[i][j] = -colk[i] * pinv;
+      else
+        M[i][j] -= colk[i] * rowk[j] * pinv;
+    }
+    __syncthreads();
+  }
+  for (int e = t; e < nb * nb; e += blockDim.x) {
+    const int i = e / nb, j = e % nb;
+    Pinv[i * nb + j] = M[i][j];
+  }
+}
+
+// R[t][j] = sum_s Pinv[t][s] A[k0+s][j]
+__global__ void k_gj_rowpanel(const double* __restrict__ A, long long n, long long k0, int nb,
+                              const double* __restrict__ Pinv, double* __restrict__ R) {
+  const long long total = (long long)nb * n;
+  for (long long g = blockIdx.x * (long long)kVB + threadIdx.x; g < total; g += (long long)gridDim.x * kVB) {
+    const int t = (int)(g / n);
+    const long long j = g - (long long)t * n;
+    double s = 0;
+    for (int q = 0; q < nb; ++q) s += Pinv[t * nb + q] * A[(k0 + q) * n + j];
+    R[g] = s;
+  }
+}
+
+// Cb[i][t] = A[i][k0+t]
+__global__ void k_gj_colpanel(const double* __restrict__ A, long long n, long long k0, int nb, double* __restrict__ Cb) {
+  const long long total = (long long)nb * n;
+  for (long long g = blockIdx.x * (long long)kVB + threadIdx.x; g < total; g += (long long)gridDim.x * kVB) {
+    const long long i = g / nb;
+    const int t = (int)(g - i * nb);
+    Cb[g] = A[i * n + k0 + t];
+  }
+}
+
+// A[i][j] -= sum_t Cb[i][t] R[t][j]   for i, j outside the pivot block
+__global__ void __launch_bounds__(256) k_gj_update(double* __restrict__ A, long long n, long long k0, int nb,
+                                                   const double* __restrict__ Cb, const double* __restrict__ R) {
+  const long long bi = blockIdx.y, bj = blockIdx.x;
+  const long long kb = k0 / kGJ;
+  if (bi == kb || bj == kb) return;
+  __shared__ double Cs[kGJ][kGJ + 1];
+  __shared__ double Rs[kGJ][kGJ + 1];
+  const int t = threadIdx.x;
+  const long long i0 = bi * kGJ, j0 = bj * kGJ;
+  for (int e = t; e < kGJ * kGJ; e += 256) {
+    const int r = e / kGJ, c = e % kGJ;
+    Cs[r][c] = (i0 + r < n && c < nb) ? Cb[(i0 + r) * nb + c] : 0.0;
+    Rs[r][c] = (r < nb && j0 + c < n) ? R[(long long)r * n + j0 + c] : 0.0;
+  }
+  __syncthreads();
+  const int ty = t / 16, tx = t % 16;
+  double acc[4][4] = {};
+  for (int q = 0; q < nb; ++q) {
+    double a[4], b[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) a[r] = Cs[ty * 4 + r][q];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) b[c] = Rs[q][tx * 4 + c];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[r][c] += a[r] * b[c];
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const long long i = i0 + ty * 4 + r;
+    if (i >= n) continue;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const long long j = j0 + tx * 4 + c;
+      if (j < n) A[i * n + j] -= acc[r][c];
+    }
+  }
+}
+
+// Column k block: A[i][k0+t] = -sum_s Cb[i][s] Pinv[s][t] (i outside), Pinv inside.
+__global__ void k_gj_fincol(double* __restrict__ A, long long n, long long k0, int nb, const double* __restrict__ Cb,
+                            const double* __restrict__ Pinv) {
+  const long long total = (long long)nb * n;
+  for (long long g = blockIdx.x * (long long)kVB + threadIdx.x; g < total; g += (long long)gridDim.x * kVB) {
+    const long long i = g / nb;
+    const int t = (int)(g - i * nb);
+    double v;
+    if (i >= k0 && i < k0 + nb) {
+      v = Pinv[(i - k0) * nb + t];
+    } else {
+      v = 0;
+      for (int s = 0; s < nb; ++s) v -= Cb[i * nb + s] * Pinv[s * nb + t];
+    }
+    A[i * n + k0 + t] = v;
+  }
+}
+
+// Row k block: A[k0+t][j] = R[t][j] for j outside the pivot block.
+__global__ void k_gj_finrow(double* __restrict__ A, long long n, long long k0, int nb, const double* __restrict__ R) {
+  const long long total = (long long)nb * n;
+  for (long long g = blockIdx.x * (long long)kVB + threadIdx.x; g < total; g += (long long)gridDim.x * kVB) {
+    const int t = (int)(g / n);
+    const long long j = g - (long long)t * n;
+    if (j >= k0 && j < k0 + nb) continue;
+    A[(k0 + t) * n + j] = R[g];
+  }
+}
+
+template <typename T>
+__global__ void k_coarse_gather(const T* __restrict__ r, const int* __restrict__ dof_of, long long nf,
+                                double* __restrict__ rf) {
+  for (long long f = blockIdx.x * (long long)kVB + threadIdx.x; f < nf; f += (long long)gridDim.x * kVB)
+    rf[f] = (double)r[dof_of[f]];
+}
+
+__global__ void k_gemv_rows(const double* __restrict__ K, long long nf, const double* __restrict__ x,
+                            double* __restrict__ y) {
+  __shared__ double sh[kVB];
+  const long long i = blockIdx.x;
+  const double* row = K + i * nf;
+  double acc = 0;
+  for (long long j = threadIdx.x; j < nf; j += kVB) acc += row[j] * x[j];
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) y[i] = s;
+}
+
+template <typename T>
+__global__ void k_coarse_scatter(const double* __restrict__ zf, const int* __restrict__ dof_of, long long nf,
+                                 T* __restrict__ z) {
+  for (long long f = blockIdx.x * (long long)kVB + threadIdx.x; f < nf; f += (long long)gridDim.x * kVB)
+    z[dof_of[f]] = (T)zf[f];
+}
+
+}  // namespace
+
+// ---- launch wrappers ------------------------------------------------------------------
+
+template <typename T>
+void fill_dirichlet(T* y, const T* x, long long n, const Lattice& lt, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_dirichlet<T>, dim3(grid_for(n)), dim3(kVB), 0, s, y, x, n, lt);
+}
+template <typename T>
+void zero_constrained(T* v, long long n, const Lattice& lt, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_constrained<T>, dim3(grid_for(n)), dim3(kVB), 0, s, v, n, lt);
+}
+template <typename T>
+void fill(T* v, T val, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(n)), dim3(kVB), 0, s, v, val, n);
+}
+template <typename TI, typename TO>
+void cast(const TI* in, TO* out, long long n, hipStream_t s) {
+  hipLaunchKernelGGL((k_cast<TI, TO>), dim3(grid_for(n)), dim3(kVB), 0, s, in, out, n);
+}
+template <typename TA, typename TB>
+void dot(const TA* a, const TB* b, long long n, double* part, double* out, hipStream_t s) {
+  const unsigned g = red_grid(n);
+  hipLaunchKernelGGL((k_dot_part<TA, TB>), dim3(g), dim3(kVB), 0, s, a, b, n, part);
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kVB), 0, s, part, (int)g, out);
+}
+void min_reduce(const double* part, int np, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_min_final, dim3(1), dim3(kVB), 0, s, part, np, out);
+}
+void set_scalar(double* p, double v, hipStream_t s) { hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, s, p, v); }
+void scalar_div(double* sc, int dst, int num, int den, int copy_to, int copy_from, double* hist, int hidx,
+                hipStream_t s) {
+  hipLaunchKernelGGL(k_scalar_div, dim3(1), dim3(1), 0, s, sc, dst, num, den, copy_to, copy_from, hist, hidx);
+}
+template <typename T>
+void cg_update(T* x, T* r, const T* p, const T* Ap, long long n, const double* sc, double* part, hipStream_t s) {
+  const unsigned g = red_grid(n);
+  hipLaunchKernelGGL(k_cg_update<T>, dim3(g), dim3(kVB), 0, s, x, r, p, Ap, n, sc, part);
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kVB), 0, s, part, (int)g, const_cast<double*>(sc) + SC_RR);
+}
+template <typename T>
+void lanczos_update(T* r, T* z, const T* Ap, const T* dinv, long long n, const double* sc, double* part,
+                    hipStream_t s) {
+  const unsigned g = red_grid(n);
+  hipLaunchKernelGGL(k_lanczos_update<T>, dim3(g), dim3(kVB), 0, s, r, z, Ap, dinv, n, sc, part);
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kVB), 0, s, part, (int)g, const_cast<double*>(sc) + SC_RZNEW);
+}
+template <typename T>
+void cg_pupdate(T* p, const T* z, long long n, const double* sc, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_pupdate<T>, dim3(grid_for(n)), dim3(kVB), 0, s, p, z, n, sc);
+}
+template <typename T>
+void axpby(T* y, const T* x, T a, T b, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpby<T>, dim3(grid_for(n)), dim3(kVB), 0, s, y, x, a, b, n);
+}
+template <typename T>
+void lincomb3(T* z, T a, const T* x, T b, const T* y, T c, const T* w, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(k_lincomb3<T>, dim3(grid_for(n)), dim3(kVB), 0, s, z, a, x, b, y, c, w, n);
+}
+template <typename T>
+void cheb_step(const T* f, const T* t, const T* dinv, T* d, T* x, T cd, T cr, int xzero, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(k_cheb<T>, dim3(grid_for(n)), dim3(kVB), 0, s, f, t, dinv, d, x, cd, cr, xzero, n);
+}
+template <typename T>
+void set_constrained(T* v, T val, long long n, const Lattice& lt, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_constrained<T>, dim3(grid_for(n)), dim3(kVB), 0, s, v, val, n, lt);
+}
+template <typename T>
+void splitmix_uniform(T* v, long long n, unsigned long long seed, hipStream_t s) {
+  hipLaunchKernelGGL(k_splitmix<T>, dim3(grid_for(n)), dim3(kVB), 0, s, v, n, seed);
+}
+template <typename TO>
+void reciprocal(const double* in, TO* out, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(k_reciprocal<TO>, dim3(grid_for(n)), dim3(kVB), 0, s, in, out, n);
+}
+template <typename T>
+void sweep(const T* in, T* out, const SweepArgs<T>& a, hipStream_t s) {
+  long long m = (long long)a.n[0] * a.n[1] * a.n[2] / a.n[a.axis] * a.band.nout * a.comps;
+  hipLaunchKernelGGL(k_sweep<T>, dim3(grid_for(m)), dim3(kVB), 0, s, in, out, a);
+}
+
+void set_dirichlet(double* u, const Lattice& lt, const double* fv, double scale, long long n, hipStream_t s) {
+  FaceVals f = {};
+  for (int face = 0; face < 2 * lt.dim; ++face)
+    for (int c = 0; c < lt.dim; ++c) f.v[face][c] = fv[face * lt.dim + c];
+  hipLaunchKernelGGL(k_set_dirichlet, dim3(grid_for(n)), dim3(kVB), 0, s, u, lt, f, scale, n);
+}
+void dirichlet_delta(const double* u, double* dg, const Lattice& lt, const double* fv, double scale, long long n,
+                     hipStream_t s) {
+  FaceVals f = {};
+  for (int face = 0; face < 2 * lt.dim; ++face)
+    for (int c = 0; c < lt.dim; ++c) f.v[face][c] = fv[face * lt.dim + c];
+  hipLaunchKernelGGL(k_dirichlet_delta, dim3(grid_for(n)), dim3(kVB), 0, s, u, dg, lt, f, scale, n);
+}
+
+void material_bits(uint32_t* bits, long long ncells, int N, int dim, int n1, const Tables<double>& tb, double h,
+                   const double* incl, int nincl, int nwords, hipStream_t s) {
+  hipLaunchKernelGGL(k_material_bits, dim3(grid_for(ncells * nwords)), dim3(kVB), 0, s, bits, ncells, N, dim, n1, tb,
+                     h, incl, nincl, nwords);
+}
+
+void gj_pivot(double* A, long long n, long long k0, int nb, double* Pinv, int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(256), 0, s, A, n, k0, nb, Pinv, flag);
+}
+void gj_panels(const double* A, long long n, long long k0, int nb, const double* Pinv, double* Cb, double* R,
+               hipStream_t s) {
+  hipLaunchKernelGGL(k_gj_rowpanel, dim3(grid_for((long long)nb * n)), dim3(kVB), 0, s, A, n, k0, nb, Pinv, R);
+  hipLaunchKernelGGL(k_gj_colpanel, dim3(grid_for((long long)nb * n)), dim3(kVB), 0, s, A, n, k0, nb, Cb);
+}
+void gj_update(double* A, long long n, long long k0, int nb, const double* Cb, const double* R, hipStream_t s) {
+  const unsigned nt = (unsigned)((n + kGJ - 1) / kGJ);
+  hipLaunchKernelGGL(k_gj_update, dim3(nt, nt), dim3(256), 0, s, A, n, k0, nb, Cb, R);
+}
+void gj_finish(double* A, long long n, long long k0, int nb, const double* Cb, const double* R, const double* Pinv,
+               hipStream_t s) {
+  hipLaunchKernelGGL(k_gj_fincol, dim3(grid_for((long long)nb * n)), dim3(kVB), 0, s, A, n, k0, nb, Cb, Pinv);
+  hipLaunchKernelGGL(k_gj_finrow, dim3(grid_for((long long)nb * n)), dim3(kVB), 0, s, A, n, k0, nb, R);
+}
+template <typename T>
+void coarse_apply(const double* Kinv, long long nf, const int* dof_of, const T* r, double* rf, double* zf, T* z,
+                  hipStream_t s) {
+  hipLaunchKernelGGL(k_coarse_gather<T>, dim3(grid_for(nf)), dim3(kVB), 0, s, r, dof_of, nf, rf);
+  hipLaunchKernelGGL(k_gemv_rows, dim3((unsigned)nf), dim3(kVB), 0, s, Kinv, nf, rf, zf);
+  hipLaunchKernelGGL(k_coarse_scatter<T>, dim3(grid_for(nf)), dim3(kVB), 0, s, zf, dof_of, nf, z);
+}
+
+#define MFH_INST_T(T)                                                                                          \
+  template void fill_dirichlet<T>(T*, const T*, long long, const Lattice&, hipStream_t);                       \
+  template void zero_constrained<T>(T*, long long, const Lattice&, hipStream_t);                               \
+  template void fill<T>(T*, T, long long, hipStream_t);                                                        \
+  template void cg_update<T>(T*, T*, const T*, const T*, long long, const double*, double*, hipStream_t);      \
+  template void lanczos_update<T>(T*, T*, const T*, const T*, long long, const double*, double*, hipStream_t); \
+  template void cg_pupdate<T>(T*, const T*, long long, const double*, hipStream_t);                            \
+  template void axpby<T>(T*, const T*, T, T, long long, hipStream_t);                                          \
+  template void lincomb3<T>(T*, T, const T*, T, const T*, T, const T*, long long, hipStream_t);                \
+  template void cheb_step<T>(const T*, const T*, const T*, T*, T*, T, T, int, long long, hipStream_t);         \
+  template void reciprocal<T>(const double*, T*, long long, hipStream_t);                                      \
+  template void set_constrained<T>(T*, T, long long, const Lattice&, hipStream_t);                             \
+  template void splitmix_uniform<T>(T*, long long, unsigned long long, hipStream_t);                           \
+                                      \
+  template void sweep<T>(const T*, T*, const SweepArgs<T>&, hipStream_t);                                      \
+  template void coarse_apply<T>(const double*, long long, const int*, const T*, double*, double*, T*, hipStream_t);
+MFH_INST_T(float)
+MFH_INST_T(double)
+#undef MFH_INST_T
+template void fill<uint32_t>(uint32_t*, uint32_t, long long, hipStream_t);
+template void fill<int>(int*, int, long long, hipStream_t);
+template void cast<double, float>(const double*, float*, long long, hipStream_t);
+template void cast<float, double>(const float*, double*, long long, hipStream_t);
+template void cast<double, double>(const double*, double*, long long, hipStream_t);
+template void dot<double, double>(const double*, const double*, long long, double*, double*, hipStream_t);
+template void dot<float, float>(const float*, const float*, long long, double*, double*, hipStream_t);
+
+}  // namespace mfh

@@ -1,0 +1,275 @@
+"""Thin ctypes binding of libmfh.so (include/mfh.h).
+
+Argument marshalling only: torch tensors supply device memory and the current
+HIP stream; every step of the computation runs in the library's kernels.  The
+binding refuses to run when the library is missing.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmfh.so")
+
+MFH_OK = 0
+STATUS = {0: "OK", -1: "INVALID_ARG", -2: "HIP", -3: "WORKSPACE", -4: "INVERTED",
+          -5: "NOT_CONVERGED", -6: "BREAKDOWN", -7: "NOT_SPD"}
+F64, F32 = 0, 1
+QP_RECOMPUTE, QP_CACHE_F, QP_CACHE_T2 = 0, 1, 2
+SCATTER_ATOMIC, SCATTER_COLOR = 0, 1
+
+
+class MfhError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"mfh {STATUS.get(status, status)}: {message}")
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int), ("n_cells", ctypes.c_int), ("degree", ctypes.c_int),
+        ("n_levels", ctypes.c_int), ("n_materials", ctypes.c_int),
+        ("mu", ctypes.POINTER(ctypes.c_double)), ("lambda_", ctypes.POINTER(ctypes.c_double)),
+        ("n_inclusions", ctypes.c_int), ("inclusions", ctypes.POINTER(ctypes.c_double)),
+        ("dirichlet_mask", ctypes.c_uint), ("qp_policy", ctypes.c_int), ("scatter", ctypes.c_int),
+        ("vcycle_dtype", ctypes.c_int), ("cheb_degree", ctypes.c_int), ("n_smooth", ctypes.c_int),
+        ("eig_iters", ctypes.c_int), ("cheb_lo", ctypes.c_double), ("cheb_hi", ctypes.c_double),
+    ]
+
+
+class NewtonRecord(ctypes.Structure):
+    _fields_ = [
+        ("load_step", ctypes.c_int), ("newton_iter", ctypes.c_int), ("cg_iters", ctypes.c_int),
+        ("residual_norm", ctypes.c_double), ("residual_after", ctypes.c_double),
+        ("du_norm", ctypes.c_double), ("cg_relres", ctypes.c_double), ("min_J", ctypes.c_double),
+        ("setup_ms", ctypes.c_double), ("residual_ms", ctypes.c_double), ("solve_ms", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+_P = ctypes.c_void_p
+_D = ctypes.POINTER(ctypes.c_double)
+
+
+def lib():
+    """Loads libmfh.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1904_13131_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    st = ctypes.c_int
+    sig = {
+        "mfh_desc_defaults": (None, [ctypes.POINTER(Desc)]),
+        "mfh_workspace_size": (st, [ctypes.POINTER(Desc), ctypes.POINTER(ctypes.c_size_t)]),
+        "mfh_create": (st, [ctypes.POINTER(Desc), _P, ctypes.c_size_t, _P, ctypes.POINTER(_P)]),
+        "mfh_destroy": (st, [_P]),
+        "mfh_n_dofs": (st, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_longlong)]),
+        "mfh_set_deformation": (st, [_P, _P, _D]),
+        "mfh_tangent_vmult": (st, [_P, ctypes.c_int, ctypes.c_int, _P, _P]),
+        "mfh_residual": (st, [_P, _P, _P]),
+        "mfh_gmg_vcycle": (st, [_P, _P, _P]),
+        "mfh_cg_solve": (st, [_P, _P, _P, ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _D]),
+        "mfh_last_error": (ctypes.c_char_p, [_P]),
+        "mfh_apply_dirichlet": (st, [_P, _P, _D, ctypes.c_double]),
+        "mfh_newton_solve": (st, [_P, _P, _D, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                  ctypes.c_double, ctypes.c_int, ctypes.POINTER(NewtonRecord), ctypes.c_int,
+                                  ctypes.POINTER(ctypes.c_int)]),
+        "mfh_level_displacement": (st, [_P, ctypes.c_int, _P]),
+        "mfh_level_diagonal": (st, [_P, ctypes.c_int, _P]),
+        "mfh_level_lambda_max": (st, [_P, ctypes.c_int, _D]),
+        "mfh_prolongate": (st, [_P, ctypes.c_int, ctypes.c_int, _P, _P]),
+        "mfh_restrict": (st, [_P, ctypes.c_int, ctypes.c_int, _P, _P]),
+        "mfh_chebyshev": (st, [_P, ctypes.c_int, _P, _P]),
+        "mfh_timer_enable": (st, [_P, ctypes.c_int]),
+        "mfh_timer_read": (st, [_P, _D, ctypes.POINTER(ctypes.c_longlong)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(st, handle=None):
+    if st != MFH_OK:
+        msg = lib().mfh_last_error(handle)
+        raise MfhError(st, msg.decode() if msg else "")
+
+
+def _darr(vals):
+    vals = [float(v) for v in vals]
+    return (ctypes.c_double * max(1, len(vals)))(*vals)
+
+
+def make_desc(dim, n_cells, degree, n_levels=1, mu=(1.0,), lam=(1.5,), inclusions=(), dirichlet_mask=0,
+              qp_policy=QP_RECOMPUTE, scatter=SCATTER_ATOMIC, vcycle_dtype=F32, cheb_degree=4, n_smooth=2,
+              eig_iters=30, cheb_lo=0.6, cheb_hi=1.2):
+    """Builds an mfh_desc; the returned tuple keeps the host arrays alive."""
+    d = Desc()
+    lib().mfh_desc_defaults(ctypes.byref(d))
+    mu_a, lam_a = _darr(mu), _darr(lam)
+    rows = []
+    for c, r, m in inclusions:
+        rows += list(c)[:dim] + [r, m]
+    inc_a = _darr(rows)
+    d.dim, d.n_cells, d.degree, d.n_levels = dim, n_cells, degree, n_levels
+    d.n_materials = len(mu)
+    d.mu = ctypes.cast(mu_a, _D)
+    d.lambda_ = ctypes.cast(lam_a, _D)
+    d.n_inclusions = len(inclusions)
+    d.inclusions = ctypes.cast(inc_a, _D)
+    d.dirichlet_mask = dirichlet_mask
+    d.qp_policy, d.scatter, d.vcycle_dtype = qp_policy, scatter, vcycle_dtype
+    d.cheb_degree, d.n_smooth, d.eig_iters = cheb_degree, n_smooth, eig_iters
+    d.cheb_lo, d.cheb_hi = cheb_lo, cheb_hi
+    return d, (mu_a, lam_a, inc_a)
+
+
+def workspace_size(desc):
+    n = ctypes.c_size_t()
+    _check(lib().mfh_workspace_size(ctypes.byref(desc), ctypes.byref(n)))
+    return n.value
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Problem:
+    """One mfh_problem with its workspace (a torch uint8 device tensor)."""
+
+    def __init__(self, dim, n_cells, degree, device="cuda", **kw):
+        self.desc, self._keep = make_desc(dim, n_cells, degree, **kw)
+        self.device = torch.device(device)
+        self.dim = dim
+        size = workspace_size(self.desc)
+        self.workspace = torch.empty(size + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.workspace.data_ptr()) % 256
+        base = self.workspace.data_ptr() + off
+        self.stream = torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        _check(lib().mfh_create(ctypes.byref(self.desc), ctypes.c_void_p(base), size,
+                                ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self.handle = h
+        self.n_levels = self.desc.n_levels
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().mfh_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def n_dofs(self, level=-1):
+        level = level % self.n_levels
+        n = ctypes.c_longlong()
+        _check(lib().mfh_n_dofs(self.handle, level, ctypes.byref(n)), self.handle)
+        return n.value
+
+    def _vec(self, level, dtype):
+        return torch.empty(self.n_dofs(level), dtype=dtype, device=self.device)
+
+    def set_deformation(self, u):
+        assert u.dtype == torch.float64 and u.is_contiguous() and u.numel() == self.n_dofs()
+        mj = ctypes.c_double()
+        _check(lib().mfh_set_deformation(self.handle, _ptr(u), ctypes.byref(mj)), self.handle)
+        return mj.value
+
+    def tangent_vmult(self, x, y=None, level=-1):
+        level = level % self.n_levels
+        dt = F64 if x.dtype == torch.float64 else F32
+        assert x.dtype in (torch.float64, torch.float32) and x.is_contiguous()
+        assert x.numel() == self.n_dofs(level)
+        y = self._vec(level, x.dtype) if y is None else y
+        _check(lib().mfh_tangent_vmult(self.handle, level, dt, _ptr(x), _ptr(y)), self.handle)
+        return y
+
+    def residual(self, u, r=None):
+        assert u.dtype == torch.float64 and u.numel() == self.n_dofs()
+        r = self._vec(-1, torch.float64) if r is None else r
+        _check(lib().mfh_residual(self.handle, _ptr(u), _ptr(r)), self.handle)
+        return r
+
+    def gmg_vcycle(self, r, z=None):
+        assert r.dtype == torch.float64 and r.numel() == self.n_dofs()
+        z = self._vec(-1, torch.float64) if z is None else z
+        _check(lib().mfh_gmg_vcycle(self.handle, _ptr(r), _ptr(z)), self.handle)
+        return z
+
+    def cg_solve(self, b, x=None, rtol=1e-8, max_it=200, raise_on_error=True):
+        assert b.dtype == torch.float64 and b.numel() == self.n_dofs()
+        x = self._vec(-1, torch.float64) if x is None else x
+        it = ctypes.c_int()
+        rel = ctypes.c_double()
+        st = lib().mfh_cg_solve(self.handle, _ptr(b), _ptr(x), rtol, max_it, ctypes.byref(it), ctypes.byref(rel))
+        if raise_on_error:
+            _check(st, self.handle)
+        return x, it.value, rel.value, st
+
+    def apply_dirichlet(self, u, face_values, scale=1.0):
+        fv = _darr([v for row in face_values for v in row])
+        _check(lib().mfh_apply_dirichlet(self.handle, _ptr(u), fv, scale), self.handle)
+
+    def newton_solve(self, u, face_values, n_steps, cg_rtol=1e-8, cg_max_it=200, du_tol=1e-5, r_tol=1e-8,
+                     max_newton=20, max_records=512, raise_on_error=True):
+        fv = _darr([v for row in face_values for v in row])
+        recs = (NewtonRecord * max_records)()
+        n = ctypes.c_int()
+        st = lib().mfh_newton_solve(self.handle, _ptr(u), fv, n_steps, cg_rtol, cg_max_it, du_tol, r_tol,
+                                    max_newton, recs, max_records, ctypes.byref(n))
+        out = [recs[i].as_dict() for i in range(min(n.value, max_records))]
+        if raise_on_error:
+            _check(st, self.handle)
+        return out, st
+
+    def level_displacement(self, level):
+        u = self._vec(level, torch.float64)
+        _check(lib().mfh_level_displacement(self.handle, level % self.n_levels, _ptr(u)), self.handle)
+        return u
+
+    def level_diagonal(self, level):
+        d = self._vec(level, torch.float64)
+        _check(lib().mfh_level_diagonal(self.handle, level % self.n_levels, _ptr(d)), self.handle)
+        return d
+
+    def level_lambda_max(self, level):
+        v = ctypes.c_double()
+        _check(lib().mfh_level_lambda_max(self.handle, level % self.n_levels, ctypes.byref(v)), self.handle)
+        return v.value
+
+    def prolongate(self, level, x, y=None):
+        dt = F64 if x.dtype == torch.float64 else F32
+        y = self._vec(level, x.dtype) if y is None else y
+        _check(lib().mfh_prolongate(self.handle, level, dt, _ptr(x), _ptr(y)), self.handle)
+        return y
+
+    def restrict(self, level, x, y=None):
+        dt = F64 if x.dtype == torch.float64 else F32
+        y = self._vec(level - 1, x.dtype) if y is None else y
+        _check(lib().mfh_restrict(self.handle, level, dt, _ptr(x), _ptr(y)), self.handle)
+        return y
+
+    def timer_enable(self, enable=True):
+        _check(lib().mfh_timer_enable(self.handle, 1 if enable else 0), self.handle)
+
+    def timer_read(self):
+        ms = ctypes.c_double()
+        n = ctypes.c_longlong()
+        _check(lib().mfh_timer_read(self.handle, ctypes.byref(ms), ctypes.byref(n)), self.handle)
+        return ms.value, n.value
+
+    def chebyshev(self, level, f, x):
+        _check(lib().mfh_chebyshev(self.handle, level, _ptr(f), _ptr(x)), self.handle)
+        return x

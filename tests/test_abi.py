@@ -1,0 +1,85 @@
+"""CPU checks of the C ABI: the library loads, exports every function the
+header declares, validates descriptors on the host, and the product package
+never touches the oracle."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mfh.h")
+LIB = os.path.join(ROOT, "paper_1904_13131_amd", "libmfh.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mfh_[a-z_0-9]+)\s*\(", text)))
+
+
+def _lib():
+    if not os.path.exists(LIB):
+        pytest.fail(f"{LIB} not built: run python -m paper_1904_13131_amd.build")
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ["mfh_workspace_size", "mfh_create", "mfh_destroy", "mfh_set_deformation", "mfh_tangent_vmult",
+                 "mfh_residual", "mfh_gmg_vcycle", "mfh_cg_solve", "mfh_last_error", "mfh_newton_solve"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib()
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def _desc(**kw):
+    from paper_1904_13131_amd import make_desc
+    base = dict(dim=3, n_cells=8, degree=2, n_levels=2, mu=(1.0, 100.0), lam=(1.5, 150.0))
+    base.update(kw)
+    return make_desc(**base)
+
+
+def test_workspace_size_on_host():
+    from paper_1904_13131_amd import workspace_size
+    d, keep = _desc()
+    n1 = workspace_size(d)
+    d2, keep2 = _desc(n_cells=16, n_levels=3)
+    assert workspace_size(d2) > n1 > 0
+
+
+@pytest.mark.parametrize("bad", [
+    dict(dim=4), dict(degree=0), dict(degree=5), dict(n_cells=0), dict(n_cells=6, n_levels=3),
+    dict(mu=(-1.0,), lam=(1.0,)), dict(qp_policy=3), dict(scatter=2), dict(vcycle_dtype=5),
+    dict(cheb_degree=0), dict(n_smooth=0), dict(eig_iters=0), dict(cheb_lo=1.3, cheb_hi=1.2),
+    dict(dirichlet_mask=1 << 18), dict(inclusions=[((0.5, 0.5, 0.5), 0.2, 2)]),
+])
+def test_invalid_descriptors_rejected(bad):
+    from paper_1904_13131_amd import MfhError, workspace_size
+    d, keep = _desc(**bad)
+    with pytest.raises(MfhError) as e:
+        workspace_size(d)
+    assert e.value.name == "INVALID_ARG"
+
+
+def test_create_rejects_small_or_null_workspace():
+    from paper_1904_13131_amd import make_desc, mfh
+    L = mfh.lib()
+    d, keep = make_desc(2, 4, 1)
+    h = ctypes.c_void_p()
+    st = L.mfh_create(ctypes.byref(d), None, 0, None, ctypes.byref(h))
+    assert st == -1
+    assert b"workspace" in L.mfh_last_error(None)
+
+
+def test_product_never_imports_the_oracle():
+    pkg = os.path.join(ROOT, "paper_1904_13131_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".cpp", ".hpp", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "oracle" not in text.replace("oracle_", ""), f

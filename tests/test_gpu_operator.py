@@ -1,0 +1,167 @@
+"""GPU parity of the matrix-free tangent vmult and the residual (eq. mf_vmult,
+eq. algebraic_tangent, eq. linear_system) against the oracle's assembled
+operators, through the C ABI.
+
+Bar: relative l2 error <= 1e-12 in FP64 and <= 1e-5 in FP32 (x rounded to
+FP32 first), for every quadrature-point policy and both scatter modes.  The
+small cases span several blocks of cells with a ragged last block; the full
+config-2 size (32^3 Q2, 823,875 DoFs) is checked on sampled rows that the
+oracle computes one by one, plus identities that hold at any size.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import fe
+from tests.gpu_helpers import dev, device_problem, host, log_case, oracle_problem, rel_l2, requires_gpu
+
+pytestmark = [pytest.mark.gpu, requires_gpu]
+
+CLAMP3 = W.clamp_bottom_top(3)
+CLAMP2 = W.clamp_bottom_top(2)
+
+CASES = {
+    "cfg1_2d_q1": W.config1(),
+    "2d_q2": W.problem(2, 7, 2, disc=True, u_amp=0.04, u_kmax=2, mask=W.face_bits(2, 0, 0)),
+    "2d_q3_clamp": W.problem(2, 5, 3, disc=True, u_amp=0.04, u_kmax=2, mask=CLAMP2),
+    "2d_q4": W.problem(2, 4, 4, disc=True, u_amp=0.04, u_kmax=2),
+    "3d_q1_clamp": W.problem(3, 5, 1, n_spheres=3, u_amp=0.05, u_kmax=2, mask=CLAMP3),
+    "3d_q2": W.problem(3, 4, 2, n_spheres=3, u_amp=0.05, u_kmax=2),
+    "3d_q2_mixedmask": W.problem(3, 3, 2, n_spheres=2, u_amp=0.05, u_kmax=2,
+                                 mask=W.face_bits(3, 0, 0, [0]) | W.face_bits(3, 1, 1, [1, 2]) | W.face_bits(3, 2, 0)),
+    "3d_q3": W.problem(3, 3, 3, n_spheres=3, u_amp=0.04, u_kmax=2),
+    "3d_q4_clamp": W.problem(3, 2, 4, n_spheres=2, u_amp=0.04, u_kmax=2, mask=CLAMP3),
+}
+
+_ORACLE = {}
+
+
+def _oracle(name):
+    if name not in _ORACLE:
+        w = CASES[name]
+        mesh, mat, cons = oracle_problem(w)
+        K = fe.constrain_matrix(fe.tangent_matrix(mesh, mat, w["u"]), cons)
+        R = fe.residual(mesh, mat, w["u"], cons)
+        _ORACLE[name] = (mesh, mat, cons, K, R)
+    return _ORACLE[name]
+
+
+@pytest.mark.parametrize("scatter", [0, 1], ids=["atomic", "color"])
+@pytest.mark.parametrize("policy", [0, 1, 2], ids=["R", "CF", "C2"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_vmult_fp64(name, policy, scatter):
+    log_case("vmult_fp64", name=name, policy=policy, scatter=scatter)
+    w = CASES[name]
+    _, _, _, K, _ = _oracle(name)
+    P = device_problem(w, qp_policy=policy, scatter=scatter)
+    mj = P.set_deformation(dev(w["u"]))
+    assert mj > 0
+    y = host(P.tangent_vmult(dev(w["x"])))
+    assert rel_l2(y, K @ w["x"]) <= 1e-12
+
+
+@pytest.mark.parametrize("policy", [0, 1, 2], ids=["R", "CF", "C2"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_vmult_fp32(name, policy):
+    log_case("vmult_fp32", name=name, policy=policy)
+    w = CASES[name]
+    _, _, _, K, _ = _oracle(name)
+    P = device_problem(w, qp_policy=policy)
+    P.set_deformation(dev(w["u"]))
+    x32 = w["x"].astype(np.float32)
+    y = host(P.tangent_vmult(dev(x32, torch.float32)))
+    assert rel_l2(y, K @ x32.astype(np.float64)) <= 1e-5
+
+
+@pytest.mark.parametrize("scatter", [0, 1], ids=["atomic", "color"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_residual(name, scatter):
+    log_case("residual", name=name, scatter=scatter)
+    w = CASES[name]
+    _, _, cons, _, R = _oracle(name)
+    P = device_problem(w, scatter=scatter)
+    r = host(P.residual(dev(w["u"])))
+    assert rel_l2(r, R) <= 1e-12
+    assert np.all(r[cons] == 0.0)
+
+
+def test_color_scatter_is_deterministic():
+    w = CASES["3d_q2"]
+    log_case("color_determinism", name="3d_q2")
+    P = device_problem(w, scatter=1)
+    P.set_deformation(dev(w["u"]))
+    x = dev(w["x"])
+    a = host(P.tangent_vmult(x))
+    b = host(P.tangent_vmult(x))
+    assert np.array_equal(a, b)
+
+
+def test_min_J_matches_oracle():
+    w = CASES["3d_q3"]
+    log_case("minJ", name="3d_q3")
+    mesh, _, _, _, _ = _oracle("3d_q3")
+    P = device_problem(w)
+    mj = P.set_deformation(dev(w["u"]))
+    assert abs(mj - fe.min_jacobian(mesh, w["u"])) <= 1e-13
+
+
+# ---- full config-2 size: 32^3 Q2, 823,875 DoFs ---------------------------------------
+
+_C2 = {}
+
+
+def _config2():
+    if not _C2:
+        w = W.config2()
+        mesh, mat, cons = oracle_problem(w)
+        rng = np.random.default_rng(17)
+        rows = np.sort(rng.choice(mesh.n_dofs, 160, replace=False))
+        # include lattice corners, edges and faces
+        L = mesh.L
+        extra = [0, L - 1, L * L - 1, mesh.n_nodes - 1, mesh.n_nodes + L * (L // 2), 2 * mesh.n_nodes + 3]
+        rows = np.unique(np.concatenate([rows, extra]))
+        _C2.update(w=w, mesh=mesh, mat=mat, rows=rows,
+                   ref=fe.vmult_rows(mesh, mat, w["u"], w["x"], rows),
+                   ref32=fe.vmult_rows(mesh, mat, w["u"], w["x"].astype(np.float32).astype(np.float64), rows),
+                   rres=fe.residual_rows(mesh, mat, w["u"], rows))
+    return _C2
+
+
+@pytest.mark.parametrize("policy", [0, 1, 2], ids=["R", "CF", "C2"])
+def test_config2_sampled_rows(policy):
+    c = _config2()
+    w = c["w"]
+    log_case("config2_rows", policy=policy, n_dofs=c["mesh"].n_dofs)
+    P = device_problem(w, qp_policy=policy)
+    P.set_deformation(dev(w["u"]))
+    y = host(P.tangent_vmult(dev(w["x"])))
+    scale = np.abs(c["ref"]).max()
+    assert np.abs(y[c["rows"]] - c["ref"]).max() <= 1e-12 * scale
+    y32 = host(P.tangent_vmult(dev(w["x"].astype(np.float32), torch.float32)))
+    assert np.linalg.norm(y32[c["rows"]] - c["ref32"]) <= 1e-5 * np.linalg.norm(c["ref32"])
+    r = host(P.residual(dev(w["u"])))
+    assert np.abs(r[c["rows"]] - c["rres"]).max() <= 1e-12 * max(np.abs(c["rres"]).max(), 1e-300) + 1e-15
+
+
+def test_config2_identities():
+    """Translations are in the kernel of the unconstrained tangent; the
+    operator is symmetric (x^T K y = y^T K x)."""
+    c = _config2()
+    w = c["w"]
+    log_case("config2_identities")
+    P = device_problem(w)
+    P.set_deformation(dev(w["u"]))
+    n = P.n_dofs()
+    nn = n // 3
+    for comp in range(3):
+        t = torch.zeros(n, dtype=torch.float64, device="cuda")
+        t[comp * nn:(comp + 1) * nn] = 1.0
+        kt = host(P.tangent_vmult(t))
+        kx = host(P.tangent_vmult(dev(w["x"])))
+        assert np.abs(kt).max() <= 1e-12 * np.abs(kx).max()
+    a = dev(W.normal_vector(n, 31))
+    b = dev(W.normal_vector(n, 32))
+    ka, kb = P.tangent_vmult(a), P.tangent_vmult(b)
+    s1, s2 = float(torch.dot(b, ka)), float(torch.dot(a, kb))
+    assert abs(s1 - s2) <= 1e-12 * abs(s1)
