@@ -74,10 +74,14 @@ enum { MFH_F64 = 0, MFH_F32 = 1 };
  *             Algorithm 2's cached tau/J, c1, c2.                               */
 enum { MFH_QP_RECOMPUTE = 0, MFH_QP_CACHE_F = 1, MFH_QP_CACHE_T2 = 2 };
 
-/* Scatter of cell results into the output vector: ATOMIC (hardware float
- * atomics; summation order varies run to run) or COLOR (2^dim launches over
- * cells of equal coordinate parity, plain read-modify-write, deterministic). */
-enum { MFH_SCATTER_ATOMIC = 0, MFH_SCATTER_COLOR = 1 };
+/* Scatter of cell results into the output vector: ATOMIC (one hardware float
+ * atomic per cell node; summation order varies run to run), COLOR (2^dim
+ * launches over cells of equal coordinate parity, plain read-modify-write,
+ * deterministic) or TILE (one block per tile of cells: tile nodes staged in
+ * LDS, contributions summed there, global atomics only on tile faces shared
+ * with a neighbouring tile; order varies).  The choice affects tangent_vmult
+ * only; all other cell kernels use ATOMIC when TILE is selected. */
+enum { MFH_SCATTER_ATOMIC = 0, MFH_SCATTER_COLOR = 1, MFH_SCATTER_TILE = 2 };
 
 typedef struct mfh_problem mfh_problem;
 

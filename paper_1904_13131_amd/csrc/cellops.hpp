@@ -369,6 +369,22 @@ __device__ __forceinline__ void scatter(T* __restrict__ dst, const CellArgs<T>& 
     }
 }
 
+// Atomic scatter that leaves the last x-node to the next lane (skip_last).
+template <int DIM, int N1, typename T>
+__device__ __forceinline__ void scatter_merged(T* __restrict__ dst, const CellArgs<T>& a,
+                                               const CellPos<DIM, N1>& cp, bool act, const T (&v)[DIM][N1],
+                                               bool skip_last) {
+  if (!act) return;
+#pragma unroll
+  for (int c = 0; c < DIM; ++c)
+#pragma unroll
+    for (int k = 0; k < N1; ++k) {
+      if (k == N1 - 1 && skip_last) continue;
+      if (cp.faces(k, a.L) & a.fmask[c]) continue;
+      atomic_add(dst + c * a.nn + cp.base + k, v[c][k]);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Quadrature-point algebra (Sec. 2.3).  All gradients are physical (1/h
 // applied).  Referential route used by the device:
@@ -602,7 +618,460 @@ __global__ void __launch_bounds__(kBlock) k_tangent(CellArgs<T> a) {
 
   T out[DIM][N1];
   SF::template backward<DIM>(gx, out, lds, pen, cl, act, a.tb);
-  scatter<DIM, N1, T>(a.y, a, cp, act, out);
+  if (a.color < 0) {
+    // The x-neighbour of this cell (same pencil) sits in the previous lane when
+    // both are in one wave: its last x-node is this cell's first one.  Pass it
+    // over and let one lane add the sum, saving a third of the atomics.
+    const int lane = t & 63;
+    const bool from_prev = act && cl > 0 && lane > 0 && (cp.e % a.N) != 0;
+    const bool to_next = act && cl + 1 < G::CPB && lane < 63 && lin + 1 < a.nlaunch && ((cp.e + 1) % a.N) != 0;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+      const T v = __shfl_up(out[c][N1 - 1], 1);
+      if (from_prev) out[c][0] += v;
+    }
+    scatter_merged<DIM, N1, T>(a.y, a, cp, act, out, to_next);
+  } else {
+    scatter<DIM, N1, T>(a.y, a, cp, act, out);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Tile variant of the tangent vmult (atomic scatter).  One block owns a tile of
+// TX x TY x TZ cells (2-D: TX x TY).  The tile's lattice nodes are loaded once,
+// coalesced, into LDS; each (cell, pencil) thread reads its x-line from there,
+// runs the same sweeps and quadrature-point stage as k_tangent, and adds its
+// results into an LDS copy of the tile's nodes (ds_add).  Nodes inside the
+// tile, or on a tile face that is the domain boundary, receive all their
+// contributions from this block and are written with plain stores; nodes on a
+// face shared with a neighbouring tile are added with global atomics.  Compared
+// with one atomic per cell node this divides the global atomics by ~3 for
+// Q2 tiles of 4x4x2 and replaces the per-cell gathers with one coalesced
+// load per tile node.
+template <int DIM, int P, int TX, int TY, int TZ>
+struct TileGeo {
+  static constexpr int N1 = P + 1;
+  static constexpr int NP = DIM == 3 ? N1 * N1 : N1;
+  static constexpr int NCELL = TX * TY * (DIM == 3 ? TZ : 1);
+  static constexpr int ACTIVE = NCELL * NP;
+  static constexpr int BLOCK = (ACTIVE + 63) / 64 * 64;
+  static constexpr int GX = TX * P + 1, GY = TY * P + 1, GZ = DIM == 3 ? TZ * P + 1 : 1;
+  static constexpr int NG = GX * GY * GZ;
+  static constexpr int NV = NP * N1;
+};
+
+// Sum-factorisation sweeps of SumFact with the cell count of a tile.
+template <int DIM, int N1, int NCELL, typename T>
+struct TileSF {
+  static constexpr int NV = (DIM == 3 ? N1 * N1 : N1) * N1;
+  __device__ static __forceinline__ int pt(int x, int y, int z) { return x + N1 * (y + N1 * z); }
+  __device__ static __forceinline__ T& at(T* lds, int arr, int p, int cl) { return lds[(arr * NV + p) * NCELL + cl]; }
+
+  template <int NC>
+  __device__ static void forward(const T (&v)[NC][N1], T* g, T* lds, int pen, int cl, bool act,
+                                 const Tables<T>& tb) {
+    // g points at g[NC][DIM][N1] in registers
+    T (&G)[NC][DIM][N1] = *reinterpret_cast<T(*)[NC][DIM][N1]>(g);
+    if constexpr (DIM == 3) {
+      const int p0 = pen % N1, p1 = pen / N1;
+      if (act) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+          for (int q = 0; q < N1; ++q) {
+            T s = 0, d = 0;
+#pragma unroll
+            for (int a = 0; a < N1; ++a) {
+              s += tb.S[q][a] * v[c][a];
+              d += tb.D[q][a] * v[c][a];
+            }
+            at(lds, 3 * c + 0, pt(q, p0, p1), cl) = s;
+            at(lds, 3 * c + 1, pt(q, p0, p1), cl) = d;
+          }
+      }
+      __syncthreads();
+      if (act) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          T s[N1], d[N1];
+#pragma unroll
+          for (int b = 0; b < N1; ++b) {
+            s[b] = at(lds, 3 * c + 0, pt(p0, b, p1), cl);
+            d[b] = at(lds, 3 * c + 1, pt(p0, b, p1), cl);
+          }
+#pragma unroll
+          for (int q = 0; q < N1; ++q) {
+            T ss = 0, sd = 0, ds = 0;
+#pragma unroll
+            for (int b = 0; b < N1; ++b) {
+              ss += tb.S[q][b] * s[b];
+              sd += tb.D[q][b] * s[b];
+              ds += tb.S[q][b] * d[b];
+            }
+            at(lds, 3 * c + 0, pt(p0, q, p1), cl) = ss;
+            at(lds, 3 * c + 1, pt(p0, q, p1), cl) = sd;
+            at(lds, 3 * c + 2, pt(p0, q, p1), cl) = ds;
+          }
+        }
+      }
+      __syncthreads();
+      if (act) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          T ss[N1], sd[N1], ds[N1];
+#pragma unroll
+          for (int k = 0; k < N1; ++k) {
+            ss[k] = at(lds, 3 * c + 0, pt(p0, p1, k), cl);
+            sd[k] = at(lds, 3 * c + 1, pt(p0, p1, k), cl);
+            ds[k] = at(lds, 3 * c + 2, pt(p0, p1, k), cl);
+          }
+#pragma unroll
+          for (int q = 0; q < N1; ++q) {
+            T gx = 0, gy = 0, gz = 0;
+#pragma unroll
+            for (int k = 0; k < N1; ++k) {
+              gx += tb.S[q][k] * ds[k];
+              gy += tb.S[q][k] * sd[k];
+              gz += tb.D[q][k] * ss[k];
+            }
+            G[c][0][q] = gx;
+            G[c][1][q] = gy;
+            G[c][2][q] = gz;
+          }
+        }
+      }
+      __syncthreads();
+    } else {
+      const int b = pen;
+      if (act) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+          for (int q = 0; q < N1; ++q) {
+            T s = 0, d = 0;
+#pragma unroll
+            for (int a = 0; a < N1; ++a) {
+              s += tb.S[q][a] * v[c][a];
+              d += tb.D[q][a] * v[c][a];
+            }
+            at(lds, 2 * c + 0, pt(q, b, 0), cl) = s;
+            at(lds, 2 * c + 1, pt(q, b, 0), cl) = d;
+          }
+      }
+      __syncthreads();
+      if (act) {
+        const int qx = pen;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          T s[N1], d[N1];
+#pragma unroll
+          for (int j = 0; j < N1; ++j) {
+            s[j] = at(lds, 2 * c + 0, pt(qx, j, 0), cl);
+            d[j] = at(lds, 2 * c + 1, pt(qx, j, 0), cl);
+          }
+#pragma unroll
+          for (int q = 0; q < N1; ++q) {
+            T gx = 0, gy = 0;
+#pragma unroll
+            for (int j = 0; j < N1; ++j) {
+              gx += tb.S[q][j] * d[j];
+              gy += tb.D[q][j] * s[j];
+            }
+            G[c][0][q] = gx;
+            G[c][1][q] = gy;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+
+  template <int NC>
+  __device__ static void backward(const T* Pin, T (&out)[NC][N1], T* lds, int pen, int cl, bool act,
+                                  const Tables<T>& tb) {
+    const T (&Pq)[NC][DIM][N1] = *reinterpret_cast<const T(*)[NC][DIM][N1]>(Pin);
+    if constexpr (DIM == 3) {
+      const int p0 = pen % N1, p1 = pen / N1;
+      if (act) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+          for (int k = 0; k < N1; ++k) {
+            T z0 = 0, z1 = 0, z2 = 0;
+#pragma unroll
+            for (int q = 0; q < N1; ++q) {
+              z0 += tb.S[q][k] * Pq[c][0][q];
+              z1 += tb.S[q][k] * Pq[c][1][q];
+              z2 += tb.D[q][k] * Pq[c][2][q];
+            }
+            at(lds, 3 * c + 0, pt(p0, p1, k), cl) = z0;
+            at(lds, 3 * c + 1, pt(p0, p1, k), cl) = z1;
+            at(lds, 3 * c + 2, pt(p0, p1, k), cl) = z2;
+          }
+      }
+      __syncthreads();
+      if (act) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          T z0[N1], z1[N1], z2[N1];
+#pragma unroll
+          for (int q = 0; q < N1; ++q) {
+            z0[q] = at(lds, 3 * c + 0, pt(p0, q, p1), cl);
+            z1[q] = at(lds, 3 * c + 1, pt(p0, q, p1), cl);
+            z2[q] = at(lds, 3 * c + 2, pt(p0, q, p1), cl);
+          }
+#pragma unroll
+          for (int b = 0; b < N1; ++b) {
+            T yd = 0, ys = 0;
+#pragma unroll
+            for (int q = 0; q < N1; ++q) {
+              yd += tb.S[q][b] * z0[q];
+              ys += tb.D[q][b] * z1[q] + tb.S[q][b] * z2[q];
+            }
+            at(lds, 3 * c + 0, pt(p0, b, p1), cl) = yd;
+            at(lds, 3 * c + 1, pt(p0, b, p1), cl) = ys;
+          }
+        }
+      }
+      __syncthreads();
+      if (act) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          T yd[N1], ys[N1];
+#pragma unroll
+          for (int q = 0; q < N1; ++q) {
+            yd[q] = at(lds, 3 * c + 0, pt(q, p0, p1), cl);
+            ys[q] = at(lds, 3 * c + 1, pt(q, p0, p1), cl);
+          }
+#pragma unroll
+          for (int a = 0; a < N1; ++a) {
+            T s = 0;
+#pragma unroll
+            for (int q = 0; q < N1; ++q) s += tb.D[q][a] * yd[q] + tb.S[q][a] * ys[q];
+            out[c][a] = s;
+          }
+        }
+      }
+      __syncthreads();
+    } else {
+      if (act) {
+        const int qx = pen;
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+          for (int j = 0; j < N1; ++j) {
+            T yd = 0, ys = 0;
+#pragma unroll
+            for (int q = 0; q < N1; ++q) {
+              yd += tb.S[q][j] * Pq[c][0][q];
+              ys += tb.D[q][j] * Pq[c][1][q];
+            }
+            at(lds, 2 * c + 0, pt(qx, j, 0), cl) = yd;
+            at(lds, 2 * c + 1, pt(qx, j, 0), cl) = ys;
+          }
+      }
+      __syncthreads();
+      if (act) {
+        const int b = pen;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          T yd[N1], ys[N1];
+#pragma unroll
+          for (int q = 0; q < N1; ++q) {
+            yd[q] = at(lds, 2 * c + 0, pt(q, b, 0), cl);
+            ys[q] = at(lds, 2 * c + 1, pt(q, b, 0), cl);
+          }
+#pragma unroll
+          for (int a = 0; a < N1; ++a) {
+            T s = 0;
+#pragma unroll
+            for (int q = 0; q < N1; ++q) s += tb.D[q][a] * yd[q] + tb.S[q][a] * ys[q];
+            out[c][a] = s;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+};
+
+// Tile origin and extent of block b.
+template <int DIM, int TX, int TY, int TZ>
+struct TilePos {
+  int cx0, cy0, cz0;    // first cell of the tile
+  int ex, ey, ez;       // cells of the tile inside the domain along each axis
+  __device__ void init(long long b, int N) {
+    const int ntx = (N + TX - 1) / TX, nty = (N + TY - 1) / TY;
+    const int tx = (int)(b % ntx);
+    const long long r = b / ntx;
+    const int ty = (int)(r % nty);
+    const int tz = DIM == 3 ? (int)(r / nty) : 0;
+    cx0 = tx * TX;
+    cy0 = ty * TY;
+    cz0 = tz * TZ;
+    ex = min(TX, N - cx0);
+    ey = min(TY, N - cy0);
+    ez = DIM == 3 ? min(TZ, N - cz0) : 1;
+  }
+};
+
+template <int DIM, int P, typename T, int POL, int TX, int TY, int TZ, int NC>
+__global__ void __launch_bounds__((TileGeo<DIM, P, TX, TY, TZ>::BLOCK))
+k_tangent_tile(CellArgs<T> a) {
+  using TG = TileGeo<DIM, P, TX, TY, TZ>;
+  constexpr int N1 = P + 1, NCELL = TG::NCELL, NG = TG::NG, GX = TG::GX, GY = TG::GY;
+  constexpr int NARR = DIM == 3 ? 3 : 2;
+  using SF = TileSF<DIM, N1, NCELL, T>;
+  __shared__ T xs[DIM * NG];                                   // x tile, then y accumulator
+  __shared__ T us[POL == POL_R ? DIM * NG : 1];                // displacement tile (recompute)
+  __shared__ T sf[NC * NARR * TG::NV * NCELL];
+
+  const int t = threadIdx.x;
+  const long long nb = gridDim.x;
+  TilePos<DIM, TX, TY, TZ> tp;
+  tp.init(xcd_block(blockIdx.x, nb), a.N);
+  const int L = a.L;
+
+  // 1. tile nodes -> LDS (x masked on constrained DoFs)
+  for (int idx = t; idx < DIM * NG; idx += TG::BLOCK) {
+    const int c = idx / NG, g = idx - c * NG;
+    const int gi = g % GX, gj = (g / GX) % GY, gk = DIM == 3 ? g / (GX * GY) : 0;
+    const int I = tp.cx0 * P + gi, J = tp.cy0 * P + gj, K = tp.cz0 * P + gk;
+    T xv = 0, uv = 0;
+    if (I < L && J < L && (DIM == 2 || K < L)) {
+      const long long node = I + (long long)L * (J + (long long)L * K);
+      xv = a.x[c * a.nn + node];
+      if (a.mask_in && (node_faces(I, J, K, L, DIM) & a.fmask[c])) xv = 0;
+      if constexpr (POL == POL_R) uv = a.u[c * a.nn + node];
+    }
+    xs[idx] = xv;
+    if constexpr (POL == POL_R) us[idx] = uv;
+  }
+  __syncthreads();
+
+  // 2. per (cell, pencil) thread
+  const int cl = t % NCELL, pen = t / NCELL;
+  const int lx = cl % TX, ly = (cl / TX) % TY, lz = DIM == 3 ? cl / (TX * TY) : 0;
+  const bool act = pen < TG::NP && lx < tp.ex && ly < tp.ey && lz < tp.ez;
+  const int pb = DIM == 3 ? pen % N1 : pen, pc = DIM == 3 ? pen / N1 : 0;
+  const int p0 = pb, p1 = pc;
+  const int g0 = lx * P + GX * ((ly * P + pb) + GY * (lz * P + pc));   // tile node of the line's first node
+  const long long e = (tp.cx0 + lx) + (long long)a.N * ((tp.cy0 + ly) + (long long)a.N * (tp.cz0 + lz));
+
+  T gx[DIM][DIM][N1];
+  T gu[POL == POL_R ? DIM : 1][DIM][N1];
+  if constexpr (POL == POL_R) {
+#pragma unroll
+    for (int c0 = 0; c0 < DIM; c0 += NC) {
+      T v[NC][N1];
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int k = 0; k < N1; ++k) v[c][k] = act ? us[(c0 + c) * NG + g0 + k] : T(0);
+      SF::template forward<NC>(v, &gu[c0][0][0], sf, pen, cl, act, a.tb);
+    }
+  }
+#pragma unroll
+  for (int c0 = 0; c0 < DIM; c0 += NC) {
+    T v[NC][N1];
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int k = 0; k < N1; ++k) v[c][k] = act ? xs[(c0 + c) * NG + g0 + k] : T(0);
+    SF::template forward<NC>(v, &gx[c0][0][0], sf, pen, cl, act, a.tb);
+  }
+  // x is consumed: the tile buffer becomes the accumulator
+  for (int idx = t; idx < DIM * NG; idx += TG::BLOCK) xs[idx] = T(0);
+
+  if (act) {
+#pragma unroll
+    for (int q = 0; q < N1; ++q) {
+      const int qp = qp_index<DIM, N1>(p0, p1, q);
+      const int mid = material_of(a, e, qp);
+      const T mu = mid ? a.mu[1] : a.mu[0];
+      const T lam = mid ? a.lam[1] : a.lam[0];
+      const T wt = qp_weight<DIM, N1, T>(a.tb, p0, p1, q) * a.wscale;
+      T Hx[DIM][DIM];
+#pragma unroll
+      for (int i = 0; i < DIM; ++i)
+#pragma unroll
+        for (int I = 0; I < DIM; ++I) Hx[i][I] = gx[i][I][q] * a.invh;
+      T Fi[DIM][DIM], S[DIM][DIM], c1;
+      if constexpr (POL == POL_R || POL == POL_CF) {
+        T H[DIM][DIM];
+        if constexpr (POL == POL_R) {
+#pragma unroll
+          for (int i = 0; i < DIM; ++i)
+#pragma unroll
+            for (int I = 0; I < DIM; ++I) H[i][I] = gu[i][I][q] * a.invh;
+        } else {
+          const T* cq = a.cache + (long long)qp * a.ncells + e;
+          const long long stride = (long long)TG::NV * a.ncells;
+#pragma unroll
+          for (int i = 0; i < DIM; ++i)
+#pragma unroll
+            for (int I = 0; I < DIM; ++I) H[i][I] = cq[(i * DIM + I) * stride] - (i == I ? T(1) : T(0));
+        }
+        T F[DIM][DIM], jm1;
+        kinematics<DIM, T>(H, F, Fi, jm1);
+        c1 = mu - T(2) * lam * log1p_t<T>(jm1);
+        pk2<DIM, T>(Fi, mu, c1, S);
+      } else {
+        const T* cq = a.cache + (long long)qp * a.ncells + e;
+        const long long stride = (long long)TG::NV * a.ncells;
+        int w = 0;
+#pragma unroll
+        for (int I = 0; I < DIM; ++I)
+#pragma unroll
+          for (int j = 0; j < DIM; ++j) Fi[I][j] = cq[(w++) * stride];
+#pragma unroll
+        for (int I = 0; I < DIM; ++I)
+#pragma unroll
+          for (int J = I; J < DIM; ++J) {
+            const T s = cq[(w++) * stride];
+            S[I][J] = s;
+            S[J][I] = s;
+          }
+        c1 = cq[w * stride];
+      }
+      tangent_qp<DIM, T>(Hx, Fi, S, c1, lam, wt);
+#pragma unroll
+      for (int i = 0; i < DIM; ++i)
+#pragma unroll
+        for (int I = 0; I < DIM; ++I) gx[i][I][q] = Hx[i][I];
+    }
+  }
+
+#pragma unroll
+  for (int c0 = 0; c0 < DIM; c0 += NC) {
+    T out[NC][N1];
+    SF::template backward<NC>(&gx[c0][0][0], out, sf, pen, cl, act, a.tb);
+    if (act) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int k = 0; k < N1; ++k) atomicAdd(&xs[(c0 + c) * NG + g0 + k], out[c][k]);
+    }
+  }
+  __syncthreads();
+
+  // 3. tile nodes -> global: exclusive nodes stored, shared tile faces added atomically
+  for (int idx = t; idx < DIM * NG; idx += TG::BLOCK) {
+    const int c = idx / NG, g = idx - c * NG;
+    const int gi = g % GX, gj = (g / GX) % GY, gk = DIM == 3 ? g / (GX * GY) : 0;
+    const int I = tp.cx0 * P + gi, J = tp.cy0 * P + gj, K = tp.cz0 * P + gk;
+    if (!(I < L && J < L && (DIM == 2 || K < L))) continue;
+    if (node_faces(I, J, K, L, DIM) & a.fmask[c]) continue;
+    const bool shx = (gi == 0 && I != 0) || (gi == tp.ex * P && I != L - 1);
+    const bool shy = (gj == 0 && J != 0) || (gj == tp.ey * P && J != L - 1);
+    const bool shz = DIM == 3 && ((gk == 0 && K != 0) || (gk == tp.ez * P && K != L - 1));
+    const long long node = I + (long long)L * (J + (long long)L * K);
+    T* p = a.y + c * a.nn + node;
+    if (shx || shy || shz)
+      atomic_add(p, xs[idx]);
+    else
+      *p = xs[idx];
+  }
 }
 
 // Residual of the weak form: y += sum_q w P(F) : Grad N (FP64).

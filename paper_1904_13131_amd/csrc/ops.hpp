@@ -14,6 +14,10 @@ struct OpFns {
   void (*qpdata_d[3])(const CellArgs<double>&, double* cache, unsigned grid, hipStream_t);
   void (*qpdata_f[3])(const CellArgs<double>&, float* cache, unsigned grid, hipStream_t);
   void (*diag)(const CellArgs<double>&, unsigned grid, hipStream_t);
+  // tile variant of the tangent vmult (atomic scatter only); grid = tiles(N)
+  void (*tangent_tile_d[3])(const CellArgs<double>&, unsigned grid, hipStream_t);
+  void (*tangent_tile_f[3])(const CellArgs<float>&, unsigned grid, hipStream_t);
+  long long (*tiles[2])(int N);   // [0] double, [1] float
   void (*coarse_assemble)(const CellArgs<double>&, const int* fmap, long long nf, double* K,
                           unsigned grid, hipStream_t);
   int cpb;        // cells per block of the pencil kernels

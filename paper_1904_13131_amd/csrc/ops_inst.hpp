@@ -8,8 +8,48 @@
 
 namespace mfh {
 
+// Tile shape (cells per axis) and components per sweep batch of the tile kernel,
+// per dimension, degree and precision.  A tile uses cells x (pencils per cell)
+// threads; the FP64 kernels hold about 2x the registers of the FP32 ones, so
+// their tiles stay within 256 threads (two resident blocks per CU).
+template <int DIM, int P, typename T>
+struct TileCfg;
+#define MFH_TILE(D, P, T, X, Y, Z, C) \
+  template <> struct TileCfg<D, P, T> { static constexpr int TX = X, TY = Y, TZ = Z, NC = C; };
+MFH_TILE(3, 1, double, 4, 4, 4, 3)
+MFH_TILE(3, 1, float, 4, 4, 4, 3)
+MFH_TILE(3, 2, double, 3, 3, 3, 3)
+MFH_TILE(3, 2, float, 4, 4, 2, 3)
+MFH_TILE(3, 3, double, 2, 2, 4, 1)
+MFH_TILE(3, 3, float, 2, 2, 4, 3)
+MFH_TILE(3, 4, double, 2, 2, 2, 1)
+MFH_TILE(3, 4, float, 2, 2, 2, 1)
+MFH_TILE(2, 1, double, 16, 8, 1, 2)
+MFH_TILE(2, 1, float, 16, 8, 1, 2)
+MFH_TILE(2, 2, double, 16, 5, 1, 2)
+MFH_TILE(2, 2, float, 16, 5, 1, 2)
+MFH_TILE(2, 3, double, 8, 8, 1, 2)
+MFH_TILE(2, 3, float, 8, 8, 1, 2)
+MFH_TILE(2, 4, double, 8, 6, 1, 2)
+MFH_TILE(2, 4, float, 8, 6, 1, 2)
+#undef MFH_TILE
+
 template <int DIM, int P>
 struct OpInst {
+  template <typename T, int POL>
+  static void tangent_tile(const CellArgs<T>& a, unsigned grid, hipStream_t s) {
+    using TC = TileCfg<DIM, P, T>;
+    using TGeo = TileGeo<DIM, P, TC::TX, TC::TY, TC::TZ>;
+    hipLaunchKernelGGL((k_tangent_tile<DIM, P, T, POL, TC::TX, TC::TY, TC::TZ, TC::NC>), dim3(grid),
+                       dim3(TGeo::BLOCK), 0, s, a);
+  }
+  template <typename T>
+  static long long tiles(int N) {
+    using TC = TileCfg<DIM, P, T>;
+    const long long tx = (N + TC::TX - 1) / TC::TX, ty = (N + TC::TY - 1) / TC::TY;
+    const long long tz = DIM == 3 ? (N + TC::TZ - 1) / TC::TZ : 1;
+    return tx * ty * tz;
+  }
   template <typename T, int POL>
   static void tangent(const CellArgs<T>& a, unsigned grid, hipStream_t s) {
     hipLaunchKernelGGL((k_tangent<DIM, P, T, POL>), dim3(grid), dim3(kBlock), 0, s, a);
@@ -36,6 +76,9 @@ struct OpInst {
         {&qpdata<double, POL_R>, &qpdata<double, POL_CF>, &qpdata<double, POL_C2>},
         {&qpdata<float, POL_R>, &qpdata<float, POL_CF>, &qpdata<float, POL_C2>},
         &diag,
+        {&tangent_tile<double, POL_R>, &tangent_tile<double, POL_CF>, &tangent_tile<double, POL_C2>},
+        {&tangent_tile<float, POL_R>, &tangent_tile<float, POL_CF>, &tangent_tile<float, POL_C2>},
+        {&tiles<double>, &tiles<float>},
         &coarse_assemble,
         Geo<DIM, P + 1>::CPB,
         kBlock / (DIM == 3 ? (P + 1) * (P + 1) * (P + 1) : (P + 1) * (P + 1)),

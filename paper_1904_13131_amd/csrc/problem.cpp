@@ -9,9 +9,10 @@
 #include <memory>
 #include <stdexcept>
 #include <string>
+#include <type_traits>
 #include <vector>
 
-#include "../../include/mfh.h"
+#include "mfh.h"
 #include "ops.hpp"
 #include "tables.hpp"
 #include "vec.hpp"
@@ -172,7 +173,7 @@ void validate(const mfh_desc* d) {
   }
   if (d->dirichlet_mask >> (2 * d->dim * d->dim)) bad("dirichlet_mask has bits beyond 2*dim*dim");
   if (d->qp_policy < 0 || d->qp_policy > 2) bad("qp_policy must be 0..2");
-  if (d->scatter != MFH_SCATTER_ATOMIC && d->scatter != MFH_SCATTER_COLOR) bad("bad scatter mode");
+  if (d->scatter < MFH_SCATTER_ATOMIC || d->scatter > MFH_SCATTER_TILE) bad("bad scatter mode");
   if (d->vcycle_dtype != MFH_F32 && d->vcycle_dtype != MFH_F64) bad("bad vcycle_dtype");
   if (d->cheb_degree < 1 || d->cheb_degree > 16) bad("cheb_degree must be 1..16");
   if (d->n_smooth < 1 || d->n_smooth > 8) bad("n_smooth must be 1..8");
@@ -383,6 +384,9 @@ struct Sel<double> {
   static void run(const OpFns* o, int pol, const CellArgs<double>& a, unsigned g, hipStream_t s) {
     o->tangent_d[pol](a, g, s);
   }
+  static void run_tile(const OpFns* o, int pol, const CellArgs<double>& a, unsigned g, hipStream_t s) {
+    o->tangent_tile_d[pol](a, g, s);
+  }
   static Band<double> band(const DevBand& b) { return b.get<double>(); }
 };
 template <>
@@ -391,6 +395,9 @@ struct Sel<float> {
   static const float* cache(const Level& v) { return v.cache32; }
   static void run(const OpFns* o, int pol, const CellArgs<float>& a, unsigned g, hipStream_t s) {
     o->tangent_f[pol](a, g, s);
+  }
+  static void run_tile(const OpFns* o, int pol, const CellArgs<float>& a, unsigned g, hipStream_t s) {
+    o->tangent_tile_f[pol](a, g, s);
   }
   static Band<float> band(const DevBand& b) { return b.get<float>(); }
 };
@@ -423,7 +430,10 @@ void vmult(mfh_problem* P, int l, const T* x, T* y, int mask_in = 1) {
   a.mask_in = mask_in;
   const int cpb = P->ops->cpb;
   timer_mark(P);
-  if (P->d.scatter == MFH_SCATTER_ATOMIC) {
+  if (P->d.scatter == MFH_SCATTER_TILE) {
+    const int ti = std::is_same<T, double>::value ? 0 : 1;
+    Sel<T>::run_tile(P->ops, P->d.qp_policy, a, (unsigned)P->ops->tiles[ti](v.N), P->stream);
+  } else if (P->d.scatter == MFH_SCATTER_ATOMIC) {
     Sel<T>::run(P->ops, P->d.qp_policy, a, (unsigned)((v.ncells + cpb - 1) / cpb), P->stream);
   } else {
     for (int color = 0; color < (1 << P->d.dim); ++color) {
@@ -441,7 +451,7 @@ void residual(mfh_problem* P, const double* u, double* r) {
   fill_dirichlet<double>(r, nullptr, v.ndofs, v.lt, P->stream);
   CellArgs<double> a = cell_args<double>(P, v, u, nullptr, nullptr, r);
   const int cpb = P->ops->cpb;
-  if (P->d.scatter == MFH_SCATTER_ATOMIC) {
+  if (P->d.scatter != MFH_SCATTER_COLOR) {
     P->ops->residual(a, (unsigned)((v.ncells + cpb - 1) / cpb), P->stream);
   } else {
     for (int color = 0; color < (1 << P->d.dim); ++color) {

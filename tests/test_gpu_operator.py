@@ -47,7 +47,7 @@ def _oracle(name):
     return _ORACLE[name]
 
 
-@pytest.mark.parametrize("scatter", [0, 1], ids=["atomic", "color"])
+@pytest.mark.parametrize("scatter", [0, 1, 2], ids=["atomic", "color", "tile"])
 @pytest.mark.parametrize("policy", [0, 1, 2], ids=["R", "CF", "C2"])
 @pytest.mark.parametrize("name", list(CASES))
 def test_vmult_fp64(name, policy, scatter):
@@ -61,13 +61,14 @@ def test_vmult_fp64(name, policy, scatter):
     assert rel_l2(y, K @ w["x"]) <= 1e-12
 
 
+@pytest.mark.parametrize("scatter", [0, 2], ids=["atomic", "tile"])
 @pytest.mark.parametrize("policy", [0, 1, 2], ids=["R", "CF", "C2"])
 @pytest.mark.parametrize("name", list(CASES))
-def test_vmult_fp32(name, policy):
-    log_case("vmult_fp32", name=name, policy=policy)
+def test_vmult_fp32(name, policy, scatter):
+    log_case("vmult_fp32", name=name, policy=policy, scatter=scatter)
     w = CASES[name]
     _, _, _, K, _ = _oracle(name)
-    P = device_problem(w, qp_policy=policy)
+    P = device_problem(w, qp_policy=policy, scatter=scatter)
     P.set_deformation(dev(w["u"]))
     x32 = w["x"].astype(np.float32)
     y = host(P.tangent_vmult(dev(x32, torch.float32)))
@@ -128,12 +129,13 @@ def _config2():
     return _C2
 
 
+@pytest.mark.parametrize("scatter", [0, 2], ids=["atomic", "tile"])
 @pytest.mark.parametrize("policy", [0, 1, 2], ids=["R", "CF", "C2"])
-def test_config2_sampled_rows(policy):
+def test_config2_sampled_rows(policy, scatter):
     c = _config2()
     w = c["w"]
-    log_case("config2_rows", policy=policy, n_dofs=c["mesh"].n_dofs)
-    P = device_problem(w, qp_policy=policy)
+    log_case("config2_rows", policy=policy, scatter=scatter, n_dofs=c["mesh"].n_dofs)
+    P = device_problem(w, qp_policy=policy, scatter=scatter)
     P.set_deformation(dev(w["u"]))
     y = host(P.tangent_vmult(dev(w["x"])))
     scale = np.abs(c["ref"]).max()
