@@ -59,7 +59,8 @@ typedef enum {
   MFH_ERR_INVERTED = -4,      /* a quadrature point has J = det F <= 0 (Sec. 2.1)       */
   MFH_ERR_NOT_CONVERGED = -5, /* CG / Newton hit its iteration limit; outputs still set */
   MFH_ERR_BREAKDOWN = -6,     /* CG: p^T A p <= 0 or a NaN appeared                     */
-  MFH_ERR_NOT_SPD = -7        /* coarse-level factorisation met a non-positive pivot    */
+  MFH_ERR_NOT_SPD = -7        /* coarse-level tangent numerically singular (zero or
+                                 non-finite pivot); see mfh_coarse_inertia               */
 } mfh_status;
 
 enum { MFH_F64 = 0, MFH_F32 = 1 };
@@ -161,7 +162,7 @@ mfh_status mfh_residual(mfh_problem* problem, const double* u_dev, double* r_dev
  * INVALID_ARG there while operator application keeps working.  The first
  * call after set_deformation builds the preconditioner data and synchronises;
  * later calls are async.  Errors: INVALID_ARG, NOT_SPD (coarse-level tangent
- * not positive definite), BREAKDOWN (eigenvalue estimate), HIP. */
+ * numerically singular), BREAKDOWN (eigenvalue estimate), HIP. */
 mfh_status mfh_gmg_vcycle(mfh_problem* problem, const double* r_dev, double* z_dev);
 
 /* Solves K_c x = b on the finest level with FP64 CG preconditioned by the
@@ -186,6 +187,7 @@ typedef struct {
   double cg_relres;
   double min_J;
   double setup_ms, residual_ms, solve_ms;   /* host wall time of each phase         */
+  int coarse_negative;       /* negative eigenvalues of the coarse-level tangent          */
 } mfh_newton_record;
 
 /* Sets u on constrained DoFs to scale * face_values[2*axis + side][comp]
@@ -225,6 +227,16 @@ mfh_status mfh_restrict(mfh_problem* problem, int level, int dtype, const void* 
 /* One degree-cheb_degree Chebyshev application on `level` >= 1 in the
  * V-cycle's precision (vcycle_dtype): x <- x + p(D^-1 A)(D^-1 (f - A x)).  Async. */
 mfh_status mfh_chebyshev(mfh_problem* problem, int level, const void* f_dev, void* x_dev);
+
+/* Number of negative eigenvalues of the coarse-level tangent about the current
+ * linearisation point (the signs of its elimination pivots).  The V-cycle's
+ * coarse solve is exact for any nonsingular coarse tangent; a nonzero count
+ * means the coarse mesh does not resolve the material well enough for the
+ * level linearised about the interpolated displacement to stay positive
+ * definite (the assumption of Sec. 6), and the preconditioner is then
+ * indefinite.  Builds the preconditioner data if needed (synchronises).
+ * Errors: INVALID_ARG, NOT_SPD, HIP. */
+mfh_status mfh_coarse_inertia(mfh_problem* problem, int* negative);
 
 /* ---- Kernel timers (measurement of the operator kernel) ---- */
 

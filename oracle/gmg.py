@@ -12,7 +12,11 @@ Readings taken where the paper is silent:
 
 * "restrict the displacement" = nodal interpolation of the finer field at the
   coarser support points, applied recursively fine -> coarse;
-* the coarse level is solved exactly (dense Cholesky) in FP64;
+* the coarse level is solved exactly (dense LU) in FP64.  Linearised about the
+  interpolated displacement, the coarse tangent can be indefinite when the
+  coarse mesh does not resolve the material (the assumption of Sec. 6); the
+  exact solve is still defined, and ``coarse_negative`` records its number of
+  negative eigenvalues;
 * the eigenvalue estimate runs Jacobi-preconditioned CG on A y = r0 with r0
   drawn from SplitMix64 (``oracle.rng``, seed ``EIG_SEED``) in [-1, 1) and
   zeroed on constrained DoFs; the largest eigenvalue of the Lanczos
@@ -193,7 +197,9 @@ class Hierarchy:
                 lmax = np.nan
             self.lam_max.append(lmax)
             self.interval.append((self.cheb_lo * lmax, self.cheb_hi * lmax))
-        self.coarse = sla.cho_factor(self.A[0].toarray(), lower=True)
+        A0 = self.A[0].toarray()
+        self.coarse = sla.lu_factor(A0)
+        self.coarse_negative = int((np.linalg.eigvalsh(A0) < 0).sum())
 
     def smooth(self, l, f, x):
         lo, hi = self.interval[l]
@@ -206,7 +212,7 @@ class Hierarchy:
         """One V-cycle applied to the residual r on level l (default finest)."""
         l = self.n_levels - 1 if l is None else l
         if l == 0:
-            return sla.cho_solve(self.coarse, r)
+            return sla.lu_solve(self.coarse, r)
         x = self.smooth(l, r, np.zeros_like(r))
         rc = self.P[l].T @ (r - self.A[l] @ x)
         rc[self.cons[l - 1]] = 0.0

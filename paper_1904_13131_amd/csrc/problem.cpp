@@ -133,6 +133,7 @@ struct mfh_problem {
   bool deformed = false;
   bool precond_ready = false;        // diagonals, lambda_max, coarse inverse built
   bool has_coarse = false;           // coarse level small enough for the dense direct solve
+  int coarse_negative = 0;           // negative pivots (eigenvalues) of the coarse tangent
   std::string err;
   // kernel timers
   bool timing = false;
@@ -321,7 +322,7 @@ size_t layout(mfh_problem* P, char* base) {
   P->gj_R = b.take<double>((size_t)P->nf * 64);
   P->crf = b.take<double>(std::max<long long>(1, P->nf));
   P->czf = b.take<double>(std::max<long long>(1, P->nf));
-  P->flag = b.take<int>(1);
+  P->flag = b.take<int>(2);
   return b.off + 256;
 }
 
@@ -718,19 +719,21 @@ void setup_precond(mfh_problem* P) {
     fill<double>(P->Kinv, 0.0, nf * nf, s);
     CellArgs<double> a = cell_args<double>(P, c, c.u64, nullptr, nullptr, nullptr);
     P->ops->coarse_assemble(a, P->fmap, nf, P->Kinv, (unsigned)c.ncells, s);
-    fill<int>(P->flag, 0, 1, s);
+    fill<int>(P->flag, 0, 2, s);
+    diag_absmax(P->Kinv, nf, P->sc + SC_TMP, s);
     for (long long k0 = 0; k0 < nf; k0 += 64) {
       const int nb = (int)std::min<long long>(64, nf - k0);
-      gj_pivot(P->Kinv, nf, k0, nb, P->gj_P, P->flag, s);
+      gj_pivot(P->Kinv, nf, k0, nb, P->gj_P, P->flag, P->sc + SC_TMP, 1e-12, s);
       gj_panels(P->Kinv, nf, k0, nb, P->gj_P, P->gj_C, P->gj_R, s);
       gj_update(P->Kinv, nf, k0, nb, P->gj_C, P->gj_R, s);
       gj_finish(P->Kinv, nf, k0, nb, P->gj_C, P->gj_R, P->gj_P, s);
     }
     check_launch("coarse inverse");
-    int flag = 0;
-    HIPCHECK(hipMemcpyAsync(&flag, P->flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    int flag[2] = {0, 0};
+    HIPCHECK(hipMemcpyAsync(flag, P->flag, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHECK(hipStreamSynchronize(s));
-    if (flag) throw Error(MFH_ERR_NOT_SPD, "coarse-level tangent is not positive definite");
+    P->coarse_negative = flag[1];
+    if (flag[0]) throw Error(MFH_ERR_NOT_SPD, "coarse-level tangent is numerically singular");
   }
   HIPCHECK(hipStreamSynchronize(s));
   P->precond_ready = true;
@@ -1037,6 +1040,7 @@ mfh_status mfh_newton_solve(mfh_problem* P, double* u, const double* fv, int n_s
         t0 = Clock::now();
         r.min_J = set_deformation(P, u);
         setup_precond(P);
+        r.coarse_negative = P->coarse_negative;
         r.setup_ms = ms_since(t0);
         t0 = Clock::now();
         if (it == 0) {
@@ -1153,6 +1157,17 @@ mfh_status mfh_chebyshev(mfh_problem* P, int level, const void* f, void* x) {
     else
       cheb_apply<double>(P, level, static_cast<const double*>(f), static_cast<double*>(x), false);
     check_launch("chebyshev");
+  });
+}
+
+mfh_status mfh_coarse_inertia(mfh_problem* P, int* negative) {
+  if (!P) return MFH_ERR_INVALID_ARG;
+  return guarded(P, [&] {
+    need(negative != nullptr, "negative is NULL");
+    need(P->deformed, "set_deformation has not succeeded yet");
+    need(P->has_coarse, "coarsest level too large for the direct solve: use more levels");
+    setup_precond(P);
+    *negative = P->coarse_negative;
   });
 }
 

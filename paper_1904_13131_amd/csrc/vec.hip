@@ -283,11 +283,16 @@ __global__ void k_material_bits(uint32_t* __restrict__ bits, long long ncells, i
 
 constexpr int kGJ = 64;
 
+// Inverts the pivot block in LDS by Gauss-Jordan without pivoting.  The
+// pivots are those of a symmetric LDL^T elimination, so their signs give the
+// inertia: flag[1] counts negative pivots; flag[0] is set when a pivot is not
+// finite or |p| <= tol * scale[0] (numerically singular).
 __global__ void k_gj_pivot(double* __restrict__ A, long long n, long long k0, int nb, double* __restrict__ Pinv,
-                           int* flag) {
+                           int* flag, const double* scale, double tol) {
   __shared__ double M[kGJ][kGJ + 1];
   __shared__ double colk[kGJ], rowk[kGJ];
   const int t = threadIdx.x;
+  const double thr = tol * scale[0];
   for (int e = t; e < nb * nb; e += blockDim.x) {
     const int i = e / nb, j = e % nb;
     M[i][j] = A[(k0 + i) * n + k0 + j];
@@ -300,7 +305,10 @@ __global__ void k_gj_pivot(double* __restrict__ A, long long n, long long k0, in
     }
     __syncthreads();
     const double p = rowk[k];
-    if (t == 0 && !(p > 0.0)) *flag = 1;
+    if (t == 0) {
+      if (!(fabs(p) > thr) || !isfinite(p)) flag[0] = 1;
+      if (p < 0.0) flag[1] += 1;
+    }
     const double pinv = 1.0 / p;
     for (int e = t; e < nb * nb; e += blockDim.x) {
       const int i = e / nb, j = e % nb;
@@ -319,6 +327,20 @@ __global__ void k_gj_pivot(double* __restrict__ A, long long n, long long k0, in
     const int i = e / nb, j = e % nb;
     Pinv[i * nb + j] = M[i][j];
   }
+}
+
+// scale[0] = max_i |A[i][i]|
+__global__ void k_diag_absmax(const double* __restrict__ A, long long n, double* scale) {
+  __shared__ double sh[kVB];
+  double m = 0;
+  for (long long i = threadIdx.x; i < n; i += kVB) m = fmax(m, fabs(A[i * n + i]));
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = kVB / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) scale[0] = sh[0];
 }
 
 // R[t][j] = sum_s Pinv[t][s] A[k0+s][j]
@@ -540,8 +562,12 @@ void material_bits(uint32_t* bits, long long ncells, int N, int dim, int n1, con
                      h, incl, nincl, nwords);
 }
 
-void gj_pivot(double* A, long long n, long long k0, int nb, double* Pinv, int* flag, hipStream_t s) {
-  hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(256), 0, s, A, n, k0, nb, Pinv, flag);
+void gj_pivot(double* A, long long n, long long k0, int nb, double* Pinv, int* flag, const double* scale, double tol,
+              hipStream_t s) {
+  hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(256), 0, s, A, n, k0, nb, Pinv, flag, scale, tol);
+}
+void diag_absmax(const double* A, long long n, double* scale, hipStream_t s) {
+  hipLaunchKernelGGL(k_diag_absmax, dim3(1), dim3(kVB), 0, s, A, n, scale);
 }
 void gj_panels(const double* A, long long n, long long k0, int nb, const double* Pinv, double* Cb, double* R,
                hipStream_t s) {

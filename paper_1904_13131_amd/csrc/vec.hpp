@@ -87,8 +87,12 @@ void dirichlet_delta(const double* u, double* dg, const Lattice& lt, const doubl
 void material_bits(uint32_t* bits, long long ncells, int N, int dim, int n1, const Tables<double>& tb, double h,
                    const double* incl, int nincl, int nwords, hipStream_t s);
 
-// Coarse direct solve: in-place block Gauss-Jordan inverse of an SPD matrix.
-void gj_pivot(double* A, long long n, long long k0, int nb, double* Pinv, int* flag, hipStream_t s);
+// Coarse direct solve: in-place block Gauss-Jordan inverse of a symmetric
+// nonsingular matrix (no pivoting).  flag[0]: singular pivot met; flag[1]:
+// number of negative pivots (the inertia of the matrix).
+void diag_absmax(const double* A, long long n, double* scale, hipStream_t s);
+void gj_pivot(double* A, long long n, long long k0, int nb, double* Pinv, int* flag, const double* scale, double tol,
+              hipStream_t s);
 void gj_panels(const double* A, long long n, long long k0, int nb, const double* Pinv, double* Cb, double* R,
                hipStream_t s);
 void gj_update(double* A, long long n, long long k0, int nb, const double* Cb, const double* R, hipStream_t s);

@@ -45,6 +45,7 @@ class NewtonRecord(ctypes.Structure):
         ("residual_norm", ctypes.c_double), ("residual_after", ctypes.c_double),
         ("du_norm", ctypes.c_double), ("cg_relres", ctypes.c_double), ("min_J", ctypes.c_double),
         ("setup_ms", ctypes.c_double), ("residual_ms", ctypes.c_double), ("solve_ms", ctypes.c_double),
+        ("coarse_negative", ctypes.c_int),
     ]
 
     def as_dict(self):
@@ -87,6 +88,7 @@ def lib():
         "mfh_prolongate": (st, [_P, ctypes.c_int, ctypes.c_int, _P, _P]),
         "mfh_restrict": (st, [_P, ctypes.c_int, ctypes.c_int, _P, _P]),
         "mfh_chebyshev": (st, [_P, ctypes.c_int, _P, _P]),
+        "mfh_coarse_inertia": (st, [_P, ctypes.POINTER(ctypes.c_int)]),
         "mfh_timer_enable": (st, [_P, ctypes.c_int]),
         "mfh_timer_read": (st, [_P, _D, ctypes.POINTER(ctypes.c_longlong)]),
     }
@@ -260,6 +262,11 @@ class Problem:
         y = self._vec(level - 1, x.dtype) if y is None else y
         _check(lib().mfh_restrict(self.handle, level, dt, _ptr(x), _ptr(y)), self.handle)
         return y
+
+    def coarse_inertia(self):
+        n = ctypes.c_int()
+        _check(lib().mfh_coarse_inertia(self.handle, ctypes.byref(n)), self.handle)
+        return n.value
 
     def timer_enable(self, enable=True):
         _check(lib().mfh_timer_enable(self.handle, 1 if enable else 0), self.handle)

@@ -156,6 +156,30 @@ def test_newton_uniaxial_closed_form(vdt):
     assert all(r["cg_relres"] <= 1e-8 for r in recs)
 
 
+def test_coarse_inertia_matches_oracle():
+    """A hydrostatically compressed clamped body has an indefinite tangent; the
+    exact coarse solve counts its negative eigenvalues (pivot signs)."""
+    from paper_1904_13131_amd import Problem
+    log_case("coarse_inertia")
+    mask = W.clamp_bottom_top(3)
+    m = fe.Mesh(3, 2, 2)
+    X = m.node_coords()
+    u = np.ascontiguousarray((-0.15 * X).T.reshape(-1))
+    cons = m.constrained(mask)
+    K = fe.constrain_matrix(fe.tangent_matrix(m, fe.Material([1.0], [1.5]), u), cons).toarray()
+    ev = np.linalg.eigvalsh(K)
+    want = int((ev < 0).sum())
+    kappa = np.abs(ev).max() / np.abs(ev).min()
+    assert want > 0
+    P = Problem(3, 2, 2, n_levels=1, mu=(1.0,), lam=(1.5,), dirichlet_mask=mask, vcycle_dtype=F64)
+    P.set_deformation(dev(u))
+    assert P.coarse_inertia() == want
+    b = W.normal_vector(P.n_dofs(), 3)
+    b[cons] = 0.0
+    z = host(P.gmg_vcycle(dev(b)))            # one level: the V-cycle is the exact solve
+    assert rel_l2(K @ z, b) <= 1e-14 * kappa   # backward-stable bound for the condition number
+
+
 def test_error_paths():
     from paper_1904_13131_amd import Problem
     log_case("errors")
@@ -189,7 +213,7 @@ def test_error_paths():
     P.set_deformation(dev(u))
     y = host(P.tangent_vmult(dev(b)))
     assert rel_l2(y, H.A[-1] @ b) <= 1e-12
-    # a compressed coarse level whose tangent is indefinite
+    # an unconstrained compressed coarse level: singular (translations) and indefinite
     Pc = Problem(3, 2, 1, n_levels=1, mu=(1.0,), lam=(1.5,))
     mc = fe.Mesh(3, 2, 1)
     Xc = mc.node_coords()
