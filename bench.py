@@ -32,6 +32,13 @@ POLICIES = {0: "recompute", 1: "cache_F", 2: "cache_T2"}
 
 # Algorithmic flop counts: minimal sum factorisation of one
 # d-component field, 4 d^2 n^(d+1), plus the quadrature-point algebra per point.
+# HBM bytes per launch of the config-2 cell kernel from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE (scaled by a 256 MiB copy; profiles/tangent_vmult_q2_32cube_hbm_counters.md),
+# valid only for the kernel source they were taken on.
+TRAFFIC_SOURCE_SHA = "5ce735f120729aec"
+TRAFFIC = {"recompute/f64": 47457545, "cache_F/f64": 104571648, "cache_T2/f64": 155377258,
+           "recompute/f32": 26753497, "cache_F/f32": 55156583, "cache_T2/f32": 80341153}
+
 QP_FLOPS_3D = {0: 313, 1: 307, 2: 188}
 QP_FLOPS_2D = {0: 118, 1: 116, 2: 78}
 CACHE_WORDS = {3: {0: 0, 1: 9, 2: 16}, 2: {0: 0, 1: 4, 2: 8}}
@@ -53,8 +60,18 @@ def algorithmic_cost(dim, degree, n_cells, n_dofs, policy, word):
     return flops, nbytes
 
 
+def measured_traffic(policy, dtype):
+    import hashlib
+    src = os.path.join(ROOT, "paper_1904_13131_amd", "csrc", "cellops.hpp")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if sha != TRAFFIC_SOURCE_SHA:
+        return None
+    return TRAFFIC.get(f"{POLICIES[policy]}/{dtype}")
+
+
 def roofline(dim, degree, n_cells, n_dofs, policy, dtype, kernel_ms):
     word = 8 if dtype == "f64" else 4
+    traffic = measured_traffic(policy, dtype)
     flops, nbytes = algorithmic_cost(dim, degree, n_cells, n_dofs, policy, word)
     t_hbm = nbytes / (HBM_PEAK_GBS * 1e9)
     t_alu = flops / (PEAK_TFLOPS[dtype] * 1e12)
@@ -62,10 +79,10 @@ def roofline(dim, degree, n_cells, n_dofs, policy, dtype, kernel_ms):
     if t_hbm >= t_alu:
         ach = nbytes / s / 1e9
         return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-                "traffic": None, "alg_bytes": nbytes, "alg_flops": flops}
+                "traffic": traffic, "alg_bytes": nbytes, "alg_flops": flops}
     ach = flops / s / 1e12
     return {"bound": "alu", "achieved": ach, "peak": PEAK_TFLOPS[dtype], "unit": "TFLOP/s",
-            "frac": ach / PEAK_TFLOPS[dtype], "traffic": None, "alg_bytes": nbytes, "alg_flops": flops}
+            "frac": ach / PEAK_TFLOPS[dtype], "traffic": traffic, "alg_bytes": nbytes, "alg_flops": flops}
 
 
 def time_vmult(P, x, y, steps, warmup, cold=False, flush=None):
@@ -107,6 +124,47 @@ def cpu_baseline(w, n_sample_cells=32768):
             "host_threads_available": os.cpu_count()}
 
 
+def newton_bench(w, n_cells=64, n_levels=5, stretch=0.1, n_steps=4):
+    """Config 3: Newton load stepping with GMG-CG (1e-8) on the config-2 material,
+    64^3 Q2 (6.44M DoFs), levels 4^3..64^3, clamped bottom/top, 10 % stretch in
+    4 steps; mixed-precision (FP32 V-cycle) and all-FP64 forms."""
+    import torch
+
+    import workloads as W
+    from paper_1904_13131_amd import F32, F64, Problem
+    out = {"workload": f"3-D Q2 {n_cells}^3 ({(2 * n_cells + 1) ** 3 * 3:,} DoFs), levels "
+                       f"{n_cells >> (n_levels - 1)}^3..{n_cells}^3, config-2 material, clamped bottom/top, "
+                       f"{stretch:.0%} stretch in {n_steps} load steps, FP64 CG to 1e-8 with a V(2,2) "
+                       f"Chebyshev(4) GMG preconditioner, FP64 dense coarse solve"}
+    for name, vdt in (("mixed", F32), ("fp64", F64)):
+        P = Problem(3, n_cells, 2, n_levels=n_levels, mu=tuple(w["mu"]), lam=tuple(w["lam"]),
+                    inclusions=w["inclusions"], dirichlet_mask=W.clamp_bottom_top(3), vcycle_dtype=vdt)
+        u = torch.zeros(P.n_dofs(), dtype=torch.float64, device="cuda")
+        fv = np.zeros((6, 3))
+        fv[5][2] = stretch
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        recs, st = P.newton_solve(u, fv, n_steps=n_steps, raise_on_error=False)
+        total = time.perf_counter() - t0
+        steps = [r["setup_ms"] + r["residual_ms"] + r["solve_ms"] for r in recs]
+        out[name] = {
+            "status": int(st), "newton_steps": len(recs), "total_s": round(total, 3),
+            "median_step_ms": float(np.median(steps)), "mean_step_ms": float(np.mean(steps)),
+            "median_setup_ms": float(np.median([r["setup_ms"] for r in recs])),
+            "median_solve_ms": float(np.median([r["solve_ms"] for r in recs])),
+            "cg_iters": [r["cg_iters"] for r in recs],
+            "max_cg_relres": max(r["cg_relres"] for r in recs),
+            "final_residual": recs[-1]["residual_after"] if recs else None,
+            "coarse_negative_eigs": max(r["coarse_negative"] for r in recs) if recs else None,
+        }
+        print(f"[bench] newton {name}: {len(recs)} steps, median {out[name]['median_step_ms']:.1f} ms, "
+              f"total {total:.2f} s, status {st}", file=sys.stderr, flush=True)
+        del P
+        torch.cuda.empty_cache()
+    out["speedup_mixed_vs_fp64"] = out["fp64"]["median_step_ms"] / out["mixed"]["median_step_ms"]
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,6 +175,7 @@ def main(argv=None):
     ap.add_argument("--dtypes", default="f64,f32")
     ap.add_argument("--no-cold", action="store_true")
     ap.add_argument("--scatter", type=int, default=0, help="0 atomic, 1 colour, 2 tile")
+    ap.add_argument("--no-newton", action="store_true", help="skip the config-3 Newton-step measurement")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 256 MiB device copy (reference for HBM byte counters)")
     a = ap.parse_args(argv)
@@ -198,6 +257,8 @@ def main(argv=None):
     }
     out["roofline"]["kernel_ms"] = r["kernel_ms"]
     out["roofline"]["kernel_ms_cold"] = r["kernel_ms_cold"]
+    if not a.no_newton:
+        out["newton_step"] = newton_bench(w)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)
