@@ -180,7 +180,7 @@ const char* mfh_last_error(const mfh_problem* problem);
 /* ---- Newton load stepping (Sec. 3 Newton-Raphson, Sec. 7 tolerances) ---- */
 
 typedef struct {
-  int load_step, newton_iter, cg_iters;
+  int load_step, newton_iter, cg_iters;   /* load_step counts attempted increments */
   double residual_norm;      /* |rhs| of this Newton step (free rows)                   */
   double residual_after;     /* |R(u)| on free rows after the update                    */
   double du_norm;            /* |du|_2                                                  */
@@ -188,6 +188,8 @@ typedef struct {
   double min_J;
   double setup_ms, residual_ms, solve_ms;   /* host wall time of each phase         */
   int coarse_negative;       /* negative eigenvalues of the coarse-level tangent          */
+  double load_fraction;      /* fraction of the prescribed values this increment reaches  */
+  int cutbacks;              /* load-increment halvings so far in the solve               */
 } mfh_newton_record;
 
 /* Sets u on constrained DoFs to scale * face_values[2*axis + side][comp]
@@ -200,8 +202,12 @@ mfh_status mfh_apply_dirichlet(mfh_problem* problem, double* u_dev,
  * (as for mfh_apply_dirichlet) are applied in n_steps equal increments; the
  * first Newton step of each increment carries it linearly
  * (K_c d = -(R(u) + K(u) dg), u <- u + dg + d), later steps solve
- * K_c du = -R(u).  A step converges when |du| <= du_tol and
- * |R| <= r_tol or |R| <= r_tol |R0| (R0: first right-hand side of the step).
+ * K_c du = -R(u).  An increment converges when |du| <= du_tol and
+ * |R| <= r_tol or |R| <= r_tol |R0| (R0: first right-hand side of the
+ * increment), R on free rows.  When an update inverts a quadrature point or
+ * max_newton steps do not converge, u is restored to the start of the
+ * increment and the increment is halved (at most 8 times in a solve); after a
+ * converged cut increment the increment doubles again up to 1/n_steps.
  * u (device FP64) is the initial state and receives the solution.  Up to
  * max_records records are written to the host array; *n_records receives the
  * number of Newton steps taken.  Synchronises.

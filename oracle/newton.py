@@ -30,7 +30,7 @@ def dirichlet_vector(mesh, face_values, mask, scale=1.0):
 
 
 def solve(hier, face_values, n_steps, rtol=1e-8, max_cg=200, du_tol=1e-5,
-          r_tol=1e-8, max_newton=20, u0=None, log=None):
+          r_tol=1e-8, max_newton=20, u0=None, log=None, max_cutbacks=8):
     """Full Newton solve; returns (u, records) with one record per Newton step.
 
     The prescribed increment dg of a load step enters the first Newton step of
@@ -38,35 +38,60 @@ def solve(hier, face_values, n_steps, rtol=1e-8, max_cg=200, du_tol=1e-5,
     constraints): K_c d = -(R(u) + K(u) dg) on free rows, u <- u + dg + d.
     Later Newton steps solve K_c du = -R(u).  R0, the reference for the
     relative residual test, is the norm of that first right-hand side.
+    The paper does not say what happens when an increment fails; here an
+    update that inverts a quadrature point (non-finite residual) or an
+    increment that does not converge within max_newton steps is undone and
+    the increment halved; after a converged cut increment it doubles again up
+    to 1/n_steps.
     """
     mesh = hier.meshes[-1]
     cons = hier.cons[-1]
     free = ~cons
     u = np.zeros(mesh.n_dofs) if u0 is None else np.array(u0, dtype=np.float64)
     records = []
-    for step in range(1, n_steps + 1):
-        g = dirichlet_vector(mesh, face_values, hier.mask, step / n_steps)
-        dg = np.where(cons, g - u, 0.0)
-        R0 = None
-        for it in range(max_newton):
-            R = fe.residual(mesh, hier.mat, u)
-            hier.set_deformation(u)
-            b = -R
-            if it == 0:
-                b = b - fe.tangent_matrix(mesh, hier.mat, u) @ dg
-            b[cons] = 0.0
-            nb = np.linalg.norm(b)
-            if R0 is None:
-                R0 = nb
-            d, cg_it, rel = gmg.pcg(lambda v: hier.A[-1] @ v, b, hier.vcycle, rtol, max_cg)
-            du = d + dg if it == 0 else d
-            u += du
-            ndu = np.linalg.norm(du)
-            Rn = np.linalg.norm(fe.residual(mesh, hier.mat, u)[free])
-            rec = dict(step=step, newton=it, res=nb, res_after=Rn, du=ndu, cg_iters=cg_it, cg_rel=rel)
-            records.append(rec)
-            if log:
-                log(rec)
-            if ndu <= du_tol and (Rn <= r_tol or Rn <= r_tol * R0):
-                break
+    h0 = 1.0 / n_steps
+    done, h, cut = 0.0, h0, 0
+    with np.errstate(invalid="ignore"):
+        while done < 1.0 - 1e-12:
+            target = min(1.0, done + h)
+            saved = u.copy()
+            g = dirichlet_vector(mesh, face_values, hier.mask, target)
+            dg = np.where(cons, g - u, 0.0)
+            R0 = None
+            conv = False
+            for it in range(max_newton):
+                R = fe.residual(mesh, hier.mat, u)
+                hier.set_deformation(u)
+                b = -R
+                if it == 0:
+                    b = b - fe.tangent_matrix(mesh, hier.mat, u) @ dg
+                b[cons] = 0.0
+                nb = np.linalg.norm(b)
+                if R0 is None:
+                    R0 = nb
+                d, cg_it, rel = gmg.pcg(lambda v: hier.A[-1] @ v, b, hier.vcycle, rtol, max_cg)
+                du = d + dg if it == 0 else d
+                u += du
+                ndu = np.linalg.norm(du)
+                Rn = np.linalg.norm(fe.residual(mesh, hier.mat, u)[free])
+                rec = dict(load_fraction=target, newton=it, res=nb, res_after=Rn, du=ndu, cg_iters=cg_it,
+                           cg_rel=rel, cutbacks=cut)
+                records.append(rec)
+                if log:
+                    log(rec)
+                if not np.isfinite(Rn):
+                    break
+                if ndu <= du_tol and (Rn <= r_tol or Rn <= r_tol * R0):
+                    conv = True
+                    break
+            if conv:
+                done = target
+                if h < h0:
+                    h = min(h0, 2.0 * h)
+                continue
+            u = saved
+            cut += 1
+            if cut > max_cutbacks:
+                raise RuntimeError(f"Newton failed after {max_cutbacks} cut-backs at load fraction {done}")
+            h *= 0.5
     return u, records

@@ -121,7 +121,7 @@ struct mfh_problem {
   char* tmpA = nullptr;
   char* tmpB = nullptr;
   double *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_Ap = nullptr;
-  double *nw_R = nullptr, *nw_dg = nullptr, *nw_b = nullptr, *nw_du = nullptr;
+  double *nw_R = nullptr, *nw_dg = nullptr, *nw_b = nullptr, *nw_du = nullptr, *nw_save = nullptr;
   // coarse level
   long long nf = 0;
   int* fmap = nullptr;               // dof -> free index or -1
@@ -313,6 +313,7 @@ size_t layout(mfh_problem* P, char* base) {
   P->nw_dg = b.take<double>(top.ndofs);
   P->nw_b = b.take<double>(top.ndofs);
   P->nw_du = b.take<double>(top.ndofs);
+  P->nw_save = b.take<double>(top.ndofs);
   const Level& c = P->lv[0];
   P->fmap = b.take<int>(P->has_coarse ? c.ndofs : 1);
   P->dof_of = b.take<int>(std::max<long long>(1, P->nf));
@@ -1023,22 +1024,35 @@ mfh_status mfh_newton_solve(mfh_problem* P, double* u, const double* fv, int n_s
     const long long n = v.ndofs;
     hipStream_t s = P->stream;
     const int top = (int)P->lv.size() - 1;
-    for (int step = 1; step <= n_steps; ++step) {
-      const double scale = (double)step / n_steps;
-      dirichlet_delta(u, P->nw_dg, v.lt, fv, scale, n, s);
+    const double h0 = 1.0 / n_steps;
+    double done = 0.0, h = h0;
+    int step = 0, cutbacks = 0;
+    const int kMaxCut = 8;
+    while (done < 1.0 - 1e-12) {
+      const double target = std::fmin(1.0, done + h);
+      ++step;
+      HIPCHECK(hipMemcpyAsync(P->nw_save, u, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+      dirichlet_delta(u, P->nw_dg, v.lt, fv, target, n, s);
       double R0 = -1;
-      bool conv = false;
+      bool conv = false, bad = false;
       bool have_R = false;
       for (int it = 0; it < max_newton; ++it) {
         mfh_newton_record r{};
         r.load_step = step;
         r.newton_iter = it;
+        r.load_fraction = target;
+        r.cutbacks = cutbacks;
         auto t0 = Clock::now();
         if (!have_R) residual(P, u, P->nw_R);
         HIPCHECK(hipStreamSynchronize(s));
         r.residual_ms = ms_since(t0);
         t0 = Clock::now();
-        r.min_J = set_deformation(P, u);
+        mfh_status sd = guarded(P, [&] { r.min_J = set_deformation(P, u); });
+        if (sd == MFH_ERR_INVERTED) {
+          bad = true;
+          break;
+        }
+        if (sd != MFH_OK) throw Error(sd, P->err);
         setup_precond(P);
         r.coarse_negative = P->coarse_negative;
         r.setup_ms = ms_since(t0);
@@ -1067,12 +1081,28 @@ mfh_status mfh_newton_solve(mfh_problem* P, double* u, const double* fv, int n_s
         if (rec && nrec < max_rec) rec[nrec] = r;
         ++nrec;
         if (cr.st == MFH_ERR_NOT_CONVERGED) throw Error(cr.st, "CG did not converge inside Newton");
+        if (!std::isfinite(r.residual_after)) {   // the update inverted a quadrature point
+          bad = true;
+          break;
+        }
         if (r.du_norm <= du_tol && (r.residual_after <= r_tol || r.residual_after <= r_tol * R0)) {
           conv = true;
           break;
         }
       }
-      if (!conv) throw Error(MFH_ERR_NOT_CONVERGED, "Newton did not converge in load step " + std::to_string(step));
+      if (conv) {
+        done = target;
+        if (h < h0) h = std::fmin(h0, 2.0 * h);   // grow back after a successful cut increment
+        continue;
+      }
+      // inverted or not converged: restore the state of the step start and halve the increment
+      HIPCHECK(hipMemcpyAsync(u, P->nw_save, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+      HIPCHECK(hipStreamSynchronize(s));
+      if (++cutbacks > kMaxCut)
+        throw Error(bad ? MFH_ERR_INVERTED : MFH_ERR_NOT_CONVERGED,
+                    std::string("Newton failed after ") + std::to_string(kMaxCut) + " load-step cut-backs at load fraction " +
+                        std::to_string(done));
+      h *= 0.5;
     }
   });
   if (n_rec) *n_rec = nrec;

@@ -45,7 +45,7 @@ class NewtonRecord(ctypes.Structure):
         ("residual_norm", ctypes.c_double), ("residual_after", ctypes.c_double),
         ("du_norm", ctypes.c_double), ("cg_relres", ctypes.c_double), ("min_J", ctypes.c_double),
         ("setup_ms", ctypes.c_double), ("residual_ms", ctypes.c_double), ("solve_ms", ctypes.c_double),
-        ("coarse_negative", ctypes.c_int),
+        ("coarse_negative", ctypes.c_int), ("load_fraction", ctypes.c_double), ("cutbacks", ctypes.c_int),
     ]
 
     def as_dict(self):

@@ -156,6 +156,30 @@ def test_newton_uniaxial_closed_form(vdt):
     assert all(r["cg_relres"] <= 1e-8 for r in recs)
 
 
+@pytest.mark.parametrize("vdt", [F64, F32], ids=["f64", "f32"])
+def test_newton_cutback_matches_oracle(vdt):
+    """2-D plane strain with a stiff disc compressed by 30 % in one increment:
+    the linearised increment inverts elements, so both drivers halve it; the
+    converged solutions agree."""
+    from paper_1904_13131_amd import Problem
+    from oracle import newton
+    log_case("newton_cutback", vcycle=vdt)
+    mu, lam = W.two_phase_material()
+    incl = [(np.array([0.5, 0.5]), 0.3, 1)]
+    mask = W.clamp_bottom_top(2)
+    H = gmg.Hierarchy(2, 2, 2, 3, fe.Material(mu, lam, incl), mask)
+    fv = np.zeros((4, 2))
+    fv[3][1] = -0.3
+    u_o, recs_o = newton.solve(H, fv, n_steps=1)
+    P = Problem(2, 8, 2, n_levels=3, mu=tuple(mu), lam=tuple(lam), inclusions=incl, dirichlet_mask=mask,
+                vcycle_dtype=vdt)
+    u = torch.zeros(P.n_dofs(), dtype=torch.float64, device="cuda")
+    recs, st = P.newton_solve(u, fv, n_steps=1)
+    assert max(r["cutbacks"] for r in recs) == max(r["cutbacks"] for r in recs_o) > 0
+    assert recs[-1]["load_fraction"] == 1.0
+    assert rel_l2(host(u), u_o) <= 1e-7
+
+
 def test_coarse_inertia_matches_oracle():
     """A hydrostatically compressed clamped body has an indefinite tangent; the
     exact coarse solve counts its negative eigenvalues (pivot signs)."""
