@@ -225,7 +225,8 @@ class Hierarchy:
 def pcg(apply_A, b, precond, rtol, max_it):
     """Preconditioned CG (Hestenes-Stiefel), x0 = 0, stop at |r|/|b| <= rtol.
 
-    Returns (x, iterations, relative residual).
+    Returns (x, iterations, relative residual); the relative residual is NaN
+    when CG breaks down (p^T A p <= 0, which an SPD operator never gives).
     """
     b = np.asarray(b, dtype=np.float64)
     x = np.zeros_like(b)
@@ -240,10 +241,13 @@ def pcg(apply_A, b, precond, rtol, max_it):
     rel = 1.0
     while it < max_it:
         Ap = apply_A(p)
-        alpha = rz / (p @ Ap)
+        pAp = p @ Ap
+        it += 1
+        if not pAp > 0.0:
+            return x, it, np.nan
+        alpha = rz / pAp
         x += alpha * p
         r -= alpha * Ap
-        it += 1
         rel = np.linalg.norm(r) / nb
         if rel <= rtol:
             break

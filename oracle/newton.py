@@ -39,10 +39,12 @@ def solve(hier, face_values, n_steps, rtol=1e-8, max_cg=200, du_tol=1e-5,
     Later Newton steps solve K_c du = -R(u).  R0, the reference for the
     relative residual test, is the norm of that first right-hand side.
     The paper does not say what happens when an increment fails; here an
-    update that inverts a quadrature point (non-finite residual) or an
-    increment that does not converge within max_newton steps is undone and
-    the increment halved; after a converged cut increment it doubles again up
-    to 1/n_steps.
+    update that inverts a quadrature point (non-finite residual), a CG
+    breakdown (p^T K p <= 0: the tangent is indefinite at the iterate), a CG
+    that misses rtol in max_cg steps, or an increment that does not converge
+    within max_newton steps is undone and
+    the failed increment halved; after a converged cut increment the step
+    doubles again up to 1/n_steps.
     """
     mesh = hier.meshes[-1]
     cons = hier.cons[-1]
@@ -70,6 +72,13 @@ def solve(hier, face_values, n_steps, rtol=1e-8, max_cg=200, du_tol=1e-5,
                 if R0 is None:
                     R0 = nb
                 d, cg_it, rel = gmg.pcg(lambda v: hier.A[-1] @ v, b, hier.vcycle, rtol, max_cg)
+                if not np.isfinite(rel):          # CG breakdown
+                    rec = dict(load_fraction=target, newton=it, res=nb, res_after=np.nan, du=np.nan,
+                               cg_iters=cg_it, cg_rel=rel, cutbacks=cut)
+                    records.append(rec)
+                    if log:
+                        log(rec)
+                    break
                 du = d + dg if it == 0 else d
                 u += du
                 ndu = np.linalg.norm(du)
@@ -79,7 +88,7 @@ def solve(hier, face_values, n_steps, rtol=1e-8, max_cg=200, du_tol=1e-5,
                 records.append(rec)
                 if log:
                     log(rec)
-                if not np.isfinite(Rn):
+                if not np.isfinite(Rn) or rel > rtol:     # inverted, or the linear solve failed
                     break
                 if ndu <= du_tol and (Rn <= r_tol or Rn <= r_tol * R0):
                     conv = True
@@ -93,5 +102,5 @@ def solve(hier, face_values, n_steps, rtol=1e-8, max_cg=200, du_tol=1e-5,
             cut += 1
             if cut > max_cutbacks:
                 raise RuntimeError(f"Newton failed after {max_cutbacks} cut-backs at load fraction {done}")
-            h *= 0.5
+            h = 0.5 * (target - done)
     return u, records

@@ -101,6 +101,18 @@ def test_pcg_with_vcycle_matches_direct_solve():
     assert np.all(x[H.cons[-1]] == 0)
 
 
+def test_pcg_reports_breakdown_on_negative_curvature():
+    """CG on an indefinite operator stops with a NaN relative residual at the
+    first direction of non-positive curvature (p^T A p <= 0)."""
+    A = np.diag([1.0, -1.0, 2.0])
+    b = np.array([0.0, 1.0, 0.0])
+    x, it, rel = gmg.pcg(lambda v: A @ v, b, lambda r: r.copy(), 1e-8, 10)
+    assert it == 1 and np.isnan(rel) and np.all(x == 0)
+    # an SPD operator with the same right-hand side converges in one step
+    x, it, rel = gmg.pcg(lambda v: np.abs(A) @ v, b, lambda r: r.copy(), 1e-8, 10)
+    assert it == 1 and rel == 0.0 and np.allclose(x, b)
+
+
 def test_vcycle_is_symmetric_and_h_independent():
     """The V-cycle is a symmetric preconditioner, and for a homogeneous body
     the PCG iteration count does not grow under refinement (Sec. 6)."""

@@ -34,3 +34,22 @@ def test_uniaxial_stretch_closed_form(dim, p, delta):
     Pzz = (mu * (1 + delta) ** 2 - (mu - 2 * lam * np.log(s ** (dim - 1) * (1 + delta)))) / (1 + delta)
     assert abs(R[top, ax].sum() - Pzz) < 1e-9
     assert all(r["cg_rel"] <= 1e-8 for r in recs)
+
+
+def test_cutback_reaches_the_same_equilibrium():
+    """A stiff disc compressed 30 % in one increment: the first Newton
+    iterates hit negative curvature (CG breakdown), so the driver halves the
+    failed increment; the converged state is the one four uncut increments
+    reach (the equilibrium of a hyperelastic body does not depend on the
+    loading path while it stays on one branch)."""
+    mu, lam = W.two_phase_material()
+    mat = fe.Material(mu, lam, [(np.array([0.5, 0.5]), 0.3, 1)])
+    H = gmg.Hierarchy(2, 2, 2, 3, mat, W.clamp_bottom_top(2))
+    fv = np.zeros((4, 2))
+    fv[3][1] = -0.3
+    u1, r1 = newton.solve(H, fv, n_steps=1)
+    u4, r4 = newton.solve(H, fv, n_steps=4)
+    assert max(r["cutbacks"] for r in r1) == 2 and max(r["cutbacks"] for r in r4) == 0
+    assert [r["load_fraction"] for r in r1 if not np.isfinite(r["cg_rel"])] == [1.0, 1.0]
+    assert r1[-1]["load_fraction"] == 1.0
+    assert np.linalg.norm(u1 - u4) <= 1e-10 * np.linalg.norm(u4)
