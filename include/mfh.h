@@ -204,10 +204,14 @@ mfh_status mfh_apply_dirichlet(mfh_problem* problem, double* u_dev,
  * (K_c d = -(R(u) + K(u) dg), u <- u + dg + d), later steps solve
  * K_c du = -R(u).  An increment converges when |du| <= du_tol and
  * |R| <= r_tol or |R| <= r_tol |R0| (R0: first right-hand side of the
- * increment), R on free rows.  When an update inverts a quadrature point or
- * max_newton steps do not converge, u is restored to the start of the
- * increment and the increment is halved (at most 8 times in a solve); after a
- * converged cut increment the increment doubles again up to 1/n_steps.
+ * increment), R on free rows.  An increment fails when an update inverts a
+ * quadrature point, when the CG breaks down (p^T K p <= 0: the tangent is
+ * indefinite at the iterate) or does not reach cg_rtol in cg_max_it steps, or
+ * when max_newton steps do not converge; then u is restored to the start of
+ * the increment and the failed increment is halved (at most 8 times in a
+ * solve); after a converged cut increment the step doubles again up to
+ * 1/n_steps.  The record of a Newton step whose CG broke down carries NaN in
+ * cg_relres and residual_after.
  * u (device FP64) is the initial state and receives the solution.  Up to
  * max_records records are written to the host array; *n_records receives the
  * number of Newton steps taken.  Synchronises.
@@ -243,6 +247,53 @@ mfh_status mfh_chebyshev(mfh_problem* problem, int level, const void* f_dev, voi
  * indefinite.  Builds the preconditioner data if needed (synchronises).
  * Errors: INVALID_ARG, NOT_SPD, HIP. */
 mfh_status mfh_coarse_inertia(mfh_problem* problem, int* negative);
+
+/* ---- Graph capture ---- */
+
+/* enable != 0: the CG replays its V-cycle from a HIP graph captured on the
+ * problem's stream (captured at the first V-cycle after each
+ * set_deformation, since the Chebyshev coefficients are kernel arguments).
+ * Has no effect for problems created on the null stream, which cannot be
+ * captured.  Default off. */
+mfh_status mfh_enable_graphs(mfh_problem* problem, int enable);
+
+/* ---- Batches of independent problems (many meshes, degrees, materials) ---- */
+
+typedef struct mfh_batch mfh_batch;
+
+/* Device bytes for a batch over n existing problems (all with one qp_policy). */
+mfh_status mfh_batch_workspace_size(int n, mfh_problem* const* problems, size_t* bytes);
+
+/* Builds the device work lists of a batch: problems are binned by (dim,
+ * degree); each bin's tangent vmult is one persistent launch whose grid
+ * (grid_mult x resident blocks per CU x CUs, capped by the work) walks the
+ * (problem, cell block) items of all its problems.  The problems keep their
+ * own workspaces and must outlive the batch; the batch workspace (device,
+ * 256-byte aligned) holds the per-problem argument tables.  Work is enqueued
+ * on `hip_stream`.  Synchronises.  Errors: INVALID_ARG, WORKSPACE, HIP. */
+mfh_status mfh_batch_create(int n, mfh_problem* const* problems, void* workspace, size_t bytes,
+                            void* hip_stream, int grid_mult, mfh_batch** out);
+mfh_status mfh_batch_destroy(mfh_batch* batch);
+const char* mfh_batch_last_error(const mfh_batch* batch);
+
+/* set_deformation of every problem (host array u of device pointers), run
+ * from up to n_threads host threads, each problem on its own stream; min J per
+ * problem into the host array min_J (may be NULL).  Synchronises. */
+mfh_status mfh_batch_set_deformation(mfh_batch* batch, const double* const* u, double* min_J, int n_threads);
+
+/* y[i] = K_c,i x[i] for every problem i, on the finest levels (host arrays of
+ * device pointers, dtype as for mfh_tangent_vmult): one batched output fill
+ * and one persistent launch per (dim, degree) bin.  Async on the batch
+ * stream; every problem must have a linearisation point. */
+mfh_status mfh_batch_tangent_vmult(mfh_batch* batch, int dtype, const void* const* x, void* const* y);
+
+/* mfh_cg_solve of every problem (host arrays of device pointers), run from up
+ * to n_threads host threads so that the problems' streams execute
+ * concurrently; per-problem iterations, relative residuals and host wall
+ * time (ms) into the host arrays (may be NULL).  Synchronises.  Returns the
+ * first failing problem's status. */
+mfh_status mfh_batch_cg_solve(mfh_batch* batch, const double* const* b, double* const* x, double rtol,
+                              int max_it, int n_threads, int* iters, double* relres, double* solve_ms);
 
 /* ---- Kernel timers (measurement of the operator kernel) ---- */
 

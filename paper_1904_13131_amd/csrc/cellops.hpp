@@ -524,18 +524,18 @@ __device__ __forceinline__ int material_of(const CellArgs<T>& a, long long e, in
 }
 
 // ---------------------------------------------------------------------------
-// Tangent vmult: y += K x over the cells of this launch (y pre-filled).
+// Tangent vmult body for cell block `blk` of one level: y += K x over the
+// block's cells (y pre-filled).  Shared by the single-problem kernel and the
+// batched work-list kernel.
 template <int DIM, int P, typename T, int POL>
-__global__ void __launch_bounds__(kBlock) k_tangent(CellArgs<T> a) {
+__device__ __forceinline__ void tangent_block(const CellArgs<T>& a, long long blk, T* lds) {
   constexpr int N1 = P + 1;
   using G = Geo<DIM, N1>;
   using SF = SumFact<DIM, N1, T>;
   constexpr int NW = CacheWords<DIM, POL>::value;
-  __shared__ T lds[DIM * G::NARR * G::NV * G::CPB];
 
   const int t = threadIdx.x;
   const int cl = t % G::CPB, pen = t / G::CPB;
-  const long long blk = a.color < 0 ? xcd_block(blockIdx.x, gridDim.x) : (long long)blockIdx.x;
   const long long lin = blk * G::CPB + cl;
   const bool act = pen < G::NP && lin < a.nlaunch;
   CellPos<DIM, N1> cp;
@@ -633,6 +633,44 @@ __global__ void __launch_bounds__(kBlock) k_tangent(CellArgs<T> a) {
     scatter_merged<DIM, N1, T>(a.y, a, cp, act, out, to_next);
   } else {
     scatter<DIM, N1, T>(a.y, a, cp, act, out);
+  }
+}
+
+// Tangent vmult: y += K x over the cells of this launch (y pre-filled).
+template <int DIM, int P, typename T, int POL>
+__global__ void __launch_bounds__(kBlock) k_tangent(CellArgs<T> a) {
+  using G = Geo<DIM, P + 1>;
+  __shared__ T lds[DIM * G::NARR * G::NV * G::CPB];
+  const long long blk = a.color < 0 ? xcd_block(blockIdx.x, gridDim.x) : (long long)blockIdx.x;
+  tangent_block<DIM, P, T, POL>(a, blk, lds);
+}
+
+// Batched tangent vmult over many independent problems of one degree: a
+// persistent grid walks the work list of (problem, cell block) items; item i
+// belongs to the problem whose block offset off[p] <= i < off[p+1].  The
+// problem index is wave-uniform, so its arguments come in through scalar loads.
+template <int DIM, int P, typename T, int POL>
+__global__ void __launch_bounds__(kBlock) k_tangent_batch(const CellArgs<T>* __restrict__ args,
+                                                          const long long* __restrict__ off, int nprob,
+                                                          const T* const* __restrict__ xs, T* const* __restrict__ ys) {
+  using G = Geo<DIM, P + 1>;
+  __shared__ T lds[DIM * G::NARR * G::NV * G::CPB];
+  const long long total = off[nprob];
+  for (long long item = blockIdx.x; item < total; item += gridDim.x) {
+    int lo = 0, hi = nprob - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (off[mid] <= item)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    lo = __builtin_amdgcn_readfirstlane(lo);
+    CellArgs<T> a = args[lo];
+    a.x = xs[lo];
+    a.y = ys[lo];
+    tangent_block<DIM, P, T, POL>(a, item - off[lo], lds);
+    __syncthreads();
   }
 }
 

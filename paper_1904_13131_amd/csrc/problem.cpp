@@ -2,8 +2,10 @@
 // set_deformation, operator application, V-cycle, CG, Newton, and the C ABI.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <chrono>
 #include <cmath>
+#include <thread>
 #include <cstdio>
 #include <cstring>
 #include <memory>
@@ -139,8 +141,21 @@ struct mfh_problem {
   bool timing = false;
   std::vector<hipEvent_t> ev;        // pairs (start, stop)
   size_t ev_used = 0;
+  // V-cycle graph (captured on the problem's stream, replayed by the CG)
+  bool use_graphs = false;
+  bool graph_ready = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  void drop_graph() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    gexec = nullptr;
+    graph = nullptr;
+    graph_ready = false;
+  }
   ~mfh_problem() {
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    drop_graph();
   }
 };
 
@@ -653,6 +668,7 @@ void interpolate_down(mfh_problem* P, int l) {
 // Builds every level operator about u (Sec. 6).  Returns min J over all levels.
 double set_deformation(mfh_problem* P, const double* u) {
   const mfh_desc& d = P->d;
+  P->drop_graph();
   const int nl = (int)P->lv.size();
   hipStream_t s = P->stream;
   Level& top = P->lv.back();
@@ -740,6 +756,23 @@ void setup_precond(mfh_problem* P) {
   P->precond_ready = true;
 }
 
+// z = V-cycle(r) on the CG's own vectors (r = cg_r, z = cg_z); replays the
+// captured graph when graphs are enabled and the stream can be captured.
+void precond(mfh_problem* P) {
+  if (P->use_graphs && P->stream != nullptr) {
+    if (!P->graph_ready) {
+      HIPCHECK(hipStreamBeginCapture(P->stream, hipStreamCaptureModeThreadLocal));
+      vcycle(P, P->cg_r, P->cg_z);
+      HIPCHECK(hipStreamEndCapture(P->stream, &P->graph));
+      HIPCHECK(hipGraphInstantiate(&P->gexec, P->graph, nullptr, nullptr, 0));
+      P->graph_ready = true;
+    }
+    HIPCHECK(hipGraphLaunch(P->gexec, P->stream));
+  } else {
+    vcycle(P, P->cg_r, P->cg_z);
+  }
+}
+
 struct CgResult {
   int iters = 0;
   double relres = 0;
@@ -765,7 +798,7 @@ CgResult cg_solve(mfh_problem* P, const double* b, double* x, double rtol, int m
     return res;
   }
   if (bb == 0.0) return res;
-  vcycle(P, r, z);
+  precond(P);
   HIPCHECK(hipMemcpyAsync(p, z, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
   dot<double, double>(r, z, n, P->part, P->sc + SC_RZ, s);
   res.st = MFH_ERR_NOT_CONVERGED;
@@ -789,7 +822,7 @@ CgResult cg_solve(mfh_problem* P, const double* b, double* x, double rtol, int m
       break;
     }
     if (it == max_it) break;
-    vcycle(P, r, z);
+    precond(P);
     dot<double, double>(r, z, n, P->part, P->sc + SC_RZNEW, s);
     scalar_div(P->sc, SC_BETA, SC_RZNEW, SC_RZ, SC_RZ, SC_RZNEW, nullptr, 0, s);
     cg_pupdate<double>(p, z, n, P->sc, s);
@@ -973,7 +1006,14 @@ mfh_status mfh_gmg_vcycle(mfh_problem* P, const double* r, double* z) {
     need(P->deformed, "set_deformation has not succeeded yet");
     need(P->has_coarse, "coarsest level too large for the direct solve: use more levels");
     setup_precond(P);
-    vcycle(P, r, z);
+    if (P->use_graphs && P->stream != nullptr) {
+      const long long n = P->lv.back().ndofs;
+      HIPCHECK(hipMemcpyAsync(P->cg_r, r, sizeof(double) * n, hipMemcpyDeviceToDevice, P->stream));
+      precond(P);
+      HIPCHECK(hipMemcpyAsync(z, P->cg_z, sizeof(double) * n, hipMemcpyDeviceToDevice, P->stream));
+    } else {
+      vcycle(P, r, z);
+    }
     check_launch("gmg_vcycle");
   });
 }
@@ -1034,7 +1074,8 @@ mfh_status mfh_newton_solve(mfh_problem* P, double* u, const double* fv, int n_s
       HIPCHECK(hipMemcpyAsync(P->nw_save, u, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
       dirichlet_delta(u, P->nw_dg, v.lt, fv, target, n, s);
       double R0 = -1;
-      bool conv = false, bad = false;
+      bool conv = false;
+      mfh_status fail = MFH_ERR_NOT_CONVERGED;   // why the increment failed
       bool have_R = false;
       for (int it = 0; it < max_newton; ++it) {
         mfh_newton_record r{};
@@ -1049,7 +1090,7 @@ mfh_status mfh_newton_solve(mfh_problem* P, double* u, const double* fv, int n_s
         t0 = Clock::now();
         mfh_status sd = guarded(P, [&] { r.min_J = set_deformation(P, u); });
         if (sd == MFH_ERR_INVERTED) {
-          bad = true;
+          fail = MFH_ERR_INVERTED;
           break;
         }
         if (sd != MFH_OK) throw Error(sd, P->err);
@@ -1068,7 +1109,15 @@ mfh_status mfh_newton_solve(mfh_problem* P, double* u, const double* fv, int n_s
         CgResult cr = cg_solve(P, P->nw_b, P->nw_du, cg_rtol, cg_max_it);
         r.cg_iters = cr.iters;
         r.cg_relres = cr.relres;
-        if (cr.st == MFH_ERR_BREAKDOWN) throw Error(cr.st, "CG breakdown inside Newton");
+        if (cr.st == MFH_ERR_BREAKDOWN) {   // p^T K p <= 0: the tangent is indefinite at this iterate
+          r.cg_relres = NAN;
+          r.residual_after = NAN;
+          r.solve_ms = ms_since(t0);
+          if (rec && nrec < max_rec) rec[nrec] = r;
+          ++nrec;
+          fail = MFH_ERR_BREAKDOWN;
+          break;
+        }
         if (it == 0) axpby<double>(P->nw_du, P->nw_dg, 1.0, 1.0, n, s);
         axpby<double>(u, P->nw_du, 1.0, 1.0, n, s);
         r.solve_ms = ms_since(t0);
@@ -1080,9 +1129,9 @@ mfh_status mfh_newton_solve(mfh_problem* P, double* u, const double* fv, int n_s
         r.residual_ms += ms_since(t0);
         if (rec && nrec < max_rec) rec[nrec] = r;
         ++nrec;
-        if (cr.st == MFH_ERR_NOT_CONVERGED) throw Error(cr.st, "CG did not converge inside Newton");
+        if (cr.st == MFH_ERR_NOT_CONVERGED) break;   // the linear solve failed: cut the increment back
         if (!std::isfinite(r.residual_after)) {   // the update inverted a quadrature point
-          bad = true;
+          fail = MFH_ERR_INVERTED;
           break;
         }
         if (r.du_norm <= du_tol && (r.residual_after <= r_tol || r.residual_after <= r_tol * R0)) {
@@ -1099,10 +1148,10 @@ mfh_status mfh_newton_solve(mfh_problem* P, double* u, const double* fv, int n_s
       HIPCHECK(hipMemcpyAsync(u, P->nw_save, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
       HIPCHECK(hipStreamSynchronize(s));
       if (++cutbacks > kMaxCut)
-        throw Error(bad ? MFH_ERR_INVERTED : MFH_ERR_NOT_CONVERGED,
+        throw Error(fail,
                     std::string("Newton failed after ") + std::to_string(kMaxCut) + " load-step cut-backs at load fraction " +
                         std::to_string(done));
-      h *= 0.5;
+      h = 0.5 * (target - done);
     }
   });
   if (n_rec) *n_rec = nrec;
@@ -1223,6 +1272,294 @@ mfh_status mfh_timer_read(mfh_problem* P, double* total_ms, long long* launches)
     }
     *total_ms = t;
     *launches = (long long)(P->ev_used / 2);
+  });
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------------
+// Batches of independent problems.
+
+struct mfh_batch {
+  std::vector<mfh_problem*> probs;
+  hipStream_t stream = nullptr;
+  int policy = 0;
+  int grid_mult = 1;
+  int n_cu = 256;
+  struct Bin {
+    int dim = 0, degree = 0;
+    std::vector<int> ids;
+    mfh::CellArgs<double>* a64 = nullptr;
+    mfh::CellArgs<float>* a32 = nullptr;
+    long long* off = nullptr;
+    void** xs = nullptr;
+    void** ys = nullptr;
+    long long total = 0;
+    const mfh::OpFns* ops = nullptr;
+  };
+  std::vector<Bin> bins;
+  mfh::FillItem<double>* f64 = nullptr;
+  mfh::FillItem<float>* f32 = nullptr;
+  long long* foff = nullptr;
+  long long fchunks = 0;
+  std::string err;
+};
+
+namespace mfh {
+namespace {
+
+size_t batch_layout(mfh_batch* B, char* base) {
+  Bump b;
+  b.base = base;
+  for (auto& bin : B->bins) {
+    const size_t nb = bin.ids.size();
+    bin.a64 = b.take<CellArgs<double>>(nb);
+    bin.a32 = b.take<CellArgs<float>>(nb);
+    bin.off = b.take<long long>(nb + 1);
+    bin.xs = b.take<void*>(nb);
+    bin.ys = b.take<void*>(nb);
+  }
+  const size_t n = B->probs.size();
+  B->f64 = b.take<FillItem<double>>(n);
+  B->f32 = b.take<FillItem<float>>(n);
+  B->foff = b.take<long long>(n + 1);
+  return b.off + 256;
+}
+
+void batch_bins(mfh_batch* B) {
+  B->bins.clear();
+  for (int i = 0; i < (int)B->probs.size(); ++i) {
+    const mfh_problem* P = B->probs[i];
+    mfh_batch::Bin* bin = nullptr;
+    for (auto& x : B->bins)
+      if (x.dim == P->d.dim && x.degree == P->d.degree) bin = &x;
+    if (!bin) {
+      B->bins.emplace_back();
+      bin = &B->bins.back();
+      bin->dim = P->d.dim;
+      bin->degree = P->d.degree;
+      bin->ops = P->ops;
+    }
+    bin->ids.push_back(i);
+  }
+}
+
+template <typename T>
+void batch_vmult(mfh_batch* B, const void* const* x, void* const* y) {
+  hipStream_t s = B->stream;
+  const size_t n = B->probs.size();
+  // fill items (outputs: 0, or x on constrained DoFs)
+  std::vector<FillItem<T>> items(n);
+  for (size_t i = 0; i < n; ++i) {
+    const Level& v = B->probs[i]->lv.back();
+    items[i] = FillItem<T>{static_cast<T*>(y[i]), static_cast<const T*>(x[i]), v.lt, v.ndofs};
+  }
+  FillItem<T>* fdev = std::is_same<T, double>::value ? reinterpret_cast<FillItem<T>*>(B->f64)
+                                                     : reinterpret_cast<FillItem<T>*>(B->f32);
+  HIPCHECK(hipMemcpyAsync(fdev, items.data(), sizeof(FillItem<T>) * n, hipMemcpyHostToDevice, s));
+  fill_dirichlet_batch<T>(fdev, B->foff, (int)n, B->fchunks, s);
+  const int ti = std::is_same<T, double>::value ? 0 : 1;
+  for (auto& bin : B->bins) {
+    const size_t nb = bin.ids.size();
+    std::vector<void*> xs(nb), ys(nb);
+    for (size_t k = 0; k < nb; ++k) {
+      xs[k] = const_cast<void*>(x[bin.ids[k]]);
+      ys[k] = y[bin.ids[k]];
+    }
+    HIPCHECK(hipMemcpyAsync(bin.xs, xs.data(), sizeof(void*) * nb, hipMemcpyHostToDevice, s));
+    HIPCHECK(hipMemcpyAsync(bin.ys, ys.data(), sizeof(void*) * nb, hipMemcpyHostToDevice, s));
+    const long long resident = (long long)bin.ops->batch_blocks_per_cu[ti]() * B->n_cu * B->grid_mult;
+    const unsigned grid = (unsigned)std::max<long long>(1, std::min(bin.total, resident));
+    if (std::is_same<T, double>::value)
+      bin.ops->tangent_batch_d[B->policy](bin.a64, bin.off, (int)nb, reinterpret_cast<const double* const*>(bin.xs),
+                                          reinterpret_cast<double* const*>(bin.ys), grid, s);
+    else
+      bin.ops->tangent_batch_f[B->policy](bin.a32, bin.off, (int)nb, reinterpret_cast<const float* const*>(bin.xs),
+                                          reinterpret_cast<float* const*>(bin.ys), grid, s);
+  }
+  check_launch("batch tangent_vmult");
+}
+
+template <typename F>
+mfh_status batch_guarded(mfh_batch* B, F&& f) {
+  try {
+    f();
+    if (B) B->err.clear();
+    return MFH_OK;
+  } catch (const Error& e) {
+    if (B) B->err = e.what(); else g_err = e.what();
+    return e.st;
+  } catch (const std::exception& e) {
+    if (B) B->err = e.what(); else g_err = e.what();
+    return MFH_ERR_INVALID_ARG;
+  }
+}
+
+void batch_validate(int n, mfh_problem* const* probs) {
+  need(n >= 1 && probs != nullptr, "need n >= 1 problems");
+  for (int i = 0; i < n; ++i) {
+    need(probs[i] != nullptr, "NULL problem in batch");
+    need(probs[i]->d.qp_policy == probs[0]->d.qp_policy, "all problems of a batch must use one qp_policy");
+  }
+}
+
+// Runs fn(i) for every problem on up to n_threads host threads; returns the
+// first non-OK status in problem order.
+template <typename F>
+mfh_status batch_parallel(int n, int n_threads, F&& fn, std::vector<mfh_status>& st) {
+  st.assign(n, MFH_OK);
+  std::atomic<int> next(0);
+  auto worker = [&] {
+    for (int i = next++; i < n; i = next++) st[i] = fn(i);
+  };
+  const int nt = std::max(1, std::min(n_threads, n));
+  std::vector<std::thread> th;
+  for (int k = 1; k < nt; ++k) th.emplace_back(worker);
+  worker();
+  for (auto& t : th) t.join();
+  for (int i = 0; i < n; ++i)
+    if (st[i] != MFH_OK) return st[i];
+  return MFH_OK;
+}
+
+}  // namespace
+}  // namespace mfh
+
+extern "C" {
+
+mfh_status mfh_enable_graphs(mfh_problem* P, int enable) {
+  if (!P) return MFH_ERR_INVALID_ARG;
+  return guarded(P, [&] {
+    P->drop_graph();
+    P->use_graphs = enable != 0;
+  });
+}
+
+mfh_status mfh_batch_workspace_size(int n, mfh_problem* const* probs, size_t* bytes) {
+  return batch_guarded(nullptr, [&] {
+    batch_validate(n, probs);
+    need(bytes != nullptr, "bytes is NULL");
+    mfh_batch tmp;
+    tmp.probs.assign(probs, probs + n);
+    batch_bins(&tmp);
+    *bytes = batch_layout(&tmp, nullptr);
+  });
+}
+
+mfh_status mfh_batch_create(int n, mfh_problem* const* probs, void* ws, size_t bytes, void* stream, int grid_mult,
+                            mfh_batch** out) {
+  std::unique_ptr<mfh_batch> B(new mfh_batch());
+  mfh_status st = batch_guarded(nullptr, [&] {
+    batch_validate(n, probs);
+    need(out != nullptr && ws != nullptr, "NULL argument");
+    need((reinterpret_cast<uintptr_t>(ws) & 255) == 0, "workspace must be 256-byte aligned");
+    need(grid_mult >= 1 && grid_mult <= 64, "grid_mult must be 1..64");
+    B->probs.assign(probs, probs + n);
+    B->stream = static_cast<hipStream_t>(stream);
+    B->policy = probs[0]->d.qp_policy;
+    B->grid_mult = grid_mult;
+    batch_bins(B.get());
+    const size_t need_bytes = batch_layout(B.get(), nullptr);
+    if (bytes < need_bytes) throw Error(MFH_ERR_WORKSPACE, "batch workspace too small: need " + std::to_string(need_bytes));
+    batch_layout(B.get(), static_cast<char*>(ws));
+    int dev = 0;
+    HIPCHECK(hipGetDevice(&dev));
+    HIPCHECK(hipDeviceGetAttribute(&B->n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    hipStream_t s = B->stream;
+    for (auto& bin : B->bins) {
+      const size_t nb = bin.ids.size();
+      std::vector<CellArgs<double>> a64(nb);
+      std::vector<CellArgs<float>> a32(nb);
+      std::vector<long long> off(nb + 1, 0);
+      for (size_t k = 0; k < nb; ++k) {
+        const mfh_problem* P = B->probs[bin.ids[k]];
+        const Level& v = P->lv.back();
+        a64[k] = cell_args<double>(P, v, v.u64, v.cache64, nullptr, nullptr);
+        a32[k] = cell_args<float>(P, v, v.u32, v.cache32, nullptr, nullptr);
+        off[k + 1] = off[k] + (v.ncells + P->ops->cpb - 1) / P->ops->cpb;
+      }
+      bin.total = off[nb];
+      HIPCHECK(hipMemcpyAsync(bin.a64, a64.data(), sizeof(CellArgs<double>) * nb, hipMemcpyHostToDevice, s));
+      HIPCHECK(hipMemcpyAsync(bin.a32, a32.data(), sizeof(CellArgs<float>) * nb, hipMemcpyHostToDevice, s));
+      HIPCHECK(hipMemcpyAsync(bin.off, off.data(), sizeof(long long) * (nb + 1), hipMemcpyHostToDevice, s));
+    }
+    std::vector<long long> foff(n + 1, 0);
+    for (int i = 0; i < n; ++i) {
+      const long long nd = B->probs[i]->lv.back().ndofs;
+      foff[i + 1] = foff[i] + (nd + kFillChunk - 1) / kFillChunk;
+    }
+    B->fchunks = foff[n];
+    HIPCHECK(hipMemcpyAsync(B->foff, foff.data(), sizeof(long long) * (n + 1), hipMemcpyHostToDevice, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    *out = B.release();
+  });
+  return st;
+}
+
+mfh_status mfh_batch_destroy(mfh_batch* B) {
+  delete B;
+  return MFH_OK;
+}
+
+const char* mfh_batch_last_error(const mfh_batch* B) { return B ? B->err.c_str() : g_err.c_str(); }
+
+mfh_status mfh_batch_set_deformation(mfh_batch* B, const double* const* u, double* min_J, int n_threads) {
+  if (!B) return MFH_ERR_INVALID_ARG;
+  return batch_guarded(B, [&] {
+    need(u != nullptr, "u is NULL");
+    const int n = (int)B->probs.size();
+    std::vector<mfh_status> st;
+    const mfh_status r = batch_parallel(n, n_threads, [&](int i) {
+      double mj = 0;
+      const mfh_status s = mfh_set_deformation(B->probs[i], u[i], &mj);
+      if (min_J) min_J[i] = mj;
+      return s;
+    }, st);
+    if (r != MFH_OK) {
+      for (int i = 0; i < n; ++i)
+        if (st[i] != MFH_OK) throw Error(st[i], "problem " + std::to_string(i) + ": " + B->probs[i]->err);
+    }
+  });
+}
+
+mfh_status mfh_batch_tangent_vmult(mfh_batch* B, int dtype, const void* const* x, void* const* y) {
+  if (!B) return MFH_ERR_INVALID_ARG;
+  return batch_guarded(B, [&] {
+    need(x && y, "x/y is NULL");
+    for (size_t i = 0; i < B->probs.size(); ++i) {
+      need(x[i] && y[i] && x[i] != y[i], "bad x/y pointer");
+      need(B->probs[i]->deformed, "set_deformation has not succeeded on every problem");
+    }
+    if (dtype == MFH_F64)
+      batch_vmult<double>(B, x, y);
+    else if (dtype == MFH_F32)
+      batch_vmult<float>(B, x, y);
+    else
+      need(false, "dtype must be MFH_F64 or MFH_F32");
+  });
+}
+
+mfh_status mfh_batch_cg_solve(mfh_batch* B, const double* const* b, double* const* x, double rtol, int max_it,
+                              int n_threads, int* iters, double* relres, double* solve_ms) {
+  if (!B) return MFH_ERR_INVALID_ARG;
+  return batch_guarded(B, [&] {
+    need(b && x, "b/x is NULL");
+    const int n = (int)B->probs.size();
+    std::vector<mfh_status> st;
+    const mfh_status r = batch_parallel(n, n_threads, [&](int i) {
+      auto t0 = Clock::now();
+      int it = 0;
+      double rel = 0;
+      const mfh_status s = mfh_cg_solve(B->probs[i], b[i], x[i], rtol, max_it, &it, &rel);
+      if (iters) iters[i] = it;
+      if (relres) relres[i] = rel;
+      if (solve_ms) solve_ms[i] = ms_since(t0);
+      return s;
+    }, st);
+    if (r != MFH_OK) {
+      for (int i = 0; i < n; ++i)
+        if (st[i] != MFH_OK) throw Error(st[i], "problem " + std::to_string(i) + ": " + B->probs[i]->err);
+    }
   });
 }
 

@@ -34,6 +34,27 @@ __global__ void k_fill_dirichlet(T* __restrict__ y, const T* __restrict__ x, lon
 }
 
 template <typename T>
+__global__ void k_fill_dirichlet_batch(const FillItem<T>* __restrict__ items, const long long* __restrict__ off, int n) {
+  const long long total = off[n];
+  for (long long c = blockIdx.x; c < total; c += gridDim.x) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (off[mid] <= c)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    lo = __builtin_amdgcn_readfirstlane(lo);
+    const FillItem<T> it = items[lo];
+    const long long b0 = (c - off[lo]) * kFillChunk;
+    const long long b1 = b0 + kFillChunk < it.n ? b0 + kFillChunk : it.n;
+    for (long long i = b0 + threadIdx.x; i < b1; i += kVB)
+      it.y[i] = constrained_dof(it.lt, i) ? it.x[i] : T(0);
+  }
+}
+
+template <typename T>
 __global__ void k_zero_constrained(T* __restrict__ v, long long n, Lattice lt) {
   for (long long i = blockIdx.x * (long long)kVB + threadIdx.x; i < n; i += (long long)gridDim.x * kVB)
     if (constrained_dof(lt, i)) v[i] = T(0);
@@ -470,6 +491,10 @@ void fill_dirichlet(T* y, const T* x, long long n, const Lattice& lt, hipStream_
   hipLaunchKernelGGL(k_fill_dirichlet<T>, dim3(grid_for(n)), dim3(kVB), 0, s, y, x, n, lt);
 }
 template <typename T>
+void fill_dirichlet_batch(const FillItem<T>* items, const long long* off, int n, long long chunks, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_dirichlet_batch<T>, dim3(grid_for(chunks * kVB, 8192)), dim3(kVB), 0, s, items, off, n);
+}
+template <typename T>
 void zero_constrained(T* v, long long n, const Lattice& lt, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_constrained<T>, dim3(grid_for(n)), dim3(kVB), 0, s, v, n, lt);
 }
@@ -593,6 +618,7 @@ void coarse_apply(const double* Kinv, long long nf, const int* dof_of, const T* 
 
 #define MFH_INST_T(T)                                                                                          \
   template void fill_dirichlet<T>(T*, const T*, long long, const Lattice&, hipStream_t);                       \
+  template void fill_dirichlet_batch<T>(const FillItem<T>*, const long long*, int, long long, hipStream_t);     \
   template void zero_constrained<T>(T*, long long, const Lattice&, hipStream_t);                               \
   template void fill<T>(T*, T, long long, hipStream_t);                                                        \
   template void cg_update<T>(T*, T*, const T*, const T*, long long, const double*, double*, hipStream_t);      \

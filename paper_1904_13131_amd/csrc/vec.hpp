@@ -42,6 +42,19 @@ struct SweepArgs {
 };
 
 template <typename T> void fill_dirichlet(T* y, const T* x, long long n, const Lattice& lt, hipStream_t s);
+
+// Batched fill: item k covers entries [chunk*c, chunk*(c+1)) of problem k's
+// vectors; off[k] is the first chunk of problem k (off[n] = total chunks).
+template <typename T>
+struct FillItem {
+  T* y;
+  const T* x;
+  Lattice lt;
+  long long n;
+};
+constexpr long long kFillChunk = 4096;
+template <typename T> void fill_dirichlet_batch(const FillItem<T>* items, const long long* off, int n, long long chunks,
+                                                hipStream_t s);
 template <typename T> void zero_constrained(T* v, long long n, const Lattice& lt, hipStream_t s);
 template <typename T> void fill(T* v, T val, long long n, hipStream_t s);
 template <typename TI, typename TO> void cast(const TI* in, TO* out, long long n, hipStream_t s);

@@ -89,6 +89,16 @@ def lib():
         "mfh_restrict": (st, [_P, ctypes.c_int, ctypes.c_int, _P, _P]),
         "mfh_chebyshev": (st, [_P, ctypes.c_int, _P, _P]),
         "mfh_coarse_inertia": (st, [_P, ctypes.POINTER(ctypes.c_int)]),
+        "mfh_enable_graphs": (st, [_P, ctypes.c_int]),
+        "mfh_batch_workspace_size": (st, [ctypes.c_int, ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_size_t)]),
+        "mfh_batch_create": (st, [ctypes.c_int, ctypes.POINTER(_P), _P, ctypes.c_size_t, _P, ctypes.c_int,
+                                  ctypes.POINTER(_P)]),
+        "mfh_batch_destroy": (st, [_P]),
+        "mfh_batch_last_error": (ctypes.c_char_p, [_P]),
+        "mfh_batch_set_deformation": (st, [_P, ctypes.POINTER(_P), _D, ctypes.c_int]),
+        "mfh_batch_tangent_vmult": (st, [_P, ctypes.c_int, ctypes.POINTER(_P), ctypes.POINTER(_P)]),
+        "mfh_batch_cg_solve": (st, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.c_double, ctypes.c_int,
+                                    ctypes.c_int, ctypes.POINTER(ctypes.c_int), _D, _D]),
         "mfh_timer_enable": (st, [_P, ctypes.c_int]),
         "mfh_timer_read": (st, [_P, _D, ctypes.POINTER(ctypes.c_longlong)]),
     }
@@ -148,7 +158,7 @@ def _ptr(t):
 class Problem:
     """One mfh_problem with its workspace (a torch uint8 device tensor)."""
 
-    def __init__(self, dim, n_cells, degree, device="cuda", **kw):
+    def __init__(self, dim, n_cells, degree, device="cuda", stream=None, **kw):
         self.desc, self._keep = make_desc(dim, n_cells, degree, **kw)
         self.device = torch.device(device)
         self.dim = dim
@@ -156,7 +166,7 @@ class Problem:
         self.workspace = torch.empty(size + 256, dtype=torch.uint8, device=self.device)
         off = (-self.workspace.data_ptr()) % 256
         base = self.workspace.data_ptr() + off
-        self.stream = torch.cuda.current_stream(self.device)
+        self.stream = torch.cuda.current_stream(self.device) if stream is None else stream
         h = ctypes.c_void_p()
         _check(lib().mfh_create(ctypes.byref(self.desc), ctypes.c_void_p(base), size,
                                 ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
@@ -263,6 +273,9 @@ class Problem:
         _check(lib().mfh_restrict(self.handle, level, dt, _ptr(x), _ptr(y)), self.handle)
         return y
 
+    def enable_graphs(self, enable=True):
+        _check(lib().mfh_enable_graphs(self.handle, 1 if enable else 0), self.handle)
+
     def coarse_inertia(self):
         n = ctypes.c_int()
         _check(lib().mfh_coarse_inertia(self.handle, ctypes.byref(n)), self.handle)
@@ -280,3 +293,63 @@ class Problem:
     def chebyshev(self, level, f, x):
         _check(lib().mfh_chebyshev(self.handle, level, _ptr(f), _ptr(x)), self.handle)
         return x
+
+
+def _check_batch(st, handle):
+    if st != MFH_OK:
+        msg = lib().mfh_batch_last_error(handle)
+        raise MfhError(st, msg.decode() if msg else "")
+
+
+def _parr(tensors):
+    return (ctypes.c_void_p * len(tensors))(*[t.data_ptr() for t in tensors])
+
+
+class Batch:
+    """An mfh_batch over existing Problems (kept alive by the batch)."""
+
+    def __init__(self, problems, stream=None, grid_mult=1):
+        self.problems = list(problems)
+        n = len(self.problems)
+        handles = (ctypes.c_void_p * n)(*[p.handle.value for p in self.problems])
+        self._handles = handles
+        size = ctypes.c_size_t()
+        _check_batch(lib().mfh_batch_workspace_size(n, handles, ctypes.byref(size)), None)
+        dev = self.problems[0].device
+        self.workspace = torch.empty(size.value + 256, dtype=torch.uint8, device=dev)
+        base = self.workspace.data_ptr() + (-self.workspace.data_ptr()) % 256
+        self.stream = torch.cuda.current_stream(dev) if stream is None else stream
+        h = ctypes.c_void_p()
+        _check_batch(lib().mfh_batch_create(n, handles, ctypes.c_void_p(base), size.value,
+                                            ctypes.c_void_p(self.stream.cuda_stream), grid_mult, ctypes.byref(h)), None)
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().mfh_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_deformation(self, us, n_threads=8):
+        mj = (ctypes.c_double * len(us))()
+        _check_batch(lib().mfh_batch_set_deformation(self.handle, _parr(us), mj, n_threads), self.handle)
+        return list(mj)
+
+    def tangent_vmult(self, xs, ys):
+        dt = F64 if xs[0].dtype == torch.float64 else F32
+        _check_batch(lib().mfh_batch_tangent_vmult(self.handle, dt, _parr(xs), _parr(ys)), self.handle)
+        return ys
+
+    def cg_solve(self, bs, xs, rtol=1e-8, max_it=200, n_threads=8):
+        n = len(bs)
+        it = (ctypes.c_int * n)()
+        rel = (ctypes.c_double * n)()
+        ms = (ctypes.c_double * n)()
+        _check_batch(lib().mfh_batch_cg_solve(self.handle, _parr(bs), _parr(xs), rtol, max_it, n_threads, it, rel, ms),
+                     self.handle)
+        return list(it), list(rel), list(ms)

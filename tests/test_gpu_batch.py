@@ -1,0 +1,127 @@
+"""GPU tests of the batched path (many independent problems of different
+meshes, degrees and materials) and of the graph-captured V-cycle."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import fe
+from paper_1904_13131_amd import F32, F64, Batch, Problem
+from tests.gpu_helpers import dev, host, log_case, rel_l2, requires_gpu
+
+pytestmark = [pytest.mark.gpu, requires_gpu]
+
+SMALL_LEVELS = {2: 2, 4: 2, 6: 2}
+
+
+def sdev(a, dtype=torch.float64):
+    """Device copy, synchronised (the problems run on their own streams)."""
+    t = dev(a, dtype)
+    torch.cuda.synchronize()
+    return t
+
+
+def _problems(n, seed, **kw):
+    descs = W.config4(n=n, seed=seed, sizes=(2, 4, 6), degrees=(1, 2, 3))
+    mu, lam = W.two_phase_material()
+    probs, fields = [], []
+    for d in descs:
+        incl, u, x = W.batch_fields(d)
+        s = torch.cuda.Stream()
+        P = Problem(3, d["n_cells"], d["degree"], n_levels=SMALL_LEVELS[d["n_cells"]], mu=tuple(mu), lam=tuple(lam),
+                    inclusions=incl, dirichlet_mask=d["mask"], stream=s, **kw)
+        probs.append(P)
+        fields.append((d, incl, u, x))
+    torch.cuda.synchronize()
+    return probs, fields
+
+
+@pytest.mark.parametrize("policy", [0, 2], ids=["R", "C2"])
+def test_batch_vmult_matches_single_and_oracle(policy):
+    log_case("batch_vmult", policy=policy)
+    probs, fields = _problems(14, 61, qp_policy=policy)
+    us = [dev(f[2]) for f in fields]
+    B = Batch(probs)
+    mj = B.set_deformation(us)
+    torch.cuda.synchronize()
+    assert all(m > 0 for m in mj)
+    for dt, tdt, tol in ((F64, torch.float64, 1e-13), (F32, torch.float32, 2e-6)):
+        xs = [dev(f[3], tdt) for f in fields]
+        ys = [torch.empty_like(x) for x in xs]
+        for gm in (1, 4):
+            Bg = Batch(probs, grid_mult=gm)
+            Bg.tangent_vmult(xs, ys)
+            torch.cuda.synchronize()
+            for P, x, y in zip(probs, xs, ys):
+                ref = P.tangent_vmult(x)
+                torch.cuda.synchronize()
+                assert rel_l2(host(y), host(ref)) <= tol
+    # two problems against the oracle
+    for k in (0, 5):
+        d, incl, u, x = fields[k]
+        m = fe.Mesh(3, d["n_cells"], d["degree"])
+        mu, lam = W.two_phase_material()
+        K = fe.constrain_matrix(fe.tangent_matrix(m, fe.Material(mu, lam, incl), u), m.constrained(d["mask"]))
+        xs = [dev(f[3]) for f in fields]
+        ys = [torch.empty_like(v) for v in xs]
+        B.tangent_vmult(xs, ys)
+        torch.cuda.synchronize()
+        assert rel_l2(host(ys[k]), K @ x) <= 1e-12
+
+
+def test_batch_cg_solve():
+    log_case("batch_cg")
+    probs, fields = _problems(8, 62)
+    us = [dev(f[2]) for f in fields]
+    B = Batch(probs)
+    B.set_deformation(us)
+    bs = []
+    for (d, incl, u, x), P in zip(fields, probs):
+        m = fe.Mesh(3, d["n_cells"], d["degree"])
+        b = x.copy()
+        b[m.constrained(d["mask"])] = 0.0
+        bs.append(dev(b))
+    xs = [torch.empty_like(b) for b in bs]
+    torch.cuda.synchronize()
+    it, rel, ms = B.cg_solve(bs, xs, rtol=1e-8, max_it=300, n_threads=4)
+    assert all(r <= 1e-8 for r in rel)
+    d, incl, u, x = fields[0]
+    m = fe.Mesh(3, d["n_cells"], d["degree"])
+    mu, lam = W.two_phase_material()
+    K = fe.constrain_matrix(fe.tangent_matrix(m, fe.Material(mu, lam, incl), u), m.constrained(d["mask"]))
+    b0 = host(bs[0])
+    assert np.linalg.norm(b0 - K @ host(xs[0])) <= 1.05e-8 * np.linalg.norm(b0)
+
+
+@pytest.mark.parametrize("vdt", [F64, F32], ids=["f64", "f32"])
+def test_graph_vcycle_replays_match_eager(vdt):
+    """The captured V-cycle is replayed several times with eager work and
+    synchronisations in between; every replay equals the eager V-cycle."""
+    log_case("graph_replay", vcycle=vdt)
+    mu, lam = W.two_phase_material()
+    incl = W.spheres(3, 3)
+    s = torch.cuda.Stream()
+    P = Problem(3, 8, 2, n_levels=3, mu=tuple(mu), lam=tuple(lam), inclusions=incl,
+                dirichlet_mask=W.clamp_bottom_top(3), vcycle_dtype=vdt, stream=s)
+    m = fe.Mesh(3, 8, 2)
+    cons = m.constrained(W.clamp_bottom_top(3))
+    u = W.stretched_field(3, m.L, 0.05, 4, 0.0125)
+    b = W.normal_vector(m.n_dofs, 8)
+    b[cons] = 0.0
+    torch.cuda.synchronize()
+    P.set_deformation(sdev(u))
+    z_eager = host(P.gmg_vcycle(sdev(b)))
+    P.enable_graphs(True)
+    tol = 1e-12 if vdt == F64 else 2e-5
+    other = sdev(W.normal_vector(m.n_dofs, 9))
+    for rep in range(4):
+        z = host(P.gmg_vcycle(sdev(b)))
+        assert rel_l2(z, z_eager) <= tol, rep
+        P.tangent_vmult(other)            # eager work between replays
+        torch.cuda.synchronize()
+    x_g, it_g, rel_g, _ = P.cg_solve(sdev(b), rtol=1e-8, max_it=200)
+    P.enable_graphs(False)
+    x_e, it_e, rel_e, _ = P.cg_solve(sdev(b), rtol=1e-8, max_it=200)
+    assert rel_g <= 1e-8 and rel_e <= 1e-8
+    assert abs(it_g - it_e) <= 1
+    assert rel_l2(host(x_g), host(x_e)) <= 1e-7

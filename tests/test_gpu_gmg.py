@@ -159,8 +159,8 @@ def test_newton_uniaxial_closed_form(vdt):
 @pytest.mark.parametrize("vdt", [F64, F32], ids=["f64", "f32"])
 def test_newton_cutback_matches_oracle(vdt):
     """2-D plane strain with a stiff disc compressed by 30 % in one increment:
-    the linearised increment inverts elements, so both drivers halve it; the
-    converged solutions agree."""
+    the second Newton iterate meets negative curvature (CG breakdown), so both
+    drivers halve the failed increment, twice; the converged solutions agree."""
     from paper_1904_13131_amd import Problem
     from oracle import newton
     log_case("newton_cutback", vcycle=vdt)
@@ -175,7 +175,7 @@ def test_newton_cutback_matches_oracle(vdt):
                 vcycle_dtype=vdt)
     u = torch.zeros(P.n_dofs(), dtype=torch.float64, device="cuda")
     recs, st = P.newton_solve(u, fv, n_steps=1)
-    assert max(r["cutbacks"] for r in recs) == max(r["cutbacks"] for r in recs_o) > 0
+    assert max(r["cutbacks"] for r in recs) == max(r["cutbacks"] for r in recs_o) == 2
     assert recs[-1]["load_fraction"] == 1.0
     assert rel_l2(host(u), u_o) <= 1e-7
 

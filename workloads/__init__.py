@@ -112,3 +112,46 @@ def config2(n_cells=32):
     smooth u of amplitude 0.1 (seed 4), x ~ N(0,1) (seed 5)."""
     return problem(3, n_cells, 2, n_spheres=20, sphere_seed=3, u_seed=4, u_amp=0.1,
                    u_kmax=1, x_seed=5)
+
+
+BATCH_LEVELS = {8: 3, 12: 3, 16: 4, 24: 4}
+
+
+def config4(n=256, seed=6, sizes=(8, 12, 16, 24), degrees=(1, 2, 3)):
+    """256 independent 3-D problems: N uniform in {8, 12, 16, 24} cells per
+    direction, degree uniform in {1, 2, 3}, 1-10 spheres (r in [0.05, 0.12]),
+    bottom and top clamped.  The linearisation point is a loaded state: a
+    uniaxial stretch u_z = e Z with e ~ U[0.02, 0.08] plus a smooth seeded
+    perturbation of amplitude e / 4, so max |u| <= 0.1.  (Smooth fields that
+    compress the body by a few percent already make the tangent indefinite,
+    which no CG solve survives.)  Returns light descriptors; ``batch_fields``
+    draws the vectors."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        N = int(rng.choice(sizes))
+        p = int(rng.choice(degrees))
+        ns = int(rng.integers(1, 11))
+        stretch = float(rng.uniform(0.02, 0.08))
+        seeds = [int(v) for v in rng.integers(0, 2 ** 31, size=3)]
+        out.append(dict(dim=3, n_cells=N, degree=p, n_levels=BATCH_LEVELS.get(N, 1), n_spheres=ns,
+                        stretch=stretch, amp=0.25 * stretch, sphere_seed=seeds[0], u_seed=seeds[1],
+                        x_seed=seeds[2], mask=clamp_bottom_top(3)))
+    return out
+
+
+def stretched_field(dim, L, stretch, seed, amp):
+    """u = stretch * X_last e_last + a smooth seeded perturbation (``sine_field``)."""
+    u = sine_field(dim, L, seed, amp, kmax=1)
+    t = np.arange(L, dtype=np.float64) / (L - 1)
+    u[(dim - 1) * L ** dim:] += stretch * np.repeat(t, L ** (dim - 1))
+    return u
+
+
+def batch_fields(desc):
+    """(inclusions, u, x) of one config-4 problem."""
+    L = desc["degree"] * desc["n_cells"] + 1
+    incl = spheres(desc["n_spheres"], desc["sphere_seed"], 3)
+    u = stretched_field(3, L, desc["stretch"], desc["u_seed"], desc["amp"])
+    x = normal_vector(3 * L ** 3, desc["x_seed"])
+    return incl, u, x
