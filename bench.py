@@ -165,6 +165,108 @@ def newton_bench(w, n_cells=64, n_levels=5, stretch=0.1, n_steps=4):
     return out
 
 
+def batch_bench(policy=2, steps=20, warmup=3, n=256):
+    """Config 4: 256 independent 3-D problems (N in {8, 12, 16, 24}, p in {1, 2, 3},
+    1-10 spheres, loaded linearisation point).  Aggregate batched vmult DoFs/s in
+    FP64 and FP32 against one launch per problem, and one Newton correction per
+    problem (K du = -R) by mixed-precision GMG-CG to 1e-8, all problems in
+    lockstep from one host thread, with graph-captured V-cycles."""
+    import torch
+
+    import workloads as W
+    from paper_1904_13131_amd import F32, Batch, Problem
+    mu, lam = W.two_phase_material()
+    descs = W.config4(n=n)
+    probs, us, x64 = [], [], []
+    t0 = time.perf_counter()
+    for d in descs:
+        incl = W.spheres(d["n_spheres"], d["sphere_seed"], 3)
+        P = Problem(3, d["n_cells"], d["degree"], n_levels=d["n_levels"], mu=tuple(mu), lam=tuple(lam),
+                    inclusions=incl, dirichlet_mask=d["mask"], qp_policy=policy, vcycle_dtype=F32,
+                    stream=torch.cuda.Stream())
+        _, u, x = W.batch_fields(d, coords=P.node_coords_1d())
+        probs.append(P)
+        us.append(torch.as_tensor(u, device="cuda"))
+        x64.append(torch.as_tensor(x, device="cuda"))
+    torch.cuda.synchronize()
+    t_create = time.perf_counter() - t0
+    dofs = [P.n_dofs() for P in probs]
+    total = int(sum(dofs))
+    ws_gb = sum(P.workspace.numel() for P in probs) / 1e9
+    B = Batch(probs)
+    t0 = time.perf_counter()
+    mj = B.set_deformation(us)
+    t_setdef = time.perf_counter() - t0
+    out = {"workload": f"{n} independent 3-D problems (seed 6): N in {{8,12,16,24}}, p in {{1,2,3}}, 1-10 spheres, "
+                       f"uniaxial stretch 2-8 % plus a smooth perturbation of 1/20 of it; {total:,} DoFs in total "
+                       f"({min(dofs):,}..{max(dofs):,})",
+           "n_problems": n, "total_dofs": total, "qp_policy": POLICIES[policy], "workspace_gb": round(ws_gb, 2),
+           "create_s": round(t_create, 2), "set_deformation_s": round(t_setdef, 3), "min_J": min(mj),
+           "degree_bins": len({d["degree"] for d in descs})}
+    stream = torch.cuda.current_stream()
+    for name, xs in (("f64", x64), ("f32", [x.float() for x in x64])):
+        ys = [torch.empty_like(x) for x in xs]
+        for _ in range(warmup):
+            B.tangent_vmult(xs, ys)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            B.tangent_vmult(xs, ys)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_b = e0.elapsed_time(e1) / steps
+        for _ in range(warmup):
+            for P, x, y in zip(probs, xs, ys):
+                P.tangent_vmult(x, y)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            for P, x, y in zip(probs, xs, ys):
+                P.tangent_vmult(x, y)
+        torch.cuda.synchronize()
+        ms_l = (time.perf_counter() - t0) * 1e3 / steps
+        out[f"vmult_{name}"] = {"batched_ms": ms_b, "batched_dofs_per_s": total / (ms_b * 1e-3),
+                                "per_problem_launches_ms": ms_l, "per_problem_dofs_per_s": total / (ms_l * 1e-3),
+                                "speedup_batched_vs_per_problem": ms_l / ms_b}
+        print(f"[bench] batch vmult {name}: {ms_b:.3f} ms ({total / (ms_b * 1e-3):.3e} DoF/s), "
+              f"one launch per problem {ms_l:.3f} ms", file=sys.stderr, flush=True)
+        del ys
+    # one Newton correction per problem: K du = -R(u), mixed-precision GMG-CG to 1e-8
+    bs = [P.residual(u) for P, u in zip(probs, us)]      # on the problems' streams
+    torch.cuda.synchronize()
+    for b in bs:
+        b.neg_()
+    xs = [torch.empty_like(b) for b in bs]
+    torch.cuda.synchronize()
+    for P in probs:
+        P.enable_graphs(True)
+    runs = {}
+    for label in ("first", "graphs", "eager"):
+        if label == "eager":
+            for P in probs:
+                P.enable_graphs(False)
+        t0 = time.perf_counter()
+        it, rel, ms = B.cg_solve(bs, xs, rtol=1e-8, max_it=300)
+        wall = time.perf_counter() - t0
+        runs[label] = {"wall_s": round(wall, 4), "dofs_per_s": total / wall,
+                       "per_problem_ms": {"median": float(np.median(ms)), "p90": float(np.percentile(ms, 90)),
+                                          "max": float(np.max(ms))},
+                       "cg_iters": {"min": int(min(it)), "median": float(np.median(it)), "max": int(max(it))},
+                       "max_relres": float(max(rel))}
+        print(f"[bench] batch solve ({label}): {wall:.3f} s wall, per-problem median {np.median(ms):.1f} ms, "
+              f"iters {min(it)}..{max(it)}, max relres {max(rel):.2e}", file=sys.stderr, flush=True)
+    out["solve"] = {"note": "first: includes the preconditioner set-up (diagonals, eigenvalue estimates, coarse "
+                            "inverse) and the graph capture; graphs: replayed V-cycle graphs; eager: no graphs",
+                    **runs}
+    B.close()
+    for P in probs:
+        P.close()
+    del probs, us, x64, bs, xs
+    torch.cuda.empty_cache()
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -176,6 +278,7 @@ def main(argv=None):
     ap.add_argument("--no-cold", action="store_true")
     ap.add_argument("--scatter", type=int, default=0, help="0 atomic, 1 colour, 2 tile")
     ap.add_argument("--no-newton", action="store_true", help="skip the config-3 Newton-step measurement")
+    ap.add_argument("--no-batch", action="store_true", help="skip the config-4 batched measurement")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 256 MiB device copy (reference for HBM byte counters)")
     a = ap.parse_args(argv)
@@ -259,6 +362,8 @@ def main(argv=None):
     out["roofline"]["kernel_ms_cold"] = r["kernel_ms_cold"]
     if not a.no_newton:
         out["newton_step"] = newton_bench(w)
+    if not a.no_batch:
+        out["batched"] = batch_bench()
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

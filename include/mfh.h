@@ -221,6 +221,13 @@ mfh_status mfh_newton_solve(mfh_problem* problem, double* u_dev, const double* f
                             double r_tol, int max_newton,
                             mfh_newton_record* records, int max_records, int* n_records);
 
+/* Coordinates of the support points along one axis of `level` (all axes
+ * are alike): the L = degree * N + 1 lattice positions in [0, 1], the
+ * Gauss-Lobatto-Legendre points of every cell (Sec. 7), into the host array
+ * x (L doubles).  Node (i, j, k) sits at (x[i], x[j], x[k]).  Host only.
+ * Errors: INVALID_ARG. */
+mfh_status mfh_node_coords_1d(mfh_problem* problem, int level, double* x_host);
+
 /* ---- Access to multigrid pieces, for verification against a reference ---- */
 
 /* Copies the FP64 level displacement of the last set_deformation. Sync. */
@@ -265,35 +272,46 @@ typedef struct mfh_batch mfh_batch;
 mfh_status mfh_batch_workspace_size(int n, mfh_problem* const* problems, size_t* bytes);
 
 /* Builds the device work lists of a batch: problems are binned by (dim,
- * degree); each bin's tangent vmult is one persistent launch whose grid
- * (grid_mult x resident blocks per CU x CUs, capped by the work) walks the
- * (problem, cell block) items of all its problems.  The problems keep their
- * own workspaces and must outlive the batch; the batch workspace (device,
- * 256-byte aligned) holds the per-problem argument tables.  Work is enqueued
- * on `hip_stream`.  Synchronises.  Errors: INVALID_ARG, WORKSPACE, HIP. */
+ * degree); each bin's tangent vmult is one launch with one workgroup per
+ * (problem, cell block) item of all its problems.  The problems keep their
+ * own workspaces and streams and must outlive the batch; the batch workspace
+ * (device, 256-byte aligned) holds the per-problem argument tables and the
+ * item lists; the batch also allocates a small pinned host buffer (a few
+ * hundred bytes per problem) for the scalars its solves read back.  Batched
+ * vmults are enqueued on `hip_stream`.  Synchronises.
+ * Errors: INVALID_ARG, WORKSPACE, HIP. */
 mfh_status mfh_batch_create(int n, mfh_problem* const* problems, void* workspace, size_t bytes,
-                            void* hip_stream, int grid_mult, mfh_batch** out);
+                            void* hip_stream, mfh_batch** out);
 mfh_status mfh_batch_destroy(mfh_batch* batch);
 const char* mfh_batch_last_error(const mfh_batch* batch);
 
-/* set_deformation of every problem (host array u of device pointers), run
- * from up to n_threads host threads, each problem on its own stream; min J per
- * problem into the host array min_J (may be NULL).  Synchronises. */
-mfh_status mfh_batch_set_deformation(mfh_batch* batch, const double* const* u, double* min_J, int n_threads);
+/* mfh_set_deformation of every problem (host array u of device pointers):
+ * the level data of all problems are enqueued on their own streams first and
+ * drained once; min J per problem into the host array min_J (may be NULL; NaN
+ * for a failed problem).  Synchronises.  Returns the first failing problem's
+ * status (INVERTED, HIP, INVALID_ARG); the other problems are set. */
+mfh_status mfh_batch_set_deformation(mfh_batch* batch, const double* const* u, double* min_J);
 
 /* y[i] = K_c,i x[i] for every problem i, on the finest levels (host arrays of
  * device pointers, dtype as for mfh_tangent_vmult): one batched output fill
- * and one persistent launch per (dim, degree) bin.  Async on the batch
- * stream; every problem must have a linearisation point. */
+ * and one launch per (dim, degree) bin.  Async on the batch stream, except
+ * that a pointer set different from the previous call's is uploaded and the
+ * batch stream synchronised first; every problem must have a linearisation
+ * point. */
 mfh_status mfh_batch_tangent_vmult(mfh_batch* batch, int dtype, const void* const* x, void* const* y);
 
-/* mfh_cg_solve of every problem (host arrays of device pointers), run from up
- * to n_threads host threads so that the problems' streams execute
- * concurrently; per-problem iterations, relative residuals and host wall
- * time (ms) into the host arrays (may be NULL).  Synchronises.  Returns the
- * first failing problem's status. */
+/* mfh_cg_solve of every problem (host arrays of device pointers) from one
+ * host thread, in lockstep: the preconditioner set-ups of all problems are
+ * enqueued and drained together, then every round issues one PCG iteration of
+ * every unfinished problem on its own stream (V-cycles replayed from graphs
+ * when enabled) and judges them all after one drain.  Each problem follows
+ * the same sequence of operations as mfh_cg_solve.  Per-problem iterations,
+ * relative residuals (|b - K_c x| / |b| at the end) and the time (ms, from the
+ * call's start) at which the problem finished, into the host arrays (may be
+ * NULL).  Synchronises.  Returns the first failing problem's status
+ * (NOT_CONVERGED, BREAKDOWN, NOT_SPD, HIP); the others are solved. */
 mfh_status mfh_batch_cg_solve(mfh_batch* batch, const double* const* b, double* const* x, double rtol,
-                              int max_it, int n_threads, int* iters, double* relres, double* solve_ms);
+                              int max_it, int* iters, double* relres, double* solve_ms);
 
 /* ---- Kernel timers (measurement of the operator kernel) ---- */
 

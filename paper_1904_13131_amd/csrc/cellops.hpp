@@ -528,7 +528,8 @@ __device__ __forceinline__ int material_of(const CellArgs<T>& a, long long e, in
 // block's cells (y pre-filled).  Shared by the single-problem kernel and the
 // batched work-list kernel.
 template <int DIM, int P, typename T, int POL>
-__device__ __forceinline__ void tangent_block(const CellArgs<T>& a, long long blk, T* lds) {
+__device__ __forceinline__ void tangent_block(const CellArgs<T>& a, const T* __restrict__ x, T* __restrict__ y,
+                                              long long blk, T* lds) {
   constexpr int N1 = P + 1;
   using G = Geo<DIM, N1>;
   using SF = SumFact<DIM, N1, T>;
@@ -546,7 +547,7 @@ __device__ __forceinline__ void tangent_block(const CellArgs<T>& a, long long bl
   T gx[DIM][DIM][N1];
   {
     T v[DIM][N1];
-    gather<DIM, N1, T>(a.x, a, cp, act, true, v);
+    gather<DIM, N1, T>(x, a, cp, act, true, v);
     SF::template forward<DIM>(v, gx, lds, pen, cl, act, a.tb);
   }
   T gu[DIM][DIM][N1];
@@ -630,9 +631,9 @@ __device__ __forceinline__ void tangent_block(const CellArgs<T>& a, long long bl
       const T v = __shfl_up(out[c][N1 - 1], 1);
       if (from_prev) out[c][0] += v;
     }
-    scatter_merged<DIM, N1, T>(a.y, a, cp, act, out, to_next);
+    scatter_merged<DIM, N1, T>(y, a, cp, act, out, to_next);
   } else {
-    scatter<DIM, N1, T>(a.y, a, cp, act, out);
+    scatter<DIM, N1, T>(y, a, cp, act, out);
   }
 }
 
@@ -642,36 +643,33 @@ __global__ void __launch_bounds__(kBlock) k_tangent(CellArgs<T> a) {
   using G = Geo<DIM, P + 1>;
   __shared__ T lds[DIM * G::NARR * G::NV * G::CPB];
   const long long blk = a.color < 0 ? xcd_block(blockIdx.x, gridDim.x) : (long long)blockIdx.x;
-  tangent_block<DIM, P, T, POL>(a, blk, lds);
+  tangent_block<DIM, P, T, POL>(a, a.x, a.y, blk, lds);
 }
 
-// Batched tangent vmult over many independent problems of one degree: a
-// persistent grid walks the work list of (problem, cell block) items; item i
-// belongs to the problem whose block offset off[p] <= i < off[p+1].  The
-// problem index is wave-uniform, so its arguments come in through scalar loads.
+// Batched tangent vmult over many independent problems of one degree: one
+// workgroup per (problem, cell block) item of the bin's work list, item i
+// being cell block item[i].y of problem item[i].x.  The item index is
+// XCD-aware (neighbouring cell blocks of a problem share an L2) and
+// wave-uniform, so the item and the problem's arguments come in through
+// scalar loads; the block body is the single-problem one.
 template <int DIM, int P, typename T, int POL>
 __global__ void __launch_bounds__(kBlock) k_tangent_batch(const CellArgs<T>* __restrict__ args,
-                                                          const long long* __restrict__ off, int nprob,
+                                                          const int2* __restrict__ items,
                                                           const T* const* __restrict__ xs, T* const* __restrict__ ys) {
   using G = Geo<DIM, P + 1>;
   __shared__ T lds[DIM * G::NARR * G::NV * G::CPB];
-  const long long total = off[nprob];
-  for (long long item = blockIdx.x; item < total; item += gridDim.x) {
-    int lo = 0, hi = nprob - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (off[mid] <= item)
-        lo = mid;
-      else
-        hi = mid - 1;
-    }
-    lo = __builtin_amdgcn_readfirstlane(lo);
-    CellArgs<T> a = args[lo];
-    a.x = xs[lo];
-    a.y = ys[lo];
-    tangent_block<DIM, P, T, POL>(a, item - off[lo], lds);
-    __syncthreads();
-  }
+  // The tables are read through the constant address space, where
+  // wave-uniform addresses become scalar loads; the arguments are used in
+  // place (no private copy), as kernel arguments are.
+  using CArgs = const CellArgs<T> __attribute__((address_space(4)));
+  using CInt = const int __attribute__((address_space(4)));
+  using CPtrX = const T* const __attribute__((address_space(4)));
+  using CPtrY = T* const __attribute__((address_space(4)));
+  const long long i = xcd_block(blockIdx.x, gridDim.x);
+  const int p = ((CInt*)items)[2 * i];
+  const int blk = ((CInt*)items)[2 * i + 1];
+  const CellArgs<T>& a = *(const CellArgs<T>*)((CArgs*)args + p);
+  tangent_block<DIM, P, T, POL>(a, ((CPtrX*)xs)[p], ((CPtrY*)ys)[p], blk, lds);
 }
 
 // ---------------------------------------------------------------------------

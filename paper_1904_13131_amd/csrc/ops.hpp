@@ -18,12 +18,11 @@ struct OpFns {
   void (*tangent_tile_d[3])(const CellArgs<double>&, unsigned grid, hipStream_t);
   void (*tangent_tile_f[3])(const CellArgs<float>&, unsigned grid, hipStream_t);
   long long (*tiles[2])(int N);   // [0] double, [1] float
-  // batched vmult over problems of this (dim, degree): persistent grid over the work list
-  void (*tangent_batch_d[3])(const CellArgs<double>* args, const long long* off, int nprob, const double* const* xs,
-                             double* const* ys, unsigned grid, hipStream_t);
-  void (*tangent_batch_f[3])(const CellArgs<float>* args, const long long* off, int nprob, const float* const* xs,
-                             float* const* ys, unsigned grid, hipStream_t);
-  int (*batch_blocks_per_cu[2])();   // resident blocks per CU of the batched kernel (occupancy)
+  // batched vmult over problems of this (dim, degree): one workgroup per (problem, cell block) item
+  void (*tangent_batch_d[3])(const CellArgs<double>* args, const int2* items, const double* const* xs,
+                             double* const* ys, unsigned n_items, hipStream_t);
+  void (*tangent_batch_f[3])(const CellArgs<float>* args, const int2* items, const float* const* xs,
+                             float* const* ys, unsigned n_items, hipStream_t);
   void (*coarse_assemble)(const CellArgs<double>&, const int* fmap, long long nf, double* K,
                           unsigned grid, hipStream_t);
   int cpb;        // cells per block of the pencil kernels

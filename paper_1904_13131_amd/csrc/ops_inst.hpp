@@ -55,17 +55,9 @@ struct OpInst {
     hipLaunchKernelGGL((k_tangent<DIM, P, T, POL>), dim3(grid), dim3(kBlock), 0, s, a);
   }
   template <typename T, int POL>
-  static void tangent_batch(const CellArgs<T>* args, const long long* off, int nprob, const T* const* xs,
-                            T* const* ys, unsigned grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_tangent_batch<DIM, P, T, POL>), dim3(grid), dim3(kBlock), 0, s, args, off, nprob, xs, ys);
-  }
-  template <typename T>
-  static int batch_blocks_per_cu() {
-    int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, (const void*)k_tangent_batch<DIM, P, T, POL_R>, kBlock, 0) !=
-        hipSuccess)
-      n = 1;
-    return n > 0 ? n : 1;
+  static void tangent_batch(const CellArgs<T>* args, const int2* items, const T* const* xs, T* const* ys,
+                            unsigned n_items, hipStream_t s) {
+    hipLaunchKernelGGL((k_tangent_batch<DIM, P, T, POL>), dim3(n_items), dim3(kBlock), 0, s, args, items, xs, ys);
   }
   static void residual(const CellArgs<double>& a, unsigned grid, hipStream_t s) {
     hipLaunchKernelGGL((k_residual<DIM, P>), dim3(grid), dim3(kBlock), 0, s, a);
@@ -94,7 +86,6 @@ struct OpInst {
         {&tiles<double>, &tiles<float>},
         {&tangent_batch<double, POL_R>, &tangent_batch<double, POL_CF>, &tangent_batch<double, POL_C2>},
         {&tangent_batch<float, POL_R>, &tangent_batch<float, POL_CF>, &tangent_batch<float, POL_C2>},
-        {&batch_blocks_per_cu<double>, &batch_blocks_per_cu<float>},
         &coarse_assemble,
         Geo<DIM, P + 1>::CPB,
         kBlock / (DIM == 3 ? (P + 1) * (P + 1) * (P + 1) : (P + 1) * (P + 1)),

@@ -2,10 +2,8 @@
 // set_deformation, operator application, V-cycle, CG, Newton, and the C ABI.
 #include <hip/hip_runtime.h>
 
-#include <atomic>
 #include <chrono>
 #include <cmath>
-#include <thread>
 #include <cstdio>
 #include <cstring>
 #include <memory>
@@ -119,7 +117,7 @@ struct mfh_problem {
   double* sc = nullptr;              // device scalars
   double* part = nullptr;            // reduction partials
   double* minj = nullptr;            // per level min J
-  double* hist = nullptr;            // Lanczos alpha/beta history (2 * eig_iters)
+  double* hist = nullptr;            // Lanczos alpha/beta history (2 * eig_iters per level)
   char* tmpA = nullptr;
   char* tmpB = nullptr;
   double *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_Ap = nullptr;
@@ -310,7 +308,7 @@ size_t layout(mfh_problem* P, char* base) {
   P->sc = b.take<double>(SC_COUNT);
   P->part = b.take<double>((size_t)std::max<long long>(kRedBlocks, top.ncells / P->ops->cpb + 16));
   P->minj = b.take<double>(P->lv.size());
-  P->hist = b.take<double>(2 * (size_t)d.eig_iters + 2);
+  P->hist = b.take<double>(2 * (size_t)d.eig_iters * P->lv.size() + 2);
   // transfer intermediates: dim * Lf^(dim-1) * Lc entries of up to 8 bytes
   size_t tmp = 8;
   for (size_t l = 1; l < P->lv.size(); ++l) {
@@ -600,9 +598,10 @@ double read_scalar(mfh_problem* P, const double* dev) {
 }
 
 // Largest eigenvalue of D^-1 A on level l from eig_iters Jacobi-PCG steps
-// (CG-Lanczos relation), in the V-cycle precision.
+// (CG-Lanczos relation), in the V-cycle precision.  The iterations are
+// enqueued here; their alpha/beta history lands in hist (2 * eig_iters).
 template <typename T>
-double lambda_max(mfh_problem* P, int l) {
+void lanczos_enqueue(mfh_problem* P, int l, double* hist) {
   Level& v = P->lv[l];
   const long long n = v.ndofs;
   T* r = static_cast<T*>(v.vb);
@@ -618,14 +617,16 @@ double lambda_max(mfh_problem* P, int l) {
   for (int j = 0; j < it; ++j) {
     vmult<T>(P, l, p, Ap);
     dot<T, T>(p, Ap, n, P->part, P->sc + SC_PAP, P->stream);
-    scalar_div(P->sc, SC_ALPHA, SC_RZ, SC_PAP, -1, -1, P->hist, j, P->stream);
+    scalar_div(P->sc, SC_ALPHA, SC_RZ, SC_PAP, -1, -1, hist, j, P->stream);
     lanczos_update<T>(r, z, Ap, dinv, n, P->sc, P->part, P->stream);
-    scalar_div(P->sc, SC_BETA, SC_RZNEW, SC_RZ, SC_RZ, SC_RZNEW, P->hist, it + j, P->stream);
+    scalar_div(P->sc, SC_BETA, SC_RZNEW, SC_RZ, SC_RZ, SC_RZNEW, hist, it + j, P->stream);
     cg_pupdate<T>(p, z, n, P->sc, P->stream);
   }
-  std::vector<double> h(2 * it);
-  HIPCHECK(hipMemcpyAsync(h.data(), P->hist, sizeof(double) * 2 * it, hipMemcpyDeviceToHost, P->stream));
-  HIPCHECK(hipStreamSynchronize(P->stream));
+}
+
+// Host side of the estimate: the Lanczos tridiagonal from the CG coefficients
+// (up to the first non-positive or non-finite one) and its largest eigenvalue.
+double lanczos_lambda(const double* h, int it, int l) {
   std::vector<double> al, be;
   for (int j = 0; j < it; ++j) {
     const double a = h[j], bta = h[it + j];
@@ -665,10 +666,13 @@ void interpolate_down(mfh_problem* P, int l) {
   transfer<double>(P, f.I1, f.L, c.L, f.u64, c.u64, false, false, c.lt);
 }
 
-// Builds every level operator about u (Sec. 6).  Returns min J over all levels.
-double set_deformation(mfh_problem* P, const double* u) {
+// Builds every level operator about u (Sec. 6): enqueues the level
+// displacements and quadrature data; min J of every level lands in P->minj.
+void setdef_enqueue(mfh_problem* P, const double* u) {
   const mfh_desc& d = P->d;
   P->drop_graph();
+  P->deformed = false;
+  P->precond_ready = false;
   const int nl = (int)P->lv.size();
   hipStream_t s = P->stream;
   Level& top = P->lv.back();
@@ -686,32 +690,41 @@ double set_deformation(mfh_problem* P, const double* u) {
     min_reduce(P->part, (int)g, P->minj + l, s);
   }
   check_launch("quadrature data");
-  std::vector<double> mj(nl);
-  HIPCHECK(hipMemcpyAsync(mj.data(), P->minj, sizeof(double) * nl, hipMemcpyDeviceToHost, s));
-  HIPCHECK(hipStreamSynchronize(s));
+}
+
+// Host side after the stream has drained: min J over the levels (mj[nl]
+// copied from P->minj); an inverted quadrature point is an error.
+double setdef_finish(mfh_problem* P, const double* mj) {
   double minJ = 1e300;
-  for (double m : mj) minJ = std::fmin(minJ, m);
+  for (size_t l = 0; l < P->lv.size(); ++l) minJ = std::fmin(minJ, mj[l]);
   if (!(minJ > 0)) {
-    P->deformed = false;
     char buf[160];
     std::snprintf(buf, sizeof buf, "deformation inverts a quadrature point: min J = %.6g", minJ);
     throw Error(MFH_ERR_INVERTED, buf);
   }
   P->deformed = true;
-  P->precond_ready = false;
-  HIPCHECK(hipStreamSynchronize(s));
   return minJ;
+}
+
+double set_deformation(mfh_problem* P, const double* u) {
+  setdef_enqueue(P, u);
+  std::vector<double> mj(P->lv.size());
+  HIPCHECK(hipMemcpyAsync(mj.data(), P->minj, sizeof(double) * mj.size(), hipMemcpyDeviceToHost, P->stream));
+  HIPCHECK(hipStreamSynchronize(P->stream));
+  return setdef_finish(P, mj.data());
 }
 
 // Preconditioner data about the current linearisation point: operator
 // diagonals, Chebyshev intervals (lambda_max) and the coarse inverse.  Built on
-// the first solver call after every set_deformation.
-void setup_precond(mfh_problem* P) {
-  if (P->precond_ready) return;
+// the first solver call after every set_deformation.  The enqueue half issues
+// all device work; the host half needs the Lanczos histories (P->hist) and
+// the coarse pivot flags (P->flag) copied back.
+size_t setup_host_words(const mfh_problem* P) { return 2 * (size_t)P->d.eig_iters * P->lv.size() + 2; }
+
+void setup_enqueue(mfh_problem* P) {
   const mfh_desc& d = P->d;
   const int nl = (int)P->lv.size();
   hipStream_t s = P->stream;
-  // diagonals and smoother intervals
   for (int l = 0; l < nl; ++l) {
     Level& v = P->lv[l];
     fill<double>(v.diag64, 0.0, v.ndofs, s);
@@ -724,19 +737,22 @@ void setup_precond(mfh_problem* P) {
       reciprocal<double>(v.diag64, static_cast<double*>(v.dinv), v.ndofs, s);
   }
   check_launch("diagonal");
+  const int it = d.eig_iters;
   for (int l = 1; l < nl; ++l) {
-    Level& v = P->lv[l];
-    v.lam_max = d.vcycle_dtype == MFH_F32 ? lambda_max<float>(P, l) : lambda_max<double>(P, l);
-    set_cheb_coeffs(P, v);
+    double* h = P->hist + 2 * (size_t)it * l;
+    if (d.vcycle_dtype == MFH_F32)
+      lanczos_enqueue<float>(P, l, h);
+    else
+      lanczos_enqueue<double>(P, l, h);
   }
   // coarse level: dense FP64 tangent on free DoFs, inverted in place
   Level& c = P->lv[0];
   const long long nf = P->nf;
+  fill<int>(P->flag, 0, 2, s);
   if (nf) {
     fill<double>(P->Kinv, 0.0, nf * nf, s);
     CellArgs<double> a = cell_args<double>(P, c, c.u64, nullptr, nullptr, nullptr);
     P->ops->coarse_assemble(a, P->fmap, nf, P->Kinv, (unsigned)c.ncells, s);
-    fill<int>(P->flag, 0, 2, s);
     diag_absmax(P->Kinv, nf, P->sc + SC_TMP, s);
     for (long long k0 = 0; k0 < nf; k0 += 64) {
       const int nb = (int)std::min<long long>(64, nf - k0);
@@ -745,28 +761,57 @@ void setup_precond(mfh_problem* P) {
       gj_update(P->Kinv, nf, k0, nb, P->gj_C, P->gj_R, s);
       gj_finish(P->Kinv, nf, k0, nb, P->gj_C, P->gj_R, P->gj_P, s);
     }
-    check_launch("coarse inverse");
-    int flag[2] = {0, 0};
-    HIPCHECK(hipMemcpyAsync(flag, P->flag, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
-    HIPCHECK(hipStreamSynchronize(s));
-    P->coarse_negative = flag[1];
-    if (flag[0]) throw Error(MFH_ERR_NOT_SPD, "coarse-level tangent is numerically singular");
   }
-  HIPCHECK(hipStreamSynchronize(s));
+  check_launch("coarse inverse");
+}
+
+// Enqueues the copy of what the host half needs into host (setup_host_words doubles).
+void setup_copy_back(mfh_problem* P, double* host) {
+  const size_t nh = 2 * (size_t)P->d.eig_iters * P->lv.size();
+  HIPCHECK(hipMemcpyAsync(host, P->hist, sizeof(double) * nh, hipMemcpyDeviceToHost, P->stream));
+  HIPCHECK(hipMemcpyAsync(host + nh, P->flag, 2 * sizeof(int), hipMemcpyDeviceToHost, P->stream));
+}
+
+void setup_finish(mfh_problem* P, const double* host) {
+  const int nl = (int)P->lv.size();
+  const int it = P->d.eig_iters;
+  for (int l = 1; l < nl; ++l) {
+    Level& v = P->lv[l];
+    v.lam_max = lanczos_lambda(host + 2 * (size_t)it * l, it, l);
+    set_cheb_coeffs(P, v);
+  }
+  int flag[2];
+  std::memcpy(flag, host + 2 * (size_t)it * nl, sizeof flag);
+  P->coarse_negative = flag[1];
+  if (flag[0]) throw Error(MFH_ERR_NOT_SPD, "coarse-level tangent is numerically singular");
   P->precond_ready = true;
+}
+
+void setup_precond(mfh_problem* P) {
+  if (P->precond_ready) return;
+  setup_enqueue(P);
+  std::vector<double> host(setup_host_words(P));
+  setup_copy_back(P, host.data());
+  HIPCHECK(hipStreamSynchronize(P->stream));
+  setup_finish(P, host.data());
 }
 
 // z = V-cycle(r) on the CG's own vectors (r = cg_r, z = cg_z); replays the
 // captured graph when graphs are enabled and the stream can be captured.
+bool graphs_on(const mfh_problem* P) { return P->use_graphs && P->stream != nullptr; }
+
+void capture_vcycle(mfh_problem* P) {
+  if (!graphs_on(P) || P->graph_ready) return;
+  HIPCHECK(hipStreamBeginCapture(P->stream, hipStreamCaptureModeThreadLocal));
+  vcycle(P, P->cg_r, P->cg_z);
+  HIPCHECK(hipStreamEndCapture(P->stream, &P->graph));
+  HIPCHECK(hipGraphInstantiate(&P->gexec, P->graph, nullptr, nullptr, 0));
+  P->graph_ready = true;
+}
+
 void precond(mfh_problem* P) {
-  if (P->use_graphs && P->stream != nullptr) {
-    if (!P->graph_ready) {
-      HIPCHECK(hipStreamBeginCapture(P->stream, hipStreamCaptureModeThreadLocal));
-      vcycle(P, P->cg_r, P->cg_z);
-      HIPCHECK(hipStreamEndCapture(P->stream, &P->graph));
-      HIPCHECK(hipGraphInstantiate(&P->gexec, P->graph, nullptr, nullptr, 0));
-      P->graph_ready = true;
-    }
+  if (graphs_on(P)) {
+    capture_vcycle(P);
     HIPCHECK(hipGraphLaunch(P->gexec, P->stream));
   } else {
     vcycle(P, P->cg_r, P->cg_z);
@@ -779,18 +824,61 @@ struct CgResult {
   mfh_status st = MFH_OK;
 };
 
+// Enqueued pieces of the preconditioned CG (Hestenes-Stiefel, x0 = 0) on the
+// problem's own vectors; the single-problem solve and the batched lockstep
+// solve issue the same sequence per problem.
+void cg_start(mfh_problem* P, const double* b, double* x) {   // x = 0, r = b, bb = b.b
+  const long long n = P->lv.back().ndofs;
+  fill<double>(x, 0.0, n, P->stream);
+  HIPCHECK(hipMemcpyAsync(P->cg_r, b, sizeof(double) * n, hipMemcpyDeviceToDevice, P->stream));
+  dot<double, double>(b, b, n, P->part, P->sc + SC_BB, P->stream);
+}
+
+void cg_first_dir(mfh_problem* P) {   // z = M r, p = z, rz = r.z
+  const long long n = P->lv.back().ndofs;
+  precond(P);
+  HIPCHECK(hipMemcpyAsync(P->cg_p, P->cg_z, sizeof(double) * n, hipMemcpyDeviceToDevice, P->stream));
+  dot<double, double>(P->cg_r, P->cg_z, n, P->part, P->sc + SC_RZ, P->stream);
+}
+
+void cg_step(mfh_problem* P, double* x) {   // Ap = K p, alpha = rz / pAp, x += alpha p, r -= alpha Ap, rr
+  const long long n = P->lv.back().ndofs;
+  vmult<double>(P, (int)P->lv.size() - 1, P->cg_p, P->cg_Ap);
+  dot<double, double>(P->cg_p, P->cg_Ap, n, P->part, P->sc + SC_PAP, P->stream);
+  scalar_div(P->sc, SC_ALPHA, SC_RZ, SC_PAP, -1, -1, nullptr, 0, P->stream);
+  cg_update<double>(x, P->cg_r, P->cg_p, P->cg_Ap, n, P->sc, P->part, P->stream);
+}
+
+void cg_next_dir(mfh_problem* P) {   // z = M r, beta = r.z / rz, p = z + beta p
+  const long long n = P->lv.back().ndofs;
+  precond(P);
+  dot<double, double>(P->cg_r, P->cg_z, n, P->part, P->sc + SC_RZNEW, P->stream);
+  scalar_div(P->sc, SC_BETA, SC_RZNEW, SC_RZ, SC_RZ, SC_RZNEW, nullptr, 0, P->stream);
+  cg_pupdate<double>(P->cg_p, P->cg_z, n, P->sc, P->stream);
+}
+
+void cg_true_residual(mfh_problem* P, const double* b, const double* x) {   // |b - K_c x|^2 into SC_TMP
+  const long long n = P->lv.back().ndofs;
+  vmult<double>(P, (int)P->lv.size() - 1, x, P->cg_Ap);
+  lincomb3<double>(P->cg_r, 1.0, b, -1.0, P->cg_Ap, 0.0, nullptr, n, P->stream);
+  dot<double, double>(P->cg_r, P->cg_r, n, P->part, P->sc + SC_TMP, P->stream);
+}
+
+// Host decision after an iteration: BREAKDOWN, OK (converged), NOT_CONVERGED
+// (budget spent) or 1 (continue).
+int cg_judge(const double* h, double bb, int it, double rtol, int max_it, double* relres) {
+  const double pAp = h[SC_PAP], rr = h[SC_RR];
+  if (!(pAp > 0) || !std::isfinite(rr)) return MFH_ERR_BREAKDOWN;
+  *relres = std::sqrt(rr / bb);
+  if (*relres <= rtol) return MFH_OK;
+  if (it == max_it) return MFH_ERR_NOT_CONVERGED;
+  return 1;
+}
+
 CgResult cg_solve(mfh_problem* P, const double* b, double* x, double rtol, int max_it) {
-  Level& v = P->lv.back();
-  const long long n = v.ndofs;
   hipStream_t s = P->stream;
-  double* r = P->cg_r;
-  double* z = P->cg_z;
-  double* p = P->cg_p;
-  double* Ap = P->cg_Ap;
   CgResult res;
-  fill<double>(x, 0.0, n, s);
-  HIPCHECK(hipMemcpyAsync(r, b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-  dot<double, double>(b, b, n, P->part, P->sc + SC_BB, s);
+  cg_start(P, b, x);
   const double bb = read_scalar(P, P->sc + SC_BB);
   if (!std::isfinite(bb)) {
     res.st = MFH_ERR_BREAKDOWN;
@@ -798,39 +886,22 @@ CgResult cg_solve(mfh_problem* P, const double* b, double* x, double rtol, int m
     return res;
   }
   if (bb == 0.0) return res;
-  precond(P);
-  HIPCHECK(hipMemcpyAsync(p, z, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-  dot<double, double>(r, z, n, P->part, P->sc + SC_RZ, s);
+  cg_first_dir(P);
   res.st = MFH_ERR_NOT_CONVERGED;
   for (int it = 1; it <= max_it; ++it) {
-    vmult<double>(P, (int)P->lv.size() - 1, p, Ap);
-    dot<double, double>(p, Ap, n, P->part, P->sc + SC_PAP, s);
-    scalar_div(P->sc, SC_ALPHA, SC_RZ, SC_PAP, -1, -1, nullptr, 0, s);
-    cg_update<double>(x, r, p, Ap, n, P->sc, P->part, s);
+    cg_step(P, x);
     double h[SC_COUNT];
     HIPCHECK(hipMemcpyAsync(h, P->sc, sizeof(double) * SC_COUNT, hipMemcpyDeviceToHost, s));
     HIPCHECK(hipStreamSynchronize(s));
     res.iters = it;
-    const double pAp = h[SC_PAP], rr = h[SC_RR];
-    if (!(pAp > 0) || !std::isfinite(rr)) {
-      res.st = MFH_ERR_BREAKDOWN;
+    const int j = cg_judge(h, bb, it, rtol, max_it, &res.relres);
+    if (j != 1) {
+      res.st = (mfh_status)j;
       break;
     }
-    res.relres = std::sqrt(rr / bb);
-    if (res.relres <= rtol) {
-      res.st = MFH_OK;
-      break;
-    }
-    if (it == max_it) break;
-    precond(P);
-    dot<double, double>(r, z, n, P->part, P->sc + SC_RZNEW, s);
-    scalar_div(P->sc, SC_BETA, SC_RZNEW, SC_RZ, SC_RZ, SC_RZNEW, nullptr, 0, s);
-    cg_pupdate<double>(p, z, n, P->sc, s);
+    cg_next_dir(P);
   }
-  // explicit final residual |b - K_c x| / |b|
-  vmult<double>(P, (int)P->lv.size() - 1, x, Ap);
-  lincomb3<double>(r, 1.0, b, -1.0, Ap, 0.0, nullptr, n, s);
-  dot<double, double>(r, r, n, P->part, P->sc + SC_TMP, s);
+  cg_true_residual(P, b, x);
   const double rr = read_scalar(P, P->sc + SC_TMP);
   if (res.st != MFH_ERR_BREAKDOWN) res.relres = std::sqrt(rr / bb);
   check_launch("cg");
@@ -1158,6 +1229,16 @@ mfh_status mfh_newton_solve(mfh_problem* P, double* u, const double* fv, int n_s
   return st;
 }
 
+mfh_status mfh_node_coords_1d(mfh_problem* P, int level, double* x) {
+  if (!P) return MFH_ERR_INVALID_ARG;
+  return guarded(P, [&] {
+    check_level(P, level);
+    need(x != nullptr, "x is NULL");
+    const std::vector<double> X = lattice_coords(P->lv[level].N, P->d.degree);
+    std::memcpy(x, X.data(), sizeof(double) * X.size());
+  });
+}
+
 mfh_status mfh_level_displacement(mfh_problem* P, int level, double* u) {
   if (!P) return MFH_ERR_INVALID_ARG;
   return guarded(P, [&] {
@@ -1284,25 +1365,31 @@ struct mfh_batch {
   std::vector<mfh_problem*> probs;
   hipStream_t stream = nullptr;
   int policy = 0;
-  int grid_mult = 1;
-  int n_cu = 256;
   struct Bin {
     int dim = 0, degree = 0;
     std::vector<int> ids;
     mfh::CellArgs<double>* a64 = nullptr;
     mfh::CellArgs<float>* a32 = nullptr;
-    long long* off = nullptr;
+    int2* items = nullptr;             // (index in bin, cell block) per workgroup
     void** xs = nullptr;
     void** ys = nullptr;
-    long long total = 0;
+    long long n_items = 0;
     const mfh::OpFns* ops = nullptr;
+    std::vector<const void*> last_x, last_y;   // pointer tables on the device (skip re-upload)
   };
   std::vector<Bin> bins;
   mfh::FillItem<double>* f64 = nullptr;
   mfh::FillItem<float>* f32 = nullptr;
   long long* foff = nullptr;
   long long fchunks = 0;
+  std::vector<const void*> last_fx, last_fy;   // fill items on the device (per dtype slot 0/1)
+  int last_fill_dtype = -1;
+  double* pin = nullptr;               // pinned host words, one slot per problem
+  std::vector<size_t> slot;            // slot offsets into pin
   std::string err;
+  ~mfh_batch() {
+    if (pin) (void)hipHostFree(pin);
+  }
 };
 
 namespace mfh {
@@ -1315,7 +1402,12 @@ size_t batch_layout(mfh_batch* B, char* base) {
     const size_t nb = bin.ids.size();
     bin.a64 = b.take<CellArgs<double>>(nb);
     bin.a32 = b.take<CellArgs<float>>(nb);
-    bin.off = b.take<long long>(nb + 1);
+    bin.n_items = 0;
+    for (int i : bin.ids) {
+      const mfh_problem* P = B->probs[i];
+      bin.n_items += (P->lv.back().ncells + P->ops->cpb - 1) / P->ops->cpb;
+    }
+    bin.items = b.take<int2>(bin.n_items);
     bin.xs = b.take<void*>(nb);
     bin.ys = b.take<void*>(nb);
   }
@@ -1348,34 +1440,43 @@ template <typename T>
 void batch_vmult(mfh_batch* B, const void* const* x, void* const* y) {
   hipStream_t s = B->stream;
   const size_t n = B->probs.size();
-  // fill items (outputs: 0, or x on constrained DoFs)
-  std::vector<FillItem<T>> items(n);
-  for (size_t i = 0; i < n; ++i) {
-    const Level& v = B->probs[i]->lv.back();
-    items[i] = FillItem<T>{static_cast<T*>(y[i]), static_cast<const T*>(x[i]), v.lt, v.ndofs};
-  }
-  FillItem<T>* fdev = std::is_same<T, double>::value ? reinterpret_cast<FillItem<T>*>(B->f64)
-                                                     : reinterpret_cast<FillItem<T>*>(B->f32);
-  HIPCHECK(hipMemcpyAsync(fdev, items.data(), sizeof(FillItem<T>) * n, hipMemcpyHostToDevice, s));
-  fill_dirichlet_batch<T>(fdev, B->foff, (int)n, B->fchunks, s);
   const int ti = std::is_same<T, double>::value ? 0 : 1;
+  // fill items (outputs: 0, or x on constrained DoFs); uploaded only when the pointers change
+  std::vector<const void*> fx(x, x + n), fy(y, y + n);
+  FillItem<T>* fdev = ti == 0 ? reinterpret_cast<FillItem<T>*>(B->f64) : reinterpret_cast<FillItem<T>*>(B->f32);
+  if (B->last_fill_dtype != ti || fx != B->last_fx || fy != B->last_fy) {
+    std::vector<FillItem<T>> items(n);
+    for (size_t i = 0; i < n; ++i) {
+      const Level& v = B->probs[i]->lv.back();
+      items[i] = FillItem<T>{static_cast<T*>(y[i]), static_cast<const T*>(x[i]), v.lt, v.ndofs};
+    }
+    HIPCHECK(hipMemcpyAsync(fdev, items.data(), sizeof(FillItem<T>) * n, hipMemcpyHostToDevice, s));
+    HIPCHECK(hipStreamSynchronize(s));   // the host table goes out of scope
+    B->last_fill_dtype = ti;
+    B->last_fx = fx;
+    B->last_fy = fy;
+  }
+  fill_dirichlet_batch<T>(fdev, B->foff, (int)n, B->fchunks, s);
   for (auto& bin : B->bins) {
     const size_t nb = bin.ids.size();
-    std::vector<void*> xs(nb), ys(nb);
+    std::vector<const void*> xs(nb), ys(nb);
     for (size_t k = 0; k < nb; ++k) {
-      xs[k] = const_cast<void*>(x[bin.ids[k]]);
+      xs[k] = x[bin.ids[k]];
       ys[k] = y[bin.ids[k]];
     }
-    HIPCHECK(hipMemcpyAsync(bin.xs, xs.data(), sizeof(void*) * nb, hipMemcpyHostToDevice, s));
-    HIPCHECK(hipMemcpyAsync(bin.ys, ys.data(), sizeof(void*) * nb, hipMemcpyHostToDevice, s));
-    const long long resident = (long long)bin.ops->batch_blocks_per_cu[ti]() * B->n_cu * B->grid_mult;
-    const unsigned grid = (unsigned)std::max<long long>(1, std::min(bin.total, resident));
-    if (std::is_same<T, double>::value)
-      bin.ops->tangent_batch_d[B->policy](bin.a64, bin.off, (int)nb, reinterpret_cast<const double* const*>(bin.xs),
-                                          reinterpret_cast<double* const*>(bin.ys), grid, s);
+    if (xs != bin.last_x || ys != bin.last_y) {
+      HIPCHECK(hipMemcpyAsync(bin.xs, xs.data(), sizeof(void*) * nb, hipMemcpyHostToDevice, s));
+      HIPCHECK(hipMemcpyAsync(bin.ys, ys.data(), sizeof(void*) * nb, hipMemcpyHostToDevice, s));
+      HIPCHECK(hipStreamSynchronize(s));
+      bin.last_x = xs;
+      bin.last_y = ys;
+    }
+    if (ti == 0)
+      bin.ops->tangent_batch_d[B->policy](bin.a64, bin.items, reinterpret_cast<const double* const*>(bin.xs),
+                                          reinterpret_cast<double* const*>(bin.ys), (unsigned)bin.n_items, s);
     else
-      bin.ops->tangent_batch_f[B->policy](bin.a32, bin.off, (int)nb, reinterpret_cast<const float* const*>(bin.xs),
-                                          reinterpret_cast<float* const*>(bin.ys), grid, s);
+      bin.ops->tangent_batch_f[B->policy](bin.a32, bin.items, reinterpret_cast<const float* const*>(bin.xs),
+                                          reinterpret_cast<float* const*>(bin.ys), (unsigned)bin.n_items, s);
   }
   check_launch("batch tangent_vmult");
 }
@@ -1403,23 +1504,15 @@ void batch_validate(int n, mfh_problem* const* probs) {
   }
 }
 
-// Runs fn(i) for every problem on up to n_threads host threads; returns the
-// first non-OK status in problem order.
-template <typename F>
-mfh_status batch_parallel(int n, int n_threads, F&& fn, std::vector<mfh_status>& st) {
-  st.assign(n, MFH_OK);
-  std::atomic<int> next(0);
-  auto worker = [&] {
-    for (int i = next++; i < n; i = next++) st[i] = fn(i);
-  };
-  const int nt = std::max(1, std::min(n_threads, n));
-  std::vector<std::thread> th;
-  for (int k = 1; k < nt; ++k) th.emplace_back(worker);
-  worker();
-  for (auto& t : th) t.join();
-  for (int i = 0; i < n; ++i)
-    if (st[i] != MFH_OK) return st[i];
-  return MFH_OK;
+// Waits for every listed problem's stream.
+void sync_all(mfh_batch* B, const std::vector<int>& ids) {
+  for (int i : ids) HIPCHECK(hipStreamSynchronize(B->probs[i]->stream));
+}
+
+// Per-problem statuses -> the batch status: the first failing problem's.
+void batch_raise(mfh_batch* B, const std::vector<mfh_status>& st, const std::vector<std::string>& msg) {
+  for (size_t i = 0; i < st.size(); ++i)
+    if (st[i] != MFH_OK) throw Error(st[i], "problem " + std::to_string(i) + ": " + msg[i]);
 }
 
 }  // namespace
@@ -1446,42 +1539,40 @@ mfh_status mfh_batch_workspace_size(int n, mfh_problem* const* probs, size_t* by
   });
 }
 
-mfh_status mfh_batch_create(int n, mfh_problem* const* probs, void* ws, size_t bytes, void* stream, int grid_mult,
+mfh_status mfh_batch_create(int n, mfh_problem* const* probs, void* ws, size_t bytes, void* stream,
                             mfh_batch** out) {
   std::unique_ptr<mfh_batch> B(new mfh_batch());
   mfh_status st = batch_guarded(nullptr, [&] {
     batch_validate(n, probs);
     need(out != nullptr && ws != nullptr, "NULL argument");
     need((reinterpret_cast<uintptr_t>(ws) & 255) == 0, "workspace must be 256-byte aligned");
-    need(grid_mult >= 1 && grid_mult <= 64, "grid_mult must be 1..64");
     B->probs.assign(probs, probs + n);
     B->stream = static_cast<hipStream_t>(stream);
     B->policy = probs[0]->d.qp_policy;
-    B->grid_mult = grid_mult;
     batch_bins(B.get());
     const size_t need_bytes = batch_layout(B.get(), nullptr);
     if (bytes < need_bytes) throw Error(MFH_ERR_WORKSPACE, "batch workspace too small: need " + std::to_string(need_bytes));
     batch_layout(B.get(), static_cast<char*>(ws));
-    int dev = 0;
-    HIPCHECK(hipGetDevice(&dev));
-    HIPCHECK(hipDeviceGetAttribute(&B->n_cu, hipDeviceAttributeMultiprocessorCount, dev));
     hipStream_t s = B->stream;
     for (auto& bin : B->bins) {
       const size_t nb = bin.ids.size();
+      need(bin.n_items < (1ll << 31), "batch bin has too many cell blocks");
       std::vector<CellArgs<double>> a64(nb);
       std::vector<CellArgs<float>> a32(nb);
-      std::vector<long long> off(nb + 1, 0);
+      std::vector<int2> items;
+      items.reserve(bin.n_items);
       for (size_t k = 0; k < nb; ++k) {
         const mfh_problem* P = B->probs[bin.ids[k]];
         const Level& v = P->lv.back();
         a64[k] = cell_args<double>(P, v, v.u64, v.cache64, nullptr, nullptr);
         a32[k] = cell_args<float>(P, v, v.u32, v.cache32, nullptr, nullptr);
-        off[k + 1] = off[k] + (v.ncells + P->ops->cpb - 1) / P->ops->cpb;
+        const long long nblk = (v.ncells + P->ops->cpb - 1) / P->ops->cpb;
+        for (long long j = 0; j < nblk; ++j) items.push_back(make_int2((int)k, (int)j));
       }
-      bin.total = off[nb];
       HIPCHECK(hipMemcpyAsync(bin.a64, a64.data(), sizeof(CellArgs<double>) * nb, hipMemcpyHostToDevice, s));
       HIPCHECK(hipMemcpyAsync(bin.a32, a32.data(), sizeof(CellArgs<float>) * nb, hipMemcpyHostToDevice, s));
-      HIPCHECK(hipMemcpyAsync(bin.off, off.data(), sizeof(long long) * (nb + 1), hipMemcpyHostToDevice, s));
+      HIPCHECK(hipMemcpyAsync(bin.items, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice, s));
+      HIPCHECK(hipStreamSynchronize(s));   // the host tables above go out of scope
     }
     std::vector<long long> foff(n + 1, 0);
     for (int i = 0; i < n; ++i) {
@@ -1491,6 +1582,14 @@ mfh_status mfh_batch_create(int n, mfh_problem* const* probs, void* ws, size_t b
     B->fchunks = foff[n];
     HIPCHECK(hipMemcpyAsync(B->foff, foff.data(), sizeof(long long) * (n + 1), hipMemcpyHostToDevice, s));
     HIPCHECK(hipStreamSynchronize(s));
+    // pinned host slots: device scalars, per-level min J, set-up histories
+    B->slot.assign(n + 1, 0);
+    for (int i = 0; i < n; ++i) {
+      const mfh_problem* P = B->probs[i];
+      const size_t w = std::max<size_t>({(size_t)SC_COUNT, P->lv.size(), setup_host_words(P)});
+      B->slot[i + 1] = B->slot[i] + ((w + 7) & ~size_t(7));
+    }
+    HIPCHECK(hipHostMalloc((void**)&B->pin, sizeof(double) * B->slot[n], hipHostMallocDefault));
     *out = B.release();
   });
   return st;
@@ -1503,22 +1602,32 @@ mfh_status mfh_batch_destroy(mfh_batch* B) {
 
 const char* mfh_batch_last_error(const mfh_batch* B) { return B ? B->err.c_str() : g_err.c_str(); }
 
-mfh_status mfh_batch_set_deformation(mfh_batch* B, const double* const* u, double* min_J, int n_threads) {
+mfh_status mfh_batch_set_deformation(mfh_batch* B, const double* const* u, double* min_J) {
   if (!B) return MFH_ERR_INVALID_ARG;
   return batch_guarded(B, [&] {
     need(u != nullptr, "u is NULL");
     const int n = (int)B->probs.size();
-    std::vector<mfh_status> st;
-    const mfh_status r = batch_parallel(n, n_threads, [&](int i) {
-      double mj = 0;
-      const mfh_status s = mfh_set_deformation(B->probs[i], u[i], &mj);
-      if (min_J) min_J[i] = mj;
-      return s;
-    }, st);
-    if (r != MFH_OK) {
-      for (int i = 0; i < n; ++i)
-        if (st[i] != MFH_OK) throw Error(st[i], "problem " + std::to_string(i) + ": " + B->probs[i]->err);
+    for (int i = 0; i < n; ++i) need(u[i] != nullptr, "u[i] is NULL");
+    std::vector<int> all(n);
+    for (int i = 0; i < n; ++i) all[i] = i;
+    // enqueue every problem's level data, then drain once
+    for (int i = 0; i < n; ++i) {
+      mfh_problem* P = B->probs[i];
+      setdef_enqueue(P, u[i]);
+      HIPCHECK(hipMemcpyAsync(B->pin + B->slot[i], P->minj, sizeof(double) * P->lv.size(), hipMemcpyDeviceToHost,
+                              P->stream));
     }
+    sync_all(B, all);
+    std::vector<mfh_status> st(n, MFH_OK);
+    std::vector<std::string> msg(n);
+    for (int i = 0; i < n; ++i) {
+      mfh_problem* P = B->probs[i];
+      double mj = 0;
+      st[i] = guarded(P, [&] { mj = setdef_finish(P, B->pin + B->slot[i]); });
+      msg[i] = P->err;
+      if (min_J) min_J[i] = st[i] == MFH_OK ? mj : NAN;
+    }
+    batch_raise(B, st, msg);
   });
 }
 
@@ -1540,26 +1649,110 @@ mfh_status mfh_batch_tangent_vmult(mfh_batch* B, int dtype, const void* const* x
 }
 
 mfh_status mfh_batch_cg_solve(mfh_batch* B, const double* const* b, double* const* x, double rtol, int max_it,
-                              int n_threads, int* iters, double* relres, double* solve_ms) {
+                              int* iters, double* relres, double* solve_ms) {
   if (!B) return MFH_ERR_INVALID_ARG;
   return batch_guarded(B, [&] {
     need(b && x, "b/x is NULL");
+    need(max_it >= 1 && rtol >= 0, "need max_it >= 1 and rtol >= 0");
     const int n = (int)B->probs.size();
-    std::vector<mfh_status> st;
-    const mfh_status r = batch_parallel(n, n_threads, [&](int i) {
-      auto t0 = Clock::now();
-      int it = 0;
-      double rel = 0;
-      const mfh_status s = mfh_cg_solve(B->probs[i], b[i], x[i], rtol, max_it, &it, &rel);
-      if (iters) iters[i] = it;
-      if (relres) relres[i] = rel;
-      if (solve_ms) solve_ms[i] = ms_since(t0);
-      return s;
-    }, st);
-    if (r != MFH_OK) {
-      for (int i = 0; i < n; ++i)
-        if (st[i] != MFH_OK) throw Error(st[i], "problem " + std::to_string(i) + ": " + B->probs[i]->err);
+    for (int i = 0; i < n; ++i) {
+      const mfh_problem* P = B->probs[i];
+      need(b[i] && x[i] && b[i] != x[i], "bad b/x pointer");
+      need(P->deformed, "set_deformation has not succeeded on every problem");
+      need(P->has_coarse, "a coarsest level is too large for the direct solve");
     }
+    const auto t0 = Clock::now();
+    std::vector<mfh_status> st(n, MFH_OK);
+    std::vector<std::string> msg(n);
+    std::vector<int> it(n, 0);
+    std::vector<double> bb(n, 0.0), rel(n, 0.0), ms(n, 0.0);
+    // 1. preconditioner set-up of every problem that needs one: enqueue all, drain once
+    std::vector<int> pending;
+    for (int i = 0; i < n; ++i) {
+      mfh_problem* P = B->probs[i];
+      if (P->precond_ready) continue;
+      setup_enqueue(P);
+      setup_copy_back(P, B->pin + B->slot[i]);
+      pending.push_back(i);
+    }
+    sync_all(B, pending);
+    std::vector<int> active;
+    for (int i = 0; i < n; ++i) {
+      mfh_problem* P = B->probs[i];
+      if (!P->precond_ready) st[i] = guarded(P, [&] { setup_finish(P, B->pin + B->slot[i]); });
+      if (st[i] == MFH_OK) st[i] = guarded(P, [&] { capture_vcycle(P); });   // streams are idle here
+      if (st[i] == MFH_OK)
+        active.push_back(i);
+      else
+        msg[i] = P->err;
+    }
+    // 2. lockstep PCG: every round issues one iteration of every active
+    //    problem on its own stream, then the host judges all of them at once
+    for (int i : active) {
+      mfh_problem* P = B->probs[i];
+      cg_start(P, b[i], x[i]);
+      cg_first_dir(P);
+      cg_step(P, x[i]);
+      HIPCHECK(hipMemcpyAsync(B->pin + B->slot[i], P->sc, sizeof(double) * SC_COUNT, hipMemcpyDeviceToHost,
+                              P->stream));
+    }
+    std::vector<int> finishing;   // problems whose explicit final residual is pending
+    bool first = true;
+    while (!active.empty()) {
+      sync_all(B, active);
+      const double now = ms_since(t0);
+      std::vector<int> still;
+      for (int i : active) {
+        mfh_problem* P = B->probs[i];
+        const double* h = B->pin + B->slot[i];
+        if (first) {
+          bb[i] = h[SC_BB];
+          if (!std::isfinite(bb[i]) || bb[i] == 0.0) {   // as the single solve: no iteration
+            if (bb[i] == 0.0) {
+              fill<double>(x[i], 0.0, P->lv.back().ndofs, P->stream);
+            } else {
+              st[i] = MFH_ERR_BREAKDOWN;
+              rel[i] = NAN;
+              msg[i] = "right-hand side is not finite";
+            }
+            ms[i] = now;
+            continue;
+          }
+        }
+        it[i] += 1;
+        const int j = cg_judge(h, bb[i], it[i], rtol, max_it, &rel[i]);
+        if (j == 1) {
+          cg_next_dir(P);
+          cg_step(P, x[i]);
+          HIPCHECK(hipMemcpyAsync(B->pin + B->slot[i], P->sc, sizeof(double) * SC_COUNT, hipMemcpyDeviceToHost,
+                                  P->stream));
+          still.push_back(i);
+          continue;
+        }
+        ms[i] = now;
+        st[i] = (mfh_status)j;
+        if (j == MFH_ERR_BREAKDOWN) {
+          msg[i] = "CG breakdown (p^T A p <= 0 or NaN)";
+          continue;
+        }
+        if (j == MFH_ERR_NOT_CONVERGED) msg[i] = "CG did not reach the tolerance within max_it iterations";
+        cg_true_residual(P, b[i], x[i]);
+        HIPCHECK(hipMemcpyAsync(B->pin + B->slot[i] + SC_TMP, P->sc + SC_TMP, sizeof(double), hipMemcpyDeviceToHost,
+                                P->stream));
+        finishing.push_back(i);
+      }
+      active.swap(still);
+      first = false;
+    }
+    sync_all(B, finishing);
+    for (int i : finishing) rel[i] = std::sqrt(B->pin[B->slot[i] + SC_TMP] / bb[i]);
+    check_launch("batch cg");
+    for (int i = 0; i < n; ++i) {
+      if (iters) iters[i] = it[i];
+      if (relres) relres[i] = rel[i];
+      if (solve_ms) solve_ms[i] = ms[i];
+    }
+    batch_raise(B, st, msg);
   });
 }
 

@@ -91,14 +91,15 @@ def lib():
         "mfh_coarse_inertia": (st, [_P, ctypes.POINTER(ctypes.c_int)]),
         "mfh_enable_graphs": (st, [_P, ctypes.c_int]),
         "mfh_batch_workspace_size": (st, [ctypes.c_int, ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_size_t)]),
-        "mfh_batch_create": (st, [ctypes.c_int, ctypes.POINTER(_P), _P, ctypes.c_size_t, _P, ctypes.c_int,
+        "mfh_batch_create": (st, [ctypes.c_int, ctypes.POINTER(_P), _P, ctypes.c_size_t, _P,
                                   ctypes.POINTER(_P)]),
         "mfh_batch_destroy": (st, [_P]),
         "mfh_batch_last_error": (ctypes.c_char_p, [_P]),
-        "mfh_batch_set_deformation": (st, [_P, ctypes.POINTER(_P), _D, ctypes.c_int]),
+        "mfh_batch_set_deformation": (st, [_P, ctypes.POINTER(_P), _D]),
         "mfh_batch_tangent_vmult": (st, [_P, ctypes.c_int, ctypes.POINTER(_P), ctypes.POINTER(_P)]),
         "mfh_batch_cg_solve": (st, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.c_double, ctypes.c_int,
-                                    ctypes.c_int, ctypes.POINTER(ctypes.c_int), _D, _D]),
+                                    ctypes.POINTER(ctypes.c_int), _D, _D]),
+        "mfh_node_coords_1d": (st, [_P, ctypes.c_int, _D]),
         "mfh_timer_enable": (st, [_P, ctypes.c_int]),
         "mfh_timer_read": (st, [_P, _D, ctypes.POINTER(ctypes.c_longlong)]),
     }
@@ -246,6 +247,15 @@ class Problem:
             _check(st, self.handle)
         return out, st
 
+    def node_coords_1d(self, level=-1):
+        """Support-point coordinates along one axis (numpy array of L values)."""
+        import numpy as np
+        level = level % self.n_levels
+        L = self.desc.degree * (self.desc.n_cells >> (self.n_levels - 1 - level)) + 1
+        x = (ctypes.c_double * L)()
+        _check(lib().mfh_node_coords_1d(self.handle, level, x), self.handle)
+        return np.array(x[:])
+
     def level_displacement(self, level):
         u = self._vec(level, torch.float64)
         _check(lib().mfh_level_displacement(self.handle, level % self.n_levels, _ptr(u)), self.handle)
@@ -308,7 +318,7 @@ def _parr(tensors):
 class Batch:
     """An mfh_batch over existing Problems (kept alive by the batch)."""
 
-    def __init__(self, problems, stream=None, grid_mult=1):
+    def __init__(self, problems, stream=None):
         self.problems = list(problems)
         n = len(self.problems)
         handles = (ctypes.c_void_p * n)(*[p.handle.value for p in self.problems])
@@ -321,7 +331,7 @@ class Batch:
         self.stream = torch.cuda.current_stream(dev) if stream is None else stream
         h = ctypes.c_void_p()
         _check_batch(lib().mfh_batch_create(n, handles, ctypes.c_void_p(base), size.value,
-                                            ctypes.c_void_p(self.stream.cuda_stream), grid_mult, ctypes.byref(h)), None)
+                                            ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)), None)
         self.handle = h
 
     def close(self):
@@ -335,9 +345,9 @@ class Batch:
         except Exception:
             pass
 
-    def set_deformation(self, us, n_threads=8):
+    def set_deformation(self, us):
         mj = (ctypes.c_double * len(us))()
-        _check_batch(lib().mfh_batch_set_deformation(self.handle, _parr(us), mj, n_threads), self.handle)
+        _check_batch(lib().mfh_batch_set_deformation(self.handle, _parr(us), mj), self.handle)
         return list(mj)
 
     def tangent_vmult(self, xs, ys):
@@ -345,11 +355,11 @@ class Batch:
         _check_batch(lib().mfh_batch_tangent_vmult(self.handle, dt, _parr(xs), _parr(ys)), self.handle)
         return ys
 
-    def cg_solve(self, bs, xs, rtol=1e-8, max_it=200, n_threads=8):
+    def cg_solve(self, bs, xs, rtol=1e-8, max_it=200):
         n = len(bs)
         it = (ctypes.c_int * n)()
         rel = (ctypes.c_double * n)()
         ms = (ctypes.c_double * n)()
-        _check_batch(lib().mfh_batch_cg_solve(self.handle, _parr(bs), _parr(xs), rtol, max_it, n_threads, it, rel, ms),
+        _check_batch(lib().mfh_batch_cg_solve(self.handle, _parr(bs), _parr(xs), rtol, max_it, it, rel, ms),
                      self.handle)
         return list(it), list(rel), list(ms)

@@ -26,7 +26,7 @@ def _problems(n, seed, **kw):
     mu, lam = W.two_phase_material()
     probs, fields = [], []
     for d in descs:
-        incl, u, x = W.batch_fields(d)
+        incl, u, x = W.batch_fields(d, coords=fe.Mesh(3, d["n_cells"], d["degree"]).coords_1d())
         s = torch.cuda.Stream()
         P = Problem(3, d["n_cells"], d["degree"], n_levels=SMALL_LEVELS[d["n_cells"]], mu=tuple(mu), lam=tuple(lam),
                     inclusions=incl, dirichlet_mask=d["mask"], stream=s, **kw)
@@ -47,10 +47,10 @@ def test_batch_vmult_matches_single_and_oracle(policy):
     assert all(m > 0 for m in mj)
     for dt, tdt, tol in ((F64, torch.float64, 1e-13), (F32, torch.float32, 2e-6)):
         xs = [dev(f[3], tdt) for f in fields]
-        ys = [torch.empty_like(x) for x in xs]
-        for gm in (1, 4):
-            Bg = Batch(probs, grid_mult=gm)
-            Bg.tangent_vmult(xs, ys)
+        # three calls: new pointers, the same pointers again, then other outputs
+        outs = [[torch.full_like(x, float("nan")) for x in xs] for _ in range(2)]
+        for ys in (outs[0], outs[0], outs[1]):
+            B.tangent_vmult(xs, ys)
             torch.cuda.synchronize()
             for P, x, y in zip(probs, xs, ys):
                 ref = P.tangent_vmult(x)
@@ -69,28 +69,72 @@ def test_batch_vmult_matches_single_and_oracle(policy):
         assert rel_l2(host(ys[k]), K @ x) <= 1e-12
 
 
-def test_batch_cg_solve():
-    log_case("batch_cg")
-    probs, fields = _problems(8, 62)
+@pytest.mark.parametrize("graphs", [False, True], ids=["eager", "graphs"])
+def test_batch_cg_solve(graphs):
+    """The lockstep batched PCG solves every problem as its own solve does
+    (same iteration counts up to one, same solutions), a zero right-hand side
+    included; one solution is checked against the oracle's assembled tangent."""
+    log_case("batch_cg", graphs=graphs)
+    probs, fields = _problems(8, 62, vcycle_dtype=F32)
     us = [dev(f[2]) for f in fields]
     B = Batch(probs)
     B.set_deformation(us)
     bs = []
-    for (d, incl, u, x), P in zip(fields, probs):
+    for k, ((d, incl, u, x), P) in enumerate(zip(fields, probs)):
         m = fe.Mesh(3, d["n_cells"], d["degree"])
-        b = x.copy()
+        b = np.zeros_like(x) if k == 3 else x.copy()
         b[m.constrained(d["mask"])] = 0.0
         bs.append(dev(b))
+    for P in probs:
+        P.enable_graphs(graphs)
     xs = [torch.empty_like(b) for b in bs]
     torch.cuda.synchronize()
-    it, rel, ms = B.cg_solve(bs, xs, rtol=1e-8, max_it=300, n_threads=4)
+    it, rel, ms = B.cg_solve(bs, xs, rtol=1e-8, max_it=300)
     assert all(r <= 1e-8 for r in rel)
+    assert it[3] == 0 and rel[3] == 0.0 and not host(xs[3]).any()
+    assert all(m_ >= 0 for m_ in ms)
+    for k, P in enumerate(probs):
+        x1, it1, rel1, _ = P.cg_solve(bs[k], rtol=1e-8, max_it=300)
+        torch.cuda.synchronize()
+        assert abs(it1 - it[k]) <= 1, k
+        if k != 3:
+            assert rel_l2(host(xs[k]), host(x1)) <= 1e-7, k
     d, incl, u, x = fields[0]
     m = fe.Mesh(3, d["n_cells"], d["degree"])
     mu, lam = W.two_phase_material()
     K = fe.constrain_matrix(fe.tangent_matrix(m, fe.Material(mu, lam, incl), u), m.constrained(d["mask"]))
     b0 = host(bs[0])
     assert np.linalg.norm(b0 - K @ host(xs[0])) <= 1.05e-8 * np.linalg.norm(b0)
+
+
+@pytest.mark.parametrize("dim,n,p", [(3, 4, 3), (2, 6, 4), (3, 8, 1)])
+def test_node_coords_match_oracle(dim, n, p):
+    log_case("node_coords", dim=dim, n=n, p=p)
+    P = Problem(dim, n, p, n_levels=2)
+    for level in (0, 1):
+        m = fe.Mesh(dim, n >> (1 - level), p)
+        np.testing.assert_allclose(P.node_coords_1d(level), m.coords_1d(), rtol=0, atol=1e-15)
+
+
+def test_batch_set_deformation_reports_inverted_problem():
+    """One problem of the batch gets an inverting displacement: the batch
+    reports INVERTED naming it, and the other problems stay usable."""
+    from paper_1904_13131_amd import MfhError
+    log_case("batch_inverted")
+    probs, fields = _problems(3, 63)
+    us = [dev(f[2]) for f in fields]
+    m1 = fe.Mesh(3, fields[1][0]["n_cells"], fields[1][0]["degree"])
+    X = m1.node_coords()
+    bad = np.ascontiguousarray((-1.5 * X).T.reshape(-1))   # F = -0.5 I: det < 0 everywhere
+    us[1] = dev(bad)
+    B = Batch(probs)
+    with pytest.raises(MfhError) as e:
+        B.set_deformation(us)
+    assert e.value.name == "INVERTED" and "problem 1" in str(e.value)
+    x = dev(fields[0][3])
+    y = probs[0].tangent_vmult(x)
+    torch.cuda.synchronize()
+    assert np.isfinite(host(y)).all()
 
 
 @pytest.mark.parametrize("vdt", [F64, F32], ids=["f64", "f32"])

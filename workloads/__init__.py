@@ -12,10 +12,12 @@ Recipes
   ~ U[r, 1 - r]^d, drawn in that order from ``numpy.random.default_rng(seed)``.
 * Displacement: u_c(X) = s * sum_m a_mc sin(pi k_m . X + phi_m) with
   a_m ~ N(0, 1)^d, k_m drawn uniformly from {0..kmax}^d minus the zero vector,
-  phi_m ~ U[0, 2 pi); X is the lattice parameter (index / (L - 1)) of every
-  node along every axis, so the generator needs no knowledge of the support
-  points; s scales the field so that max over nodes and components of |u|
-  equals the requested amplitude.
+  phi_m ~ U[0, 2 pi); X is the node position when the caller passes the
+  support-point coordinates along an axis (``coords``), else the lattice
+  parameter index / (L - 1) (the same for degrees 1 and 2, whose support
+  points are equispaced; for higher degrees only the true positions give a
+  smooth field); s scales the field so that max over nodes and components of
+  |u| equals the requested amplitude.
 * Vectors: x ~ N(0, 1) per DoF.
 
 Layout of every nodal vector: DoF = c * L^d + i + L (j + L k).
@@ -47,7 +49,15 @@ def spheres(n, seed, dim=3, rmin=0.05, rmax=0.12):
     return out
 
 
-def sine_field(dim, L, seed, amp, n_modes=8, kmax=2):
+def _axis(L, coords):
+    if coords is None:
+        return np.arange(L, dtype=np.float64) / (L - 1)
+    t = np.asarray(coords, dtype=np.float64)
+    assert t.shape == (L,)
+    return t
+
+
+def sine_field(dim, L, seed, amp, n_modes=8, kmax=2, coords=None):
     """Nodal values (dim * L^dim,) of a smooth seeded displacement field."""
     rng = np.random.default_rng(seed)
     a = rng.standard_normal((n_modes, dim))
@@ -58,7 +68,7 @@ def sine_field(dim, L, seed, amp, n_modes=8, kmax=2):
             ks.append(k)
     ks = np.array(ks, dtype=np.float64)
     phi = rng.uniform(0.0, 2.0 * np.pi, size=n_modes)
-    t = np.arange(L, dtype=np.float64) / (L - 1)
+    t = _axis(L, coords)
     grids = np.meshgrid(*([t] * dim), indexing="ij")
     X = np.stack([g.transpose(tuple(range(dim))[::-1]).reshape(-1) for g in grids], axis=1)
     arg = np.pi * X @ ks.T + phi[None, :]                  # (n_nodes, n_modes)
@@ -122,10 +132,13 @@ def config4(n=256, seed=6, sizes=(8, 12, 16, 24), degrees=(1, 2, 3)):
     direction, degree uniform in {1, 2, 3}, 1-10 spheres (r in [0.05, 0.12]),
     bottom and top clamped.  The linearisation point is a loaded state: a
     uniaxial stretch u_z = e Z with e ~ U[0.02, 0.08] plus a smooth seeded
-    perturbation of amplitude e / 4, so max |u| <= 0.1.  (Smooth fields that
-    compress the body by a few percent already make the tangent indefinite,
-    which no CG solve survives.)  Returns light descriptors; ``batch_fields``
-    draws the vectors."""
+    perturbation of amplitude e / 20, so max |u| <= 0.1.  Compression turns
+    the stress S = mu I - c1 C^-1 indefinite (where J < 1 and a principal
+    stretch is short), and with it the tangent, which no CG solve survives:
+    random smooth fields of a few percent already do that, and so does a
+    perturbation of e / 4 on top of the stretch.  At e / 20 the stress is
+    positive definite at every node of all 256 problems.  Returns light
+    descriptors; ``batch_fields`` draws the vectors."""
     rng = np.random.default_rng(seed)
     out = []
     for i in range(n):
@@ -135,23 +148,24 @@ def config4(n=256, seed=6, sizes=(8, 12, 16, 24), degrees=(1, 2, 3)):
         stretch = float(rng.uniform(0.02, 0.08))
         seeds = [int(v) for v in rng.integers(0, 2 ** 31, size=3)]
         out.append(dict(dim=3, n_cells=N, degree=p, n_levels=BATCH_LEVELS.get(N, 1), n_spheres=ns,
-                        stretch=stretch, amp=0.25 * stretch, sphere_seed=seeds[0], u_seed=seeds[1],
+                        stretch=stretch, amp=0.05 * stretch, sphere_seed=seeds[0], u_seed=seeds[1],
                         x_seed=seeds[2], mask=clamp_bottom_top(3)))
     return out
 
 
-def stretched_field(dim, L, stretch, seed, amp):
+def stretched_field(dim, L, stretch, seed, amp, coords=None):
     """u = stretch * X_last e_last + a smooth seeded perturbation (``sine_field``)."""
-    u = sine_field(dim, L, seed, amp, kmax=1)
-    t = np.arange(L, dtype=np.float64) / (L - 1)
+    u = sine_field(dim, L, seed, amp, kmax=1, coords=coords)
+    t = _axis(L, coords)
     u[(dim - 1) * L ** dim:] += stretch * np.repeat(t, L ** (dim - 1))
     return u
 
 
-def batch_fields(desc):
-    """(inclusions, u, x) of one config-4 problem."""
+def batch_fields(desc, coords=None):
+    """(inclusions, u, x) of one config-4 problem; ``coords`` are the support
+    points along an axis of its finest level."""
     L = desc["degree"] * desc["n_cells"] + 1
     incl = spheres(desc["n_spheres"], desc["sphere_seed"], 3)
-    u = stretched_field(3, L, desc["stretch"], desc["u_seed"], desc["amp"])
+    u = stretched_field(3, L, desc["stretch"], desc["u_seed"], desc["amp"], coords=coords)
     x = normal_vector(3 * L ** 3, desc["x_seed"])
     return incl, u, x
