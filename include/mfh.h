@@ -78,11 +78,16 @@ enum { MFH_QP_RECOMPUTE = 0, MFH_QP_CACHE_F = 1, MFH_QP_CACHE_T2 = 2 };
 /* Scatter of cell results into the output vector: ATOMIC (one hardware float
  * atomic per cell node; summation order varies run to run), COLOR (2^dim
  * launches over cells of equal coordinate parity, plain read-modify-write,
- * deterministic) or TILE (one block per tile of cells: tile nodes staged in
+ * deterministic), TILE (one block per tile of cells: tile nodes staged in
  * LDS, contributions summed there, global atomics only on tile faces shared
- * with a neighbouring tile; order varies).  The choice affects tangent_vmult
- * only; all other cell kernels use ATOMIC when TILE is selected. */
-enum { MFH_SCATTER_ATOMIC = 0, MFH_SCATTER_COLOR = 1, MFH_SCATTER_TILE = 2 };
+ * with a neighbouring tile; order varies) or ELEMENT (the cell kernel stores
+ * every cell's nodal results in an element buffer, a second kernel sums the
+ * at most 2^dim cell contributions of every node in a fixed order and writes
+ * each output entry once: deterministic, no atomics, no separate output
+ * fill; the workspace grows by dim * (p+1)^dim * cells of the finest level
+ * doubles).  The choice affects tangent_vmult only; all other cell kernels
+ * use ATOMIC when TILE or ELEMENT is selected. */
+enum { MFH_SCATTER_ATOMIC = 0, MFH_SCATTER_COLOR = 1, MFH_SCATTER_TILE = 2, MFH_SCATTER_ELEMENT = 3 };
 
 typedef struct mfh_problem mfh_problem;
 
@@ -315,9 +320,11 @@ mfh_status mfh_batch_cg_solve(mfh_batch* batch, const double* const* b, double* 
 
 /* ---- Kernel timers (measurement of the operator kernel) ---- */
 
-/* enable != 0: from now on every cell-kernel launch of mfh_tangent_vmult is
- * bracketed by HIP events on the problem's stream (the output fill is not
- * included); enable == 0 stops recording.  Either call resets the totals. */
+/* enable != 0: from now on the cell kernels of every mfh_tangent_vmult are
+ * bracketed by HIP events on the problem's stream (the output fill of the
+ * atomic, colour and tile scatters is not included; with the ELEMENT scatter
+ * the bracket holds the cell kernel and the node-sum kernel); enable == 0
+ * stops recording.  Either call resets the totals. */
 mfh_status mfh_timer_enable(mfh_problem* problem, int enable);
 /* Synchronises and returns the summed duration (ms) and the number of the
  * timed cell-kernel launches since the last mfh_timer_enable. */

@@ -619,7 +619,16 @@ __device__ __forceinline__ void tangent_block(const CellArgs<T>& a, const T* __r
 
   T out[DIM][N1];
   SF::template backward<DIM>(gx, out, lds, pen, cl, act, a.tb);
-  if (a.color < 0) {
+  if (a.elem != nullptr) {
+    // element buffer: one coalesced store per (component, node) across the block's cells
+    if (act) {
+      const int line = DIM == 3 ? N1 * (p0 + N1 * p1) : N1 * p0;
+#pragma unroll
+      for (int c = 0; c < DIM; ++c)
+#pragma unroll
+        for (int k = 0; k < N1; ++k) a.elem[((long long)c * G::NV + line + k) * a.ncells + cp.e] = out[c][k];
+    }
+  } else if (a.color < 0) {
     // The x-neighbour of this cell (same pencil) sits in the previous lane when
     // both are in one wave: its last x-node is this cell's first one.  Pass it
     // over and let one lane add the sum, saving a third of the atomics.
@@ -635,6 +644,67 @@ __device__ __forceinline__ void tangent_block(const CellArgs<T>& a, const T* __r
   } else {
     scatter<DIM, N1, T>(y, a, cp, act, out);
   }
+}
+
+// Second pass of the ELEMENT scatter: y at every node is the sum of the
+// element-buffer entries of the (at most 2^dim) cells containing it, in a
+// fixed order; constrained entries take x (mask_in = 1) or 0.  One thread per
+// node of an (i, j) plane; blockIdx.y is the plane k, blockIdx.z the
+// component.  j = t / L comes from a multiply-high by magic = ceil(2^32 / L),
+// exact for t < L^2 while L^3 < 2^32.
+template <int DIM, int P, typename T>
+__global__ void __launch_bounds__(kBlock) k_elem_gather(CellArgs<T> a, unsigned magic) {
+  constexpr int N1 = P + 1;
+  constexpr int NV = Geo<DIM, N1>::NV;
+  const int N = a.N, L = a.L;
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= L * L) return;
+  const int j = (int)__umulhi((unsigned)t, magic);
+  const int i = t - j * L;
+  const int k = blockIdx.y;
+  const int c = blockIdx.z;
+  const long long gi = c * a.nn + t + (long long)L * L * k;
+  if (node_faces(i, j, k, L, DIM) & a.fmask[c]) {
+    a.y[gi] = a.mask_in ? a.x[gi] : T(0);
+    return;
+  }
+  int ce[3][2], cn[3][2], m[3];
+  const int idx[3] = {i, j, k};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if (d >= DIM) {
+      ce[d][0] = 0;
+      cn[d][0] = 0;
+      ce[d][1] = 0;
+      cn[d][1] = 0;
+      m[d] = 1;
+      continue;
+    }
+    const int q = idx[d] / P, rem = idx[d] - q * P;
+    const bool inner = rem != 0;
+    // two candidates: (q - 1, P) and (q, 0) on a cell corner line, else (q, rem)
+    const bool has_lo = !inner && q > 0, has_hi = inner || q < N;
+    ce[d][0] = has_lo ? q - 1 : q;
+    cn[d][0] = has_lo ? P : rem;
+    ce[d][1] = q;
+    cn[d][1] = 0;
+    m[d] = (has_lo && has_hi) ? 2 : 1;
+  }
+  const T* base = a.elem + (long long)c * NV * a.ncells;
+  T acc = 0;
+#pragma unroll
+  for (int zz = 0; zz < (DIM == 3 ? 2 : 1); ++zz)
+#pragma unroll
+    for (int yy = 0; yy < 2; ++yy)
+#pragma unroll
+      for (int xx = 0; xx < 2; ++xx) {
+        if (xx < m[0] && yy < m[1] && zz < m[2]) {
+          const int e = ce[0][xx] + N * (ce[1][yy] + N * ce[2][zz]);
+          const int n = cn[0][xx] + N1 * (cn[1][yy] + N1 * cn[2][zz]);
+          acc += base[(long long)n * a.ncells + e];
+        }
+      }
+  a.y[gi] = acc;
 }
 
 // Tangent vmult: y += K x over the cells of this launch (y pre-filled).

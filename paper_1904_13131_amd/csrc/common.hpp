@@ -42,6 +42,8 @@ struct CellArgs {
   const T* x;           // input vector
   T* y;                 // output vector
   double* blockmin;     // per-block min J (cache build)
+  T* elem;              // element buffer (ELEMENT scatter): value of node n, component c of
+                        // cell e at (c * (p+1)^dim + n) * ncells + e; null: scatter into y
   int mask_in;          // 1: constrained entries of x read as zero (K_c); 0: read as given
 };
 

@@ -23,6 +23,9 @@ struct OpFns {
                              double* const* ys, unsigned n_items, hipStream_t);
   void (*tangent_batch_f[3])(const CellArgs<float>* args, const int2* items, const float* const* xs,
                              float* const* ys, unsigned n_items, hipStream_t);
+  // second pass of the ELEMENT scatter
+  void (*elem_gather_d)(const CellArgs<double>&, hipStream_t);
+  void (*elem_gather_f)(const CellArgs<float>&, hipStream_t);
   void (*coarse_assemble)(const CellArgs<double>&, const int* fmap, long long nf, double* K,
                           unsigned grid, hipStream_t);
   int cpb;        // cells per block of the pencil kernels

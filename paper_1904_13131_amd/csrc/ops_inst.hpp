@@ -59,6 +59,13 @@ struct OpInst {
                             unsigned n_items, hipStream_t s) {
     hipLaunchKernelGGL((k_tangent_batch<DIM, P, T, POL>), dim3(n_items), dim3(kBlock), 0, s, args, items, xs, ys);
   }
+  template <typename T>
+  static void elem_gather(const CellArgs<T>& a, hipStream_t s) {
+    const unsigned plane = (unsigned)a.L * (unsigned)a.L;
+    const unsigned magic = (unsigned)((((unsigned long long)1 << 32) + (unsigned)a.L - 1) / (unsigned)a.L);
+    const dim3 grid((plane + kBlock - 1) / kBlock, DIM == 3 ? a.L : 1, DIM);
+    hipLaunchKernelGGL((k_elem_gather<DIM, P, T>), grid, dim3(kBlock), 0, s, a, magic);
+  }
   static void residual(const CellArgs<double>& a, unsigned grid, hipStream_t s) {
     hipLaunchKernelGGL((k_residual<DIM, P>), dim3(grid), dim3(kBlock), 0, s, a);
   }
@@ -86,6 +93,8 @@ struct OpInst {
         {&tiles<double>, &tiles<float>},
         {&tangent_batch<double, POL_R>, &tangent_batch<double, POL_CF>, &tangent_batch<double, POL_C2>},
         {&tangent_batch<float, POL_R>, &tangent_batch<float, POL_CF>, &tangent_batch<float, POL_C2>},
+        &elem_gather<double>,
+        &elem_gather<float>,
         &coarse_assemble,
         Geo<DIM, P + 1>::CPB,
         kBlock / (DIM == 3 ? (P + 1) * (P + 1) * (P + 1) : (P + 1) * (P + 1)),

@@ -129,6 +129,7 @@ struct mfh_problem {
   double* Kinv = nullptr;
   double *gj_P = nullptr, *gj_C = nullptr, *gj_R = nullptr, *crf = nullptr, *czf = nullptr;
   int* flag = nullptr;
+  double* elem = nullptr;            // element buffer of the ELEMENT scatter (finest level size)
   std::vector<int> h_fmap, h_dof_of;
   bool deformed = false;
   bool precond_ready = false;        // diagonals, lambda_max, coarse inverse built
@@ -174,6 +175,8 @@ void validate(const mfh_desc* d) {
   if (d->dim != 2 && d->dim != 3) bad("dim must be 2 or 3");
   if (d->degree < 1 || d->degree > kMaxDeg) bad("degree must be 1..4");
   if (d->n_cells < 1) bad("n_cells must be >= 1");
+  // 32-bit lattice indexing: L = degree * n_cells + 1 with L^3 < 2^32, cells < 2^31
+  if ((long long)d->degree * d->n_cells + 1 > 1600) bad("degree * n_cells + 1 must be <= 1600");
   if (d->n_levels < 1 || d->n_levels > 12) bad("n_levels must be 1..12");
   if (d->n_cells % (1 << (d->n_levels - 1)) != 0) bad("n_cells must be divisible by 2^(n_levels-1)");
   if (d->n_materials < 1 || d->n_materials > 2) bad("n_materials must be 1 or 2");
@@ -187,7 +190,7 @@ void validate(const mfh_desc* d) {
   }
   if (d->dirichlet_mask >> (2 * d->dim * d->dim)) bad("dirichlet_mask has bits beyond 2*dim*dim");
   if (d->qp_policy < 0 || d->qp_policy > 2) bad("qp_policy must be 0..2");
-  if (d->scatter < MFH_SCATTER_ATOMIC || d->scatter > MFH_SCATTER_TILE) bad("bad scatter mode");
+  if (d->scatter < MFH_SCATTER_ATOMIC || d->scatter > MFH_SCATTER_ELEMENT) bad("bad scatter mode");
   if (d->vcycle_dtype != MFH_F32 && d->vcycle_dtype != MFH_F64) bad("bad vcycle_dtype");
   if (d->cheb_degree < 1 || d->cheb_degree > 16) bad("cheb_degree must be 1..16");
   if (d->n_smooth < 1 || d->n_smooth > 8) bad("n_smooth must be 1..8");
@@ -337,6 +340,9 @@ size_t layout(mfh_problem* P, char* base) {
   P->crf = b.take<double>(std::max<long long>(1, P->nf));
   P->czf = b.take<double>(std::max<long long>(1, P->nf));
   P->flag = b.take<int>(2);
+  size_t nodes_per_cell = 1;
+  for (int k = 0; k < d.dim; ++k) nodes_per_cell *= (size_t)(d.degree + 1);
+  P->elem = d.scatter == MFH_SCATTER_ELEMENT ? b.take<double>((size_t)d.dim * nodes_per_cell * top.ncells) : nullptr;
   return b.off + 256;
 }
 
@@ -402,6 +408,7 @@ struct Sel<double> {
   static void run_tile(const OpFns* o, int pol, const CellArgs<double>& a, unsigned g, hipStream_t s) {
     o->tangent_tile_d[pol](a, g, s);
   }
+  static void elem_gather(const OpFns* o, const CellArgs<double>& a, hipStream_t s) { o->elem_gather_d(a, s); }
   static Band<double> band(const DevBand& b) { return b.get<double>(); }
 };
 template <>
@@ -414,6 +421,7 @@ struct Sel<float> {
   static void run_tile(const OpFns* o, int pol, const CellArgs<float>& a, unsigned g, hipStream_t s) {
     o->tangent_tile_f[pol](a, g, s);
   }
+  static void elem_gather(const OpFns* o, const CellArgs<float>& a, hipStream_t s) { o->elem_gather_f(a, s); }
   static Band<float> band(const DevBand& b) { return b.get<float>(); }
 };
 
@@ -440,10 +448,18 @@ void timer_mark(mfh_problem* P) {
 template <typename T>
 void vmult(mfh_problem* P, int l, const T* x, T* y, int mask_in = 1) {
   const Level& v = P->lv[l];
-  fill_dirichlet<T>(y, mask_in ? x : nullptr, v.ndofs, v.lt, P->stream);
   CellArgs<T> a = cell_args<T>(P, v, Sel<T>::u(v), Sel<T>::cache(v), x, y);
   a.mask_in = mask_in;
   const int cpb = P->ops->cpb;
+  if (P->d.scatter == MFH_SCATTER_ELEMENT) {   // cell kernel into the element buffer, then the node sums
+    a.elem = reinterpret_cast<T*>(P->elem);
+    timer_mark(P);
+    Sel<T>::run(P->ops, P->d.qp_policy, a, (unsigned)((v.ncells + cpb - 1) / cpb), P->stream);
+    Sel<T>::elem_gather(P->ops, a, P->stream);
+    timer_mark(P);
+    return;
+  }
+  fill_dirichlet<T>(y, mask_in ? x : nullptr, v.ndofs, v.lt, P->stream);
   timer_mark(P);
   if (P->d.scatter == MFH_SCATTER_TILE) {
     const int ti = std::is_same<T, double>::value ? 0 : 1;

@@ -17,7 +17,7 @@ STATUS = {0: "OK", -1: "INVALID_ARG", -2: "HIP", -3: "WORKSPACE", -4: "INVERTED"
           -5: "NOT_CONVERGED", -6: "BREAKDOWN", -7: "NOT_SPD"}
 F64, F32 = 0, 1
 QP_RECOMPUTE, QP_CACHE_F, QP_CACHE_T2 = 0, 1, 2
-SCATTER_ATOMIC, SCATTER_COLOR, SCATTER_TILE = 0, 1, 2
+SCATTER_ATOMIC, SCATTER_COLOR, SCATTER_TILE, SCATTER_ELEMENT = 0, 1, 2, 3
 
 
 class MfhError(RuntimeError):

@@ -47,7 +47,7 @@ def _oracle(name):
     return _ORACLE[name]
 
 
-@pytest.mark.parametrize("scatter", [0, 1, 2], ids=["atomic", "color", "tile"])
+@pytest.mark.parametrize("scatter", [0, 1, 2, 3], ids=["atomic", "color", "tile", "elem"])
 @pytest.mark.parametrize("policy", [0, 1, 2], ids=["R", "CF", "C2"])
 @pytest.mark.parametrize("name", list(CASES))
 def test_vmult_fp64(name, policy, scatter):
@@ -61,7 +61,7 @@ def test_vmult_fp64(name, policy, scatter):
     assert rel_l2(y, K @ w["x"]) <= 1e-12
 
 
-@pytest.mark.parametrize("scatter", [0, 2], ids=["atomic", "tile"])
+@pytest.mark.parametrize("scatter", [0, 2, 3], ids=["atomic", "tile", "elem"])
 @pytest.mark.parametrize("policy", [0, 1, 2], ids=["R", "CF", "C2"])
 @pytest.mark.parametrize("name", list(CASES))
 def test_vmult_fp32(name, policy, scatter):
@@ -87,15 +87,19 @@ def test_residual(name, scatter):
     assert np.all(r[cons] == 0.0)
 
 
-def test_color_scatter_is_deterministic():
+@pytest.mark.parametrize("scatter", [1, 3], ids=["color", "elem"])
+def test_deterministic_scatters(scatter):
+    """The colour and element scatters fix the summation order: repeated
+    applications are bitwise equal (FP64 and FP32)."""
     w = CASES["3d_q2"]
-    log_case("color_determinism", name="3d_q2")
-    P = device_problem(w, scatter=1)
+    log_case("determinism", name="3d_q2", scatter=scatter)
+    P = device_problem(w, scatter=scatter)
     P.set_deformation(dev(w["u"]))
-    x = dev(w["x"])
-    a = host(P.tangent_vmult(x))
-    b = host(P.tangent_vmult(x))
-    assert np.array_equal(a, b)
+    for dt in (torch.float64, torch.float32):
+        x = dev(w["x"], dt)
+        a = host(P.tangent_vmult(x))
+        b = host(P.tangent_vmult(x))
+        assert np.array_equal(a, b)
 
 
 def test_min_J_matches_oracle():
@@ -129,7 +133,7 @@ def _config2():
     return _C2
 
 
-@pytest.mark.parametrize("scatter", [0, 2], ids=["atomic", "tile"])
+@pytest.mark.parametrize("scatter", [0, 2, 3], ids=["atomic", "tile", "elem"])
 @pytest.mark.parametrize("policy", [0, 1, 2], ids=["R", "CF", "C2"])
 def test_config2_sampled_rows(policy, scatter):
     c = _config2()
