@@ -30,14 +30,16 @@ HBM_PEAK_GBS = 8000.0
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
 POLICIES = {0: "recompute", 1: "cache_F", 2: "cache_T2"}
 
-# Algorithmic flop counts: minimal sum factorisation of one
-# d-component field, 4 d^2 n^(d+1), plus the quadrature-point algebra per point.
-# HBM bytes per launch of the config-2 cell kernel from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE (scaled by a 256 MiB copy; profiles/tangent_vmult_q2_32cube_hbm_counters.md),
-# valid only for the kernel source they were taken on.
-TRAFFIC_SOURCE_SHA = "5ce735f120729aec"
-TRAFFIC = {"recompute/f64": 47457545, "cache_F/f64": 104571648, "cache_T2/f64": 155377258,
-           "recompute/f32": 26753497, "cache_F/f32": 55156583, "cache_T2/f32": 80341153}
+# Algorithmic flop counts: minimal sum factorisation of one d-component field,
+# 4 d^2 n^(d+1), plus the per-quadrature-point algebra.  Measured HBM bytes per
+# vmult of config 2 (cell kernel + node-sum kernel of the ELEMENT scatter) from
+# rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by a 256 MiB device copy (reads
+# x2.0, writes x1.0; profiles/tangent_vmult_q2_32cube_hbm_counters.md); valid
+# only for the kernel source they were taken on.
+TRAFFIC_SOURCE_SHA = "f71c09921f6870ff"
+TRAFFIC = {"recompute/f64/element": 65935806, "recompute/f32/element": 34143648,
+           "cache_F/f64/element": 123532654, "cache_F/f32/element": 62651445,
+           "cache_T2/f64/element": 174136611, "cache_T2/f32/element": 88777530}
 
 QP_FLOPS_3D = {0: 313, 1: 307, 2: 188}
 QP_FLOPS_2D = {0: 118, 1: 116, 2: 78}
@@ -60,29 +62,34 @@ def algorithmic_cost(dim, degree, n_cells, n_dofs, policy, word):
     return flops, nbytes
 
 
-def measured_traffic(policy, dtype):
+def measured_traffic(policy, dtype, scatter):
     import hashlib
     src = os.path.join(ROOT, "paper_1904_13131_amd", "csrc", "cellops.hpp")
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     if sha != TRAFFIC_SOURCE_SHA:
         return None
-    return TRAFFIC.get(f"{POLICIES[policy]}/{dtype}")
+    return TRAFFIC.get(f"{POLICIES[policy]}/{dtype}/{scatter}")
 
 
-def roofline(dim, degree, n_cells, n_dofs, policy, dtype, kernel_ms):
+def roofline(dim, degree, n_cells, n_dofs, policy, dtype, kernel_ms, scatter):
     word = 8 if dtype == "f64" else 4
-    traffic = measured_traffic(policy, dtype)
+    traffic = measured_traffic(policy, dtype, scatter)
     flops, nbytes = algorithmic_cost(dim, degree, n_cells, n_dofs, policy, word)
     t_hbm = nbytes / (HBM_PEAK_GBS * 1e9)
     t_alu = flops / (PEAK_TFLOPS[dtype] * 1e12)
     s = kernel_ms * 1e-3
+    timed = {"element": "cell kernel k_tangent + node-sum kernel k_elem_gather of one vmult (ELEMENT scatter)",
+             "atomic": "cell kernel k_tangent (atomic scatter; output fill excluded)",
+             "tile": "tile kernel k_tangent_tile (output fill excluded)",
+             "color": "the 2^d colour launches of k_tangent"}[scatter]
     if t_hbm >= t_alu:
         ach = nbytes / s / 1e9
         return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-                "traffic": traffic, "alg_bytes": nbytes, "alg_flops": flops}
+                "traffic": traffic, "alg_bytes": nbytes, "alg_flops": flops, "timed": timed}
     ach = flops / s / 1e12
     return {"bound": "alu", "achieved": ach, "peak": PEAK_TFLOPS[dtype], "unit": "TFLOP/s",
-            "frac": ach / PEAK_TFLOPS[dtype], "traffic": traffic, "alg_bytes": nbytes, "alg_flops": flops}
+            "frac": ach / PEAK_TFLOPS[dtype], "traffic": traffic, "alg_bytes": nbytes, "alg_flops": flops,
+            "timed": timed}
 
 
 def time_vmult(P, x, y, steps, warmup, cold=False, flush=None):
@@ -165,7 +172,7 @@ def newton_bench(w, n_cells=64, n_levels=5, stretch=0.1, n_steps=4):
     return out
 
 
-def batch_bench(policy=2, steps=20, warmup=3, n=256):
+def batch_bench(policy=2, steps=20, warmup=3, n=256, solve=True):
     """Config 4: 256 independent 3-D problems (N in {8, 12, 16, 24}, p in {1, 2, 3},
     1-10 spheres, loaded linearisation point).  Aggregate batched vmult DoFs/s in
     FP64 and FP32 against one launch per problem, and one Newton correction per
@@ -232,6 +239,12 @@ def batch_bench(policy=2, steps=20, warmup=3, n=256):
         print(f"[bench] batch vmult {name}: {ms_b:.3f} ms ({total / (ms_b * 1e-3):.3e} DoF/s), "
               f"one launch per problem {ms_l:.3f} ms", file=sys.stderr, flush=True)
         del ys
+    if not solve:
+        B.close()
+        for P in probs:
+            P.close()
+        torch.cuda.empty_cache()
+        return out
     # one Newton correction per problem: K du = -R(u), mixed-precision GMG-CG to 1e-8
     bs = [P.residual(u) for P, u in zip(probs, us)]      # on the problems' streams
     torch.cuda.synchronize()
@@ -276,9 +289,10 @@ def main(argv=None):
     ap.add_argument("--policies", default="0,1,2")
     ap.add_argument("--dtypes", default="f64,f32")
     ap.add_argument("--no-cold", action="store_true")
-    ap.add_argument("--scatter", type=int, default=0, help="0 atomic, 1 colour, 2 tile")
+    ap.add_argument("--scatter", type=int, default=-1, help="-1 auto (tuned table), 0 atomic, 1 colour, 2 tile, 3 element")
     ap.add_argument("--no-newton", action="store_true", help="skip the config-3 Newton-step measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the config-4 batched measurement")
+    ap.add_argument("--no-batch-solve", action="store_true", help="config 4: time the batched vmult only")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 256 MiB device copy (reference for HBM byte counters)")
     a = ap.parse_args(argv)
@@ -290,7 +304,8 @@ def main(argv=None):
     import torch
 
     import workloads as W
-    from paper_1904_13131_amd import Problem
+    from paper_1904_13131_amd import F32, F64, Problem
+    from paper_1904_13131_amd.mfh import SCATTER_NAMES
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     w = W.config2()
@@ -322,9 +337,11 @@ def main(argv=None):
             kms_cold = float("nan")
             if not a.no_cold:
                 _, kms_cold = time_vmult(P, x, y, max(5, a.steps // 5), 1, cold=True, flush=flush)
+            mode = SCATTER_NAMES[P.scatter_mode(-1, F64 if dt == "f64" else F32)]
             res[(pol, dt)] = dict(ms_per_step=ms, kernel_ms=kms, kernel_ms_cold=kms_cold,
-                                  dofs_per_s=n_dofs / (ms * 1e-3), kernel_dofs_per_s=n_dofs / (kms * 1e-3))
-            print(f"[bench] {POLICIES[pol]:9s} {dt}: {ms * 1e3:8.1f} us/vmult, kernel {kms * 1e3:8.1f} us "
+                                  dofs_per_s=n_dofs / (ms * 1e-3), kernel_dofs_per_s=n_dofs / (kms * 1e-3),
+                                  scatter=mode)
+            print(f"[bench] {POLICIES[pol]:9s} {dt} ({mode}): {ms * 1e3:8.1f} us/vmult, kernel {kms * 1e3:8.1f} us "
                   f"(cold {kms_cold * 1e3:8.1f} us), {n_dofs / (ms * 1e-3):.3e} DoF/s", file=sys.stderr, flush=True)
         del P
         torch.cuda.empty_cache()
@@ -351,10 +368,12 @@ def main(argv=None):
                                "matrix mu=1 nu=0.3 with 20 seeded spheres (r 0.05-0.12, 100x stiffer), smooth "
                                "seeded displacement amplitude 0.1; one FP64 tangent vmult per step",
                    "n_dofs": n_dofs, "cells": nc ** dim, "degree": deg, "qp_policy": POLICIES[best[0]],
-                   "scatter": {0: "atomic", 1: "colour", 2: "tile"}[a.scatter]},
-        "roofline": roofline(dim, deg, nc, n_dofs, best[0], "f64", r["kernel_ms"]),
+                   "scatter": ("auto: " if a.scatter < 0 else "") + r["scatter"]},
+        "roofline": roofline(dim, deg, nc, n_dofs, best[0], "f64", r["kernel_ms"], r["scatter"]),
         "fp32": {"value": res[best32]["dofs_per_s"], "unit": "DoF/s", "qp_policy": POLICIES[best32[0]],
-                 "roofline": roofline(dim, deg, nc, n_dofs, best32[0], "f32", res[best32]["kernel_ms"])},
+                 "scatter": res[best32]["scatter"],
+                 "roofline": roofline(dim, deg, nc, n_dofs, best32[0], "f32", res[best32]["kernel_ms"],
+                                      res[best32]["scatter"])},
         "variants": {f"{POLICIES[k[0]]}/{k[1]}": {kk: (round(v, 6) if isinstance(v, float) else v)
                                                  for kk, v in res[k].items()} for k in res},
     }
@@ -363,7 +382,7 @@ def main(argv=None):
     if not a.no_newton:
         out["newton_step"] = newton_bench(w)
     if not a.no_batch:
-        out["batched"] = batch_bench()
+        out["batched"] = batch_bench(solve=not a.no_batch_solve)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

@@ -85,9 +85,18 @@ enum { MFH_QP_RECOMPUTE = 0, MFH_QP_CACHE_F = 1, MFH_QP_CACHE_T2 = 2 };
  * at most 2^dim cell contributions of every node in a fixed order and writes
  * each output entry once: deterministic, no atomics, no separate output
  * fill; the workspace grows by dim * (p+1)^dim * cells of the finest level
- * doubles).  The choice affects tangent_vmult only; all other cell kernels
- * use ATOMIC when TILE or ELEMENT is selected. */
-enum { MFH_SCATTER_ATOMIC = 0, MFH_SCATTER_COLOR = 1, MFH_SCATTER_TILE = 2, MFH_SCATTER_ELEMENT = 3 };
+ * doubles).  AUTO takes, for every level and precision, the mode measured
+ * fastest on gfx950 for the problem's dimension, degree, qp policy and the
+ * level's cell count (a table built by the package's autotuner and compiled
+ * into the library).  The choice affects tangent_vmult only; all other cell
+ * kernels use ATOMIC when TILE or ELEMENT is selected. */
+enum {
+  MFH_SCATTER_AUTO = -1,
+  MFH_SCATTER_ATOMIC = 0,
+  MFH_SCATTER_COLOR = 1,
+  MFH_SCATTER_TILE = 2,
+  MFH_SCATTER_ELEMENT = 3
+};
 
 typedef struct mfh_problem mfh_problem;
 
@@ -114,7 +123,7 @@ typedef struct {
 } mfh_desc;
 
 /* Fills *desc with the paper's solver settings (degree 4, 2 steps, 30
- * iterations, [0.6, 1.2]), RECOMPUTE, ATOMIC, F32 V-cycle; geometry fields
+ * iterations, [0.6, 1.2]), RECOMPUTE, AUTO scatter, F32 V-cycle; geometry fields
  * are zeroed and must be set by the caller. */
 void mfh_desc_defaults(mfh_desc* desc);
 
@@ -225,6 +234,11 @@ mfh_status mfh_newton_solve(mfh_problem* problem, double* u_dev, const double* f
                             int n_steps, double cg_rtol, int cg_max_it, double du_tol,
                             double r_tol, int max_newton,
                             mfh_newton_record* records, int max_records, int* n_records);
+
+/* The scatter mode tangent_vmult uses on `level` in precision dtype (the
+ * descriptor's mode, or the tuned choice under MFH_SCATTER_AUTO) into *mode.
+ * Host only.  Errors: INVALID_ARG. */
+mfh_status mfh_scatter_mode(const mfh_problem* problem, int level, int dtype, int* mode);
 
 /* Coordinates of the support points along one axis of `level` (all axes
  * are alike): the L = degree * N + 1 lattice positions in [0, 1], the

@@ -15,6 +15,7 @@
 #include "mfh.h"
 #include "ops.hpp"
 #include "tables.hpp"
+#include "tuned.hpp"
 #include "vec.hpp"
 
 namespace mfh {
@@ -190,7 +191,7 @@ void validate(const mfh_desc* d) {
   }
   if (d->dirichlet_mask >> (2 * d->dim * d->dim)) bad("dirichlet_mask has bits beyond 2*dim*dim");
   if (d->qp_policy < 0 || d->qp_policy > 2) bad("qp_policy must be 0..2");
-  if (d->scatter < MFH_SCATTER_ATOMIC || d->scatter > MFH_SCATTER_ELEMENT) bad("bad scatter mode");
+  if (d->scatter < MFH_SCATTER_AUTO || d->scatter > MFH_SCATTER_ELEMENT) bad("bad scatter mode");
   if (d->vcycle_dtype != MFH_F32 && d->vcycle_dtype != MFH_F64) bad("bad vcycle_dtype");
   if (d->cheb_degree < 1 || d->cheb_degree > 16) bad("cheb_degree must be 1..16");
   if (d->n_smooth < 1 || d->n_smooth > 8) bad("n_smooth must be 1..8");
@@ -280,6 +281,14 @@ void build_host(mfh_problem* P) {
 }
 
 // Assigns every device buffer; returns the bytes used.
+// Scatter of the tangent vmult on level v in precision t (0: FP64, 1: FP32):
+// the descriptor's mode, or with MFH_SCATTER_AUTO the measured choice for
+// (dim, degree, precision, qp policy, cells of the level).
+int scatter_mode(const mfh_problem* P, const Level& v, int t) {
+  if (P->d.scatter != MFH_SCATTER_AUTO) return P->d.scatter;
+  return tuned_scatter(P->d.dim, P->d.degree, t, P->d.qp_policy, v.ncells);
+}
+
 size_t layout(mfh_problem* P, char* base) {
   const mfh_desc& d = P->d;
   Bump b;
@@ -342,7 +351,10 @@ size_t layout(mfh_problem* P, char* base) {
   P->flag = b.take<int>(2);
   size_t nodes_per_cell = 1;
   for (int k = 0; k < d.dim; ++k) nodes_per_cell *= (size_t)(d.degree + 1);
-  P->elem = d.scatter == MFH_SCATTER_ELEMENT ? b.take<double>((size_t)d.dim * nodes_per_cell * top.ncells) : nullptr;
+  bool any_elem = false;
+  for (const Level& v : P->lv)
+    for (int t = 0; t < 2; ++t) any_elem |= scatter_mode(P, v, t) == MFH_SCATTER_ELEMENT;
+  P->elem = any_elem ? b.take<double>((size_t)d.dim * nodes_per_cell * top.ncells) : nullptr;
   return b.off + 256;
 }
 
@@ -451,7 +463,8 @@ void vmult(mfh_problem* P, int l, const T* x, T* y, int mask_in = 1) {
   CellArgs<T> a = cell_args<T>(P, v, Sel<T>::u(v), Sel<T>::cache(v), x, y);
   a.mask_in = mask_in;
   const int cpb = P->ops->cpb;
-  if (P->d.scatter == MFH_SCATTER_ELEMENT) {   // cell kernel into the element buffer, then the node sums
+  const int mode = scatter_mode(P, v, std::is_same<T, double>::value ? 0 : 1);
+  if (mode == MFH_SCATTER_ELEMENT) {   // cell kernel into the element buffer, then the node sums
     a.elem = reinterpret_cast<T*>(P->elem);
     timer_mark(P);
     Sel<T>::run(P->ops, P->d.qp_policy, a, (unsigned)((v.ncells + cpb - 1) / cpb), P->stream);
@@ -461,10 +474,10 @@ void vmult(mfh_problem* P, int l, const T* x, T* y, int mask_in = 1) {
   }
   fill_dirichlet<T>(y, mask_in ? x : nullptr, v.ndofs, v.lt, P->stream);
   timer_mark(P);
-  if (P->d.scatter == MFH_SCATTER_TILE) {
+  if (mode == MFH_SCATTER_TILE) {
     const int ti = std::is_same<T, double>::value ? 0 : 1;
     Sel<T>::run_tile(P->ops, P->d.qp_policy, a, (unsigned)P->ops->tiles[ti](v.N), P->stream);
-  } else if (P->d.scatter == MFH_SCATTER_ATOMIC) {
+  } else if (mode == MFH_SCATTER_ATOMIC) {
     Sel<T>::run(P->ops, P->d.qp_policy, a, (unsigned)((v.ncells + cpb - 1) / cpb), P->stream);
   } else {
     for (int color = 0; color < (1 << P->d.dim); ++color) {
@@ -971,7 +984,7 @@ void mfh_desc_defaults(mfh_desc* d) {
   d->n_levels = 1;
   d->n_materials = 1;
   d->qp_policy = MFH_QP_RECOMPUTE;
-  d->scatter = MFH_SCATTER_ATOMIC;
+  d->scatter = MFH_SCATTER_AUTO;
   d->vcycle_dtype = MFH_F32;
   d->cheb_degree = 4;
   d->n_smooth = 2;
@@ -1243,6 +1256,16 @@ mfh_status mfh_newton_solve(mfh_problem* P, double* u, const double* fv, int n_s
   });
   if (n_rec) *n_rec = nrec;
   return st;
+}
+
+mfh_status mfh_scatter_mode(const mfh_problem* P, int level, int dtype, int* mode) {
+  if (!P) return MFH_ERR_INVALID_ARG;
+  return guarded(const_cast<mfh_problem*>(P), [&] {
+    check_level(P, level);
+    need(mode != nullptr, "mode is NULL");
+    need(dtype == MFH_F64 || dtype == MFH_F32, "dtype must be MFH_F64 or MFH_F32");
+    *mode = scatter_mode(P, P->lv[level], dtype == MFH_F64 ? 0 : 1);
+  });
 }
 
 mfh_status mfh_node_coords_1d(mfh_problem* P, int level, double* x) {

@@ -17,7 +17,8 @@ STATUS = {0: "OK", -1: "INVALID_ARG", -2: "HIP", -3: "WORKSPACE", -4: "INVERTED"
           -5: "NOT_CONVERGED", -6: "BREAKDOWN", -7: "NOT_SPD"}
 F64, F32 = 0, 1
 QP_RECOMPUTE, QP_CACHE_F, QP_CACHE_T2 = 0, 1, 2
-SCATTER_ATOMIC, SCATTER_COLOR, SCATTER_TILE, SCATTER_ELEMENT = 0, 1, 2, 3
+SCATTER_AUTO, SCATTER_ATOMIC, SCATTER_COLOR, SCATTER_TILE, SCATTER_ELEMENT = -1, 0, 1, 2, 3
+SCATTER_NAMES = {0: "atomic", 1: "color", 2: "tile", 3: "element"}
 
 
 class MfhError(RuntimeError):
@@ -100,6 +101,7 @@ def lib():
         "mfh_batch_cg_solve": (st, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.c_double, ctypes.c_int,
                                     ctypes.POINTER(ctypes.c_int), _D, _D]),
         "mfh_node_coords_1d": (st, [_P, ctypes.c_int, _D]),
+        "mfh_scatter_mode": (st, [_P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
         "mfh_timer_enable": (st, [_P, ctypes.c_int]),
         "mfh_timer_read": (st, [_P, _D, ctypes.POINTER(ctypes.c_longlong)]),
     }
@@ -123,7 +125,7 @@ def _darr(vals):
 
 
 def make_desc(dim, n_cells, degree, n_levels=1, mu=(1.0,), lam=(1.5,), inclusions=(), dirichlet_mask=0,
-              qp_policy=QP_RECOMPUTE, scatter=SCATTER_ATOMIC, vcycle_dtype=F32, cheb_degree=4, n_smooth=2,
+              qp_policy=QP_RECOMPUTE, scatter=SCATTER_AUTO, vcycle_dtype=F32, cheb_degree=4, n_smooth=2,
               eig_iters=30, cheb_lo=0.6, cheb_hi=1.2):
     """Builds an mfh_desc; the returned tuple keeps the host arrays alive."""
     d = Desc()
@@ -246,6 +248,12 @@ class Problem:
         if raise_on_error:
             _check(st, self.handle)
         return out, st
+
+    def scatter_mode(self, level=-1, dtype=F64):
+        """Scatter mode the vmult uses on a level (resolved when the descriptor says AUTO)."""
+        m = ctypes.c_int()
+        _check(lib().mfh_scatter_mode(self.handle, level % self.n_levels, dtype, ctypes.byref(m)), self.handle)
+        return m.value
 
     def node_coords_1d(self, level=-1):
         """Support-point coordinates along one axis (numpy array of L values)."""

@@ -47,7 +47,7 @@ def _oracle(name):
     return _ORACLE[name]
 
 
-@pytest.mark.parametrize("scatter", [0, 1, 2, 3], ids=["atomic", "color", "tile", "elem"])
+@pytest.mark.parametrize("scatter", [0, 1, 2, 3, -1], ids=["atomic", "color", "tile", "elem", "auto"])
 @pytest.mark.parametrize("policy", [0, 1, 2], ids=["R", "CF", "C2"])
 @pytest.mark.parametrize("name", list(CASES))
 def test_vmult_fp64(name, policy, scatter):
@@ -61,7 +61,7 @@ def test_vmult_fp64(name, policy, scatter):
     assert rel_l2(y, K @ w["x"]) <= 1e-12
 
 
-@pytest.mark.parametrize("scatter", [0, 2, 3], ids=["atomic", "tile", "elem"])
+@pytest.mark.parametrize("scatter", [0, 2, 3, -1], ids=["atomic", "tile", "elem", "auto"])
 @pytest.mark.parametrize("policy", [0, 1, 2], ids=["R", "CF", "C2"])
 @pytest.mark.parametrize("name", list(CASES))
 def test_vmult_fp32(name, policy, scatter):
