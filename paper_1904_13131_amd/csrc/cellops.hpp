@@ -653,19 +653,17 @@ __device__ __forceinline__ void tangent_block(const CellArgs<T>& a, const T* __r
 // component.  j = t / L comes from a multiply-high by magic = ceil(2^32 / L),
 // exact for t < L^2 while L^3 < 2^32.
 template <int DIM, int P, typename T>
-__global__ void __launch_bounds__(kBlock) k_elem_gather(CellArgs<T> a, unsigned magic) {
+__device__ __forceinline__ void elem_gather_node(const CellArgs<T>& a, const T* __restrict__ x, T* __restrict__ y,
+                                                 int t, int k, int c, unsigned magic) {
   constexpr int N1 = P + 1;
   constexpr int NV = Geo<DIM, N1>::NV;
   const int N = a.N, L = a.L;
-  const int t = blockIdx.x * kBlock + threadIdx.x;
   if (t >= L * L) return;
   const int j = (int)__umulhi((unsigned)t, magic);
   const int i = t - j * L;
-  const int k = blockIdx.y;
-  const int c = blockIdx.z;
   const long long gi = c * a.nn + t + (long long)L * L * k;
   if (node_faces(i, j, k, L, DIM) & a.fmask[c]) {
-    a.y[gi] = a.mask_in ? a.x[gi] : T(0);
+    y[gi] = a.mask_in ? x[gi] : T(0);
     return;
   }
   int ce[3][2], cn[3][2], m[3];
@@ -704,7 +702,32 @@ __global__ void __launch_bounds__(kBlock) k_elem_gather(CellArgs<T> a, unsigned 
           acc += base[(long long)n * a.ncells + e];
         }
       }
-  a.y[gi] = acc;
+  y[gi] = acc;
+}
+
+template <int DIM, int P, typename T>
+__global__ void __launch_bounds__(kBlock) k_elem_gather(CellArgs<T> a, unsigned magic) {
+  elem_gather_node<DIM, P, T>(a, a.x, a.y, blockIdx.x * kBlock + threadIdx.x, blockIdx.y, blockIdx.z, magic);
+}
+
+// Batched second pass: one workgroup per item (problem, plane k, component,
+// block of the plane) of the problems that use the ELEMENT scatter.
+
+template <int DIM, int P, typename T>
+__global__ void __launch_bounds__(kBlock) k_elem_gather_batch(const CellArgs<T>* __restrict__ args,
+                                                              const GatherItem* __restrict__ items,
+                                                              const T* const* __restrict__ xs,
+                                                              T* const* __restrict__ ys) {
+  using CArgs = const CellArgs<T> __attribute__((address_space(4)));
+  using CInt = const int __attribute__((address_space(4)));
+  using CPtrX = const T* const __attribute__((address_space(4)));
+  using CPtrY = T* const __attribute__((address_space(4)));
+  const CInt* it = (CInt*)(items + blockIdx.x);
+  const int p = it[0], kc = it[1], blk = it[2];
+  const unsigned magic = (unsigned)it[3];
+  const CellArgs<T>& a = *(const CellArgs<T>*)((CArgs*)args + p);
+  elem_gather_node<DIM, P, T>(a, ((CPtrX*)xs)[p], ((CPtrY*)ys)[p], blk * kBlock + threadIdx.x, kc >> 2, kc & 3,
+                              magic);
 }
 
 // Tangent vmult: y += K x over the cells of this launch (y pre-filled).

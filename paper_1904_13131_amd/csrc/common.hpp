@@ -47,6 +47,14 @@ struct CellArgs {
   int mask_in;          // 1: constrained entries of x read as zero (K_c); 0: read as given
 };
 
+// Work item of the batched node-sum kernel (ELEMENT scatter).
+struct GatherItem {
+  int p;            // problem index in the bin's argument table
+  int kc;           // plane k * 4 + component
+  int blk;          // block of kBlock nodes in the (i, j) plane
+  unsigned magic;   // ceil(2^32 / L) of the problem's lattice
+};
+
 // Lattice description for the vector kernels.
 struct Lattice {
   int L, dim;

@@ -26,6 +26,10 @@ struct OpFns {
   // second pass of the ELEMENT scatter
   void (*elem_gather_d)(const CellArgs<double>&, hipStream_t);
   void (*elem_gather_f)(const CellArgs<float>&, hipStream_t);
+  void (*elem_gather_batch_d)(const CellArgs<double>* args, const GatherItem* items, const double* const* xs,
+                              double* const* ys, unsigned n_items, hipStream_t);
+  void (*elem_gather_batch_f)(const CellArgs<float>* args, const GatherItem* items, const float* const* xs,
+                              float* const* ys, unsigned n_items, hipStream_t);
   void (*coarse_assemble)(const CellArgs<double>&, const int* fmap, long long nf, double* K,
                           unsigned grid, hipStream_t);
   int cpb;        // cells per block of the pencil kernels

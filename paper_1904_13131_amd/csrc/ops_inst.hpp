@@ -60,6 +60,11 @@ struct OpInst {
     hipLaunchKernelGGL((k_tangent_batch<DIM, P, T, POL>), dim3(n_items), dim3(kBlock), 0, s, args, items, xs, ys);
   }
   template <typename T>
+  static void elem_gather_batch(const CellArgs<T>* args, const GatherItem* items, const T* const* xs, T* const* ys,
+                                unsigned n_items, hipStream_t s) {
+    hipLaunchKernelGGL((k_elem_gather_batch<DIM, P, T>), dim3(n_items), dim3(kBlock), 0, s, args, items, xs, ys);
+  }
+  template <typename T>
   static void elem_gather(const CellArgs<T>& a, hipStream_t s) {
     const unsigned plane = (unsigned)a.L * (unsigned)a.L;
     const unsigned magic = (unsigned)((((unsigned long long)1 << 32) + (unsigned)a.L - 1) / (unsigned)a.L);
@@ -95,6 +100,8 @@ struct OpInst {
         {&tangent_batch<float, POL_R>, &tangent_batch<float, POL_CF>, &tangent_batch<float, POL_C2>},
         &elem_gather<double>,
         &elem_gather<float>,
+        &elem_gather_batch<double>,
+        &elem_gather_batch<float>,
         &coarse_assemble,
         Geo<DIM, P + 1>::CPB,
         kBlock / (DIM == 3 ? (P + 1) * (P + 1) * (P + 1) : (P + 1) * (P + 1)),

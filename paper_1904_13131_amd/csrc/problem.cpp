@@ -1413,16 +1413,19 @@ struct mfh_batch {
     void** xs = nullptr;
     void** ys = nullptr;
     long long n_items = 0;
+    mfh::GatherItem* g[2] = {nullptr, nullptr};   // node-sum items of the ELEMENT problems, per precision
+    long long n_g[2] = {0, 0};
     const mfh::OpFns* ops = nullptr;
     std::vector<const void*> last_x, last_y;   // pointer tables on the device (skip re-upload)
   };
   std::vector<Bin> bins;
+  // output fills of the problems on the atomic scatter, per precision (0 FP64, 1 FP32)
   mfh::FillItem<double>* f64 = nullptr;
   mfh::FillItem<float>* f32 = nullptr;
-  long long* foff = nullptr;
-  long long fchunks = 0;
-  std::vector<const void*> last_fx, last_fy;   // fill items on the device (per dtype slot 0/1)
-  int last_fill_dtype = -1;
+  long long* foff[2] = {nullptr, nullptr};
+  long long fchunks[2] = {0, 0};
+  std::vector<int> fill_ids[2];
+  std::vector<const void*> last_fx[2], last_fy[2];
   double* pin = nullptr;               // pinned host words, one slot per problem
   std::vector<size_t> slot;            // slot offsets into pin
   std::string err;
@@ -1434,6 +1437,16 @@ struct mfh_batch {
 namespace mfh {
 namespace {
 
+// The batch follows every problem's own scatter choice for its finest level:
+// ELEMENT problems write their element buffers and get a batched node-sum
+// pass, the others are scattered with atomics into a pre-filled output.
+bool batch_elem(const mfh_problem* P, int t) { return scatter_mode(P, P->lv.back(), t) == MFH_SCATTER_ELEMENT; }
+
+long long gather_blocks(const mfh_problem* P) {
+  const long long L = P->lv.back().L;
+  return ((L * L + kBlock - 1) / kBlock) * (P->d.dim == 3 ? L : 1) * P->d.dim;
+}
+
 size_t batch_layout(mfh_batch* B, char* base) {
   Bump b;
   b.base = base;
@@ -1442,18 +1455,26 @@ size_t batch_layout(mfh_batch* B, char* base) {
     bin.a64 = b.take<CellArgs<double>>(nb);
     bin.a32 = b.take<CellArgs<float>>(nb);
     bin.n_items = 0;
+    bin.n_g[0] = bin.n_g[1] = 0;
     for (int i : bin.ids) {
       const mfh_problem* P = B->probs[i];
       bin.n_items += (P->lv.back().ncells + P->ops->cpb - 1) / P->ops->cpb;
+      for (int t = 0; t < 2; ++t)
+        if (batch_elem(P, t)) bin.n_g[t] += gather_blocks(P);
     }
     bin.items = b.take<int2>(bin.n_items);
+    for (int t = 0; t < 2; ++t) bin.g[t] = b.take<GatherItem>(bin.n_g[t]);
     bin.xs = b.take<void*>(nb);
     bin.ys = b.take<void*>(nb);
   }
-  const size_t n = B->probs.size();
-  B->f64 = b.take<FillItem<double>>(n);
-  B->f32 = b.take<FillItem<float>>(n);
-  B->foff = b.take<long long>(n + 1);
+  for (int t = 0; t < 2; ++t) {
+    B->fill_ids[t].clear();
+    for (int i = 0; i < (int)B->probs.size(); ++i)
+      if (!batch_elem(B->probs[i], t)) B->fill_ids[t].push_back(i);
+    B->foff[t] = b.take<long long>(B->fill_ids[t].size() + 1);
+  }
+  B->f64 = b.take<FillItem<double>>(B->fill_ids[0].size());
+  B->f32 = b.take<FillItem<float>>(B->fill_ids[1].size());
   return b.off + 256;
 }
 
@@ -1478,24 +1499,30 @@ void batch_bins(mfh_batch* B) {
 template <typename T>
 void batch_vmult(mfh_batch* B, const void* const* x, void* const* y) {
   hipStream_t s = B->stream;
-  const size_t n = B->probs.size();
   const int ti = std::is_same<T, double>::value ? 0 : 1;
-  // fill items (outputs: 0, or x on constrained DoFs); uploaded only when the pointers change
-  std::vector<const void*> fx(x, x + n), fy(y, y + n);
-  FillItem<T>* fdev = ti == 0 ? reinterpret_cast<FillItem<T>*>(B->f64) : reinterpret_cast<FillItem<T>*>(B->f32);
-  if (B->last_fill_dtype != ti || fx != B->last_fx || fy != B->last_fy) {
-    std::vector<FillItem<T>> items(n);
-    for (size_t i = 0; i < n; ++i) {
-      const Level& v = B->probs[i]->lv.back();
-      items[i] = FillItem<T>{static_cast<T*>(y[i]), static_cast<const T*>(x[i]), v.lt, v.ndofs};
+  // output fill (0, or x on constrained DoFs) of the atomic-scatter problems;
+  // the fill table is uploaded only when the pointers change
+  const std::vector<int>& fid = B->fill_ids[ti];
+  if (!fid.empty()) {
+    std::vector<const void*> fx(fid.size()), fy(fid.size());
+    for (size_t k = 0; k < fid.size(); ++k) {
+      fx[k] = x[fid[k]];
+      fy[k] = y[fid[k]];
     }
-    HIPCHECK(hipMemcpyAsync(fdev, items.data(), sizeof(FillItem<T>) * n, hipMemcpyHostToDevice, s));
-    HIPCHECK(hipStreamSynchronize(s));   // the host table goes out of scope
-    B->last_fill_dtype = ti;
-    B->last_fx = fx;
-    B->last_fy = fy;
+    FillItem<T>* fdev = ti == 0 ? reinterpret_cast<FillItem<T>*>(B->f64) : reinterpret_cast<FillItem<T>*>(B->f32);
+    if (fx != B->last_fx[ti] || fy != B->last_fy[ti]) {
+      std::vector<FillItem<T>> items(fid.size());
+      for (size_t k = 0; k < fid.size(); ++k) {
+        const Level& v = B->probs[fid[k]]->lv.back();
+        items[k] = FillItem<T>{static_cast<T*>(y[fid[k]]), static_cast<const T*>(x[fid[k]]), v.lt, v.ndofs};
+      }
+      HIPCHECK(hipMemcpyAsync(fdev, items.data(), sizeof(FillItem<T>) * fid.size(), hipMemcpyHostToDevice, s));
+      HIPCHECK(hipStreamSynchronize(s));   // the host table goes out of scope
+      B->last_fx[ti] = fx;
+      B->last_fy[ti] = fy;
+    }
+    fill_dirichlet_batch<T>(fdev, B->foff[ti], (int)fid.size(), B->fchunks[ti], s);
   }
-  fill_dirichlet_batch<T>(fdev, B->foff, (int)n, B->fchunks, s);
   for (auto& bin : B->bins) {
     const size_t nb = bin.ids.size();
     std::vector<const void*> xs(nb), ys(nb);
@@ -1510,12 +1537,19 @@ void batch_vmult(mfh_batch* B, const void* const* x, void* const* y) {
       bin.last_x = xs;
       bin.last_y = ys;
     }
-    if (ti == 0)
+    if (ti == 0) {
       bin.ops->tangent_batch_d[B->policy](bin.a64, bin.items, reinterpret_cast<const double* const*>(bin.xs),
                                           reinterpret_cast<double* const*>(bin.ys), (unsigned)bin.n_items, s);
-    else
+      if (bin.n_g[0])
+        bin.ops->elem_gather_batch_d(bin.a64, bin.g[0], reinterpret_cast<const double* const*>(bin.xs),
+                                     reinterpret_cast<double* const*>(bin.ys), (unsigned)bin.n_g[0], s);
+    } else {
       bin.ops->tangent_batch_f[B->policy](bin.a32, bin.items, reinterpret_cast<const float* const*>(bin.xs),
                                           reinterpret_cast<float* const*>(bin.ys), (unsigned)bin.n_items, s);
+      if (bin.n_g[1])
+        bin.ops->elem_gather_batch_f(bin.a32, bin.g[1], reinterpret_cast<const float* const*>(bin.xs),
+                                     reinterpret_cast<float* const*>(bin.ys), (unsigned)bin.n_g[1], s);
+    }
   }
   check_launch("batch tangent_vmult");
 }
@@ -1598,29 +1632,48 @@ mfh_status mfh_batch_create(int n, mfh_problem* const* probs, void* ws, size_t b
       need(bin.n_items < (1ll << 31), "batch bin has too many cell blocks");
       std::vector<CellArgs<double>> a64(nb);
       std::vector<CellArgs<float>> a32(nb);
+      need(bin.n_g[0] < (1ll << 31) && bin.n_g[1] < (1ll << 31), "batch bin has too many node blocks");
       std::vector<int2> items;
       items.reserve(bin.n_items);
+      std::vector<GatherItem> g[2];
       for (size_t k = 0; k < nb; ++k) {
         const mfh_problem* P = B->probs[bin.ids[k]];
         const Level& v = P->lv.back();
         a64[k] = cell_args<double>(P, v, v.u64, v.cache64, nullptr, nullptr);
         a32[k] = cell_args<float>(P, v, v.u32, v.cache32, nullptr, nullptr);
+        if (batch_elem(P, 0)) a64[k].elem = P->elem;
+        if (batch_elem(P, 1)) a32[k].elem = reinterpret_cast<float*>(P->elem);
         const long long nblk = (v.ncells + P->ops->cpb - 1) / P->ops->cpb;
         for (long long j = 0; j < nblk; ++j) items.push_back(make_int2((int)k, (int)j));
+        const unsigned L = (unsigned)v.L;
+        const unsigned magic = (unsigned)((((unsigned long long)1 << 32) + L - 1) / L);
+        const int pblocks = (int)((L * L + kBlock - 1) / kBlock);
+        for (int t = 0; t < 2; ++t) {
+          if (!batch_elem(P, t)) continue;
+          for (int kk = 0; kk < (P->d.dim == 3 ? (int)L : 1); ++kk)
+            for (int c = 0; c < P->d.dim; ++c)
+              for (int blk = 0; blk < pblocks; ++blk) g[t].push_back(GatherItem{(int)k, kk * 4 + c, blk, magic});
+        }
       }
       HIPCHECK(hipMemcpyAsync(bin.a64, a64.data(), sizeof(CellArgs<double>) * nb, hipMemcpyHostToDevice, s));
       HIPCHECK(hipMemcpyAsync(bin.a32, a32.data(), sizeof(CellArgs<float>) * nb, hipMemcpyHostToDevice, s));
       HIPCHECK(hipMemcpyAsync(bin.items, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice, s));
+      for (int t = 0; t < 2; ++t)
+        if (!g[t].empty())
+          HIPCHECK(hipMemcpyAsync(bin.g[t], g[t].data(), sizeof(GatherItem) * g[t].size(), hipMemcpyHostToDevice, s));
       HIPCHECK(hipStreamSynchronize(s));   // the host tables above go out of scope
     }
-    std::vector<long long> foff(n + 1, 0);
-    for (int i = 0; i < n; ++i) {
-      const long long nd = B->probs[i]->lv.back().ndofs;
-      foff[i + 1] = foff[i] + (nd + kFillChunk - 1) / kFillChunk;
+    for (int t = 0; t < 2; ++t) {
+      const std::vector<int>& fid = B->fill_ids[t];
+      std::vector<long long> foff(fid.size() + 1, 0);
+      for (size_t k = 0; k < fid.size(); ++k) {
+        const long long nd = B->probs[fid[k]]->lv.back().ndofs;
+        foff[k + 1] = foff[k] + (nd + kFillChunk - 1) / kFillChunk;
+      }
+      B->fchunks[t] = foff.back();
+      HIPCHECK(hipMemcpyAsync(B->foff[t], foff.data(), sizeof(long long) * foff.size(), hipMemcpyHostToDevice, s));
+      HIPCHECK(hipStreamSynchronize(s));
     }
-    B->fchunks = foff[n];
-    HIPCHECK(hipMemcpyAsync(B->foff, foff.data(), sizeof(long long) * (n + 1), hipMemcpyHostToDevice, s));
-    HIPCHECK(hipStreamSynchronize(s));
     // pinned host slots: device scalars, per-level min J, set-up histories
     B->slot.assign(n + 1, 0);
     for (int i = 0; i < n; ++i) {
