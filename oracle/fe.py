@@ -218,10 +218,27 @@ def element_residual(mesh, mat, u, cells):
 
 
 def element_tangent(mesh, mat, u, cells):
+    """K_e[c, i, a, k, b] = sum_q w_q G[q, a, I] A[c, q, i, I, k, L] G[q, b, L].
+
+    Evaluated as two contractions (trial gradient first, then one matrix
+    product over the pair (q, I)); the single four-operand einsum computes the
+    same sum in another order and is two orders of magnitude slower at degree 4.
+    """
     F = deformation_gradient(mesh, u, cells)
     mu, lam = mat.params(mesh, cells)
     A = material.dP_dF(F, mu, lam)                                     # (nc, nQ, d, d, d, d)
-    return np.einsum("q,qaI,cqiIkL,qbL->ciakb", mesh.W, mesh.G, A, mesh.G, optimize=True)
+    nc, nq, d = A.shape[0], A.shape[1], A.shape[2]
+    nA = mesh.G.shape[1]
+    AG = np.einsum("cqiIkL,qbL->cqiIkb", A, mesh.G)                    # (nc, nQ, d, d, d, nA)
+    X = AG.transpose(0, 2, 1, 3, 4, 5).reshape(nc, d, nq * d, d * nA)  # sum index (q, I)
+    WG = (mesh.W[:, None, None] * mesh.G).transpose(1, 0, 2).reshape(nA, nq * d)
+    return np.matmul(WG, X).reshape(nc, d, nA, d, nA)
+
+
+def _cell_chunk(mesh, chunk):
+    """Cells per chunk, bounded so that one chunk's intermediates stay near 256 MB."""
+    per_cell = mesh.G.shape[0] * mesh.d ** 3 * mesh.G.shape[1] * 8
+    return max(1, min(chunk, (1 << 28) // per_cell))
 
 
 def _chunks(n, size):
@@ -244,7 +261,7 @@ def tangent_matrix(mesh, mat, u, chunk=1024):
     """Assembled (unconstrained) tangent as scipy CSR."""
     nd = mesh.d * mesh.nA
     rows, cols, vals = [], [], []
-    for cells in _chunks(mesh.n_cells, chunk):
+    for cells in _chunks(mesh.n_cells, _cell_chunk(mesh, chunk)):
         Ke = element_tangent(mesh, mat, u, cells).reshape(len(cells), nd, nd)
         dofs = mesh.cell_dofs(cells).reshape(len(cells), nd)
         rows.append(np.repeat(dofs, nd, axis=1).reshape(-1))
@@ -270,6 +287,7 @@ def vmult_ebe(mesh, mat, u, x, constrained=None, cells=None, chunk=512):
     y = np.zeros(mesh.n_dofs)
     cells_all = mesh.all_cells() if cells is None else np.asarray(cells)
     nd = mesh.d * mesh.nA
+    chunk = _cell_chunk(mesh, chunk)
     for s in range(0, len(cells_all), chunk):
         cells = cells_all[s:s + chunk]
         Ke = element_tangent(mesh, mat, u, cells).reshape(len(cells), nd, nd)
