@@ -172,6 +172,113 @@ def newton_bench(w, n_cells=64, n_levels=5, stretch=0.1, n_steps=4):
     return out
 
 
+def _config5_problem(n_cells, n_levels, level_field):
+    import workloads as W
+    from paper_1904_13131_amd import F32, Problem
+    mu, lam = W.two_phase_material()
+    return Problem(3, n_cells, 4, n_levels=n_levels, mu=tuple(mu), lam=tuple(lam), inclusions=W.spheres(200, 7),
+                   dirichlet_mask=W.clamp_bottom_top(3), qp_policy=2, vcycle_dtype=F32, level_field=level_field)
+
+
+def _config5_newton(n_cells, n_levels, strain, n_steps, level_field, cg_max_it=500):
+    """Newton load stepping to `strain` (negative: compression) in n_steps increments."""
+    import torch
+    P = _config5_problem(n_cells, n_levels, level_field)
+    u = torch.zeros(P.n_dofs(), dtype=torch.float64, device="cuda")
+    fv = np.zeros((6, 3))
+    fv[5][2] = strain
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    recs, st, done = [], 0, 0.0
+    name = f"{'compression' if strain < 0 else 'tension'} {abs(strain):.0%}, {['nodal', 'vertex'][level_field]}"
+    for k in range(1, n_steps + 1):   # one call per load step (progress lines between them)
+        rk, st = P.newton_solve(u, fv * (k / n_steps), n_steps=1, cg_max_it=cg_max_it, raise_on_error=False)
+        for r in rk:
+            r["load_fraction"] = (k - 1 + r["load_fraction"]) / n_steps
+        recs += rk
+        print(f"[bench] config5 {name} load step {k}: {len(rk)} Newton steps, CG iterations "
+              f"{[r['cg_iters'] for r in rk]}, status {st}, {time.perf_counter() - t0:.1f} s",
+              file=sys.stderr, flush=True)
+        if st != 0:
+            break
+        done = k / n_steps
+    total = time.perf_counter() - t0
+    ok = [r for r in recs if np.isfinite(r["residual_after"]) and r["cg_relres"] <= 1e-8]
+    P.close()
+    del P
+    torch.cuda.empty_cache()
+    return {"loading": name, "level_field": ["nodal", "vertex"][level_field], "status": int(st),
+            "wall_s": round(total, 2), "newton_steps": len(recs), "strain_reached": done * strain,
+            "cutbacks": max([r["cutbacks"] for r in recs] or [0]),
+            "median_newton_step_ms": float(np.median([r["setup_ms"] + r["residual_ms"] + r["solve_ms"]
+                                                      for r in ok])) if ok else None,
+            "cg_iters_converged_steps": [r["cg_iters"] for r in ok],
+            "max_coarse_negative": max([r["coarse_negative"] for r in recs] or [0]),
+            "min_J_last": recs[-1]["min_J"] if recs else None}
+
+
+def config5_bench(n_cells=48, n_levels=5, n_steps=5, steps=10):
+    """Config 5: 3-D Q4 48^3 (21.6 M DoFs), 5^3 Gauss points, 200 spheres (seed 7),
+    config-2 material law, bottom/top clamped, levels 3^3..48^3, FP32 V(2,2)
+    Chebyshev(4) GMG under FP64 CG.  Level vmults (FP32 on three levels, FP64 on
+    the finest) and the FP64 residual at a smooth start state; then Newton to
+    20 % compression (paper-literal nodal level fields) and to 20 % tension with
+    vertex level fields."""
+    import torch
+
+    import workloads as W
+    from paper_1904_13131_amd import F32, F64
+    from paper_1904_13131_amd.mfh import SCATTER_NAMES
+    P = _config5_problem(n_cells, n_levels, 0)
+    n = P.n_dofs()
+    out = {"workload": f"3-D Q4 {n_cells}^3 ({n:,} DoFs), 125 Gauss points per cell, 200 spheres (seed 7), "
+                       f"config-2 material, clamped bottom/top, {n_steps} load steps, levels "
+                       f"{n_cells >> (n_levels - 1)}^3..{n_cells}^3, FP32 V(2,2) Chebyshev(4) GMG under FP64 CG "
+                       f"to 1e-8 (at most 500 iterations), FP64 dense coarse solve", "qp_policy": "cache_T2"}
+    u0 = torch.as_tensor(W.sine_field(3, 4 * n_cells + 1, 4, 0.01, kmax=1, coords=P.node_coords_1d()),
+                         device="cuda")
+    P.set_deformation(u0)
+    lv = {}
+    for level in range(n_levels - 1, max(-1, n_levels - 4), -1):
+        nl = P.n_dofs(level)
+        x = torch.as_tensor(W.normal_vector(nl, 5), device="cuda")
+        for dt, tdt, code in (("f32", torch.float32, F32), ("f64", torch.float64, F64)):
+            if dt == "f64" and level != n_levels - 1:
+                continue
+            xx = x.to(tdt)
+            y = torch.empty_like(xx)
+            for _ in range(3):
+                P.tangent_vmult(xx, y, level=level)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(P.stream)
+            for _ in range(steps):
+                P.tangent_vmult(xx, y, level=level)
+            e1.record(P.stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            lv[f"level{level}_{dt}"] = {"n_dofs": nl, "ms": ms, "dofs_per_s": nl / (ms * 1e-3),
+                                        "scatter": SCATTER_NAMES[P.scatter_mode(level, code)]}
+            print(f"[bench] config5 vmult level {level} {dt}: {ms:.3f} ms, {nl / (ms * 1e-3):.3e} DoF/s",
+                  file=sys.stderr, flush=True)
+    r = torch.empty_like(u0)
+    for _ in range(2):
+        P.residual(u0, r)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(P.stream)
+    for _ in range(steps):
+        P.residual(u0, r)
+    e1.record(P.stream)
+    torch.cuda.synchronize()
+    out["level_vmults"] = lv
+    out["residual_fp64_ms"] = e0.elapsed_time(e1) / steps
+    P.close()
+    del P
+    torch.cuda.empty_cache()
+    out["newton"] = [_config5_newton(n_cells, n_levels, -0.2, n_steps, 0),
+                     _config5_newton(n_cells, n_levels, +0.2, n_steps, 1)]
+    return out
+
+
 def batch_bench(policy=2, steps=20, warmup=3, n=256, solve=True):
     """Config 4: 256 independent 3-D problems (N in {8, 12, 16, 24}, p in {1, 2, 3},
     1-10 spheres, loaded linearisation point).  Aggregate batched vmult DoFs/s in
@@ -293,6 +400,7 @@ def main(argv=None):
     ap.add_argument("--no-newton", action="store_true", help="skip the config-3 Newton-step measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the config-4 batched measurement")
     ap.add_argument("--no-batch-solve", action="store_true", help="config 4: time the batched vmult only")
+    ap.add_argument("--config5", action="store_true", help="also run config 5 (Q4 48^3 Newton, minutes)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 256 MiB device copy (reference for HBM byte counters)")
     a = ap.parse_args(argv)
@@ -383,6 +491,8 @@ def main(argv=None):
         out["newton_step"] = newton_bench(w)
     if not a.no_batch:
         out["batched"] = batch_bench(solve=not a.no_batch_solve)
+    if a.config5:
+        out["config5"] = config5_bench()
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

@@ -98,6 +98,16 @@ enum {
   MFH_SCATTER_ELEMENT = 3
 };
 
+/* Displacement the coarser level operators are linearised about (Sec. 6
+ * restricts the fine displacement to every level without saying how):
+ * NODAL interpolates the finer level's field at the coarser support points,
+ * level by level; VERTEX takes the fine field's values at the coarser level's
+ * cell vertices and fills each coarse cell multilinearly.  The two agree for
+ * degree 1; for higher degrees NODAL reproduces more of the field, while
+ * VERTEX cannot overshoot between vertices, which keeps the coarse tangents of
+ * strongly heterogeneous bodies positive definite for longer under load. */
+enum { MFH_LEVEL_FIELD_NODAL = 0, MFH_LEVEL_FIELD_VERTEX = 1 };
+
 typedef struct mfh_problem mfh_problem;
 
 typedef struct {
@@ -120,10 +130,12 @@ typedef struct {
   int n_smooth;              /* Chebyshev applications pre and post (paper: 2), 1..8      */
   int eig_iters;             /* CG iterations for lambda_max (paper: 30), 1..200          */
   double cheb_lo, cheb_hi;   /* smoother interval factors (paper: 0.6, 1.2)              */
+  int level_field;           /* MFH_LEVEL_FIELD_*: displacement on the coarser levels     */
 } mfh_desc;
 
 /* Fills *desc with the paper's solver settings (degree 4, 2 steps, 30
- * iterations, [0.6, 1.2]), RECOMPUTE, AUTO scatter, F32 V-cycle; geometry fields
+ * iterations, [0.6, 1.2]), RECOMPUTE, AUTO scatter, F32 V-cycle, NODAL level
+ * fields; geometry fields
  * are zeroed and must be set by the caller. */
 void mfh_desc_defaults(mfh_desc* desc);
 

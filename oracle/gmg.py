@@ -11,7 +11,9 @@ deal.II's preconditioned CG as the outer solver.
 Readings taken where the paper is silent:
 
 * "restrict the displacement" = nodal interpolation of the finer field at the
-  coarser support points, applied recursively fine -> coarse;
+  coarser support points, applied recursively fine -> coarse (``"nodal"``);
+  the alternative ``"vertex"`` takes the values at the coarse cell vertices
+  and fills each coarse cell multilinearly;
 * the coarse level is solved exactly (dense LU) in FP64.  Linearised about the
   interpolated displacement, the coarse tangent can be indefinite when the
   coarse mesh does not resolve the material (the assumption of Sec. 6); the
@@ -61,6 +63,24 @@ def interpolation_1d(fine, coarse):
     return _eval_global_1d(fine, coarse.coords_1d())
 
 
+def vertex_interpolation_1d(fine, coarse):
+    """V1[I_c, I_f]: the coarse node's value is the linear interpolant, along
+    the axis, of the fine field's values at the two vertices of the coarse cell
+    that holds it (the vertices are fine lattice nodes)."""
+    Xf, Xc = fine.coords_1d(), coarse.coords_1d()
+    hc = 1.0 / coarse.N
+    V = np.zeros((len(Xc), len(Xf)))
+    for k, x in enumerate(Xc):
+        e = min(int(np.floor(x / hc + 1e-12)), coarse.N - 1)
+        t = (x - e * hc) / hc
+        lo = int(np.argmin(np.abs(Xf - e * hc)))
+        hi = int(np.argmin(np.abs(Xf - (e + 1) * hc)))
+        V[k, lo] += 1.0 - t
+        V[k, hi] += t
+    V[np.abs(V) < 1e-15] = 0.0
+    return V
+
+
 def _tensor(M1, d):
     """Tensor-product operator on node vectors (node = i + L j + L^2 k), applied
     per component (block diagonal over the d components)."""
@@ -75,8 +95,9 @@ def prolongation(coarse, fine):
     return _tensor(prolongation_1d(coarse, fine), fine.d)
 
 
-def interpolation(fine, coarse):
-    return _tensor(interpolation_1d(fine, coarse), fine.d)
+def interpolation(fine, coarse, level_field="nodal"):
+    M1 = interpolation_1d(fine, coarse) if level_field == "nodal" else vertex_interpolation_1d(fine, coarse)
+    return _tensor(M1, fine.d)
 
 
 # --- smoother pieces -------------------------------------------------------------
@@ -157,13 +178,13 @@ class Hierarchy:
     """
 
     def __init__(self, dim, n_coarse, degree, n_levels, mat, mask=0,
-                 cheb_degree=4, n_smooth=2, eig_iters=30, cheb_lo=0.6, cheb_hi=1.2):
+                 cheb_degree=4, n_smooth=2, eig_iters=30, cheb_lo=0.6, cheb_hi=1.2, level_field="nodal"):
         self.meshes = [fe.Mesh(dim, n_coarse * 2 ** l, degree) for l in range(n_levels)]
         self.mat = mat
         self.mask = mask
         self.cons = [m.constrained(mask) for m in self.meshes]
         self.P = [None] + [prolongation(self.meshes[l - 1], self.meshes[l]) for l in range(1, n_levels)]
-        self.I = [None] + [interpolation(self.meshes[l], self.meshes[l - 1]) for l in range(1, n_levels)]
+        self.I = [None] + [interpolation(self.meshes[l], self.meshes[l - 1], level_field) for l in range(1, n_levels)]
         self.cheb_degree = cheb_degree
         self.n_smooth = n_smooth
         self.eig_iters = eig_iters

@@ -197,6 +197,7 @@ void validate(const mfh_desc* d) {
   if (d->n_smooth < 1 || d->n_smooth > 8) bad("n_smooth must be 1..8");
   if (d->eig_iters < 1 || d->eig_iters > 200) bad("eig_iters must be 1..200");
   if (!(d->cheb_lo > 0) || !(d->cheb_hi > d->cheb_lo)) bad("need 0 < cheb_lo < cheb_hi");
+  if (d->level_field != MFH_LEVEL_FIELD_NODAL && d->level_field != MFH_LEVEL_FIELD_VERTEX) bad("bad level_field");
 }
 
 // Largest coarse level that gets the dense FP64 direct solve; problems with a
@@ -240,7 +241,19 @@ void build_host(mfh_problem* P) {
       std::vector<double> R1((size_t)c.L * v.L);
       for (int i = 0; i < v.L; ++i)
         for (int j = 0; j < c.L; ++j) R1[(size_t)j * v.L + i] = P1[(size_t)i * c.L + j];
-      const std::vector<double> I1 = eval_global_1d(v.N, d.degree, Xc);   // Lc x Lf
+      std::vector<double> I1;   // Lc x Lf: level displacement from this level to the coarser one
+      if (d.level_field == MFH_LEVEL_FIELD_NODAL) {
+        I1 = eval_global_1d(v.N, d.degree, Xc);
+      } else {   // values at the coarse cell's vertices (fine nodes 2pe, 2p(e+1)), linear in between
+        I1.assign((size_t)c.L * v.L, 0.0);
+        const double hc = 1.0 / c.N;
+        for (int J = 0; J < c.L; ++J) {
+          const int e = std::min(J / d.degree, c.N - 1);
+          const double t = (Xc[J] - e * hc) / hc;
+          I1[(size_t)J * v.L + 2 * d.degree * e] += 1.0 - t;
+          I1[(size_t)J * v.L + 2 * d.degree * (e + 1)] += t;
+        }
+      }
       v.P1.host = make_band(P1, v.L, c.L);
       v.R1.host = make_band(R1, c.L, v.L);
       v.I1.host = make_band(I1, c.L, v.L);
@@ -991,6 +1004,7 @@ void mfh_desc_defaults(mfh_desc* d) {
   d->eig_iters = 30;
   d->cheb_lo = 0.6;
   d->cheb_hi = 1.2;
+  d->level_field = MFH_LEVEL_FIELD_NODAL;
 }
 
 mfh_status mfh_workspace_size(const mfh_desc* desc, size_t* bytes) {

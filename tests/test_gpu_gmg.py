@@ -17,6 +17,11 @@ HIER = {
     "3d_q2": dict(dim=3, n_coarse=2, degree=2, n_levels=3, spheres=3, amp=0.01),
     "2d_q3": dict(dim=2, n_coarse=2, degree=3, n_levels=3, spheres=0, amp=0.01),
     "3d_q1": dict(dim=3, n_coarse=2, degree=1, n_levels=3, spheres=2, amp=0.01),
+    # loaded states (stretch of the last axis plus a small perturbation at the node positions)
+    "2d_q4_vertex": dict(dim=2, n_coarse=1, degree=4, n_levels=3, spheres=0, amp=0.0025, level_field="vertex",
+                         stretch=0.05),
+    "3d_q3_vertex": dict(dim=3, n_coarse=1, degree=3, n_levels=3, spheres=2, amp=0.0025, level_field="vertex",
+                         stretch=0.05),
 }
 _CACHE = {}
 
@@ -30,10 +35,14 @@ def _setup(name):
     incl = W.spheres(c["spheres"], 3, dim) if c["spheres"] else [(np.full(dim, 0.5), 0.3, 1)]
     mask = W.clamp_bottom_top(dim)
     mat = fe.Material(mu, lam, incl)
-    H = gmg.Hierarchy(dim, c["n_coarse"], c["degree"], c["n_levels"], mat, mask)
+    H = gmg.Hierarchy(dim, c["n_coarse"], c["degree"], c["n_levels"], mat, mask,
+                      level_field=c.get("level_field", "nodal"))
     fine = H.meshes[-1]
-    u = W.sine_field(dim, fine.L, 4, c["amp"], kmax=1)
-    u[H.cons[-1]] = 0.0
+    if "stretch" in c:
+        u = W.stretched_field(dim, fine.L, c["stretch"], 4, c["amp"], coords=fine.coords_1d())
+    else:
+        u = W.sine_field(dim, fine.L, 4, c["amp"], kmax=1)
+        u[H.cons[-1]] = 0.0
     H.set_deformation(u)
     b = W.normal_vector(fine.n_dofs, 5)
     b[H.cons[-1]] = 0.0
@@ -45,7 +54,8 @@ def _device(name, vdt, **kw):
     from paper_1904_13131_amd import Problem
     c, mu, lam, incl, mask, H, u, b = _setup(name)
     P = Problem(c["dim"], c["n_coarse"] * 2 ** (c["n_levels"] - 1), c["degree"], n_levels=c["n_levels"],
-                mu=tuple(mu), lam=tuple(lam), inclusions=incl, dirichlet_mask=mask, vcycle_dtype=vdt, **kw)
+                mu=tuple(mu), lam=tuple(lam), inclusions=incl, dirichlet_mask=mask, vcycle_dtype=vdt,
+                level_field=1 if c.get("level_field") == "vertex" else 0, **kw)
     P.set_deformation(dev(u))
     return P
 

@@ -32,6 +32,9 @@ CASES = {
                                  mask=W.face_bits(3, 0, 0, [0]) | W.face_bits(3, 1, 1, [1, 2]) | W.face_bits(3, 2, 0)),
     "3d_q3": W.problem(3, 3, 3, n_spheres=3, u_amp=0.04, u_kmax=2),
     "3d_q4_clamp": W.problem(3, 2, 4, n_spheres=2, u_amp=0.04, u_kmax=2, mask=CLAMP3),
+    # several tiles per direction (tile modes), ragged for Q3
+    "3d_q4_tiles": W.problem(3, 4, 4, n_spheres=4, u_amp=0.03, u_kmax=1, mask=CLAMP3),
+    "3d_q3_tiles": W.problem(3, 5, 3, n_spheres=4, u_amp=0.03, u_kmax=1, mask=CLAMP3),
 }
 
 _ORACLE = {}

@@ -142,3 +142,36 @@ def test_level_displacements_are_nodal_interpolants():
         Xl = H.meshes[l].node_coords()
         want = np.ascontiguousarray(np.stack([np.sin(3 * Xl[:, 0]) * Xl[:, 1], Xl[:, 0] ** 2], 0).reshape(-1))
         np.testing.assert_allclose(us[l], want, atol=1e-14)   # p = 2 nodes nest: injection
+
+
+@pytest.mark.parametrize("dim,p", [(2, 3), (3, 4), (2, 1)])
+def test_vertex_level_fields(dim, p):
+    """VERTEX level fields: every coarse level carries the fine field's values
+    at its own cell vertices and is multilinear in each of its cells, so it
+    reproduces any globally multilinear field exactly; for degree 1 it equals
+    nodal interpolation."""
+    mat = fe.Material([1.0], [1.5])
+    H = gmg.Hierarchy(dim, 1, p, 3, mat, level_field="vertex")
+    Hn = gmg.Hierarchy(dim, 1, p, 3, mat, level_field="nodal")
+    fine = H.meshes[-1]
+    X = fine.node_coords()
+    # a globally multilinear field: reproduced on every level
+    lin = np.prod(1.0 + 0.3 * X, axis=1)
+    u = np.ascontiguousarray(np.stack([lin * (c + 1) for c in range(dim)], 0).reshape(-1))
+    for l, ul in enumerate(H.level_displacements(u)):
+        Xl = H.meshes[l].node_coords()
+        want = np.ascontiguousarray(np.stack([np.prod(1.0 + 0.3 * Xl, axis=1) * (c + 1) for c in range(dim)], 0).reshape(-1))
+        np.testing.assert_allclose(ul, want, atol=1e-13)
+    # a smooth non-multilinear field: coarse vertex values equal the fine values there
+    g = np.sin(2.0 * X[:, 0]) + np.cos(3.0 * X[:, -1]) * X[:, 0]
+    u = np.ascontiguousarray(np.tile(g, dim))
+    us = H.level_displacements(u)
+    for l in range(2):
+        m = H.meshes[l]
+        Xl = m.node_coords()
+        on_vertex = np.all(np.isclose((Xl * m.N) % 1.0, 0.0) | np.isclose((Xl * m.N) % 1.0, 1.0), axis=1)
+        gl = np.sin(2.0 * Xl[:, 0]) + np.cos(3.0 * Xl[:, -1]) * Xl[:, 0]
+        np.testing.assert_allclose(us[l][:m.n_nodes][on_vertex], gl[on_vertex], atol=1e-13)
+    if p == 1:
+        for a, b in zip(H.level_displacements(u), Hn.level_displacements(u)):
+            np.testing.assert_allclose(a, b, atol=1e-14)
