@@ -505,12 +505,23 @@ __device__ __forceinline__ void tangent_qp(T (&Hx)[DIM][DIM], const T (&Fi)[DIM]
     for (int I = 0; I < DIM; ++I) Hx[i][I] = P[i][I] * wt;
 }
 
+// arr[i] for a thread-dependent i by compare-and-select over the N1 entries:
+// indexing a kernel-argument array with a runtime index makes the compiler
+// copy the whole argument block to scratch memory first.
+template <int N1, typename T>
+__device__ __forceinline__ T pick(const T (&arr)[kMaxN1], int i) {
+  T v = arr[0];
+#pragma unroll
+  for (int k = 1; k < N1; ++k) v = (i == k) ? arr[k] : v;
+  return v;
+}
+
 template <int DIM, int N1, typename T>
 __device__ __forceinline__ T qp_weight(const Tables<T>& tb, int p0, int p1, int q) {
   if constexpr (DIM == 3)
-    return tb.w[p0] * tb.w[p1] * tb.w[q];
+    return pick<N1>(tb.w, p0) * pick<N1>(tb.w, p1) * tb.w[q];
   else
-    return tb.w[p0] * tb.w[q];
+    return pick<N1>(tb.w, p0) * tb.w[q];
 }
 
 template <int DIM, int N1>
@@ -706,7 +717,8 @@ __device__ __forceinline__ void elem_gather_node(const CellArgs<T>& a, const T* 
 }
 
 template <int DIM, int P, typename T>
-__global__ void __launch_bounds__(kBlock) k_elem_gather(CellArgs<T> a, unsigned magic) {
+__global__ void __launch_bounds__(kBlock) k_elem_gather(CellArgs<T> arg, unsigned magic) {
+  const CellArgs<T>& a = kernel_args(arg);
   elem_gather_node<DIM, P, T>(a, a.x, a.y, blockIdx.x * kBlock + threadIdx.x, blockIdx.y, blockIdx.z, magic);
 }
 
@@ -732,9 +744,10 @@ __global__ void __launch_bounds__(kBlock) k_elem_gather_batch(const CellArgs<T>*
 
 // Tangent vmult: y += K x over the cells of this launch (y pre-filled).
 template <int DIM, int P, typename T, int POL>
-__global__ void __launch_bounds__(kBlock) k_tangent(CellArgs<T> a) {
+__global__ void __launch_bounds__(kBlock) k_tangent(CellArgs<T> arg) {
   using G = Geo<DIM, P + 1>;
   __shared__ T lds[DIM * G::NARR * G::NV * G::CPB];
+  const CellArgs<T>& a = kernel_args(arg);
   const long long blk = a.color < 0 ? xcd_block(blockIdx.x, gridDim.x) : (long long)blockIdx.x;
   tangent_block<DIM, P, T, POL>(a, a.x, a.y, blk, lds);
 }
@@ -1205,7 +1218,8 @@ k_tangent_tile(CellArgs<T> a) {
 
 // Residual of the weak form: y += sum_q w P(F) : Grad N (FP64).
 template <int DIM, int P>
-__global__ void __launch_bounds__(kBlock) k_residual(CellArgs<double> a) {
+__global__ void __launch_bounds__(kBlock) k_residual(CellArgs<double> arg) {
+  const CellArgs<double>& a = kernel_args(arg);
   using T = double;
   constexpr int N1 = P + 1;
   using G = Geo<DIM, N1>;
@@ -1257,7 +1271,8 @@ __global__ void __launch_bounds__(kBlock) k_residual(CellArgs<double> a) {
 // (CF: F;  C2: F^-1, S (upper triangle, row major), c1) in precision T.
 // The displacement is read in FP64 and everything is evaluated in FP64.
 template <int DIM, int P, typename T, int POL>
-__global__ void __launch_bounds__(kBlock) k_qpdata(CellArgs<double> a, T* __restrict__ cache) {
+__global__ void __launch_bounds__(kBlock) k_qpdata(CellArgs<double> arg, T* __restrict__ cache) {
+  const CellArgs<double>& a = kernel_args(arg);
   using D = double;
   constexpr int N1 = P + 1;
   using G = Geo<DIM, N1>;

@@ -47,6 +47,17 @@ struct CellArgs {
   int mask_in;          // 1: constrained entries of x read as zero (K_c); 0: read as given
 };
 
+// The kernel's first argument read in place from the kernarg segment (offset
+// 0, constant address space): uniform reads become scalar loads and the
+// compiler does not copy the argument block to private memory, which it does
+// for large blocks whose fields are used many times (degree >= 3).
+template <typename A>
+__device__ __forceinline__ const A& kernel_args(const A& byval) {
+  (void)byval;
+  using CA = const A __attribute__((address_space(4)));
+  return *(const A*)(CA*)__builtin_amdgcn_kernarg_segment_ptr();
+}
+
 // Work item of the batched node-sum kernel (ELEMENT scatter).
 struct GatherItem {
   int p;            // problem index in the bin's argument table
