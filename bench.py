@@ -217,7 +217,7 @@ def _config5_newton(n_cells, n_levels, strain, n_steps, level_field, cg_max_it=5
             "min_J_last": recs[-1]["min_J"] if recs else None}
 
 
-def config5_bench(n_cells=48, n_levels=5, n_steps=5, steps=10):
+def config5_bench(n_cells=48, n_levels=5, n_steps=5, steps=10, newton=True):
     """Config 5: 3-D Q4 48^3 (21.6 M DoFs), 5^3 Gauss points, 200 spheres (seed 7),
     config-2 material law, bottom/top clamped, levels 3^3..48^3, FP32 V(2,2)
     Chebyshev(4) GMG under FP64 CG.  Level vmults (FP32 on three levels, FP64 on
@@ -274,8 +274,9 @@ def config5_bench(n_cells=48, n_levels=5, n_steps=5, steps=10):
     P.close()
     del P
     torch.cuda.empty_cache()
-    out["newton"] = [_config5_newton(n_cells, n_levels, -0.2, n_steps, 0),
-                     _config5_newton(n_cells, n_levels, +0.2, n_steps, 1)]
+    if newton:
+        out["newton"] = [_config5_newton(n_cells, n_levels, -0.2, n_steps, 0),
+                         _config5_newton(n_cells, n_levels, +0.2, n_steps, 1)]
     return out
 
 
@@ -401,6 +402,7 @@ def main(argv=None):
     ap.add_argument("--no-batch", action="store_true", help="skip the config-4 batched measurement")
     ap.add_argument("--no-batch-solve", action="store_true", help="config 4: time the batched vmult only")
     ap.add_argument("--config5", action="store_true", help="also run config 5 (Q4 48^3 Newton, minutes)")
+    ap.add_argument("--config5-vmult-only", action="store_true", help="config 5: level vmults only, no Newton")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 256 MiB device copy (reference for HBM byte counters)")
     a = ap.parse_args(argv)
@@ -454,7 +456,10 @@ def main(argv=None):
         del P
         torch.cuda.empty_cache()
     if not any(k[1] == "f64" for k in res) or not any(k[1] == "f32" for k in res):
-        print(json.dumps({"partial": True, "variants": {f"{POLICIES[k[0]]}/{k[1]}": res[k] for k in res}}))
+        part = {"partial": True, "variants": {f"{POLICIES[k[0]]}/{k[1]}": res[k] for k in res}}
+        if a.config5 or a.config5_vmult_only:
+            part["config5"] = config5_bench(newton=not a.config5_vmult_only)
+        print(json.dumps(part))
         return 0
     best = max((k for k in res if k[1] == "f64"), key=lambda k: res[k]["dofs_per_s"])
     best32 = max((k for k in res if k[1] == "f32"), key=lambda k: res[k]["dofs_per_s"])
@@ -491,8 +496,8 @@ def main(argv=None):
         out["newton_step"] = newton_bench(w)
     if not a.no_batch:
         out["batched"] = batch_bench(solve=not a.no_batch_solve)
-    if a.config5:
-        out["config5"] = config5_bench()
+    if a.config5 or a.config5_vmult_only:
+        out["config5"] = config5_bench(newton=not a.config5_vmult_only)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)
