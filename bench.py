@@ -142,10 +142,17 @@ def newton_bench(w, n_cells=64, n_levels=5, stretch=0.1, n_steps=4):
     out = {"workload": f"3-D Q2 {n_cells}^3 ({(2 * n_cells + 1) ** 3 * 3:,} DoFs), levels "
                        f"{n_cells >> (n_levels - 1)}^3..{n_cells}^3, config-2 material, clamped bottom/top, "
                        f"{stretch:.0%} stretch in {n_steps} load steps, FP64 CG to 1e-8 with a V(2,2) "
-                       f"Chebyshev(4) GMG preconditioner, FP64 dense coarse solve"}
-    for name, vdt in (("mixed", F32), ("fp64", F64)):
+                       f"Chebyshev(4) GMG preconditioner, FP64 dense coarse solve (variants: V(1,1), the "
+                       f"Chebyshev coarse solver to 1e-3, eigenvalue estimates of the first linearisation "
+                       f"reused)"}
+    runs = (("mixed", dict(vcycle_dtype=F32)), ("fp64", dict(vcycle_dtype=F64)),
+            # solver settings of the paper (Sec. 7) and their alternatives, all mixed precision
+            ("mixed_V11", dict(vcycle_dtype=F32, n_smooth=1)),
+            ("mixed_chebyshev_coarse", dict(vcycle_dtype=F32, coarse_solver=1)),
+            ("mixed_eig_reuse", dict(vcycle_dtype=F32, eig_refresh=0)))
+    for name, kw in runs:
         P = Problem(3, n_cells, 2, n_levels=n_levels, mu=tuple(w["mu"]), lam=tuple(w["lam"]),
-                    inclusions=w["inclusions"], dirichlet_mask=W.clamp_bottom_top(3), vcycle_dtype=vdt)
+                    inclusions=w["inclusions"], dirichlet_mask=W.clamp_bottom_top(3), **kw)
         u = torch.zeros(P.n_dofs(), dtype=torch.float64, device="cuda")
         fv = np.zeros((6, 3))
         fv[5][2] = stretch

@@ -108,6 +108,16 @@ enum {
  * strongly heterogeneous bodies positive definite for longer under load. */
 enum { MFH_LEVEL_FIELD_NODAL = 0, MFH_LEVEL_FIELD_VERTEX = 1 };
 
+/* Coarsest-level solve inside the V-cycle: DIRECT (dense FP64 inverse of the
+ * coarse tangent on the free DoFs, exact; coarse levels up to 20,000 DoFs) or
+ * CHEBYSHEV (Sec. 7: the Chebyshev iteration used as a solver that reduces the
+ * residual by three orders of magnitude: Jacobi-preconditioned, on the
+ * interval [lambda_min, cheb_hi * lambda_max] of the coarse level's CG-Lanczos
+ * estimates, degree = ceil(acosh(1000) / acosh((b + a) / (b - a))), at most
+ * 1000; a fixed polynomial, so the V-cycle stays a symmetric linear operator;
+ * needs a definite coarse tangent and allows coarse levels of any size). */
+enum { MFH_COARSE_DIRECT = 0, MFH_COARSE_CHEBYSHEV = 1 };
+
 typedef struct mfh_problem mfh_problem;
 
 typedef struct {
@@ -131,11 +141,15 @@ typedef struct {
   int eig_iters;             /* CG iterations for lambda_max (paper: 30), 1..200          */
   double cheb_lo, cheb_hi;   /* smoother interval factors (paper: 0.6, 1.2)              */
   int level_field;           /* MFH_LEVEL_FIELD_*: displacement on the coarser levels     */
+  int coarse_solver;         /* MFH_COARSE_*                                             */
+  int eig_refresh;           /* eigenvalue estimates: 1 every linearisation, k every k-th,
+                                0 only the first (then reused)                           */
 } mfh_desc;
 
 /* Fills *desc with the paper's solver settings (degree 4, 2 steps, 30
  * iterations, [0.6, 1.2]), RECOMPUTE, AUTO scatter, F32 V-cycle, NODAL level
- * fields; geometry fields
+ * fields, DIRECT coarse solve, eigenvalue estimates at every linearisation;
+ * geometry fields
  * are zeroed and must be set by the caller. */
 void mfh_desc_defaults(mfh_desc* desc);
 
@@ -283,7 +297,7 @@ mfh_status mfh_chebyshev(mfh_problem* problem, int level, const void* f_dev, voi
  * level linearised about the interpolated displacement to stay positive
  * definite (the assumption of Sec. 6), and the preconditioner is then
  * indefinite.  Builds the preconditioner data if needed (synchronises).
- * Errors: INVALID_ARG, NOT_SPD, HIP. */
+ * DIRECT coarse solver only.  Errors: INVALID_ARG, NOT_SPD, HIP. */
 mfh_status mfh_coarse_inertia(mfh_problem* problem, int* negative);
 
 /* ---- Graph capture ---- */

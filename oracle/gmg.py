@@ -14,7 +14,10 @@ Readings taken where the paper is silent:
   coarser support points, applied recursively fine -> coarse (``"nodal"``);
   the alternative ``"vertex"`` takes the values at the coarse cell vertices
   and fills each coarse cell multilinearly;
-* the coarse level is solved exactly (dense LU) in FP64.  Linearised about the
+* the coarse level is solved exactly (dense LU) in FP64, or (``coarse_solver=
+  "chebyshev"``, Sec. 7) by the Chebyshev iteration as a solver: interval
+  [lambda_min, 1.2 lambda_max] from the coarse level's CG-Lanczos run, degree
+  from the bound 1 / T_k <= 1e-3.  Linearised about the
   interpolated displacement, the coarse tangent can be indefinite when the
   coarse mesh does not resolve the material (the assumption of Sec. 6); the
   exact solve is still defined, and ``coarse_negative`` records its number of
@@ -160,7 +163,21 @@ def lanczos_lambda_max(apply_A, dinv, r0, iters):
         T[j, j] = 1.0 / alphas[j] + (betas[j - 1] / alphas[j - 1] if j > 0 else 0.0)
         if j + 1 < m:
             T[j, j + 1] = T[j + 1, j] = np.sqrt(betas[j]) / alphas[j]
-    return float(np.linalg.eigvalsh(T).max()), m
+    ev = np.linalg.eigvalsh(T)
+    lanczos_lambda_max.last_min = float(ev.min())    # smallest Ritz value of the same run
+    return float(ev.max()), m
+
+
+COARSE_REDUCTION = 1e-3     # Sec. 7: the coarse Chebyshev solver reduces the residual by 10^3
+
+
+def chebyshev_solver_degree(lo, hi, eps):
+    """Smallest k with 1 / T_k((hi + lo) / (hi - lo)) <= eps (the Chebyshev
+    iteration's error bound on [lo, hi]), at most 1000."""
+    if not (lo > 0 and hi > lo):
+        raise ValueError("the Chebyshev coarse solver needs 0 < lambda_min < lambda_max")
+    k = np.arccosh(1.0 / eps) / np.arccosh((hi + lo) / (hi - lo))
+    return int(min(1000, max(1, np.ceil(k))))
 
 
 def eig_start_vector(n, constrained):
@@ -178,7 +195,8 @@ class Hierarchy:
     """
 
     def __init__(self, dim, n_coarse, degree, n_levels, mat, mask=0,
-                 cheb_degree=4, n_smooth=2, eig_iters=30, cheb_lo=0.6, cheb_hi=1.2, level_field="nodal"):
+                 cheb_degree=4, n_smooth=2, eig_iters=30, cheb_lo=0.6, cheb_hi=1.2, level_field="nodal",
+                 coarse_solver="direct"):
         self.meshes = [fe.Mesh(dim, n_coarse * 2 ** l, degree) for l in range(n_levels)]
         self.mat = mat
         self.mask = mask
@@ -189,6 +207,7 @@ class Hierarchy:
         self.n_smooth = n_smooth
         self.eig_iters = eig_iters
         self.cheb_lo, self.cheb_hi = cheb_lo, cheb_hi
+        self.coarse_solver = coarse_solver
 
     @property
     def n_levels(self):
@@ -210,14 +229,20 @@ class Hierarchy:
             self.A.append(A)
             dinv = 1.0 / diagonal(A)
             self.dinv.append(dinv)
-            if l > 0:
+            if l > 0 or self.coarse_solver == "chebyshev":
                 lmax, _ = lanczos_lambda_max(lambda v, A=A: A @ v, dinv,
                                              eig_start_vector(m.n_dofs, self.cons[l]),
                                              self.eig_iters)
+                lmin = lanczos_lambda_max.last_min
             else:
-                lmax = np.nan
+                lmax = lmin = np.nan
             self.lam_max.append(lmax)
-            self.interval.append((self.cheb_lo * lmax, self.cheb_hi * lmax))
+            if l == 0 and self.coarse_solver == "chebyshev":
+                self.lam_min0 = lmin
+                self.interval.append((lmin, self.cheb_hi * lmax))
+                self.coarse_degree = chebyshev_solver_degree(lmin, self.cheb_hi * lmax, COARSE_REDUCTION)
+            else:
+                self.interval.append((self.cheb_lo * lmax, self.cheb_hi * lmax))
         A0 = self.A[0].toarray()
         self.coarse = sla.lu_factor(A0)
         self.coarse_negative = int((np.linalg.eigvalsh(A0) < 0).sum())
@@ -233,6 +258,10 @@ class Hierarchy:
         """One V-cycle applied to the residual r on level l (default finest)."""
         l = self.n_levels - 1 if l is None else l
         if l == 0:
+            if self.coarse_solver == "chebyshev":
+                lo, hi = self.interval[0]
+                return chebyshev(lambda v: self.A[0] @ v, self.dinv[0], r, np.zeros_like(r), lo, hi,
+                                 self.coarse_degree)
             return sla.lu_solve(self.coarse, r)
         x = self.smooth(l, r, np.zeros_like(r))
         rc = self.P[l].T @ (r - self.A[l] @ x)

@@ -98,6 +98,7 @@ struct Level {
   void* dinv = nullptr;        // vcycle dtype
   void *vb = nullptr, *vx = nullptr, *vt = nullptr, *vd = nullptr;   // vcycle dtype
   double lam_max = 0;
+  double lam_min = 0;          // coarsest level with the Chebyshev coarse solver
   std::vector<double> cd, cr;  // Chebyshev step coefficients
   DevBand P1, R1, I1;          // transfers from level-1 into this level (l >= 1)
 };
@@ -131,9 +132,14 @@ struct mfh_problem {
   double *gj_P = nullptr, *gj_C = nullptr, *gj_R = nullptr, *crf = nullptr, *czf = nullptr;
   int* flag = nullptr;
   double* elem = nullptr;            // element buffer of the ELEMENT scatter (finest level size)
+  // FP64 work vectors of the Chebyshev coarse solver (coarse level size): 1/diag, b, x, t, d
+  double *cc_dinv = nullptr, *cc_b = nullptr, *cc_x = nullptr, *cc_t = nullptr, *cc_d = nullptr;
   std::vector<int> h_fmap, h_dof_of;
   bool deformed = false;
   bool precond_ready = false;        // diagonals, lambda_max, coarse inverse built
+  bool eig_ready = false;            // eigenvalue estimates exist (reused when eig_refresh allows)
+  bool eig_fresh = false;            // this set-up recomputes them
+  long long n_linearisations = 0;    // successful set_deformation calls
   bool has_coarse = false;           // coarse level small enough for the dense direct solve
   int coarse_negative = 0;           // negative pivots (eigenvalues) of the coarse tangent
   std::string err;
@@ -198,6 +204,8 @@ void validate(const mfh_desc* d) {
   if (d->eig_iters < 1 || d->eig_iters > 200) bad("eig_iters must be 1..200");
   if (!(d->cheb_lo > 0) || !(d->cheb_hi > d->cheb_lo)) bad("need 0 < cheb_lo < cheb_hi");
   if (d->level_field != MFH_LEVEL_FIELD_NODAL && d->level_field != MFH_LEVEL_FIELD_VERTEX) bad("bad level_field");
+  if (d->coarse_solver != MFH_COARSE_DIRECT && d->coarse_solver != MFH_COARSE_CHEBYSHEV) bad("bad coarse_solver");
+  if (d->eig_refresh < 0) bad("eig_refresh must be >= 0");
 }
 
 // Largest coarse level that gets the dense FP64 direct solve; problems with a
@@ -268,8 +276,9 @@ void build_host(mfh_problem* P) {
   Level& c = P->lv[0];
   P->h_fmap.assign(c.ndofs, -1);
   P->h_dof_of.clear();
-  P->has_coarse = c.ndofs <= kMaxCoarseDofs;
-  for (long long dof = 0; P->has_coarse && dof < c.ndofs; ++dof) {
+  const bool direct = d.coarse_solver == MFH_COARSE_DIRECT;
+  P->has_coarse = !direct || c.ndofs <= kMaxCoarseDofs;   // the Chebyshev coarse solver has no size limit
+  for (long long dof = 0; direct && P->has_coarse && dof < c.ndofs; ++dof) {
     const int comp = (int)(dof / c.nn);
     long long n = dof - comp * c.nn;
     const int i = (int)(n % c.L);
@@ -362,6 +371,10 @@ size_t layout(mfh_problem* P, char* base) {
   P->crf = b.take<double>(std::max<long long>(1, P->nf));
   P->czf = b.take<double>(std::max<long long>(1, P->nf));
   P->flag = b.take<int>(2);
+  if (d.coarse_solver == MFH_COARSE_CHEBYSHEV) {
+    const long long n0 = P->lv[0].ndofs;
+    for (double** q : {&P->cc_dinv, &P->cc_b, &P->cc_x, &P->cc_t, &P->cc_d}) *q = b.take<double>(n0);
+  }
   size_t nodes_per_cell = 1;
   for (int k = 0; k < d.dim; ++k) nodes_per_cell *= (size_t)(d.degree + 1);
   bool any_elem = false;
@@ -579,7 +592,7 @@ void cheb_apply(mfh_problem* P, int l, const T* f, T* x, bool xzero) {
   T* t = static_cast<T*>(v.vt);
   T* dvec = static_cast<T*>(v.vd);
   const T* dinv = static_cast<const T*>(v.dinv);
-  for (int j = 0; j < P->d.cheb_degree; ++j) {
+  for (int j = 0; j < (int)v.cd.size(); ++j) {
     const bool first_zero = (j == 0 && xzero);
     const T* tt = nullptr;
     if (!first_zero) {
@@ -598,7 +611,19 @@ void smooth(mfh_problem* P, int l, const T* f, T* x, bool xzero) {
 template <typename T>
 void coarse_solve(mfh_problem* P, const T* b, T* x) {
   const Level& c = P->lv[0];
-  fill<T>(x, T(0), c.ndofs, P->stream);
+  const long long n = c.ndofs;
+  if (P->d.coarse_solver == MFH_COARSE_CHEBYSHEV) {   // FP64 Chebyshev iteration from x = 0
+    cast<T, double>(b, P->cc_b, n, P->stream);
+    for (int j = 0; j < (int)c.cd.size(); ++j) {
+      const bool first = j == 0;
+      if (!first) vmult<double>(P, 0, P->cc_x, P->cc_t);
+      cheb_step<double>(P->cc_b, first ? nullptr : P->cc_t, P->cc_dinv, P->cc_d, P->cc_x, c.cd[j], c.cr[j],
+                        first ? 1 : 0, n, P->stream);
+    }
+    cast<double, T>(P->cc_x, x, n, P->stream);
+    return;
+  }
+  fill<T>(x, T(0), n, P->stream);
   if (P->nf) coarse_apply<T>(P->Kinv, P->nf, P->dof_of, b, P->crf, P->czf, x, P->stream);
 }
 
@@ -666,9 +691,30 @@ void lanczos_enqueue(mfh_problem* P, int l, double* hist) {
   }
 }
 
+// The same estimate on the coarsest level in FP64 (Chebyshev coarse solver),
+// on the solver's own FP64 vectors.
+void coarse_lanczos_enqueue(mfh_problem* P, double* hist) {
+  Level& v = P->lv[0];
+  const long long n = v.ndofs;
+  double *r = P->cc_b, *z = P->cc_x, *p = P->cc_d, *Ap = P->cc_t;
+  splitmix_uniform<double>(r, n, 0x5EEDull, P->stream);
+  zero_constrained<double>(r, n, v.lt, P->stream);
+  cheb_step<double>(r, nullptr, P->cc_dinv, z, p, 0.0, 1.0, 1, n, P->stream);
+  dot<double, double>(r, z, n, P->part, P->sc + SC_RZ, P->stream);
+  const int it = P->d.eig_iters;
+  for (int j = 0; j < it; ++j) {
+    vmult<double>(P, 0, p, Ap);
+    dot<double, double>(p, Ap, n, P->part, P->sc + SC_PAP, P->stream);
+    scalar_div(P->sc, SC_ALPHA, SC_RZ, SC_PAP, -1, -1, hist, j, P->stream);
+    lanczos_update<double>(r, z, Ap, P->cc_dinv, n, P->sc, P->part, P->stream);
+    scalar_div(P->sc, SC_BETA, SC_RZNEW, SC_RZ, SC_RZ, SC_RZNEW, hist, it + j, P->stream);
+    cg_pupdate<double>(p, z, n, P->sc, P->stream);
+  }
+}
+
 // Host side of the estimate: the Lanczos tridiagonal from the CG coefficients
 // (up to the first non-positive or non-finite one) and its largest eigenvalue.
-double lanczos_lambda(const double* h, int it, int l) {
+double lanczos_lambda(const double* h, int it, int l, double* lam_min = nullptr) {
   std::vector<double> al, be;
   for (int j = 0; j < it; ++j) {
     const double a = h[j], bta = h[it + j];
@@ -684,22 +730,42 @@ double lanczos_lambda(const double* h, int it, int l) {
     dg[j] = 1.0 / al[j] + (j > 0 ? be[j - 1] / al[j - 1] : 0.0);
     if (j + 1 < m) off[j] = std::sqrt(be[j]) / al[j];
   }
+  if (lam_min) *lam_min = tridiag_min_eig(dg, off);
   return tridiag_max_eig(dg, off);
 }
 
-void set_cheb_coeffs(mfh_problem* P, Level& v) {
-  const double lo = P->d.cheb_lo * v.lam_max, hi = P->d.cheb_hi * v.lam_max;
+// Coefficients of a degree-`degree` Chebyshev iteration on [lo, hi]
+// (Saad, Alg. 12.1), applied by cheb_step.
+void set_cheb_interval(Level& v, double lo, double hi, int degree) {
   const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
-  v.cd.assign(P->d.cheb_degree, 0.0);
-  v.cr.assign(P->d.cheb_degree, 0.0);
+  v.cd.assign(degree, 0.0);
+  v.cr.assign(degree, 0.0);
   double rho = 1.0 / sigma;
   v.cr[0] = 1.0 / theta;
-  for (int j = 1; j < P->d.cheb_degree; ++j) {
+  for (int j = 1; j < degree; ++j) {
     const double rn = 1.0 / (2.0 * sigma - rho);
     v.cd[j] = rn * rho;
     v.cr[j] = 2.0 * rn / delta;
     rho = rn;
   }
+}
+
+void set_cheb_coeffs(mfh_problem* P, Level& v) {
+  set_cheb_interval(v, P->d.cheb_lo * v.lam_max, P->d.cheb_hi * v.lam_max, P->d.cheb_degree);
+}
+
+// Chebyshev iteration as the coarse solver (Sec. 7): on [lam_min, cheb_hi *
+// lam_max], of the degree whose error bound 1 / T_k((b + a) / (b - a)) reaches
+// 1e-3.
+constexpr double kCoarseReduction = 1e-3;
+void set_coarse_chebyshev(mfh_problem* P, Level& v) {
+  if (!(v.lam_min > 0) || !(v.lam_max > v.lam_min))
+    throw Error(MFH_ERR_NOT_SPD, "Chebyshev coarse solver: the coarse tangent is not definite (lambda_min estimate " +
+                                     std::to_string(v.lam_min) + ")");
+  const double a = v.lam_min, b = P->d.cheb_hi * v.lam_max;
+  const double k = std::acosh(1.0 / kCoarseReduction) / std::acosh((b + a) / (b - a));
+  const int degree = (int)std::min(1000.0, std::max(1.0, std::ceil(k)));
+  set_cheb_interval(v, a, b, degree);
 }
 
 void interpolate_down(mfh_problem* P, int l) {
@@ -745,6 +811,7 @@ double setdef_finish(mfh_problem* P, const double* mj) {
     throw Error(MFH_ERR_INVERTED, buf);
   }
   P->deformed = true;
+  ++P->n_linearisations;
   return minJ;
 }
 
@@ -780,18 +847,26 @@ void setup_enqueue(mfh_problem* P) {
   }
   check_launch("diagonal");
   const int it = d.eig_iters;
-  for (int l = 1; l < nl; ++l) {
+  const bool cheb_coarse = d.coarse_solver == MFH_COARSE_CHEBYSHEV;
+  // eigenvalue estimates: every eig_refresh-th linearisation (0: only the first)
+  P->eig_fresh = !P->eig_ready ||
+                 (d.eig_refresh > 0 && (P->n_linearisations - 1) % d.eig_refresh == 0);
+  for (int l = 1; P->eig_fresh && l < nl; ++l) {
     double* h = P->hist + 2 * (size_t)it * l;
     if (d.vcycle_dtype == MFH_F32)
       lanczos_enqueue<float>(P, l, h);
     else
       lanczos_enqueue<double>(P, l, h);
   }
-  // coarse level: dense FP64 tangent on free DoFs, inverted in place
+  if (cheb_coarse) {   // the coarse solver runs in FP64 whatever the V-cycle precision
+    reciprocal<double>(P->lv[0].diag64, P->cc_dinv, P->lv[0].ndofs, s);
+    if (P->eig_fresh) coarse_lanczos_enqueue(P, P->hist);
+  }
+  // coarse level (direct solver): dense FP64 tangent on free DoFs, inverted in place
   Level& c = P->lv[0];
   const long long nf = P->nf;
   fill<int>(P->flag, 0, 2, s);
-  if (nf) {
+  if (nf && !cheb_coarse) {
     fill<double>(P->Kinv, 0.0, nf * nf, s);
     CellArgs<double> a = cell_args<double>(P, c, c.u64, nullptr, nullptr, nullptr);
     P->ops->coarse_assemble(a, P->fmap, nf, P->Kinv, (unsigned)c.ncells, s);
@@ -817,15 +892,24 @@ void setup_copy_back(mfh_problem* P, double* host) {
 void setup_finish(mfh_problem* P, const double* host) {
   const int nl = (int)P->lv.size();
   const int it = P->d.eig_iters;
-  for (int l = 1; l < nl; ++l) {
-    Level& v = P->lv[l];
-    v.lam_max = lanczos_lambda(host + 2 * (size_t)it * l, it, l);
-    set_cheb_coeffs(P, v);
+  const bool cheb_coarse = P->d.coarse_solver == MFH_COARSE_CHEBYSHEV;
+  if (P->eig_fresh) {
+    for (int l = 1; l < nl; ++l) {
+      Level& v = P->lv[l];
+      v.lam_max = lanczos_lambda(host + 2 * (size_t)it * l, it, l);
+      set_cheb_coeffs(P, v);
+    }
+    if (cheb_coarse) {
+      Level& c = P->lv[0];
+      c.lam_max = lanczos_lambda(host, it, 0, &c.lam_min);
+      set_coarse_chebyshev(P, c);
+    }
+    P->eig_ready = true;
   }
   int flag[2];
   std::memcpy(flag, host + 2 * (size_t)it * nl, sizeof flag);
-  P->coarse_negative = flag[1];
-  if (flag[0]) throw Error(MFH_ERR_NOT_SPD, "coarse-level tangent is numerically singular");
+  P->coarse_negative = cheb_coarse ? 0 : flag[1];
+  if (!cheb_coarse && flag[0]) throw Error(MFH_ERR_NOT_SPD, "coarse-level tangent is numerically singular");
   P->precond_ready = true;
 }
 
@@ -1005,6 +1089,8 @@ void mfh_desc_defaults(mfh_desc* d) {
   d->cheb_lo = 0.6;
   d->cheb_hi = 1.2;
   d->level_field = MFH_LEVEL_FIELD_NODAL;
+  d->coarse_solver = MFH_COARSE_DIRECT;
+  d->eig_refresh = 1;
 }
 
 mfh_status mfh_workspace_size(const mfh_desc* desc, size_t* bytes) {
@@ -1378,6 +1464,7 @@ mfh_status mfh_coarse_inertia(mfh_problem* P, int* negative) {
   return guarded(P, [&] {
     need(negative != nullptr, "negative is NULL");
     need(P->deformed, "set_deformation has not succeeded yet");
+    need(P->d.coarse_solver == MFH_COARSE_DIRECT, "the coarse inertia comes from the direct coarse solve");
     need(P->has_coarse, "coarsest level too large for the direct solve: use more levels");
     setup_precond(P);
     *negative = P->coarse_negative;

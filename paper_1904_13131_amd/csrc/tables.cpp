@@ -181,6 +181,14 @@ BandHost make_band(const std::vector<double>& M, int nout, int nin) {
   return b;
 }
 
+double tridiag_min_eig(const std::vector<double>& d, const std::vector<double>& e) {
+  // Smallest eigenvalue: the largest of the negated matrix.
+  std::vector<double> nd(d.size()), ne(e.size());
+  for (size_t i = 0; i < d.size(); ++i) nd[i] = -d[i];
+  for (size_t i = 0; i < e.size(); ++i) ne[i] = -e[i];
+  return -tridiag_max_eig(nd, ne);
+}
+
 double tridiag_max_eig(const std::vector<double>& d, const std::vector<double>& e) {
   // Largest eigenvalue of the symmetric tridiagonal matrix (diagonal d,
   // off-diagonal e) by bisection on the Sturm count.

@@ -30,5 +30,6 @@ std::vector<double> eval_global_1d(int N, int p, const std::vector<double>& X);
 BandHost make_band(const std::vector<double>& M, int nout, int nin);
 // Largest eigenvalue of a symmetric tridiagonal matrix.
 double tridiag_max_eig(const std::vector<double>& d, const std::vector<double>& e);
+double tridiag_min_eig(const std::vector<double>& d, const std::vector<double>& e);
 
 }  // namespace mfh

@@ -20,6 +20,7 @@ QP_RECOMPUTE, QP_CACHE_F, QP_CACHE_T2 = 0, 1, 2
 SCATTER_AUTO, SCATTER_ATOMIC, SCATTER_COLOR, SCATTER_TILE, SCATTER_ELEMENT = -1, 0, 1, 2, 3
 SCATTER_NAMES = {0: "atomic", 1: "color", 2: "tile", 3: "element"}
 LEVEL_FIELD_NODAL, LEVEL_FIELD_VERTEX = 0, 1
+COARSE_DIRECT, COARSE_CHEBYSHEV = 0, 1
 
 
 class MfhError(RuntimeError):
@@ -38,7 +39,7 @@ class Desc(ctypes.Structure):
         ("dirichlet_mask", ctypes.c_uint), ("qp_policy", ctypes.c_int), ("scatter", ctypes.c_int),
         ("vcycle_dtype", ctypes.c_int), ("cheb_degree", ctypes.c_int), ("n_smooth", ctypes.c_int),
         ("eig_iters", ctypes.c_int), ("cheb_lo", ctypes.c_double), ("cheb_hi", ctypes.c_double),
-        ("level_field", ctypes.c_int),
+        ("level_field", ctypes.c_int), ("coarse_solver", ctypes.c_int), ("eig_refresh", ctypes.c_int),
     ]
 
 
@@ -128,7 +129,7 @@ def _darr(vals):
 
 def make_desc(dim, n_cells, degree, n_levels=1, mu=(1.0,), lam=(1.5,), inclusions=(), dirichlet_mask=0,
               qp_policy=QP_RECOMPUTE, scatter=SCATTER_AUTO, vcycle_dtype=F32, cheb_degree=4, n_smooth=2,
-              eig_iters=30, cheb_lo=0.6, cheb_hi=1.2, level_field=0):
+              eig_iters=30, cheb_lo=0.6, cheb_hi=1.2, level_field=0, coarse_solver=0, eig_refresh=1):
     """Builds an mfh_desc; the returned tuple keeps the host arrays alive."""
     d = Desc()
     lib().mfh_desc_defaults(ctypes.byref(d))
@@ -148,6 +149,7 @@ def make_desc(dim, n_cells, degree, n_levels=1, mu=(1.0,), lam=(1.5,), inclusion
     d.cheb_degree, d.n_smooth, d.eig_iters = cheb_degree, n_smooth, eig_iters
     d.cheb_lo, d.cheb_hi = cheb_lo, cheb_hi
     d.level_field = level_field
+    d.coarse_solver, d.eig_refresh = coarse_solver, eig_refresh
     return d, (mu_a, lam_a, inc_a)
 
 

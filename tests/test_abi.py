@@ -56,7 +56,7 @@ def test_workspace_size_on_host():
     dict(dim=4), dict(degree=0), dict(degree=5), dict(n_cells=0), dict(n_cells=1024, degree=2, n_levels=1), dict(n_cells=6, n_levels=3),
     dict(mu=(-1.0,), lam=(1.0,)), dict(qp_policy=3), dict(scatter=4), dict(scatter=-2), dict(vcycle_dtype=5),
     dict(cheb_degree=0), dict(n_smooth=0), dict(eig_iters=0), dict(cheb_lo=1.3, cheb_hi=1.2),
-    dict(dirichlet_mask=1 << 18), dict(level_field=2), dict(inclusions=[((0.5, 0.5, 0.5), 0.2, 2)]),
+    dict(dirichlet_mask=1 << 18), dict(level_field=2), dict(coarse_solver=2), dict(eig_refresh=-1), dict(inclusions=[((0.5, 0.5, 0.5), 0.2, 2)]),
 ])
 def test_invalid_descriptors_rejected(bad):
     from paper_1904_13131_amd import MfhError, workspace_size

@@ -22,6 +22,8 @@ HIER = {
                          stretch=0.05),
     "3d_q3_vertex": dict(dim=3, n_coarse=1, degree=3, n_levels=3, spheres=2, amp=0.0025, level_field="vertex",
                          stretch=0.05),
+    # the paper's coarse solver: Chebyshev iteration reducing the residual by 10^3
+    "3d_q2_chebcoarse": dict(dim=3, n_coarse=2, degree=2, n_levels=3, spheres=3, amp=0.01, coarse="chebyshev"),
 }
 _CACHE = {}
 
@@ -36,7 +38,7 @@ def _setup(name):
     mask = W.clamp_bottom_top(dim)
     mat = fe.Material(mu, lam, incl)
     H = gmg.Hierarchy(dim, c["n_coarse"], c["degree"], c["n_levels"], mat, mask,
-                      level_field=c.get("level_field", "nodal"))
+                      level_field=c.get("level_field", "nodal"), coarse_solver=c.get("coarse", "direct"))
     fine = H.meshes[-1]
     if "stretch" in c:
         u = W.stretched_field(dim, fine.L, c["stretch"], 4, c["amp"], coords=fine.coords_1d())
@@ -55,7 +57,8 @@ def _device(name, vdt, **kw):
     c, mu, lam, incl, mask, H, u, b = _setup(name)
     P = Problem(c["dim"], c["n_coarse"] * 2 ** (c["n_levels"] - 1), c["degree"], n_levels=c["n_levels"],
                 mu=tuple(mu), lam=tuple(lam), inclusions=incl, dirichlet_mask=mask, vcycle_dtype=vdt,
-                level_field=1 if c.get("level_field") == "vertex" else 0, **kw)
+                level_field=1 if c.get("level_field") == "vertex" else 0,
+                coarse_solver=1 if c.get("coarse") == "chebyshev" else 0, **kw)
     P.set_deformation(dev(u))
     return P
 
@@ -111,7 +114,12 @@ def test_chebyshev_and_vcycle_fp64(name):
     got = host(P.chebyshev(top, dev(f), dev(x0)))
     assert rel_l2(got, want) <= 1e-7
     z = host(P.gmg_vcycle(dev(b)))
-    assert rel_l2(z, H.vcycle(b)) <= 1e-7
+    # With the Chebyshev coarse solver the coarse polynomial (degree ~40) is
+    # built on [lambda_min, 1.2 lambda_max] from 30 Lanczos steps; the smallest
+    # Ritz value is far from converged and carries the summation-order
+    # differences of the two runs at ~1e-8, which the polynomial amplifies.
+    tol = 1e-6 if c.get("coarse") == "chebyshev" else 1e-7
+    assert rel_l2(z, H.vcycle(b)) <= tol
 
 
 @pytest.mark.parametrize("name", list(HIER))
@@ -256,3 +264,22 @@ def test_error_paths():
     with pytest.raises(MfhError) as e:
         Pc.cg_solve(dev(np.ones(Pc.n_dofs())), rtol=1e-8, max_it=5)
     assert e.value.name == "NOT_SPD"
+
+
+def test_eigenvalue_reuse():
+    """eig_refresh = 0 keeps the first linearisation's estimates (and the
+    smoother built from them) for later ones; 1 recomputes them each time."""
+    from paper_1904_13131_amd import Problem
+    log_case("eig_reuse")
+    c, mu, lam, incl, mask, H, u, b = _setup("3d_q2")
+    for refresh in (0, 1):
+        P = _device("3d_q2", F64, eig_refresh=refresh)
+        lam1 = [P.level_lambda_max(l) for l in (1, 2)]
+        P.set_deformation(dev(0.5 * u))
+        lam2 = [P.level_lambda_max(l) for l in (1, 2)]
+        if refresh == 0:
+            assert lam2 == lam1
+        else:
+            assert all(abs(a - b_) > 1e-12 * a for a, b_ in zip(lam1, lam2))
+        x, it, rel, st = P.cg_solve(dev(b), rtol=1e-8, max_it=200)
+        assert rel <= 1e-8

@@ -175,3 +175,36 @@ def test_vertex_level_fields(dim, p):
     if p == 1:
         for a, b in zip(H.level_displacements(u), Hn.level_displacements(u)):
             np.testing.assert_allclose(a, b, atol=1e-14)
+
+
+def test_chebyshev_coarse_solver():
+    """Sec. 7's coarse solver: the degree follows the Chebyshev error bound,
+    and one application reduces the coarse residual (in the D^-1 A energy of a
+    definite operator) by at least the requested 10^3 when the interval holds
+    the spectrum; with the Lanczos interval it still reduces by about that."""
+    # kappa = 100: acosh(1000) = 7.6009, acosh(101/99) = 0.20067 -> 37.9; the classical
+    # estimate ln(2/eps) sqrt(kappa) / 2 = 38.0 agrees
+    assert gmg.chebyshev_solver_degree(1.0, 100.0, 1e-3) == 38
+    # exact interval on a diagonal operator: guaranteed reduction
+    rng = np.random.default_rng(0)
+    lam = np.linspace(0.5, 40.0, 200)
+    A = np.diag(lam)
+    k = gmg.chebyshev_solver_degree(0.5, 40.0, 1e-3)
+    b = rng.standard_normal(200)
+    x = gmg.chebyshev(lambda v: A @ v, np.ones(200), b, np.zeros(200), 0.5, 40.0, k)
+    e0, e = np.linalg.solve(A, b), np.linalg.solve(A, b) - x
+    assert np.sqrt(e @ A @ e) <= 1e-3 * np.sqrt(e0 @ A @ e0) * (1 + 1e-12)
+    # in the hierarchy
+    mat = fe.Material([1.0], [1.5])
+    H = gmg.Hierarchy(3, 2, 2, 2, mat, W.clamp_bottom_top(3), coarse_solver="chebyshev")
+    H.set_deformation(np.zeros(H.meshes[-1].n_dofs))
+    assert 0 < H.lam_min0 < H.lam_max[0]
+    r = W.normal_vector(H.meshes[0].n_dofs, 3)
+    r[H.cons[0]] = 0
+    z = H.vcycle(r, 0)
+    res = r - H.A[0] @ z
+    assert np.linalg.norm(res) <= 0.05 * np.linalg.norm(r)
+    b = W.normal_vector(H.meshes[-1].n_dofs, 5)
+    b[H.cons[-1]] = 0
+    _, it, rel = gmg.pcg(lambda v: H.A[-1] @ v, b, H.vcycle, 1e-8, 200)
+    assert rel <= 1e-8
