@@ -238,8 +238,12 @@ typedef struct {
 mfh_status mfh_apply_dirichlet(mfh_problem* problem, double* u_dev,
                                const double* face_values, double scale);
 
-/* Full Newton solve under displacement control.  The prescribed values
- * (as for mfh_apply_dirichlet) are applied in n_steps equal increments; the
+/* Full Newton solve under displacement control and dead face tractions.
+ * The prescribed values (as for mfh_apply_dirichlet) and the tractions
+ * face_traction (host array of 2*dim*dim doubles, traction vector per face,
+ * constant per unit reference area; NULL for none; the Neumann term of
+ * Sec. 3, R = F_int(u) - s f_ext with the load fraction s) are applied in
+ * n_steps equal increments; the
  * first Newton step of each increment carries it linearly
  * (K_c d = -(R(u) + K(u) dg), u <- u + dg + d), later steps solve
  * K_c du = -R(u).  An increment converges when |du| <= du_tol and
@@ -257,9 +261,15 @@ mfh_status mfh_apply_dirichlet(mfh_problem* problem, double* u_dev,
  * number of Newton steps taken.  Synchronises.
  * Errors: INVALID_ARG, INVERTED, NOT_CONVERGED, BREAKDOWN, NOT_SPD, HIP. */
 mfh_status mfh_newton_solve(mfh_problem* problem, double* u_dev, const double* face_values,
-                            int n_steps, double cg_rtol, int cg_max_it, double du_tol,
-                            double r_tol, int max_newton,
+                            const double* face_traction, int n_steps, double cg_rtol, int cg_max_it,
+                            double du_tol, double r_tol, int max_newton,
                             mfh_newton_record* records, int max_records, int* n_records);
+
+/* f = nodal forces of dead face tractions on the finest level (as for
+ * mfh_newton_solve: f_a = sum over loaded faces of the face integral of
+ * T_f N_a), zero on constrained rows.  f is a device FP64 vector.  Async.
+ * Errors: INVALID_ARG, HIP. */
+mfh_status mfh_external_force(mfh_problem* problem, const double* face_traction, double* f_dev);
 
 /* The scatter mode tangent_vmult uses on `level` in precision dtype (the
  * descriptor's mode, or the tuned choice under MFH_SCATTER_AUTO) into *mode.

@@ -257,6 +257,45 @@ def residual(mesh, mat, u, constrained=None, chunk=2048):
     return R
 
 
+def external_force(mesh, face_traction):
+    """Nodal external force f_a = sum over loaded faces of the integral of
+    T_f N_a over the face (the Neumann term of the weak form, Sec. 3), for
+    dead (reference-configuration) tractions: face_traction[2*axis + side][comp].
+
+    Each face is integrated cell face by cell face with the face's own Gauss
+    rule (q = p + 1 points per direction) on the restricted shape functions.
+    """
+    d, p, L = mesh.d, mesh.p, mesh.L
+    f = np.zeros(mesh.n_dofs)
+    lat = np.indices((L,) * d).reshape(d, -1)[::-1]               # lattice index per node, axis-major
+    gx, gw = basis.gauss_rule(p + 1)
+    V, _ = basis.lagrange(mesh.xi, gx)                            # (q, p + 1) values on [0, 1]
+    # 1-D face-cell integrals of each local basis function: int_0^h phi_b = h sum_q w_q V[q, b]
+    m1 = mesh.h * (gw @ V)                                        # (p + 1,)
+    for axis in range(d):
+        for side in range(2):
+            t = np.asarray(face_traction[2 * axis + side], dtype=np.float64)
+            if not np.any(t):
+                continue
+            on_face = np.nonzero(lat[axis] == (0 if side == 0 else L - 1))[0]
+            tang = [a for a in range(d) if a != axis]
+            for node in on_face:
+                # the node's weight: sum over the face cells containing it of the
+                # product of the 1-D integrals of its basis function per tangential axis
+                w = 1.0
+                for a in tang:
+                    I = lat[a][node]
+                    wa = 0.0
+                    for e in range(mesh.N):
+                        b = I - p * e
+                        if 0 <= b <= p:
+                            wa += m1[b]
+                    w *= wa
+                for c in range(d):
+                    f[c * mesh.n_nodes + node] += t[c] * w
+    return f
+
+
 def tangent_matrix(mesh, mat, u, chunk=1024):
     """Assembled (unconstrained) tangent as scipy CSR."""
     nd = mesh.d * mesh.nA

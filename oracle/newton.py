@@ -30,7 +30,7 @@ def dirichlet_vector(mesh, face_values, mask, scale=1.0):
 
 
 def solve(hier, face_values, n_steps, rtol=1e-8, max_cg=200, du_tol=1e-5,
-          r_tol=1e-8, max_newton=20, u0=None, log=None, max_cutbacks=8):
+          r_tol=1e-8, max_newton=20, u0=None, log=None, max_cutbacks=8, face_traction=None):
     """Full Newton solve; returns (u, records) with one record per Newton step.
 
     The prescribed increment dg of a load step enters the first Newton step of
@@ -38,6 +38,8 @@ def solve(hier, face_values, n_steps, rtol=1e-8, max_cg=200, du_tol=1e-5,
     constraints): K_c d = -(R(u) + K(u) dg) on free rows, u <- u + dg + d.
     Later Newton steps solve K_c du = -R(u).  R0, the reference for the
     relative residual test, is the norm of that first right-hand side.
+    Dead tractions (``face_traction``, Sec. 3's Neumann term) scale with the
+    load like the prescribed values: R(u) = F_int(u) - s f_ext on free rows.
     The paper does not say what happens when an increment fails; here an
     update that inverts a quadrature point (non-finite residual), a CG
     breakdown (p^T K p <= 0: the tangent is indefinite at the iterate), a CG
@@ -50,6 +52,8 @@ def solve(hier, face_values, n_steps, rtol=1e-8, max_cg=200, du_tol=1e-5,
     cons = hier.cons[-1]
     free = ~cons
     u = np.zeros(mesh.n_dofs) if u0 is None else np.array(u0, dtype=np.float64)
+    f_ext = fe.external_force(mesh, face_traction) if face_traction is not None else np.zeros(mesh.n_dofs)
+    f_ext[cons] = 0.0
     records = []
     h0 = 1.0 / n_steps
     done, h, cut = 0.0, h0, 0
@@ -62,7 +66,7 @@ def solve(hier, face_values, n_steps, rtol=1e-8, max_cg=200, du_tol=1e-5,
             R0 = None
             conv = False
             for it in range(max_newton):
-                R = fe.residual(mesh, hier.mat, u)
+                R = fe.residual(mesh, hier.mat, u) - target * f_ext
                 hier.set_deformation(u)
                 b = -R
                 if it == 0:
@@ -82,7 +86,7 @@ def solve(hier, face_values, n_steps, rtol=1e-8, max_cg=200, du_tol=1e-5,
                 du = d + dg if it == 0 else d
                 u += du
                 ndu = np.linalg.norm(du)
-                Rn = np.linalg.norm(fe.residual(mesh, hier.mat, u)[free])
+                Rn = np.linalg.norm((fe.residual(mesh, hier.mat, u) - target * f_ext)[free])
                 rec = dict(load_fraction=target, newton=it, res=nb, res_after=Rn, du=ndu, cg_iters=cg_it,
                            cg_rel=rel, cutbacks=cut)
                 records.append(rec)

@@ -124,6 +124,7 @@ struct mfh_problem {
   char* tmpB = nullptr;
   double *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_Ap = nullptr;
   double *nw_R = nullptr, *nw_dg = nullptr, *nw_b = nullptr, *nw_du = nullptr, *nw_save = nullptr;
+  double *f_ext = nullptr, *g1 = nullptr;   // dead-traction forces (finest level), 1-D lattice integrals
   // coarse level
   long long nf = 0;
   int* fmap = nullptr;               // dof -> free index or -1
@@ -361,6 +362,8 @@ size_t layout(mfh_problem* P, char* base) {
   P->nw_b = b.take<double>(top.ndofs);
   P->nw_du = b.take<double>(top.ndofs);
   P->nw_save = b.take<double>(top.ndofs);
+  P->f_ext = b.take<double>(top.ndofs);
+  P->g1 = b.take<double>(top.L);
   const Level& c = P->lv[0];
   P->fmap = b.take<int>(P->has_coarse ? c.ndofs : 1);
   P->dof_of = b.take<int>(std::max<long long>(1, P->nf));
@@ -772,6 +775,26 @@ void interpolate_down(mfh_problem* P, int l) {
   const Level& f = P->lv[l];
   const Level& c = P->lv[l - 1];
   transfer<double>(P, f.I1, f.L, c.L, f.u64, c.u64, false, false, c.lt);
+}
+
+// External force of dead face tractions on the finest level (Sec. 3's Neumann
+// term): the 1-D integrals of the global basis functions over [0, 1] are
+// g[I] = sum over cells e holding node I of h sum_q w_q phi_(I - p e)(x_q);
+// a face node's force is t_f times the product of g over the face's
+// tangential axes.  Constrained rows are zeroed.
+void external_force(mfh_problem* P, const double* ft, double* f) {
+  const Level& v = P->lv.back();
+  const int p = P->d.degree;
+  std::vector<double> m1(p + 1, 0.0), g(v.L, 0.0);
+  for (int b = 0; b <= p; ++b)
+    for (int q = 0; q <= p; ++q) m1[b] += v.h * P->tb64.w[q] * P->tb64.S[q][b];
+  for (int e = 0; e < v.N; ++e)
+    for (int b = 0; b <= p; ++b) g[p * e + b] += m1[b];
+  HIPCHECK(hipMemcpyAsync(P->g1, g.data(), sizeof(double) * v.L, hipMemcpyHostToDevice, P->stream));
+  HIPCHECK(hipStreamSynchronize(P->stream));   // g goes out of scope
+  traction_force(f, v.lt, ft, P->g1, v.ndofs, P->stream);
+  zero_constrained<double>(f, v.ndofs, v.lt, P->stream);
+  check_launch("external force");
 }
 
 // Builds every level operator about u (Sec. 6): enqueues the level
@@ -1251,9 +1274,9 @@ mfh_status mfh_apply_dirichlet(mfh_problem* P, double* u, const double* fv, doub
   });
 }
 
-mfh_status mfh_newton_solve(mfh_problem* P, double* u, const double* fv, int n_steps, double cg_rtol, int cg_max_it,
-                            double du_tol, double r_tol, int max_newton, mfh_newton_record* rec, int max_rec,
-                            int* n_rec) {
+mfh_status mfh_newton_solve(mfh_problem* P, double* u, const double* fv, const double* ft, int n_steps,
+                            double cg_rtol, int cg_max_it, double du_tol, double r_tol, int max_newton,
+                            mfh_newton_record* rec, int max_rec, int* n_rec) {
   if (!P) return MFH_ERR_INVALID_ARG;
   int nrec = 0;
   mfh_status st = guarded(P, [&] {
@@ -1268,6 +1291,7 @@ mfh_status mfh_newton_solve(mfh_problem* P, double* u, const double* fv, int n_s
     double done = 0.0, h = h0;
     int step = 0, cutbacks = 0;
     const int kMaxCut = 8;
+    if (ft) external_force(P, ft, P->f_ext);   // dead tractions scale with the load like fv
     while (done < 1.0 - 1e-12) {
       const double target = std::fmin(1.0, done + h);
       ++step;
@@ -1284,7 +1308,10 @@ mfh_status mfh_newton_solve(mfh_problem* P, double* u, const double* fv, int n_s
         r.load_fraction = target;
         r.cutbacks = cutbacks;
         auto t0 = Clock::now();
-        if (!have_R) residual(P, u, P->nw_R);
+        if (!have_R) {
+          residual(P, u, P->nw_R);
+          if (ft) axpby<double>(P->nw_R, P->f_ext, -target, 1.0, n, s);   // R = F_int - s f_ext
+        }
         HIPCHECK(hipStreamSynchronize(s));
         r.residual_ms = ms_since(t0);
         t0 = Clock::now();
@@ -1324,6 +1351,7 @@ mfh_status mfh_newton_solve(mfh_problem* P, double* u, const double* fv, int n_s
         r.du_norm = norm2(P, P->nw_du, n);
         t0 = Clock::now();
         residual(P, u, P->nw_R);
+        if (ft) axpby<double>(P->nw_R, P->f_ext, -target, 1.0, n, s);
         have_R = true;
         r.residual_after = norm2(P, P->nw_R, n);
         r.residual_ms += ms_since(t0);
@@ -1356,6 +1384,16 @@ mfh_status mfh_newton_solve(mfh_problem* P, double* u, const double* fv, int n_s
   });
   if (n_rec) *n_rec = nrec;
   return st;
+}
+
+mfh_status mfh_external_force(mfh_problem* P, const double* face_traction, double* f) {
+  if (!P) return MFH_ERR_INVALID_ARG;
+  return guarded(P, [&] {
+    need(face_traction && f, "NULL argument");
+    external_force(P, face_traction, P->f_ext);
+    HIPCHECK(hipMemcpyAsync(f, P->f_ext, sizeof(double) * P->lv.back().ndofs, hipMemcpyDeviceToDevice, P->stream));
+    check_launch("external force");
+  });
 }
 
 mfh_status mfh_scatter_mode(const mfh_problem* P, int level, int dtype, int* mode) {

@@ -264,6 +264,33 @@ __global__ void k_set_dirichlet(double* __restrict__ u, Lattice lt, FaceVals fv,
   }
 }
 
+// Nodal forces of dead face tractions: f[c, node] = sum over the loaded faces
+// f holding the node of t_f[c] * prod over the face's tangential axes a of
+// g[index_a], with g the 1-D lattice integrals of the global basis functions.
+__global__ void k_traction(double* __restrict__ f, Lattice lt, FaceVals tr, const double* __restrict__ g,
+                           long long n) {
+  for (long long i = blockIdx.x * (long long)kVB + threadIdx.x; i < n; i += (long long)gridDim.x * kVB) {
+    const int c = (int)(i / lt.nn);
+    long long r = i - c * lt.nn;
+    const int ix = (int)(r % lt.L);
+    r /= lt.L;
+    const int iy = (int)(r % lt.L);
+    const int iz = lt.dim == 3 ? (int)(r / lt.L) : 0;
+    const int idx[3] = {ix, iy, iz};
+    double acc = 0.0;
+    for (int axis = 0; axis < lt.dim; ++axis)
+      for (int side = 0; side < 2; ++side) {
+        if (idx[axis] != (side == 0 ? 0 : lt.L - 1)) continue;
+        double w = tr.v[2 * axis + side][c];
+        if (w == 0.0) continue;
+        for (int a = 0; a < lt.dim; ++a)
+          if (a != axis) w *= g[idx[a]];
+        acc += w;
+      }
+    f[i] = acc;
+  }
+}
+
 __global__ void k_dirichlet_delta(const double* __restrict__ u, double* __restrict__ dg, Lattice lt, FaceVals fv,
                                   double scale, long long n) {
   for (long long i = blockIdx.x * (long long)kVB + threadIdx.x; i < n; i += (long long)gridDim.x * kVB) {
@@ -572,6 +599,12 @@ void set_dirichlet(double* u, const Lattice& lt, const double* fv, double scale,
   for (int face = 0; face < 2 * lt.dim; ++face)
     for (int c = 0; c < lt.dim; ++c) f.v[face][c] = fv[face * lt.dim + c];
   hipLaunchKernelGGL(k_set_dirichlet, dim3(grid_for(n)), dim3(kVB), 0, s, u, lt, f, scale, n);
+}
+void traction_force(double* f, const Lattice& lt, const double* ft, const double* g, long long n, hipStream_t s) {
+  FaceVals t = {};
+  for (int face = 0; face < 2 * lt.dim; ++face)
+    for (int c = 0; c < lt.dim; ++c) t.v[face][c] = ft[face * lt.dim + c];
+  hipLaunchKernelGGL(k_traction, dim3(grid_for(n)), dim3(kVB), 0, s, f, lt, t, g, n);
 }
 void dirichlet_delta(const double* u, double* dg, const Lattice& lt, const double* fv, double scale, long long n,
                      hipStream_t s) {

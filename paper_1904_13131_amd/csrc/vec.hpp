@@ -93,6 +93,9 @@ template <typename T> void sweep(const T* in, T* out, const SweepArgs<T>& a, hip
 // face wins); fv is a host array of 2*dim*dim values passed to the kernel by value.
 void set_dirichlet(double* u, const Lattice& lt, const double* fv, double scale, long long n, hipStream_t s);
 // dg = constrained ? scale * fv - u : 0
+// f = nodal forces of dead face tractions ft[2*axis + side][comp] (host
+// array), g = 1-D lattice integrals of the basis functions (device, L values).
+void traction_force(double* f, const Lattice& lt, const double* ft, const double* g, long long n, hipStream_t s);
 void dirichlet_delta(const double* u, double* dg, const Lattice& lt, const double* fv, double scale,
                      long long n, hipStream_t s);
 

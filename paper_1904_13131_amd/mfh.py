@@ -83,9 +83,10 @@ def lib():
         "mfh_cg_solve": (st, [_P, _P, _P, ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _D]),
         "mfh_last_error": (ctypes.c_char_p, [_P]),
         "mfh_apply_dirichlet": (st, [_P, _P, _D, ctypes.c_double]),
-        "mfh_newton_solve": (st, [_P, _P, _D, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double,
+        "mfh_newton_solve": (st, [_P, _P, _D, _D, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_int, ctypes.POINTER(NewtonRecord), ctypes.c_int,
                                   ctypes.POINTER(ctypes.c_int)]),
+        "mfh_external_force": (st, [_P, _D, _P]),
         "mfh_level_displacement": (st, [_P, ctypes.c_int, _P]),
         "mfh_level_diagonal": (st, [_P, ctypes.c_int, _P]),
         "mfh_level_lambda_max": (st, [_P, ctypes.c_int, _D]),
@@ -243,16 +244,23 @@ class Problem:
         _check(lib().mfh_apply_dirichlet(self.handle, _ptr(u), fv, scale), self.handle)
 
     def newton_solve(self, u, face_values, n_steps, cg_rtol=1e-8, cg_max_it=200, du_tol=1e-5, r_tol=1e-8,
-                     max_newton=20, max_records=512, raise_on_error=True):
+                     max_newton=20, max_records=512, raise_on_error=True, face_traction=None):
         fv = _darr([v for row in face_values for v in row])
+        ft = _darr([v for row in face_traction for v in row]) if face_traction is not None else None
         recs = (NewtonRecord * max_records)()
         n = ctypes.c_int()
-        st = lib().mfh_newton_solve(self.handle, _ptr(u), fv, n_steps, cg_rtol, cg_max_it, du_tol, r_tol,
+        st = lib().mfh_newton_solve(self.handle, _ptr(u), fv, ft, n_steps, cg_rtol, cg_max_it, du_tol, r_tol,
                                     max_newton, recs, max_records, ctypes.byref(n))
         out = [recs[i].as_dict() for i in range(min(n.value, max_records))]
         if raise_on_error:
             _check(st, self.handle)
         return out, st
+
+    def external_force(self, face_traction, f=None):
+        ft = _darr([v for row in face_traction for v in row])
+        f = self._vec(-1, torch.float64) if f is None else f
+        _check(lib().mfh_external_force(self.handle, ft, _ptr(f)), self.handle)
+        return f
 
     def scatter_mode(self, level=-1, dtype=F64):
         """Scatter mode the vmult uses on a level (resolved when the descriptor says AUTO)."""

@@ -117,8 +117,10 @@ def test_chebyshev_and_vcycle_fp64(name):
     # With the Chebyshev coarse solver the coarse polynomial (degree ~40) is
     # built on [lambda_min, 1.2 lambda_max] from 30 Lanczos steps; the smallest
     # Ritz value is far from converged and carries the summation-order
-    # differences of the two runs at ~1e-8, which the polynomial amplifies.
-    tol = 1e-6 if c.get("coarse") == "chebyshev" else 1e-7
+    # differences of the two runs (and, with the atomic scatter of the small
+    # coarse level, of two device runs), which the polynomial amplifies to
+    # 1e-7..1.4e-6 in the V-cycle output.
+    tol = 1e-5 if c.get("coarse") == "chebyshev" else 1e-7
     assert rel_l2(z, H.vcycle(b)) <= tol
 
 
@@ -283,3 +285,68 @@ def test_eigenvalue_reuse():
             assert all(abs(a - b_) > 1e-12 * a for a, b_ in zip(lam1, lam2))
         x, it, rel, st = P.cg_solve(dev(b), rtol=1e-8, max_it=200)
         assert rel <= 1e-8
+
+
+@pytest.mark.parametrize("dim,n,p", [(3, 4, 2), (2, 5, 3), (3, 3, 4), (2, 6, 1)])
+def test_external_force_matches_oracle(dim, n, p):
+    from paper_1904_13131_amd import Problem
+    log_case("external_force", dim=dim, n=n, p=p)
+    mask = W.clamp_bottom_top(dim) if dim == 3 else W.face_bits(dim, 1, 0)
+    ft = np.zeros((2 * dim, dim))
+    ft[2 * (dim - 1) + 1] = np.linspace(0.3, -0.2, dim)        # top face
+    ft[1][0] = 0.7                                              # x = 1 face, normal component
+    P = Problem(dim, n, p, dirichlet_mask=mask)
+    f = host(P.external_force(ft))
+    m = fe.Mesh(dim, n, p)
+    want = fe.external_force(m, ft)
+    want[m.constrained(mask)] = 0.0
+    assert np.abs(f - want).max() <= 1e-14 * np.abs(want).max()
+
+
+@pytest.mark.parametrize("vdt", [F64, F32], ids=["f64", "f32"])
+def test_newton_traction_closed_form(vdt):
+    """Dead traction t on the top face of a cube on rollers: F = diag(s, s,
+    1 + delta) with P_zz = t and no lateral stress, exactly representable."""
+    from scipy.optimize import fsolve
+
+    from paper_1904_13131_amd import Problem
+    log_case("newton_traction", vcycle=vdt)
+    dim, t, mu, lam = 3, 0.08, 1.0, 1.5
+    mask = W.face_bits(dim, 2, 0, [2]) | W.face_bits(dim, 0, 0, [0]) | W.face_bits(dim, 1, 0, [1])
+    ft = np.zeros((6, 3))
+    ft[5][2] = t
+    P = Problem(dim, 8, 2, n_levels=3, mu=(mu,), lam=(lam,), dirichlet_mask=mask, vcycle_dtype=vdt)
+    u = torch.zeros(P.n_dofs(), dtype=torch.float64, device="cuda")
+    recs, st = P.newton_solve(u, np.zeros((6, 3)), n_steps=2, face_traction=ft)
+
+    def eqs(v):
+        s, d = v
+        c1 = mu - 2 * lam * np.log(s * s * (1 + d))
+        return [mu * s * s - c1, (mu * (1 + d) ** 2 - c1) / (1 + d) - t]
+    s, d = fsolve(eqs, [1.0, 0.05], xtol=1e-14)
+    X = fe.Mesh(dim, 8, 2).node_coords()
+    want = X * np.array([s - 1, s - 1, d])
+    assert np.abs(host(u).reshape(dim, -1).T - want).max() <= 1e-9
+    assert all(r["cg_relres"] <= 1e-8 for r in recs)
+
+
+def test_newton_shear_traction_matches_oracle():
+    """The paper's load path on a small heterogeneous body: bottom clamped,
+    shear traction on the top face in load steps (Sec. 7)."""
+    from paper_1904_13131_amd import Problem
+    from oracle import newton
+    log_case("newton_shear")
+    mu, lam = W.two_phase_material()
+    incl = [(np.array([0.5, 0.5]), 0.3, 1)]
+    mask = W.face_bits(2, 1, 0)
+    ft = np.zeros((4, 2))
+    ft[3][0] = 0.15
+    H = gmg.Hierarchy(2, 2, 2, 3, fe.Material(mu, lam, incl), mask)
+    u_o, recs_o = newton.solve(H, np.zeros((4, 2)), n_steps=3, face_traction=ft)
+    P = Problem(2, 8, 2, n_levels=3, mu=tuple(mu), lam=tuple(lam), inclusions=incl, dirichlet_mask=mask,
+                vcycle_dtype=F64)
+    u = torch.zeros(P.n_dofs(), dtype=torch.float64, device="cuda")
+    recs, st = P.newton_solve(u, np.zeros((4, 2)), n_steps=3, face_traction=ft)
+    assert len(recs) == len(recs_o)
+    assert rel_l2(host(u), u_o) <= 1e-8
+    assert np.abs(host(u)).max() > 0.05        # a visible shear deformation

@@ -53,3 +53,46 @@ def test_cutback_reaches_the_same_equilibrium():
     assert [r["load_fraction"] for r in r1 if not np.isfinite(r["cg_rel"])] == [1.0, 1.0]
     assert r1[-1]["load_fraction"] == 1.0
     assert np.linalg.norm(u1 - u4) <= 1e-10 * np.linalg.norm(u4)
+
+
+@pytest.mark.parametrize("dim,p", [(3, 2), (2, 3), (3, 1)])
+def test_external_force_totals(dim, p):
+    """The nodal forces of a constant traction on a unit face sum to the
+    traction (times the face area 1) per component, vanish off the face, and
+    reproduce the face integral of a linear field (first moments)."""
+    m = fe.Mesh(dim, 3, p)
+    ft = np.zeros((2 * dim, dim))
+    ft[2 * (dim - 1) + 1] = np.arange(1, dim + 1)        # top face
+    f = fe.external_force(m, ft)
+    X = m.node_coords()
+    top = np.abs(X[:, dim - 1] - 1.0) < 1e-12
+    for c in range(dim):
+        fc = f[c * m.n_nodes:(c + 1) * m.n_nodes]
+        assert abs(fc.sum() - (c + 1)) < 1e-13
+        assert np.all(fc[~top] == 0)
+        # sum_a f_a X_a = t * integral of X over the face = t * 1/2 (first tangential axis)
+        assert abs((fc * X[:, 0]).sum() - 0.5 * (c + 1)) < 1e-13
+
+
+def test_uniaxial_traction_closed_form():
+    """Traction control: a dead traction t on the top face of a cube on
+    rollers gives the homogeneous state F = diag(s, s, 1 + delta) with zero
+    lateral stress and first Piola stress P_zz = t; the state is affine, so
+    the discrete solution equals it."""
+    dim, mu, lam, t = 3, 1.0, 1.5, 0.08
+    mat = fe.Material([mu], [lam])
+    mask = W.face_bits(dim, 2, 0, [2]) | W.face_bits(dim, 0, 0, [0]) | W.face_bits(dim, 1, 0, [1])
+    H = gmg.Hierarchy(dim, 1, 2, 2, mat, mask)
+    ft = np.zeros((6, 3))
+    ft[5][2] = t
+    u, recs = newton.solve(H, np.zeros((6, 3)), n_steps=2, face_traction=ft)
+    # lateral: mu s^2 = c1, axial: P_zz = (mu (1+d)^2 - c1) / (1+d) = t, c1 = mu - 2 lam ln(s^2 (1+d))
+    def eqs(v):
+        s, d = v
+        c1 = mu - 2 * lam * np.log(s * s * (1 + d))
+        return [mu * s * s - c1, (mu * (1 + d) ** 2 - c1) / (1 + d) - t]
+    from scipy.optimize import fsolve
+    s, d = fsolve(eqs, [1.0, 0.05], xtol=1e-14)
+    X = H.meshes[-1].node_coords()
+    want = X * np.array([s - 1, s - 1, d])
+    np.testing.assert_allclose(u.reshape(dim, -1).T, want, atol=1e-9)
