@@ -131,6 +131,88 @@ def cpu_baseline(w, n_sample_cells=32768):
             "host_threads_available": os.cpu_count()}
 
 
+MB_CASES = ((1, 64), (2, 32), (3, 21), (4, 16))   # (degree, cells per direction): 0.79-0.82 M DoFs
+
+
+def _time_ms(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def matrix_based_bench(steps=20, warmup=3, library_spmv=True):
+    """Matrix-free vmult against the matrix-based operator (K_c assembled in
+    CSR, one SpMV per step) for Q1-Q4 at about 0.8 M DoFs, with the memory
+    each needs per DoF."""
+    import torch
+
+    import workloads as W
+    from paper_1904_13131_amd import Problem
+    out = []
+    for deg, nc in MB_CASES:
+        w = W.problem(3, nc, deg, n_spheres=20, sphere_seed=3, u_seed=4, u_amp=0.1, u_kmax=1, x_seed=5)
+        u = torch.as_tensor(w["u"], device="cuda")
+        x = torch.as_tensor(w["x"], device="cuda")
+        y = torch.empty_like(x)
+        row = {"degree": deg, "cells": nc ** 3}
+        for pol in (0, 2):
+            P = Problem(3, nc, deg, mu=tuple(w["mu"]), lam=tuple(w["lam"]), inclusions=w["inclusions"],
+                        qp_policy=pol)
+            P.set_deformation(u)
+            n = P.n_dofs()
+            ms = _time_ms(lambda: P.tangent_vmult(x, y), steps, warmup)
+            nq = (deg + 1) ** 3
+            mem = 8 * n + CACHE_WORDS[3][pol] * nq * nc ** 3 * 8 + 4 * nc ** 3 * ((nq + 31) // 32)
+            row[f"mf_{POLICIES[pol]}"] = {"ms": ms, "dofs_per_s": n / (ms * 1e-3), "bytes_per_dof": mem / n}
+            if pol == 0:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                csr = P.csr_assemble()
+                t_asm = time.perf_counter() - t0
+                rows, nnz = P.csr_size()
+                yc = torch.empty_like(x)
+                ms_c = _time_ms(lambda: P.csr_spmv(csr, x, yc), steps, warmup)
+                ref = P.tangent_vmult(x)
+                err = float((yc - ref).norm() / ref.norm())
+                nbytes = 12 * nnz + 8 * (rows + 1) + 16 * rows
+                row["n_dofs"] = n
+                row["csr"] = {"ms": ms_c, "dofs_per_s": n / (ms_c * 1e-3), "nnz": nnz,
+                              "nnz_per_row": nnz / rows, "bytes_per_dof": (12 * nnz + 8 * (rows + 1)) / n,
+                              "assembly_s": t_asm, "alg_bytes": nbytes,
+                              "achieved_gbs": nbytes / (ms_c * 1e-3) / 1e9,
+                              "frac_hbm": nbytes / (ms_c * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                              "hbm_bound_ms": nbytes / (HBM_PEAK_GBS * 1e9) * 1e3, "rel_err_vs_mf": err}
+                if library_spmv:
+                    try:
+                        A = torch.sparse_csr_tensor(csr[0], csr[1].long(), csr[2], (rows, rows))
+                        ms_l = _time_ms(lambda: torch.mv(A, x), steps, warmup)
+                        err_l = float((torch.mv(A, x) - ref).norm() / ref.norm())
+                        row["csr_torch_sparse"] = {"ms": ms_l, "rel_err_vs_mf": err_l}
+                        del A
+                    except RuntimeError as e:
+                        row["csr_torch_sparse"] = {"error": str(e)[:200]}
+                del csr
+            del P
+            torch.cuda.empty_cache()
+        mf_best = min(row["mf_recompute"]["ms"], row["mf_cache_T2"]["ms"])
+        row["mf_speedup_vs_csr"] = row["csr"]["ms"] / mf_best
+        row["mf_speedup_vs_csr_at_hbm_peak"] = row["csr"]["hbm_bound_ms"] / mf_best
+        print(f"[bench] matrix-based Q{deg} {nc}^3: CSR {row['csr']['ms'] * 1e3:.1f} us "
+              f"({row['csr']['bytes_per_dof']:.0f} B/DoF, {row['csr']['achieved_gbs']:.0f} GB/s), MF recompute "
+              f"{row['mf_recompute']['ms'] * 1e3:.1f} us, MF cache_T2 {row['mf_cache_T2']['ms'] * 1e3:.1f} us "
+              f"({row['mf_cache_T2']['bytes_per_dof']:.0f} B/DoF)", file=sys.stderr, flush=True)
+        out.append(row)
+    return out
+
+
 def newton_bench(w, n_cells=64, n_levels=5, stretch=0.1, n_steps=4, shear_traction=0.1):
     """Config 3: Newton load stepping with GMG-CG (1e-8) on the config-2 material,
     64^3 Q2 (6.44M DoFs), levels 4^3..64^3, clamped bottom/top, 10 % stretch in
@@ -431,6 +513,8 @@ def main(argv=None):
     ap.add_argument("--no-batch-solve", action="store_true", help="config 4: time the batched vmult only")
     ap.add_argument("--config5", action="store_true", help="also run config 5 (Q4 48^3 Newton, minutes)")
     ap.add_argument("--config5-vmult-only", action="store_true", help="config 5: level vmults only, no Newton")
+    ap.add_argument("--no-matrix-based", action="store_true", help="skip the CSR matrix-based comparison")
+    ap.add_argument("--matrix-based-only", action="store_true", help="only the CSR matrix-based comparison")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 256 MiB device copy (reference for HBM byte counters)")
     a = ap.parse_args(argv)
@@ -446,6 +530,9 @@ def main(argv=None):
     from paper_1904_13131_amd.mfh import SCATTER_NAMES
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if a.matrix_based_only:
+        print(json.dumps({"partial": True, "matrix_based": matrix_based_bench()}), flush=True)
+        return 0
     w = W.config2()
     dim, nc, deg = w["dim"], w["n_cells"], w["degree"]
     u = torch.as_tensor(w["u"], device="cuda")
@@ -520,6 +607,8 @@ def main(argv=None):
     }
     out["roofline"]["kernel_ms"] = r["kernel_ms"]
     out["roofline"]["kernel_ms_cold"] = r["kernel_ms_cold"]
+    if not a.no_matrix_based:
+        out["matrix_based"] = matrix_based_bench()
     if not a.no_newton:
         out["newton_step"] = newton_bench(w)
     if not a.no_batch:

@@ -189,6 +189,31 @@ mfh_status mfh_set_deformation(mfh_problem* problem, const double* u_dev, double
 mfh_status mfh_tangent_vmult(mfh_problem* problem, int level, int dtype,
                              const void* x_dev, void* y_dev);
 
+/* ---- Matrix-based baseline: K_c in CSR form ---- */
+
+/* Sizes of the CSR form of a level's constrained tangent K_c (the matrix of
+ * eq. algebraic_tangent with the constraints of Sec. 3), the operator of the
+ * matrix-based approach that Sec. 4 and Sec. 7.1 compare against.  n_rows = dim * nodes, DoF numbering as the vectors.
+ * A free row lists every DoF of the cells that hold its node, component-major
+ * and by ascending node index within a component (constrained columns stay as
+ * stored zeros); a constrained row holds its diagonal only.  Host outputs, no
+ * device work.  Errors: INVALID_ARG. */
+mfh_status mfh_csr_size(mfh_problem* problem, int level, long long* n_rows_host, long long* nnz_host);
+
+/* Fills caller-allocated device arrays with K_c of the level at the current
+ * linearisation point: row_ptr (n_rows + 1 int64), col (nnz int32, sorted
+ * within each row), val (nnz FP64).  Element matrices are added with atomics,
+ * so values may differ from run to run in the last bits.  Synchronises.
+ * Errors: INVALID_ARG (also for n_rows >= 2^31), HIP. */
+mfh_status mfh_csr_assemble(mfh_problem* problem, int level, long long* row_ptr_dev, int* col_dev,
+                            double* val_dev);
+
+/* y = A x (FP64) for the CSR arrays written by mfh_csr_assemble for this
+ * level; one wavefront per row.  Async on the problem's stream.
+ * Errors: INVALID_ARG, HIP. */
+mfh_status mfh_csr_spmv(mfh_problem* problem, int level, const long long* row_ptr_dev, const int* col_dev,
+                        const double* val_dev, const double* x_dev, double* y_dev);
+
 /* r = residual of the weak form at displacement u on the finest level
  * (eq. linear_system, volume term; FP64), zero on constrained rows.  u is any
  * device FP64 displacement (not necessarily the linearisation point).  Async.

@@ -1444,17 +1444,88 @@ __global__ void __launch_bounds__(kBlock) k_diag(CellArgs<double> a) {
     if (!(f & a.fmask[al])) atomic_add(a.y + al * a.nn + node, acc[al]);
 }
 
-// Dense coarse-level tangent over free DoFs (FP64), one block per cell and one
-// thread per cell node a.  With v = F^-T Grad N (spatial gradient of a shape
-// function) the tangent entry of eq. (algebraic_tangent) between DoFs (a, i)
-// and (b, k) is, for this material law,
+// Destination of assembled element-matrix entries: the dense coarse matrix
+// over free DoFs, K[fi * nf + fj] with fi / fj the free indices of the two
+// DoFs (fmap = -1 on constrained DoFs).
+struct DenseSink {
+  const int* fmap;
+  long long nf;
+  double* K;
+  long long fi[3];
+  template <int DIM>
+  __device__ void begin(const CellArgs<double>& a, long long node, int, int, int) {
+    for (int i = 0; i < DIM; ++i) fi[i] = fmap[i * a.nn + node];
+  }
+  template <int DIM>
+  __device__ void add(const CellArgs<double>& a, long long nodeb, int, int, int, const double (&acc)[DIM][DIM]) {
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      const int fj = fmap[k * a.nn + nodeb];
+      if (fj < 0) continue;
+#pragma unroll
+      for (int i = 0; i < DIM; ++i)
+        if (fi[i] >= 0) atomic_add(K + fi[i] * nf + fj, acc[i][k]);
+    }
+  }
+};
+
+// Destination for the CSR form of K_c.  Row (i, node a) of a free DoF holds
+// the columns (k, node b) for every component k and every node b of the
+// cells that contain a, component-major and lexicographic within a
+// component; per axis the node range of those cells is [lo, lo + len), so the
+// position of a column is computed, not searched.  Rows of constrained DoFs
+// hold their diagonal only and are skipped here, as are constrained columns.
+__device__ __forceinline__ void csr_axis_range(int I, int P, int L, int& lo, int& len) {
+  if (I % P != 0) {
+    lo = I - I % P;
+    len = P + 1;
+  } else {
+    lo = I - P > 0 ? I - P : 0;
+    len = (I + P < L - 1 ? I + P : L - 1) - lo + 1;
+  }
+}
+
+struct CsrSink {
+  const long long* row_ptr;
+  double* val;
+  int P;
+  long long base[3];   // row start of (i, a); -1 for a constrained row
+  int lo[3], len[3];
+  long long blk;       // columns per component
+  template <int DIM>
+  __device__ void begin(const CellArgs<double>& a, long long node, int I, int J, int K) {
+    const unsigned f = node_faces(I, J, K, a.L, DIM);
+    csr_axis_range(I, P, a.L, lo[0], len[0]);
+    csr_axis_range(J, P, a.L, lo[1], len[1]);
+    lo[2] = 0;
+    len[2] = 1;
+    if (DIM == 3) csr_axis_range(K, P, a.L, lo[2], len[2]);
+    blk = (long long)len[0] * len[1] * len[2];
+    for (int i = 0; i < DIM; ++i) base[i] = (f & a.fmask[i]) ? -1 : row_ptr[i * a.nn + node];
+  }
+  template <int DIM>
+  __device__ void add(const CellArgs<double>& a, long long, int Ib, int Jb, int Kb, const double (&acc)[DIM][DIM]) {
+    const unsigned fb = node_faces(Ib, Jb, Kb, a.L, DIM);
+    const long long off = ((long long)(Kb - lo[2]) * len[1] + (Jb - lo[1])) * len[0] + (Ib - lo[0]);
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+      if (fb & a.fmask[k]) continue;
+#pragma unroll
+      for (int i = 0; i < DIM; ++i)
+        if (base[i] >= 0) atomic_add(val + base[i] + k * blk + off, acc[i][k]);
+    }
+  }
+};
+
+// Element tangent of one cell (FP64), one block per cell and one thread per
+// cell node a, added into a Sink.  With v = F^-T Grad N (spatial gradient of a
+// shape function) the tangent entry of eq. (algebraic_tangent) between DoFs
+// (a, i) and (b, k) is, for this material law,
 //   sum_q w_q |cell| [ c1 v_a,k v_b,i + 2 lambda v_a,i v_b,k + mu delta_ik Grad N_a . Grad N_b ]
 // (material part with J c = 2 c1 Ssym + 2 lambda I (x) I, geometric part with
-// tau = mu b - c1 I).  Entries are added atomically into K[fi * nf + fj],
-// fi / fj the free indices of the two DoFs (fmap = -1 on constrained DoFs).
-template <int DIM, int P>
-__global__ void __launch_bounds__(kBlock) k_coarse_assemble(CellArgs<double> a, const int* __restrict__ fmap,
-                                                             long long nf, double* __restrict__ K) {
+// tau = mu b - c1 I).
+template <int DIM, int P, typename Sink>
+__global__ void __launch_bounds__(kBlock) k_cell_matrix(CellArgs<double> a, Sink sink) {
   using D = double;
   constexpr int N1 = P + 1;
   constexpr int NV = DIM == 3 ? N1 * N1 * N1 : N1 * N1;
@@ -1507,9 +1578,7 @@ __global__ void __launch_bounds__(kBlock) k_coarse_assemble(CellArgs<double> a, 
   }
   __syncthreads();
   if (!act) return;
-  int fi[DIM];
-#pragma unroll
-  for (int i = 0; i < DIM; ++i) fi[i] = fmap[i * a.nn + node];
+  sink.template begin<DIM>(a, node, ex * P + ax, ey * P + ay, ez * P + az);
   const D hd = a.wscale / a.invh;   // h^d
   for (int b = 0; b < NV; ++b) {
     const int bx = b % N1, by = (b / N1) % N1, bz = DIM == 3 ? b / (N1 * N1) : 0;
@@ -1559,14 +1628,7 @@ __global__ void __launch_bounds__(kBlock) k_coarse_assemble(CellArgs<double> a, 
           acc[i][k] += wq * (c1 * va[k] * vb[i] + l2 * va[i] * vb[k] + (i == k ? mu * gg : 0.0));
     }
     const long long nodeb = (ex * P + bx) + (long long)a.L * ((ey * P + by) + (long long)a.L * (ez * P + bz));
-#pragma unroll
-    for (int k = 0; k < DIM; ++k) {
-      const int fj = fmap[k * a.nn + nodeb];
-      if (fj < 0) continue;
-#pragma unroll
-      for (int i = 0; i < DIM; ++i)
-        if (fi[i] >= 0) atomic_add(K + (long long)fi[i] * nf + fj, acc[i][k]);
-    }
+    sink.template add<DIM>(a, nodeb, ex * P + bx, ey * P + by, ez * P + bz, acc);
   }
 }
 

@@ -32,6 +32,9 @@ struct OpFns {
                               float* const* ys, unsigned n_items, hipStream_t);
   void (*coarse_assemble)(const CellArgs<double>&, const int* fmap, long long nf, double* K,
                           unsigned grid, hipStream_t);
+  // element tangents added into the CSR values of K_c (pattern of the lattice)
+  void (*csr_assemble)(const CellArgs<double>&, const long long* row_ptr, double* val, unsigned grid,
+                       hipStream_t);
   int cpb;        // cells per block of the pencil kernels
   int cpb_diag;   // cells per block of the diagonal kernel
   int cache_words[3];

@@ -83,7 +83,13 @@ struct OpInst {
   }
   static void coarse_assemble(const CellArgs<double>& a, const int* fmap, long long nf, double* K,
                               unsigned grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_coarse_assemble<DIM, P>), dim3(grid), dim3(kBlock), 0, s, a, fmap, nf, K);
+    DenseSink sink{fmap, nf, K, {}};
+    hipLaunchKernelGGL((k_cell_matrix<DIM, P, DenseSink>), dim3(grid), dim3(kBlock), 0, s, a, sink);
+  }
+  static void csr_assemble(const CellArgs<double>& a, const long long* row_ptr, double* val, unsigned grid,
+                           hipStream_t s) {
+    CsrSink sink{row_ptr, val, P, {}, {}, {}, 0};
+    hipLaunchKernelGGL((k_cell_matrix<DIM, P, CsrSink>), dim3(grid), dim3(kBlock), 0, s, a, sink);
   }
   static const OpFns* table() {
     static const OpFns t = {
@@ -103,6 +109,7 @@ struct OpInst {
         &elem_gather_batch<double>,
         &elem_gather_batch<float>,
         &coarse_assemble,
+        &csr_assemble,
         Geo<DIM, P + 1>::CPB,
         kBlock / (DIM == 3 ? (P + 1) * (P + 1) * (P + 1) : (P + 1) * (P + 1)),
         {CacheWords<DIM, POL_R>::value, CacheWords<DIM, POL_CF>::value, CacheWords<DIM, POL_C2>::value},

@@ -1083,6 +1083,40 @@ mfh_status guarded(mfh_problem* P, F&& f) {
   }
 }
 
+// Row pointer of the CSR form of K_c on a level (see csr_pattern): a free row
+// holds dim * prod over the axes of the node range of the cells holding its
+// node, a constrained row its diagonal.
+std::vector<long long> csr_row_ptr(const mfh_problem* P, const Level& v) {
+  const int p = P->d.degree, L = v.L, dim = P->d.dim;
+  std::vector<long long> len(L);
+  for (int I = 0; I < L; ++I) {
+    const int lo = I % p ? I - I % p : std::max(0, I - p);
+    const int hi = I % p ? lo + p : std::min(L - 1, I + p);
+    len[I] = hi - lo + 1;
+  }
+  std::vector<long long> rp(v.ndofs + 1);
+  rp[0] = 0;
+  long long r = 0;
+  for (int c = 0; c < dim; ++c)
+    for (int K = 0; K < (dim == 3 ? L : 1); ++K)
+      for (int J = 0; J < L; ++J)
+        for (int I = 0; I < L; ++I, ++r) {
+          unsigned f = (I == 0 ? 1u : 0u) | (I == L - 1 ? 2u : 0u) | (J == 0 ? 4u : 0u) | (J == L - 1 ? 8u : 0u);
+          if (dim == 3) f |= (K == 0 ? 16u : 0u) | (K == L - 1 ? 32u : 0u);
+          const long long n = (f & v.lt.fmask[c]) ? 1 : dim * len[I] * len[J] * (dim == 3 ? len[K] : 1);
+          rp[r + 1] = rp[r] + n;
+        }
+  return rp;
+}
+
+// Lanes per row of the CSR SpMV: 16 for mean rows up to 100 entries, else 8
+// (measured on the 3-D lattice patterns of degrees 1 to 4).
+int csr_group(const mfh_problem* P) {
+  const int p = P->d.degree, dim = P->d.dim;
+  const double ml = (double)(2 * p + 1 + (p - 1) * (p + 1)) / p;   // mean node range per axis (interior)
+  return dim * std::pow(ml, dim) <= 100.0 ? 16 : 8;
+}
+
 void need(bool c, const char* m) {
   if (!c) throw Error(MFH_ERR_INVALID_ARG, m);
 }
@@ -1208,6 +1242,48 @@ mfh_status mfh_tangent_vmult(mfh_problem* P, int level, int dtype, const void* x
     else
       need(false, "dtype must be MFH_F64 or MFH_F32");
     check_launch("tangent_vmult");
+  });
+}
+
+mfh_status mfh_csr_size(mfh_problem* P, int level, long long* n_rows, long long* nnz) {
+  if (!P) return MFH_ERR_INVALID_ARG;
+  return guarded(P, [&] {
+    check_level(P, level);
+    need(n_rows && nnz, "n_rows/nnz is NULL");
+    const Level& v = P->lv[level];
+    *n_rows = v.ndofs;
+    *nnz = csr_row_ptr(P, v).back();
+  });
+}
+
+mfh_status mfh_csr_assemble(mfh_problem* P, int level, long long* row_ptr, int* col, double* val) {
+  if (!P) return MFH_ERR_INVALID_ARG;
+  return guarded(P, [&] {
+    check_level(P, level);
+    need(row_ptr && col && val, "row_ptr/col/val is NULL");
+    need(P->deformed, "set_deformation has not succeeded yet");
+    const Level& v = P->lv[level];
+    need(v.ndofs < (1LL << 31), "more than 2^31 - 1 rows: the column indices are int32");
+    const std::vector<long long> rp = csr_row_ptr(P, v);
+    HIPCHECK(hipMemcpyAsync(row_ptr, rp.data(), sizeof(long long) * rp.size(), hipMemcpyHostToDevice, P->stream));
+    HIPCHECK(hipStreamSynchronize(P->stream));   // rp is pageable and local
+    csr_pattern(row_ptr, col, val, v.lt, P->d.degree, v.ndofs, P->stream);
+    CellArgs<double> a = cell_args<double>(P, v, v.u64, nullptr, nullptr, nullptr);
+    P->ops->csr_assemble(a, row_ptr, val, (unsigned)v.ncells, P->stream);
+    check_launch("csr_assemble");
+    HIPCHECK(hipStreamSynchronize(P->stream));
+  });
+}
+
+mfh_status mfh_csr_spmv(mfh_problem* P, int level, const long long* row_ptr, const int* col, const double* val,
+                        const double* x, double* y) {
+  if (!P) return MFH_ERR_INVALID_ARG;
+  return guarded(P, [&] {
+    check_level(P, level);
+    need(row_ptr && col && val && x && y, "row_ptr/col/val/x/y is NULL");
+    need(x != y, "x and y must not overlap");
+    csr_spmv(row_ptr, col, val, x, y, P->lv[level].ndofs, csr_group(P), P->stream);
+    check_launch("csr_spmv");
   });
 }
 

@@ -291,6 +291,87 @@ __global__ void k_traction(double* __restrict__ f, Lattice lt, FaceVals tr, cons
   }
 }
 
+// CSR pattern of K_c on the lattice, one thread per row: a free row (c, node)
+// lists component-major the nodes of the cells holding the node (per axis the
+// range [lo, lo + len) of csr_axis_range, x fastest), a constrained row its
+// diagonal only (value 1).  Values of free rows start at zero.
+__device__ __forceinline__ void csr_range(int I, int P, int L, int& lo, int& len) {
+  if (I % P != 0) {
+    lo = I - I % P;
+    len = P + 1;
+  } else {
+    lo = I - P > 0 ? I - P : 0;
+    len = (I + P < L - 1 ? I + P : L - 1) - lo + 1;
+  }
+}
+
+__global__ void k_csr_pattern(const long long* __restrict__ row_ptr, int* __restrict__ col,
+                              double* __restrict__ val, Lattice lt, int P, long long n) {
+  for (long long r = blockIdx.x * (long long)kVB + threadIdx.x; r < n; r += (long long)gridDim.x * kVB) {
+    const long long p0 = row_ptr[r];
+    if (constrained_dof(lt, r)) {
+      col[p0] = (int)r;
+      val[p0] = 1.0;
+      continue;
+    }
+    const int c = (int)(r / lt.nn);
+    long long m = r - c * lt.nn;
+    const int I = (int)(m % lt.L);
+    m /= lt.L;
+    const int J = (int)(m % lt.L);
+    const int K = lt.dim == 3 ? (int)(m / lt.L) : 0;
+    int lo[3] = {0, 0, 0}, len[3] = {1, 1, 1};
+    csr_range(I, P, lt.L, lo[0], len[0]);
+    csr_range(J, P, lt.L, lo[1], len[1]);
+    if (lt.dim == 3) csr_range(K, P, lt.L, lo[2], len[2]);
+    long long q = p0;
+    for (int k = 0; k < lt.dim; ++k)
+      for (int z = lo[2]; z < lo[2] + len[2]; ++z)
+        for (int y = lo[1]; y < lo[1] + len[1]; ++y)
+          for (int x = lo[0]; x < lo[0] + len[0]; ++x) {
+            col[q] = (int)(k * lt.nn + x + (long long)lt.L * (y + (long long)lt.L * z));
+            val[q] = 0.0;
+            ++q;
+          }
+  }
+}
+
+// y = A x for a CSR matrix (FP64).  A group of G lanes per row (64 / G rows
+// per wavefront), U entries per lane loaded before their products are summed
+// (loads in flight hide the latency of the dependent x gathers), then a
+// butterfly sum inside the group.  Small groups with deep unrolling measured
+// fastest on the lattice patterns (mean rows of 80-650 entries); non-temporal
+// loads of the matrix were slower.
+template <int G, int U>
+__global__ void __launch_bounds__(256) k_csr_spmv(const long long* __restrict__ row_ptr, const int* __restrict__ col,
+                                                  const double* __restrict__ val, const double* __restrict__ x,
+                                                  double* __restrict__ y, long long n) {
+  constexpr int RPW = 64 / G;   // rows per wavefront
+  const int lane = threadIdx.x & 63;
+  const long long r = ((long long)blockIdx.x * 4 + (threadIdx.x >> 6)) * RPW + lane / G;
+  const int l = lane % G;
+  double s = 0.0;
+  if (r < n) {
+    const long long e = row_ptr[r + 1];
+    long long q = row_ptr[r] + l;
+    for (; q + (U - 1) * G < e; q += U * G) {
+      double v[U];
+      int c[U];
+#pragma unroll
+      for (int k = 0; k < U; ++k) {
+        v[k] = val[q + k * G];
+        c[k] = col[q + k * G];
+      }
+#pragma unroll
+      for (int k = 0; k < U; ++k) s += v[k] * x[c[k]];
+    }
+    for (; q < e; q += G) s += val[q] * x[col[q]];
+  }
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (r < n && l == 0) y[r] = s;
+}
+
 __global__ void k_dirichlet_delta(const double* __restrict__ u, double* __restrict__ dg, Lattice lt, FaceVals fv,
                                   double scale, long long n) {
   for (long long i = blockIdx.x * (long long)kVB + threadIdx.x; i < n; i += (long long)gridDim.x * kVB) {
@@ -605,6 +686,20 @@ void traction_force(double* f, const Lattice& lt, const double* ft, const double
   for (int face = 0; face < 2 * lt.dim; ++face)
     for (int c = 0; c < lt.dim; ++c) t.v[face][c] = ft[face * lt.dim + c];
   hipLaunchKernelGGL(k_traction, dim3(grid_for(n)), dim3(kVB), 0, s, f, lt, t, g, n);
+}
+void csr_pattern(const long long* row_ptr, int* col, double* val, const Lattice& lt, int P, long long n,
+                 hipStream_t s) {
+  hipLaunchKernelGGL(k_csr_pattern, dim3(grid_for(n)), dim3(kVB), 0, s, row_ptr, col, val, lt, P, n);
+}
+void csr_spmv(const long long* row_ptr, const int* col, const double* val, const double* x, double* y, long long n,
+              int group, hipStream_t s) {
+  if (n == 0) return;
+  const long long rows_per_block = 4 * (64 / group);
+  const dim3 grid((unsigned)((n + rows_per_block - 1) / rows_per_block));
+  if (group == 16)
+    hipLaunchKernelGGL((k_csr_spmv<16, 4>), grid, dim3(256), 0, s, row_ptr, col, val, x, y, n);
+  else
+    hipLaunchKernelGGL((k_csr_spmv<8, 8>), grid, dim3(256), 0, s, row_ptr, col, val, x, y, n);
 }
 void dirichlet_delta(const double* u, double* dg, const Lattice& lt, const double* fv, double scale, long long n,
                      hipStream_t s) {

@@ -96,6 +96,12 @@ void set_dirichlet(double* u, const Lattice& lt, const double* fv, double scale,
 // f = nodal forces of dead face tractions ft[2*axis + side][comp] (host
 // array), g = 1-D lattice integrals of the basis functions (device, L values).
 void traction_force(double* f, const Lattice& lt, const double* ft, const double* g, long long n, hipStream_t s);
+// CSR form of K_c: pattern (columns, identity rows, zero values) and y = A x.
+void csr_pattern(const long long* row_ptr, int* col, double* val, const Lattice& lt, int P, long long n,
+                 hipStream_t s);
+// group: lanes per row, 8 (eight entries per lane in flight) or 16 (four)
+void csr_spmv(const long long* row_ptr, const int* col, const double* val, const double* x, double* y, long long n,
+              int group, hipStream_t s);
 void dirichlet_delta(const double* u, double* dg, const Lattice& lt, const double* fv, double scale,
                      long long n, hipStream_t s);
 

@@ -108,6 +108,9 @@ def lib():
         "mfh_scatter_mode": (st, [_P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
         "mfh_timer_enable": (st, [_P, ctypes.c_int]),
         "mfh_timer_read": (st, [_P, _D, ctypes.POINTER(ctypes.c_longlong)]),
+        "mfh_csr_size": (st, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong)]),
+        "mfh_csr_assemble": (st, [_P, ctypes.c_int, _P, _P, _P]),
+        "mfh_csr_spmv": (st, [_P, ctypes.c_int, _P, _P, _P, _P, _P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -261,6 +264,33 @@ class Problem:
         f = self._vec(-1, torch.float64) if f is None else f
         _check(lib().mfh_external_force(self.handle, ft, _ptr(f)), self.handle)
         return f
+
+    def csr_size(self, level=-1):
+        """(n_rows, nnz) of the CSR form of K_c on a level."""
+        n, z = ctypes.c_longlong(), ctypes.c_longlong()
+        _check(lib().mfh_csr_size(self.handle, level % self.n_levels, ctypes.byref(n), ctypes.byref(z)), self.handle)
+        return n.value, z.value
+
+    def csr_assemble(self, level=-1):
+        """K_c of a level at the linearisation point as device CSR arrays
+        (row_ptr int64, col int32, val float64)."""
+        level = level % self.n_levels
+        n, nnz = self.csr_size(level)
+        rp = torch.empty(n + 1, dtype=torch.int64, device=self.device)
+        col = torch.empty(nnz, dtype=torch.int32, device=self.device)
+        val = torch.empty(nnz, dtype=torch.float64, device=self.device)
+        _check(lib().mfh_csr_assemble(self.handle, level, _ptr(rp), _ptr(col), _ptr(val)), self.handle)
+        return rp, col, val
+
+    def csr_spmv(self, csr, x, y=None, level=-1):
+        """y = A x for the arrays of csr_assemble (FP64)."""
+        level = level % self.n_levels
+        rp, col, val = csr
+        assert x.dtype == torch.float64 and x.is_contiguous() and x.numel() == self.n_dofs(level)
+        y = self._vec(level, torch.float64) if y is None else y
+        _check(lib().mfh_csr_spmv(self.handle, level, _ptr(rp), _ptr(col), _ptr(val), _ptr(x), _ptr(y)),
+               self.handle)
+        return y
 
     def scatter_mode(self, level=-1, dtype=F64):
         """Scatter mode the vmult uses on a level (resolved when the descriptor says AUTO)."""
