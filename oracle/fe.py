@@ -172,9 +172,10 @@ class Mesh:
 
 
 class Material:
-    """Piecewise-constant Neo-Hookean parameters.
+    """Piecewise-constant material parameters.
 
-    ``mu[m]``, ``lam[m]`` for material m (0 = matrix).  ``inclusions`` is a list
+    ``mu[m]``, ``lam[m]`` for material m (0 = matrix); ``mu2[m]`` the
+    second-invariant modulus of the Mooney-Rivlin law (zero: Neo-Hookean).  ``inclusions`` is a list
     of (centre, radius, material_id); a point X belongs to an inclusion when
     |X - centre|^2 <= radius^2, later inclusions overriding earlier ones.  The
     indicator is sampled at every quadrature point's reference position on
@@ -182,9 +183,10 @@ class Material:
     spheres are not mesh-aligned).
     """
 
-    def __init__(self, mu, lam, inclusions=()):
+    def __init__(self, mu, lam, inclusions=(), mu2=None):
         self.mu = np.asarray(mu, dtype=np.float64)
         self.lam = np.asarray(lam, dtype=np.float64)
+        self.mu2 = np.zeros_like(self.mu) if mu2 is None else np.asarray(mu2, dtype=np.float64)
         self.inclusions = [(np.asarray(c, dtype=np.float64), float(r), int(m))
                            for (c, r, m) in inclusions]
 
@@ -200,6 +202,9 @@ class Material:
         ids = self.ids_at(mesh.qp_coords(cells))
         return self.mu[ids], self.lam[ids]                             # (nc, nQ)
 
+    def mu2_at(self, mesh, cells):
+        return self.mu2[self.ids_at(mesh.qp_coords(cells))]
+
 
 # --- element kernels -----------------------------------------------------------
 
@@ -213,7 +218,7 @@ def deformation_gradient(mesh, u, cells):
 def element_residual(mesh, mat, u, cells):
     F = deformation_gradient(mesh, u, cells)
     mu, lam = mat.params(mesh, cells)
-    P = material.pk1(F, mu, lam)
+    P = material.pk1(F, mu, lam, mat.mu2_at(mesh, cells))
     return np.einsum("q,qaI,cqiI->cia", mesh.W, mesh.G, P)            # (nc, d, nA)
 
 
@@ -226,7 +231,7 @@ def element_tangent(mesh, mat, u, cells):
     """
     F = deformation_gradient(mesh, u, cells)
     mu, lam = mat.params(mesh, cells)
-    A = material.dP_dF(F, mu, lam)                                     # (nc, nQ, d, d, d, d)
+    A = material.dP_dF(F, mu, lam, mat.mu2_at(mesh, cells))           # (nc, nQ, d, d, d, d)
     nc, nq, d = A.shape[0], A.shape[1], A.shape[2]
     nA = mesh.G.shape[1]
     AG = np.einsum("cqiIkL,qbL->cqiIkb", A, mesh.G)                    # (nc, nQ, d, d, d, nA)

@@ -187,3 +187,43 @@ def test_config1_shapes():
     K = fe.tangent_matrix(m, fe.Material(c["mu"], c["lam"], c["inclusions"]), c["u"])
     assert K.nnz == 9604
     assert fe.min_jacobian(m, c["u"]) > 0
+
+
+# --- Mooney-Rivlin law (second law, tensor4 route) ---
+
+def _mr_setup(dim, N, p, amp=0.05, seed=4):
+    m, mat, u = _setup(dim, N, p, amp=amp, seed=seed)
+    return m, fe.Material(mat.mu, mat.lam, mat.inclusions, mu2=W.two_phase_mu2()), u
+
+
+@pytest.mark.parametrize("dim,N,p", [(2, 3, 2), (3, 2, 2), (3, 2, 1)])
+def test_mr_tangent_is_derivative_of_residual(dim, N, p):
+    m, mat, u = _mr_setup(dim, N, p)
+    K = fe.tangent_matrix(m, mat, u)
+    v = W.normal_vector(m.n_dofs, 12)
+    eps = 1e-6
+    fd = (fe.residual(m, mat, u + eps * v) - fe.residual(m, mat, u - eps * v)) / (2 * eps)
+    Kv = K @ v
+    assert np.linalg.norm(fd - Kv) / np.linalg.norm(Kv) < 1e-8
+    assert abs(K - K.T).max() <= 1e-12 * abs(K).max()
+    # the second-invariant term changes the operator
+    K0 = fe.tangent_matrix(m, fe.Material(mat.mu, mat.lam, mat.inclusions), u)
+    assert abs(K - K0).max() > 1e-3 * abs(K0).max()
+
+
+@pytest.mark.parametrize("dim,N,p", [(2, 3, 2), (3, 2, 2)])
+def test_mr_homogeneous_deformation_forces(dim, N, p):
+    """As for the Neo-Hookean law, with P = tau F^-T from the law's spatial
+    closed form."""
+    m, _, _ = _setup(dim, N, p, amp=0)
+    mu, lam, mu2 = 0.8, 1.9, 0.35
+    mat = fe.Material([mu], [lam], mu2=[mu2])
+    rng = np.random.default_rng(5)
+    F0 = np.eye(dim) + 0.2 * rng.standard_normal((dim, dim))
+    X = m.node_coords()
+    u = _nodal(m, X @ (F0 - np.eye(dim)).T)
+    R = fe.residual(m, mat, u).reshape(dim, -1).T
+    P = material.mr_tau_closed_form(F0, np.float64(mu), np.float64(lam), np.float64(mu2)) @ np.linalg.inv(F0).T
+    np.testing.assert_allclose(R.T @ X, P, atol=1e-12)
+    interior = np.all((X > 1e-12) & (X < 1 - 1e-12), axis=1)
+    assert np.abs(R[interior]).max() < 1e-12

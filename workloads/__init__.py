@@ -38,6 +38,20 @@ def two_phase_material(stiff=100.0):
     return mu, lam
 
 
+def two_phase_mu2(stiff=100.0, frac=0.3):
+    """Second-invariant moduli of a Mooney-Rivlin variant: frac * mu per phase."""
+    return frac * two_phase_material(stiff)[0]
+
+
+def two_phase_mooney_rivlin(stiff=100.0, frac=0.3):
+    """(mu, lambda, mu2) of the Mooney-Rivlin law with the same small-strain
+    Lame pair as two_phase_material: mu + mu2 and 2 lambda + 2 mu2 match the
+    Neo-Hookean mu and 2 lambda (mu2 = frac * mu)."""
+    mu, lam = two_phase_material(stiff)
+    mu2 = frac * mu
+    return mu - mu2, lam - mu2, mu2
+
+
 def spheres(n, seed, dim=3, rmin=0.05, rmax=0.12):
     """List of (centre, radius, material_id=1)."""
     rng = np.random.default_rng(seed)
