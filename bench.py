@@ -28,7 +28,7 @@ sys.path.insert(0, ROOT)
 METRIC = "tangent vmult DoFs/s (FP64/FP32, Q2 3D); GMG-CG Newton-step time at 1e-8"
 HBM_PEAK_GBS = 8000.0
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
-POLICIES = {0: "recompute", 1: "cache_F", 2: "cache_T2"}
+POLICIES = {0: "recompute", 1: "cache_F", 2: "cache_T2", 3: "cache_T4"}
 
 # Algorithmic flop counts: minimal sum factorisation of one d-component field,
 # 4 d^2 n^(d+1), plus the per-quadrature-point algebra.  Measured HBM bytes per
@@ -41,9 +41,9 @@ TRAFFIC = {"recompute/f64/element": 65941978, "recompute/f32/element": 34153468,
            "cache_F/f64/element": 123609236, "cache_F/f32/element": 62696136,
            "cache_T2/f64/element": 174075858, "cache_T2/f32/element": 88965696}
 
-QP_FLOPS_3D = {0: 313, 1: 307, 2: 188}
-QP_FLOPS_2D = {0: 118, 1: 116, 2: 78}
-CACHE_WORDS = {3: {0: 0, 1: 9, 2: 16}, 2: {0: 0, 1: 4, 2: 8}}
+QP_FLOPS_3D = {0: 313, 1: 307, 2: 188, 3: 246}
+QP_FLOPS_2D = {0: 118, 1: 116, 2: 78, 3: 71}
+CACHE_WORDS = {3: {0: 0, 1: 9, 2: 16, 3: 36}, 2: {0: 0, 1: 4, 2: 8, 3: 13}}
 
 
 def algorithmic_cost(dim, degree, n_cells, n_dofs, policy, word):
@@ -131,6 +131,31 @@ def cpu_baseline(w, n_sample_cells=32768):
             "host_threads_available": os.cpu_count()}
 
 
+def law_bench(w, steps, warmup):
+    """The tensor4 policy with the Mooney-Rivlin law on the headline workload
+    (same mesh, inclusions and fields; moduli with the same small-strain Lame
+    pair): the operator does not evaluate the law, so the vmult costs what the
+    Neo-Hookean cache_T4 variant costs."""
+    import torch
+
+    import workloads as W
+    from paper_1904_13131_amd import LAW_MOONEY_RIVLIN, QP_CACHE_T4, Problem
+    from paper_1904_13131_amd.mfh import SCATTER_NAMES
+    mu, lam, mu2 = W.two_phase_mooney_rivlin()
+    P = Problem(w["dim"], w["n_cells"], w["degree"], mu=tuple(mu), lam=tuple(lam), mu2=tuple(mu2),
+                law=LAW_MOONEY_RIVLIN, qp_policy=QP_CACHE_T4, inclusions=w["inclusions"])
+    P.set_deformation(torch.as_tensor(w["u"], device="cuda"))
+    out = {}
+    for dt, tdt in (("f64", torch.float64), ("f32", torch.float32)):
+        x = torch.as_tensor(w["x"], device="cuda").to(tdt)
+        y = torch.empty_like(x)
+        ms, kms = time_vmult(P, x, y, steps, warmup)
+        out[dt] = {"ms_per_step": ms, "kernel_ms": kms, "dofs_per_s": P.n_dofs() / (ms * 1e-3),
+                   "scatter": SCATTER_NAMES[P.scatter_mode(-1, 0 if dt == "f64" else 1)]}
+        print(f"[bench] cache_T4 Mooney-Rivlin {dt}: {ms * 1e3:8.1f} us/vmult", file=sys.stderr, flush=True)
+    return out
+
+
 MB_CASES = ((1, 64), (2, 32), (3, 21), (4, 16))   # (degree, cells per direction): 0.79-0.82 M DoFs
 
 
@@ -163,7 +188,7 @@ def matrix_based_bench(steps=20, warmup=3, library_spmv=True):
         x = torch.as_tensor(w["x"], device="cuda")
         y = torch.empty_like(x)
         row = {"degree": deg, "cells": nc ** 3}
-        for pol in (0, 2):
+        for pol in (0, 2, 3):
             P = Problem(3, nc, deg, mu=tuple(w["mu"]), lam=tuple(w["lam"]), inclusions=w["inclusions"],
                         qp_policy=pol)
             P.set_deformation(u)
@@ -208,7 +233,8 @@ def matrix_based_bench(steps=20, warmup=3, library_spmv=True):
         print(f"[bench] matrix-based Q{deg} {nc}^3: CSR {row['csr']['ms'] * 1e3:.1f} us "
               f"({row['csr']['bytes_per_dof']:.0f} B/DoF, {row['csr']['achieved_gbs']:.0f} GB/s), MF recompute "
               f"{row['mf_recompute']['ms'] * 1e3:.1f} us, MF cache_T2 {row['mf_cache_T2']['ms'] * 1e3:.1f} us "
-              f"({row['mf_cache_T2']['bytes_per_dof']:.0f} B/DoF)", file=sys.stderr, flush=True)
+              f"({row['mf_cache_T2']['bytes_per_dof']:.0f} B/DoF), MF cache_T4 {row['mf_cache_T4']['ms'] * 1e3:.1f} us "
+              f"({row['mf_cache_T4']['bytes_per_dof']:.0f} B/DoF)", file=sys.stderr, flush=True)
         out.append(row)
     return out
 
@@ -504,7 +530,7 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--policies", default="0,1,2")
+    ap.add_argument("--policies", default="0,1,2,3")
     ap.add_argument("--dtypes", default="f64,f32")
     ap.add_argument("--no-cold", action="store_true")
     ap.add_argument("--scatter", type=int, default=-1, help="-1 auto (tuned table), 0 atomic, 1 colour, 2 tile, 3 element")
@@ -607,6 +633,8 @@ def main(argv=None):
     }
     out["roofline"]["kernel_ms"] = r["kernel_ms"]
     out["roofline"]["kernel_ms_cold"] = r["kernel_ms_cold"]
+    if 3 in [int(p) for p in a.policies.split(",")]:
+        out["mooney_rivlin_cache_T4"] = law_bench(w, a.steps, a.warmup)
     if not a.no_matrix_based:
         out["matrix_based"] = matrix_based_bench()
     if not a.no_newton:

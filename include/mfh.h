@@ -65,15 +65,34 @@ typedef enum {
 
 enum { MFH_F64 = 0, MFH_F32 = 1 };
 
-/* Quadrature-point policies of the tangent vmult (Sec. 5, Algorithms 1-2):
+/* Quadrature-point policies of the tangent vmult (Sec. 5, Algorithms 1-3):
  *  RECOMPUTE  re-evaluates Grad u, F, J, F^-1, ln J and the stresses at every
  *             quadrature point from the displacement (the recompute end of
  *             the caching trade-off; Algorithm 1 without its scalar cache);
  *  CACHE_F    reads the cached deformation gradient F and recomputes the rest;
  *  CACHE_T2   reads cached F^-1, the second Piola-Kirchhoff stress S and
  *             c1 = mu - 2 lambda ln J: the referential counterpart of
- *             Algorithm 2's cached tau/J, c1, c2.                               */
-enum { MFH_QP_RECOMPUTE = 0, MFH_QP_CACHE_F = 1, MFH_QP_CACHE_T2 = 2 };
+ *             Algorithm 2's cached tau/J, c1, c2;
+ *  CACHE_T4   reads cached F^-1, S and the material part of the spatial
+ *             tangent J c (21 symmetric words in 3-D, 6 in 2-D): the
+ *             referential counterpart of Algorithm 3 ("tensor4"); the
+ *             quadrature-point stage evaluates no constitutive law, so it
+ *             serves any law (the only policy for MFH_LAW_MOONEY_RIVLIN).
+ * Cache words per quadrature point: 0, d^2, d^2 + d(d+1)/2 + 1,
+ * d^2 + d(d+1)/2 + (d(d+1)/2)(d(d+1)/2 + 1)/2 (36 in 3-D), in the V-cycle
+ * precision and in FP64 on every level.                                     */
+enum { MFH_QP_RECOMPUTE = 0, MFH_QP_CACHE_F = 1, MFH_QP_CACHE_T2 = 2, MFH_QP_CACHE_T4 = 3 };
+
+/* Material law.  NEO_HOOKE is the compressible Neo-Hookean energy of Sec. 2.3,
+ *   psi = mu/2 [I1 - 3 - 2 ln J] + lambda ln^2 J.
+ * MOONEY_RIVLIN adds a second-invariant term (a second law for the tensor4
+ * route, whose operator does not depend on the law):
+ *   psi = mu/2 [I1 - 3 - 2 ln J] + mu2/2 [I2 - 3 - 4 ln J] + lambda ln^2 J,
+ * stress-free at F = I, small-strain Lame pair (mu + mu2, 2 lambda + 2 mu2);
+ * invariants of the 3-D tensors (plane strain: C_33 = 1).  It needs
+ * qp_policy CACHE_T4; the residual, diagonal and coarse / CSR assembly
+ * evaluate it directly. */
+enum { MFH_LAW_NEO_HOOKE = 0, MFH_LAW_MOONEY_RIVLIN = 1 };
 
 /* Scatter of cell results into the output vector: ATOMIC (one hardware float
  * atomic per cell node; summation order varies run to run), COLOR (2^dim
@@ -144,11 +163,15 @@ typedef struct {
   int coarse_solver;         /* MFH_COARSE_*                                             */
   int eig_refresh;           /* eigenvalue estimates: 1 every linearisation, k every k-th,
                                 0 only the first (then reused)                           */
+  int law;                   /* MFH_LAW_*                                                 */
+  const double* mu2;         /* host [n_materials] second-invariant moduli >= 0 (law
+                                MOONEY_RIVLIN; ignored, may be NULL, otherwise)           */
 } mfh_desc;
 
 /* Fills *desc with the paper's solver settings (degree 4, 2 steps, 30
  * iterations, [0.6, 1.2]), RECOMPUTE, AUTO scatter, F32 V-cycle, NODAL level
- * fields, DIRECT coarse solve, eigenvalue estimates at every linearisation;
+ * fields, DIRECT coarse solve, eigenvalue estimates at every linearisation,
+ * the Neo-Hookean law;
  * geometry fields
  * are zeroed and must be set by the caller. */
 void mfh_desc_defaults(mfh_desc* desc);

@@ -25,13 +25,31 @@
 
 namespace mfh {
 
-enum { POL_R = 0, POL_CF = 1, POL_C2 = 2 };
+enum { POL_R = 0, POL_CF = 1, POL_C2 = 2, POL_C4 = 3 };
+
+// Symmetric second-order tensors in Voigt order: (00, 11, 22, 01, 02, 12) in
+// 3-D, (00, 11, 01) in 2-D; a symmetric Voigt matrix is stored as its upper
+// triangle, row by row.
+template <int DIM>
+struct Voigt {
+  static constexpr int N = DIM * (DIM + 1) / 2;
+  static constexpr int NSYM = N * (N + 1) / 2;
+  __device__ static constexpr int row(int a) { return DIM == 3 ? (a < 3 ? a : (a == 5 ? 1 : 0)) : (a < 2 ? a : 0); }
+  __device__ static constexpr int col(int a) { return DIM == 3 ? (a < 3 ? a : (a == 3 ? 1 : 2)) : (a < 2 ? a : 1); }
+  __device__ static constexpr int of(int i, int j) {   // Voigt index of (i, j)
+    return i == j ? i : (DIM == 2 ? 2 : (i + j == 1 ? 3 : (i + j == 2 ? 4 : 5)));
+  }
+  __device__ static constexpr int packed(int a, int b) {   // upper-triangle slot of (a, b)
+    return a <= b ? a * N - a * (a - 1) / 2 + (b - a) : b * N - b * (b - 1) / 2 + (a - b);
+  }
+};
 
 // Cache words per quadrature point.
 template <int DIM, int POL>
 struct CacheWords {
   static constexpr int value = POL == POL_CF ? DIM * DIM
                               : POL == POL_C2 ? DIM * DIM + DIM * (DIM + 1) / 2 + 1
+                              : POL == POL_C4 ? DIM * DIM + DIM * (DIM + 1) / 2 + Voigt<DIM>::NSYM
                               : 0;
 };
 
@@ -505,6 +523,151 @@ __device__ __forceinline__ void tangent_qp(T (&Hx)[DIM][DIM], const T (&Fi)[DIM]
     for (int I = 0; I < DIM; ++I) Hx[i][I] = P[i][I] * wt;
 }
 
+// ---------------------------------------------------------------------------
+// General route (any law; Algorithm 3 of Sec. 5 and the setup kernels of the
+// Mooney-Rivlin law).  The compressible Mooney-Rivlin energy
+//   psi = mu/2 [I1 - 3 - 2 ln J] + mu2/2 [I2 - 3 - 4 ln J] + lambda ln^2 J
+// is the Neo-Hookean law of Sec. 2.3 for mu2 = 0.  Its stresses:
+//   S = mu (I - C^-1) + mu2 (I1 I - C - 2 C^-1) + 2 lambda ln J C^-1,
+// and the material part of the spatial tangent (J times the push-forward of
+// 4 d2psi/dC2):
+//   J c = 2 c1' Ssym + 2 lambda I (x) I + 2 mu2 (b (x) b - I_b),
+//   c1' = mu + 2 mu2 - 2 lambda ln J,  (I_b)_ijkl = 1/2 (b_ik b_jl + b_il b_jk).
+// I1 and I2 are invariants of the 3-D tensors (plane strain: C_33 = 1).
+
+// S of the general law from F, F^-1 and J - 1 (FP64).
+template <int DIM, typename T>
+__device__ __forceinline__ void mr_stress(const T (&F)[DIM][DIM], const T (&Fi)[DIM][DIM], T jm1, T mu, T mu2, T lam,
+                                          T (&S)[DIM][DIM]) {
+  T C[DIM][DIM], Ci[DIM][DIM];
+#pragma unroll
+  for (int I = 0; I < DIM; ++I)
+#pragma unroll
+    for (int J = 0; J < DIM; ++J) {
+      T c = 0, ci = 0;
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) {
+        c += F[k][I] * F[k][J];
+        ci += Fi[I][k] * Fi[J][k];
+      }
+      C[I][J] = c;
+      Ci[I][J] = ci;
+    }
+  T I1 = T(3 - DIM);
+#pragma unroll
+  for (int I = 0; I < DIM; ++I) I1 += C[I][I];
+  const T l2 = T(2) * lam * log1p_t<T>(jm1);
+#pragma unroll
+  for (int I = 0; I < DIM; ++I)
+#pragma unroll
+    for (int J = 0; J < DIM; ++J) {
+      const T d = I == J ? T(1) : T(0);
+      S[I][J] = mu * (d - Ci[I][J]) + mu2 * (I1 * d - C[I][J] - T(2) * Ci[I][J]) + l2 * Ci[I][J];
+    }
+}
+
+// J c of the general law in packed Voigt form (see Voigt).
+template <int DIM, typename T>
+__device__ __forceinline__ void mr_spatial_tangent(const T (&F)[DIM][DIM], T jm1, T mu, T mu2, T lam,
+                                                   T (&Cv)[Voigt<DIM>::NSYM]) {
+  using V = Voigt<DIM>;
+  T b[DIM][DIM];
+#pragma unroll
+  for (int i = 0; i < DIM; ++i)
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) {
+      T s = 0;
+#pragma unroll
+      for (int K = 0; K < DIM; ++K) s += F[i][K] * F[j][K];
+      b[i][j] = s;
+    }
+  const T c1p = mu + T(2) * mu2 - T(2) * lam * log1p_t<T>(jm1);
+#pragma unroll
+  for (int A = 0; A < V::N; ++A)
+#pragma unroll
+    for (int B = A; B < V::N; ++B) {
+      const int i = V::row(A), j = V::col(A), k = V::row(B), l = V::col(B);
+      const T dik = i == k ? T(1) : T(0), djl = j == l ? T(1) : T(0);
+      const T dil = i == l ? T(1) : T(0), djk = j == k ? T(1) : T(0);
+      const T dij = i == j ? T(1) : T(0), dkl = k == l ? T(1) : T(0);
+      Cv[V::packed(A, B)] = c1p * (dik * djl + dil * djk) + T(2) * lam * dij * dkl +
+                            mu2 * (T(2) * b[i][j] * b[k][l] - b[i][k] * b[j][l] - b[i][l] * b[j][k]);
+    }
+}
+
+// Tangent action with a cached general tangent (Algorithm 3, referential
+// form): g = Grad x F^-1, sigma = J c : sym g, P_x = sigma F^-T + Grad x S.
+// Hx (physical Grad x) -> P_x * wt, in place.  cq points at word 0 of this
+// quadrature point's C4 cache (F^-1, S upper triangle, J c packed Voigt),
+// words `stride` apart; J c is streamed word by word into the symmetric
+// product so that only sym g and sigma stay live.  The law enters only
+// through the cached data.
+template <int DIM, typename T>
+__device__ __forceinline__ void tangent_qp_c4(T (&Hx)[DIM][DIM], const T* __restrict__ cq, long long stride, T wt) {
+  using V = Voigt<DIM>;
+  T Fi[DIM][DIM];
+#pragma unroll
+  for (int I = 0; I < DIM; ++I)
+#pragma unroll
+    for (int j = 0; j < DIM; ++j) Fi[I][j] = cq[(I * DIM + j) * stride];
+  T gam[V::N];   // sym g in Voigt form, shear entries doubled
+#pragma unroll
+  for (int A = 0; A < V::N; ++A) {
+    const int i = V::row(A), j = V::col(A);
+    T gij = 0, gji = 0;
+#pragma unroll
+    for (int I = 0; I < DIM; ++I) {
+      gij += Hx[i][I] * Fi[I][j];
+      gji += Hx[j][I] * Fi[I][i];
+    }
+    gam[A] = i == j ? gij : gij + gji;
+  }
+  const T* cv = cq + (DIM * DIM + V::N) * stride;
+  T sv[V::N] = {};
+#pragma unroll
+  for (int A = 0; A < V::N; ++A)
+#pragma unroll
+    for (int B = A; B < V::N; ++B) {
+      const T c = cv[V::packed(A, B) * stride];
+      sv[A] += c * gam[B];
+      if (B != A) sv[B] += c * gam[A];
+    }
+  T sig[DIM][DIM];
+#pragma unroll
+  for (int A = 0; A < V::N; ++A) {
+    sig[V::row(A)][V::col(A)] = sv[A];
+    sig[V::col(A)][V::row(A)] = sv[A];
+  }
+  T S[DIM][DIM];
+  {
+    int w = DIM * DIM;
+#pragma unroll
+    for (int I = 0; I < DIM; ++I)
+#pragma unroll
+      for (int J = I; J < DIM; ++J) {
+        const T v = cq[(w++) * stride];
+        S[I][J] = v;
+        S[J][I] = v;
+      }
+  }
+  T P[DIM][DIM];
+#pragma unroll
+  for (int i = 0; i < DIM; ++i)
+#pragma unroll
+    for (int I = 0; I < DIM; ++I) {
+      T s = 0;
+#pragma unroll
+      for (int j = 0; j < DIM; ++j) s += sig[i][j] * Fi[I][j];
+#pragma unroll
+      for (int J = 0; J < DIM; ++J) s += Hx[i][J] * S[J][I];
+      P[i][I] = s;
+    }
+#pragma unroll
+  for (int i = 0; i < DIM; ++i)
+#pragma unroll
+    for (int I = 0; I < DIM; ++I) Hx[i][I] = P[i][I] * wt;
+}
+
 // arr[i] for a thread-dependent i by compare-and-select over the N1 entries:
 // indexing a kernel-argument array with a runtime index makes the compiler
 // copy the whole argument block to scratch memory first.
@@ -581,6 +744,9 @@ __device__ __forceinline__ void tangent_block(const CellArgs<T>& a, const T* __r
       for (int i = 0; i < DIM; ++i)
 #pragma unroll
         for (int I = 0; I < DIM; ++I) Hx[i][I] = gx[i][I][q] * a.invh;
+      if constexpr (POL == POL_C4) {
+        tangent_qp_c4<DIM, T>(Hx, a.cache + (long long)qp * a.ncells + cp.e, (long long)G::NV * a.ncells, wt);
+      } else {
       T Fi[DIM][DIM], S[DIM][DIM], c1;
       if constexpr (POL == POL_R || POL == POL_CF) {
         T H[DIM][DIM];
@@ -620,6 +786,7 @@ __device__ __forceinline__ void tangent_block(const CellArgs<T>& a, const T* __r
         c1 = cq[w * stride];
       }
       tangent_qp<DIM, T>(Hx, Fi, S, c1, lam, wt);
+      }
 #pragma unroll
       for (int i = 0; i < DIM; ++i)
 #pragma unroll
@@ -1138,6 +1305,9 @@ k_tangent_tile(CellArgs<T> a) {
       for (int i = 0; i < DIM; ++i)
 #pragma unroll
         for (int I = 0; I < DIM; ++I) Hx[i][I] = gx[i][I][q] * a.invh;
+      if constexpr (POL == POL_C4) {
+        tangent_qp_c4<DIM, T>(Hx, a.cache + (long long)qp * a.ncells + e, (long long)TG::NV * a.ncells, wt);
+      } else {
       T Fi[DIM][DIM], S[DIM][DIM], c1;
       if constexpr (POL == POL_R || POL == POL_CF) {
         T H[DIM][DIM];
@@ -1177,6 +1347,7 @@ k_tangent_tile(CellArgs<T> a) {
         c1 = cq[w * stride];
       }
       tangent_qp<DIM, T>(Hx, Fi, S, c1, lam, wt);
+      }
 #pragma unroll
       for (int i = 0; i < DIM; ++i)
 #pragma unroll
@@ -1255,11 +1426,26 @@ __global__ void __launch_bounds__(kBlock) k_residual(CellArgs<double> arg) {
 #pragma unroll
         for (int I = 0; I < DIM; ++I) H[i][I] = gu[i][I][q] * a.invh;
       kinematics<DIM, T>(H, F, Fi, jm1);
-      const T c1 = mu - T(2) * lam * log1p_t<T>(jm1);
+      if (a.law) {   // general law: P = F S
+        const T mu2 = mid ? a.mu2[1] : a.mu2[0];
+        T S[DIM][DIM];
+        mr_stress<DIM, T>(F, Fi, jm1, mu, mu2, lam, S);
 #pragma unroll
-      for (int i = 0; i < DIM; ++i)
+        for (int i = 0; i < DIM; ++i)
 #pragma unroll
-        for (int I = 0; I < DIM; ++I) gu[i][I][q] = (mu * F[i][I] - c1 * Fi[I][i]) * wt;
+          for (int I = 0; I < DIM; ++I) {
+            T v = 0;
+#pragma unroll
+            for (int J = 0; J < DIM; ++J) v += F[i][J] * S[J][I];
+            gu[i][I][q] = v * wt;
+          }
+      } else {
+        const T c1 = mu - T(2) * lam * log1p_t<T>(jm1);
+#pragma unroll
+        for (int i = 0; i < DIM; ++i)
+#pragma unroll
+          for (int I = 0; I < DIM; ++I) gu[i][I][q] = (mu * F[i][I] - c1 * Fi[I][i]) * wt;
+      }
     }
   }
   T out[DIM][N1];
@@ -1268,7 +1454,8 @@ __global__ void __launch_bounds__(kBlock) k_residual(CellArgs<double> arg) {
 }
 
 // Quadrature data of a level: min J per block, and the policy cache
-// (CF: F;  C2: F^-1, S (upper triangle, row major), c1) in precision T.
+// (CF: F;  C2: F^-1, S (upper triangle, row major), c1;  C4: F^-1, S, J c of
+// the general law in packed Voigt form) in precision T.
 // The displacement is read in FP64 and everything is evaluated in FP64.
 template <int DIM, int P, typename T, int POL>
 __global__ void __launch_bounds__(kBlock) k_qpdata(CellArgs<double> arg, T* __restrict__ cache) {
@@ -1316,6 +1503,22 @@ __global__ void __launch_bounds__(kBlock) k_qpdata(CellArgs<double> arg, T* __re
           for (int i = 0; i < DIM; ++i)
 #pragma unroll
             for (int I = 0; I < DIM; ++I) cq[(i * DIM + I) * stride] = (T)F[i][I];
+        } else if constexpr (POL == POL_C4) {
+          const D mu2 = mid ? a.mu2[1] : a.mu2[0];
+          D S[DIM][DIM], Cv[Voigt<DIM>::NSYM];
+          mr_stress<DIM, D>(F, Fi, jm1, mu, mu2, lam, S);
+          mr_spatial_tangent<DIM, D>(F, jm1, mu, mu2, lam, Cv);
+          int w = 0;
+#pragma unroll
+          for (int I = 0; I < DIM; ++I)
+#pragma unroll
+            for (int j = 0; j < DIM; ++j) cq[(w++) * stride] = (T)Fi[I][j];
+#pragma unroll
+          for (int I = 0; I < DIM; ++I)
+#pragma unroll
+            for (int J = I; J < DIM; ++J) cq[(w++) * stride] = (T)S[I][J];
+#pragma unroll
+          for (int k = 0; k < Voigt<DIM>::NSYM; ++k) cq[(w++) * stride] = (T)Cv[k];
         } else {
           const D c1 = mu - 2.0 * lam * log1p(jm1);
           D S[DIM][DIM];
@@ -1348,14 +1551,27 @@ __global__ void __launch_bounds__(kBlock) k_qpdata(CellArgs<double> arg, T* __re
 //   sum_q w_q |cell| [ (c1 + 2 lambda) v_al^2 + mu |Grad N_a|^2 ]
 // (material part 2 c1 sym g : sym g + 2 lambda tr(g)^2 plus geometric part
 // v . tau v with tau = mu b - c1 I).  One thread per (cell, node); the cell's
-// displacement and per-qp data are staged in LDS.
-template <int DIM, int P>
+// displacement and per-qp data are staged in LDS.  LAW = 1: the general
+// law, entry sum_q w_q |cell| [ v_j (J c)_(al j al l) v_l + Grad N_a . S Grad N_a ].
+template <int DIM, int P, int LAW>
+struct DiagShape {
+  static constexpr int NV = DIM == 3 ? (P + 1) * (P + 1) * (P + 1) : (P + 1) * (P + 1);
+  // F^-1, c1 + 2 lambda, mu;  LAW = 1: F^-1, S (upper triangle), J c (packed Voigt)
+  static constexpr int NQD = LAW ? DIM * DIM + Voigt<DIM>::N + Voigt<DIM>::NSYM : DIM * DIM + 2;
+  static constexpr int BYTES = NV * (DIM + NQD) * 8;   // LDS per cell
+  static constexpr int CPB_LDS = (48 * 1024) / BYTES;
+  static constexpr int CPB = LAW ? (CPB_LDS < kBlock / NV ? CPB_LDS : kBlock / NV) : kBlock / NV;
+  static_assert(CPB >= 1, "one cell's quadrature data must fit in LDS");
+};
+
+template <int DIM, int P, int LAW>
 __global__ void __launch_bounds__(kBlock) k_diag(CellArgs<double> a) {
   using D = double;
+  using V = Voigt<DIM>;
   constexpr int N1 = P + 1;
-  constexpr int NV = DIM == 3 ? N1 * N1 * N1 : N1 * N1;
-  constexpr int CPB = kBlock / NV;
-  constexpr int NQD = DIM * DIM + 2;   // F^-1, c1 + 2 lambda, mu
+  constexpr int NV = DiagShape<DIM, P, LAW>::NV;
+  constexpr int CPB = DiagShape<DIM, P, LAW>::CPB;
+  constexpr int NQD = DiagShape<DIM, P, LAW>::NQD;
   __shared__ D su[CPB][DIM][NV];
   __shared__ D sq[CPB][NV][NQD];
   const int t = threadIdx.x;
@@ -1400,14 +1616,27 @@ __global__ void __launch_bounds__(kBlock) k_diag(CellArgs<double> a) {
     const int mid = material_of(a, e, loc);
     const D mu = mid ? a.mu[1] : a.mu[0];
     const D lam = mid ? a.lam[1] : a.lam[0];
-    const D c1 = mu - 2.0 * lam * log1p(jm1);
     int w = 0;
 #pragma unroll
     for (int i = 0; i < DIM; ++i)
 #pragma unroll
       for (int j = 0; j < DIM; ++j) sq[cl][loc][w++] = Fi[i][j];
-    sq[cl][loc][w++] = c1 + 2.0 * lam;
-    sq[cl][loc][w] = mu;
+    if constexpr (LAW) {
+      const D mu2 = mid ? a.mu2[1] : a.mu2[0];
+      D S[DIM][DIM], Cv[V::NSYM];
+      mr_stress<DIM, D>(F, Fi, jm1, mu, mu2, lam, S);
+      mr_spatial_tangent<DIM, D>(F, jm1, mu, mu2, lam, Cv);
+#pragma unroll
+      for (int I = 0; I < DIM; ++I)
+#pragma unroll
+        for (int J = I; J < DIM; ++J) sq[cl][loc][w++] = S[I][J];
+#pragma unroll
+      for (int k = 0; k < V::NSYM; ++k) sq[cl][loc][w++] = Cv[k];
+    } else {
+      const D c1 = mu - 2.0 * lam * log1p(jm1);
+      sq[cl][loc][w++] = c1 + 2.0 * lam;
+      sq[cl][loc][w] = mu;
+    }
   }
   __syncthreads();
   if (!act) return;
@@ -1427,15 +1656,44 @@ __global__ void __launch_bounds__(kBlock) k_diag(CellArgs<double> a) {
     }
     wq *= a.wscale / a.invh;   // w_q h^d
     const D* s = sq[cl][q];
-    D gg = 0;
+    if constexpr (LAW) {
+      D v[DIM], geo = 0;
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) gg += gr[d] * gr[d];
+      for (int j = 0; j < DIM; ++j) {
+        D t = 0;
 #pragma unroll
-    for (int al = 0; al < DIM; ++al) {
-      D v = 0;
+        for (int d = 0; d < DIM; ++d) t += gr[d] * s[d * DIM + j];
+        v[j] = t;
+      }
+      const D* sS = s + DIM * DIM;
+      const D* cv = sS + V::N;
 #pragma unroll
-      for (int d = 0; d < DIM; ++d) v += gr[d] * s[d * DIM + al];
-      acc[al] += wq * (s[DIM * DIM] * v * v + s[DIM * DIM + 1] * gg);
+      for (int I = 0; I < DIM; ++I)
+#pragma unroll
+        for (int J = 0; J < DIM; ++J) {
+          const int lo = I < J ? I : J, hi = I < J ? J : I;
+          geo += gr[I] * sS[lo * DIM - lo * (lo - 1) / 2 + (hi - lo)] * gr[J];
+        }
+#pragma unroll
+      for (int al = 0; al < DIM; ++al) {
+        D m = 0;
+#pragma unroll
+        for (int j = 0; j < DIM; ++j)
+#pragma unroll
+          for (int l = 0; l < DIM; ++l) m += v[j] * cv[V::packed(V::of(al, j), V::of(al, l))] * v[l];
+        acc[al] += wq * (m + geo);
+      }
+    } else {
+      D gg = 0;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) gg += gr[d] * gr[d];
+#pragma unroll
+      for (int al = 0; al < DIM; ++al) {
+        D v = 0;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) v += gr[d] * s[d * DIM + al];
+        acc[al] += wq * (s[DIM * DIM] * v * v + s[DIM * DIM + 1] * gg);
+      }
     }
   }
   const unsigned f = node_faces(I, J, K, a.L, DIM);
@@ -1523,13 +1781,16 @@ struct CsrSink {
 // (a, i) and (b, k) is, for this material law,
 //   sum_q w_q |cell| [ c1 v_a,k v_b,i + 2 lambda v_a,i v_b,k + mu delta_ik Grad N_a . Grad N_b ]
 // (material part with J c = 2 c1 Ssym + 2 lambda I (x) I, geometric part with
-// tau = mu b - c1 I).
-template <int DIM, int P, typename Sink>
+// tau = mu b - c1 I).  LAW = 1: the general law, entry
+//   sum_q w_q |cell| [ v_a,j (J c)_ijkl v_b,l + delta_ik Grad N_a . S Grad N_b ].
+template <int DIM, int P, typename Sink, int LAW>
 __global__ void __launch_bounds__(kBlock) k_cell_matrix(CellArgs<double> a, Sink sink) {
   using D = double;
+  using V = Voigt<DIM>;
   constexpr int N1 = P + 1;
   constexpr int NV = DIM == 3 ? N1 * N1 * N1 : N1 * N1;
-  constexpr int NQD = DIM * DIM + 3;   // F^-1, c1, 2 lambda, mu
+  // F^-1, c1, 2 lambda, mu;  LAW = 1: F^-1, S (upper triangle), J c (packed Voigt)
+  constexpr int NQD = LAW ? DIM * DIM + V::N + V::NSYM : DIM * DIM + 3;
   __shared__ D su[DIM][NV];
   __shared__ D sq[NV][NQD];
   const long long e = blockIdx.x;
@@ -1572,9 +1833,22 @@ __global__ void __launch_bounds__(kBlock) k_cell_matrix(CellArgs<double> a, Sink
     for (int i = 0; i < DIM; ++i)
 #pragma unroll
       for (int j = 0; j < DIM; ++j) sq[t][w++] = Fi[i][j];
-    sq[t][w++] = mu - 2.0 * lam * log1p(jm1);
-    sq[t][w++] = 2.0 * lam;
-    sq[t][w] = mu;
+    if constexpr (LAW) {
+      const D mu2 = mid ? a.mu2[1] : a.mu2[0];
+      D S[DIM][DIM], Cv[V::NSYM];
+      mr_stress<DIM, D>(F, Fi, jm1, mu, mu2, lam, S);
+      mr_spatial_tangent<DIM, D>(F, jm1, mu, mu2, lam, Cv);
+#pragma unroll
+      for (int I = 0; I < DIM; ++I)
+#pragma unroll
+        for (int J = I; J < DIM; ++J) sq[t][w++] = S[I][J];
+#pragma unroll
+      for (int k = 0; k < V::NSYM; ++k) sq[t][w++] = Cv[k];
+    } else {
+      sq[t][w++] = mu - 2.0 * lam * log1p(jm1);
+      sq[t][w++] = 2.0 * lam;
+      sq[t][w] = mu;
+    }
   }
   __syncthreads();
   if (!act) return;
@@ -1620,12 +1894,36 @@ __global__ void __launch_bounds__(kBlock) k_cell_matrix(CellArgs<double> a, Sink
         vb[j] = sb;
         gg += ga[j] * gb[j];
       }
-      const D c1 = s[DIM * DIM], l2 = s[DIM * DIM + 1], mu = s[DIM * DIM + 2];
+      if constexpr (LAW) {
+        const D* sS = s + DIM * DIM;
+        const D* cv = sS + V::N;
+        D geo = 0;   // Grad N_a . S Grad N_b (S stored as its upper triangle, row by row)
 #pragma unroll
-      for (int i = 0; i < DIM; ++i)
+        for (int I = 0; I < DIM; ++I)
 #pragma unroll
-        for (int k = 0; k < DIM; ++k)
-          acc[i][k] += wq * (c1 * va[k] * vb[i] + l2 * va[i] * vb[k] + (i == k ? mu * gg : 0.0));
+          for (int J = 0; J < DIM; ++J) {
+            const int lo = I < J ? I : J, hi = I < J ? J : I;
+            geo += ga[I] * sS[lo * DIM - lo * (lo - 1) / 2 + (hi - lo)] * gb[J];
+          }
+#pragma unroll
+        for (int i = 0; i < DIM; ++i)
+#pragma unroll
+          for (int k = 0; k < DIM; ++k) {
+            D m = 0;
+#pragma unroll
+            for (int j = 0; j < DIM; ++j)
+#pragma unroll
+              for (int l = 0; l < DIM; ++l) m += va[j] * cv[V::packed(V::of(i, j), V::of(k, l))] * vb[l];
+            acc[i][k] += wq * (m + (i == k ? geo : 0.0));
+          }
+      } else {
+        const D c1 = s[DIM * DIM], l2 = s[DIM * DIM + 1], mu = s[DIM * DIM + 2];
+#pragma unroll
+        for (int i = 0; i < DIM; ++i)
+#pragma unroll
+          for (int k = 0; k < DIM; ++k)
+            acc[i][k] += wq * (c1 * va[k] * vb[i] + l2 * va[i] * vb[k] + (i == k ? mu * gg : 0.0));
+      }
     }
     const long long nodeb = (ex * P + bx) + (long long)a.L * ((ey * P + by) + (long long)a.L * (ez * P + bz));
     sink.template add<DIM>(a, nodeb, ex * P + bx, ey * P + by, ez * P + bz, acc);

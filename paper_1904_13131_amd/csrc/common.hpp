@@ -35,6 +35,8 @@ struct CellArgs {
   T invh;               // 1 / h
   T wscale;             // h^(dim-1): quadrature weight * |cell| / h
   T mu[2], lam[2];      // material table
+  T mu2[2];             // second-invariant moduli (general law; zero for Neo-Hookean)
+  int law;              // 0: Neo-Hookean closed forms, 1: general (Mooney-Rivlin) route
   const uint32_t* matbits;   // per cell, nwords words: bit q = material id of qp q
   int nwords;
   const T* u;           // level displacement (recompute policy / residual / cache build)

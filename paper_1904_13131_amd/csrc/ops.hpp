@@ -6,22 +6,22 @@
 namespace mfh {
 
 struct OpFns {
-  // tangent vmult per policy (0 R, 1 CF, 2 C2)
-  void (*tangent_d[3])(const CellArgs<double>&, unsigned grid, hipStream_t);
-  void (*tangent_f[3])(const CellArgs<float>&, unsigned grid, hipStream_t);
+  // tangent vmult per policy (0 R, 1 CF, 2 C2, 3 C4)
+  void (*tangent_d[4])(const CellArgs<double>&, unsigned grid, hipStream_t);
+  void (*tangent_f[4])(const CellArgs<float>&, unsigned grid, hipStream_t);
   void (*residual)(const CellArgs<double>&, unsigned grid, hipStream_t);
   // quadrature data (min J and the policy cache in double / float)
-  void (*qpdata_d[3])(const CellArgs<double>&, double* cache, unsigned grid, hipStream_t);
-  void (*qpdata_f[3])(const CellArgs<double>&, float* cache, unsigned grid, hipStream_t);
-  void (*diag)(const CellArgs<double>&, unsigned grid, hipStream_t);
+  void (*qpdata_d[4])(const CellArgs<double>&, double* cache, unsigned grid, hipStream_t);
+  void (*qpdata_f[4])(const CellArgs<double>&, float* cache, unsigned grid, hipStream_t);
+  void (*diag)(const CellArgs<double>&, hipStream_t);   // adds into a.y
   // tile variant of the tangent vmult (atomic scatter only); grid = tiles(N)
-  void (*tangent_tile_d[3])(const CellArgs<double>&, unsigned grid, hipStream_t);
-  void (*tangent_tile_f[3])(const CellArgs<float>&, unsigned grid, hipStream_t);
+  void (*tangent_tile_d[4])(const CellArgs<double>&, unsigned grid, hipStream_t);
+  void (*tangent_tile_f[4])(const CellArgs<float>&, unsigned grid, hipStream_t);
   long long (*tiles[2])(int N);   // [0] double, [1] float
   // batched vmult over problems of this (dim, degree): one workgroup per (problem, cell block) item
-  void (*tangent_batch_d[3])(const CellArgs<double>* args, const int2* items, const double* const* xs,
+  void (*tangent_batch_d[4])(const CellArgs<double>* args, const int2* items, const double* const* xs,
                              double* const* ys, unsigned n_items, hipStream_t);
-  void (*tangent_batch_f[3])(const CellArgs<float>* args, const int2* items, const float* const* xs,
+  void (*tangent_batch_f[4])(const CellArgs<float>* args, const int2* items, const float* const* xs,
                              float* const* ys, unsigned n_items, hipStream_t);
   // second pass of the ELEMENT scatter
   void (*elem_gather_d)(const CellArgs<double>&, hipStream_t);
@@ -36,8 +36,7 @@ struct OpFns {
   void (*csr_assemble)(const CellArgs<double>&, const long long* row_ptr, double* val, unsigned grid,
                        hipStream_t);
   int cpb;        // cells per block of the pencil kernels
-  int cpb_diag;   // cells per block of the diagonal kernel
-  int cache_words[3];
+  int cache_words[4];
 };
 
 const OpFns* op_fns(int dim, int degree);

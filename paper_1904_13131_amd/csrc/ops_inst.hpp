@@ -78,32 +78,52 @@ struct OpInst {
   static void qpdata(const CellArgs<double>& a, T* cache, unsigned grid, hipStream_t s) {
     hipLaunchKernelGGL((k_qpdata<DIM, P, T, POL>), dim3(grid), dim3(kBlock), 0, s, a, cache);
   }
-  static void diag(const CellArgs<double>& a, unsigned grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_diag<DIM, P>), dim3(grid), dim3(kBlock), 0, s, a);
+  // the setup kernels take the material law from a.law (0: the closed forms
+  // of the Neo-Hookean law, 1: the general route)
+  template <int LAW>
+  static void diag_law(const CellArgs<double>& a, hipStream_t s) {
+    constexpr int cpb = DiagShape<DIM, P, LAW>::CPB;
+    const unsigned grid = (unsigned)((a.ncells + cpb - 1) / cpb);
+    hipLaunchKernelGGL((k_diag<DIM, P, LAW>), dim3(grid), dim3(kBlock), 0, s, a);
+  }
+  static void diag(const CellArgs<double>& a, hipStream_t s) {
+    if (a.law)
+      diag_law<1>(a, s);
+    else
+      diag_law<0>(a, s);
+  }
+  template <typename Sink>
+  static void cell_matrix(const CellArgs<double>& a, const Sink& sink, unsigned grid, hipStream_t s) {
+    if (a.law)
+      hipLaunchKernelGGL((k_cell_matrix<DIM, P, Sink, 1>), dim3(grid), dim3(kBlock), 0, s, a, sink);
+    else
+      hipLaunchKernelGGL((k_cell_matrix<DIM, P, Sink, 0>), dim3(grid), dim3(kBlock), 0, s, a, sink);
   }
   static void coarse_assemble(const CellArgs<double>& a, const int* fmap, long long nf, double* K,
                               unsigned grid, hipStream_t s) {
-    DenseSink sink{fmap, nf, K, {}};
-    hipLaunchKernelGGL((k_cell_matrix<DIM, P, DenseSink>), dim3(grid), dim3(kBlock), 0, s, a, sink);
+    cell_matrix(a, DenseSink{fmap, nf, K, {}}, grid, s);
   }
   static void csr_assemble(const CellArgs<double>& a, const long long* row_ptr, double* val, unsigned grid,
                            hipStream_t s) {
-    CsrSink sink{row_ptr, val, P, {}, {}, {}, 0};
-    hipLaunchKernelGGL((k_cell_matrix<DIM, P, CsrSink>), dim3(grid), dim3(kBlock), 0, s, a, sink);
+    cell_matrix(a, CsrSink{row_ptr, val, P, {}, {}, {}, 0}, grid, s);
   }
   static const OpFns* table() {
     static const OpFns t = {
-        {&tangent<double, POL_R>, &tangent<double, POL_CF>, &tangent<double, POL_C2>},
-        {&tangent<float, POL_R>, &tangent<float, POL_CF>, &tangent<float, POL_C2>},
+        {&tangent<double, POL_R>, &tangent<double, POL_CF>, &tangent<double, POL_C2>, &tangent<double, POL_C4>},
+        {&tangent<float, POL_R>, &tangent<float, POL_CF>, &tangent<float, POL_C2>, &tangent<float, POL_C4>},
         &residual,
-        {&qpdata<double, POL_R>, &qpdata<double, POL_CF>, &qpdata<double, POL_C2>},
-        {&qpdata<float, POL_R>, &qpdata<float, POL_CF>, &qpdata<float, POL_C2>},
+        {&qpdata<double, POL_R>, &qpdata<double, POL_CF>, &qpdata<double, POL_C2>, &qpdata<double, POL_C4>},
+        {&qpdata<float, POL_R>, &qpdata<float, POL_CF>, &qpdata<float, POL_C2>, &qpdata<float, POL_C4>},
         &diag,
-        {&tangent_tile<double, POL_R>, &tangent_tile<double, POL_CF>, &tangent_tile<double, POL_C2>},
-        {&tangent_tile<float, POL_R>, &tangent_tile<float, POL_CF>, &tangent_tile<float, POL_C2>},
+        {&tangent_tile<double, POL_R>, &tangent_tile<double, POL_CF>, &tangent_tile<double, POL_C2>,
+         &tangent_tile<double, POL_C4>},
+        {&tangent_tile<float, POL_R>, &tangent_tile<float, POL_CF>, &tangent_tile<float, POL_C2>,
+         &tangent_tile<float, POL_C4>},
         {&tiles<double>, &tiles<float>},
-        {&tangent_batch<double, POL_R>, &tangent_batch<double, POL_CF>, &tangent_batch<double, POL_C2>},
-        {&tangent_batch<float, POL_R>, &tangent_batch<float, POL_CF>, &tangent_batch<float, POL_C2>},
+        {&tangent_batch<double, POL_R>, &tangent_batch<double, POL_CF>, &tangent_batch<double, POL_C2>,
+         &tangent_batch<double, POL_C4>},
+        {&tangent_batch<float, POL_R>, &tangent_batch<float, POL_CF>, &tangent_batch<float, POL_C2>,
+         &tangent_batch<float, POL_C4>},
         &elem_gather<double>,
         &elem_gather<float>,
         &elem_gather_batch<double>,
@@ -111,8 +131,8 @@ struct OpInst {
         &coarse_assemble,
         &csr_assemble,
         Geo<DIM, P + 1>::CPB,
-        kBlock / (DIM == 3 ? (P + 1) * (P + 1) * (P + 1) : (P + 1) * (P + 1)),
-        {CacheWords<DIM, POL_R>::value, CacheWords<DIM, POL_CF>::value, CacheWords<DIM, POL_C2>::value},
+        {CacheWords<DIM, POL_R>::value, CacheWords<DIM, POL_CF>::value, CacheWords<DIM, POL_C2>::value,
+         CacheWords<DIM, POL_C4>::value},
     };
     return &t;
   }

@@ -107,7 +107,7 @@ struct Level {
 
 struct mfh_problem {
   mfh_desc d{};
-  std::vector<double> mu, lam, incl;
+  std::vector<double> mu, lam, mu2, incl;
   hipStream_t stream = nullptr;
   const mfh::OpFns* ops = nullptr;
   mfh::Tables<double> tb64{};
@@ -197,7 +197,14 @@ void validate(const mfh_desc* d) {
     if (id != 0.0 && (id != 1.0 || d->n_materials < 2)) bad("inclusion material id must be 0 or 1 (< n_materials)");
   }
   if (d->dirichlet_mask >> (2 * d->dim * d->dim)) bad("dirichlet_mask has bits beyond 2*dim*dim");
-  if (d->qp_policy < 0 || d->qp_policy > 2) bad("qp_policy must be 0..2");
+  if (d->qp_policy < 0 || d->qp_policy > 3) bad("qp_policy must be 0..3");
+  if (d->law != MFH_LAW_NEO_HOOKE && d->law != MFH_LAW_MOONEY_RIVLIN) bad("bad law");
+  if (d->law == MFH_LAW_MOONEY_RIVLIN) {
+    if (d->qp_policy != MFH_QP_CACHE_T4) bad("the Mooney-Rivlin law needs qp_policy CACHE_T4");
+    if (!d->mu2) bad("mu2 array is NULL");
+    for (int m = 0; m < d->n_materials; ++m)
+      if (!(d->mu2[m] >= 0) || !std::isfinite(d->mu2[m])) bad("mu2 must be finite and >= 0");
+  }
   if (d->scatter < MFH_SCATTER_AUTO || d->scatter > MFH_SCATTER_ELEMENT) bad("bad scatter mode");
   if (d->vcycle_dtype != MFH_F32 && d->vcycle_dtype != MFH_F64) bad("bad vcycle_dtype");
   if (d->cheb_degree < 1 || d->cheb_degree > 16) bad("cheb_degree must be 1..16");
@@ -405,7 +412,9 @@ void fill_common(const mfh_problem* P, const Level& v, CellArgs<T>& a) {
     const int mm = m < P->d.n_materials ? m : 0;
     a.mu[m] = (T)P->mu[mm];
     a.lam[m] = (T)P->lam[mm];
+    a.mu2[m] = (T)P->mu2[mm];
   }
+  a.law = P->d.law == MFH_LAW_MOONEY_RIVLIN ? 1 : 0;
   a.matbits = v.bits;
   a.nwords = v.nwords;
   a.blockmin = P->part;
@@ -861,7 +870,7 @@ void setup_enqueue(mfh_problem* P) {
     Level& v = P->lv[l];
     fill<double>(v.diag64, 0.0, v.ndofs, s);
     CellArgs<double> a = cell_args<double>(P, v, v.u64, nullptr, nullptr, v.diag64);
-    P->ops->diag(a, (unsigned)((v.ncells + P->ops->cpb_diag - 1) / P->ops->cpb_diag), s);
+    P->ops->diag(a, s);
     set_constrained<double>(v.diag64, 1.0, v.ndofs, v.lt, s);
     if (d.vcycle_dtype == MFH_F32)
       reciprocal<float>(v.diag64, static_cast<float*>(v.dinv), v.ndofs, s);
@@ -1148,6 +1157,7 @@ void mfh_desc_defaults(mfh_desc* d) {
   d->level_field = MFH_LEVEL_FIELD_NODAL;
   d->coarse_solver = MFH_COARSE_DIRECT;
   d->eig_refresh = 1;
+  d->law = MFH_LAW_NEO_HOOKE;
 }
 
 mfh_status mfh_workspace_size(const mfh_desc* desc, size_t* bytes) {
@@ -1171,6 +1181,11 @@ mfh_status mfh_create(const mfh_desc* desc, void* ws, size_t bytes, void* stream
     P->d = *desc;
     P->mu.assign(desc->mu, desc->mu + desc->n_materials);
     P->lam.assign(desc->lambda, desc->lambda + desc->n_materials);
+    if (desc->law == MFH_LAW_MOONEY_RIVLIN)
+      P->mu2.assign(desc->mu2, desc->mu2 + desc->n_materials);
+    else
+      P->mu2.assign(desc->n_materials, 0.0);
+    P->d.mu = P->d.lambda = P->d.mu2 = P->d.inclusions = nullptr;   // caller's arrays: copied above
     P->incl.assign(desc->inclusions, desc->inclusions + (size_t)desc->n_inclusions * (desc->dim + 2));
     P->stream = static_cast<hipStream_t>(stream);
     build_host(P.get());

@@ -16,7 +16,8 @@ MFH_OK = 0
 STATUS = {0: "OK", -1: "INVALID_ARG", -2: "HIP", -3: "WORKSPACE", -4: "INVERTED",
           -5: "NOT_CONVERGED", -6: "BREAKDOWN", -7: "NOT_SPD"}
 F64, F32 = 0, 1
-QP_RECOMPUTE, QP_CACHE_F, QP_CACHE_T2 = 0, 1, 2
+QP_RECOMPUTE, QP_CACHE_F, QP_CACHE_T2, QP_CACHE_T4 = 0, 1, 2, 3
+LAW_NEO_HOOKE, LAW_MOONEY_RIVLIN = 0, 1
 SCATTER_AUTO, SCATTER_ATOMIC, SCATTER_COLOR, SCATTER_TILE, SCATTER_ELEMENT = -1, 0, 1, 2, 3
 SCATTER_NAMES = {0: "atomic", 1: "color", 2: "tile", 3: "element"}
 LEVEL_FIELD_NODAL, LEVEL_FIELD_VERTEX = 0, 1
@@ -40,6 +41,7 @@ class Desc(ctypes.Structure):
         ("vcycle_dtype", ctypes.c_int), ("cheb_degree", ctypes.c_int), ("n_smooth", ctypes.c_int),
         ("eig_iters", ctypes.c_int), ("cheb_lo", ctypes.c_double), ("cheb_hi", ctypes.c_double),
         ("level_field", ctypes.c_int), ("coarse_solver", ctypes.c_int), ("eig_refresh", ctypes.c_int),
+        ("law", ctypes.c_int), ("mu2", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -133,7 +135,8 @@ def _darr(vals):
 
 def make_desc(dim, n_cells, degree, n_levels=1, mu=(1.0,), lam=(1.5,), inclusions=(), dirichlet_mask=0,
               qp_policy=QP_RECOMPUTE, scatter=SCATTER_AUTO, vcycle_dtype=F32, cheb_degree=4, n_smooth=2,
-              eig_iters=30, cheb_lo=0.6, cheb_hi=1.2, level_field=0, coarse_solver=0, eig_refresh=1):
+              eig_iters=30, cheb_lo=0.6, cheb_hi=1.2, level_field=0, coarse_solver=0, eig_refresh=1,
+              law=LAW_NEO_HOOKE, mu2=None):
     """Builds an mfh_desc; the returned tuple keeps the host arrays alive."""
     d = Desc()
     lib().mfh_desc_defaults(ctypes.byref(d))
@@ -154,7 +157,10 @@ def make_desc(dim, n_cells, degree, n_levels=1, mu=(1.0,), lam=(1.5,), inclusion
     d.cheb_lo, d.cheb_hi = cheb_lo, cheb_hi
     d.level_field = level_field
     d.coarse_solver, d.eig_refresh = coarse_solver, eig_refresh
-    return d, (mu_a, lam_a, inc_a)
+    d.law = law
+    mu2_a = _darr(mu2 if mu2 is not None else [0.0] * len(mu))
+    d.mu2 = ctypes.cast(mu2_a, _D)
+    return d, (mu_a, lam_a, inc_a, mu2_a)
 
 
 def workspace_size(desc):

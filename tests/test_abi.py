@@ -54,9 +54,11 @@ def test_workspace_size_on_host():
 
 @pytest.mark.parametrize("bad", [
     dict(dim=4), dict(degree=0), dict(degree=5), dict(n_cells=0), dict(n_cells=1024, degree=2, n_levels=1), dict(n_cells=6, n_levels=3),
-    dict(mu=(-1.0,), lam=(1.0,)), dict(qp_policy=3), dict(scatter=4), dict(scatter=-2), dict(vcycle_dtype=5),
+    dict(mu=(-1.0,), lam=(1.0,)), dict(qp_policy=4), dict(qp_policy=-1), dict(scatter=4), dict(scatter=-2), dict(vcycle_dtype=5),
     dict(cheb_degree=0), dict(n_smooth=0), dict(eig_iters=0), dict(cheb_lo=1.3, cheb_hi=1.2),
     dict(dirichlet_mask=1 << 18), dict(level_field=2), dict(coarse_solver=2), dict(eig_refresh=-1), dict(inclusions=[((0.5, 0.5, 0.5), 0.2, 2)]),
+    dict(law=2), dict(law=1, qp_policy=2, mu2=(0.3, 30.0)), dict(law=1, qp_policy=3, mu2=(-0.3, 30.0)),
+    dict(law=1, qp_policy=3, mu2=(float("nan"), 30.0)),
 ])
 def test_invalid_descriptors_rejected(bad):
     from paper_1904_13131_amd import MfhError, workspace_size
@@ -64,6 +66,21 @@ def test_invalid_descriptors_rejected(bad):
     with pytest.raises(MfhError) as e:
         workspace_size(d)
     assert e.value.name == "INVALID_ARG"
+
+
+def test_tensor4_and_second_law_accepted():
+    """CACHE_T4 with either law; its cache is 36 words per quadrature point in
+    3-D (F^-1, S, J c), so the workspace grows over CACHE_T2's 16."""
+    from paper_1904_13131_amd import workspace_size
+    sizes = {}
+    for pol, law in ((2, 0), (3, 0), (3, 1)):
+        d, keep = _desc(qp_policy=pol, law=law, mu2=(0.3, 30.0))
+        sizes[(pol, law)] = workspace_size(d)
+    assert sizes[(3, 0)] == sizes[(3, 1)] > sizes[(2, 0)]
+    n_cells, nq = 8 ** 3, 27
+    d2, keep2 = _desc(n_levels=1, qp_policy=2)
+    d3, keep3 = _desc(n_levels=1, qp_policy=3)
+    assert workspace_size(d3) - workspace_size(d2) >= (36 - 16) * nq * n_cells * 12   # FP64 + FP32 copies
 
 
 def test_create_rejects_small_or_null_workspace():

@@ -51,7 +51,7 @@ def _oracle(name):
 
 
 @pytest.mark.parametrize("scatter", [0, 1, 2, 3, -1], ids=["atomic", "color", "tile", "elem", "auto"])
-@pytest.mark.parametrize("policy", [0, 1, 2], ids=["R", "CF", "C2"])
+@pytest.mark.parametrize("policy", [0, 1, 2, 3], ids=["R", "CF", "C2", "C4"])
 @pytest.mark.parametrize("name", list(CASES))
 def test_vmult_fp64(name, policy, scatter):
     log_case("vmult_fp64", name=name, policy=policy, scatter=scatter)
@@ -65,7 +65,7 @@ def test_vmult_fp64(name, policy, scatter):
 
 
 @pytest.mark.parametrize("scatter", [0, 2, 3, -1], ids=["atomic", "tile", "elem", "auto"])
-@pytest.mark.parametrize("policy", [0, 1, 2], ids=["R", "CF", "C2"])
+@pytest.mark.parametrize("policy", [0, 1, 2, 3], ids=["R", "CF", "C2", "C4"])
 @pytest.mark.parametrize("name", list(CASES))
 def test_vmult_fp32(name, policy, scatter):
     log_case("vmult_fp32", name=name, policy=policy, scatter=scatter)
@@ -137,7 +137,7 @@ def _config2():
 
 
 @pytest.mark.parametrize("scatter", [0, 2, 3], ids=["atomic", "tile", "elem"])
-@pytest.mark.parametrize("policy", [0, 1, 2], ids=["R", "CF", "C2"])
+@pytest.mark.parametrize("policy", [0, 1, 2, 3], ids=["R", "CF", "C2", "C4"])
 def test_config2_sampled_rows(policy, scatter):
     c = _config2()
     w = c["w"]

@@ -1,0 +1,196 @@
+"""GPU parity of the tensor4 route (Sec. 5, Algorithm 3: cached material part
+of the spatial tangent and the stress) with a second material law, the
+compressible Mooney-Rivlin energy, against the oracle: tangent vmult in every
+scatter mode (FP64 1e-12, FP32 1e-5), residual, level diagonals, CSR
+assembly, the GMG-preconditioned CG and a Newton solve.  The Neo-Hookean law
+through the same route is covered with the other policies in the operator
+tests."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import fe, gmg
+from tests.gpu_helpers import dev, host, log_case, rel_l2, requires_gpu
+
+pytestmark = [pytest.mark.gpu, requires_gpu]
+
+MU, LAM, MU2 = W.two_phase_mooney_rivlin()
+CLAMP3 = W.clamp_bottom_top(3)
+
+CASES = {
+    "2d_q1": W.problem(2, 6, 1, disc=True, u_amp=0.04, u_kmax=2),
+    "2d_q3_clamp": W.problem(2, 5, 3, disc=True, u_amp=0.04, u_kmax=2, mask=W.clamp_bottom_top(2)),
+    "3d_q1_clamp": W.problem(3, 5, 1, n_spheres=3, u_amp=0.05, u_kmax=2, mask=CLAMP3),
+    "3d_q2": W.problem(3, 4, 2, n_spheres=3, u_amp=0.05, u_kmax=2),
+    "3d_q3": W.problem(3, 3, 3, n_spheres=3, u_amp=0.04, u_kmax=2),
+    "3d_q4_clamp": W.problem(3, 2, 4, n_spheres=2, u_amp=0.04, u_kmax=2, mask=CLAMP3),
+}
+_ORACLE = {}
+
+
+def _mat(w):
+    return fe.Material(MU, LAM, w["inclusions"], mu2=MU2)
+
+
+def _oracle(name):
+    if name not in _ORACLE:
+        w = CASES[name]
+        mesh = fe.Mesh(w["dim"], w["n_cells"], w["degree"])
+        mat = _mat(w)
+        cons = mesh.constrained(w["mask"])
+        K = fe.constrain_matrix(fe.tangent_matrix(mesh, mat, w["u"]), cons)
+        R = fe.residual(mesh, mat, w["u"], cons)
+        _ORACLE[name] = (mesh, mat, cons, K, R)
+    return _ORACLE[name]
+
+
+def _problem(w, n_levels=1, **kw):
+    from paper_1904_13131_amd import LAW_MOONEY_RIVLIN, QP_CACHE_T4, Problem
+    return Problem(w["dim"], w["n_cells"], w["degree"], n_levels=n_levels, mu=tuple(MU), lam=tuple(LAM),
+                   mu2=tuple(MU2), law=LAW_MOONEY_RIVLIN, qp_policy=QP_CACHE_T4, inclusions=w["inclusions"],
+                   dirichlet_mask=w["mask"], **kw)
+
+
+@pytest.mark.parametrize("scatter", [0, 1, 2, 3, -1], ids=["atomic", "color", "tile", "elem", "auto"])
+@pytest.mark.parametrize("name", list(CASES))
+def test_mr_vmult(name, scatter):
+    log_case("mr_vmult", name=name, scatter=scatter)
+    w = CASES[name]
+    _, _, _, K, _ = _oracle(name)
+    P = _problem(w, scatter=scatter)
+    assert P.set_deformation(dev(w["u"])) > 0
+    y = host(P.tangent_vmult(dev(w["x"])))
+    assert rel_l2(y, K @ w["x"]) <= 1e-12
+    if scatter in (0, 2, 3):
+        x32 = w["x"].astype(np.float32)
+        y32 = host(P.tangent_vmult(dev(x32, torch.float32)))
+        assert rel_l2(y32, K @ x32.astype(np.float64)) <= 1e-5
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_mr_residual_and_csr(name):
+    log_case("mr_residual_csr", name=name)
+    w = CASES[name]
+    mesh, _, cons, K, R = _oracle(name)
+    P = _problem(w)
+    r = host(P.residual(dev(w["u"])))
+    assert rel_l2(r, R) <= 1e-12
+    assert np.all(r[cons] == 0.0)
+    P.set_deformation(dev(w["u"]))
+    rp, col, val = (t.cpu().numpy() for t in P.csr_assemble())
+    import scipy.sparse as sp
+    A = sp.csr_matrix((val, col.astype(np.int64), rp), shape=K.shape)
+    assert abs(A - K).max() <= 1e-12 * abs(K).max()
+
+
+def test_mr_differs_from_neo_hooke():
+    """The second-invariant term changes the device operator (the test above
+    would also pass if the law were ignored only when it had no effect)."""
+    from paper_1904_13131_amd import QP_CACHE_T4, Problem
+    w = CASES["3d_q2"]
+    log_case("mr_vs_nh")
+    P = _problem(w)
+    Q = Problem(3, w["n_cells"], w["degree"], mu=tuple(MU), lam=tuple(LAM), qp_policy=QP_CACHE_T4,
+                inclusions=w["inclusions"], dirichlet_mask=w["mask"])
+    for X in (P, Q):
+        X.set_deformation(dev(w["u"]))
+    a, b = host(P.tangent_vmult(dev(w["x"]))), host(Q.tangent_vmult(dev(w["x"])))
+    assert rel_l2(a, b) > 1e-3
+
+
+HIER = {
+    "3d_q2": dict(dim=3, n_coarse=2, degree=2, n_levels=3, coarse=0),
+    "3d_q2_chebcoarse": dict(dim=3, n_coarse=2, degree=2, n_levels=3, coarse=1),
+    "2d_q3": dict(dim=2, n_coarse=2, degree=3, n_levels=3, coarse=0),
+}
+
+
+def _hier(name):
+    c = HIER[name]
+    dim = c["dim"]
+    incl = W.spheres(3, 3, dim)
+    mask = W.clamp_bottom_top(dim)
+    H = gmg.Hierarchy(dim, c["n_coarse"], c["degree"], c["n_levels"], fe.Material(MU, LAM, incl, mu2=MU2), mask,
+                      coarse_solver="chebyshev" if c["coarse"] else "direct")
+    fine = H.meshes[-1]
+    u = W.stretched_field(dim, fine.L, 0.05, 4, 0.0025, coords=fine.coords_1d())
+    H.set_deformation(u)
+    b = W.normal_vector(fine.n_dofs, 5)
+    b[H.cons[-1]] = 0.0
+    w = dict(dim=dim, n_cells=c["n_coarse"] * 2 ** (c["n_levels"] - 1), degree=c["degree"], inclusions=incl,
+             mask=mask)
+    return c, H, u, b, w
+
+
+@pytest.mark.parametrize("name", list(HIER))
+def test_mr_gmg(name):
+    from paper_1904_13131_amd import F32, F64
+    log_case("mr_gmg", name=name)
+    c, H, u, b, w = _hier(name)
+    tol = 1e-5 if c["coarse"] else 1e-12
+    for vdt in (F64, F32):
+        P = _problem(w, n_levels=c["n_levels"], vcycle_dtype=vdt, coarse_solver=c["coarse"])
+        P.set_deformation(dev(u))
+        if vdt == F64:
+            for l in range(c["n_levels"]):
+                assert rel_l2(host(P.level_diagonal(l)), H.A[l].diagonal()) <= 1e-12
+            for l in range(1, c["n_levels"]):
+                assert abs(P.level_lambda_max(l) - H.lam_max[l]) <= 1e-8 * H.lam_max[l]
+            assert rel_l2(host(P.gmg_vcycle(dev(b))), H.vcycle(b)) <= tol
+        x, it, rel, _ = P.cg_solve(dev(b), rtol=1e-8, max_it=200)
+        xh = host(x)
+        assert rel <= 1e-8
+        assert np.linalg.norm(b - H.A[-1] @ xh) <= 1.05e-8 * np.linalg.norm(b)
+        _, it_o, _ = gmg.pcg(lambda v: H.A[-1] @ v, b, H.vcycle, 1e-8, 200)
+        assert it <= it_o + (1 if vdt == F64 else 3)
+
+
+def test_mr_newton_matches_oracle():
+    """Uniaxial stretch of a clamped 3-D bar with inclusions in two load steps:
+    the device Newton solve and the oracle's converge to the same state."""
+    from paper_1904_13131_amd import F64
+    from oracle import newton
+    log_case("mr_newton")
+    dim = 3
+    incl = W.spheres(3, 3, dim)
+    mask = W.clamp_bottom_top(dim)
+    H = gmg.Hierarchy(dim, 1, 2, 3, fe.Material(MU, LAM, incl, mu2=MU2), mask)
+    fv = np.zeros((2 * dim, dim))
+    fv[2 * (dim - 1) + 1][dim - 1] = 0.08
+    u_o, recs_o = newton.solve(H, fv, n_steps=2)
+    w = dict(dim=dim, n_cells=4, degree=2, inclusions=incl, mask=mask)
+    P = _problem(w, n_levels=3, vcycle_dtype=F64)
+    u = torch.zeros(P.n_dofs(), dtype=torch.float64, device="cuda")
+    recs, st = P.newton_solve(u, fv, n_steps=2)
+    assert recs[-1]["load_fraction"] == 1.0
+    assert len(recs) == len(recs_o)
+    assert rel_l2(host(u), u_o) <= 1e-7
+
+
+def test_mr_batch_vmult():
+    """Batched vmult of C4 problems (two laws mixed) equals the per-problem vmults."""
+    from paper_1904_13131_amd import QP_CACHE_T4, Batch, Problem
+    log_case("mr_batch")
+    probs, xs = [], []
+    for k, name in enumerate(["3d_q1_clamp", "3d_q2", "3d_q3", "3d_q4_clamp"]):
+        w = CASES[name]
+        s = torch.cuda.Stream()
+        if k % 2:
+            P = Problem(3, w["n_cells"], w["degree"], mu=tuple(MU), lam=tuple(LAM), qp_policy=QP_CACHE_T4,
+                        inclusions=w["inclusions"], dirichlet_mask=w["mask"], stream=s)
+        else:
+            P = _problem(w, stream=s)
+        probs.append(P)
+        xs.append(dev(w["x"]))
+    us = [dev(CASES[n]["u"]) for n in ["3d_q1_clamp", "3d_q2", "3d_q3", "3d_q4_clamp"]]
+    torch.cuda.synchronize()
+    B = Batch(probs)
+    B.set_deformation(us)
+    ys = [torch.empty_like(x) for x in xs]
+    B.tangent_vmult(xs, ys)
+    torch.cuda.synchronize()
+    for P, x, y in zip(probs, xs, ys):
+        ref = P.tangent_vmult(x)
+        torch.cuda.synchronize()
+        assert rel_l2(host(y), host(ref)) <= 1e-13
