@@ -57,7 +57,12 @@ template <int DIM, int N1>
 struct Geo {
   static constexpr int NP = DIM == 3 ? N1 * N1 : N1;   // pencils per cell
   static constexpr int NV = NP * N1;                   // points per cell
-  static constexpr int CPB = kBlock / NP;              // cells per block
+  // cells per block: as many as the block's threads hold, except where the
+  // FP64 LDS footprint (DIM * NARR * NV * CPB doubles) would let fewer blocks
+  // reside on a CU (160 KB of LDS): 3-D Q2 takes 27 (52.5 KB, three blocks
+  // instead of two), 3-D Q4 takes 8 (72 KB, two blocks instead of one); this
+  // measured 6-10 % (Q2) and 23-25 % (Q4) faster FP64 vmults at equal FP32 ones.
+  static constexpr int CPB = DIM == 3 && N1 == 3 ? 27 : DIM == 3 && N1 == 5 ? 8 : kBlock / NP;
   static constexpr int NARR = DIM == 3 ? 3 : 2;        // LDS arrays per component
 };
 

@@ -221,7 +221,11 @@ def test_coarse_inertia_matches_oracle():
     b = W.normal_vector(P.n_dofs(), 3)
     b[cons] = 0.0
     z = host(P.gmg_vcycle(dev(b)))            # one level: the V-cycle is the exact solve
-    assert rel_l2(K @ z, b) <= 1e-14 * kappa   # backward-stable bound for the condition number
+    # the solve multiplies by an explicitly inverted matrix (Gauss-Jordan), whose
+    # residual is bounded by a modest multiple of n u kappa, not u kappa; the
+    # matrix entries themselves are summed by atomics, so the rounding varies
+    n_free = int((~cons).sum())
+    assert rel_l2(K @ z, b) <= n_free * np.finfo(np.float64).eps * kappa
 
 
 def test_error_paths():
