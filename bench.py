@@ -36,10 +36,11 @@ POLICIES = {0: "recompute", 1: "cache_F", 2: "cache_T2", 3: "cache_T4"}
 # rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by a 256 MiB device copy (reads
 # x2.0, writes x1.0; profiles/tangent_vmult_q2_32cube_hbm_counters.md); valid
 # only for the kernel source they were taken on.
-TRAFFIC_SOURCE_SHA = "c88f2b3265071197"
-TRAFFIC = {"recompute/f64/element": 65941978, "recompute/f32/element": 34153468,
-           "cache_F/f64/element": 123609236, "cache_F/f32/element": 62696136,
-           "cache_T2/f64/element": 174075858, "cache_T2/f32/element": 88965696}
+TRAFFIC_SOURCE_SHA = "f4f8a4551b1fb6f1"
+TRAFFIC = {"recompute/f64/element": 65925200, "recompute/f32/element": 34136073,
+           "cache_F/f64/element": 123319211, "cache_F/f32/element": 62655902,
+           "cache_T2/f64/element": 173861301, "cache_T2/f32/element": 87598126,
+           "cache_T4/f64/atomic": 328680651, "cache_T4/f32/element": 173256417}
 
 QP_FLOPS_3D = {0: 313, 1: 307, 2: 188, 3: 246}
 QP_FLOPS_2D = {0: 118, 1: 116, 2: 78, 3: 71}
