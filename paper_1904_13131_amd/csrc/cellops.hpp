@@ -321,12 +321,14 @@ struct CellPos {
   __device__ void init(const CellArgs<T>& a, long long lin, int pen) {
     constexpr int P = N1 - 1;
     int ex, ey, ez;
-    if (a.color < 0) {
+    if (a.color < 0) {   // cells of a level < 2^32 (lattice of at most 1600^3 nodes)
       e = lin;
-      ex = (int)(lin % a.N);
-      const long long r = lin / a.N;
-      ey = (int)(r % a.N);
-      ez = (int)(r / a.N);
+      const unsigned ul = (unsigned)lin, un = (unsigned)a.N;
+      const unsigned r = ul / un;
+      ex = (int)(ul - r * un);
+      const unsigned r2 = r / un;
+      ey = (int)(r - r2 * un);
+      ez = (int)r2;
     } else {
       const int cx = a.color & 1, cy = (a.color >> 1) & 1, cz = (a.color >> 2) & 1;
       const int nx = (a.N - cx + 1) / 2, ny = (a.N - cy + 1) / 2;
@@ -361,16 +363,18 @@ template <int DIM, int N1, typename T>
 __device__ __forceinline__ void gather(const T* __restrict__ src, const CellArgs<T>& a,
                                        const CellPos<DIM, N1>& cp, bool act, bool masked,
                                        T (&v)[DIM][N1]) {
+  // all loads first (inactive lanes read the valid line of cell 0), then the masking,
+  // so that the loads of every component are in flight together
+#pragma unroll
+  for (int c = 0; c < DIM; ++c)
+#pragma unroll
+    for (int k = 0; k < N1; ++k) v[c][k] = src[c * a.nn + cp.base + k];
 #pragma unroll
   for (int c = 0; c < DIM; ++c)
 #pragma unroll
     for (int k = 0; k < N1; ++k) {
-      T val = 0;
-      if (act) {
-        val = src[c * a.nn + cp.base + k];
-        if (masked && a.mask_in && (cp.faces(k, a.L) & a.fmask[c])) val = 0;
-      }
-      v[c][k] = val;
+      const bool zero = !act || (masked && a.mask_in && (cp.faces(k, a.L) & a.fmask[c]));
+      v[c][k] = zero ? T(0) : v[c][k];
     }
 }
 
@@ -743,12 +747,13 @@ __device__ __forceinline__ void tangent_block(const CellArgs<T>& a, const T* __r
       const int mid = material_of(a, cp.e, qp);
       const T mu = mid ? a.mu[1] : a.mu[0];
       const T lam = mid ? a.lam[1] : a.lam[0];
-      const T wt = qp_weight<DIM, N1, T>(a.tb, p0, p1, q) * a.wscale;
+      // the action is linear in Grad x: the 1/h of the trial gradient joins the weight
+      const T wt = qp_weight<DIM, N1, T>(a.tb, p0, p1, q) * a.wscale * a.invh;
       T Hx[DIM][DIM];
 #pragma unroll
       for (int i = 0; i < DIM; ++i)
 #pragma unroll
-        for (int I = 0; I < DIM; ++I) Hx[i][I] = gx[i][I][q] * a.invh;
+        for (int I = 0; I < DIM; ++I) Hx[i][I] = gx[i][I][q];
       if constexpr (POL == POL_C4) {
         tangent_qp_c4<DIM, T>(Hx, a.cache + (long long)qp * a.ncells + cp.e, (long long)G::NV * a.ncells, wt);
       } else {
@@ -816,8 +821,8 @@ __device__ __forceinline__ void tangent_block(const CellArgs<T>& a, const T* __r
     // both are in one wave: its last x-node is this cell's first one.  Pass it
     // over and let one lane add the sum, saving a third of the atomics.
     const int lane = t & 63;
-    const bool from_prev = act && cl > 0 && lane > 0 && (cp.e % a.N) != 0;
-    const bool to_next = act && cl + 1 < G::CPB && lane < 63 && lin + 1 < a.nlaunch && ((cp.e + 1) % a.N) != 0;
+    const bool from_prev = act && cl > 0 && lane > 0 && !cp.first_i;
+    const bool to_next = act && cl + 1 < G::CPB && lane < 63 && lin + 1 < a.nlaunch && !cp.last_i;
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
       const T v = __shfl_up(out[c][N1 - 1], 1);
@@ -832,38 +837,31 @@ __device__ __forceinline__ void tangent_block(const CellArgs<T>& a, const T* __r
 // Second pass of the ELEMENT scatter: y at every node is the sum of the
 // element-buffer entries of the (at most 2^dim) cells containing it, in a
 // fixed order; constrained entries take x (mask_in = 1) or 0.  One thread per
-// node of an (i, j) plane; blockIdx.y is the plane k, blockIdx.z the
-// component.  j = t / L comes from a multiply-high by magic = ceil(2^32 / L),
-// exact for t < L^2 while L^3 < 2^32.
+// node of an (i, j) plane and all its components (the d * 2^d loads are in
+// flight together); blockIdx.y is the plane k.  j = t / L comes from a
+// multiply-high by magic = ceil(2^32 / L), exact for t < L^2 while L^3 < 2^32.
 template <int DIM, int P, typename T>
 __device__ __forceinline__ void elem_gather_node(const CellArgs<T>& a, const T* __restrict__ x, T* __restrict__ y,
-                                                 int t, int k, int c, unsigned magic) {
+                                                 int t, int k, unsigned magic) {
   constexpr int N1 = P + 1;
   constexpr int NV = Geo<DIM, N1>::NV;
   const int N = a.N, L = a.L;
   if (t >= L * L) return;
   const int j = (int)__umulhi((unsigned)t, magic);
   const int i = t - j * L;
-  const long long gi = c * a.nn + t + (long long)L * L * k;
-  if (node_faces(i, j, k, L, DIM) & a.fmask[c]) {
-    y[gi] = a.mask_in ? x[gi] : T(0);
-    return;
-  }
+  const unsigned fc = node_faces(i, j, k, L, DIM);
   int ce[3][2], cn[3][2], m[3];
   const int idx[3] = {i, j, k};
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     if (d >= DIM) {
-      ce[d][0] = 0;
-      cn[d][0] = 0;
-      ce[d][1] = 0;
-      cn[d][1] = 0;
+      ce[d][0] = ce[d][1] = 0;
+      cn[d][0] = cn[d][1] = 0;
       m[d] = 1;
       continue;
     }
     const int q = idx[d] / P, rem = idx[d] - q * P;
     const bool inner = rem != 0;
-    // two candidates: (q - 1, P) and (q, 0) on a cell corner line, else (q, rem)
     const bool has_lo = !inner && q > 0, has_hi = inner || q < N;
     ce[d][0] = has_lo ? q - 1 : q;
     cn[d][0] = has_lo ? P : rem;
@@ -871,31 +869,44 @@ __device__ __forceinline__ void elem_gather_node(const CellArgs<T>& a, const T* 
     cn[d][1] = 0;
     m[d] = (has_lo && has_hi) ? 2 : 1;
   }
-  const T* base = a.elem + (long long)c * NV * a.ncells;
-  T acc = 0;
+  // the (at most 2^DIM) entries of every component: loads first, then the sums
+  T v[DIM][DIM == 3 ? 8 : 4];
 #pragma unroll
-  for (int zz = 0; zz < (DIM == 3 ? 2 : 1); ++zz)
+  for (int c = 0; c < DIM; ++c) {
+    const T* base = a.elem + (long long)c * NV * a.ncells;
 #pragma unroll
-    for (int yy = 0; yy < 2; ++yy)
+    for (int zz = 0; zz < (DIM == 3 ? 2 : 1); ++zz)
 #pragma unroll
-      for (int xx = 0; xx < 2; ++xx) {
-        if (xx < m[0] && yy < m[1] && zz < m[2]) {
+      for (int yy = 0; yy < 2; ++yy)
+#pragma unroll
+        for (int xx = 0; xx < 2; ++xx) {
+          const int s = xx + 2 * (yy + 2 * zz);
+          const bool on = xx < m[0] && yy < m[1] && zz < m[2];
           const int e = ce[0][xx] + N * (ce[1][yy] + N * ce[2][zz]);
           const int n = cn[0][xx] + N1 * (cn[1][yy] + N1 * cn[2][zz]);
-          acc += base[(long long)n * a.ncells + e];
+          const T val = base[on ? (long long)n * a.ncells + e : 0];   // in bounds for every lane
+          v[c][s] = on ? val : T(0);
         }
-      }
-  y[gi] = acc;
+  }
+#pragma unroll
+  for (int c = 0; c < DIM; ++c) {
+    const long long gi = c * a.nn + t + (long long)L * L * k;
+    T acc = 0;
+#pragma unroll
+    for (int s = 0; s < (DIM == 3 ? 8 : 4); ++s) acc += v[c][s];
+    if (fc & a.fmask[c]) acc = a.mask_in ? x[gi] : T(0);
+    y[gi] = acc;
+  }
 }
 
 template <int DIM, int P, typename T>
 __global__ void __launch_bounds__(kBlock) k_elem_gather(CellArgs<T> arg, unsigned magic) {
   const CellArgs<T>& a = kernel_args(arg);
-  elem_gather_node<DIM, P, T>(a, a.x, a.y, blockIdx.x * kBlock + threadIdx.x, blockIdx.y, blockIdx.z, magic);
+  elem_gather_node<DIM, P, T>(a, a.x, a.y, blockIdx.x * kBlock + threadIdx.x, blockIdx.y, magic);
 }
 
-// Batched second pass: one workgroup per item (problem, plane k, component,
-// block of the plane) of the problems that use the ELEMENT scatter.
+// Batched second pass: one workgroup per item (problem, plane k, block of the
+// plane) of the problems that use the ELEMENT scatter.
 
 template <int DIM, int P, typename T>
 __global__ void __launch_bounds__(kBlock) k_elem_gather_batch(const CellArgs<T>* __restrict__ args,
@@ -907,11 +918,10 @@ __global__ void __launch_bounds__(kBlock) k_elem_gather_batch(const CellArgs<T>*
   using CPtrX = const T* const __attribute__((address_space(4)));
   using CPtrY = T* const __attribute__((address_space(4)));
   const CInt* it = (CInt*)(items + blockIdx.x);
-  const int p = it[0], kc = it[1], blk = it[2];
+  const int p = it[0], k = it[1], blk = it[2];
   const unsigned magic = (unsigned)it[3];
   const CellArgs<T>& a = *(const CellArgs<T>*)((CArgs*)args + p);
-  elem_gather_node<DIM, P, T>(a, ((CPtrX*)xs)[p], ((CPtrY*)ys)[p], blk * kBlock + threadIdx.x, kc >> 2, kc & 3,
-                              magic);
+  elem_gather_node<DIM, P, T>(a, ((CPtrX*)xs)[p], ((CPtrY*)ys)[p], blk * kBlock + threadIdx.x, k, magic);
 }
 
 // Tangent vmult: y += K x over the cells of this launch (y pre-filled).

@@ -63,7 +63,7 @@ __device__ __forceinline__ const A& kernel_args(const A& byval) {
 // Work item of the batched node-sum kernel (ELEMENT scatter).
 struct GatherItem {
   int p;            // problem index in the bin's argument table
-  int kc;           // plane k * 4 + component
+  int k;            // plane k of the lattice (0 in 2-D)
   int blk;          // block of kBlock nodes in the (i, j) plane
   unsigned magic;   // ceil(2^32 / L) of the problem's lattice
 };

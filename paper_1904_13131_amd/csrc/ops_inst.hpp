@@ -68,7 +68,7 @@ struct OpInst {
   static void elem_gather(const CellArgs<T>& a, hipStream_t s) {
     const unsigned plane = (unsigned)a.L * (unsigned)a.L;
     const unsigned magic = (unsigned)((((unsigned long long)1 << 32) + (unsigned)a.L - 1) / (unsigned)a.L);
-    const dim3 grid((plane + kBlock - 1) / kBlock, DIM == 3 ? a.L : 1, DIM);
+    const dim3 grid((plane + kBlock - 1) / kBlock, DIM == 3 ? a.L : 1, 1);
     hipLaunchKernelGGL((k_elem_gather<DIM, P, T>), grid, dim3(kBlock), 0, s, a, magic);
   }
   static void residual(const CellArgs<double>& a, unsigned grid, hipStream_t s) {

@@ -1674,7 +1674,7 @@ bool batch_elem(const mfh_problem* P, int t) { return scatter_mode(P, P->lv.back
 
 long long gather_blocks(const mfh_problem* P) {
   const long long L = P->lv.back().L;
-  return ((L * L + kBlock - 1) / kBlock) * (P->d.dim == 3 ? L : 1) * P->d.dim;
+  return ((L * L + kBlock - 1) / kBlock) * (P->d.dim == 3 ? L : 1);
 }
 
 size_t batch_layout(mfh_batch* B, char* base) {
@@ -1881,8 +1881,7 @@ mfh_status mfh_batch_create(int n, mfh_problem* const* probs, void* ws, size_t b
         for (int t = 0; t < 2; ++t) {
           if (!batch_elem(P, t)) continue;
           for (int kk = 0; kk < (P->d.dim == 3 ? (int)L : 1); ++kk)
-            for (int c = 0; c < P->d.dim; ++c)
-              for (int blk = 0; blk < pblocks; ++blk) g[t].push_back(GatherItem{(int)k, kk * 4 + c, blk, magic});
+            for (int blk = 0; blk < pblocks; ++blk) g[t].push_back(GatherItem{(int)k, kk, blk, magic});
         }
       }
       HIPCHECK(hipMemcpyAsync(bin.a64, a64.data(), sizeof(CellArgs<double>) * nb, hipMemcpyHostToDevice, s));
