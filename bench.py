@@ -36,11 +36,11 @@ POLICIES = {0: "recompute", 1: "cache_F", 2: "cache_T2", 3: "cache_T4"}
 # rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by a 256 MiB device copy (reads
 # x2.0, writes x1.0; profiles/tangent_vmult_q2_32cube_hbm_counters.md); valid
 # only for the kernel source they were taken on.
-TRAFFIC_SOURCE_SHA = "f4f8a4551b1fb6f1"
-TRAFFIC = {"recompute/f64/element": 65925200, "recompute/f32/element": 34136073,
-           "cache_F/f64/element": 123319211, "cache_F/f32/element": 62655902,
-           "cache_T2/f64/element": 173861301, "cache_T2/f32/element": 87598126,
-           "cache_T4/f64/atomic": 328680651, "cache_T4/f32/element": 173256417}
+TRAFFIC_SOURCE_SHA = "73a8440c8f063bcc"
+TRAFFIC = {"recompute/f64/element": 65952731, "cache_F/f64/element": 123286366,
+           "cache_T2/f64/element": 173970456, "cache_T4/f64/element": 354076461,
+           "recompute/f32/element": 34136544, "cache_F/f32/element": 62522345,
+           "cache_T2/f32/element": 87753531, "cache_T4/f32/element": 173974422}
 
 QP_FLOPS_3D = {0: 313, 1: 307, 2: 188, 3: 246}
 QP_FLOPS_2D = {0: 118, 1: 116, 2: 78, 3: 71}
@@ -255,6 +255,9 @@ def newton_bench(w, n_cells=64, n_levels=5, stretch=0.1, n_steps=4, shear_tracti
                        f"Chebyshev coarse solver to 1e-3, eigenvalue estimates of the first linearisation "
                        f"reused)"}
     runs = (("mixed", dict(vcycle_dtype=F32)), ("fp64", dict(vcycle_dtype=F64)),
+            # quadrature-point data cached on every level (Algorithm 2's trade-off)
+            ("mixed_cache_T2", dict(vcycle_dtype=F32, qp_policy=2)),
+            ("mixed_cache_F", dict(vcycle_dtype=F32, qp_policy=1)),
             # solver settings of the paper (Sec. 7) and their alternatives, all mixed precision
             ("mixed_V11", dict(vcycle_dtype=F32, n_smooth=1)),
             ("mixed_chebyshev_coarse", dict(vcycle_dtype=F32, coarse_solver=1)),
