@@ -1,0 +1,108 @@
+"""Edge cases of the device path against the oracle: single-cell meshes of
+every degree, fully constrained boundaries, zero and undeformed inputs, a
+body that is all inclusion, and the largest lattice the library accepts (2-D,
+1600 nodes per direction), checked on sampled rows.
+
+Bars as in the operator tests: FP64 relative l2 <= 1e-12 (absolute on
+sampled rows, relative to the largest entry)."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import fe
+from tests.gpu_helpers import dev, device_problem, host, log_case, oracle_problem, rel_l2, requires_gpu
+
+pytestmark = [pytest.mark.gpu, requires_gpu]
+
+ALL_FACES = {2: (1 << 8) - 1, 3: (1 << 18) - 1}
+
+
+@pytest.mark.parametrize("policy", [0, 1, 2, 3], ids=["R", "CF", "C2", "C4"])
+@pytest.mark.parametrize("dim,p", [(2, 1), (2, 4), (3, 1), (3, 2), (3, 3), (3, 4)])
+def test_single_cell(dim, p, policy):
+    log_case("single_cell", dim=dim, p=p, policy=policy)
+    w = W.problem(dim, 1, p, disc=(dim == 2), n_spheres=0 if dim == 2 else 1, u_amp=0.03, u_kmax=1,
+                  mask=W.face_bits(dim, 0, 0))
+    mesh, mat, cons = oracle_problem(w)
+    K = fe.constrain_matrix(fe.tangent_matrix(mesh, mat, w["u"]), cons)
+    P = device_problem(w, qp_policy=policy)
+    P.set_deformation(dev(w["u"]))
+    y = host(P.tangent_vmult(dev(w["x"])))
+    assert rel_l2(y, K @ w["x"]) <= 1e-12
+    r = host(P.residual(dev(w["u"])))
+    assert rel_l2(r, fe.residual(mesh, mat, w["u"], cons)) <= 1e-12
+
+
+@pytest.mark.parametrize("scatter", [0, 1, 2, 3], ids=["atomic", "color", "tile", "elem"])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_fully_constrained_boundary(dim, scatter):
+    """Every face fixes every component: boundary rows are the identity (y = x
+    there) and the interior rows see x with its boundary entries zeroed."""
+    log_case("all_faces", dim=dim, scatter=scatter)
+    w = W.problem(dim, 4 if dim == 3 else 6, 2, n_spheres=2 if dim == 3 else 0, disc=dim == 2, u_amp=0.03,
+                  u_kmax=1, mask=ALL_FACES[dim])
+    mesh, mat, cons = oracle_problem(w)
+    K = fe.constrain_matrix(fe.tangent_matrix(mesh, mat, w["u"]), cons)
+    P = device_problem(w, scatter=scatter)
+    P.set_deformation(dev(w["u"]))
+    y = host(P.tangent_vmult(dev(w["x"])))
+    assert np.array_equal(y[cons], w["x"][cons])
+    assert rel_l2(y, K @ w["x"]) <= 1e-12
+    r = host(P.residual(dev(w["u"])))
+    assert np.all(r[cons] == 0.0)
+
+
+@pytest.mark.parametrize("policy", [0, 2], ids=["R", "C2"])
+def test_zero_input_and_undeformed_state(policy):
+    """K x = 0 for x = 0 (every scatter path writes every entry); at u = 0 the
+    operator is the small-strain one (oracle at u = 0) and the residual is 0."""
+    log_case("zero_and_undeformed", policy=policy)
+    w = W.problem(3, 5, 2, n_spheres=3, u_amp=0.0, mask=W.clamp_bottom_top(3))
+    mesh, mat, cons = oracle_problem(w)
+    K0 = fe.constrain_matrix(fe.tangent_matrix(mesh, mat, np.zeros(mesh.n_dofs)), cons)
+    for scatter in (0, 1, 2, 3):
+        P = device_problem(w, qp_policy=policy, scatter=scatter)
+        assert P.set_deformation(dev(np.zeros(mesh.n_dofs))) == 1.0
+        y = torch.full((mesh.n_dofs,), float("nan"), dtype=torch.float64, device="cuda")
+        P.tangent_vmult(dev(np.zeros(mesh.n_dofs)), y)
+        assert not host(y).any()
+        assert rel_l2(host(P.tangent_vmult(dev(w["x"]))), K0 @ w["x"]) <= 1e-12
+        assert not host(P.residual(dev(np.zeros(mesh.n_dofs)))).any()
+
+
+def test_body_that_is_all_inclusion():
+    """One inclusion covering the whole body: the operator is the stiff
+    material's, i.e. 100 times the matrix material's (both moduli scale)."""
+    log_case("all_inclusion")
+    w = W.problem(3, 3, 2, u_amp=0.04, u_kmax=1)
+    w["inclusions"] = [(np.full(3, 0.5), 2.0, 1)]
+    mesh, mat, cons = oracle_problem(w)
+    K = fe.tangent_matrix(mesh, mat, w["u"])
+    soft = fe.tangent_matrix(mesh, fe.Material([w["mu"][0]], [w["lam"][0]]), w["u"])
+    assert abs(K - 100.0 * soft).max() <= 1e-11 * abs(K).max()
+    P = device_problem(w)
+    P.set_deformation(dev(w["u"]))
+    assert rel_l2(host(P.tangent_vmult(dev(w["x"]))), K @ w["x"]) <= 1e-12
+
+
+def test_largest_lattice_2d():
+    """2-D Q1 with 1599 cells per direction: 1600 nodes per direction, the
+    largest lattice the descriptor accepts (5.12 M DoFs); sampled rows
+    (corners, edges, interior) against the oracle's row-wise vmult, and
+    translations in the kernel of the unconstrained operator."""
+    log_case("largest_2d")
+    w = W.problem(2, 1599, 1, disc=True, u_amp=0.02, u_kmax=1)
+    mesh, mat, cons = oracle_problem(w)
+    assert mesh.L == 1600
+    P = device_problem(w)
+    P.set_deformation(dev(w["u"]))
+    y = host(P.tangent_vmult(dev(w["x"])))
+    L = mesh.L
+    rng = np.random.default_rng(9)
+    rows = np.unique(np.concatenate([rng.choice(mesh.n_dofs, 40, replace=False),
+                                     [0, L - 1, L * (L - 1), L * L - 1, L * L + L // 2, 2 * L * L - 1]]))
+    ref = fe.vmult_rows(mesh, mat, w["u"], w["x"], rows)
+    np.testing.assert_allclose(y[rows], ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+    t = np.concatenate([np.ones(L * L), np.zeros(L * L)])
+    assert np.abs(host(P.tangent_vmult(dev(t)))).max() <= 1e-9
