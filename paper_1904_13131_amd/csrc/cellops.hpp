@@ -604,21 +604,42 @@ __device__ __forceinline__ void mr_spatial_tangent(const T (&F)[DIM][DIM], T jm1
     }
 }
 
+// Per-lane arrays at a wave-uniform base (caches, element buffer): with O32
+// the lane's offset is a 32-bit byte count, so the loads and stores take the
+// base from scalar registers and need no 64-bit address arithmetic per
+// access; the launcher picks O32 when every offset of the level fits
+// (NV * cells * sizeof(T) < 2^32), else the 64-bit form.
+template <bool O32, typename T>
+__device__ __forceinline__ T lane_load(const T* ubase, long long lane, unsigned lane_bytes) {
+  if constexpr (O32)
+    return *(const T*)((const char*)ubase + lane_bytes);
+  else
+    return ubase[lane];
+}
+template <bool O32, typename T>
+__device__ __forceinline__ void lane_store(T* ubase, long long lane, unsigned lane_bytes, T v) {
+  if constexpr (O32)
+    *(T*)((char*)ubase + lane_bytes) = v;
+  else
+    ubase[lane] = v;
+}
+
 // Tangent action with a cached general tangent (Algorithm 3, referential
 // form): g = Grad x F^-1, sigma = J c : sym g, P_x = sigma F^-T + Grad x S.
-// Hx (physical Grad x) -> P_x * wt, in place.  cq points at word 0 of this
-// quadrature point's C4 cache (F^-1, S upper triangle, J c packed Voigt),
-// words `stride` apart; J c is streamed word by word into the symmetric
-// product so that only sym g and sigma stay live.  The law enters only
-// through the cached data.
-template <int DIM, typename T>
-__device__ __forceinline__ void tangent_qp_c4(T (&Hx)[DIM][DIM], const T* __restrict__ cq, long long stride, T wt) {
+// Hx (Grad x) -> P_x * wt, in place.  Word w of this quadrature point's C4
+// cache (F^-1, S upper triangle, J c packed Voigt) is lane element `lane` of
+// the array at qb + w * stride; J c is streamed word by word into the
+// symmetric product so that only sym g and sigma stay live.  The law enters
+// only through the cached data.
+template <int DIM, typename T, bool O32>
+__device__ __forceinline__ void tangent_qp_c4(T (&Hx)[DIM][DIM], const T* __restrict__ qb, long long stride,
+                                              long long lane, unsigned lane_bytes, T wt) {
   using V = Voigt<DIM>;
   T Fi[DIM][DIM];
 #pragma unroll
   for (int I = 0; I < DIM; ++I)
 #pragma unroll
-    for (int j = 0; j < DIM; ++j) Fi[I][j] = cq[(I * DIM + j) * stride];
+    for (int j = 0; j < DIM; ++j) Fi[I][j] = lane_load<O32>(qb + (I * DIM + j) * stride, lane, lane_bytes);
   T gam[V::N];   // sym g in Voigt form, shear entries doubled
 #pragma unroll
   for (int A = 0; A < V::N; ++A) {
@@ -631,13 +652,13 @@ __device__ __forceinline__ void tangent_qp_c4(T (&Hx)[DIM][DIM], const T* __rest
     }
     gam[A] = i == j ? gij : gij + gji;
   }
-  const T* cv = cq + (DIM * DIM + V::N) * stride;
+  const T* cv = qb + (DIM * DIM + V::N) * stride;
   T sv[V::N] = {};
 #pragma unroll
   for (int A = 0; A < V::N; ++A)
 #pragma unroll
     for (int B = A; B < V::N; ++B) {
-      const T c = cv[V::packed(A, B) * stride];
+      const T c = lane_load<O32>(cv + V::packed(A, B) * stride, lane, lane_bytes);
       sv[A] += c * gam[B];
       if (B != A) sv[B] += c * gam[A];
     }
@@ -654,7 +675,7 @@ __device__ __forceinline__ void tangent_qp_c4(T (&Hx)[DIM][DIM], const T* __rest
     for (int I = 0; I < DIM; ++I)
 #pragma unroll
       for (int J = I; J < DIM; ++J) {
-        const T v = cq[(w++) * stride];
+        const T v = lane_load<O32>(qb + (w++) * stride, lane, lane_bytes);
         S[I][J] = v;
         S[J][I] = v;
       }
@@ -710,7 +731,7 @@ __device__ __forceinline__ int material_of(const CellArgs<T>& a, long long e, in
 // Tangent vmult body for cell block `blk` of one level: y += K x over the
 // block's cells (y pre-filled).  Shared by the single-problem kernel and the
 // batched work-list kernel.
-template <int DIM, int P, typename T, int POL>
+template <int DIM, int P, typename T, int POL, bool O32>
 __device__ __forceinline__ void tangent_block(const CellArgs<T>& a, const T* __restrict__ x, T* __restrict__ y,
                                               long long blk, T* lds) {
   constexpr int N1 = P + 1;
@@ -740,11 +761,17 @@ __device__ __forceinline__ void tangent_block(const CellArgs<T>& a, const T* __r
     SF::template forward<DIM>(v, gu, lds, pen, cl, act, a.tb);
   }
 
+  // cache word w of quadrature point (p0, p1, q): lane element qp(p0, p1, 0) *
+  // cells + e of the array at cache + (w * NV + q * NP) * cells
+  const long long lane_c = (long long)qp_index<DIM, N1>(p0, p1, 0) * a.ncells + cp.e;
+  const unsigned lane_cb = O32 ? (unsigned)lane_c * (unsigned)sizeof(T) : 0u;
+  const long long wstride = (long long)G::NV * a.ncells;
   if (act) {
 #pragma unroll
     for (int q = 0; q < N1; ++q) {
       const int qp = qp_index<DIM, N1>(p0, p1, q);
       const int mid = material_of(a, cp.e, qp);
+      const T* qb = a.cache + (long long)q * G::NP * a.ncells;
       const T mu = mid ? a.mu[1] : a.mu[0];
       const T lam = mid ? a.lam[1] : a.lam[0];
       // the action is linear in Grad x: the 1/h of the trial gradient joins the weight
@@ -755,7 +782,7 @@ __device__ __forceinline__ void tangent_block(const CellArgs<T>& a, const T* __r
 #pragma unroll
         for (int I = 0; I < DIM; ++I) Hx[i][I] = gx[i][I][q];
       if constexpr (POL == POL_C4) {
-        tangent_qp_c4<DIM, T>(Hx, a.cache + (long long)qp * a.ncells + cp.e, (long long)G::NV * a.ncells, wt);
+        tangent_qp_c4<DIM, T, O32>(Hx, qb, wstride, lane_c, lane_cb, wt);
       } else {
       T Fi[DIM][DIM], S[DIM][DIM], c1;
       if constexpr (POL == POL_R || POL == POL_CF) {
@@ -766,34 +793,31 @@ __device__ __forceinline__ void tangent_block(const CellArgs<T>& a, const T* __r
 #pragma unroll
             for (int I = 0; I < DIM; ++I) H[i][I] = gu[i][I][q] * a.invh;
         } else {
-          const T* cq = a.cache + (long long)qp * a.ncells + cp.e;
-          const long long stride = (long long)G::NV * a.ncells;
 #pragma unroll
           for (int i = 0; i < DIM; ++i)
 #pragma unroll
-            for (int I = 0; I < DIM; ++I) H[i][I] = cq[(i * DIM + I) * stride] - (i == I ? T(1) : T(0));
+            for (int I = 0; I < DIM; ++I)
+              H[i][I] = lane_load<O32>(qb + (i * DIM + I) * wstride, lane_c, lane_cb) - (i == I ? T(1) : T(0));
         }
         T F[DIM][DIM], jm1;
         kinematics<DIM, T>(H, F, Fi, jm1);
         c1 = mu - T(2) * lam * log1p_t<T>(jm1);
         pk2<DIM, T>(Fi, mu, c1, S);
       } else {
-        const T* cq = a.cache + (long long)qp * a.ncells + cp.e;
-        const long long stride = (long long)G::NV * a.ncells;
         int w = 0;
 #pragma unroll
         for (int I = 0; I < DIM; ++I)
 #pragma unroll
-          for (int j = 0; j < DIM; ++j) Fi[I][j] = cq[(w++) * stride];
+          for (int j = 0; j < DIM; ++j) Fi[I][j] = lane_load<O32>(qb + (w++) * wstride, lane_c, lane_cb);
 #pragma unroll
         for (int I = 0; I < DIM; ++I)
 #pragma unroll
           for (int J = I; J < DIM; ++J) {
-            const T s = cq[(w++) * stride];
-            S[I][J] = s;
-            S[J][I] = s;
+            const T v = lane_load<O32>(qb + (w++) * wstride, lane_c, lane_cb);
+            S[I][J] = v;
+            S[J][I] = v;
           }
-        c1 = cq[w * stride];
+        c1 = lane_load<O32>(qb + w * wstride, lane_c, lane_cb);
       }
       tangent_qp<DIM, T>(Hx, Fi, S, c1, lam, wt);
       }
@@ -814,7 +838,11 @@ __device__ __forceinline__ void tangent_block(const CellArgs<T>& a, const T* __r
 #pragma unroll
       for (int c = 0; c < DIM; ++c)
 #pragma unroll
-        for (int k = 0; k < N1; ++k) a.elem[((long long)c * G::NV + line + k) * a.ncells + cp.e] = out[c][k];
+        for (int k = 0; k < N1; ++k) {
+          const long long lane_e = (long long)line * a.ncells + cp.e;
+          lane_store<O32>(a.elem + ((long long)c * G::NV + k) * a.ncells, lane_e,
+                          O32 ? (unsigned)lane_e * (unsigned)sizeof(T) : 0u, out[c][k]);
+        }
     }
   } else if (a.color < 0) {
     // The x-neighbour of this cell (same pencil) sits in the previous lane when
@@ -925,13 +953,13 @@ __global__ void __launch_bounds__(kBlock) k_elem_gather_batch(const CellArgs<T>*
 }
 
 // Tangent vmult: y += K x over the cells of this launch (y pre-filled).
-template <int DIM, int P, typename T, int POL>
+template <int DIM, int P, typename T, int POL, bool O32>
 __global__ void __launch_bounds__(kBlock) k_tangent(CellArgs<T> arg) {
   using G = Geo<DIM, P + 1>;
   __shared__ T lds[DIM * G::NARR * G::NV * G::CPB];
   const CellArgs<T>& a = kernel_args(arg);
   const long long blk = a.color < 0 ? xcd_block(blockIdx.x, gridDim.x) : (long long)blockIdx.x;
-  tangent_block<DIM, P, T, POL>(a, a.x, a.y, blk, lds);
+  tangent_block<DIM, P, T, POL, O32>(a, a.x, a.y, blk, lds);
 }
 
 // Batched tangent vmult over many independent problems of one degree: one
@@ -940,7 +968,7 @@ __global__ void __launch_bounds__(kBlock) k_tangent(CellArgs<T> arg) {
 // XCD-aware (neighbouring cell blocks of a problem share an L2) and
 // wave-uniform, so the item and the problem's arguments come in through
 // scalar loads; the block body is the single-problem one.
-template <int DIM, int P, typename T, int POL>
+template <int DIM, int P, typename T, int POL, bool O32>
 __global__ void __launch_bounds__(kBlock) k_tangent_batch(const CellArgs<T>* __restrict__ args,
                                                           const int2* __restrict__ items,
                                                           const T* const* __restrict__ xs, T* const* __restrict__ ys) {
@@ -957,7 +985,7 @@ __global__ void __launch_bounds__(kBlock) k_tangent_batch(const CellArgs<T>* __r
   const int p = ((CInt*)items)[2 * i];
   const int blk = ((CInt*)items)[2 * i + 1];
   const CellArgs<T>& a = *(const CellArgs<T>*)((CArgs*)args + p);
-  tangent_block<DIM, P, T, POL>(a, ((CPtrX*)xs)[p], ((CPtrY*)ys)[p], blk, lds);
+  tangent_block<DIM, P, T, POL, O32>(a, ((CPtrX*)xs)[p], ((CPtrY*)ys)[p], blk, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -1321,7 +1349,7 @@ k_tangent_tile(CellArgs<T> a) {
 #pragma unroll
         for (int I = 0; I < DIM; ++I) Hx[i][I] = gx[i][I][q] * a.invh;
       if constexpr (POL == POL_C4) {
-        tangent_qp_c4<DIM, T>(Hx, a.cache + (long long)qp * a.ncells + e, (long long)TG::NV * a.ncells, wt);
+        tangent_qp_c4<DIM, T, false>(Hx, a.cache, (long long)TG::NV * a.ncells, (long long)qp * a.ncells + e, 0u, wt);
       } else {
       T Fi[DIM][DIM], S[DIM][DIM], c1;
       if constexpr (POL == POL_R || POL == POL_CF) {

@@ -19,10 +19,11 @@ struct OpFns {
   void (*tangent_tile_f[4])(const CellArgs<float>&, unsigned grid, hipStream_t);
   long long (*tiles[2])(int N);   // [0] double, [1] float
   // batched vmult over problems of this (dim, degree): one workgroup per (problem, cell block) item
+  // (max_cells: the largest cell count of the bin's problems)
   void (*tangent_batch_d[4])(const CellArgs<double>* args, const int2* items, const double* const* xs,
-                             double* const* ys, unsigned n_items, hipStream_t);
+                             double* const* ys, unsigned n_items, long long max_cells, hipStream_t);
   void (*tangent_batch_f[4])(const CellArgs<float>* args, const int2* items, const float* const* xs,
-                             float* const* ys, unsigned n_items, hipStream_t);
+                             float* const* ys, unsigned n_items, long long max_cells, hipStream_t);
   // second pass of the ELEMENT scatter
   void (*elem_gather_d)(const CellArgs<double>&, hipStream_t);
   void (*elem_gather_f)(const CellArgs<float>&, hipStream_t);

@@ -50,14 +50,28 @@ struct OpInst {
     const long long tz = DIM == 3 ? (N + TC::TZ - 1) / TC::TZ : 1;
     return tx * ty * tz;
   }
+  // 32-bit lane offsets (see lane_load) when every per-lane offset of a level
+  // with `cells` cells fits
+  template <typename T>
+  static bool off32(long long cells) {
+    return (long long)Geo<DIM, P + 1>::NV * cells * (long long)sizeof(T) < (1LL << 32);
+  }
   template <typename T, int POL>
   static void tangent(const CellArgs<T>& a, unsigned grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_tangent<DIM, P, T, POL>), dim3(grid), dim3(kBlock), 0, s, a);
+    if (off32<T>(a.ncells))
+      hipLaunchKernelGGL((k_tangent<DIM, P, T, POL, true>), dim3(grid), dim3(kBlock), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_tangent<DIM, P, T, POL, false>), dim3(grid), dim3(kBlock), 0, s, a);
   }
   template <typename T, int POL>
   static void tangent_batch(const CellArgs<T>* args, const int2* items, const T* const* xs, T* const* ys,
-                            unsigned n_items, hipStream_t s) {
-    hipLaunchKernelGGL((k_tangent_batch<DIM, P, T, POL>), dim3(n_items), dim3(kBlock), 0, s, args, items, xs, ys);
+                            unsigned n_items, long long max_cells, hipStream_t s) {
+    if (off32<T>(max_cells))
+      hipLaunchKernelGGL((k_tangent_batch<DIM, P, T, POL, true>), dim3(n_items), dim3(kBlock), 0, s, args, items, xs,
+                         ys);
+    else
+      hipLaunchKernelGGL((k_tangent_batch<DIM, P, T, POL, false>), dim3(n_items), dim3(kBlock), 0, s, args, items,
+                         xs, ys);
   }
   template <typename T>
   static void elem_gather_batch(const CellArgs<T>* args, const GatherItem* items, const T* const* xs, T* const* ys,

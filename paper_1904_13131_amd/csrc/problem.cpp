@@ -1643,6 +1643,7 @@ struct mfh_batch {
     void** xs = nullptr;
     void** ys = nullptr;
     long long n_items = 0;
+    long long max_cells = 0;           // largest finest-level cell count of the bin's problems
     mfh::GatherItem* g[2] = {nullptr, nullptr};   // node-sum items of the ELEMENT problems, per precision
     long long n_g[2] = {0, 0};
     const mfh::OpFns* ops = nullptr;
@@ -1685,10 +1686,12 @@ size_t batch_layout(mfh_batch* B, char* base) {
     bin.a64 = b.take<CellArgs<double>>(nb);
     bin.a32 = b.take<CellArgs<float>>(nb);
     bin.n_items = 0;
+    bin.max_cells = 0;
     bin.n_g[0] = bin.n_g[1] = 0;
     for (int i : bin.ids) {
       const mfh_problem* P = B->probs[i];
       bin.n_items += (P->lv.back().ncells + P->ops->cpb - 1) / P->ops->cpb;
+      bin.max_cells = std::max(bin.max_cells, P->lv.back().ncells);
       for (int t = 0; t < 2; ++t)
         if (batch_elem(P, t)) bin.n_g[t] += gather_blocks(P);
     }
@@ -1769,13 +1772,15 @@ void batch_vmult(mfh_batch* B, const void* const* x, void* const* y) {
     }
     if (ti == 0) {
       bin.ops->tangent_batch_d[B->policy](bin.a64, bin.items, reinterpret_cast<const double* const*>(bin.xs),
-                                          reinterpret_cast<double* const*>(bin.ys), (unsigned)bin.n_items, s);
+                                          reinterpret_cast<double* const*>(bin.ys), (unsigned)bin.n_items,
+                                          bin.max_cells, s);
       if (bin.n_g[0])
         bin.ops->elem_gather_batch_d(bin.a64, bin.g[0], reinterpret_cast<const double* const*>(bin.xs),
                                      reinterpret_cast<double* const*>(bin.ys), (unsigned)bin.n_g[0], s);
     } else {
       bin.ops->tangent_batch_f[B->policy](bin.a32, bin.items, reinterpret_cast<const float* const*>(bin.xs),
-                                          reinterpret_cast<float* const*>(bin.ys), (unsigned)bin.n_items, s);
+                                          reinterpret_cast<float* const*>(bin.ys), (unsigned)bin.n_items,
+                                          bin.max_cells, s);
       if (bin.n_g[1])
         bin.ops->elem_gather_batch_f(bin.a32, bin.g[1], reinterpret_cast<const float* const*>(bin.xs),
                                      reinterpret_cast<float* const*>(bin.ys), (unsigned)bin.n_g[1], s);
