@@ -106,3 +106,36 @@ def test_largest_lattice_2d():
     np.testing.assert_allclose(y[rows], ref, rtol=0, atol=1e-12 * np.abs(ref).max())
     t = np.concatenate([np.ones(L * L), np.zeros(L * L)])
     assert np.abs(host(P.tangent_vmult(dev(t)))).max() <= 1e-9
+
+
+def test_level_beyond_32bit_lane_offsets():
+    """3-D Q1 with 407^3 cells (203 M DoFs): in FP64 the per-lane offsets of
+    the cache and element buffer exceed 2^32 bytes, so the vmult takes the
+    64-bit addressing form; in FP32 they lie between 2^31 and 2^32 (32-bit
+    form with offsets beyond the signed range).  Both agree with the recompute
+    policy on the atomic scatter over the whole vector and with the oracle on
+    sampled rows."""
+    from paper_1904_13131_amd import F32
+    log_case("large_offsets", cells=407 ** 3)
+    w = W.problem(3, 407, 1, n_spheres=20, u_amp=0.05, u_kmax=1, n_modes=2)
+    assert 8 * 407 ** 3 * 8 >= 2 ** 32 > 8 * 407 ** 3 * 4 >= 2 ** 31
+    mesh, mat, cons = oracle_problem(w)
+    u, x = dev(w["u"]), dev(w["x"])
+    rng = np.random.default_rng(11)
+    rows = np.unique(np.concatenate([rng.integers(0, mesh.n_dofs, 16), [mesh.n_dofs - 1]]))
+    ref = fe.vmult_rows(mesh, mat, w["u"], w["x"], rows)
+    P = device_problem(w, qp_policy=0, scatter=0)
+    P.set_deformation(u)
+    y_ref = P.tangent_vmult(x)
+    torch.cuda.synchronize()
+    del P
+    torch.cuda.empty_cache()
+    Q = device_problem(w, qp_policy=1, scatter=3, vcycle_dtype=F32)
+    Q.set_deformation(u)
+    y = Q.tangent_vmult(x)
+    torch.cuda.synchronize()
+    assert float((y - y_ref).norm() / y_ref.norm()) <= 1e-12
+    yh = host(y)
+    np.testing.assert_allclose(yh[rows], ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+    y32 = Q.tangent_vmult(x.float())
+    assert float((y32.double() - y_ref).norm() / y_ref.norm()) <= 1e-5
