@@ -259,12 +259,20 @@ def newton_bench(w, n_cells=64, n_levels=5, stretch=0.1, n_steps=4, shear_tracti
             ("mixed_cache_T2", dict(vcycle_dtype=F32, qp_policy=2)),
             ("mixed_cache_F", dict(vcycle_dtype=F32, qp_policy=1)),
             # solver settings of the paper (Sec. 7) and their alternatives, all mixed precision
+            # V-cycles replayed from HIP graphs (on a stream of the problem's own)
+            ("mixed_graphs", dict(vcycle_dtype=F32, graphs=True)),
             ("mixed_V11", dict(vcycle_dtype=F32, n_smooth=1)),
             ("mixed_chebyshev_coarse", dict(vcycle_dtype=F32, coarse_solver=1)),
             ("mixed_eig_reuse", dict(vcycle_dtype=F32, eig_refresh=0)))
     for name, kw in runs:
+        kw = dict(kw)
+        graphs = kw.pop("graphs", False)
+        if graphs:
+            kw["stream"] = torch.cuda.Stream()
         P = Problem(3, n_cells, 2, n_levels=n_levels, mu=tuple(w["mu"]), lam=tuple(w["lam"]),
                     inclusions=w["inclusions"], dirichlet_mask=W.clamp_bottom_top(3), **kw)
+        if graphs:
+            P.enable_graphs(True)
         u = torch.zeros(P.n_dofs(), dtype=torch.float64, device="cuda")
         fv = np.zeros((6, 3))
         fv[5][2] = stretch

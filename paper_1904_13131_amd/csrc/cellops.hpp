@@ -784,42 +784,42 @@ __device__ __forceinline__ void tangent_block(const CellArgs<T>& a, const T* __r
       if constexpr (POL == POL_C4) {
         tangent_qp_c4<DIM, T, O32>(Hx, qb, wstride, lane_c, lane_cb, wt);
       } else {
-      T Fi[DIM][DIM], S[DIM][DIM], c1;
-      if constexpr (POL == POL_R || POL == POL_CF) {
-        T H[DIM][DIM];
-        if constexpr (POL == POL_R) {
+        T Fi[DIM][DIM], S[DIM][DIM], c1;
+        if constexpr (POL == POL_R || POL == POL_CF) {
+          T H[DIM][DIM];
+          if constexpr (POL == POL_R) {
 #pragma unroll
-          for (int i = 0; i < DIM; ++i)
+            for (int i = 0; i < DIM; ++i)
 #pragma unroll
-            for (int I = 0; I < DIM; ++I) H[i][I] = gu[i][I][q] * a.invh;
-        } else {
+              for (int I = 0; I < DIM; ++I) H[i][I] = gu[i][I][q] * a.invh;
+          } else {
 #pragma unroll
-          for (int i = 0; i < DIM; ++i)
+            for (int i = 0; i < DIM; ++i)
 #pragma unroll
-            for (int I = 0; I < DIM; ++I)
-              H[i][I] = lane_load<O32>(qb + (i * DIM + I) * wstride, lane_c, lane_cb) - (i == I ? T(1) : T(0));
-        }
-        T F[DIM][DIM], jm1;
-        kinematics<DIM, T>(H, F, Fi, jm1);
-        c1 = mu - T(2) * lam * log1p_t<T>(jm1);
-        pk2<DIM, T>(Fi, mu, c1, S);
-      } else {
-        int w = 0;
-#pragma unroll
-        for (int I = 0; I < DIM; ++I)
-#pragma unroll
-          for (int j = 0; j < DIM; ++j) Fi[I][j] = lane_load<O32>(qb + (w++) * wstride, lane_c, lane_cb);
-#pragma unroll
-        for (int I = 0; I < DIM; ++I)
-#pragma unroll
-          for (int J = I; J < DIM; ++J) {
-            const T v = lane_load<O32>(qb + (w++) * wstride, lane_c, lane_cb);
-            S[I][J] = v;
-            S[J][I] = v;
+              for (int I = 0; I < DIM; ++I)
+                H[i][I] = lane_load<O32>(qb + (i * DIM + I) * wstride, lane_c, lane_cb) - (i == I ? T(1) : T(0));
           }
-        c1 = lane_load<O32>(qb + w * wstride, lane_c, lane_cb);
-      }
-      tangent_qp<DIM, T>(Hx, Fi, S, c1, lam, wt);
+          T F[DIM][DIM], jm1;
+          kinematics<DIM, T>(H, F, Fi, jm1);
+          c1 = mu - T(2) * lam * log1p_t<T>(jm1);
+          pk2<DIM, T>(Fi, mu, c1, S);
+        } else {
+          int w = 0;
+#pragma unroll
+          for (int I = 0; I < DIM; ++I)
+#pragma unroll
+            for (int j = 0; j < DIM; ++j) Fi[I][j] = lane_load<O32>(qb + (w++) * wstride, lane_c, lane_cb);
+#pragma unroll
+          for (int I = 0; I < DIM; ++I)
+#pragma unroll
+            for (int J = I; J < DIM; ++J) {
+              const T v = lane_load<O32>(qb + (w++) * wstride, lane_c, lane_cb);
+              S[I][J] = v;
+              S[J][I] = v;
+            }
+          c1 = lane_load<O32>(qb + w * wstride, lane_c, lane_cb);
+        }
+        tangent_qp<DIM, T>(Hx, Fi, S, c1, lam, wt);
       }
 #pragma unroll
       for (int i = 0; i < DIM; ++i)
@@ -1351,45 +1351,45 @@ k_tangent_tile(CellArgs<T> a) {
       if constexpr (POL == POL_C4) {
         tangent_qp_c4<DIM, T, false>(Hx, a.cache, (long long)TG::NV * a.ncells, (long long)qp * a.ncells + e, 0u, wt);
       } else {
-      T Fi[DIM][DIM], S[DIM][DIM], c1;
-      if constexpr (POL == POL_R || POL == POL_CF) {
-        T H[DIM][DIM];
-        if constexpr (POL == POL_R) {
+        T Fi[DIM][DIM], S[DIM][DIM], c1;
+        if constexpr (POL == POL_R || POL == POL_CF) {
+          T H[DIM][DIM];
+          if constexpr (POL == POL_R) {
 #pragma unroll
-          for (int i = 0; i < DIM; ++i)
+            for (int i = 0; i < DIM; ++i)
 #pragma unroll
-            for (int I = 0; I < DIM; ++I) H[i][I] = gu[i][I][q] * a.invh;
+              for (int I = 0; I < DIM; ++I) H[i][I] = gu[i][I][q] * a.invh;
+          } else {
+            const T* cq = a.cache + (long long)qp * a.ncells + e;
+            const long long stride = (long long)TG::NV * a.ncells;
+#pragma unroll
+            for (int i = 0; i < DIM; ++i)
+#pragma unroll
+              for (int I = 0; I < DIM; ++I) H[i][I] = cq[(i * DIM + I) * stride] - (i == I ? T(1) : T(0));
+          }
+          T F[DIM][DIM], jm1;
+          kinematics<DIM, T>(H, F, Fi, jm1);
+          c1 = mu - T(2) * lam * log1p_t<T>(jm1);
+          pk2<DIM, T>(Fi, mu, c1, S);
         } else {
           const T* cq = a.cache + (long long)qp * a.ncells + e;
           const long long stride = (long long)TG::NV * a.ncells;
+          int w = 0;
 #pragma unroll
-          for (int i = 0; i < DIM; ++i)
+          for (int I = 0; I < DIM; ++I)
 #pragma unroll
-            for (int I = 0; I < DIM; ++I) H[i][I] = cq[(i * DIM + I) * stride] - (i == I ? T(1) : T(0));
+            for (int j = 0; j < DIM; ++j) Fi[I][j] = cq[(w++) * stride];
+#pragma unroll
+          for (int I = 0; I < DIM; ++I)
+#pragma unroll
+            for (int J = I; J < DIM; ++J) {
+              const T s = cq[(w++) * stride];
+              S[I][J] = s;
+              S[J][I] = s;
+            }
+          c1 = cq[w * stride];
         }
-        T F[DIM][DIM], jm1;
-        kinematics<DIM, T>(H, F, Fi, jm1);
-        c1 = mu - T(2) * lam * log1p_t<T>(jm1);
-        pk2<DIM, T>(Fi, mu, c1, S);
-      } else {
-        const T* cq = a.cache + (long long)qp * a.ncells + e;
-        const long long stride = (long long)TG::NV * a.ncells;
-        int w = 0;
-#pragma unroll
-        for (int I = 0; I < DIM; ++I)
-#pragma unroll
-          for (int j = 0; j < DIM; ++j) Fi[I][j] = cq[(w++) * stride];
-#pragma unroll
-        for (int I = 0; I < DIM; ++I)
-#pragma unroll
-          for (int J = I; J < DIM; ++J) {
-            const T s = cq[(w++) * stride];
-            S[I][J] = s;
-            S[J][I] = s;
-          }
-        c1 = cq[w * stride];
-      }
-      tangent_qp<DIM, T>(Hx, Fi, S, c1, lam, wt);
+        tangent_qp<DIM, T>(Hx, Fi, S, c1, lam, wt);
       }
 #pragma unroll
       for (int i = 0; i < DIM; ++i)
