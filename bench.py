@@ -36,11 +36,11 @@ POLICIES = {0: "recompute", 1: "cache_F", 2: "cache_T2", 3: "cache_T4"}
 # rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by a 256 MiB device copy (reads
 # x2.0, writes x1.0; profiles/tangent_vmult_q2_32cube_hbm_counters.md); valid
 # only for the kernel source they were taken on.
-TRAFFIC_SOURCE_SHA = "73a8440c8f063bcc"
-TRAFFIC = {"recompute/f64/element": 65952731, "cache_F/f64/element": 123286366,
-           "cache_T2/f64/element": 173970456, "cache_T4/f64/element": 354076461,
-           "recompute/f32/element": 34136544, "cache_F/f32/element": 62522345,
-           "cache_T2/f32/element": 87753531, "cache_T4/f32/element": 173974422}
+TRAFFIC_SOURCE_SHA = "c39cf63a12346529"
+TRAFFIC = {"recompute/f64/element": 65948480, "cache_F/f64/element": 123277391,
+           "cache_T2/f64/element": 173809950, "cache_T4/f64/element": 356067449,
+           "recompute/f32/element": 34103746, "cache_F/f32/element": 62518273,
+           "cache_T2/f32/element": 87627989, "cache_T4/f32/element": 176139134}
 
 QP_FLOPS_3D = {0: 313, 1: 307, 2: 188, 3: 246}
 QP_FLOPS_2D = {0: 118, 1: 116, 2: 78, 3: 71}
