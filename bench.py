@@ -240,6 +240,30 @@ def matrix_based_bench(steps=20, warmup=3, library_spmv=True):
     return out
 
 
+def cpu_newton_baseline(w, n_cells=8, n_levels=3, stretch=0.025):
+    """The oracle's Newton solve with its GMG-CG (same solver settings and
+    material) on a small mesh of the config-3 recipe, one load step, timed on
+    the host cores: the oracle beside the device Newton step."""
+    from oracle import fe, gmg, newton
+    import workloads as W
+    H = gmg.Hierarchy(3, n_cells >> (n_levels - 1), 2, n_levels, fe.Material(w["mu"], w["lam"], w["inclusions"]),
+                      W.clamp_bottom_top(3))
+    fv = np.zeros((6, 3))
+    fv[5][2] = stretch
+    r0 = resource.getrusage(resource.RUSAGE_SELF)
+    t0 = time.perf_counter()
+    u, recs = newton.solve(H, fv, n_steps=1)
+    wall = time.perf_counter() - t0
+    r1 = resource.getrusage(resource.RUSAGE_SELF)
+    cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
+    n = H.meshes[-1].n_dofs
+    return {"value": wall / max(len(recs), 1) * 1e3, "unit": "ms per Newton step", "cores": round(cpu / wall, 1),
+            "kind": "oracle", "newton_steps": len(recs), "cg_iters": [r["cg_iters"] for r in recs],
+            "sample": f"oracle Newton + GMG-CG (V(2,2) Chebyshev(4), direct coarse solve, CG to 1e-8) on 3-D Q2 "
+                      f"{n_cells}^3 ({n:,} DoFs, levels {n_cells >> (n_levels - 1)}^3..{n_cells}^3), one load step of "
+                      f"{stretch:.1%} stretch, {wall:.1f} s wall"}
+
+
 def newton_bench(w, n_cells=64, n_levels=5, stretch=0.1, n_steps=4, shear_traction=0.1):
     """Config 3: Newton load stepping with GMG-CG (1e-8) on the config-2 material,
     64^3 Q2 (6.44M DoFs), levels 4^3..64^3, clamped bottom/top, 10 % stretch in
@@ -651,6 +675,8 @@ def main(argv=None):
         out["matrix_based"] = matrix_based_bench()
     if not a.no_newton:
         out["newton_step"] = newton_bench(w)
+        if not a.no_cpu:
+            out["newton_step"]["cpu_oracle"] = cpu_newton_baseline(w)
     if not a.no_batch:
         out["batched"] = batch_bench(solve=not a.no_batch_solve)
     if a.config5 or a.config5_vmult_only:
