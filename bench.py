@@ -42,9 +42,9 @@ TRAFFIC = {"recompute/f64/element": 65948480, "cache_F/f64/element": 123277391,
            "recompute/f32/element": 34103746, "cache_F/f32/element": 62518273,
            "cache_T2/f32/element": 87627989, "cache_T4/f32/element": 176139134}
 
-QP_FLOPS_3D = {0: 313, 1: 307, 2: 188, 3: 246}
-QP_FLOPS_2D = {0: 118, 1: 116, 2: 78, 3: 71}
-CACHE_WORDS = {3: {0: 0, 1: 9, 2: 16, 3: 36}, 2: {0: 0, 1: 4, 2: 8, 3: 13}}
+QP_FLOPS_3D = {0: 261, 1: 255, 2: 170, 3: 246}
+QP_FLOPS_2D = {0: 100, 1: 98, 2: 55, 3: 71}
+CACHE_WORDS = {3: {0: 0, 1: 9, 2: 10, 3: 36}, 2: {0: 0, 1: 4, 2: 5, 3: 13}}
 
 
 def algorithmic_cost(dim, degree, n_cells, n_dofs, policy, word):

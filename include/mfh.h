@@ -70,15 +70,17 @@ enum { MFH_F64 = 0, MFH_F32 = 1 };
  *             quadrature point from the displacement (the recompute end of
  *             the caching trade-off; Algorithm 1 without its scalar cache);
  *  CACHE_F    reads the cached deformation gradient F and recomputes the rest;
- *  CACHE_T2   reads cached F^-1, the second Piola-Kirchhoff stress S and
- *             c1 = mu - 2 lambda ln J: the referential counterpart of
- *             Algorithm 2's cached tau/J, c1, c2;
+ *  CACHE_T2   reads cached F^-1 and c1 = mu - 2 lambda ln J: the
+ *             referential counterpart of Algorithm 2's cached tau/J, c1, c2
+ *             (for this law the geometric term Grad x S equals
+ *             mu Grad x - c1 Grad x F^-1 F^-T, so the stress need not be
+ *             stored);
  *  CACHE_T4   reads cached F^-1, S and the material part of the spatial
  *             tangent J c (21 symmetric words in 3-D, 6 in 2-D): the
  *             referential counterpart of Algorithm 3 ("tensor4"); the
  *             quadrature-point stage evaluates no constitutive law, so it
  *             serves any law (the only policy for MFH_LAW_MOONEY_RIVLIN).
- * Cache words per quadrature point: 0, d^2, d^2 + d(d+1)/2 + 1,
+ * Cache words per quadrature point: 0, d^2, d^2 + 1,
  * d^2 + d(d+1)/2 + (d(d+1)/2)(d(d+1)/2 + 1)/2 (36 in 3-D), in the V-cycle
  * precision and in FP64 on every level.                                     */
 enum { MFH_QP_RECOMPUTE = 0, MFH_QP_CACHE_F = 1, MFH_QP_CACHE_T2 = 2, MFH_QP_CACHE_T4 = 3 };

@@ -48,7 +48,7 @@ struct Voigt {
 template <int DIM, int POL>
 struct CacheWords {
   static constexpr int value = POL == POL_CF ? DIM * DIM
-                              : POL == POL_C2 ? DIM * DIM + DIM * (DIM + 1) / 2 + 1
+                              : POL == POL_C2 ? DIM * DIM + 1
                               : POL == POL_C4 ? DIM * DIM + DIM * (DIM + 1) / 2 + Voigt<DIM>::NSYM
                               : 0;
 };
@@ -421,6 +421,7 @@ __device__ __forceinline__ void scatter_merged(T* __restrict__ dst, const CellAr
 //   sigma = 2 c1 sym(g) + 2 lambda tr(g) I        (J c : sym g, Sec. 2.3)
 //   P_x = sigma F^-T + Grad x S                    (tangent, eq. tangent
 //                                                   pulled back: g tau F^-T = Grad x S)
+//       = mu Grad x + (c1 g^T + 2 lambda tr(g) I) F^-T   (evaluated form, no S)
 // and the residual stress P = mu F - c1 F^-T (= tau F^-T with tau = mu b - c1 I).
 
 template <typename T> __device__ __forceinline__ T log1p_t(T x);
@@ -472,26 +473,15 @@ __device__ __forceinline__ T kinematics(const T (&H)[DIM][DIM], T (&F)[DIM][DIM]
   return J;
 }
 
-// S = mu I - c1 F^-1 F^-T, symmetric.
+// Tangent action at one quadrature point for the Neo-Hookean law:
+// Hx (Grad x) -> P_x * wt, in place.  With g = Grad x F^-1 and
+// S = mu I - c1 C^-1 the geometric part is Grad x S = mu Grad x - c1 g F^-T,
+// so that P_x = sigma F^-T + Grad x S collapses to
+//   P_x = mu Grad x + (c1 g^T + 2 lambda tr(g) I) F^-T
+// (2 c1 sym g - c1 g = c1 g^T): the stress is never formed, and the cached
+// policies need only F^-1 and c1 besides the material's (mu, lambda).
 template <int DIM, typename T>
-__device__ __forceinline__ void pk2(const T (&Fi)[DIM][DIM], T mu, T c1, T (&S)[DIM][DIM]) {
-#pragma unroll
-  for (int I = 0; I < DIM; ++I)
-#pragma unroll
-    for (int J = I; J < DIM; ++J) {
-      T ci = 0;
-#pragma unroll
-      for (int k = 0; k < DIM; ++k) ci += Fi[I][k] * Fi[J][k];
-      const T s = (I == J ? mu : T(0)) - c1 * ci;
-      S[I][J] = s;
-      S[J][I] = s;
-    }
-}
-
-// Tangent action at one quadrature point: Hx (physical Grad x) -> P_x * wt, in place.
-template <int DIM, typename T>
-__device__ __forceinline__ void tangent_qp(T (&Hx)[DIM][DIM], const T (&Fi)[DIM][DIM],
-                                           const T (&S)[DIM][DIM], T c1, T lam, T wt) {
+__device__ __forceinline__ void tangent_qp(T (&Hx)[DIM][DIM], const T (&Fi)[DIM][DIM], T c1, T mu, T lam, T wt) {
   T g[DIM][DIM];
 #pragma unroll
   for (int i = 0; i < DIM; ++i)
@@ -505,31 +495,16 @@ __device__ __forceinline__ void tangent_qp(T (&Hx)[DIM][DIM], const T (&Fi)[DIM]
   T tr = 0;
 #pragma unroll
   for (int i = 0; i < DIM; ++i) tr += g[i][i];
-  T sig[DIM][DIM];
-#pragma unroll
-  for (int i = 0; i < DIM; ++i)
-#pragma unroll
-    for (int j = i; j < DIM; ++j) {
-      const T s = c1 * (g[i][j] + g[j][i]) + (i == j ? T(2) * lam * tr : T(0));
-      sig[i][j] = s;
-      sig[j][i] = s;
-    }
-  T P[DIM][DIM];
+  const T l2t = T(2) * lam * tr;
 #pragma unroll
   for (int i = 0; i < DIM; ++i)
 #pragma unroll
     for (int I = 0; I < DIM; ++I) {
       T s = 0;
 #pragma unroll
-      for (int j = 0; j < DIM; ++j) s += sig[i][j] * Fi[I][j];
-#pragma unroll
-      for (int J = 0; J < DIM; ++J) s += Hx[i][J] * S[J][I];
-      P[i][I] = s;
+      for (int j = 0; j < DIM; ++j) s += g[j][i] * Fi[I][j];
+      Hx[i][I] = (mu * Hx[i][I] + c1 * s + l2t * Fi[I][i]) * wt;
     }
-#pragma unroll
-  for (int i = 0; i < DIM; ++i)
-#pragma unroll
-    for (int I = 0; I < DIM; ++I) Hx[i][I] = P[i][I] * wt;
 }
 
 // ---------------------------------------------------------------------------
@@ -784,7 +759,7 @@ __device__ __forceinline__ void tangent_block(const CellArgs<T>& a, const T* __r
       if constexpr (POL == POL_C4) {
         tangent_qp_c4<DIM, T, O32>(Hx, qb, wstride, lane_c, lane_cb, wt);
       } else {
-        T Fi[DIM][DIM], S[DIM][DIM], c1;
+        T Fi[DIM][DIM], c1;
         if constexpr (POL == POL_R || POL == POL_CF) {
           T H[DIM][DIM];
           if constexpr (POL == POL_R) {
@@ -802,24 +777,14 @@ __device__ __forceinline__ void tangent_block(const CellArgs<T>& a, const T* __r
           T F[DIM][DIM], jm1;
           kinematics<DIM, T>(H, F, Fi, jm1);
           c1 = mu - T(2) * lam * log1p_t<T>(jm1);
-          pk2<DIM, T>(Fi, mu, c1, S);
         } else {
-          int w = 0;
 #pragma unroll
           for (int I = 0; I < DIM; ++I)
 #pragma unroll
-            for (int j = 0; j < DIM; ++j) Fi[I][j] = lane_load<O32>(qb + (w++) * wstride, lane_c, lane_cb);
-#pragma unroll
-          for (int I = 0; I < DIM; ++I)
-#pragma unroll
-            for (int J = I; J < DIM; ++J) {
-              const T v = lane_load<O32>(qb + (w++) * wstride, lane_c, lane_cb);
-              S[I][J] = v;
-              S[J][I] = v;
-            }
-          c1 = lane_load<O32>(qb + w * wstride, lane_c, lane_cb);
+            for (int j = 0; j < DIM; ++j) Fi[I][j] = lane_load<O32>(qb + (I * DIM + j) * wstride, lane_c, lane_cb);
+          c1 = lane_load<O32>(qb + DIM * DIM * wstride, lane_c, lane_cb);
         }
-        tangent_qp<DIM, T>(Hx, Fi, S, c1, lam, wt);
+        tangent_qp<DIM, T>(Hx, Fi, c1, mu, lam, wt);
       }
 #pragma unroll
       for (int i = 0; i < DIM; ++i)
@@ -1351,7 +1316,7 @@ k_tangent_tile(CellArgs<T> a) {
       if constexpr (POL == POL_C4) {
         tangent_qp_c4<DIM, T, false>(Hx, a.cache, (long long)TG::NV * a.ncells, (long long)qp * a.ncells + e, 0u, wt);
       } else {
-        T Fi[DIM][DIM], S[DIM][DIM], c1;
+        T Fi[DIM][DIM], c1;
         if constexpr (POL == POL_R || POL == POL_CF) {
           T H[DIM][DIM];
           if constexpr (POL == POL_R) {
@@ -1370,26 +1335,16 @@ k_tangent_tile(CellArgs<T> a) {
           T F[DIM][DIM], jm1;
           kinematics<DIM, T>(H, F, Fi, jm1);
           c1 = mu - T(2) * lam * log1p_t<T>(jm1);
-          pk2<DIM, T>(Fi, mu, c1, S);
         } else {
           const T* cq = a.cache + (long long)qp * a.ncells + e;
           const long long stride = (long long)TG::NV * a.ncells;
-          int w = 0;
 #pragma unroll
           for (int I = 0; I < DIM; ++I)
 #pragma unroll
-            for (int j = 0; j < DIM; ++j) Fi[I][j] = cq[(w++) * stride];
-#pragma unroll
-          for (int I = 0; I < DIM; ++I)
-#pragma unroll
-            for (int J = I; J < DIM; ++J) {
-              const T s = cq[(w++) * stride];
-              S[I][J] = s;
-              S[J][I] = s;
-            }
-          c1 = cq[w * stride];
+            for (int j = 0; j < DIM; ++j) Fi[I][j] = cq[(I * DIM + j) * stride];
+          c1 = cq[DIM * DIM * stride];
         }
-        tangent_qp<DIM, T>(Hx, Fi, S, c1, lam, wt);
+        tangent_qp<DIM, T>(Hx, Fi, c1, mu, lam, wt);
       }
 #pragma unroll
       for (int i = 0; i < DIM; ++i)
@@ -1497,8 +1452,8 @@ __global__ void __launch_bounds__(kBlock) k_residual(CellArgs<double> arg) {
 }
 
 // Quadrature data of a level: min J per block, and the policy cache
-// (CF: F;  C2: F^-1, S (upper triangle, row major), c1;  C4: F^-1, S, J c of
-// the general law in packed Voigt form) in precision T.
+// (CF: F;  C2: F^-1, c1;  C4: F^-1, S (upper triangle, row major), J c of the
+// general law in packed Voigt form) in precision T.
 // The displacement is read in FP64 and everything is evaluated in FP64.
 template <int DIM, int P, typename T, int POL>
 __global__ void __launch_bounds__(kBlock) k_qpdata(CellArgs<double> arg, T* __restrict__ cache) {
@@ -1564,18 +1519,11 @@ __global__ void __launch_bounds__(kBlock) k_qpdata(CellArgs<double> arg, T* __re
           for (int k = 0; k < Voigt<DIM>::NSYM; ++k) cq[(w++) * stride] = (T)Cv[k];
         } else {
           const D c1 = mu - 2.0 * lam * log1p(jm1);
-          D S[DIM][DIM];
-          pk2<DIM, D>(Fi, mu, c1, S);
-          int w = 0;
 #pragma unroll
           for (int I = 0; I < DIM; ++I)
 #pragma unroll
-            for (int j = 0; j < DIM; ++j) cq[(w++) * stride] = (T)Fi[I][j];
-#pragma unroll
-          for (int I = 0; I < DIM; ++I)
-#pragma unroll
-            for (int J = I; J < DIM; ++J) cq[(w++) * stride] = (T)S[I][J];
-          cq[w * stride] = (T)c1;
+            for (int j = 0; j < DIM; ++j) cq[(I * DIM + j) * stride] = (T)Fi[I][j];
+          cq[DIM * DIM * stride] = (T)c1;
         }
       }
     }

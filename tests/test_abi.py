@@ -70,7 +70,7 @@ def test_invalid_descriptors_rejected(bad):
 
 def test_tensor4_and_second_law_accepted():
     """CACHE_T4 with either law; its cache is 36 words per quadrature point in
-    3-D (F^-1, S, J c), so the workspace grows over CACHE_T2's 16."""
+    3-D (F^-1, S, J c), so the workspace grows over CACHE_T2's 10 (F^-1, c1)."""
     from paper_1904_13131_amd import workspace_size
     sizes = {}
     for pol, law in ((2, 0), (3, 0), (3, 1)):
@@ -80,7 +80,7 @@ def test_tensor4_and_second_law_accepted():
     n_cells, nq = 8 ** 3, 27
     d2, keep2 = _desc(n_levels=1, qp_policy=2)
     d3, keep3 = _desc(n_levels=1, qp_policy=3)
-    assert workspace_size(d3) - workspace_size(d2) >= (36 - 16) * nq * n_cells * 12   # FP64 + FP32 copies
+    assert workspace_size(d3) - workspace_size(d2) == (36 - 10) * nq * n_cells * 12   # FP64 + FP32 copies
 
 
 def test_create_rejects_small_or_null_workspace():
