@@ -36,11 +36,11 @@ POLICIES = {0: "recompute", 1: "cache_F", 2: "cache_T2", 3: "cache_T4"}
 # rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by a 256 MiB device copy (reads
 # x2.0, writes x1.0; profiles/tangent_vmult_q2_32cube_hbm_counters.md); valid
 # only for the kernel source they were taken on.
-TRAFFIC_SOURCE_SHA = "c39cf63a12346529"
-TRAFFIC = {"recompute/f64/element": 65948480, "cache_F/f64/element": 123277391,
-           "cache_T2/f64/element": 173809950, "cache_T4/f64/element": 356067449,
-           "recompute/f32/element": 34103746, "cache_F/f32/element": 62518273,
-           "cache_T2/f32/element": 87627989, "cache_T4/f32/element": 176139134}
+TRAFFIC_SOURCE_SHA = "81435bb4960d215d"
+TRAFFIC = {"recompute/f64/element": 65937438, "cache_F/f64/element": 123321293,
+           "cache_T2/f64/element": 130381653, "cache_T4/f64/atomic": 330285710,
+           "recompute/f32/element": 34124203, "cache_F/f32/element": 62454710,
+           "cache_T2/f32/element": 66041649, "cache_T4/f32/element": 175975358}
 
 QP_FLOPS_3D = {0: 261, 1: 255, 2: 170, 3: 246}
 QP_FLOPS_2D = {0: 100, 1: 98, 2: 55, 3: 71}
