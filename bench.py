@@ -275,19 +275,21 @@ def newton_bench(w, n_cells=64, n_levels=5, stretch=0.1, n_steps=4, shear_tracti
     out = {"workload": f"3-D Q2 {n_cells}^3 ({(2 * n_cells + 1) ** 3 * 3:,} DoFs), levels "
                        f"{n_cells >> (n_levels - 1)}^3..{n_cells}^3, config-2 material, clamped bottom/top, "
                        f"{stretch:.0%} stretch in {n_steps} load steps, FP64 CG to 1e-8 with a V(2,2) "
-                       f"Chebyshev(4) GMG preconditioner, FP64 dense coarse solve (variants: V(1,1), the "
+                       f"Chebyshev(4) GMG preconditioner, cached F^-1 and c1 on every level, FP64 dense coarse "
+                       f"solve (variants: recompute / cached-F level operators, V(1,1), the "
                        f"Chebyshev coarse solver to 1e-3, eigenvalue estimates of the first linearisation "
                        f"reused)"}
-    runs = (("mixed", dict(vcycle_dtype=F32)), ("fp64", dict(vcycle_dtype=F64)),
-            # quadrature-point data cached on every level (Algorithm 2's trade-off)
-            ("mixed_cache_T2", dict(vcycle_dtype=F32, qp_policy=2)),
+    # level operators with cached F^-1 and c1 (Algorithm 2's trade-off); the
+    # other policies and the paper's solver alternatives (Sec. 7) as variants
+    runs = (("mixed", dict(vcycle_dtype=F32, qp_policy=2)), ("fp64", dict(vcycle_dtype=F64, qp_policy=2)),
+            ("mixed_recompute", dict(vcycle_dtype=F32, qp_policy=0)),
+            ("fp64_recompute", dict(vcycle_dtype=F64, qp_policy=0)),
             ("mixed_cache_F", dict(vcycle_dtype=F32, qp_policy=1)),
-            # solver settings of the paper (Sec. 7) and their alternatives, all mixed precision
             # V-cycles replayed from HIP graphs (on a stream of the problem's own)
-            ("mixed_graphs", dict(vcycle_dtype=F32, graphs=True)),
-            ("mixed_V11", dict(vcycle_dtype=F32, n_smooth=1)),
-            ("mixed_chebyshev_coarse", dict(vcycle_dtype=F32, coarse_solver=1)),
-            ("mixed_eig_reuse", dict(vcycle_dtype=F32, eig_refresh=0)))
+            ("mixed_graphs", dict(vcycle_dtype=F32, qp_policy=2, graphs=True)),
+            ("mixed_V11", dict(vcycle_dtype=F32, qp_policy=2, n_smooth=1)),
+            ("mixed_chebyshev_coarse", dict(vcycle_dtype=F32, qp_policy=2, coarse_solver=1)),
+            ("mixed_eig_reuse", dict(vcycle_dtype=F32, qp_policy=2, eig_refresh=0)))
     for name, kw in runs:
         kw = dict(kw)
         graphs = kw.pop("graphs", False)
@@ -322,7 +324,7 @@ def newton_bench(w, n_cells=64, n_levels=5, stretch=0.1, n_steps=4, shear_tracti
     out["speedup_mixed_vs_fp64"] = out["fp64"]["median_step_ms"] / out["mixed"]["median_step_ms"]
     # the paper's load path (Sec. 7): bottom clamped, dead shear traction on the top face in 5 steps
     P = Problem(3, n_cells, 2, n_levels=n_levels, mu=tuple(w["mu"]), lam=tuple(w["lam"]),
-                inclusions=w["inclusions"], dirichlet_mask=W.face_bits(3, 2, 0), vcycle_dtype=F32)
+                inclusions=w["inclusions"], dirichlet_mask=W.face_bits(3, 2, 0), vcycle_dtype=F32, qp_policy=2)
     u = torch.zeros(P.n_dofs(), dtype=torch.float64, device="cuda")
     ft = np.zeros((6, 3))
     ft[5][0] = shear_traction

@@ -833,8 +833,8 @@ __device__ __forceinline__ void tangent_block(const CellArgs<T>& a, const T* __r
 // node of an (i, j) plane and all its components (the d * 2^d loads are in
 // flight together); blockIdx.y is the plane k.  j = t / L comes from a
 // multiply-high by magic = ceil(2^32 / L), exact for t < L^2 while L^3 < 2^32.
-template <int DIM, int P, typename T>
-__device__ __forceinline__ void elem_gather_node(const CellArgs<T>& a, const T* __restrict__ x, T* __restrict__ y,
+template <int DIM, int P, typename T, typename Out>
+__device__ __forceinline__ void elem_gather_node(const CellArgs<T>& a, const T* __restrict__ x, const Out& out,
                                                  int t, int k, unsigned magic) {
   constexpr int N1 = P + 1;
   constexpr int NV = Geo<DIM, N1>::NV;
@@ -888,14 +888,22 @@ __device__ __forceinline__ void elem_gather_node(const CellArgs<T>& a, const T* 
 #pragma unroll
     for (int s = 0; s < (DIM == 3 ? 8 : 4); ++s) acc += v[c][s];
     if (fc & a.fmask[c]) acc = a.mask_in ? x[gi] : T(0);
-    y[gi] = acc;
+    out(gi, acc);
   }
 }
 
 template <int DIM, int P, typename T>
 __global__ void __launch_bounds__(kBlock) k_elem_gather(CellArgs<T> arg, unsigned magic) {
   const CellArgs<T>& a = kernel_args(arg);
-  elem_gather_node<DIM, P, T>(a, a.x, a.y, blockIdx.x * kBlock + threadIdx.x, blockIdx.y, magic);
+  elem_gather_node<DIM, P, T>(a, a.x, StoreOut<T>{a.y}, blockIdx.x * kBlock + threadIdx.x, blockIdx.y, magic);
+}
+
+// Node sums fused with one Chebyshev step (the smoother's vmult on a level
+// with the ELEMENT scatter).
+template <int DIM, int P, typename T>
+__global__ void __launch_bounds__(kBlock) k_elem_gather_cheb(CellArgs<T> arg, unsigned magic, ChebOut<T> out) {
+  const CellArgs<T>& a = kernel_args(arg);
+  elem_gather_node<DIM, P, T>(a, a.x, out, blockIdx.x * kBlock + threadIdx.x, blockIdx.y, magic);
 }
 
 // Batched second pass: one workgroup per item (problem, plane k, block of the
@@ -914,7 +922,7 @@ __global__ void __launch_bounds__(kBlock) k_elem_gather_batch(const CellArgs<T>*
   const int p = it[0], k = it[1], blk = it[2];
   const unsigned magic = (unsigned)it[3];
   const CellArgs<T>& a = *(const CellArgs<T>*)((CArgs*)args + p);
-  elem_gather_node<DIM, P, T>(a, ((CPtrX*)xs)[p], ((CPtrY*)ys)[p], blk * kBlock + threadIdx.x, k, magic);
+  elem_gather_node<DIM, P, T>(a, ((CPtrX*)xs)[p], StoreOut<T>{((CPtrY*)ys)[p]}, blk * kBlock + threadIdx.x, k, magic);
 }
 
 // Tangent vmult: y += K x over the cells of this launch (y pre-filled).

@@ -68,6 +68,32 @@ struct GatherItem {
   unsigned magic;   // ceil(2^32 / L) of the problem's lattice
 };
 
+// Destinations of the node sums: the output vector, or one Chebyshev
+// smoothing step applied to the sum t = (K_c x)_i right away,
+//   d_i <- cd d_i + cr dinv_i (f_i - t_i),  x_i <- x_i + d_i,
+// so that the smoother does not write and re-read the product vector.  The
+// update of x_i is safe: x_i is read only by this thread (constrained rows)
+// and the cell kernel that read x has completed.
+template <typename T>
+struct StoreOut {
+  T* y;
+  __device__ void operator()(long long gi, T v) const { y[gi] = v; }
+};
+template <typename T>
+struct ChebOut {
+  const T* f;
+  const T* dinv;
+  T* d;
+  T* x;
+  T cd, cr;
+  __device__ void operator()(long long gi, T t) const {
+    const T r = f[gi] - t;
+    const T di = (cd != T(0) ? cd * d[gi] : T(0)) + cr * dinv[gi] * r;
+    d[gi] = di;
+    x[gi] = x[gi] + di;
+  }
+};
+
 // Lattice description for the vector kernels.
 struct Lattice {
   int L, dim;

@@ -31,6 +31,9 @@ struct OpFns {
                               double* const* ys, unsigned n_items, hipStream_t);
   void (*elem_gather_batch_f)(const CellArgs<float>* args, const GatherItem* items, const float* const* xs,
                               float* const* ys, unsigned n_items, hipStream_t);
+  // node sums fused with one Chebyshev step (ELEMENT levels of the smoother)
+  void (*elem_gather_cheb_d)(const CellArgs<double>&, const ChebOut<double>&, hipStream_t);
+  void (*elem_gather_cheb_f)(const CellArgs<float>&, const ChebOut<float>&, hipStream_t);
   void (*coarse_assemble)(const CellArgs<double>&, const int* fmap, long long nf, double* K,
                           unsigned grid, hipStream_t);
   // element tangents added into the CSR values of K_c (pattern of the lattice)

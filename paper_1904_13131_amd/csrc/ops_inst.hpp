@@ -85,6 +85,13 @@ struct OpInst {
     const dim3 grid((plane + kBlock - 1) / kBlock, DIM == 3 ? a.L : 1, 1);
     hipLaunchKernelGGL((k_elem_gather<DIM, P, T>), grid, dim3(kBlock), 0, s, a, magic);
   }
+  template <typename T>
+  static void elem_gather_cheb(const CellArgs<T>& a, const ChebOut<T>& out, hipStream_t s) {
+    const unsigned plane = (unsigned)a.L * (unsigned)a.L;
+    const unsigned magic = (unsigned)((((unsigned long long)1 << 32) + (unsigned)a.L - 1) / (unsigned)a.L);
+    const dim3 grid((plane + kBlock - 1) / kBlock, DIM == 3 ? a.L : 1, 1);
+    hipLaunchKernelGGL((k_elem_gather_cheb<DIM, P, T>), grid, dim3(kBlock), 0, s, a, magic, out);
+  }
   static void residual(const CellArgs<double>& a, unsigned grid, hipStream_t s) {
     hipLaunchKernelGGL((k_residual<DIM, P>), dim3(grid), dim3(kBlock), 0, s, a);
   }
@@ -142,6 +149,8 @@ struct OpInst {
         &elem_gather<float>,
         &elem_gather_batch<double>,
         &elem_gather_batch<float>,
+        &elem_gather_cheb<double>,
+        &elem_gather_cheb<float>,
         &coarse_assemble,
         &csr_assemble,
         Geo<DIM, P + 1>::CPB,

@@ -459,6 +459,9 @@ struct Sel<double> {
     o->tangent_tile_d[pol](a, g, s);
   }
   static void elem_gather(const OpFns* o, const CellArgs<double>& a, hipStream_t s) { o->elem_gather_d(a, s); }
+  static void elem_gather_cheb(const OpFns* o, const CellArgs<double>& a, const ChebOut<double>& c, hipStream_t s) {
+    o->elem_gather_cheb_d(a, c, s);
+  }
   static Band<double> band(const DevBand& b) { return b.get<double>(); }
 };
 template <>
@@ -472,6 +475,9 @@ struct Sel<float> {
     o->tangent_tile_f[pol](a, g, s);
   }
   static void elem_gather(const OpFns* o, const CellArgs<float>& a, hipStream_t s) { o->elem_gather_f(a, s); }
+  static void elem_gather_cheb(const OpFns* o, const CellArgs<float>& a, const ChebOut<float>& c, hipStream_t s) {
+    o->elem_gather_cheb_f(a, c, s);
+  }
   static Band<float> band(const DevBand& b) { return b.get<float>(); }
 };
 
@@ -526,6 +532,26 @@ void vmult(mfh_problem* P, int l, const T* x, T* y, int mask_in = 1) {
     }
   }
   timer_mark(P);
+}
+
+// One Chebyshev step with its operator application, on a level whose vmult
+// uses the ELEMENT scatter: the cell kernel writes the element buffer and the
+// node-sum kernel applies the step to x and d directly (same arithmetic as
+// vmult followed by cheb_step, without the product vector).  Returns false
+// (nothing enqueued) on levels with another scatter.
+template <typename T>
+bool vmult_cheb(mfh_problem* P, int l, const T* f, const T* dinv, T* d, T* x, T cd, T cr) {
+  const Level& v = P->lv[l];
+  if (scatter_mode(P, v, std::is_same<T, double>::value ? 0 : 1) != MFH_SCATTER_ELEMENT) return false;
+  CellArgs<T> a = cell_args<T>(P, v, Sel<T>::u(v), Sel<T>::cache(v), x, nullptr);
+  a.mask_in = 1;
+  a.elem = reinterpret_cast<T*>(P->elem);
+  const int cpb = P->ops->cpb;
+  timer_mark(P);
+  Sel<T>::run(P->ops, P->d.qp_policy, a, (unsigned)((v.ncells + cpb - 1) / cpb), P->stream);
+  Sel<T>::elem_gather_cheb(P->ops, a, ChebOut<T>{f, dinv, d, x, cd, cr}, P->stream);
+  timer_mark(P);
+  return true;
 }
 
 void residual(mfh_problem* P, const double* u, double* r) {
@@ -608,6 +634,7 @@ void cheb_apply(mfh_problem* P, int l, const T* f, T* x, bool xzero) {
     const bool first_zero = (j == 0 && xzero);
     const T* tt = nullptr;
     if (!first_zero) {
+      if (vmult_cheb<T>(P, l, f, dinv, dvec, x, (T)v.cd[j], (T)v.cr[j])) continue;
       vmult<T>(P, l, x, t);
       tt = t;
     }

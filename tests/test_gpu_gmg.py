@@ -354,3 +354,26 @@ def test_newton_shear_traction_matches_oracle():
     assert len(recs) == len(recs_o)
     assert rel_l2(host(u), u_o) <= 1e-8
     assert np.abs(host(u)).max() > 0.05        # a visible shear deformation
+
+
+@pytest.mark.parametrize("name", ["3d_q2", "2d_q4_vertex", "3d_q3_vertex"])
+def test_smoother_fused_with_element_node_sums(name):
+    """Every level on the ELEMENT scatter, so each Chebyshev step runs fused
+    into the node-sum kernel: smoother, V-cycle (FP64) and CG (FP32 V-cycle)
+    still match the oracle."""
+    log_case("fused_cheb", name=name)
+    c, mu, lam, incl, mask, H, u, b = _setup(name)
+    P = _device(name, F64, scatter=3)
+    top = c["n_levels"] - 1
+    assert all(P.scatter_mode(l, F64) == 3 for l in range(c["n_levels"]))
+    f = b.copy()
+    x0 = W.normal_vector(len(b), 78) * 0.1
+    x0[H.cons[-1]] = 0.0
+    lo, hi = H.interval[top]
+    want = gmg.chebyshev(lambda v: H.A[top] @ v, H.dinv[top], f, x0, lo, hi, H.cheb_degree)
+    assert rel_l2(host(P.chebyshev(top, dev(f), dev(x0))), want) <= 1e-7
+    assert rel_l2(host(P.gmg_vcycle(dev(b))), H.vcycle(b)) <= 1e-7
+    Q = _device(name, F32, scatter=3)
+    x, it, rel, _ = Q.cg_solve(dev(b), rtol=1e-8, max_it=200)
+    assert rel <= 1e-8
+    assert np.linalg.norm(b - H.A[-1] @ host(x)) <= 1.05e-8 * np.linalg.norm(b)
