@@ -416,17 +416,21 @@ constexpr int kGJ = 64;
 // pivots are those of a symmetric LDL^T elimination, so their signs give the
 // inertia: flag[1] counts negative pivots; flag[0] is set when a pivot is not
 // finite or |p| <= tol * scale[0] (numerically singular).
-__global__ void k_gj_pivot(double* __restrict__ A, long long n, long long k0, int nb, double* __restrict__ Pinv,
-                           int* flag, const double* scale, double tol) {
+__global__ void __launch_bounds__(256) k_gj_pivot(double* __restrict__ A, long long n, long long k0, int nb,
+                                                  double* __restrict__ Pinv, int* flag, const double* scale,
+                                                  double tol) {
   __shared__ double M[kGJ][kGJ + 1];
   __shared__ double colk[kGJ], rowk[kGJ];
+  // thread t owns column j = t % kGJ of rows t / kGJ + 4 r (256 threads)
+  constexpr int kRows = 256 / kGJ;
   const int t = threadIdx.x;
+  const int j = t % kGJ, i0 = t / kGJ;
   const double thr = tol * scale[0];
-  for (int e = t; e < nb * nb; e += blockDim.x) {
-    const int i = e / nb, j = e % nb;
-    M[i][j] = A[(k0 + i) * n + k0 + j];
-  }
+  if (j < nb)
+    for (int i = i0; i < nb; i += kRows) M[i][j] = A[(k0 + i) * n + k0 + j];
   __syncthreads();
+  bool bad = false;   // pivot checks in registers, written once at the end
+  int neg = 0;
   for (int k = 0; k < nb; ++k) {
     if (t < nb) {
       colk[t] = M[t][k];
@@ -434,27 +438,27 @@ __global__ void k_gj_pivot(double* __restrict__ A, long long n, long long k0, in
     }
     __syncthreads();
     const double p = rowk[k];
-    if (t == 0) {
-      if (!(fabs(p) > thr) || !isfinite(p)) flag[0] = 1;
-      if (p < 0.0) flag[1] += 1;
-    }
+    bad = bad || !(fabs(p) > thr) || !isfinite(p);
+    neg += p < 0.0 ? 1 : 0;
     const double pinv = 1.0 / p;
-    for (int e = t; e < nb * nb; e += blockDim.x) {
-      const int i = e / nb, j = e % nb;
-      if (i == k && j == k)
-        M[i][j] = pinv;
-      else if (i == k)
-        M[i][j] = rowk[j] * pinv;
-      else if (j == k)
-        M[i][j] = -colk[i] * pinv;
-      else
-        M[i][j] -= colk[i] * rowk[j] * pinv;
+    if (j < nb) {
+      const double rj = rowk[j] * pinv;
+      for (int i = i0; i < nb; i += kRows) {
+        if (i == k)
+          M[i][j] = j == k ? pinv : rj;
+        else if (j == k)
+          M[i][j] = -colk[i] * pinv;
+        else
+          M[i][j] -= colk[i] * rj;
+      }
     }
     __syncthreads();
   }
-  for (int e = t; e < nb * nb; e += blockDim.x) {
-    const int i = e / nb, j = e % nb;
-    Pinv[i * nb + j] = M[i][j];
+  if (j < nb)
+    for (int i = i0; i < nb; i += kRows) Pinv[i * nb + j] = M[i][j];
+  if (t == 0) {
+    if (bad) flag[0] = 1;
+    flag[1] += neg;
   }
 }
 
