@@ -1,6 +1,6 @@
 """Benchmark of the matrix-free finite-strain tangent on one MI355X.
 
-Workload (the configuration the headline metric is quoted on): 3-D unit cube,
+Headline workload: 3-D unit cube,
 32^3 Q2 cells (823,875 DoFs), (p+1)^3 Gauss points, compressible Neo-Hookean
 matrix (mu = 1, nu = 0.3) with 20 seeded spheres 100x stiffer, seeded smooth
 displacement of amplitude 0.1, x ~ N(0, 1).  A step is one tangent vmult
@@ -32,7 +32,7 @@ POLICIES = {0: "recompute", 1: "cache_F", 2: "cache_T2", 3: "cache_T4"}
 
 # Algorithmic flop counts: minimal sum factorisation of one d-component field,
 # 4 d^2 n^(d+1), plus the per-quadrature-point algebra.  Measured HBM bytes per
-# vmult of config 2 (cell kernel + node-sum kernel of the ELEMENT scatter) from
+# vmult of the 32^3 Q2 workload (cell kernel + node-sum kernel of the ELEMENT scatter) from
 # rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by a 256 MiB device copy (reads
 # x2.0, writes x1.0; profiles/tangent_vmult_q2_32cube_hbm_counters.md); valid
 # only for the kernel source they were taken on.
@@ -242,7 +242,7 @@ def matrix_based_bench(steps=20, warmup=3, library_spmv=True):
 
 def cpu_newton_baseline(w, n_cells=8, n_levels=3, stretch=0.025):
     """The oracle's Newton solve with its GMG-CG (same solver settings and
-    material) on a small mesh of the config-3 recipe, one load step, timed on
+    material) on a small mesh of the Newton benchmark's recipe, one load step, timed on
     the host cores: the oracle beside the device Newton step."""
     from oracle import fe, gmg, newton
     import workloads as W
@@ -265,7 +265,7 @@ def cpu_newton_baseline(w, n_cells=8, n_levels=3, stretch=0.025):
 
 
 def newton_bench(w, n_cells=64, n_levels=5, stretch=0.1, n_steps=4, shear_traction=0.1):
-    """Config 3: Newton load stepping with GMG-CG (1e-8) on the config-2 material,
+    """Newton load stepping with GMG-CG (1e-8) on the two-phase material,
     64^3 Q2 (6.44M DoFs), levels 4^3..64^3, clamped bottom/top, 10 % stretch in
     4 steps; mixed-precision (FP32 V-cycle) and all-FP64 forms."""
     import torch
@@ -273,7 +273,7 @@ def newton_bench(w, n_cells=64, n_levels=5, stretch=0.1, n_steps=4, shear_tracti
     import workloads as W
     from paper_1904_13131_amd import F32, F64, Problem
     out = {"workload": f"3-D Q2 {n_cells}^3 ({(2 * n_cells + 1) ** 3 * 3:,} DoFs), levels "
-                       f"{n_cells >> (n_levels - 1)}^3..{n_cells}^3, config-2 material, clamped bottom/top, "
+                       f"{n_cells >> (n_levels - 1)}^3..{n_cells}^3, two-phase material, clamped bottom/top, "
                        f"{stretch:.0%} stretch in {n_steps} load steps, FP64 CG to 1e-8 with a V(2,2) "
                        f"Chebyshev(4) GMG preconditioner, cached F^-1 and c1 on every level, FP64 dense coarse "
                        f"solve (variants: recompute / cached-F level operators, V(1,1), the "
@@ -346,7 +346,7 @@ def newton_bench(w, n_cells=64, n_levels=5, stretch=0.1, n_steps=4, shear_tracti
     return out
 
 
-def _config5_problem(n_cells, n_levels, level_field):
+def _q4_problem(n_cells, n_levels, level_field):
     import workloads as W
     from paper_1904_13131_amd import F32, Problem
     mu, lam = W.two_phase_material()
@@ -354,10 +354,10 @@ def _config5_problem(n_cells, n_levels, level_field):
                    dirichlet_mask=W.clamp_bottom_top(3), qp_policy=2, vcycle_dtype=F32, level_field=level_field)
 
 
-def _config5_newton(n_cells, n_levels, strain, n_steps, level_field, cg_max_it=500):
+def _q4_newton(n_cells, n_levels, strain, n_steps, level_field, cg_max_it=500):
     """Newton load stepping to `strain` (negative: compression) in n_steps increments."""
     import torch
-    P = _config5_problem(n_cells, n_levels, level_field)
+    P = _q4_problem(n_cells, n_levels, level_field)
     u = torch.zeros(P.n_dofs(), dtype=torch.float64, device="cuda")
     fv = np.zeros((6, 3))
     fv[5][2] = strain
@@ -370,7 +370,7 @@ def _config5_newton(n_cells, n_levels, strain, n_steps, level_field, cg_max_it=5
         for r in rk:
             r["load_fraction"] = (k - 1 + r["load_fraction"]) / n_steps
         recs += rk
-        print(f"[bench] config5 {name} load step {k}: {len(rk)} Newton steps, CG iterations "
+        print(f"[bench] q4_48cube {name} load step {k}: {len(rk)} Newton steps, CG iterations "
               f"{[r['cg_iters'] for r in rk]}, status {st}, {time.perf_counter() - t0:.1f} s",
               file=sys.stderr, flush=True)
         if st != 0:
@@ -391,9 +391,9 @@ def _config5_newton(n_cells, n_levels, strain, n_steps, level_field, cg_max_it=5
             "min_J_last": recs[-1]["min_J"] if recs else None}
 
 
-def config5_bench(n_cells=48, n_levels=5, n_steps=5, steps=10, newton=True):
-    """Config 5: 3-D Q4 48^3 (21.6 M DoFs), 5^3 Gauss points, 200 spheres (seed 7),
-    config-2 material law, bottom/top clamped, levels 3^3..48^3, FP32 V(2,2)
+def q4_48cube_bench(n_cells=48, n_levels=5, n_steps=5, steps=10, newton=True):
+    """3-D Q4 48^3 (21.6 M DoFs), 5^3 Gauss points, 200 spheres (seed 7),
+    two-phase Neo-Hookean material, bottom/top clamped, levels 3^3..48^3, FP32 V(2,2)
     Chebyshev(4) GMG under FP64 CG.  Level vmults (FP32 on three levels, FP64 on
     the finest) and the FP64 residual at a smooth start state; then Newton to
     20 % compression (paper-literal nodal level fields) and to 20 % tension with
@@ -403,10 +403,10 @@ def config5_bench(n_cells=48, n_levels=5, n_steps=5, steps=10, newton=True):
     import workloads as W
     from paper_1904_13131_amd import F32, F64
     from paper_1904_13131_amd.mfh import SCATTER_NAMES
-    P = _config5_problem(n_cells, n_levels, 0)
+    P = _q4_problem(n_cells, n_levels, 0)
     n = P.n_dofs()
     out = {"workload": f"3-D Q4 {n_cells}^3 ({n:,} DoFs), 125 Gauss points per cell, 200 spheres (seed 7), "
-                       f"config-2 material, clamped bottom/top, {n_steps} load steps, levels "
+                       f"two-phase material, clamped bottom/top, {n_steps} load steps, levels "
                        f"{n_cells >> (n_levels - 1)}^3..{n_cells}^3, FP32 V(2,2) Chebyshev(4) GMG under FP64 CG "
                        f"to 1e-8 (at most 500 iterations), FP64 dense coarse solve", "qp_policy": "cache_T2"}
     u0 = torch.as_tensor(W.sine_field(3, 4 * n_cells + 1, 4, 0.01, kmax=1, coords=P.node_coords_1d()),
@@ -432,7 +432,7 @@ def config5_bench(n_cells=48, n_levels=5, n_steps=5, steps=10, newton=True):
             ms = e0.elapsed_time(e1) / steps
             lv[f"level{level}_{dt}"] = {"n_dofs": nl, "ms": ms, "dofs_per_s": nl / (ms * 1e-3),
                                         "scatter": SCATTER_NAMES[P.scatter_mode(level, code)]}
-            print(f"[bench] config5 vmult level {level} {dt}: {ms:.3f} ms, {nl / (ms * 1e-3):.3e} DoF/s",
+            print(f"[bench] q4_48cube vmult level {level} {dt}: {ms:.3f} ms, {nl / (ms * 1e-3):.3e} DoF/s",
                   file=sys.stderr, flush=True)
     r = torch.empty_like(u0)
     for _ in range(2):
@@ -449,13 +449,13 @@ def config5_bench(n_cells=48, n_levels=5, n_steps=5, steps=10, newton=True):
     del P
     torch.cuda.empty_cache()
     if newton:
-        out["newton"] = [_config5_newton(n_cells, n_levels, -0.2, n_steps, 0),
-                         _config5_newton(n_cells, n_levels, +0.2, n_steps, 1)]
+        out["newton"] = [_q4_newton(n_cells, n_levels, -0.2, n_steps, 0),
+                         _q4_newton(n_cells, n_levels, +0.2, n_steps, 1)]
     return out
 
 
 def batch_bench(policy=2, steps=20, warmup=3, n=256, solve=True):
-    """Config 4: 256 independent 3-D problems (N in {8, 12, 16, 24}, p in {1, 2, 3},
+    """A batch of 256 independent 3-D problems (N in {8, 12, 16, 24}, p in {1, 2, 3},
     1-10 spheres, loaded linearisation point).  Aggregate batched vmult DoFs/s in
     FP64 and FP32 against one launch per problem, and one Newton correction per
     problem (K du = -R) by mixed-precision GMG-CG to 1e-8, all problems in
@@ -465,7 +465,7 @@ def batch_bench(policy=2, steps=20, warmup=3, n=256, solve=True):
     import workloads as W
     from paper_1904_13131_amd import F32, Batch, Problem
     mu, lam = W.two_phase_material()
-    descs = W.config4(n=n)
+    descs = W.batch_of_cubes(n=n)
     probs, us, x64 = [], [], []
     t0 = time.perf_counter()
     for d in descs:
@@ -572,11 +572,11 @@ def main(argv=None):
     ap.add_argument("--dtypes", default="f64,f32")
     ap.add_argument("--no-cold", action="store_true")
     ap.add_argument("--scatter", type=int, default=-1, help="-1 auto (tuned table), 0 atomic, 1 colour, 2 tile, 3 element")
-    ap.add_argument("--no-newton", action="store_true", help="skip the config-3 Newton-step measurement")
-    ap.add_argument("--no-batch", action="store_true", help="skip the config-4 batched measurement")
-    ap.add_argument("--no-batch-solve", action="store_true", help="config 4: time the batched vmult only")
-    ap.add_argument("--config5", action="store_true", help="also run config 5 (Q4 48^3 Newton, minutes)")
-    ap.add_argument("--config5-vmult-only", action="store_true", help="config 5: level vmults only, no Newton")
+    ap.add_argument("--no-newton", action="store_true", help="skip the 64^3 Q2 Newton-step measurement")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 256-problem batched measurement")
+    ap.add_argument("--no-batch-solve", action="store_true", help="256-problem batch: time the batched vmult only")
+    ap.add_argument("--q4-48cube", action="store_true", help="also run the Q4 48^3 level vmults and Newton (minutes)")
+    ap.add_argument("--q4-48cube-vmult-only", action="store_true", help="Q4 48^3: level vmults only, no Newton")
     ap.add_argument("--no-matrix-based", action="store_true", help="skip the CSR matrix-based comparison")
     ap.add_argument("--matrix-based-only", action="store_true", help="only the CSR matrix-based comparison")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -597,7 +597,7 @@ def main(argv=None):
     if a.matrix_based_only:
         print(json.dumps({"partial": True, "matrix_based": matrix_based_bench()}), flush=True)
         return 0
-    w = W.config2()
+    w = W.cube_spheres_q2()
     dim, nc, deg = w["dim"], w["n_cells"], w["degree"]
     u = torch.as_tensor(w["u"], device="cuda")
     x64 = torch.as_tensor(w["x"], device="cuda")
@@ -636,8 +636,8 @@ def main(argv=None):
         torch.cuda.empty_cache()
     if not any(k[1] == "f64" for k in res) or not any(k[1] == "f32" for k in res):
         part = {"partial": True, "variants": {f"{POLICIES[k[0]]}/{k[1]}": res[k] for k in res}}
-        if a.config5 or a.config5_vmult_only:
-            part["config5"] = config5_bench(newton=not a.config5_vmult_only)
+        if a.q4_48cube or a.q4_48cube_vmult_only:
+            part["q4_48cube"] = q4_48cube_bench(newton=not a.q4_48cube_vmult_only)
         print(json.dumps(part))
         return 0
     best = max((k for k in res if k[1] == "f64"), key=lambda k: res[k]["dofs_per_s"])
@@ -681,8 +681,8 @@ def main(argv=None):
             out["newton_step"]["cpu_oracle"] = cpu_newton_baseline(w)
     if not a.no_batch:
         out["batched"] = batch_bench(solve=not a.no_batch_solve)
-    if a.config5 or a.config5_vmult_only:
-        out["config5"] = config5_bench(newton=not a.config5_vmult_only)
+    if a.q4_48cube or a.q4_48cube_vmult_only:
+        out["q4_48cube"] = q4_48cube_bench(newton=not a.q4_48cube_vmult_only)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

@@ -22,7 +22,7 @@ def sdev(a, dtype=torch.float64):
 
 
 def _problems(n, seed, **kw):
-    descs = W.config4(n=n, seed=seed, sizes=(2, 4, 6), degrees=(1, 2, 3))
+    descs = W.batch_of_cubes(n=n, seed=seed, sizes=(2, 4, 6), degrees=(1, 2, 3))
     mu, lam = W.two_phase_material()
     probs, fields = [], []
     for d in descs:

@@ -21,7 +21,7 @@ pytestmark = [pytest.mark.gpu, requires_gpu]
 CLAMP3 = W.clamp_bottom_top(3)
 
 CASES = {
-    "cfg1_2d_q1": W.config1(),
+    "square_16x16_q1": W.square_disc_q1_16(),
     "2d_q3_clamp": W.problem(2, 5, 3, disc=True, u_amp=0.04, u_kmax=2, mask=W.clamp_bottom_top(2)),
     "3d_q1_clamp": W.problem(3, 5, 1, n_spheres=3, u_amp=0.05, u_kmax=2, mask=CLAMP3),
     "3d_q2_mixedmask": W.problem(3, 3, 2, n_spheres=2, u_amp=0.05, u_kmax=2,
@@ -85,12 +85,12 @@ def test_csr_coarse_level_matches_matrix_free():
         assert rel_l2(y, host(P.tangent_vmult(x, level=level))) <= 1e-12, level
 
 
-def test_csr_full_config2_size():
+def test_csr_q2_32cube():
     """32^3 Q2 (823,875 DoFs, the size of the operator benchmark): SpMV equals
     the matrix-free vmult, sampled rows equal the oracle's rows, and the row
     lengths match the closed form (3 * prod of per-axis node ranges)."""
-    w = W.config2()
-    log_case("csr_config2")
+    w = W.cube_spheres_q2()
+    log_case("csr_q2_32cube")
     mesh, mat, cons = oracle_problem(w)
     P = device_problem(w)
     u = dev(w["u"])

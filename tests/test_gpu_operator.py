@@ -5,7 +5,7 @@ operators, through the C ABI.
 Bar: relative l2 error <= 1e-12 in FP64 and <= 1e-5 in FP32 (x rounded to
 FP32 first), for every quadrature-point policy and both scatter modes.  The
 small cases span several blocks of cells with a ragged last block; the full
-config-2 size (32^3 Q2, 823,875 DoFs) is checked on sampled rows that the
+size of the 32^3 Q2 workload (823,875 DoFs) is checked on sampled rows that the
 oracle computes one by one, plus identities that hold at any size.
 """
 import numpy as np
@@ -22,7 +22,7 @@ CLAMP3 = W.clamp_bottom_top(3)
 CLAMP2 = W.clamp_bottom_top(2)
 
 CASES = {
-    "cfg1_2d_q1": W.config1(),
+    "square_16x16_q1": W.square_disc_q1_16(),
     "2d_q2": W.problem(2, 7, 2, disc=True, u_amp=0.04, u_kmax=2, mask=W.face_bits(2, 0, 0)),
     "2d_q3_clamp": W.problem(2, 5, 3, disc=True, u_amp=0.04, u_kmax=2, mask=CLAMP2),
     "2d_q4": W.problem(2, 4, 4, disc=True, u_amp=0.04, u_kmax=2),
@@ -114,14 +114,14 @@ def test_min_J_matches_oracle():
     assert abs(mj - fe.min_jacobian(mesh, w["u"])) <= 1e-13
 
 
-# ---- full config-2 size: 32^3 Q2, 823,875 DoFs ---------------------------------------
+# ---- full size: 32^3 Q2, 823,875 DoFs -------------------------------------------------
 
 _C2 = {}
 
 
-def _config2():
+def _q2_32cube():
     if not _C2:
-        w = W.config2()
+        w = W.cube_spheres_q2()
         mesh, mat, cons = oracle_problem(w)
         rng = np.random.default_rng(17)
         rows = np.sort(rng.choice(mesh.n_dofs, 160, replace=False))
@@ -138,10 +138,10 @@ def _config2():
 
 @pytest.mark.parametrize("scatter", [0, 2, 3], ids=["atomic", "tile", "elem"])
 @pytest.mark.parametrize("policy", [0, 1, 2, 3], ids=["R", "CF", "C2", "C4"])
-def test_config2_sampled_rows(policy, scatter):
-    c = _config2()
+def test_q2_32cube_sampled_rows(policy, scatter):
+    c = _q2_32cube()
     w = c["w"]
-    log_case("config2_rows", policy=policy, scatter=scatter, n_dofs=c["mesh"].n_dofs)
+    log_case("q2_32cube_rows", policy=policy, scatter=scatter, n_dofs=c["mesh"].n_dofs)
     P = device_problem(w, qp_policy=policy, scatter=scatter)
     P.set_deformation(dev(w["u"]))
     y = host(P.tangent_vmult(dev(w["x"])))
@@ -153,12 +153,12 @@ def test_config2_sampled_rows(policy, scatter):
     assert np.abs(r[c["rows"]] - c["rres"]).max() <= 1e-12 * max(np.abs(c["rres"]).max(), 1e-300) + 1e-15
 
 
-def test_config2_identities():
+def test_q2_32cube_identities():
     """Translations are in the kernel of the unconstrained tangent; the
     operator is symmetric (x^T K y = y^T K x)."""
-    c = _config2()
+    c = _q2_32cube()
     w = c["w"]
-    log_case("config2_identities")
+    log_case("q2_32cube_identities")
     P = device_problem(w)
     P.set_deformation(dev(w["u"]))
     n = P.n_dofs()

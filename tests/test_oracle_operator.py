@@ -180,8 +180,8 @@ def test_diagonal_closed_form():
     np.testing.assert_allclose(diag, K.diagonal(), rtol=1e-12)
 
 
-def test_config1_shapes():
-    c = W.config1()
+def test_square_disc_q1_16_shapes():
+    c = W.square_disc_q1_16()
     m = fe.Mesh(c["dim"], c["n_cells"], c["degree"])
     assert m.n_dofs == 578
     K = fe.tangent_matrix(m, fe.Material(c["mu"], c["lam"], c["inclusions"]), c["u"])

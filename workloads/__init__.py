@@ -125,13 +125,13 @@ def problem(dim, n_cells, degree, n_spheres=0, sphere_seed=3, u_seed=4, u_amp=0.
                 inclusions=incl, u=u, x=x, mask=mask)
 
 
-def config1():
+def square_disc_q1_16():
     """2-D plane-strain unit square, 16x16 Q1, centred disc r = 0.25 (100x stiffer),
     u = 8 seeded sine modes of amplitude 0.05 (seed 1), x ~ N(0,1) (seed 2)."""
     return problem(2, 16, 1, disc=True, u_seed=1, u_amp=0.05, u_kmax=2, x_seed=2)
 
 
-def config2(n_cells=32):
+def cube_spheres_q2(n_cells=32):
     """3-D unit cube, 32^3 Q2, 20 spheres (seed 3, r in [0.05, 0.12]),
     smooth u of amplitude 0.1 (seed 4), x ~ N(0,1) (seed 5)."""
     return problem(3, n_cells, 2, n_spheres=20, sphere_seed=3, u_seed=4, u_amp=0.1,
@@ -141,7 +141,7 @@ def config2(n_cells=32):
 BATCH_LEVELS = {8: 3, 12: 3, 16: 4, 24: 4}
 
 
-def config4(n=256, seed=6, sizes=(8, 12, 16, 24), degrees=(1, 2, 3)):
+def batch_of_cubes(n=256, seed=6, sizes=(8, 12, 16, 24), degrees=(1, 2, 3)):
     """256 independent 3-D problems: N uniform in {8, 12, 16, 24} cells per
     direction, degree uniform in {1, 2, 3}, 1-10 spheres (r in [0.05, 0.12]),
     bottom and top clamped.  The linearisation point is a loaded state: a
@@ -176,7 +176,7 @@ def stretched_field(dim, L, stretch, seed, amp, coords=None):
 
 
 def batch_fields(desc, coords=None):
-    """(inclusions, u, x) of one config-4 problem; ``coords`` are the support
+    """(inclusions, u, x) of one problem of the batch; ``coords`` are the support
     points along an axis of its finest level."""
     L = desc["degree"] * desc["n_cells"] + 1
     incl = spheres(desc["n_spheres"], desc["sphere_seed"], 3)
