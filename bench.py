@@ -36,11 +36,11 @@ POLICIES = {0: "recompute", 1: "cache_F", 2: "cache_T2", 3: "cache_T4"}
 # rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by a 256 MiB device copy (reads
 # x2.0, writes x1.0; profiles/tangent_vmult_q2_32cube_hbm_counters.md); valid
 # only for the kernel source they were taken on.
-TRAFFIC_SOURCE_SHA = "81435bb4960d215d"
-TRAFFIC = {"recompute/f64/element": 65937438, "cache_F/f64/element": 123321293,
-           "cache_T2/f64/element": 130381653, "cache_T4/f64/atomic": 330285710,
-           "recompute/f32/element": 34124203, "cache_F/f32/element": 62454710,
-           "cache_T2/f32/element": 66041649, "cache_T4/f32/element": 175975358}
+TRAFFIC_SOURCE_SHA = "1c1552f6c40a5f50"
+TRAFFIC = {"recompute/f64/element": 65926109, "cache_F/f64/element": 123295649,
+           "cache_T2/f64/element": 130352688, "cache_T4/f64/atomic": 331177397,
+           "recompute/f32/element": 34124284, "cache_F/f32/element": 62446670,
+           "cache_T2/f32/element": 65987053, "cache_T4/f32/element": 176002641}
 
 QP_FLOPS_3D = {0: 261, 1: 255, 2: 170, 3: 246}
 QP_FLOPS_2D = {0: 100, 1: 98, 2: 55, 3: 71}
@@ -94,18 +94,29 @@ def roofline(dim, degree, n_cells, n_dofs, policy, dtype, kernel_ms, scatter):
 
 
 def time_vmult(P, x, y, steps, warmup, cold=False, flush=None):
+    """(ms per step, ms per vmult inside the library's event pairs).  The steps
+    run back to back without instrumentation; a second pass of the same calls
+    with the library's timer on (an event pair around the kernels of each
+    vmult, on the library's stream) gives the kernel durations.  The event
+    pairs cost a few microseconds per call themselves, so they stay out of the
+    step time."""
     import torch
     for _ in range(warmup):
         P.tangent_vmult(x, y)
     torch.cuda.synchronize()
-    P.timer_enable(True)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
+    e0.record(P.stream)
     for _ in range(steps):
         if cold:
             flush.add_(1.0)
         P.tangent_vmult(x, y)
-    e1.record()
+    e1.record(P.stream)
+    torch.cuda.synchronize()
+    P.timer_enable(True)
+    for _ in range(steps):
+        if cold:
+            flush.add_(1.0)
+        P.tangent_vmult(x, y)
     torch.cuda.synchronize()
     kms, nl = P.timer_read()
     P.timer_enable(False)
