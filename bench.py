@@ -275,10 +275,12 @@ def cpu_newton_baseline(w, n_cells=8, n_levels=3, stretch=0.025):
                       f"{stretch:.1%} stretch, {wall:.1f} s wall"}
 
 
-def newton_bench(w, n_cells=64, n_levels=5, stretch=0.1, n_steps=4, shear_traction=0.1):
+def newton_bench(w, n_cells=64, n_levels=5, stretch=0.1, n_steps=4, shear_traction=0.1, only=None):
     """Newton load stepping with GMG-CG (1e-8) on the two-phase material,
     64^3 Q2 (6.44M DoFs), levels 4^3..64^3, clamped bottom/top, 10 % stretch in
-    4 steps; mixed-precision (FP32 V-cycle) and all-FP64 forms."""
+    4 steps; mixed-precision (FP32 V-cycle) and all-FP64 forms.  `only`: the
+    names of the runs to make ("shear_traction" for the traction load path),
+    all when None."""
     import torch
 
     import workloads as W
@@ -302,6 +304,8 @@ def newton_bench(w, n_cells=64, n_levels=5, stretch=0.1, n_steps=4, shear_tracti
             ("mixed_chebyshev_coarse", dict(vcycle_dtype=F32, qp_policy=2, coarse_solver=1)),
             ("mixed_eig_reuse", dict(vcycle_dtype=F32, qp_policy=2, eig_refresh=0)))
     for name, kw in runs:
+        if only is not None and name not in only:
+            continue
         kw = dict(kw)
         graphs = kw.pop("graphs", False)
         if graphs:
@@ -332,7 +336,10 @@ def newton_bench(w, n_cells=64, n_levels=5, stretch=0.1, n_steps=4, shear_tracti
               f"total {total:.2f} s, status {st}", file=sys.stderr, flush=True)
         del P
         torch.cuda.empty_cache()
-    out["speedup_mixed_vs_fp64"] = out["fp64"]["median_step_ms"] / out["mixed"]["median_step_ms"]
+    if "fp64" in out and "mixed" in out:
+        out["speedup_mixed_vs_fp64"] = out["fp64"]["median_step_ms"] / out["mixed"]["median_step_ms"]
+    if only is not None and "shear_traction" not in only:
+        return out
     # the paper's load path (Sec. 7): bottom clamped, dead shear traction on the top face in 5 steps
     P = Problem(3, n_cells, 2, n_levels=n_levels, mu=tuple(w["mu"]), lam=tuple(w["lam"]),
                 inclusions=w["inclusions"], dirichlet_mask=W.face_bits(3, 2, 0), vcycle_dtype=F32, qp_policy=2)
@@ -584,6 +591,8 @@ def main(argv=None):
     ap.add_argument("--no-cold", action="store_true")
     ap.add_argument("--scatter", type=int, default=-1, help="-1 auto (tuned table), 0 atomic, 1 colour, 2 tile, 3 element")
     ap.add_argument("--no-newton", action="store_true", help="skip the 64^3 Q2 Newton-step measurement")
+    ap.add_argument("--newton-runs", default="", help="comma-separated Newton runs to make (mixed, fp64, "
+                    "mixed_recompute, ..., shear_traction); all when empty")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-problem batched measurement")
     ap.add_argument("--no-batch-solve", action="store_true", help="256-problem batch: time the batched vmult only")
     ap.add_argument("--q4-48cube", action="store_true", help="also run the Q4 48^3 level vmults and Newton (minutes)")
@@ -687,7 +696,7 @@ def main(argv=None):
     if not a.no_matrix_based:
         out["matrix_based"] = matrix_based_bench()
     if not a.no_newton:
-        out["newton_step"] = newton_bench(w)
+        out["newton_step"] = newton_bench(w, only=a.newton_runs.split(",") if a.newton_runs else None)
         if not a.no_cpu:
             out["newton_step"]["cpu_oracle"] = cpu_newton_baseline(w)
     if not a.no_batch:
