@@ -603,7 +603,7 @@ def main(argv=None):
                     help="also run one plain 256 MiB device copy (reference for HBM byte counters)")
     a = ap.parse_args(argv)
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md, sharding)",
+        print("bench.py measures one GPU only: the library has no multi-GPU path",
               file=sys.stderr)
         return 2
 
