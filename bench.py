@@ -37,10 +37,10 @@ POLICIES = {0: "recompute", 1: "cache_F", 2: "cache_T2", 3: "cache_T4"}
 # x2.0, writes x1.0; profiles/tangent_vmult_q2_32cube_hbm_counters.md); valid
 # only for the kernel source they were taken on.
 TRAFFIC_SOURCE_SHA = "1c1552f6c40a5f50"
-TRAFFIC = {"recompute/f64/element": 65926109, "cache_F/f64/element": 123295649,
-           "cache_T2/f64/element": 130352688, "cache_T4/f64/atomic": 331177397,
-           "recompute/f32/element": 34124284, "cache_F/f32/element": 62446670,
-           "cache_T2/f32/element": 65987053, "cache_T4/f32/element": 176002641}
+TRAFFIC = {"recompute/f64/element": 65926172, "cache_F/f64/element": 123295089,
+           "cache_T2/f64/element": 130351420, "cache_T4/f64/atomic": 330614431,
+           "recompute/f32/element": 34124294, "cache_F/f32/element": 62446763,
+           "cache_T2/f32/element": 65994313, "cache_T4/f32/element": 175956237}
 
 QP_FLOPS_3D = {0: 261, 1: 255, 2: 170, 3: 246}
 QP_FLOPS_2D = {0: 100, 1: 98, 2: 55, 3: 71}
@@ -79,10 +79,11 @@ def roofline(dim, degree, n_cells, n_dofs, policy, dtype, kernel_ms, scatter):
     t_hbm = nbytes / (HBM_PEAK_GBS * 1e9)
     t_alu = flops / (PEAK_TFLOPS[dtype] * 1e12)
     s = kernel_ms * 1e-3
-    timed = {"element": "cell kernel k_tangent + node-sum kernel k_elem_gather of one vmult (ELEMENT scatter)",
-             "atomic": "cell kernel k_tangent (atomic scatter; output fill excluded)",
-             "tile": "tile kernel k_tangent_tile (output fill excluded)",
-             "color": "the 2^d colour launches of k_tangent"}[scatter]
+    timed = {"element": "cell kernel k_tangent + node-sum kernel k_elem_gather of each vmult (ELEMENT scatter)",
+             "atomic": "output fill + cell kernel k_tangent of each vmult (atomic scatter)",
+             "tile": "output fill + tile kernel k_tangent_tile of each vmult",
+             "color": "output fill + the 2^d colour launches of k_tangent of each vmult"}[scatter]
+    timed += ": HIP events on the library's stream around the timed steps, divided by the steps"
     if t_hbm >= t_alu:
         ach = nbytes / s / 1e9
         return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
@@ -681,14 +682,16 @@ def main(argv=None):
                                "seeded displacement amplitude 0.1; one FP64 tangent vmult per step",
                    "n_dofs": n_dofs, "cells": nc ** dim, "degree": deg, "qp_policy": POLICIES[best[0]],
                    "scatter": ("auto: " if a.scatter < 0 else "") + r["scatter"]},
-        "roofline": roofline(dim, deg, nc, n_dofs, best[0], "f64", r["kernel_ms"], r["scatter"]),
+        "roofline": roofline(dim, deg, nc, n_dofs, best[0], "f64", r["ms_per_step"], r["scatter"]),
         "fp32": {"value": res[best32]["dofs_per_s"], "unit": "DoF/s", "qp_policy": POLICIES[best32[0]],
                  "scatter": res[best32]["scatter"],
-                 "roofline": roofline(dim, deg, nc, n_dofs, best32[0], "f32", res[best32]["kernel_ms"],
+                 "roofline": roofline(dim, deg, nc, n_dofs, best32[0], "f32", res[best32]["ms_per_step"],
                                       res[best32]["scatter"])},
         "variants": {f"{POLICIES[k[0]]}/{k[1]}": {kk: (round(v, 6) if isinstance(v, float) else v)
                                                  for kk, v in res[k].items()} for k in res},
     }
+    # the same kernels timed per call inside the library's event pairs (which
+    # add about 2 us per call), warm and after a 512 MB cache flush
     out["roofline"]["kernel_ms"] = r["kernel_ms"]
     out["roofline"]["kernel_ms_cold"] = r["kernel_ms_cold"]
     if 3 in [int(p) for p in a.policies.split(",")]:
