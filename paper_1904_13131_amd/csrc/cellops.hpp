@@ -66,6 +66,21 @@ struct Geo {
   static constexpr int NARR = DIM == 3 ? 3 : 2;        // LDS arrays per component
 };
 
+// Element buffer of the ELEMENT scatter for a level of `cells` cells (T words,
+// each array cell-fastest, so that a block's cells store and load coalesced):
+//   [0, DIM * NX * cells): component c, slot s = x + P * line at
+//     (c * NX + s) * cells + e, for the x-nodes x = 0..P-1 of each x-line
+//     (line = y + N1 * z in cell-local node indices);
+//   then the overflow part, (c * NP + line) * cells + e: the sums of the last
+//     x-node (x = P) of the cells that could not hand them to their
+//     x-neighbour (last cell of a block, cells on the x = 1 face).
+// Together DIM * NV * cells words, the size of one value per cell node.
+template <int DIM, int N1>
+struct ElemLayout {
+  static constexpr int NP = Geo<DIM, N1>::NP;
+  static constexpr int NX = (N1 - 1) * NP;
+};
+
 template <int DIM, int N1, typename T>
 struct SumFact {
   using G = Geo<DIM, N1>;
@@ -797,17 +812,38 @@ __device__ __forceinline__ void tangent_block(const CellArgs<T>& a, const T* __r
   T out[DIM][N1];
   SF::template backward<DIM>(gx, out, lds, pen, cl, act, a.tb);
   if (a.elem != nullptr) {
-    // element buffer: one coalesced store per (component, node) across the block's cells
+    // Element buffer (layout at ElemLayout): x-nodes 0..P-1 of every line, one
+    // coalesced store per (component, node) across the block's cells.  The
+    // last x-node of a line is the first one of the x-neighbour's line: when
+    // that neighbour is the next cell of this block, its thread adds the sums
+    // (through LDS, free after the transposed sweeps' last barrier); otherwise
+    // (block end, x = 1 face) they go to the overflow part.
+    using EL = ElemLayout<DIM, N1>;
+    const int line = DIM == 3 ? p0 + N1 * p1 : p0;
     if (act) {
-      const int line = DIM == 3 ? N1 * (p0 + N1 * p1) : N1 * p0;
+#pragma unroll
+      for (int c = 0; c < DIM; ++c) lds[(c * G::NP + line) * G::CPB + cl] = out[c][N1 - 1];
+    }
+    __syncthreads();
+    if (act) {
+      if (cl > 0 && !cp.first_i) {
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) out[c][0] += lds[(c * G::NP + line) * G::CPB + cl - 1];
+      }
+      const long long lane_e = (long long)(P * line) * a.ncells + cp.e;
+      const unsigned lane_eb = O32 ? (unsigned)lane_e * (unsigned)sizeof(T) : 0u;
 #pragma unroll
       for (int c = 0; c < DIM; ++c)
 #pragma unroll
-        for (int k = 0; k < N1; ++k) {
-          const long long lane_e = (long long)line * a.ncells + cp.e;
-          lane_store<O32>(a.elem + ((long long)c * G::NV + k) * a.ncells, lane_e,
-                          O32 ? (unsigned)lane_e * (unsigned)sizeof(T) : 0u, out[c][k]);
-        }
+        for (int k = 0; k < P; ++k)
+          lane_store<O32>(a.elem + ((long long)c * EL::NX + k) * a.ncells, lane_e, lane_eb, out[c][k]);
+      if (cl + 1 == G::CPB || cp.last_i || lin + 1 >= a.nlaunch) {
+        const long long lane_o = (long long)line * a.ncells + cp.e;
+        const unsigned lane_ob = O32 ? (unsigned)lane_o * (unsigned)sizeof(T) : 0u;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c)
+          lane_store<O32>(a.elem + ((long long)DIM * EL::NX + c * G::NP) * a.ncells, lane_o, lane_ob, out[c][N1 - 1]);
+      }
     }
   } else if (a.color < 0) {
     // The x-neighbour of this cell (same pencil) sits in the previous lane when
@@ -828,16 +864,22 @@ __device__ __forceinline__ void tangent_block(const CellArgs<T>& a, const T* __r
 }
 
 // Second pass of the ELEMENT scatter: y at every node is the sum of the
-// element-buffer entries of the (at most 2^dim) cells containing it, in a
-// fixed order; constrained entries take x (mask_in = 1) or 0.  One thread per
-// node of an (i, j) plane and all its components (the d * 2^d loads are in
-// flight together); blockIdx.y is the plane k.  j = t / L comes from a
-// multiply-high by magic = ceil(2^32 / L), exact for t < L^2 while L^3 < 2^32.
+// element-buffer entries (ElemLayout) of the cells containing it, in a fixed
+// order; constrained entries take x (mask_in = 1) or 0.  Along x a node has
+// one entry: the slot of the cell it starts (x-node 0..P-1), which for a node
+// shared by cells q - 1 and q already holds both cells' sums, unless cell
+// q - 1 ended its cell block (then its share sits in the overflow part, a
+// second entry); the node on the x = 1 face reads the overflow of cell N - 1.
+// Along y and z, one or two cells each.  One thread per node of an (i, j)
+// plane and all its components (the loads are in flight together);
+// blockIdx.y is the plane k.  j = t / L comes from a multiply-high by
+// magic = ceil(2^32 / L), exact for t < L^2 while L^3 < 2^32.
 template <int DIM, int P, typename T, typename Out>
 __device__ __forceinline__ void elem_gather_node(const CellArgs<T>& a, const T* __restrict__ x, const Out& out,
                                                  int t, int k, unsigned magic) {
   constexpr int N1 = P + 1;
-  constexpr int NV = Geo<DIM, N1>::NV;
+  constexpr int CPB = Geo<DIM, N1>::CPB;
+  using EL = ElemLayout<DIM, N1>;
   const int N = a.N, L = a.L;
   if (t >= L * L) return;
   const int j = (int)__umulhi((unsigned)t, magic);
@@ -846,7 +888,7 @@ __device__ __forceinline__ void elem_gather_node(const CellArgs<T>& a, const T* 
   int ce[3][2], cn[3][2], m[3];
   const int idx[3] = {i, j, k};
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
+  for (int d = 1; d < 3; ++d) {
     if (d >= DIM) {
       ce[d][0] = ce[d][1] = 0;
       cn[d][0] = cn[d][1] = 0;
@@ -862,24 +904,32 @@ __device__ __forceinline__ void elem_gather_node(const CellArgs<T>& a, const T* 
     cn[d][1] = 0;
     m[d] = (has_lo && has_hi) ? 2 : 1;
   }
-  // the (at most 2^DIM) entries of every component: loads first, then the sums
+  const int qx = i / P, rx = i - qx * P;
+  const bool last = qx == N;                    // i = L - 1
+  const int ex0 = last ? N - 1 : qx;
+  const bool shared = rx == 0 && qx > 0 && qx < N;
+  // the entries of every component: loads first, then the sums
   T v[DIM][DIM == 3 ? 8 : 4];
 #pragma unroll
   for (int c = 0; c < DIM; ++c) {
-    const T* base = a.elem + (long long)c * NV * a.ncells;
+    const T* eb = a.elem + (long long)c * EL::NX * a.ncells;
+    const T* ob = a.elem + ((long long)DIM * EL::NX + (long long)c * EL::NP) * a.ncells;
 #pragma unroll
     for (int zz = 0; zz < (DIM == 3 ? 2 : 1); ++zz)
 #pragma unroll
-      for (int yy = 0; yy < 2; ++yy)
-#pragma unroll
-        for (int xx = 0; xx < 2; ++xx) {
-          const int s = xx + 2 * (yy + 2 * zz);
-          const bool on = xx < m[0] && yy < m[1] && zz < m[2];
-          const int e = ce[0][xx] + N * (ce[1][yy] + N * ce[2][zz]);
-          const int n = cn[0][xx] + N1 * (cn[1][yy] + N1 * cn[2][zz]);
-          const T val = base[on ? (long long)n * a.ncells + e : 0];   // in bounds for every lane
-          v[c][s] = on ? val : T(0);
-        }
+      for (int yy = 0; yy < 2; ++yy) {
+        const int s = yy + 2 * zz;
+        const bool on = yy < m[1] && zz < m[2];
+        const int eyz = N * (ce[1][yy] + N * ce[2][zz]);
+        const int line = cn[1][yy] + N1 * cn[2][zz];
+        const int e0 = ex0 + eyz, e1 = qx - 1 + eyz;
+        const bool on1 = on && shared && (unsigned)e1 % (unsigned)CPB == (unsigned)(CPB - 1);
+        const long long i0 = (long long)(last ? line : rx + P * line) * a.ncells + e0;
+        const T v0 = (last ? ob : eb)[on ? i0 : 0];                             // in bounds for every lane
+        const T v1 = ob[on1 ? (long long)line * a.ncells + e1 : 0];
+        v[c][2 * s] = on ? v0 : T(0);
+        v[c][2 * s + 1] = on1 ? v1 : T(0);
+      }
   }
 #pragma unroll
   for (int c = 0; c < DIM; ++c) {
