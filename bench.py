@@ -36,11 +36,11 @@ POLICIES = {0: "recompute", 1: "cache_F", 2: "cache_T2", 3: "cache_T4"}
 # rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by a 256 MiB device copy (reads
 # x2.0, writes x1.0; profiles/tangent_vmult_q2_32cube_hbm_counters.md); valid
 # only for the kernel source they were taken on.
-TRAFFIC_SOURCE_SHA = "1c1552f6c40a5f50"
-TRAFFIC = {"recompute/f64/element": 65926172, "cache_F/f64/element": 123295089,
-           "cache_T2/f64/element": 130351420, "cache_T4/f64/atomic": 330614431,
-           "recompute/f32/element": 34124294, "cache_F/f32/element": 62446763,
-           "cache_T2/f32/element": 65994313, "cache_T4/f32/element": 175956237}
+TRAFFIC_SOURCE_SHA = "3d97554492b0d0fd"
+TRAFFIC = {"recompute/f64/element": 58783655, "cache_F/f64/element": 116139061,
+           "cache_T2/f64/element": 123173541, "cache_T4/f64/element": 349130058,
+           "recompute/f32/element": 32027434, "cache_F/f32/element": 60370312,
+           "cache_T2/f32/element": 63891996, "cache_T4/f32/element": 173531014}
 
 QP_FLOPS_3D = {0: 261, 1: 255, 2: 170, 3: 246}
 QP_FLOPS_2D = {0: 100, 1: 98, 2: 55, 3: 71}
