@@ -1,7 +1,9 @@
 """Edge cases of the device path against the oracle: single-cell meshes of
 every degree, fully constrained boundaries, zero and undeformed inputs, a
-body that is all inclusion, and the largest lattice the library accepts (2-D,
-1600 nodes per direction), checked on sampled rows.
+body that is all inclusion, the largest lattice the library accepts (2-D,
+1600 nodes per direction) checked on sampled rows, 32-bit lane offsets past
+2^31 and 64-bit ones past 2^32, and element-scatter cell blocks that end in
+the middle of x-rows.
 
 Bars as in the operator tests: FP64 relative l2 <= 1e-12 (absolute on
 sampled rows, relative to the largest entry)."""
@@ -139,3 +141,26 @@ def test_level_beyond_32bit_lane_offsets():
     np.testing.assert_allclose(yh[rows], ref, rtol=0, atol=1e-12 * np.abs(ref).max())
     y32 = Q.tangent_vmult(x.float())
     assert float((y32.double() - y_ref).norm() / y_ref.norm()) <= 1e-5
+
+
+@pytest.mark.parametrize("dim,n,p", [(2, 13, 1), (2, 10, 2), (2, 9, 3), (2, 8, 4), (3, 3, 4), (3, 6, 2), (3, 5, 3)],
+                         ids=["2d_q1", "2d_q2", "2d_q3", "2d_q4", "3d_q4", "3d_q2", "3d_q3"])
+@pytest.mark.parametrize("policy", [0, 2], ids=["R", "C2"])
+def test_element_buffer_block_ends(dim, n, p, policy):
+    """Element scatter where cell blocks end in the middle of x-rows, so that
+    both routes of a shared x-face node are taken: summed by the x-neighbour
+    in the same block, and through the overflow part across block ends (and
+    on the x = 1 face).  FP64 against the oracle's assembled tangent, FP32 to
+    the FP32 bar."""
+    from paper_1904_13131_amd import F32
+    log_case("element_block_ends", dim=dim, n=n, p=p, policy=policy)
+    w = W.problem(dim, n, p, disc=dim == 2, n_spheres=0 if dim == 2 else 3, u_amp=0.04, u_kmax=1,
+                  mask=W.face_bits(dim, dim - 1, 0))
+    mesh, mat, cons = oracle_problem(w)
+    K = fe.constrain_matrix(fe.tangent_matrix(mesh, mat, w["u"]), cons)
+    ref = K @ w["x"]
+    P = device_problem(w, qp_policy=policy, scatter=3, vcycle_dtype=F32)
+    P.set_deformation(dev(w["u"]))
+    assert rel_l2(host(P.tangent_vmult(dev(w["x"]))), ref) <= 1e-12
+    y32 = P.tangent_vmult(dev(w["x"]).float())
+    assert rel_l2(host(y32.double()), K @ host(dev(w["x"]).float().double())) <= 1e-5
