@@ -327,6 +327,7 @@ def newton_bench(w, n_cells=64, n_levels=5, stretch=0.1, n_steps=4, shear_tracti
             "status": int(st), "newton_steps": len(recs), "total_s": round(total, 3),
             "median_step_ms": float(np.median(steps)), "mean_step_ms": float(np.mean(steps)),
             "median_setup_ms": float(np.median([r["setup_ms"] for r in recs])),
+            "median_residual_ms": float(np.median([r["residual_ms"] for r in recs])),
             "median_solve_ms": float(np.median([r["solve_ms"] for r in recs])),
             "cg_iters": [r["cg_iters"] for r in recs],
             "max_cg_relres": max(r["cg_relres"] for r in recs),
