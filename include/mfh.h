@@ -102,11 +102,11 @@ enum { MFH_LAW_NEO_HOOKE = 0, MFH_LAW_MOONEY_RIVLIN = 1 };
  * deterministic), TILE (one block per tile of cells: tile nodes staged in
  * LDS, contributions summed there, global atomics only on tile faces shared
  * with a neighbouring tile; order varies) or ELEMENT (the cell kernel stores
- * every cell's nodal results in an element buffer, a second kernel sums the
- * at most 2^dim cell contributions of every node in a fixed order and writes
- * each output entry once: deterministic, no atomics, no separate output
- * fill; the workspace grows by dim * (p+1)^dim * cells of the finest level
- * doubles).  AUTO takes, for every level and precision, the mode measured
+ * every cell's nodal results in an element buffer, the shared face nodes of
+ * x-neighbours in one cell block already summed, and a second kernel sums
+ * the remaining contributions of every node in a fixed order and writes each
+ * output entry once: deterministic, no atomics, no separate output fill; the
+ * workspace grows by dim * (p+1)^dim * cells of the finest level doubles).  AUTO takes, for every level and precision, the mode measured
  * fastest on gfx950 for the problem's dimension, degree, qp policy and the
  * level's cell count (a table built by the package's autotuner and compiled
  * into the library).  The choice affects tangent_vmult only; all other cell
