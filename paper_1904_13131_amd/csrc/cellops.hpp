@@ -597,8 +597,9 @@ __device__ __forceinline__ void mr_spatial_tangent(const T (&F)[DIM][DIM], T jm1
 // Per-lane arrays at a wave-uniform base (caches, element buffer): with O32
 // the lane's offset is a 32-bit byte count, so the loads and stores take the
 // base from scalar registers and need no 64-bit address arithmetic per
-// access; the launcher picks O32 when every offset of the level fits
-// (NV * cells * sizeof(T) < 2^32), else the 64-bit form.
+// access; the launcher picks O32 when every offset of the level fits, also
+// those of arrays of T pairs (NV * cells * 2 * sizeof(T) < 2^32), else the
+// 64-bit form.
 template <bool O32, typename T>
 __device__ __forceinline__ T lane_load(const T* ubase, long long lane, unsigned lane_bytes) {
   if constexpr (O32)
@@ -612,6 +613,70 @@ __device__ __forceinline__ void lane_store(T* ubase, long long lane, unsigned la
     *(T*)((char*)ubase + lane_bytes) = v;
   else
     ubase[lane] = v;
+}
+
+// cache_T2 data of a quadrature point: F^-1 (row-major) and c1.  In 3-D the
+// ten words are five pairs (words 2k, 2k+1): pair k of the point with element
+// index `at` (qp * cells + e) is element k * stride + at of the cache read as
+// an array of T pairs (stride = NV * cells), one 16-byte load per pair in
+// FP64.  In 2-D word w is element w * stride + at of the plain array.
+template <typename T> struct Vec2Of;
+template <> struct Vec2Of<double> { using type = double2; };
+template <> struct Vec2Of<float> { using type = float2; };
+
+// Reader: `base` is the wave-uniform part of `at`, `lane` the per-lane part.
+template <int DIM, typename T, bool O32>
+__device__ __forceinline__ void c2_load(const T* __restrict__ cache, long long base, long long stride, long long lane,
+                                        T (&Fi)[DIM][DIM], T& c1) {
+  if constexpr (DIM == 3) {
+    using V2 = typename Vec2Of<T>::type;
+    const V2* pb = reinterpret_cast<const V2*>(cache) + base;
+    const unsigned lb = O32 ? (unsigned)lane * (unsigned)sizeof(V2) : 0u;
+    T wv[10];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      const V2 v = lane_load<O32>(pb + k * stride, lane, lb);
+      wv[2 * k] = v.x;
+      wv[2 * k + 1] = v.y;
+    }
+#pragma unroll
+    for (int I = 0; I < 3; ++I)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) Fi[I][j] = wv[3 * I + j];
+    c1 = wv[9];
+  } else {
+    const T* wb = cache + base;
+    const unsigned lb = O32 ? (unsigned)lane * (unsigned)sizeof(T) : 0u;
+#pragma unroll
+    for (int I = 0; I < DIM; ++I)
+#pragma unroll
+      for (int j = 0; j < DIM; ++j) Fi[I][j] = lane_load<O32>(wb + (I * DIM + j) * stride, lane, lb);
+    c1 = lane_load<O32>(wb + DIM * DIM * stride, lane, lb);
+  }
+}
+
+// Writer (from the FP64 quadrature-point data, rounded to T).
+template <int DIM, typename T>
+__device__ __forceinline__ void c2_store(T* __restrict__ cache, long long at, long long stride,
+                                         const double (&Fi)[DIM][DIM], double c1) {
+  if constexpr (DIM == 3) {
+    using V2 = typename Vec2Of<T>::type;
+    V2* pb = reinterpret_cast<V2*>(cache) + at;
+    const double wv[10] = {Fi[0][0], Fi[0][1], Fi[0][2], Fi[1][0], Fi[1][1], Fi[1][2], Fi[2][0], Fi[2][1], Fi[2][2], c1};
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      V2 v;
+      v.x = (T)wv[2 * k];
+      v.y = (T)wv[2 * k + 1];
+      pb[k * stride] = v;
+    }
+  } else {
+#pragma unroll
+    for (int I = 0; I < DIM; ++I)
+#pragma unroll
+      for (int j = 0; j < DIM; ++j) cache[(I * DIM + j) * stride + at] = (T)Fi[I][j];
+    cache[DIM * DIM * stride + at] = (T)c1;
+  }
 }
 
 // Tangent action with a cached general tangent (Algorithm 3, referential
@@ -793,11 +858,7 @@ __device__ __forceinline__ void tangent_block(const CellArgs<T>& a, const T* __r
           kinematics<DIM, T>(H, F, Fi, jm1);
           c1 = mu - T(2) * lam * log1p_t<T>(jm1);
         } else {
-#pragma unroll
-          for (int I = 0; I < DIM; ++I)
-#pragma unroll
-            for (int j = 0; j < DIM; ++j) Fi[I][j] = lane_load<O32>(qb + (I * DIM + j) * wstride, lane_c, lane_cb);
-          c1 = lane_load<O32>(qb + DIM * DIM * wstride, lane_c, lane_cb);
+          c2_load<DIM, T, O32>(a.cache, (long long)q * G::NP * a.ncells, wstride, lane_c, Fi, c1);
         }
         tangent_qp<DIM, T>(Hx, Fi, c1, mu, lam, wt);
       }
@@ -1394,13 +1455,7 @@ k_tangent_tile(CellArgs<T> a) {
           kinematics<DIM, T>(H, F, Fi, jm1);
           c1 = mu - T(2) * lam * log1p_t<T>(jm1);
         } else {
-          const T* cq = a.cache + (long long)qp * a.ncells + e;
-          const long long stride = (long long)TG::NV * a.ncells;
-#pragma unroll
-          for (int I = 0; I < DIM; ++I)
-#pragma unroll
-            for (int j = 0; j < DIM; ++j) Fi[I][j] = cq[(I * DIM + j) * stride];
-          c1 = cq[DIM * DIM * stride];
+          c2_load<DIM, T, false>(a.cache, 0, (long long)TG::NV * a.ncells, (long long)qp * a.ncells + e, Fi, c1);
         }
         tangent_qp<DIM, T>(Hx, Fi, c1, mu, lam, wt);
       }
@@ -1577,11 +1632,7 @@ __global__ void __launch_bounds__(kBlock) k_qpdata(CellArgs<double> arg, T* __re
           for (int k = 0; k < Voigt<DIM>::NSYM; ++k) cq[(w++) * stride] = (T)Cv[k];
         } else {
           const D c1 = mu - 2.0 * lam * log1p(jm1);
-#pragma unroll
-          for (int I = 0; I < DIM; ++I)
-#pragma unroll
-            for (int j = 0; j < DIM; ++j) cq[(I * DIM + j) * stride] = (T)Fi[I][j];
-          cq[DIM * DIM * stride] = (T)c1;
+          c2_store<DIM, T>(cache, (long long)qp * a.ncells + cp.e, stride, Fi, c1);
         }
       }
     }

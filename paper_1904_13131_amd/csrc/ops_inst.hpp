@@ -51,10 +51,10 @@ struct OpInst {
     return tx * ty * tz;
   }
   // 32-bit lane offsets (see lane_load) when every per-lane offset of a level
-  // with `cells` cells fits
+  // with `cells` cells fits, including those into arrays of T pairs
   template <typename T>
   static bool off32(long long cells) {
-    return (long long)Geo<DIM, P + 1>::NV * cells * (long long)sizeof(T) < (1LL << 32);
+    return (long long)Geo<DIM, P + 1>::NV * cells * 2 * (long long)sizeof(T) < (1LL << 32);
   }
   template <typename T, int POL>
   static void tangent(const CellArgs<T>& a, unsigned grid, hipStream_t s) {

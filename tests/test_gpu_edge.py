@@ -111,16 +111,18 @@ def test_largest_lattice_2d():
 
 
 def test_level_beyond_32bit_lane_offsets():
-    """3-D Q1 with 407^3 cells (203 M DoFs): in FP64 the per-lane offsets of
-    the cache and element buffer exceed 2^32 bytes, so the vmult takes the
-    64-bit addressing form; in FP32 they lie between 2^31 and 2^32 (32-bit
-    form with offsets beyond the signed range).  Both agree with the recompute
-    policy on the atomic scatter over the whole vector and with the oracle on
-    sampled rows."""
+    """3-D Q1 with 350^3 cells (129 M DoFs).  The vmult addresses its per-lane
+    arrays with 32-bit byte offsets when NV * cells * 2 * word < 2^32 (the
+    factor 2 for the arrays of word pairs of the cache_T2 data), else with
+    64-bit ones.  Here FP64 takes the 64-bit form and FP32 the 32-bit form
+    with pair offsets beyond the signed range (between 2^31 and 2^32).  Both
+    agree with the recompute policy on the atomic scatter over the whole
+    vector and with the oracle on sampled rows."""
     from paper_1904_13131_amd import F32
-    log_case("large_offsets", cells=407 ** 3)
-    w = W.problem(3, 407, 1, n_spheres=20, u_amp=0.05, u_kmax=1, n_modes=2)
-    assert 8 * 407 ** 3 * 8 >= 2 ** 32 > 8 * 407 ** 3 * 4 >= 2 ** 31
+    n = 350
+    log_case("large_offsets", cells=n ** 3)
+    w = W.problem(3, n, 1, n_spheres=20, u_amp=0.05, u_kmax=1, n_modes=2)
+    assert 8 * n ** 3 * 2 * 8 >= 2 ** 32 > 8 * n ** 3 * 2 * 4 >= 2 ** 31
     mesh, mat, cons = oracle_problem(w)
     u, x = dev(w["u"]), dev(w["x"])
     rng = np.random.default_rng(11)
@@ -132,7 +134,7 @@ def test_level_beyond_32bit_lane_offsets():
     torch.cuda.synchronize()
     del P
     torch.cuda.empty_cache()
-    Q = device_problem(w, qp_policy=1, scatter=3, vcycle_dtype=F32)
+    Q = device_problem(w, qp_policy=2, scatter=3, vcycle_dtype=F32)
     Q.set_deformation(u)
     y = Q.tangent_vmult(x)
     torch.cuda.synchronize()
