@@ -173,12 +173,34 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+_DTYPES = {torch.float64: F64, torch.float32: F32}
+
+
+def _arg(t, name, device, n, dtypes=(torch.float64,)):
+    """Checks one vector argument before its pointer crosses the C ABI: a torch
+    tensor on the problem's device, of an accepted dtype, contiguous, with
+    exactly n entries.  Raises ValueError (never stripped, unlike assert)."""
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name}: expected a torch tensor, got {type(t).__name__}")
+    if t.device != device:
+        raise ValueError(f"{name}: tensor on device {t.device}, the problem lives on device {device}")
+    if t.dtype not in dtypes:
+        raise ValueError(f"{name}: dtype {t.dtype}, expected one of {[str(d) for d in dtypes]}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: tensor is not contiguous")
+    if t.numel() != n:
+        raise ValueError(f"{name}: {t.numel()} entries, expected {n}")
+    return t
+
+
 class Problem:
     """One mfh_problem with its workspace (a torch uint8 device tensor)."""
 
     def __init__(self, dim, n_cells, degree, device="cuda", stream=None, **kw):
         self.desc, self._keep = make_desc(dim, n_cells, degree, **kw)
         self.device = torch.device(device)
+        if self.device.type == "cuda" and self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
         self.dim = dim
         size = workspace_size(self.desc)
         self.workspace = torch.empty(size + 256, dtype=torch.uint8, device=self.device)
@@ -211,36 +233,40 @@ class Problem:
     def _vec(self, level, dtype):
         return torch.empty(self.n_dofs(level), dtype=dtype, device=self.device)
 
+    def _out(self, t, name, level, dtype):
+        if t is None:
+            return self._vec(level, dtype)
+        return _arg(t, name, self.device, self.n_dofs(level), (dtype,))
+
     def set_deformation(self, u):
-        assert u.dtype == torch.float64 and u.is_contiguous() and u.numel() == self.n_dofs()
+        _arg(u, "u", self.device, self.n_dofs())
         mj = ctypes.c_double()
         _check(lib().mfh_set_deformation(self.handle, _ptr(u), ctypes.byref(mj)), self.handle)
         return mj.value
 
     def tangent_vmult(self, x, y=None, level=-1):
         level = level % self.n_levels
-        dt = F64 if x.dtype == torch.float64 else F32
-        assert x.dtype in (torch.float64, torch.float32) and x.is_contiguous()
-        assert x.numel() == self.n_dofs(level)
-        y = self._vec(level, x.dtype) if y is None else y
+        _arg(x, "x", self.device, self.n_dofs(level), (torch.float64, torch.float32))
+        dt = _DTYPES[x.dtype]
+        y = self._out(y, "y", level, x.dtype)
         _check(lib().mfh_tangent_vmult(self.handle, level, dt, _ptr(x), _ptr(y)), self.handle)
         return y
 
     def residual(self, u, r=None):
-        assert u.dtype == torch.float64 and u.numel() == self.n_dofs()
-        r = self._vec(-1, torch.float64) if r is None else r
+        _arg(u, "u", self.device, self.n_dofs())
+        r = self._out(r, "r", -1, torch.float64)
         _check(lib().mfh_residual(self.handle, _ptr(u), _ptr(r)), self.handle)
         return r
 
     def gmg_vcycle(self, r, z=None):
-        assert r.dtype == torch.float64 and r.numel() == self.n_dofs()
-        z = self._vec(-1, torch.float64) if z is None else z
+        _arg(r, "r", self.device, self.n_dofs())
+        z = self._out(z, "z", -1, torch.float64)
         _check(lib().mfh_gmg_vcycle(self.handle, _ptr(r), _ptr(z)), self.handle)
         return z
 
     def cg_solve(self, b, x=None, rtol=1e-8, max_it=200, raise_on_error=True):
-        assert b.dtype == torch.float64 and b.numel() == self.n_dofs()
-        x = self._vec(-1, torch.float64) if x is None else x
+        _arg(b, "b", self.device, self.n_dofs())
+        x = self._out(x, "x", -1, torch.float64)
         it = ctypes.c_int()
         rel = ctypes.c_double()
         st = lib().mfh_cg_solve(self.handle, _ptr(b), _ptr(x), rtol, max_it, ctypes.byref(it), ctypes.byref(rel))
@@ -248,12 +274,24 @@ class Problem:
             _check(st, self.handle)
         return x, it.value, rel.value, st
 
+    def _faces(self, rows, name):
+        rows = [list(r) for r in rows]
+        if len(rows) != 2 * self.dim or any(len(r) != self.dim for r in rows):
+            raise ValueError(f"{name}: expected {2 * self.dim} faces x {self.dim} components")
+        return rows
+
     def apply_dirichlet(self, u, face_values, scale=1.0):
+        _arg(u, "u", self.device, self.n_dofs())
+        face_values = self._faces(face_values, "face_values")
         fv = _darr([v for row in face_values for v in row])
         _check(lib().mfh_apply_dirichlet(self.handle, _ptr(u), fv, scale), self.handle)
 
     def newton_solve(self, u, face_values, n_steps, cg_rtol=1e-8, cg_max_it=200, du_tol=1e-5, r_tol=1e-8,
                      max_newton=20, max_records=512, raise_on_error=True, face_traction=None):
+        _arg(u, "u", self.device, self.n_dofs())
+        face_values = self._faces(face_values, "face_values")
+        if face_traction is not None:
+            face_traction = self._faces(face_traction, "face_traction")
         fv = _darr([v for row in face_values for v in row])
         ft = _darr([v for row in face_traction for v in row]) if face_traction is not None else None
         recs = (NewtonRecord * max_records)()
@@ -266,8 +304,8 @@ class Problem:
         return out, st
 
     def external_force(self, face_traction, f=None):
-        ft = _darr([v for row in face_traction for v in row])
-        f = self._vec(-1, torch.float64) if f is None else f
+        ft = _darr([v for row in self._faces(face_traction, "face_traction") for v in row])
+        f = self._out(f, "f", -1, torch.float64)
         _check(lib().mfh_external_force(self.handle, ft, _ptr(f)), self.handle)
         return f
 
@@ -292,8 +330,12 @@ class Problem:
         """y = A x for the arrays of csr_assemble (FP64)."""
         level = level % self.n_levels
         rp, col, val = csr
-        assert x.dtype == torch.float64 and x.is_contiguous() and x.numel() == self.n_dofs(level)
-        y = self._vec(level, torch.float64) if y is None else y
+        n, nnz = self.csr_size(level)
+        _arg(rp, "row_ptr", self.device, n + 1, (torch.int64,))
+        _arg(col, "col", self.device, nnz, (torch.int32,))
+        _arg(val, "val", self.device, nnz)
+        _arg(x, "x", self.device, self.n_dofs(level))
+        y = self._out(y, "y", level, torch.float64)
         _check(lib().mfh_csr_spmv(self.handle, level, _ptr(rp), _ptr(col), _ptr(val), _ptr(x), _ptr(y)),
                self.handle)
         return y
@@ -328,15 +370,24 @@ class Problem:
         _check(lib().mfh_level_lambda_max(self.handle, level % self.n_levels, ctypes.byref(v)), self.handle)
         return v.value
 
+    def _transfer_level(self, level):
+        if not 1 <= level < self.n_levels:
+            raise ValueError(f"level {level}: transfers connect levels 1..{self.n_levels - 1} to the next coarser")
+        return level
+
     def prolongate(self, level, x, y=None):
-        dt = F64 if x.dtype == torch.float64 else F32
-        y = self._vec(level, x.dtype) if y is None else y
+        self._transfer_level(level)
+        _arg(x, "x", self.device, self.n_dofs(level - 1), (torch.float64, torch.float32))
+        dt = _DTYPES[x.dtype]
+        y = self._out(y, "y", level, x.dtype)
         _check(lib().mfh_prolongate(self.handle, level, dt, _ptr(x), _ptr(y)), self.handle)
         return y
 
     def restrict(self, level, x, y=None):
-        dt = F64 if x.dtype == torch.float64 else F32
-        y = self._vec(level - 1, x.dtype) if y is None else y
+        self._transfer_level(level)
+        _arg(x, "x", self.device, self.n_dofs(level), (torch.float64, torch.float32))
+        dt = _DTYPES[x.dtype]
+        y = self._out(y, "y", level - 1, x.dtype)
         _check(lib().mfh_restrict(self.handle, level, dt, _ptr(x), _ptr(y)), self.handle)
         return y
 
@@ -358,6 +409,10 @@ class Problem:
         return ms.value, n.value
 
     def chebyshev(self, level, f, x):
+        level = level % self.n_levels
+        dt = torch.float32 if self.desc.vcycle_dtype == F32 else torch.float64
+        _arg(f, "f", self.device, self.n_dofs(level), (dt,))
+        _arg(x, "x", self.device, self.n_dofs(level), (dt,))
         _check(lib().mfh_chebyshev(self.handle, level, _ptr(f), _ptr(x)), self.handle)
         return x
 
@@ -402,17 +457,31 @@ class Batch:
         except Exception:
             pass
 
+    def _vectors(self, ts, name, dtypes=(torch.float64,)):
+        ts = list(ts)
+        if len(ts) != len(self.problems):
+            raise ValueError(f"{name}: {len(ts)} vectors for {len(self.problems)} problems")
+        for i, (t, p) in enumerate(zip(ts, self.problems)):
+            _arg(t, f"{name}[{i}]", p.device, p.n_dofs(), dtypes)
+        if len({t.dtype for t in ts}) > 1:
+            raise ValueError(f"{name}: mixed dtypes")
+        return ts
+
     def set_deformation(self, us):
+        us = self._vectors(us, "us")
         mj = (ctypes.c_double * len(us))()
         _check_batch(lib().mfh_batch_set_deformation(self.handle, _parr(us), mj), self.handle)
         return list(mj)
 
     def tangent_vmult(self, xs, ys):
-        dt = F64 if xs[0].dtype == torch.float64 else F32
+        xs = self._vectors(xs, "xs", (torch.float64, torch.float32))
+        ys = self._vectors(ys, "ys", (xs[0].dtype,))
+        dt = _DTYPES[xs[0].dtype]
         _check_batch(lib().mfh_batch_tangent_vmult(self.handle, dt, _parr(xs), _parr(ys)), self.handle)
         return ys
 
     def cg_solve(self, bs, xs, rtol=1e-8, max_it=200):
+        bs, xs = self._vectors(bs, "bs"), self._vectors(xs, "xs")
         n = len(bs)
         it = (ctypes.c_int * n)()
         rel = (ctypes.c_double * n)()

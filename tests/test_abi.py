@@ -100,3 +100,87 @@ def test_product_never_imports_the_oracle():
             if f.endswith((".py", ".hip", ".cpp", ".hpp", ".h")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "oracle" not in text.replace("oracle_", ""), f
+
+
+# --- argument checks of the binding (host only: every case is refused before
+# any pointer reaches the library, so no kernel is launched) ---
+
+def _fake_problem(n=81, levels=2):
+    import torch
+    from paper_1904_13131_amd import mfh
+    P = mfh.Problem.__new__(mfh.Problem)
+    P.desc, P._keep = _desc(n_levels=levels)
+    P.device = torch.device("cuda", 0)
+    P.dim, P.n_levels, P.handle = 3, levels, None
+    P.n_dofs = lambda level=-1: n if level % levels == levels - 1 else n // 3
+    return P
+
+
+def test_binding_rejects_bad_vectors():
+    import torch
+    P = _fake_problem()
+    cpu = torch.zeros(81, dtype=torch.float64)
+    with pytest.raises(ValueError, match="device"):
+        P.tangent_vmult(cpu)
+    with pytest.raises(ValueError, match="device"):
+        P.set_deformation(cpu)
+    with pytest.raises(ValueError, match="device"):
+        P.residual(cpu)
+    with pytest.raises(ValueError, match="device"):
+        P.cg_solve(cpu)
+    with pytest.raises(ValueError, match="device"):
+        P.gmg_vcycle(cpu)
+    with pytest.raises(ValueError, match="tensor"):
+        P.tangent_vmult([0.0] * 81)
+
+
+def test_binding_checks_dtype_size_and_layout():
+    import torch
+    from paper_1904_13131_amd import mfh
+    dev = torch.device("cuda", 0)
+    meta = lambda n, dt=torch.float64: torch.empty(n, dtype=dt, device="meta")
+    # _arg itself, on tensors that never hold device memory
+    with pytest.raises(ValueError, match="device"):
+        mfh._arg(meta(81), "x", dev, 81)
+    x = torch.zeros(81, dtype=torch.float64)
+    cpu = torch.device("cpu")
+    mfh._arg(x, "x", cpu, 81)
+    with pytest.raises(ValueError, match="entries"):
+        mfh._arg(x, "x", cpu, 80)
+    with pytest.raises(ValueError, match="dtype"):
+        mfh._arg(x.float(), "x", cpu, 81)
+    with pytest.raises(ValueError, match="contiguous"):
+        mfh._arg(torch.zeros(162, dtype=torch.float64)[::2], "x", cpu, 81)
+    with pytest.raises(ValueError, match="dtype"):
+        mfh._arg(x, "x", cpu, 81, (torch.float32,))
+
+
+def test_binding_checks_levels_faces_and_batches():
+    import torch
+    from paper_1904_13131_amd import mfh
+    P = _fake_problem()
+    P.device = torch.device("cpu")              # lets the checks reach the level and face tests
+    x = torch.zeros(27, dtype=torch.float64)
+    with pytest.raises(ValueError, match="level"):
+        P.prolongate(0, x)
+    with pytest.raises(ValueError, match="level"):
+        P.restrict(2, x)
+    with pytest.raises(ValueError, match="entries"):
+        P.prolongate(1, torch.zeros(81, dtype=torch.float64))
+    with pytest.raises(ValueError, match="faces"):
+        P.apply_dirichlet(torch.zeros(81, dtype=torch.float64), [[0.0, 0.0, 0.0]] * 5)
+    with pytest.raises(ValueError, match="dtype"):        # output dtype must follow the input
+        P.tangent_vmult(torch.zeros(81, dtype=torch.float64), torch.zeros(81, dtype=torch.float32))
+    B = mfh.Batch.__new__(mfh.Batch)
+    B.problems, B.handle = [P, P], None
+    ok = torch.zeros(81, dtype=torch.float64)
+    with pytest.raises(ValueError, match="problems"):
+        B.tangent_vmult([ok], [ok])
+    with pytest.raises(ValueError, match="problems"):
+        B.set_deformation([ok, ok, ok])
+    with pytest.raises(ValueError, match="mixed"):
+        B.tangent_vmult([ok, ok.float()], [ok, ok])
+    with pytest.raises(ValueError, match="dtype"):
+        B.tangent_vmult([ok, ok], [ok.float(), ok.float()])
+    with pytest.raises(ValueError, match="entries"):
+        B.cg_solve([ok, ok], [ok, torch.zeros(80, dtype=torch.float64)])

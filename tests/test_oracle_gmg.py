@@ -208,3 +208,45 @@ def test_chebyshev_coarse_solver():
     b[H.cons[-1]] = 0
     _, it, rel = gmg.pcg(lambda v: H.A[-1] @ v, b, H.vcycle, 1e-8, 200)
     assert rel <= 1e-8
+
+
+def _spd(n, eigs, seed):
+    q, _ = np.linalg.qr(np.random.default_rng(seed).standard_normal((n, n)))
+    return (q * np.asarray(eigs, dtype=np.float64)) @ q.T
+
+
+def test_lanczos_extreme_ritz_values_exact_on_few_eigenvalues():
+    """With k distinct eigenvalues of D^-1 A, k CG steps span the whole Krylov
+    space, so the k Ritz values are those eigenvalues: both the largest
+    (smoother interval) and the smallest (coarse Chebyshev solver) are exact."""
+    n, dist = 24, np.array([0.7, 2.0, 5.5, 13.0])
+    A = _spd(n, np.repeat(dist, n // 4), 1)
+    est, its = gmg.lanczos_lambda_max(lambda v: A @ v, np.ones(n), W.normal_vector(n, 2), 4)
+    assert its == 4
+    assert abs(est - 13.0) <= 1e-11 * 13.0
+    assert abs(gmg.lanczos_lambda_max.last_min - 0.7) <= 1e-11 * 13.0
+
+
+def test_lanczos_smallest_ritz_value_full_run_and_interlacing():
+    """A Jacobi-preconditioned run on a 12 x 12 SPD system with a non-trivial
+    diagonal: 12 steps give the extreme eigenvalues of D^-1/2 A D^-1/2, and
+    shorter runs interlace (smallest Ritz value non-increasing, never below
+    the smallest eigenvalue; largest non-decreasing, never above the largest)."""
+    n = 12
+    B = _spd(n, np.geomspace(0.5, 40.0, n), 3)
+    d = np.geomspace(1.0, 30.0, n)
+    A = np.sqrt(d)[:, None] * B * np.sqrt(d)[None, :]        # D^-1/2 A D^-1/2 = B
+    dinv = 1.0 / A.diagonal()
+    s = np.sqrt(dinv)
+    ev = np.linalg.eigvalsh(s[:, None] * A * s[None, :])
+    r0 = W.normal_vector(n, 4)
+    lo_prev, hi_prev = np.inf, 0.0
+    for it in range(1, n + 1):
+        hi, m = gmg.lanczos_lambda_max(lambda v: A @ v, dinv, r0, it)
+        lo = gmg.lanczos_lambda_max.last_min
+        assert m == it
+        assert lo >= ev[0] * (1 - 1e-10) and hi <= ev[-1] * (1 + 1e-10)
+        assert lo <= lo_prev * (1 + 1e-10) and hi >= hi_prev * (1 - 1e-10)
+        lo_prev, hi_prev = lo, hi
+    assert abs(lo - ev[0]) <= 1e-8 * ev[0]
+    assert abs(hi - ev[-1]) <= 1e-8 * ev[-1]

@@ -227,3 +227,45 @@ def test_mr_homogeneous_deformation_forces(dim, N, p):
     np.testing.assert_allclose(R.T @ X, P, atol=1e-12)
     interior = np.all((X > 1e-12) & (X < 1 - 1e-12), axis=1)
     assert np.abs(R[interior]).max() < 1e-12
+
+
+# --- smallest Jacobian (Sec. 2.1: J = det F > 0 at every quadrature point) ---
+
+def _first_gauss_point(q):
+    """Smallest q-point Gauss-Legendre abscissa on [0, 1], closed forms of the
+    Legendre roots (P_2: 1/sqrt(3); P_3: sqrt(3/5); P_4: sqrt(3/7 + 2/7 sqrt(6/5)))."""
+    t = {2: 1 / np.sqrt(3), 3: np.sqrt(3 / 5), 4: np.sqrt(3 / 7 + 2 / 7 * np.sqrt(6 / 5))}[q]
+    return 0.5 * (1 - t)
+
+
+@pytest.mark.parametrize("dim,N,p", [(2, 3, 1), (3, 2, 2), (2, 2, 3), (3, 2, 1)])
+def test_min_jacobian_affine_is_det_F0(dim, N, p):
+    """u = (F0 - I) X is represented exactly at every degree: every quadrature
+    point carries J = det F0, so the minimum is det F0 (one inverted F0 too)."""
+    m = fe.Mesh(dim, N, p)
+    X = m.node_coords()
+    rng = np.random.default_rng(11)
+    for k in range(3):
+        F0 = np.eye(dim) + 0.3 * rng.standard_normal((dim, dim))
+        if k == 2:
+            F0[0] *= -1                                             # det F0 < 0
+        u = _nodal(m, X @ (F0 - np.eye(dim)).T)
+        assert abs(fe.min_jacobian(m, u) - np.linalg.det(F0)) <= 1e-13
+
+
+@pytest.mark.parametrize("dim,N,p", [(2, 3, 2), (3, 2, 2), (2, 2, 3), (3, 3, 3)])
+def test_min_jacobian_quadratic_field(dim, N, p):
+    """u_x = a x^2, u_y = b y^2 (exact for p >= 2): F = diag(1 + 2ax, 1 + 2by, 1),
+    J = (1 + 2ax)(1 + 2by).  With a, b > 0 the minimum sits at the quadrature
+    point nearest the origin (x = y = h g_0, g_0 the first Gauss abscissa on
+    [0, 1]); with a < 0 < b at the largest x and the smallest y."""
+    m = fe.Mesh(dim, N, p)
+    X = m.node_coords()
+    h, g0 = 1.0 / N, _first_gauss_point(p + 1)
+    lo, hi = h * g0, 1 - h * g0
+    for a, b, xs, ys in [(0.3, 0.2, lo, lo), (-0.35, 0.25, hi, lo)]:
+        f = np.zeros_like(X)
+        f[:, 0] = a * X[:, 0] ** 2
+        f[:, 1] = b * X[:, 1] ** 2
+        want = (1 + 2 * a * xs) * (1 + 2 * b * ys)
+        assert abs(fe.min_jacobian(m, _nodal(m, f)) - want) <= 1e-13
