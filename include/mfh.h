@@ -280,6 +280,7 @@ typedef struct {
   int coarse_negative;       /* negative eigenvalues of the coarse-level tangent          */
   double load_fraction;      /* fraction of the prescribed values this increment reaches  */
   int cutbacks;              /* load-increment halvings so far in the solve               */
+  double step_length;        /* alpha of the accepted update (NaN: none accepted)         */
 } mfh_newton_record;
 
 /* Sets u on constrained DoFs to scale * face_values[2*axis + side][comp]
@@ -293,19 +294,26 @@ mfh_status mfh_apply_dirichlet(mfh_problem* problem, double* u_dev,
  * face_traction (host array of 2*dim*dim doubles, traction vector per face,
  * constant per unit reference area; NULL for none; the Neumann term of
  * Sec. 3, R = F_int(u) - s f_ext with the load fraction s) are applied in
- * n_steps equal increments; the
- * first Newton step of each increment carries it linearly
- * (K_c d = -(R(u) + K(u) dg), u <- u + dg + d), later steps solve
- * K_c du = -R(u).  An increment converges when |du| <= du_tol and
- * |R| <= r_tol or |R| <= r_tol |R0| (R0: first right-hand side of the
- * increment), R on free rows.  An increment fails when an update inverts a
- * quadrature point, when the CG breaks down (p^T K p <= 0: the tangent is
- * indefinite at the iterate) or does not reach cg_rtol in cg_max_it steps, or
- * when max_newton steps do not converge; then u is restored to the start of
- * the increment and the failed increment is halved (at most 8 times in a
- * solve); after a converged cut increment the step doubles again up to
- * 1/n_steps.  The record of a Newton step whose CG broke down carries NaN in
- * cg_relres and residual_after.
+ * n_steps equal increments.  While the prescribed values g of the increment
+ * are not yet met (its first Newton step, and after a shortened step), a
+ * Newton step carries the rest dg = g - u linearly (K_c d = -(R(u) + K(u) dg),
+ * du = dg + d); otherwise it solves K_c du = -R(u).  The update is
+ * u <- u + alpha du with alpha = 1, 1/2, ... (at most 12 halvings), the first
+ * that keeps J > 0 at every quadrature point and, once g is met, lowers
+ * |R|^2 by the factor 1 - 2e-4 alpha; a full step sets the constrained
+ * entries to g exactly.  An increment converges when g is met, |du| <= du_tol
+ * and |R| <= r_tol or |R| <= r_tol |R0| (R0: first right-hand side of the
+ * increment), R on free rows.  An increment fails when the CG breaks down
+ * (p^T K p <= 0: the tangent is indefinite at the iterate; also when a level
+ * tangent stops the smoother's eigenvalue estimate at its first step, or the
+ * coarse tangent is numerically singular) or does not reach
+ * cg_rtol in cg_max_it steps, when no step length is accepted, or when
+ * max_newton steps do not converge; then u is restored to the start of the
+ * increment and the failed increment is halved, at most 8 times in a row
+ * (the count restarts after every converged increment); after a converged
+ * cut increment the step doubles again up to 1/n_steps.  The record of a
+ * Newton step whose update was not taken carries NaN in residual_after and
+ * step_length (and in cg_relres after a CG breakdown).
  * u (device FP64) is the initial state and receives the solution.  Up to
  * max_records records are written to the host array; *n_records receives the
  * number of Newton steps taken.  Synchronises.
@@ -341,6 +349,16 @@ mfh_status mfh_level_displacement(mfh_problem* problem, int level, double* u_dev
 mfh_status mfh_level_diagonal(mfh_problem* problem, int level, double* d_dev);
 /* lambda_max estimate of D^-1 A on `level` >= 1 (host). */
 mfh_status mfh_level_lambda_max(mfh_problem* problem, int level, double* lam_host);
+/* Fixes the eigenvalue estimates of `level` that the smoother (Sec. 7: the
+ * Chebyshev interval [cheb_lo, cheb_hi] * lam_max on levels >= 1) or, on level
+ * 0, the Chebyshev coarse solver ([lam_min, cheb_hi * lam_max]) is built from,
+ * in place of the Lanczos estimates; for comparing smoothers and V-cycles
+ * across implementations on one interval.  lam_max = 0 clears the override
+ * (the next solver call re-estimates).  lam_max must be finite and > 0
+ * otherwise; lam_min is read only on level 0 with the Chebyshev coarse solver
+ * and must then satisfy 0 < lam_min < lam_max (MFH_ERR_INVALID_ARG).  Kept
+ * across set_deformation calls; takes effect at the next solver call. */
+mfh_status mfh_set_level_eigenvalues(mfh_problem* problem, int level, double lam_min, double lam_max);
 /* y_fine = P x_coarse (coarse level = level-1, fine = level, 1 <= level),
  * constrained fine entries zeroed; dtype as for tangent_vmult.  Async. */
 mfh_status mfh_prolongate(mfh_problem* problem, int level, int dtype, const void* x_dev, void* y_dev);

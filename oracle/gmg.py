@@ -131,6 +131,11 @@ def chebyshev(apply_A, dinv, f, x, lo, hi, degree):
     return x
 
 
+class BreakdownError(RuntimeError):
+    """CG met p^T A p <= 0 (the operator is not positive definite) before the
+    eigenvalue estimate had a single step."""
+
+
 def lanczos_lambda_max(apply_A, dinv, r0, iters):
     """Largest eigenvalue of D^-1 A estimated from ``iters`` steps of
     Jacobi-preconditioned CG on A y = r0, through the CG-Lanczos relation
@@ -158,6 +163,8 @@ def lanczos_lambda_max(apply_A, dinv, r0, iters):
         p = z + beta * p
         rz = rz_new
     m = len(alphas)
+    if m == 0:
+        raise BreakdownError("eigenvalue estimate: the first CG step met p^T A p <= 0")
     T = np.zeros((m, m))
     for j in range(m):
         T[j, j] = 1.0 / alphas[j] + (betas[j - 1] / alphas[j - 1] if j > 0 else 0.0)
@@ -245,7 +252,12 @@ class Hierarchy:
                 self.interval.append((self.cheb_lo * lmax, self.cheb_hi * lmax))
         A0 = self.A[0].toarray()
         self.coarse = sla.lu_factor(A0)
-        self.coarse_negative = int((np.linalg.eigvalsh(A0) < 0).sum())
+        self._A0 = A0
+
+    @property
+    def coarse_negative(self):
+        """Number of negative eigenvalues of the coarse tangent (dense eigensolver)."""
+        return int((np.linalg.eigvalsh(self._A0) < 0).sum())
 
     def smooth(self, l, f, x):
         lo, hi = self.interval[l]

@@ -99,6 +99,7 @@ struct Level {
   void *vb = nullptr, *vx = nullptr, *vt = nullptr, *vd = nullptr;   // vcycle dtype
   double lam_max = 0;
   double lam_min = 0;          // coarsest level with the Chebyshev coarse solver
+  double fix_max = 0, fix_min = 0;   // caller-fixed estimates (0: use the Lanczos ones)
   std::vector<double> cd, cr;  // Chebyshev step coefficients
   DevBand P1, R1, I1;          // transfers from level-1 into this level (l >= 1)
 };
@@ -965,6 +966,18 @@ void setup_finish(mfh_problem* P, const double* host) {
     }
     P->eig_ready = true;
   }
+  // caller-fixed estimates replace the Lanczos ones (mfh_set_level_eigenvalues)
+  for (int l = 0; l < nl; ++l) {
+    Level& v = P->lv[l];
+    if (!(v.fix_max > 0)) continue;
+    v.lam_max = v.fix_max;
+    if (l > 0) {
+      set_cheb_coeffs(P, v);
+    } else if (cheb_coarse) {
+      v.lam_min = v.fix_min;
+      set_coarse_chebyshev(P, v);
+    }
+  }
   int flag[2];
   std::memcpy(flag, host + 2 * (size_t)it * nl, sizeof flag);
   P->coarse_negative = cheb_coarse ? 0 : flag[1];
@@ -1392,6 +1405,15 @@ mfh_status mfh_apply_dirichlet(mfh_problem* P, double* u, const double* fv, doub
   });
 }
 
+// Newton globalisation (the paper does not say how it handles failed steps):
+// at most kMaxCut halvings of a load increment in a row, and a step length
+// alpha = 1, 1/2, ... (at most kMaxHalvings halvings) that keeps J > 0 and,
+// once the prescribed values are met, lowers |R|^2 by the Armijo factor
+// 1 - 2 kArmijo alpha.
+constexpr int kMaxCut = 8;
+constexpr int kMaxHalvings = 12;
+constexpr double kArmijo = 1e-4;
+
 mfh_status mfh_newton_solve(mfh_problem* P, double* u, const double* fv, const double* ft, int n_steps,
                             double cg_rtol, int cg_max_it, double du_tol, double r_tol, int max_newton,
                             mfh_newton_record* rec, int max_rec, int* n_rec) {
@@ -1407,44 +1429,55 @@ mfh_status mfh_newton_solve(mfh_problem* P, double* u, const double* fv, const d
     const int top = (int)P->lv.size() - 1;
     const double h0 = 1.0 / n_steps;
     double done = 0.0, h = h0;
-    int step = 0, cutbacks = 0;
-    const int kMaxCut = 8;
+    int step = 0, cut = 0, cutbacks = 0;   // halvings in a row / in the solve
     if (ft) external_force(P, ft, P->f_ext);   // dead tractions scale with the load like fv
+    // R(v) = F_int(v) - s f_ext on free rows (constrained rows zero) into Rv
+    auto eval_residual = [&](const double* w, double* Rv, double sc) {
+      residual(P, w, Rv);
+      if (ft) axpby<double>(Rv, P->f_ext, -sc, 1.0, n, s);
+    };
     while (done < 1.0 - 1e-12) {
       const double target = std::fmin(1.0, done + h);
       ++step;
       HIPCHECK(hipMemcpyAsync(P->nw_save, u, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
-      dirichlet_delta(u, P->nw_dg, v.lt, fv, target, n, s);
       double R0 = -1;
       bool conv = false;
+      bool pending = true;                       // prescribed values of `target` not yet met
       mfh_status fail = MFH_ERR_NOT_CONVERGED;   // why the increment failed
-      bool have_R = false;
+      eval_residual(u, P->nw_R, target);
+      double rn = norm2(P, P->nw_R, n);          // |R(u)| on free rows
       for (int it = 0; it < max_newton; ++it) {
         mfh_newton_record r{};
         r.load_step = step;
         r.newton_iter = it;
         r.load_fraction = target;
         r.cutbacks = cutbacks;
+        r.step_length = NAN;
         auto t0 = Clock::now();
-        if (!have_R) {
-          residual(P, u, P->nw_R);
-          if (ft) axpby<double>(P->nw_R, P->f_ext, -target, 1.0, n, s);   // R = F_int - s f_ext
-        }
-        HIPCHECK(hipStreamSynchronize(s));
-        r.residual_ms = ms_since(t0);
-        t0 = Clock::now();
         mfh_status sd = guarded(P, [&] { r.min_J = set_deformation(P, u); });
         if (sd == MFH_ERR_INVERTED) {
           fail = MFH_ERR_INVERTED;
           break;
         }
         if (sd != MFH_OK) throw Error(sd, P->err);
-        setup_precond(P);
+        // a level tangent too indefinite for the eigenvalue estimate (breakdown
+        // at its first CG step) or a singular coarse tangent fails the increment
+        const mfh_status sp = guarded(P, [&] { setup_precond(P); });
+        if (sp == MFH_ERR_BREAKDOWN || sp == MFH_ERR_NOT_SPD) {
+          r.residual_norm = r.residual_after = r.cg_relres = NAN;
+          r.setup_ms = ms_since(t0);
+          if (rec && nrec < max_rec) rec[nrec] = r;
+          ++nrec;
+          fail = sp;
+          break;
+        }
+        if (sp != MFH_OK) throw Error(sp, P->err);
         r.coarse_negative = P->coarse_negative;
         r.setup_ms = ms_since(t0);
         t0 = Clock::now();
-        if (it == 0) {
-          vmult<double>(P, top, P->nw_dg, P->nw_b, 0);   // (I - C) K dg
+        if (pending) {   // carry the rest of the prescribed values linearly: b = -(R + (I - C) K dg)
+          dirichlet_delta(u, P->nw_dg, v.lt, fv, target, n, s);
+          vmult<double>(P, top, P->nw_dg, P->nw_b, 0);
           lincomb3<double>(P->nw_b, -1.0, P->nw_R, -1.0, P->nw_b, 0.0, nullptr, n, s);
         } else {
           lincomb3<double>(P->nw_b, -1.0, P->nw_R, 0.0, nullptr, 0.0, nullptr, n, s);
@@ -1454,49 +1487,66 @@ mfh_status mfh_newton_solve(mfh_problem* P, double* u, const double* fv, const d
         CgResult cr = cg_solve(P, P->nw_b, P->nw_du, cg_rtol, cg_max_it);
         r.cg_iters = cr.iters;
         r.cg_relres = cr.relres;
-        if (cr.st == MFH_ERR_BREAKDOWN) {   // p^T K p <= 0: the tangent is indefinite at this iterate
-          r.cg_relres = NAN;
-          r.residual_after = NAN;
-          r.solve_ms = ms_since(t0);
+        r.residual_after = NAN;
+        r.solve_ms = ms_since(t0);
+        if (cr.st != MFH_OK) {   // breakdown (p^T K p <= 0: the tangent is indefinite here) or no convergence
+          if (cr.st == MFH_ERR_BREAKDOWN) r.cg_relres = NAN;
           if (rec && nrec < max_rec) rec[nrec] = r;
           ++nrec;
-          fail = MFH_ERR_BREAKDOWN;
+          fail = cr.st;
           break;
         }
-        if (it == 0) axpby<double>(P->nw_du, P->nw_dg, 1.0, 1.0, n, s);
-        axpby<double>(u, P->nw_du, 1.0, 1.0, n, s);
-        r.solve_ms = ms_since(t0);
-        r.du_norm = norm2(P, P->nw_du, n);
+        if (pending) axpby<double>(P->nw_du, P->nw_dg, 1.0, 1.0, n, s);   // du = d + dg
+        // step length: halve until J > 0 everywhere (finite residual) and, with
+        // the prescribed values met, |R|^2 drops by the Armijo factor
         t0 = Clock::now();
-        residual(P, u, P->nw_R);
-        if (ft) axpby<double>(P->nw_R, P->f_ext, -target, 1.0, n, s);
-        have_R = true;
-        r.residual_after = norm2(P, P->nw_R, n);
-        r.residual_ms += ms_since(t0);
+        double alpha = 1.0, rt = NAN;
+        bool accepted = false;
+        for (int k = 0; k <= kMaxHalvings; ++k) {
+          lincomb3<double>(P->nw_b, 1.0, u, alpha, P->nw_du, 0.0, nullptr, n, s);   // trial state
+          if (alpha == 1.0 && pending) set_dirichlet(P->nw_b, v.lt, fv, target, n, s);
+          eval_residual(P->nw_b, P->nw_R, target);
+          rt = norm2(P, P->nw_R, n);
+          if (std::isfinite(rt) && (pending || rt * rt <= (1.0 - 2.0 * kArmijo * alpha) * rn * rn)) {
+            accepted = true;
+            break;
+          }
+          alpha *= 0.5;
+        }
+        r.residual_ms = ms_since(t0);
+        if (!accepted) {   // every trial inverted a quadrature point or failed to lower |R|
+          if (rec && nrec < max_rec) rec[nrec] = r;
+          ++nrec;
+          eval_residual(u, P->nw_R, target);   // keep nw_R = R(u) consistent
+          fail = std::isfinite(rt) ? MFH_ERR_NOT_CONVERGED : MFH_ERR_INVERTED;
+          break;
+        }
+        HIPCHECK(hipMemcpyAsync(u, P->nw_b, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+        rn = rt;
+        pending = pending && alpha < 1.0;
+        r.step_length = alpha;
+        r.du_norm = alpha * norm2(P, P->nw_du, n);
+        r.residual_after = rt;
         if (rec && nrec < max_rec) rec[nrec] = r;
         ++nrec;
-        if (cr.st == MFH_ERR_NOT_CONVERGED) break;   // the linear solve failed: cut the increment back
-        if (!std::isfinite(r.residual_after)) {   // the update inverted a quadrature point
-          fail = MFH_ERR_INVERTED;
-          break;
-        }
-        if (r.du_norm <= du_tol && (r.residual_after <= r_tol || r.residual_after <= r_tol * R0)) {
+        if (!pending && r.du_norm <= du_tol && (rt <= r_tol || rt <= r_tol * R0)) {
           conv = true;
           break;
         }
       }
       if (conv) {
         done = target;
+        cut = 0;
         if (h < h0) h = std::fmin(h0, 2.0 * h);   // grow back after a successful cut increment
         continue;
       }
-      // inverted or not converged: restore the state of the step start and halve the increment
+      // failed: restore the state of the increment's start and halve the increment
       HIPCHECK(hipMemcpyAsync(u, P->nw_save, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
       HIPCHECK(hipStreamSynchronize(s));
-      if (++cutbacks > kMaxCut)
-        throw Error(fail,
-                    std::string("Newton failed after ") + std::to_string(kMaxCut) + " load-step cut-backs at load fraction " +
-                        std::to_string(done));
+      ++cutbacks;
+      if (++cut > kMaxCut)
+        throw Error(fail, std::string("Newton failed after ") + std::to_string(kMaxCut) +
+                              " cut-backs in a row at load fraction " + std::to_string(done));
       h = 0.5 * (target - done);
     }
   });
@@ -1612,6 +1662,23 @@ mfh_status mfh_chebyshev(mfh_problem* P, int level, const void* f, void* x) {
     else
       cheb_apply<double>(P, level, static_cast<const double*>(f), static_cast<double*>(x), false);
     check_launch("chebyshev");
+  });
+}
+
+mfh_status mfh_set_level_eigenvalues(mfh_problem* P, int level, double lam_min, double lam_max) {
+  if (!P) return MFH_ERR_INVALID_ARG;
+  return guarded(P, [&] {
+    need(level >= 0 && level < (int)P->lv.size(), "level out of range");
+    need(lam_max == 0 || (std::isfinite(lam_max) && lam_max > 0), "lam_max must be 0 (clear) or finite and > 0");
+    need(lam_max == 0 || level > 0 || P->d.coarse_solver != MFH_COARSE_CHEBYSHEV ||
+             (lam_min > 0 && lam_min < lam_max),
+         "the Chebyshev coarse solver needs 0 < lam_min < lam_max");
+    Level& v = P->lv[level];
+    v.fix_max = lam_max;
+    v.fix_min = lam_max == 0 ? 0 : lam_min;
+    if (lam_max == 0) P->eig_ready = false;   // back to a fresh Lanczos estimate
+    P->precond_ready = false;   // the next solver call rebuilds the smoother coefficients
+    P->drop_graph();
   });
 }
 

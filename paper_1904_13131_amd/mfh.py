@@ -52,6 +52,7 @@ class NewtonRecord(ctypes.Structure):
         ("du_norm", ctypes.c_double), ("cg_relres", ctypes.c_double), ("min_J", ctypes.c_double),
         ("setup_ms", ctypes.c_double), ("residual_ms", ctypes.c_double), ("solve_ms", ctypes.c_double),
         ("coarse_negative", ctypes.c_int), ("load_fraction", ctypes.c_double), ("cutbacks", ctypes.c_int),
+        ("step_length", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -92,6 +93,7 @@ def lib():
         "mfh_level_displacement": (st, [_P, ctypes.c_int, _P]),
         "mfh_level_diagonal": (st, [_P, ctypes.c_int, _P]),
         "mfh_level_lambda_max": (st, [_P, ctypes.c_int, _D]),
+        "mfh_set_level_eigenvalues": (st, [_P, ctypes.c_int, ctypes.c_double, ctypes.c_double]),
         "mfh_prolongate": (st, [_P, ctypes.c_int, ctypes.c_int, _P, _P]),
         "mfh_restrict": (st, [_P, ctypes.c_int, ctypes.c_int, _P, _P]),
         "mfh_chebyshev": (st, [_P, ctypes.c_int, _P, _P]),
@@ -374,6 +376,12 @@ class Problem:
         if not 1 <= level < self.n_levels:
             raise ValueError(f"level {level}: transfers connect levels 1..{self.n_levels - 1} to the next coarser")
         return level
+
+    def set_level_eigenvalues(self, level, lam_max, lam_min=0.0):
+        """Fixes the eigenvalue estimates a level's smoother (or, on level 0, the
+        Chebyshev coarse solver) is built from; lam_max = 0 clears the override."""
+        _check(lib().mfh_set_level_eigenvalues(self.handle, level % self.n_levels, float(lam_min),
+                                               float(lam_max)), self.handle)
 
     def prolongate(self, level, x, y=None):
         self._transfer_level(level)

@@ -36,5 +36,10 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
+def rel_max(a, b):
+    """Largest entry error against the largest reference entry."""
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
 def log_case(_case, **kw):
     print(f"[case] {_case} " + " ".join(f"{k}={v}" for k, v in kw.items()), flush=True)

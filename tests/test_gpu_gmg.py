@@ -9,7 +9,7 @@ from scipy.optimize import brentq
 import workloads as W
 from oracle import fe, gmg
 from paper_1904_13131_amd import F32, F64, MfhError
-from tests.gpu_helpers import dev, host, log_case, rel_l2, requires_gpu
+from tests.gpu_helpers import dev, host, log_case, rel_l2, rel_max, requires_gpu
 
 pytestmark = [pytest.mark.gpu, requires_gpu]
 
@@ -26,6 +26,23 @@ HIER = {
     "3d_q2_chebcoarse": dict(dim=3, n_coarse=2, degree=2, n_levels=3, spheres=3, amp=0.01, coarse="chebyshev"),
 }
 _CACHE = {}
+# Largest Lanczos Ritz value after 30 FP64 CG steps, device against oracle
+# (measured up to 2e-10 over HIER; the smoother and V-cycle comparisons below
+# take the oracle's estimates instead, through mfh_set_level_eigenvalues).
+LAMBDA_TOL = 1e-9
+# FP32 V-cycle against the FP64 oracle on the same smoother intervals: a
+# linear map evaluated in FP32 (unit roundoff 6e-8) through up to 16 operator
+# applications per level and three levels.
+VCYCLE_F32_TOL = 2e-5
+
+
+def _fix_intervals(P, H):
+    """Hands the oracle's eigenvalue estimates to the device, so that both build
+    their smoothers (and the Chebyshev coarse solver) on the same intervals."""
+    for l in range(1, H.n_levels):
+        P.set_level_eigenvalues(l, H.lam_max[l])
+    if H.coarse_solver == "chebyshev":
+        P.set_level_eigenvalues(0, H.lam_max[0], H.lam_min0)
 
 
 def _setup(name):
@@ -75,7 +92,11 @@ def test_level_data(name):
         assert rel_l2(dg, H.A[l].diagonal()) <= 1e-12
     for l in range(1, c["n_levels"]):
         lam_gpu = P.level_lambda_max(l)
-        assert abs(lam_gpu - H.lam_max[l]) <= 1e-8 * H.lam_max[l]
+        err = abs(lam_gpu - H.lam_max[l]) / H.lam_max[l]
+        print(f"[lambda_max] {name} level {l}: rel err {err:.2e}", flush=True)
+        # 30 CG steps without reorthogonalisation: the two runs' summation
+        # orders differ, and the Ritz value inherits the difference
+        assert err <= LAMBDA_TOL
 
 
 @pytest.mark.parametrize("dtype", [F64, F32], ids=["f64", "f32"])
@@ -102,9 +123,13 @@ def test_transfers(name, dtype):
 
 @pytest.mark.parametrize("name", list(HIER))
 def test_chebyshev_and_vcycle_fp64(name):
+    """On the oracle's smoother intervals the FP64 Chebyshev smoother and the
+    FP64 V-cycle agree with the oracle to rounding (1e-12 relative, and the
+    largest entry error against the largest entry)."""
     log_case("cheb_vcycle_f64", name=name)
     c, mu, lam, incl, mask, H, u, b = _setup(name)
     P = _device(name, F64)
+    _fix_intervals(P, H)
     top = c["n_levels"] - 1
     f = b.copy()
     x0 = W.normal_vector(len(b), 77) * 0.1
@@ -112,16 +137,28 @@ def test_chebyshev_and_vcycle_fp64(name):
     lo, hi = H.interval[top]
     want = gmg.chebyshev(lambda v: H.A[top] @ v, H.dinv[top], f, x0, lo, hi, H.cheb_degree)
     got = host(P.chebyshev(top, dev(f), dev(x0)))
-    assert rel_l2(got, want) <= 1e-7
-    z = host(P.gmg_vcycle(dev(b)))
-    # With the Chebyshev coarse solver the coarse polynomial (degree ~40) is
-    # built on [lambda_min, 1.2 lambda_max] from 30 Lanczos steps; the smallest
-    # Ritz value is far from converged and carries the summation-order
-    # differences of the two runs (and, with the atomic scatter of the small
-    # coarse level, of two device runs), which the polynomial amplifies to
-    # 1e-7..1.4e-6 in the V-cycle output.
-    tol = 1e-5 if c.get("coarse") == "chebyshev" else 1e-7
-    assert rel_l2(z, H.vcycle(b)) <= tol
+    z, zw = host(P.gmg_vcycle(dev(b))), H.vcycle(b)
+    print(f"[cheb_vcycle_f64] {name}: chebyshev rel {rel_l2(got, want):.2e} max {rel_max(got, want):.2e}, "
+          f"vcycle rel {rel_l2(z, zw):.2e} max {rel_max(z, zw):.2e}", flush=True)
+    assert rel_l2(got, want) <= 1e-12 and rel_max(got, want) <= 1e-12
+    assert rel_l2(z, zw) <= 1e-12 and rel_max(z, zw) <= 1e-12
+
+
+@pytest.mark.parametrize("name", list(HIER))
+def test_vcycle_fp64_own_estimates(name):
+    """With its own Lanczos estimates the device V-cycle differs from the
+    oracle's only through the interval: the smoother polynomial is a smooth
+    function of lambda_max, so the V-cycle moves by a modest multiple of the
+    estimate's relative difference (Chebyshev coarse solver: the smallest
+    Ritz value also sets the coarse polynomial's degree-40 interval)."""
+    log_case("vcycle_f64_own", name=name)
+    c, mu, lam, incl, mask, H, u, b = _setup(name)
+    P = _device(name, F64)
+    z, zw = host(P.gmg_vcycle(dev(b))), H.vcycle(b)
+    dl = max(abs(P.level_lambda_max(l) - H.lam_max[l]) / H.lam_max[l] for l in range(1, c["n_levels"]))
+    print(f"[vcycle_f64_own] {name}: lambda rel {dl:.2e}, vcycle rel {rel_l2(z, zw):.2e}", flush=True)
+    factor = 1e5 if c.get("coarse") == "chebyshev" else 1e3
+    assert rel_l2(z, zw) <= max(1e-12, factor * dl)
 
 
 @pytest.mark.parametrize("name", list(HIER))
@@ -129,8 +166,10 @@ def test_vcycle_fp32(name):
     log_case("vcycle_f32", name=name)
     c, mu, lam, incl, mask, H, u, b = _setup(name)
     P = _device(name, F32)
-    z = host(P.gmg_vcycle(dev(b)))
-    assert rel_l2(z, H.vcycle(b)) <= 1e-4
+    _fix_intervals(P, H)
+    z, zw = host(P.gmg_vcycle(dev(b))), H.vcycle(b)
+    print(f"[vcycle_f32] {name}: rel {rel_l2(z, zw):.2e} max {rel_max(z, zw):.2e}", flush=True)
+    assert rel_l2(z, zw) <= VCYCLE_F32_TOL and rel_max(z, zw) <= VCYCLE_F32_TOL
 
 
 @pytest.mark.parametrize("vdt", [F64, F32], ids=["f64", "f32"])
@@ -198,6 +237,62 @@ def test_newton_cutback_matches_oracle(vdt):
     assert max(r["cutbacks"] for r in recs) == max(r["cutbacks"] for r in recs_o) == 2
     assert recs[-1]["load_fraction"] == 1.0
     assert rel_l2(host(u), u_o) <= 1e-7
+
+
+@pytest.mark.parametrize("vdt", [F64, F32], ids=["f64", "f32"])
+def test_newton_step_length_matches_oracle(vdt):
+    """35 % compression in one increment: the first full step inverts a
+    quadrature point, both drivers take alpha = 1/2, carry the rest of the
+    prescribed values in the next step, cut back twice and converge to the
+    same state."""
+    from paper_1904_13131_amd import Problem
+    from oracle import newton
+    log_case("newton_step_length", vcycle=vdt)
+    mu, lam = W.two_phase_material()
+    incl = [(np.array([0.5, 0.5]), 0.3, 1)]
+    mask = W.clamp_bottom_top(2)
+    H = gmg.Hierarchy(2, 2, 2, 3, fe.Material(mu, lam, incl), mask)
+    fv = np.zeros((4, 2))
+    fv[3][1] = -0.35
+    u_o, recs_o = newton.solve(H, fv, n_steps=1)
+    P = Problem(2, 8, 2, n_levels=3, mu=tuple(mu), lam=tuple(lam), inclusions=incl, dirichlet_mask=mask,
+                vcycle_dtype=vdt)
+    u = torch.zeros(P.n_dofs(), dtype=torch.float64, device="cuda")
+    recs, st = P.newton_solve(u, fv, n_steps=1)
+    assert st == 0
+    assert recs[0]["step_length"] == recs_o[0]["alpha"] == 0.5
+    assert max(r["cutbacks"] for r in recs) == max(r["cutbacks"] for r in recs_o)
+    assert recs[-1]["load_fraction"] == 1.0
+    if vdt == F64:
+        assert len(recs) == len(recs_o)
+    assert rel_l2(host(u), u_o) <= 1e-8
+
+
+def test_newton_q4_200_spheres_coarsest_level_matches_oracle():
+    """The Q4 body of 200 spheres (seed 7) at its coarsest resolution (3^3
+    cells, one level: the preconditioner is the exact coarse solve), clamped
+    and compressed 20 % in 5 load steps (Sec. 7 load stepping): every load
+    step converges on both sides with the same Newton steps, to the same
+    state."""
+    from paper_1904_13131_amd import Problem
+    from oracle import newton
+    log_case("newton_q4_200_spheres_3cube")
+    mu, lam = W.two_phase_material()
+    incl = W.spheres(200, 7, 3)
+    mask = W.clamp_bottom_top(3)
+    H = gmg.Hierarchy(3, 3, 4, 1, fe.Material(mu, lam, incl), mask)
+    fv = np.zeros((6, 3))
+    fv[5][2] = -0.2
+    u_o, recs_o = newton.solve(H, fv, n_steps=5)
+    P = Problem(3, 3, 4, n_levels=1, mu=tuple(mu), lam=tuple(lam), inclusions=incl, dirichlet_mask=mask,
+                vcycle_dtype=F64, qp_policy=2)
+    u = torch.zeros(P.n_dofs(), dtype=torch.float64, device="cuda")
+    recs, st = P.newton_solve(u, fv, n_steps=5)
+    assert st == 0
+    assert [r["load_fraction"] for r in recs] == [r["load_fraction"] for r in recs_o]
+    assert all(r["step_length"] == 1.0 for r in recs)
+    assert rel_l2(host(u), u_o) <= 1e-10
+    assert abs(recs[-1]["min_J"] - fe.min_jacobian(H.meshes[-1], H.us[-1])) <= 1e-8
 
 
 def test_coarse_inertia_matches_oracle():
@@ -369,10 +464,13 @@ def test_smoother_fused_with_element_node_sums(name):
     f = b.copy()
     x0 = W.normal_vector(len(b), 78) * 0.1
     x0[H.cons[-1]] = 0.0
+    _fix_intervals(P, H)
     lo, hi = H.interval[top]
     want = gmg.chebyshev(lambda v: H.A[top] @ v, H.dinv[top], f, x0, lo, hi, H.cheb_degree)
-    assert rel_l2(host(P.chebyshev(top, dev(f), dev(x0))), want) <= 1e-7
-    assert rel_l2(host(P.gmg_vcycle(dev(b))), H.vcycle(b)) <= 1e-7
+    got = host(P.chebyshev(top, dev(f), dev(x0)))
+    assert rel_l2(got, want) <= 1e-12 and rel_max(got, want) <= 1e-12
+    z, zw = host(P.gmg_vcycle(dev(b))), H.vcycle(b)
+    assert rel_l2(z, zw) <= 1e-12 and rel_max(z, zw) <= 1e-12
     Q = _device(name, F32, scatter=3)
     x, it, rel, _ = Q.cg_solve(dev(b), rtol=1e-8, max_it=200)
     assert rel <= 1e-8

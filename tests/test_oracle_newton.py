@@ -55,6 +55,28 @@ def test_cutback_reaches_the_same_equilibrium():
     assert np.linalg.norm(u1 - u4) <= 1e-10 * np.linalg.norm(u4)
 
 
+def test_shortened_step_reaches_the_same_equilibrium():
+    """The same body compressed 35 % in one increment: the full first step
+    inverts a quadrature point, so the step length halves (alpha = 1/2) and
+    the next step carries the rest of the prescribed values; after cut-backs
+    the converged state is the one seven uncut increments reach.  A wrong
+    remainder of the prescribed values would leave the top face short of
+    -0.35; a shortened step that skipped the J > 0 test would stop at NaN."""
+    mu, lam = W.two_phase_material()
+    mat = fe.Material(mu, lam, [(np.array([0.5, 0.5]), 0.3, 1)])
+    H = gmg.Hierarchy(2, 2, 2, 3, mat, W.clamp_bottom_top(2))
+    fv = np.zeros((4, 2))
+    fv[3][1] = -0.35
+    u1, r1 = newton.solve(H, fv, n_steps=1)
+    u7, r7 = newton.solve(H, fv, n_steps=7)
+    assert r1[0]["alpha"] == 0.5 and np.isfinite(r1[0]["res_after"])
+    assert all(r["alpha"] == 1.0 for r in r7)
+    assert r1[-1]["load_fraction"] == 1.0
+    top = H.meshes[-1].n_nodes + np.arange(H.meshes[-1].L ** 2 - H.meshes[-1].L, H.meshes[-1].L ** 2)
+    assert np.all(u1[top] == -0.35)
+    assert np.linalg.norm(u1 - u7) <= 1e-10 * np.linalg.norm(u7)
+
+
 @pytest.mark.parametrize("dim,p", [(3, 2), (2, 3), (3, 1)])
 def test_external_force_totals(dim, p):
     """The nodal forces of a constant traction on a unit face sum to the
