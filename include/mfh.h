@@ -368,6 +368,25 @@ mfh_status mfh_restrict(mfh_problem* problem, int level, int dtype, const void* 
  * V-cycle's precision (vcycle_dtype): x <- x + p(D^-1 A)(D^-1 (f - A x)).  Async. */
 mfh_status mfh_chebyshev(mfh_problem* problem, int level, const void* f_dev, void* x_dev);
 
+/* The coarse level's dense direct solver (the exact FP64 coarse solve that
+ * replaces the paper's Chebyshev coarse iteration, Sec. 7) on a caller's
+ * matrix: symmetric block Gauss-Jordan with symmetric pivoting (each block of
+ * 64 takes the unswept indices of largest |diagonal| of the current Schur
+ * complement and is inverted with Bunch-Kaufman 1x1/2x2 pivots), for any
+ * nonsingular symmetric matrix, definite or not.
+ * a_dev: n x n FP64 row-major symmetric matrix (device), overwritten by the
+ * inverse in the pivoted basis; inv_dev: receives A^-1 in the original order
+ * (device, n x n, must not overlap a_dev); work_dev: at least
+ * mfh_dense_inverse_workspace(n) bytes of device memory, 256-byte aligned;
+ * stream: HIP stream (NULL: default).  *negative receives the number of
+ * negative eigenvalues of A (Sylvester: signs of the 1x1 and 2x2 pivots).
+ * 1 <= n <= 20000.  Synchronises.  Errors: INVALID_ARG, WORKSPACE, NOT_SPD
+ * (numerically singular: a pivot, or a 2x2 pivot's determinant against its
+ * largest entry, at most 1e-12 max |A_ii| or not finite), HIP. */
+mfh_status mfh_dense_inverse_workspace(long long n, size_t* bytes);
+mfh_status mfh_dense_inverse(double* a_dev, double* inv_dev, long long n, void* work_dev, size_t work_bytes,
+                             void* stream, int* negative);
+
 /* Number of negative eigenvalues of the coarse-level tangent about the current
  * linearisation point (the signs of its elimination pivots).  The V-cycle's
  * coarse solve is exact for any nonsingular coarse tangent; a nonzero count

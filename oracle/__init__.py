@@ -26,8 +26,11 @@ fe        structured Q_p lattice on the unit box, per-quadrature-point
           material ids, element residual and tangent, global CSR assembly,
           Dirichlet handling, sampled rows (Sec. 3, eq. mf_vmult in Sec. 5).
 gmg       transfers, diagonal, Chebyshev smoother, Lanczos eigenvalue
-          estimate, coarse Cholesky, V-cycle, PCG (Sec. 6 and Sec. 7).
-newton    Newton-Raphson load-stepping driver (Sec. 3, Sec. 7).
+          estimate, coarse LU solve, V-cycle, PCG (Sec. 6 and Sec. 7).
+newton    Newton-Raphson load-stepping driver with cut-backs and a step
+          length that keeps J > 0 (Sec. 3, Sec. 7).
+spmv      OpenMP CSR product of the assembled tangent on all host cores
+          (spmv.c, built by ``build()``): the matrix-based CPU baseline.
 rng       the counter-based generator (SplitMix64) that both sides implement
           independently for the eigenvalue-estimate start vector.
 """

@@ -130,6 +130,9 @@ struct mfh_problem {
   long long nf = 0;
   int* fmap = nullptr;               // dof -> free index or -1
   int* dof_of = nullptr;             // free index -> dof
+  int* dof_perm = nullptr;           // position in the pivoted coarse inverse -> dof
+  int* gj_sw = nullptr;              // exchange pairs of a block step
+  double* gj_key = nullptr;          // |diagonal| of the unswept positions
   double* Kinv = nullptr;
   double *gj_P = nullptr, *gj_C = nullptr, *gj_R = nullptr, *crf = nullptr, *czf = nullptr;
   int* flag = nullptr;
@@ -220,6 +223,8 @@ void validate(const mfh_desc* d) {
 // Largest coarse level that gets the dense FP64 direct solve; problems with a
 // larger coarsest level support operator application but no V-cycle / CG.
 constexpr long long kMaxCoarseDofs = 20000;
+static_assert(kMaxCoarseDofs <= kGJMaxFree, "the pivoted coarse inverse holds at most kGJMaxFree free DoFs");
+constexpr double kSingularTol = 1e-12;   // |pivot| <= kSingularTol * max |A_ii|: numerically singular
 
 // Host-side level geometry, transfer tables and coarse-level maps.
 void build_host(mfh_problem* P) {
@@ -375,6 +380,9 @@ size_t layout(mfh_problem* P, char* base) {
   const Level& c = P->lv[0];
   P->fmap = b.take<int>(P->has_coarse ? c.ndofs : 1);
   P->dof_of = b.take<int>(std::max<long long>(1, P->nf));
+  P->dof_perm = b.take<int>(std::max<long long>(1, P->nf));
+  P->gj_sw = b.take<int>(1 + 2 * 64);
+  P->gj_key = b.take<double>(std::max<long long>(1, P->nf));
   P->Kinv = b.take<double>((size_t)P->nf * P->nf);
   P->gj_P = b.take<double>(64 * 64);
   P->gj_C = b.take<double>((size_t)P->nf * 64);
@@ -664,7 +672,7 @@ void coarse_solve(mfh_problem* P, const T* b, T* x) {
     return;
   }
   fill<T>(x, T(0), n, P->stream);
-  if (P->nf) coarse_apply<T>(P->Kinv, P->nf, P->dof_of, b, P->crf, P->czf, x, P->stream);
+  if (P->nf) coarse_apply<T>(P->Kinv, P->nf, P->dof_perm, b, P->crf, P->czf, x, P->stream);
 }
 
 template <typename T>
@@ -930,14 +938,9 @@ void setup_enqueue(mfh_problem* P) {
     fill<double>(P->Kinv, 0.0, nf * nf, s);
     CellArgs<double> a = cell_args<double>(P, c, c.u64, nullptr, nullptr, nullptr);
     P->ops->coarse_assemble(a, P->fmap, nf, P->Kinv, (unsigned)c.ncells, s);
-    diag_absmax(P->Kinv, nf, P->sc + SC_TMP, s);
-    for (long long k0 = 0; k0 < nf; k0 += 64) {
-      const int nb = (int)std::min<long long>(64, nf - k0);
-      gj_pivot(P->Kinv, nf, k0, nb, P->gj_P, P->flag, P->sc + SC_TMP, 1e-12, s);
-      gj_panels(P->Kinv, nf, k0, nb, P->gj_P, P->gj_C, P->gj_R, s);
-      gj_update(P->Kinv, nf, k0, nb, P->gj_C, P->gj_R, s);
-      gj_finish(P->Kinv, nf, k0, nb, P->gj_C, P->gj_R, P->gj_P, s);
-    }
+    HIPCHECK(hipMemcpyAsync(P->dof_perm, P->dof_of, sizeof(int) * nf, hipMemcpyDeviceToDevice, s));
+    const DenseInvWork w{P->gj_P, P->gj_C, P->gj_R, P->gj_key, P->sc + SC_TMP, P->gj_sw, P->flag};
+    dense_inverse(P->Kinv, nf, P->dof_perm, w, kSingularTol, s);
   }
   check_launch("coarse inverse");
 }
@@ -1679,6 +1682,59 @@ mfh_status mfh_set_level_eigenvalues(mfh_problem* P, int level, double lam_min, 
     if (lam_max == 0) P->eig_ready = false;   // back to a fresh Lanczos estimate
     P->precond_ready = false;   // the next solver call rebuilds the smoother coefficients
     P->drop_graph();
+  });
+}
+
+namespace {
+// Layout of the dense-inverse workspace: Pinv, C, R, key, scale (doubles), then
+// perm, sw, flag (ints), each slot 256-byte aligned.
+size_t dense_inverse_layout(long long n, char* base, mfh::DenseInvWork* w, int** perm) {
+  mfh::Bump b;
+  b.base = base;
+  double* Pinv = b.take<double>(64 * 64);
+  double* C = b.take<double>((size_t)n * 64);
+  double* R = b.take<double>((size_t)n * 64);
+  double* key = b.take<double>((size_t)n);
+  double* scale = b.take<double>(1);
+  int* pm = b.take<int>((size_t)n);
+  int* sw = b.take<int>(1 + 2 * 64);
+  int* flag = b.take<int>(2);
+  if (w) *w = mfh::DenseInvWork{Pinv, C, R, key, scale, sw, flag};
+  if (perm) *perm = pm;
+  return b.off + 256;
+}
+}  // namespace
+
+mfh_status mfh_dense_inverse_workspace(long long n, size_t* bytes) {
+  return guarded(nullptr, [&] {
+    need(bytes != nullptr, "bytes is NULL");
+    need(n >= 1 && n <= mfh::kMaxCoarseDofs, "n must be 1..20000");
+    *bytes = dense_inverse_layout(n, nullptr, nullptr, nullptr);
+  });
+}
+
+mfh_status mfh_dense_inverse(double* a, double* inv, long long n, void* work, size_t work_bytes, void* stream,
+                             int* negative) {
+  return guarded(nullptr, [&] {
+    need(a && inv && work && negative, "NULL argument");
+    need(n >= 1 && n <= mfh::kMaxCoarseDofs, "n must be 1..20000");
+    need(a + n * n <= inv || inv + n * n <= a, "a and inv must not overlap");
+    need(((uintptr_t)work & 255) == 0, "work must be 256-byte aligned");
+    if (work_bytes < dense_inverse_layout(n, nullptr, nullptr, nullptr))
+      throw Error(MFH_ERR_WORKSPACE, "work smaller than mfh_dense_inverse_workspace reports");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    mfh::DenseInvWork w{};
+    int* perm = nullptr;
+    dense_inverse_layout(n, static_cast<char*>(work), &w, &perm);
+    mfh::fill<int>(w.flag, 0, 2, s);
+    mfh::iota(perm, n, s);
+    mfh::dense_inverse(a, n, perm, w, mfh::kSingularTol, s);
+    mfh::unpermute(a, perm, n, inv, s);
+    int flag[2];
+    HIPCHECK(hipMemcpyAsync(flag, w.flag, sizeof flag, hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    *negative = flag[1];
+    if (flag[0]) throw Error(MFH_ERR_NOT_SPD, "matrix is numerically singular");
   });
 }
 

@@ -412,45 +412,251 @@ __global__ void k_material_bits(uint32_t* __restrict__ bits, long long ncells, i
 
 constexpr int kGJ = 64;
 
-// Inverts the pivot block in LDS by Gauss-Jordan without pivoting.  The
-// pivots are those of a symmetric LDL^T elimination, so their signs give the
-// inertia: flag[1] counts negative pivots; flag[0] is set when a pivot is not
-// finite or |p| <= tol * scale[0] (numerically singular).
+// Coarse inverse by symmetric block Gauss-Jordan with pivoting.  Before each
+// block step the nb unswept positions with the largest |diagonal| (the
+// diagonal of the current Schur complement: the update kernels keep every
+// unswept entry current) are moved into the block window [k0, k0 + nb) by a
+// symmetric exchange of rows and columns (the free-DoF permutation follows);
+// the block itself is inverted in LDS with Bunch-Kaufman pivoting (1x1 and
+// 2x2 pivots chosen within the block).  Sweeps commute, so the result is the
+// inverse in the permuted basis, and the pivots are those of a symmetric
+// block LDL^T elimination, whose signs give the inertia (Sylvester).
+
+// Wave-wide argmax of (v, i) over 64 lanes (larger v, then smaller i wins).
+__device__ __forceinline__ void wave_argmax(double& v, int& i) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ov = __shfl_xor(v, off);
+    const int oi = __shfl_xor(i, off);
+    if (ov > v || (ov == v && oi < i)) {
+      v = ov;
+      i = oi;
+    }
+  }
+}
+
+// key[t] = |A[k0 + t][k0 + t]| for the m = n - k0 unswept positions (+inf
+// for a non-finite entry, so that it is chosen and flagged at once).
+__global__ void k_gj_keys(const double* __restrict__ A, long long n, long long k0, double* __restrict__ key) {
+  const long long m = n - k0;
+  for (long long t = blockIdx.x * (long long)kVB + threadIdx.x; t < m; t += (long long)gridDim.x * kVB) {
+    const double d = A[(k0 + t) * n + k0 + t];
+    key[t] = isfinite(d) ? fabs(d) : INFINITY;
+  }
+}
+
+// Chooses the nb largest keys (ties: smaller position) and pairs the window
+// positions that were not chosen with the chosen positions outside the window:
+// sw[0] = number of pairs q, sw[1 + i] = window position, sw[1 + kGJ + i] =
+// outside position (absolute indices).  One workgroup of kVB threads; chosen
+// positions are marked in an LDS bitmap (m = n - k0 <= kGJMaxFree).
+__global__ void __launch_bounds__(kVB) k_gj_select(const double* __restrict__ key, long long n, long long k0, int nb,
+                                                   int* __restrict__ sw) {
+  __shared__ double wv[kVB / 64];
+  __shared__ int wi[kVB / 64];
+  __shared__ int chosen[kGJ];
+  __shared__ unsigned taken[kGJMaxFree / 32];
+  const int t = threadIdx.x;
+  const int m = (int)(n - k0);
+  for (int w = t; w < (m + 31) / 32; w += kVB) taken[w] = 0u;
+  __syncthreads();
+  for (int s = 0; s < nb; ++s) {
+    double bv = -1.0;
+    int bi = 0x7fffffff;
+    for (int i = t; i < m; i += kVB) {
+      const double v = (taken[i >> 5] >> (i & 31)) & 1u ? -1.0 : key[i];
+      if (v > bv) {   // increasing i: ties keep the smaller position
+        bv = v;
+        bi = i;
+      }
+    }
+    wave_argmax(bv, bi);
+    if ((t & 63) == 0) {
+      wv[t >> 6] = bv;
+      wi[t >> 6] = bi;
+    }
+    __syncthreads();
+    if (t == 0) {
+      for (int w = 1; w < kVB / 64; ++w)
+        if (wv[w] > bv || (wv[w] == bv && wi[w] < bi)) {
+          bv = wv[w];
+          bi = wi[w];
+        }
+      chosen[s] = bi;   // m > nb untaken keys are >= 0, so one is always found
+      taken[bi >> 5] |= 1u << (bi & 31);
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    bool in_window[kGJ];
+    for (int w = 0; w < nb; ++w) in_window[w] = false;
+    int q = 0;
+    for (int s = 0; s < nb; ++s) {
+      if (chosen[s] < nb)
+        in_window[chosen[s]] = true;
+      else
+        sw[1 + kGJ + q++] = (int)(k0 + chosen[s]);
+    }
+    int w2 = 0;
+    for (int w = 0; w < nb; ++w)
+      if (!in_window[w]) sw[1 + w2++] = (int)(k0 + w);
+    sw[0] = q;   // q == w2
+  }
+}
+
+// Symmetric exchange of the pairs of sw: rows first (this kernel), then
+// columns and the permutation (k_gj_swap_cols), as two launches.
+__global__ void k_gj_swap_rows(double* __restrict__ A, long long n, const int* __restrict__ sw) {
+  const int q = sw[0];
+  const long long total = (long long)q * n;
+  for (long long g = blockIdx.x * (long long)kVB + threadIdx.x; g < total; g += (long long)gridDim.x * kVB) {
+    const int pr = (int)(g / n);
+    const long long j = g - (long long)pr * n;
+    double* ra = A + (long long)sw[1 + pr] * n + j;
+    double* rb = A + (long long)sw[1 + kGJ + pr] * n + j;
+    const double va = *ra, vb = *rb;
+    *ra = vb;
+    *rb = va;
+  }
+}
+
+__global__ void k_gj_swap_cols(double* __restrict__ A, long long n, const int* __restrict__ sw, int* __restrict__ perm) {
+  const int q = sw[0];
+  const long long total = (long long)q * n;
+  for (long long g = blockIdx.x * (long long)kVB + threadIdx.x; g < total; g += (long long)gridDim.x * kVB) {
+    const long long i = g / q;
+    const int pr = (int)(g - i * q);
+    const int ca = sw[1 + pr], cb = sw[1 + kGJ + pr];
+    double* ea = A + i * n + ca;
+    double* eb = A + i * n + cb;
+    const double va = *ea, vb = *eb;
+    *ea = vb;
+    *eb = va;
+    if (i == 0) {
+      const int pa = perm[ca];
+      perm[ca] = perm[cb];
+      perm[cb] = pa;
+    }
+  }
+}
+
+// Inverts the symmetric pivot block [k0, k0 + nb) in LDS by Gauss-Jordan
+// sweeps in Bunch-Kaufman order: among the block's unswept indices take k with
+// the largest |M_kk| and lambda = max |M_ik| (i unswept, row r); sweep k alone
+// when |M_kk| >= alpha lambda or |M_kk| sigma >= alpha lambda^2 (sigma = max
+// |M_ir| over unswept i != r), r alone when |M_rr| >= alpha sigma, else the
+// 2x2 block {k, r} (alpha = (1 + sqrt 17) / 8).  flag[1] accumulates the
+// negative eigenvalues of the pivots; flag[0] is set when a pivot (or a 2x2
+// determinant against its largest entry) is not finite or at most tol *
+// scale[0] in magnitude (numerically singular).
 __global__ void __launch_bounds__(256) k_gj_pivot(double* __restrict__ A, long long n, long long k0, int nb,
                                                   double* __restrict__ Pinv, int* flag, const double* scale,
                                                   double tol) {
   __shared__ double M[kGJ][kGJ + 1];
-  __shared__ double colk[kGJ], rowk[kGJ];
+  __shared__ double colk[kGJ], rowk[kGJ], colr[kGJ], rowr[kGJ];
+  __shared__ int done[kGJ];
+  __shared__ int sel[2];
   // thread t owns column j = t % kGJ of rows t / kGJ + 4 r (256 threads)
   constexpr int kRows = 256 / kGJ;
+  const double alpha = 0.6403882032022076;   // (1 + sqrt(17)) / 8
   const int t = threadIdx.x;
   const int j = t % kGJ, i0 = t / kGJ;
   const double thr = tol * scale[0];
   if (j < nb)
     for (int i = i0; i < nb; i += kRows) M[i][j] = A[(k0 + i) * n + k0 + j];
+  if (t < kGJ) done[t] = 0;
   __syncthreads();
-  bool bad = false;   // pivot checks in registers, written once at the end
+  bool bad = false;   // pivot checks of thread 0, written once at the end
   int neg = 0;
-  for (int k = 0; k < nb; ++k) {
-    if (t < nb) {
-      colk[t] = M[t][k];
-      rowk[t] = M[k][t];
+  for (int swept = 0; swept < nb;) {
+    if (t < 64) {   // pivot choice by the first wave (lane = block index)
+      const bool cand = t < nb && !done[t];
+      auto mag = [](double x) { return isfinite(x) ? fabs(x) : INFINITY; };   // non-finite: chosen, then flagged
+      double v = cand ? mag(M[t][t]) : -1.0;
+      int k = t;
+      wave_argmax(v, k);
+      const double akk = v;
+      double lv = (cand && t != k) ? mag(M[t][k]) : -1.0;
+      int r = t;
+      wave_argmax(lv, r);
+      int pk = k, pr = -1;
+      if (lv > 0.0 && akk < alpha * lv) {
+        double sv = (cand && t != r) ? mag(M[t][r]) : -1.0;
+        int ri = t;
+        wave_argmax(sv, ri);
+        if (akk * sv >= alpha * lv * lv) {
+          pk = k;
+        } else if (mag(M[r][r]) >= alpha * sv) {
+          pk = r;
+        } else {
+          pk = k;
+          pr = r;
+        }
+      }
+      if (t == 0) {
+        sel[0] = pk;
+        sel[1] = pr;
+      }
     }
     __syncthreads();
-    const double p = rowk[k];
-    bad = bad || !(fabs(p) > thr) || !isfinite(p);
-    neg += p < 0.0 ? 1 : 0;
-    const double pinv = 1.0 / p;
-    if (j < nb) {
-      const double rj = rowk[j] * pinv;
-      for (int i = i0; i < nb; i += kRows) {
-        if (i == k)
-          M[i][j] = j == k ? pinv : rj;
-        else if (j == k)
-          M[i][j] = -colk[i] * pinv;
-        else
-          M[i][j] -= colk[i] * rj;
+    const int k = sel[0], r = sel[1];
+    if (r < 0) {   // 1x1 pivot
+      if (t < nb) {
+        colk[t] = M[t][k];
+        rowk[t] = M[k][t];
       }
+      __syncthreads();
+      const double p = rowk[k];
+      if (t == 0) {
+        bad = bad || !(fabs(p) > thr) || !isfinite(p);
+        neg += p < 0.0 ? 1 : 0;
+        done[k] = 1;
+      }
+      const double pinv = 1.0 / p;
+      if (j < nb) {
+        const double rj = rowk[j] * pinv;
+        for (int i = i0; i < nb; i += kRows) {
+          if (i == k)
+            M[i][j] = j == k ? pinv : rj;
+          else if (j == k)
+            M[i][j] = -colk[i] * pinv;
+          else
+            M[i][j] -= colk[i] * rj;
+        }
+      }
+      swept += 1;
+    } else {   // 2x2 pivot {k, r}: E = [[a, b], [b, c]]
+      if (t < nb) {
+        colk[t] = M[t][k];
+        rowk[t] = M[k][t];
+        colr[t] = M[t][r];
+        rowr[t] = M[r][t];
+      }
+      __syncthreads();
+      const double a = rowk[k], b = rowk[r], c = rowr[r];
+      const double det = a * c - b * b;
+      if (t == 0) {
+        bad = bad || !(fabs(det) > thr * fmax(fabs(b), fmax(fabs(a), fabs(c)))) || !isfinite(det);
+        neg += det < 0.0 ? 1 : (a + c < 0.0 ? 2 : 0);
+        done[k] = 1;
+        done[r] = 1;
+      }
+      const double e00 = c / det, e01 = -b / det, e11 = a / det;   // E^-1
+      if (j < nb) {
+        const bool jb = j == k || j == r;
+        const double rk = e00 * rowk[j] + e01 * rowr[j];   // (E^-1 M_Bj)_k
+        const double rr = e01 * rowk[j] + e11 * rowr[j];   // (E^-1 M_Bj)_r
+        const double ek = j == k ? e00 : e01, er = j == k ? e01 : e11;   // column j of E^-1
+        for (int i = i0; i < nb; i += kRows) {
+          if (i == k || i == r)
+            M[i][j] = jb ? (i == k ? ek : er) : (i == k ? rk : rr);
+          else if (jb)
+            M[i][j] = -(colk[i] * ek + colr[i] * er);
+          else
+            M[i][j] -= colk[i] * rk + colr[i] * rr;
+        }
+      }
+      swept += 2;
     }
     __syncthreads();
   }
@@ -719,6 +925,13 @@ void material_bits(uint32_t* bits, long long ncells, int N, int dim, int n1, con
                      h, incl, nincl, nwords);
 }
 
+void gj_choose_block(double* A, long long n, long long k0, int nb, double* key, int* sw, int* perm, hipStream_t s) {
+  if (n - k0 <= nb) return;   // the window already holds every unswept position
+  hipLaunchKernelGGL(k_gj_keys, dim3(grid_for(n - k0)), dim3(kVB), 0, s, A, n, k0, key);
+  hipLaunchKernelGGL(k_gj_select, dim3(1), dim3(kVB), 0, s, key, n, k0, nb, sw);
+  hipLaunchKernelGGL(k_gj_swap_rows, dim3(grid_for((long long)kGJ * n)), dim3(kVB), 0, s, A, n, sw);
+  hipLaunchKernelGGL(k_gj_swap_cols, dim3(grid_for((long long)kGJ * n)), dim3(kVB), 0, s, A, n, sw, perm);
+}
 void gj_pivot(double* A, long long n, long long k0, int nb, double* Pinv, int* flag, const double* scale, double tol,
               hipStream_t s) {
   hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(256), 0, s, A, n, k0, nb, Pinv, flag, scale, tol);
@@ -740,6 +953,32 @@ void gj_finish(double* A, long long n, long long k0, int nb, const double* Cb, c
   hipLaunchKernelGGL(k_gj_fincol, dim3(grid_for((long long)nb * n)), dim3(kVB), 0, s, A, n, k0, nb, Cb, Pinv);
   hipLaunchKernelGGL(k_gj_finrow, dim3(grid_for((long long)nb * n)), dim3(kVB), 0, s, A, n, k0, nb, R);
 }
+void dense_inverse(double* A, long long n, int* perm, const DenseInvWork& w, double tol, hipStream_t s) {
+  diag_absmax(A, n, w.scale, s);
+  for (long long k0 = 0; k0 < n; k0 += kGJ) {
+    const int nb = (int)std::min<long long>(kGJ, n - k0);
+    gj_choose_block(A, n, k0, nb, w.key, w.sw, perm, s);
+    gj_pivot(A, n, k0, nb, w.Pinv, w.flag, w.scale, tol, s);
+    gj_panels(A, n, k0, nb, w.Pinv, w.C, w.R, s);
+    gj_update(A, n, k0, nb, w.C, w.R, s);
+    gj_finish(A, n, k0, nb, w.C, w.R, w.Pinv, s);
+  }
+}
+__global__ void k_unpermute(const double* __restrict__ A, const int* __restrict__ perm, long long n,
+                            double* __restrict__ out) {
+  const long long total = n * n;
+  for (long long g = blockIdx.x * (long long)kVB + threadIdx.x; g < total; g += (long long)gridDim.x * kVB) {
+    const long long i = g / n, j = g - i * n;
+    out[(long long)perm[i] * n + perm[j]] = A[g];
+  }
+}
+void unpermute(const double* A, const int* perm, long long n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_unpermute, dim3(grid_for(n * n)), dim3(kVB), 0, s, A, perm, n, out);
+}
+__global__ void k_iota(int* __restrict__ v, long long n) {
+  for (long long g = blockIdx.x * (long long)kVB + threadIdx.x; g < n; g += (long long)gridDim.x * kVB) v[g] = (int)g;
+}
+void iota(int* v, long long n, hipStream_t s) { hipLaunchKernelGGL(k_iota, dim3(grid_for(n)), dim3(kVB), 0, s, v, n); }
 template <typename T>
 void coarse_apply(const double* Kinv, long long nf, const int* dof_of, const T* r, double* rf, double* zf, T* z,
                   hipStream_t s) {

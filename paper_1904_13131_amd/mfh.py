@@ -98,6 +98,8 @@ def lib():
         "mfh_restrict": (st, [_P, ctypes.c_int, ctypes.c_int, _P, _P]),
         "mfh_chebyshev": (st, [_P, ctypes.c_int, _P, _P]),
         "mfh_coarse_inertia": (st, [_P, ctypes.POINTER(ctypes.c_int)]),
+        "mfh_dense_inverse_workspace": (st, [ctypes.c_longlong, ctypes.POINTER(ctypes.c_size_t)]),
+        "mfh_dense_inverse": (st, [_P, _P, ctypes.c_longlong, _P, ctypes.c_size_t, _P, ctypes.POINTER(ctypes.c_int)]),
         "mfh_enable_graphs": (st, [_P, ctypes.c_int]),
         "mfh_batch_workspace_size": (st, [ctypes.c_int, ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_size_t)]),
         "mfh_batch_create": (st, [ctypes.c_int, ctypes.POINTER(_P), _P, ctypes.c_size_t, _P,
@@ -423,6 +425,29 @@ class Problem:
         _arg(x, "x", self.device, self.n_dofs(level), (dt,))
         _check(lib().mfh_chebyshev(self.handle, level, _ptr(f), _ptr(x)), self.handle)
         return x
+
+
+def dense_inverse(a, stream=None):
+    """The coarse level's pivoted dense inverse on a symmetric FP64 device
+    matrix: returns (A^-1, number of negative eigenvalues); `a` is left
+    unchanged (the library works on a copy)."""
+    if not isinstance(a, torch.Tensor) or a.dim() != 2 or a.shape[0] != a.shape[1]:
+        raise ValueError("a: expected a square 2-D torch tensor")
+    n = a.shape[0]
+    _arg(a.reshape(-1), "a", a.device, n * n)
+    if a.device.type != "cuda":
+        raise ValueError("a: expected a device tensor")
+    work_a = a.clone()
+    inv = torch.empty_like(a)
+    size = ctypes.c_size_t()
+    _check(lib().mfh_dense_inverse_workspace(n, ctypes.byref(size)))
+    ws = torch.empty(size.value + 256, dtype=torch.uint8, device=a.device)
+    base = ws.data_ptr() + (-ws.data_ptr()) % 256
+    stream = torch.cuda.current_stream(a.device) if stream is None else stream
+    neg = ctypes.c_int()
+    _check(lib().mfh_dense_inverse(_ptr(work_a), _ptr(inv), n, ctypes.c_void_p(base), size.value,
+                                   ctypes.c_void_p(stream.cuda_stream), ctypes.byref(neg)))
+    return inv, neg.value
 
 
 def _check_batch(st, handle):

@@ -27,9 +27,9 @@ HIER = {
 }
 _CACHE = {}
 # Largest Lanczos Ritz value after 30 FP64 CG steps, device against oracle
-# (measured up to 2e-10 over HIER; the smoother and V-cycle comparisons below
-# take the oracle's estimates instead, through mfh_set_level_eigenvalues).
-LAMBDA_TOL = 1e-9
+# (measured up to 1.1e-15 over HIER).  The smoother and V-cycle comparisons
+# below also run on the oracle's estimates, through mfh_set_level_eigenvalues.
+LAMBDA_TOL = 1e-13
 # FP32 V-cycle against the FP64 oracle on the same smoother intervals: a
 # linear map evaluated in FP32 (unit roundoff 6e-8) through up to 16 operator
 # applications per level and three levels.
@@ -146,19 +146,19 @@ def test_chebyshev_and_vcycle_fp64(name):
 
 @pytest.mark.parametrize("name", list(HIER))
 def test_vcycle_fp64_own_estimates(name):
-    """With its own Lanczos estimates the device V-cycle differs from the
-    oracle's only through the interval: the smoother polynomial is a smooth
-    function of lambda_max, so the V-cycle moves by a modest multiple of the
-    estimate's relative difference (Chebyshev coarse solver: the smallest
-    Ritz value also sets the coarse polynomial's degree-40 interval)."""
+    """With its own Lanczos estimates the FP64 V-cycle still agrees with the
+    oracle to 1e-12: the largest Ritz values agree to rounding (LAMBDA_TOL).
+    The Chebyshev coarse solver also takes the smallest Ritz value of the
+    coarse run, which 30 steps leave far from converged and sensitive to the
+    summation order, and its degree-40 polynomial amplifies that (measured
+    5.9e-9); on the oracle's estimates it agrees to 1e-12 (above)."""
     log_case("vcycle_f64_own", name=name)
     c, mu, lam, incl, mask, H, u, b = _setup(name)
     P = _device(name, F64)
     z, zw = host(P.gmg_vcycle(dev(b))), H.vcycle(b)
     dl = max(abs(P.level_lambda_max(l) - H.lam_max[l]) / H.lam_max[l] for l in range(1, c["n_levels"]))
     print(f"[vcycle_f64_own] {name}: lambda rel {dl:.2e}, vcycle rel {rel_l2(z, zw):.2e}", flush=True)
-    factor = 1e5 if c.get("coarse") == "chebyshev" else 1e3
-    assert rel_l2(z, zw) <= max(1e-12, factor * dl)
+    assert rel_l2(z, zw) <= (1e-7 if c.get("coarse") == "chebyshev" else 1e-12)
 
 
 @pytest.mark.parametrize("name", list(HIER))

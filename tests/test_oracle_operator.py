@@ -269,3 +269,13 @@ def test_min_jacobian_quadratic_field(dim, N, p):
         f[:, 1] = b * X[:, 1] ** 2
         want = (1 + 2 * a * xs) * (1 + 2 * b * ys)
         assert abs(fe.min_jacobian(m, _nodal(m, f)) - want) <= 1e-13
+
+
+def test_oracle_host_spmv_matches_scipy():
+    """The oracle's OpenMP CSR product (CPU baseline) computes K x."""
+    from oracle import spmv
+    m, mat, u = _setup(3, 3, 2)
+    K = fe.tangent_matrix(m, mat, u)
+    x = W.normal_vector(m.n_dofs, 3)
+    y = spmv.spmv(spmv.prepare(K), x)
+    assert np.linalg.norm(y - K @ x) <= 1e-14 * np.linalg.norm(K @ x)
