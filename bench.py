@@ -1,17 +1,22 @@
 """Benchmark of the matrix-free finite-strain tangent on one MI355X.
 
-Headline workload: 3-D unit cube,
-32^3 Q2 cells (823,875 DoFs), (p+1)^3 Gauss points, compressible Neo-Hookean
-matrix (mu = 1, nu = 0.3) with 20 seeded spheres 100x stiffer, seeded smooth
-displacement of amplitude 0.1, x ~ N(0, 1).  A step is one tangent vmult
-(gather -> sum factorisation -> quadrature-point stage -> transposed sum
-factorisation -> atomic scatter) with the inputs resident in HBM.  Every
+Headline workload: 3-D unit cube, 32^3 Q2 cells (823,875 DoFs), (p+1)^3 Gauss
+points, compressible Neo-Hookean matrix (mu = 1, nu = 0.3) with 20 seeded
+spheres 100x stiffer, seeded smooth displacement of amplitude 0.1, x ~ N(0,1).
+A step is one tangent vmult (gather -> sum factorisation -> quadrature-point
+stage -> transposed sum factorisation -> scatter in the mode the tuned table
+picks: for this workload the cell kernel writes an element buffer and a
+node-sum kernel adds it into y) with the inputs resident in HBM.  Every
 quadrature-point policy is timed in FP64 and FP32; the best FP64 one is the
-headline value.  The roofline object describes the cell kernel of the
-headline variant, timed with HIP events on the library's stream; cpu_baseline
-times the CPU oracle on a bounded sample of the same workload.
+headline value.  The roofline object covers the kernels of one vmult of the
+headline variant (both kernels of the ELEMENT scatter), timed with HIP events
+on the library's stream around the timed steps, plus per-call warm and cold
+(cache-flushed) timings.  Further parts: the 64^3 Q2 Newton benchmark (mixed
+against all-FP64 GMG-CG), the 256-problem batch, the matrix-based (CSR)
+comparison, the Q4 48^3 level vmults and Newton loadings (with a wall-time
+budget each), and cpu_baseline, the oracle timed on the host cores.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-q4] ...
 """
 import argparse
 import json
@@ -95,12 +100,12 @@ def roofline(dim, degree, n_cells, n_dofs, policy, dtype, kernel_ms, scatter):
 
 
 def time_vmult(P, x, y, steps, warmup, cold=False, flush=None):
-    """(ms per step, ms per vmult inside the library's event pairs).  The steps
-    run back to back without instrumentation; a second pass of the same calls
-    with the library's timer on (an event pair around the kernels of each
-    vmult, on the library's stream) gives the kernel durations.  The event
-    pairs cost a few microseconds per call themselves, so they stay out of the
-    step time."""
+    """(ms per step, per-call ms list).  The steps run back to back with one
+    HIP event pair on the library's stream around all of them (the step time);
+    a second pass brackets every call with its own event pair (per-call
+    durations for the median and minimum; a pair costs a few microseconds, so
+    it stays out of the step time).  cold: a 512 MB buffer is rewritten before
+    every call, which evicts the working set from the caches."""
     import torch
     for _ in range(warmup):
         P.tangent_vmult(x, y)
@@ -113,15 +118,15 @@ def time_vmult(P, x, y, steps, warmup, cold=False, flush=None):
         P.tangent_vmult(x, y)
     e1.record(P.stream)
     torch.cuda.synchronize()
-    P.timer_enable(True)
-    for _ in range(steps):
+    pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for b, e in pairs:
         if cold:
             flush.add_(1.0)
+        b.record(P.stream)
         P.tangent_vmult(x, y)
+        e.record(P.stream)
     torch.cuda.synchronize()
-    kms, nl = P.timer_read()
-    P.timer_enable(False)
-    return e0.elapsed_time(e1) / steps, kms / max(nl, 1)
+    return e0.elapsed_time(e1) / steps, [b.elapsed_time(e) for b, e in pairs]
 
 
 def _cpu_model():
@@ -205,8 +210,8 @@ def law_bench(w, steps, warmup):
     for dt, tdt in (("f64", torch.float64), ("f32", torch.float32)):
         x = torch.as_tensor(w["x"], device="cuda").to(tdt)
         y = torch.empty_like(x)
-        ms, kms = time_vmult(P, x, y, steps, warmup)
-        out[dt] = {"ms_per_step": ms, "kernel_ms": kms, "dofs_per_s": P.n_dofs() / (ms * 1e-3),
+        ms, calls = time_vmult(P, x, y, steps, warmup)
+        out[dt] = {"ms_per_step": ms, "call_ms_median": float(np.median(calls)), "dofs_per_s": P.n_dofs() / (ms * 1e-3),
                    "scatter": SCATTER_NAMES[P.scatter_mode(-1, 0 if dt == "f64" else 1)]}
         print(f"[bench] cache_T4 Mooney-Rivlin {dt}: {ms * 1e3:8.1f} us/vmult", file=sys.stderr, flush=True)
     return out
@@ -417,8 +422,26 @@ def _q4_problem(n_cells, n_levels, level_field):
                    dirichlet_mask=W.clamp_bottom_top(3), qp_policy=2, vcycle_dtype=F32, level_field=level_field)
 
 
-def _q4_newton(n_cells, n_levels, strain, n_steps, level_field, cg_max_it=500):
-    """Newton load stepping to `strain` (negative: compression) in n_steps increments."""
+def _converged_fraction(recs, du_tol=1e-5, r_tol=1e-8):
+    """Largest load fraction whose increment converged, from the Newton records
+    (an increment's records share its load fraction, with rising step numbers)."""
+    best, i = 0.0, 0
+    while i < len(recs):
+        j = i
+        while (j + 1 < len(recs) and recs[j + 1]["load_fraction"] == recs[i]["load_fraction"]
+               and recs[j + 1]["newton_iter"] == recs[j]["newton_iter"] + 1):
+            j += 1
+        last, r0 = recs[j], recs[i]["residual_norm"]
+        ra = last["residual_after"]
+        if np.isfinite(ra) and last["du_norm"] <= du_tol and (ra <= r_tol or ra <= r_tol * r0):
+            best = max(best, last["load_fraction"])
+        i = j + 1
+    return best
+
+
+def _q4_newton(n_cells, n_levels, strain, n_steps, level_field, cg_max_it=500, budget_s=60.0):
+    """Newton load stepping to `strain` (negative: compression) in n_steps
+    increments, within a wall-time budget (the library's max_seconds)."""
     import torch
     P = _q4_problem(n_cells, n_levels, level_field)
     u = torch.zeros(P.n_dofs(), dtype=torch.float64, device="cuda")
@@ -426,17 +449,26 @@ def _q4_newton(n_cells, n_levels, strain, n_steps, level_field, cg_max_it=500):
     fv[5][2] = strain
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    recs, st, done = [], 0, 0.0
+    recs, st, done, why = [], 0, 0.0, ""
     name = f"{'compression' if strain < 0 else 'tension'} {abs(strain):.0%}, {['nodal', 'vertex'][level_field]}"
     for k in range(1, n_steps + 1):   # one call per load step (progress lines between them)
-        rk, st = P.newton_solve(u, fv * (k / n_steps), n_steps=1, cg_max_it=cg_max_it, raise_on_error=False)
+        left = budget_s - (time.perf_counter() - t0)
+        if left <= 0:
+            st, why = -5, "time budget"
+            break
+        rk, st = P.newton_solve(u, fv * (k / n_steps), n_steps=1, cg_max_it=cg_max_it, raise_on_error=False,
+                                max_seconds=left)
+        frac = _converged_fraction(rk)
         for r in rk:
             r["load_fraction"] = (k - 1 + r["load_fraction"]) / n_steps
         recs += rk
         print(f"[bench] q4_48cube {name} load step {k}: {len(rk)} Newton steps, CG iterations "
-              f"{[r['cg_iters'] for r in rk]}, status {st}, {time.perf_counter() - t0:.1f} s",
+              f"{[r['cg_iters'] for r in rk][-12:]}, status {st}, {time.perf_counter() - t0:.1f} s",
               file=sys.stderr, flush=True)
         if st != 0:
+            done = (k - 1 + frac) / n_steps
+            from paper_1904_13131_amd import lib
+            why = lib().mfh_last_error(P.handle).decode()
             break
         done = k / n_steps
     total = time.perf_counter() - t0
@@ -445,16 +477,18 @@ def _q4_newton(n_cells, n_levels, strain, n_steps, level_field, cg_max_it=500):
     del P
     torch.cuda.empty_cache()
     return {"loading": name, "level_field": ["nodal", "vertex"][level_field], "status": int(st),
+            "stop_reason": why, "budget_s": budget_s,
             "wall_s": round(total, 2), "newton_steps": len(recs), "strain_reached": done * strain,
             "cutbacks": max([r["cutbacks"] for r in recs] or [0]),
+            "min_J_last": recs[-1]["min_J"] if recs else None,
+            "max_coarse_negative": max([r["coarse_negative"] for r in recs] or [0]),
             "median_newton_step_ms": float(np.median([r["setup_ms"] + r["residual_ms"] + r["solve_ms"]
                                                       for r in ok])) if ok else None,
-            "cg_iters_converged_steps": [r["cg_iters"] for r in ok],
-            "max_coarse_negative": max([r["coarse_negative"] for r in recs] or [0]),
-            "min_J_last": recs[-1]["min_J"] if recs else None}
+            "cg_iters_converged_steps": [r["cg_iters"] for r in ok][-40:],
+            "step_lengths_below_1": sum(1 for r in recs if np.isfinite(r["step_length"]) and r["step_length"] < 1)}
 
 
-def q4_48cube_bench(n_cells=48, n_levels=5, n_steps=5, steps=10, newton=True):
+def q4_48cube_bench(n_cells=48, n_levels=5, n_steps=5, steps=10, newton=True, budget_s=60.0):
     """3-D Q4 48^3 (21.6 M DoFs), 5^3 Gauss points, 200 spheres (seed 7),
     two-phase Neo-Hookean material, bottom/top clamped, levels 3^3..48^3, FP32 V(2,2)
     Chebyshev(4) GMG under FP64 CG.  Level vmults (FP32 on three levels, FP64 on
@@ -512,8 +546,8 @@ def q4_48cube_bench(n_cells=48, n_levels=5, n_steps=5, steps=10, newton=True):
     del P
     torch.cuda.empty_cache()
     if newton:
-        out["newton"] = [_q4_newton(n_cells, n_levels, -0.2, n_steps, 0),
-                         _q4_newton(n_cells, n_levels, +0.2, n_steps, 1)]
+        out["newton"] = [_q4_newton(n_cells, n_levels, -0.2, n_steps, 0, budget_s=budget_s),
+                         _q4_newton(n_cells, n_levels, +0.2, n_steps, 1, budget_s=budget_s)]
     return out
 
 
@@ -640,8 +674,11 @@ def main(argv=None):
                     "mixed_recompute, ..., shear_traction); all when empty")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-problem batched measurement")
     ap.add_argument("--no-batch-solve", action="store_true", help="256-problem batch: time the batched vmult only")
-    ap.add_argument("--q4-48cube", action="store_true", help="also run the Q4 48^3 level vmults and Newton (minutes)")
+    ap.add_argument("--no-q4", action="store_true", help="skip the Q4 48^3 level vmults and Newton runs")
+    ap.add_argument("--q4-48cube", action="store_true", help="with a partial policy/dtype run: add the Q4 48^3 part")
     ap.add_argument("--q4-48cube-vmult-only", action="store_true", help="Q4 48^3: level vmults only, no Newton")
+    ap.add_argument("--q4-budget", type=float, default=60.0,
+                    help="wall-time budget in seconds of each Q4 48^3 Newton loading (compression, tension)")
     ap.add_argument("--no-matrix-based", action="store_true", help="skip the CSR matrix-based comparison")
     ap.add_argument("--matrix-based-only", action="store_true", help="only the CSR matrix-based comparison")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -687,22 +724,23 @@ def main(argv=None):
             if dt not in dtypes:
                 continue
             y = torch.empty_like(x)
-            ms, kms = time_vmult(P, x, y, a.steps, a.warmup)
-            kms_cold = float("nan")
+            ms, calls = time_vmult(P, x, y, a.steps, a.warmup)
+            cold = [float("nan")]
             if not a.no_cold:
-                _, kms_cold = time_vmult(P, x, y, max(5, a.steps // 5), 1, cold=True, flush=flush)
+                _, cold = time_vmult(P, x, y, max(10, a.steps // 5), 1, cold=True, flush=flush)
             mode = SCATTER_NAMES[P.scatter_mode(-1, F64 if dt == "f64" else F32)]
-            res[(pol, dt)] = dict(ms_per_step=ms, kernel_ms=kms, kernel_ms_cold=kms_cold,
-                                  dofs_per_s=n_dofs / (ms * 1e-3), kernel_dofs_per_s=n_dofs / (kms * 1e-3),
-                                  scatter=mode)
-            print(f"[bench] {POLICIES[pol]:9s} {dt} ({mode}): {ms * 1e3:8.1f} us/vmult, kernel {kms * 1e3:8.1f} us "
-                  f"(cold {kms_cold * 1e3:8.1f} us), {n_dofs / (ms * 1e-3):.3e} DoF/s", file=sys.stderr, flush=True)
+            res[(pol, dt)] = dict(ms_per_step=ms, call_ms_median=float(np.median(calls)), call_ms_min=min(calls),
+                                  cold_ms_median=float(np.median(cold)), cold_ms_min=min(cold),
+                                  dofs_per_s=n_dofs / (ms * 1e-3), scatter=mode)
+            print(f"[bench] {POLICIES[pol]:9s} {dt} ({mode}): {ms * 1e3:8.1f} us/vmult, per call median "
+                  f"{np.median(calls) * 1e3:8.1f} min {min(calls) * 1e3:8.1f} us, cold median "
+                  f"{np.median(cold) * 1e3:8.1f} us, {n_dofs / (ms * 1e-3):.3e} DoF/s", file=sys.stderr, flush=True)
         del P
         torch.cuda.empty_cache()
     if not any(k[1] == "f64" for k in res) or not any(k[1] == "f32" for k in res):
         part = {"partial": True, "variants": {f"{POLICIES[k[0]]}/{k[1]}": res[k] for k in res}}
         if a.q4_48cube or a.q4_48cube_vmult_only:
-            part["q4_48cube"] = q4_48cube_bench(newton=not a.q4_48cube_vmult_only)
+            part["q4_48cube"] = q4_48cube_bench(newton=not a.q4_48cube_vmult_only, budget_s=a.q4_budget)
         print(json.dumps(part))
         return 0
     best = max((k for k in res if k[1] == "f64"), key=lambda k: res[k]["dofs_per_s"])
@@ -734,10 +772,15 @@ def main(argv=None):
         "variants": {f"{POLICIES[k[0]]}/{k[1]}": {kk: (round(v, 6) if isinstance(v, float) else v)
                                                  for kk, v in res[k].items()} for k in res},
     }
-    # the same kernels timed per call inside the library's event pairs (which
-    # add about 2 us per call), warm and after a 512 MB cache flush
-    out["roofline"]["kernel_ms"] = r["kernel_ms"]
-    out["roofline"]["kernel_ms_cold"] = r["kernel_ms_cold"]
+    # per-call timings (an event pair around each call adds a few us): warm
+    # median and minimum, and cold (after a 512 MB cache flush) median, with
+    # the fraction of the HBM roofline the cold median reaches
+    rl = out["roofline"]
+    rl.update(call_ms_median=r["call_ms_median"], call_ms_min=r["call_ms_min"], cold_ms_median=r["cold_ms_median"],
+              cold_ms_min=r["cold_ms_min"])
+    if rl["bound"] == "hbm" and np.isfinite(r["cold_ms_median"]):
+        rl["achieved_cold"] = rl["alg_bytes"] / (r["cold_ms_median"] * 1e-3) / 1e9
+        rl["frac_cold"] = rl["achieved_cold"] / rl["peak"]
     if 3 in [int(p) for p in a.policies.split(",")]:
         out["mooney_rivlin_cache_T4"] = law_bench(w, a.steps, a.warmup)
     if not a.no_matrix_based:
@@ -748,8 +791,8 @@ def main(argv=None):
             out["newton_step"]["cpu_oracle"] = cpu_newton_baseline(w)
     if not a.no_batch:
         out["batched"] = batch_bench(solve=not a.no_batch_solve)
-    if a.q4_48cube or a.q4_48cube_vmult_only:
-        out["q4_48cube"] = q4_48cube_bench(newton=not a.q4_48cube_vmult_only)
+    if not a.no_q4:
+        out["q4_48cube"] = q4_48cube_bench(newton=not a.q4_48cube_vmult_only, budget_s=a.q4_budget)
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)

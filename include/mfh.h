@@ -234,7 +234,9 @@ mfh_status mfh_csr_assemble(mfh_problem* problem, int level, long long* row_ptr_
                             double* val_dev);
 
 /* y = A x (FP64) for the CSR arrays written by mfh_csr_assemble for this
- * level; one wavefront per row.  Async on the problem's stream.
+ * level; each row is summed by a group of 16 lanes (mean rows of at most
+ * 100 entries) or 8 lanes (longer rows), each lane keeping 4 or 8 entries in
+ * flight.  Async on the problem's stream.
  * Errors: INVALID_ARG, HIP. */
 mfh_status mfh_csr_spmv(mfh_problem* problem, int level, const long long* row_ptr_dev, const int* col_dev,
                         const double* val_dev, const double* x_dev, double* y_dev);
@@ -309,18 +311,22 @@ mfh_status mfh_apply_dirichlet(mfh_problem* problem, double* u_dev,
  * coarse tangent is numerically singular) or does not reach
  * cg_rtol in cg_max_it steps, when no step length is accepted, or when
  * max_newton steps do not converge; then u is restored to the start of the
- * increment and the failed increment is halved, at most 8 times in a row
- * (the count restarts after every converged increment); after a converged
- * cut increment the step doubles again up to 1/n_steps.  The record of a
+ * increment and the failed increment is halved, down to 1/256 of a load step
+ * (the solve fails when an increment of that size fails); after a converged
+ * cut increment the step doubles again up to 1/n_steps.  max_seconds > 0 is a
+ * wall-time budget: when it is exhausted at the start of a Newton step, u is
+ * restored to the last converged load and the call returns NOT_CONVERGED
+ * (the records tell the load reached).  The record of a
  * Newton step whose update was not taken carries NaN in residual_after and
  * step_length (and in cg_relres after a CG breakdown).
  * u (device FP64) is the initial state and receives the solution.  Up to
  * max_records records are written to the host array; *n_records receives the
- * number of Newton steps taken.  Synchronises.
+ * number of Newton steps taken.  With MFH_NEWTON_LOG=1 in the environment
+ * every Newton step is also printed as one line on stderr.  Synchronises.
  * Errors: INVALID_ARG, INVERTED, NOT_CONVERGED, BREAKDOWN, NOT_SPD, HIP. */
 mfh_status mfh_newton_solve(mfh_problem* problem, double* u_dev, const double* face_values,
                             const double* face_traction, int n_steps, double cg_rtol, int cg_max_it,
-                            double du_tol, double r_tol, int max_newton,
+                            double du_tol, double r_tol, int max_newton, double max_seconds,
                             mfh_newton_record* records, int max_records, int* n_records);
 
 /* f = nodal forces of dead face tractions on the finest level (as for
@@ -336,7 +342,8 @@ mfh_status mfh_scatter_mode(const mfh_problem* problem, int level, int dtype, in
 
 /* Coordinates of the support points along one axis of `level` (all axes
  * are alike): the L = degree * N + 1 lattice positions in [0, 1], the
- * Gauss-Lobatto-Legendre points of every cell (Sec. 7), into the host array
+ * Gauss-Lobatto-Legendre points of every cell (the paper names no point
+ * family; this is the library's choice, equispaced for degree <= 2), into the host array
  * x (L doubles).  Node (i, j, k) sits at (x[i], x[j], x[k]).  Host only.
  * Errors: INVALID_ARG. */
 mfh_status mfh_node_coords_1d(mfh_problem* problem, int level, double* x_host);
@@ -409,6 +416,10 @@ mfh_status mfh_enable_graphs(mfh_problem* problem, int enable);
 /* ---- Batches of independent problems (many meshes, degrees, materials) ---- */
 
 typedef struct mfh_batch mfh_batch;
+
+/* All calls on one batch, and on the problems it holds while it exists, must
+ * come from one host thread (the batch drives the problems' streams itself);
+ * concurrent calls from several threads are not supported. */
 
 /* Device bytes for a batch over n existing problems (all with one qp_policy). */
 mfh_status mfh_batch_workspace_size(int n, mfh_problem* const* problems, size_t* bytes);

@@ -59,9 +59,9 @@ def solve(hier, face_values, n_steps, rtol=1e-8, max_cg=200, du_tol=1e-5,
     at the iterate, also when it stops the smoother's eigenvalue estimate at
     its first step), a CG that misses rtol in max_cg steps, an update for
     which no step length is accepted, or when max_newton steps do not
-    converge.  The failed increment is undone and halved, at most
-    ``max_cutbacks`` times in a row (the count restarts after every converged
-    increment); after a converged cut increment the step doubles again up to
+    converge.  The failed increment is undone and halved, down to
+    1/2^max_cutbacks of a load step (the solve fails when an increment of that
+    size fails); after a converged cut increment the step doubles again up to
     1/n_steps.
     """
     mesh = hier.meshes[-1]
@@ -72,7 +72,7 @@ def solve(hier, face_values, n_steps, rtol=1e-8, max_cg=200, du_tol=1e-5,
     f_ext[cons] = 0.0
     records = []
     h0 = 1.0 / n_steps
-    done, h, cut, total_cut = 0.0, h0, 0, 0
+    done, h, total_cut = 0.0, h0, 0
 
     def res(v, s):
         return fe.residual(mesh, hier.mat, v) - s * f_ext
@@ -141,14 +141,13 @@ def solve(hier, face_values, n_steps, rtol=1e-8, max_cg=200, du_tol=1e-5,
                     break
             if conv:
                 done = target
-                cut = 0
                 if h < h0:
                     h = min(h0, 2.0 * h)
                 continue
             u = saved
-            cut += 1
             total_cut += 1
-            if cut > max_cutbacks:
-                raise RuntimeError(f"Newton failed after {max_cutbacks} cut-backs in a row at load fraction {done}")
+            if target - done <= h0 / 2 ** max_cutbacks * (1.0 + 1e-9):
+                raise RuntimeError(f"Newton failed: an increment of 1/{2 ** max_cutbacks} of a load step did not "
+                                   f"converge at load fraction {done}")
             h = 0.5 * (target - done)
     return u, records

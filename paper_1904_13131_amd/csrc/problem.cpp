@@ -5,6 +5,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <stdexcept>
@@ -381,7 +382,7 @@ size_t layout(mfh_problem* P, char* base) {
   P->fmap = b.take<int>(P->has_coarse ? c.ndofs : 1);
   P->dof_of = b.take<int>(std::max<long long>(1, P->nf));
   P->dof_perm = b.take<int>(std::max<long long>(1, P->nf));
-  P->gj_sw = b.take<int>(1 + 2 * 64);
+  P->gj_sw = b.take<int>(1 + 4 * 64);
   P->gj_key = b.take<double>(std::max<long long>(1, P->nf));
   P->Kinv = b.take<double>((size_t)P->nf * P->nf);
   P->gj_P = b.take<double>(64 * 64);
@@ -1409,7 +1410,7 @@ mfh_status mfh_apply_dirichlet(mfh_problem* P, double* u, const double* fv, doub
 }
 
 // Newton globalisation (the paper does not say how it handles failed steps):
-// at most kMaxCut halvings of a load increment in a row, and a step length
+// failed increments are halved down to 1/2^kMaxCut of a load step, and a step length
 // alpha = 1, 1/2, ... (at most kMaxHalvings halvings) that keeps J > 0 and,
 // once the prescribed values are met, lowers |R|^2 by the Armijo factor
 // 1 - 2 kArmijo alpha.
@@ -1419,7 +1420,7 @@ constexpr double kArmijo = 1e-4;
 
 mfh_status mfh_newton_solve(mfh_problem* P, double* u, const double* fv, const double* ft, int n_steps,
                             double cg_rtol, int cg_max_it, double du_tol, double r_tol, int max_newton,
-                            mfh_newton_record* rec, int max_rec, int* n_rec) {
+                            double max_seconds, mfh_newton_record* rec, int max_rec, int* n_rec) {
   if (!P) return MFH_ERR_INVALID_ARG;
   int nrec = 0;
   mfh_status st = guarded(P, [&] {
@@ -1432,12 +1433,25 @@ mfh_status mfh_newton_solve(mfh_problem* P, double* u, const double* fv, const d
     const int top = (int)P->lv.size() - 1;
     const double h0 = 1.0 / n_steps;
     double done = 0.0, h = h0;
-    int step = 0, cut = 0, cutbacks = 0;   // halvings in a row / in the solve
+    int step = 0, cutbacks = 0;   // increment halvings in the solve
+    const auto t_start = Clock::now();
     if (ft) external_force(P, ft, P->f_ext);   // dead tractions scale with the load like fv
     // R(v) = F_int(v) - s f_ext on free rows (constrained rows zero) into Rv
     auto eval_residual = [&](const double* w, double* Rv, double sc) {
       residual(P, w, Rv);
       if (ft) axpby<double>(Rv, P->f_ext, -sc, 1.0, n, s);
+    };
+    // MFH_NEWTON_LOG=1 in the environment: one line per Newton step on stderr
+    const char* log_env = std::getenv("MFH_NEWTON_LOG");
+    const bool log = log_env && log_env[0] == '1';
+    auto log_step = [&](const mfh_newton_record& r) {
+      if (!log) return;
+      std::fprintf(stderr,
+                   "[mfh newton] load %.6f step %d: |b| %.3e, CG %d (%.1e), alpha %g, |R| %.3e, |du| %.3e, "
+                   "min J %.4f, coarse negative %d, %.0f ms\n",
+                   r.load_fraction, r.newton_iter, r.residual_norm, r.cg_iters, r.cg_relres, r.step_length,
+                   r.residual_after, r.du_norm, r.min_J, r.coarse_negative, r.setup_ms + r.solve_ms + r.residual_ms);
+      std::fflush(stderr);
     };
     while (done < 1.0 - 1e-12) {
       const double target = std::fmin(1.0, done + h);
@@ -1450,6 +1464,11 @@ mfh_status mfh_newton_solve(mfh_problem* P, double* u, const double* fv, const d
       eval_residual(u, P->nw_R, target);
       double rn = norm2(P, P->nw_R, n);          // |R(u)| on free rows
       for (int it = 0; it < max_newton; ++it) {
+        if (max_seconds > 0 && ms_since(t_start) > 1e3 * max_seconds) {
+          HIPCHECK(hipMemcpyAsync(u, P->nw_save, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+          HIPCHECK(hipStreamSynchronize(s));
+          throw Error(MFH_ERR_NOT_CONVERGED, "time budget exhausted at load fraction " + std::to_string(done));
+        }
         mfh_newton_record r{};
         r.load_step = step;
         r.newton_iter = it;
@@ -1471,6 +1490,7 @@ mfh_status mfh_newton_solve(mfh_problem* P, double* u, const double* fv, const d
           r.setup_ms = ms_since(t0);
           if (rec && nrec < max_rec) rec[nrec] = r;
           ++nrec;
+          log_step(r);
           fail = sp;
           break;
         }
@@ -1496,6 +1516,7 @@ mfh_status mfh_newton_solve(mfh_problem* P, double* u, const double* fv, const d
           if (cr.st == MFH_ERR_BREAKDOWN) r.cg_relres = NAN;
           if (rec && nrec < max_rec) rec[nrec] = r;
           ++nrec;
+          log_step(r);
           fail = cr.st;
           break;
         }
@@ -1520,6 +1541,7 @@ mfh_status mfh_newton_solve(mfh_problem* P, double* u, const double* fv, const d
         if (!accepted) {   // every trial inverted a quadrature point or failed to lower |R|
           if (rec && nrec < max_rec) rec[nrec] = r;
           ++nrec;
+          log_step(r);
           eval_residual(u, P->nw_R, target);   // keep nw_R = R(u) consistent
           fail = std::isfinite(rt) ? MFH_ERR_NOT_CONVERGED : MFH_ERR_INVERTED;
           break;
@@ -1532,6 +1554,7 @@ mfh_status mfh_newton_solve(mfh_problem* P, double* u, const double* fv, const d
         r.residual_after = rt;
         if (rec && nrec < max_rec) rec[nrec] = r;
         ++nrec;
+        log_step(r);
         if (!pending && r.du_norm <= du_tol && (rt <= r_tol || rt <= r_tol * R0)) {
           conv = true;
           break;
@@ -1539,7 +1562,6 @@ mfh_status mfh_newton_solve(mfh_problem* P, double* u, const double* fv, const d
       }
       if (conv) {
         done = target;
-        cut = 0;
         if (h < h0) h = std::fmin(h0, 2.0 * h);   // grow back after a successful cut increment
         continue;
       }
@@ -1547,9 +1569,9 @@ mfh_status mfh_newton_solve(mfh_problem* P, double* u, const double* fv, const d
       HIPCHECK(hipMemcpyAsync(u, P->nw_save, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
       HIPCHECK(hipStreamSynchronize(s));
       ++cutbacks;
-      if (++cut > kMaxCut)
-        throw Error(fail, std::string("Newton failed after ") + std::to_string(kMaxCut) +
-                              " cut-backs in a row at load fraction " + std::to_string(done));
+      if (target - done <= h0 / (1 << kMaxCut) * (1.0 + 1e-9))
+        throw Error(fail, std::string("Newton failed: an increment of 1/") + std::to_string(1 << kMaxCut) +
+                              " of a load step did not converge at load fraction " + std::to_string(done));
       h = 0.5 * (target - done);
     }
   });
@@ -1697,12 +1719,14 @@ size_t dense_inverse_layout(long long n, char* base, mfh::DenseInvWork* w, int**
   double* key = b.take<double>((size_t)n);
   double* scale = b.take<double>(1);
   int* pm = b.take<int>((size_t)n);
-  int* sw = b.take<int>(1 + 2 * 64);
+  int* sw = b.take<int>(1 + 4 * 64);
   int* flag = b.take<int>(2);
   if (w) *w = mfh::DenseInvWork{Pinv, C, R, key, scale, sw, flag};
   if (perm) *perm = pm;
   return b.off + 256;
 }
+
+void dense_inverse_run(double* a, double* inv, long long n, char* work, hipStream_t s, int* negative);
 }  // namespace
 
 mfh_status mfh_dense_inverse_workspace(long long n, size_t* bytes) {
@@ -1713,6 +1737,25 @@ mfh_status mfh_dense_inverse_workspace(long long n, size_t* bytes) {
   });
 }
 
+namespace {
+// The dense inverse on work arrays at `work` (layout of dense_inverse_layout);
+// every array is written before it is read, the flags by a fill kernel.
+void dense_inverse_run(double* a, double* inv, long long n, char* work, hipStream_t s, int* negative) {
+  mfh::DenseInvWork w{};
+  int* perm = nullptr;
+  dense_inverse_layout(n, work, &w, &perm);
+  mfh::fill<int>(w.flag, 0, 2, s);
+  mfh::iota(perm, n, s);
+  mfh::dense_inverse(a, n, perm, w, mfh::kSingularTol, s);
+  mfh::unpermute(a, perm, n, inv, s);
+  int flag[2];
+  HIPCHECK(hipMemcpyAsync(flag, w.flag, sizeof flag, hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  *negative = flag[1];
+  if (flag[0]) throw Error(MFH_ERR_NOT_SPD, "matrix is numerically singular");
+}
+}  // namespace
+
 mfh_status mfh_dense_inverse(double* a, double* inv, long long n, void* work, size_t work_bytes, void* stream,
                              int* negative) {
   return guarded(nullptr, [&] {
@@ -1722,19 +1765,7 @@ mfh_status mfh_dense_inverse(double* a, double* inv, long long n, void* work, si
     need(((uintptr_t)work & 255) == 0, "work must be 256-byte aligned");
     if (work_bytes < dense_inverse_layout(n, nullptr, nullptr, nullptr))
       throw Error(MFH_ERR_WORKSPACE, "work smaller than mfh_dense_inverse_workspace reports");
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    mfh::DenseInvWork w{};
-    int* perm = nullptr;
-    dense_inverse_layout(n, static_cast<char*>(work), &w, &perm);
-    mfh::fill<int>(w.flag, 0, 2, s);
-    mfh::iota(perm, n, s);
-    mfh::dense_inverse(a, n, perm, w, mfh::kSingularTol, s);
-    mfh::unpermute(a, perm, n, inv, s);
-    int flag[2];
-    HIPCHECK(hipMemcpyAsync(flag, w.flag, sizeof flag, hipMemcpyDeviceToHost, s));
-    HIPCHECK(hipStreamSynchronize(s));
-    *negative = flag[1];
-    if (flag[0]) throw Error(MFH_ERR_NOT_SPD, "matrix is numerically singular");
+    dense_inverse_run(a, inv, n, static_cast<char*>(work), static_cast<hipStream_t>(stream), negative);
   });
 }
 

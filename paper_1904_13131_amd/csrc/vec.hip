@@ -412,15 +412,23 @@ __global__ void k_material_bits(uint32_t* __restrict__ bits, long long ncells, i
 
 constexpr int kGJ = 64;
 
-// Coarse inverse by symmetric block Gauss-Jordan with pivoting.  Before each
-// block step the nb unswept positions with the largest |diagonal| (the
-// diagonal of the current Schur complement: the update kernels keep every
-// unswept entry current) are moved into the block window [k0, k0 + nb) by a
-// symmetric exchange of rows and columns (the free-DoF permutation follows);
-// the block itself is inverted in LDS with Bunch-Kaufman pivoting (1x1 and
-// 2x2 pivots chosen within the block).  Sweeps commute, so the result is the
-// inverse in the permuted basis, and the pivots are those of a symmetric
-// block LDL^T elimination, whose signs give the inertia (Sylvester).
+// Coarse inverse by symmetric block Gauss-Jordan with Bunch-Kaufman pivoting.
+// Each block step chooses its (up to) 64 pivots on the current Schur
+// complement of the unswept positions [k0, n) (the update kernels keep those
+// entries current): the unswept index k of largest |diagonal|, lambda = the
+// largest off-diagonal |entry| of its column (row r); k alone when |a_kk| >=
+// alpha lambda or |a_kk| sigma >= alpha lambda^2 (sigma: largest off-diagonal
+// |entry| of column r), r alone when |a_rr| >= alpha sigma, else the 2x2 block
+// {k, r} (alpha = (1 + sqrt 17) / 8).  The columns are formed lazily, from the
+// matrix at the step's start minus the updates of the pivots already chosen,
+// so the choice sees whole columns, as unblocked Bunch-Kaufman does.  The
+// chosen positions are then exchanged (rows and columns, symmetrically, the
+// free-DoF permutation following) into the block window [k0, k0 + nb), and
+// the block is swept in the chosen order (1x1 and 2x2 pivots).  Sweeps
+// commute, so the result is the inverse in the permuted basis; the pivots are
+// those of a symmetric block LDL^T elimination, whose signs give the inertia
+// (Sylvester).  At the block's last slot a needed 2x2 pivot is replaced by
+// the 1x1 pivot of the larger of |a_kk|, |a_rr|.
 
 // Wave-wide argmax of (v, i) over 64 lanes (larger v, then smaller i wins).
 __device__ __forceinline__ void wave_argmax(double& v, int& i) {
@@ -435,72 +443,199 @@ __device__ __forceinline__ void wave_argmax(double& v, int& i) {
   }
 }
 
-// key[t] = |A[k0 + t][k0 + t]| for the m = n - k0 unswept positions (+inf
-// for a non-finite entry, so that it is chosen and flagged at once).
-__global__ void k_gj_keys(const double* __restrict__ A, long long n, long long k0, double* __restrict__ key) {
-  const long long m = n - k0;
-  for (long long t = blockIdx.x * (long long)kVB + threadIdx.x; t < m; t += (long long)gridDim.x * kVB) {
-    const double d = A[(k0 + t) * n + k0 + t];
-    key[t] = isfinite(d) ? fabs(d) : INFINITY;
+__device__ __forceinline__ double mag(double x) { return isfinite(x) ? fabs(x) : INFINITY; }   // non-finite first
+
+constexpr int kSel = 1024;   // threads of the pivot-choice kernel
+
+// Block-wide argmax over kSel threads; every thread gets the result.
+__device__ __forceinline__ void block_argmax(double& v, int& i, double* sv, int* si) {
+  wave_argmax(v, i);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sv[w] = v;
+    si[w] = i;
   }
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    v = threadIdx.x < kSel / 64 ? sv[threadIdx.x] : -1.0;
+    i = threadIdx.x < kSel / 64 ? si[threadIdx.x] : 0x7fffffff;
+    wave_argmax(v, i);
+    if (threadIdx.x == 0) {
+      sv[kSel / 64] = v;
+      si[kSel / 64] = i;
+    }
+  }
+  __syncthreads();
+  v = sv[kSel / 64];
+  i = si[kSel / 64];
+  __syncthreads();
 }
 
-// Chooses the nb largest keys (ties: smaller position) and pairs the window
-// positions that were not chosen with the chosen positions outside the window:
-// sw[0] = number of pairs q, sw[1 + i] = window position, sw[1 + kGJ + i] =
-// outside position (absolute indices).  One workgroup of kVB threads; chosen
-// positions are marked in an LDS bitmap (m = n - k0 <= kGJMaxFree).
-__global__ void __launch_bounds__(kVB) k_gj_select(const double* __restrict__ key, long long n, long long k0, int nb,
-                                                   int* __restrict__ sw) {
-  __shared__ double wv[kVB / 64];
-  __shared__ int wi[kVB / 64];
-  __shared__ int chosen[kGJ];
-  __shared__ unsigned taken[kGJMaxFree / 32];
-  const int t = threadIdx.x;
-  const int m = (int)(n - k0);
-  for (int w = t; w < (m + 31) / 32; w += kVB) taken[w] = 0u;
-  __syncthreads();
-  for (int s = 0; s < nb; ++s) {
-    double bv = -1.0;
-    int bi = 0x7fffffff;
-    for (int i = t; i < m; i += kVB) {
-      const double v = (taken[i >> 5] >> (i & 31)) & 1u ? -1.0 : key[i];
-      if (v > bv) {   // increasing i: ties keep the smaller position
-        bv = v;
-        bi = i;
+// Largest |entry| of vector c over unswept positions other than `skip`.
+__device__ __forceinline__ void col_absmax(const double* c, int m, int skip, const unsigned* taken, double* sv,
+                                           int* si, double& v, int& i) {
+  v = -1.0;
+  i = 0x7fffffff;
+  for (int q = threadIdx.x; q < m; q += kSel)
+    if (q != skip && !((taken[q >> 5] >> (q & 31)) & 1u)) {
+      const double a = mag(c[q]);
+      if (a > v) {
+        v = a;
+        i = q;
       }
     }
-    wave_argmax(bv, bi);
-    if ((t & 63) == 0) {
-      wv[t >> 6] = bv;
-      wi[t >> 6] = bi;
+  block_argmax(v, i, sv, si);
+}
+
+// Column k (position relative to k0) of the current Schur complement into
+// V[slot]: row k of the matrix at the step's start (the unswept block is
+// symmetric) minus the updates of the pivot groups chosen so far.
+__device__ void form_column(const double* __restrict__ A, long long n, long long k0, int m, int k, double* V,
+                            int slot, int ng, const int* gs, const int* gn, const double (*einv)[3], double* wk) {
+  const int t = threadIdx.x;
+  if (t < ng) {
+    const int s0 = gs[t];
+    if (gn[t] == 1) {
+      wk[s0] = einv[t][0] * V[(long long)s0 * m + k];
+    } else {
+      const double a = V[(long long)s0 * m + k], b = V[(long long)(s0 + 1) * m + k];
+      wk[s0] = einv[t][0] * a + einv[t][1] * b;
+      wk[s0 + 1] = einv[t][1] * a + einv[t][2] * b;
     }
-    __syncthreads();
-    if (t == 0) {
-      for (int w = 1; w < kVB / 64; ++w)
-        if (wv[w] > bv || (wv[w] == bv && wi[w] < bi)) {
-          bv = wv[w];
-          bi = wi[w];
+  }
+  __syncthreads();
+  const int nv = ng > 0 ? gs[ng - 1] + gn[ng - 1] : 0;
+  for (int q = t; q < m; q += kSel) {
+    double c = A[(k0 + k) * n + k0 + q];
+    for (int v = 0; v < nv; ++v) c -= V[(long long)v * m + q] * wk[v];
+    V[(long long)slot * m + q] = c;
+  }
+  __syncthreads();
+}
+
+// Chooses the block's pivots (see above) and writes the exchange and the
+// pivot list: sw[0] = number of exchange pairs q, sw[1 + i] / sw[1 + kGJ + i]
+// = window / outside position of pair i, sw[1 + 2 kGJ + t] = window-relative
+// position of pivot t (after the exchange), sw[1 + 3 kGJ + t] = 1 (1x1 pivot),
+// 2 / 3 (first / second index of a 2x2 pivot).  dcur: n - k0 doubles, V: nb
+// vectors of n - k0 doubles (scratch).  One workgroup of kSel threads.
+__global__ void __launch_bounds__(kSel) k_gj_choose(const double* __restrict__ A, long long n, long long k0, int nb,
+                                                    double* __restrict__ dcur, double* __restrict__ V,
+                                                    int* __restrict__ sw) {
+  __shared__ unsigned taken[kGJMaxFree / 32];
+  __shared__ double sv[kSel / 64 + 1];
+  __shared__ int si[kSel / 64 + 1];
+  __shared__ double wk[kGJ];
+  __shared__ double einv[kGJ][3];
+  __shared__ int gs[kGJ], gn[kGJ];
+  __shared__ int sel[kGJ], kind[kGJ];
+  const double alpha = 0.6403882032022076;   // (1 + sqrt(17)) / 8
+  const int t = threadIdx.x;
+  const int m = (int)(n - k0);
+  for (int w = t; w < (m + 31) / 32; w += kSel) taken[w] = 0u;
+  for (int q = t; q < m; q += kSel) dcur[q] = A[(k0 + q) * n + k0 + q];
+  __syncthreads();
+  int cnt = 0, ng = 0;
+  while (cnt < nb) {
+    double akk = -1.0;
+    int k = 0x7fffffff;
+    for (int q = t; q < m; q += kSel)
+      if (!((taken[q >> 5] >> (q & 31)) & 1u)) {
+        const double a = mag(dcur[q]);
+        if (a > akk) {
+          akk = a;
+          k = q;
         }
-      chosen[s] = bi;   // m > nb untaken keys are >= 0, so one is always found
-      taken[bi >> 5] |= 1u << (bi & 31);
+      }
+    block_argmax(akk, k, sv, si);   // m - cnt > 0 unswept positions: k is one of them
+    form_column(A, n, k0, m, k, V, cnt, ng, gs, gn, einv, wk);
+    double lam;
+    int r;
+    col_absmax(V + (long long)cnt * m, m, k, taken, sv, si, lam, r);
+    int pk = k, two = 0;
+    if (lam > 0.0 && akk < alpha * lam) {
+      form_column(A, n, k0, m, r, V, cnt + (cnt + 1 < nb ? 1 : 0), ng, gs, gn, einv, wk);
+      // (at the last slot column r overwrites column k: only r's diagonal and sigma are needed)
+      const double* cr = V + (long long)(cnt + (cnt + 1 < nb ? 1 : 0)) * m;
+      double sig;
+      int ri;
+      col_absmax(cr, m, r, taken, sv, si, sig, ri);
+      const double arr = mag(cr[r]);
+      if (akk * sig >= alpha * lam * lam) {
+        pk = k;
+      } else if (arr >= alpha * sig) {
+        pk = r;
+      } else if (cnt + 1 < nb) {
+        two = 1;
+      } else {
+        pk = arr > akk ? r : k;   // last slot: no room for a 2x2 pivot
+      }
+      if (!two && (pk == r) != (cnt + 1 >= nb)) {   // bring the chosen column into slot cnt
+        form_column(A, n, k0, m, pk, V, cnt, ng, gs, gn, einv, wk);
+      }
     }
+    // record the group and update the diagonal of the unswept positions
+    const double* c0 = V + (long long)cnt * m;
+    if (!two) {
+      const double p = c0[pk];
+      const double ip = 1.0 / p;
+      for (int q = t; q < m; q += kSel) dcur[q] -= c0[q] * c0[q] * ip;
+      if (t == 0) {
+        gs[ng] = cnt;
+        gn[ng] = 1;
+        einv[ng][0] = ip;
+        sel[cnt] = pk;
+        kind[cnt] = 1;
+        taken[pk >> 5] |= 1u << (pk & 31);
+      }
+      ++cnt;
+    } else {
+      const double* c1 = V + (long long)(cnt + 1) * m;
+      const double a = c0[k], b = c0[r], c = c1[r];
+      const double det = a * c - b * b;
+      const double e00 = c / det, e01 = -b / det, e11 = a / det;
+      for (int q = t; q < m; q += kSel)
+        dcur[q] -= e00 * c0[q] * c0[q] + 2.0 * e01 * c0[q] * c1[q] + e11 * c1[q] * c1[q];
+      if (t == 0) {
+        gs[ng] = cnt;
+        gn[ng] = 2;
+        einv[ng][0] = e00;
+        einv[ng][1] = e01;
+        einv[ng][2] = e11;
+        sel[cnt] = k;
+        kind[cnt] = 2;
+        sel[cnt + 1] = r;
+        kind[cnt + 1] = 3;
+        taken[k >> 5] |= 1u << (k & 31);
+        taken[r >> 5] |= 1u << (r & 31);
+      }
+      cnt += 2;
+    }
+    ++ng;
     __syncthreads();
   }
-  if (t == 0) {
+  if (t == 0) {   // exchange pairs: window positions not chosen <-> chosen positions outside
     bool in_window[kGJ];
+    int wpos[kGJ];
     for (int w = 0; w < nb; ++w) in_window[w] = false;
+    for (int c = 0; c < nb; ++c)
+      if (sel[c] < nb) in_window[sel[c]] = true;
     int q = 0;
-    for (int s = 0; s < nb; ++s) {
-      if (chosen[s] < nb)
-        in_window[chosen[s]] = true;
-      else
-        sw[1 + kGJ + q++] = (int)(k0 + chosen[s]);
-    }
-    int w2 = 0;
     for (int w = 0; w < nb; ++w)
-      if (!in_window[w]) sw[1 + w2++] = (int)(k0 + w);
-    sw[0] = q;   // q == w2
+      if (!in_window[w]) wpos[q++] = w;
+    int o = 0;
+    for (int c = 0; c < nb; ++c) {
+      int pos = sel[c];
+      if (pos >= nb) {
+        sw[1 + o] = (int)(k0 + wpos[o]);
+        sw[1 + kGJ + o] = (int)(k0 + pos);
+        pos = wpos[o];
+        ++o;
+      }
+      sw[1 + 2 * kGJ + c] = pos;
+      sw[1 + 3 * kGJ + c] = kind[c];
+    }
+    sw[0] = o;
   }
 }
 
@@ -541,66 +676,30 @@ __global__ void k_gj_swap_cols(double* __restrict__ A, long long n, const int* _
 }
 
 // Inverts the symmetric pivot block [k0, k0 + nb) in LDS by Gauss-Jordan
-// sweeps in Bunch-Kaufman order: among the block's unswept indices take k with
-// the largest |M_kk| and lambda = max |M_ik| (i unswept, row r); sweep k alone
-// when |M_kk| >= alpha lambda or |M_kk| sigma >= alpha lambda^2 (sigma = max
-// |M_ir| over unswept i != r), r alone when |M_rr| >= alpha sigma, else the
-// 2x2 block {k, r} (alpha = (1 + sqrt 17) / 8).  flag[1] accumulates the
-// negative eigenvalues of the pivots; flag[0] is set when a pivot (or a 2x2
-// determinant against its largest entry) is not finite or at most tol *
-// scale[0] in magnitude (numerically singular).
+// sweeps in the order and grouping k_gj_choose recorded (sw).  flag[1]
+// accumulates the negative eigenvalues of the pivots; flag[0] is set when a
+// pivot (or a 2x2 determinant against its largest entry) is not finite or at
+// most tol * scale[0] in magnitude (numerically singular).
 __global__ void __launch_bounds__(256) k_gj_pivot(double* __restrict__ A, long long n, long long k0, int nb,
                                                   double* __restrict__ Pinv, int* flag, const double* scale,
-                                                  double tol) {
+                                                  double tol, const int* __restrict__ sw) {
   __shared__ double M[kGJ][kGJ + 1];
   __shared__ double colk[kGJ], rowk[kGJ], colr[kGJ], rowr[kGJ];
-  __shared__ int done[kGJ];
-  __shared__ int sel[2];
   // thread t owns column j = t % kGJ of rows t / kGJ + 4 r (256 threads)
   constexpr int kRows = 256 / kGJ;
-  const double alpha = 0.6403882032022076;   // (1 + sqrt(17)) / 8
   const int t = threadIdx.x;
   const int j = t % kGJ, i0 = t / kGJ;
   const double thr = tol * scale[0];
+  const int* pos = sw + 1 + 2 * kGJ;
+  const int* kind = sw + 1 + 3 * kGJ;
   if (j < nb)
     for (int i = i0; i < nb; i += kRows) M[i][j] = A[(k0 + i) * n + k0 + j];
-  if (t < kGJ) done[t] = 0;
   __syncthreads();
   bool bad = false;   // pivot checks of thread 0, written once at the end
   int neg = 0;
-  for (int swept = 0; swept < nb;) {
-    if (t < 64) {   // pivot choice by the first wave (lane = block index)
-      const bool cand = t < nb && !done[t];
-      auto mag = [](double x) { return isfinite(x) ? fabs(x) : INFINITY; };   // non-finite: chosen, then flagged
-      double v = cand ? mag(M[t][t]) : -1.0;
-      int k = t;
-      wave_argmax(v, k);
-      const double akk = v;
-      double lv = (cand && t != k) ? mag(M[t][k]) : -1.0;
-      int r = t;
-      wave_argmax(lv, r);
-      int pk = k, pr = -1;
-      if (lv > 0.0 && akk < alpha * lv) {
-        double sv = (cand && t != r) ? mag(M[t][r]) : -1.0;
-        int ri = t;
-        wave_argmax(sv, ri);
-        if (akk * sv >= alpha * lv * lv) {
-          pk = k;
-        } else if (mag(M[r][r]) >= alpha * sv) {
-          pk = r;
-        } else {
-          pk = k;
-          pr = r;
-        }
-      }
-      if (t == 0) {
-        sel[0] = pk;
-        sel[1] = pr;
-      }
-    }
-    __syncthreads();
-    const int k = sel[0], r = sel[1];
-    if (r < 0) {   // 1x1 pivot
+  for (int step = 0; step < nb;) {
+    const int k = pos[step];
+    if (kind[step] == 1) {   // 1x1 pivot
       if (t < nb) {
         colk[t] = M[t][k];
         rowk[t] = M[k][t];
@@ -610,7 +709,6 @@ __global__ void __launch_bounds__(256) k_gj_pivot(double* __restrict__ A, long l
       if (t == 0) {
         bad = bad || !(fabs(p) > thr) || !isfinite(p);
         neg += p < 0.0 ? 1 : 0;
-        done[k] = 1;
       }
       const double pinv = 1.0 / p;
       if (j < nb) {
@@ -624,8 +722,9 @@ __global__ void __launch_bounds__(256) k_gj_pivot(double* __restrict__ A, long l
             M[i][j] -= colk[i] * rj;
         }
       }
-      swept += 1;
+      step += 1;
     } else {   // 2x2 pivot {k, r}: E = [[a, b], [b, c]]
+      const int r = pos[step + 1];
       if (t < nb) {
         colk[t] = M[t][k];
         rowk[t] = M[k][t];
@@ -638,8 +737,6 @@ __global__ void __launch_bounds__(256) k_gj_pivot(double* __restrict__ A, long l
       if (t == 0) {
         bad = bad || !(fabs(det) > thr * fmax(fabs(b), fmax(fabs(a), fabs(c)))) || !isfinite(det);
         neg += det < 0.0 ? 1 : (a + c < 0.0 ? 2 : 0);
-        done[k] = 1;
-        done[r] = 1;
       }
       const double e00 = c / det, e01 = -b / det, e11 = a / det;   // E^-1
       if (j < nb) {
@@ -656,7 +753,7 @@ __global__ void __launch_bounds__(256) k_gj_pivot(double* __restrict__ A, long l
             M[i][j] -= colk[i] * rk + colr[i] * rr;
         }
       }
-      swept += 2;
+      step += 2;
     }
     __syncthreads();
   }
@@ -925,16 +1022,15 @@ void material_bits(uint32_t* bits, long long ncells, int N, int dim, int n1, con
                      h, incl, nincl, nwords);
 }
 
-void gj_choose_block(double* A, long long n, long long k0, int nb, double* key, int* sw, int* perm, hipStream_t s) {
-  if (n - k0 <= nb) return;   // the window already holds every unswept position
-  hipLaunchKernelGGL(k_gj_keys, dim3(grid_for(n - k0)), dim3(kVB), 0, s, A, n, k0, key);
-  hipLaunchKernelGGL(k_gj_select, dim3(1), dim3(kVB), 0, s, key, n, k0, nb, sw);
+void gj_choose_block(double* A, long long n, long long k0, int nb, double* key, double* V, int* sw, int* perm,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_gj_choose, dim3(1), dim3(kSel), 0, s, A, n, k0, nb, key, V, sw);
   hipLaunchKernelGGL(k_gj_swap_rows, dim3(grid_for((long long)kGJ * n)), dim3(kVB), 0, s, A, n, sw);
   hipLaunchKernelGGL(k_gj_swap_cols, dim3(grid_for((long long)kGJ * n)), dim3(kVB), 0, s, A, n, sw, perm);
 }
 void gj_pivot(double* A, long long n, long long k0, int nb, double* Pinv, int* flag, const double* scale, double tol,
-              hipStream_t s) {
-  hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(256), 0, s, A, n, k0, nb, Pinv, flag, scale, tol);
+              const int* sw, hipStream_t s) {
+  hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(256), 0, s, A, n, k0, nb, Pinv, flag, scale, tol, sw);
 }
 void diag_absmax(const double* A, long long n, double* scale, hipStream_t s) {
   hipLaunchKernelGGL(k_diag_absmax, dim3(1), dim3(kVB), 0, s, A, n, scale);
@@ -957,8 +1053,8 @@ void dense_inverse(double* A, long long n, int* perm, const DenseInvWork& w, dou
   diag_absmax(A, n, w.scale, s);
   for (long long k0 = 0; k0 < n; k0 += kGJ) {
     const int nb = (int)std::min<long long>(kGJ, n - k0);
-    gj_choose_block(A, n, k0, nb, w.key, w.sw, perm, s);
-    gj_pivot(A, n, k0, nb, w.Pinv, w.flag, w.scale, tol, s);
+    gj_choose_block(A, n, k0, nb, w.key, w.C, w.sw, perm, s);
+    gj_pivot(A, n, k0, nb, w.Pinv, w.flag, w.scale, tol, w.sw, s);
     gj_panels(A, n, k0, nb, w.Pinv, w.C, w.R, s);
     gj_update(A, n, k0, nb, w.C, w.R, s);
     gj_finish(A, n, k0, nb, w.C, w.R, w.Pinv, s);

@@ -114,7 +114,7 @@ void material_bits(uint32_t* bits, long long ncells, int N, int dim, int n1, con
 // number of negative pivots (the inertia of the matrix).
 void diag_absmax(const double* A, long long n, double* scale, hipStream_t s);
 // Work arrays of the pivoted dense inverse: Pinv 64 x 64, C and R n x 64,
-// key n, sw 1 + 2 * 64 ints, flag 2 ints (zeroed by the caller), scale 1.
+// key n, sw 1 + 4 * 64 ints, flag 2 ints (zeroed by the caller), scale 1.
 struct DenseInvWork {
   double *Pinv, *C, *R, *key, *scale;
   int *sw, *flag;
@@ -127,14 +127,16 @@ void dense_inverse(double* A, long long n, int* perm, const DenseInvWork& w, dou
 // out[perm[i]][perm[j]] = A[i][j]; v[i] = i
 void unpermute(const double* A, const int* perm, long long n, double* out, hipStream_t s);
 void iota(int* v, long long n, hipStream_t s);
-// Most free coarse DoFs the pivoted inverse handles (LDS bitmap of the block choice).
+// Most free coarse DoFs the pivoted inverse handles (LDS bitmap of the pivot choice).
 constexpr int kGJMaxFree = 20480;
-// Symmetric exchange that brings the nb unswept positions with the largest
-// |diagonal| into [k0, k0 + nb); perm (free index -> DoF) follows.  key: n
-// doubles of scratch, sw: 1 + 2 * 64 ints.
-void gj_choose_block(double* A, long long n, long long k0, int nb, double* key, int* sw, int* perm, hipStream_t s);
+// Chooses a block step's pivots (Bunch-Kaufman on the current Schur
+// complement) and exchanges them into [k0, k0 + nb); perm (free index -> DoF)
+// follows.  key: n doubles, V: 64 n doubles of scratch; sw: 1 + 4 * 64 ints
+// (exchange pairs and the pivot list that gj_pivot follows).
+void gj_choose_block(double* A, long long n, long long k0, int nb, double* key, double* V, int* sw, int* perm,
+                     hipStream_t s);
 void gj_pivot(double* A, long long n, long long k0, int nb, double* Pinv, int* flag, const double* scale, double tol,
-              hipStream_t s);
+              const int* sw, hipStream_t s);
 void gj_panels(const double* A, long long n, long long k0, int nb, const double* Pinv, double* Cb, double* R,
                hipStream_t s);
 void gj_update(double* A, long long n, long long k0, int nb, const double* Cb, const double* R, hipStream_t s);

@@ -87,8 +87,8 @@ def lib():
         "mfh_last_error": (ctypes.c_char_p, [_P]),
         "mfh_apply_dirichlet": (st, [_P, _P, _D, ctypes.c_double]),
         "mfh_newton_solve": (st, [_P, _P, _D, _D, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double,
-                                  ctypes.c_double, ctypes.c_int, ctypes.POINTER(NewtonRecord), ctypes.c_int,
-                                  ctypes.POINTER(ctypes.c_int)]),
+                                  ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.POINTER(NewtonRecord),
+                                  ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
         "mfh_external_force": (st, [_P, _D, _P]),
         "mfh_level_displacement": (st, [_P, ctypes.c_int, _P]),
         "mfh_level_diagonal": (st, [_P, ctypes.c_int, _P]),
@@ -291,7 +291,7 @@ class Problem:
         _check(lib().mfh_apply_dirichlet(self.handle, _ptr(u), fv, scale), self.handle)
 
     def newton_solve(self, u, face_values, n_steps, cg_rtol=1e-8, cg_max_it=200, du_tol=1e-5, r_tol=1e-8,
-                     max_newton=20, max_records=512, raise_on_error=True, face_traction=None):
+                     max_newton=20, max_records=512, raise_on_error=True, face_traction=None, max_seconds=0.0):
         _arg(u, "u", self.device, self.n_dofs())
         face_values = self._faces(face_values, "face_values")
         if face_traction is not None:
@@ -301,7 +301,7 @@ class Problem:
         recs = (NewtonRecord * max_records)()
         n = ctypes.c_int()
         st = lib().mfh_newton_solve(self.handle, _ptr(u), fv, ft, n_steps, cg_rtol, cg_max_it, du_tol, r_tol,
-                                    max_newton, recs, max_records, ctypes.byref(n))
+                                    max_newton, float(max_seconds), recs, max_records, ctypes.byref(n))
         out = [recs[i].as_dict() for i in range(min(n.value, max_records))]
         if raise_on_error:
             _check(st, self.handle)
@@ -439,12 +439,12 @@ def dense_inverse(a, stream=None):
         raise ValueError("a: expected a device tensor")
     work_a = a.clone()
     inv = torch.empty_like(a)
+    stream = torch.cuda.current_stream(a.device) if stream is None else stream
+    neg = ctypes.c_int()
     size = ctypes.c_size_t()
     _check(lib().mfh_dense_inverse_workspace(n, ctypes.byref(size)))
     ws = torch.empty(size.value + 256, dtype=torch.uint8, device=a.device)
     base = ws.data_ptr() + (-ws.data_ptr()) % 256
-    stream = torch.cuda.current_stream(a.device) if stream is None else stream
-    neg = ctypes.c_int()
     _check(lib().mfh_dense_inverse(_ptr(work_a), _ptr(inv), n, ctypes.c_void_p(base), size.value,
                                    ctypes.c_void_p(stream.cuda_stream), ctypes.byref(neg)))
     return inv, neg.value

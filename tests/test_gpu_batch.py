@@ -169,3 +169,60 @@ def test_graph_vcycle_replays_match_eager(vdt):
     assert rel_g <= 1e-8 and rel_e <= 1e-8
     assert abs(it_g - it_e) <= 1
     assert rel_l2(host(x_g), host(x_e)) <= 1e-7
+
+
+def _real_subset(k=8, seed=66):
+    """A seeded subset of the 256-problem batch at its real sizes, covering
+    every degree and every mesh size of the recipe."""
+    descs = W.batch_of_cubes()
+    rng = np.random.default_rng(seed)
+    pick, seen = [], set()
+    for i in rng.permutation(len(descs)):      # first cover each (degree, N) pair seen in order
+        key = (descs[i]["degree"], descs[i]["n_cells"])
+        if key not in seen:
+            seen.add(key)
+            pick.append(int(i))
+        if len(pick) == k:
+            break
+    return [descs[i] for i in sorted(pick)]
+
+
+def test_batch_real_sizes_against_oracle_rows():
+    """Eight problems of the batch at their real sizes (8^3..24^3 cells, Q1..Q3,
+    up to 1.17 M DoFs) in one batched vmult, FP64 and FP32, against the
+    oracle's assembled tangent on sampled rows (corner, edge, face and
+    interior nodes of every component)."""
+    descs = _real_subset()
+    assert {d["degree"] for d in descs} == {1, 2, 3} and len({d["n_cells"] for d in descs}) >= 3
+    mu, lam = W.two_phase_material()
+    probs, fields = [], []
+    for d in descs:
+        log_case("batch_real", n_cells=d["n_cells"], degree=d["degree"])
+        m = fe.Mesh(3, d["n_cells"], d["degree"])
+        incl, u, x = W.batch_fields(d, coords=m.coords_1d())
+        P = Problem(3, d["n_cells"], d["degree"], n_levels=d["n_levels"], mu=tuple(mu), lam=tuple(lam),
+                    inclusions=incl, dirichlet_mask=d["mask"], qp_policy=2, stream=torch.cuda.Stream())
+        probs.append(P)
+        fields.append((d, m, incl, u, x))
+    torch.cuda.synchronize()
+    B = Batch(probs)
+    assert all(mj > 0 for mj in B.set_deformation([sdev(f[3]) for f in fields]))
+    for dt, tdt in ((F64, torch.float64), (F32, torch.float32)):
+        xs = [sdev(f[4], tdt) for f in fields]
+        ys = [torch.full_like(x, float("nan")) for x in xs]
+        B.tangent_vmult(xs, ys)
+        torch.cuda.synchronize()
+        for (d, m, incl, u, x), y in zip(fields, ys):
+            L = m.L
+            rng = np.random.default_rng(d["x_seed"])
+            nodes = np.r_[0, L - 1, L * L - 1, m.n_nodes - 1, L * (L // 2) + L // 2,
+                          rng.choice(m.n_nodes, 20, replace=False)]
+            rows = np.unique(np.concatenate([nodes + c * m.n_nodes for c in range(3)]))
+            xin = x if dt == F64 else x.astype(np.float32).astype(np.float64)
+            ref = fe.vmult_rows(m, fe.Material(mu, lam, incl), u, xin, rows, m.constrained(d["mask"]))
+            got = host(y)[rows]
+            err = np.abs(got - ref).max() / np.abs(ref).max()
+            print(f"[batch_real] N {d['n_cells']} p {d['degree']} {'f64' if dt == F64 else 'f32'}: "
+                  f"max rel {err:.2e}", flush=True)
+            assert err <= (1e-12 if dt == F64 else 1e-5)
+            assert np.all(np.isfinite(host(y)))
