@@ -393,6 +393,17 @@ mfh_status mfh_chebyshev(mfh_problem* problem, int level, const void* f_dev, voi
 mfh_status mfh_dense_inverse_workspace(long long n, size_t* bytes);
 mfh_status mfh_dense_inverse(double* a_dev, double* inv_dev, long long n, void* work_dev, size_t work_bytes,
                              void* stream, int* negative);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * dense inverse with its work arrays in a static device array of the library
+ * (2.25 MiB per GPU, held until the process ends) instead of a caller
+ * workspace.  Allocates nothing.  Runs on the calling thread's current
+ * device (stream must belong to it; NULL: default stream); 1 <= n <= 2048
+ * (INVALID_ARG otherwise).  All calls on one GPU share the array, so calls
+ * that overlap in time on one GPU (other threads, other streams) race and
+ * must be serialised by the caller.  Arguments, results and errors as for
+ * mfh_dense_inverse.  Synchronises. */
+mfh_status mfh_dense_inverse_static(double* a_dev, double* inv_dev, long long n, void* stream, int* negative);
 
 /* Number of negative eigenvalues of the coarse-level tangent about the current
  * linearisation point (the signs of its elimination pivots).  The V-cycle's

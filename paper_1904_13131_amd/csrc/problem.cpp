@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <type_traits>
@@ -1766,6 +1767,48 @@ mfh_status mfh_dense_inverse(double* a, double* inv, long long n, void* work, si
     if (work_bytes < dense_inverse_layout(n, nullptr, nullptr, nullptr))
       throw Error(MFH_ERR_WORKSPACE, "work smaller than mfh_dense_inverse_workspace reports");
     dense_inverse_run(a, inv, n, static_cast<char*>(work), static_cast<hipStream_t>(stream), negative);
+  });
+}
+
+// ---- the same without a workspace (callers that cannot allocate) ----------
+// Work arrays for n <= kStaticInvMaxN in one file-scope device array; each GPU
+// the library runs on holds its own copy until the process ends.  Host code
+// never uses the array's name as an address: the device address comes from
+// hipGetSymbolAddress, once per device, with that device current.
+namespace {
+constexpr long long kStaticInvMaxN = 2048;
+constexpr size_t kStaticInvBytes = (size_t)9 << 18;   // 2.25 MiB
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+static __device__ __align__(256) char scratch[kStaticInvBytes];
+
+namespace {
+char* scratch_for_current_device() {
+  int dev = -1;
+  HIPCHECK(hipGetDevice(&dev));
+  need(dev >= 0 && dev < kMaxDevices, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIPCHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    need(p != nullptr && ((uintptr_t)p & 255) == 0, "scratch symbol address is not 256-byte aligned");
+    g_scratch_ptr[dev] = static_cast<char*>(p);
+  }
+  return g_scratch_ptr[dev];
+}
+}  // namespace
+
+mfh_status mfh_dense_inverse_static(double* a, double* inv, long long n, void* stream, int* negative) {
+  return guarded(nullptr, [&] {
+    need(a && inv && negative, "NULL argument");
+    need(n >= 1 && n <= kStaticInvMaxN, "n must be 1..2048 for the allocation-free dense inverse");
+    need(a + n * n <= inv || inv + n * n <= a, "a and inv must not overlap");
+    if (dense_inverse_layout(n, nullptr, nullptr, nullptr) > kStaticInvBytes)
+      throw Error(MFH_ERR_WORKSPACE, "static scratch smaller than the work arrays");
+    dense_inverse_run(a, inv, n, scratch_for_current_device(), static_cast<hipStream_t>(stream), negative);
   });
 }
 

@@ -100,6 +100,7 @@ def lib():
         "mfh_coarse_inertia": (st, [_P, ctypes.POINTER(ctypes.c_int)]),
         "mfh_dense_inverse_workspace": (st, [ctypes.c_longlong, ctypes.POINTER(ctypes.c_size_t)]),
         "mfh_dense_inverse": (st, [_P, _P, ctypes.c_longlong, _P, ctypes.c_size_t, _P, ctypes.POINTER(ctypes.c_int)]),
+        "mfh_dense_inverse_static": (st, [_P, _P, ctypes.c_longlong, _P, ctypes.POINTER(ctypes.c_int)]),
         "mfh_enable_graphs": (st, [_P, ctypes.c_int]),
         "mfh_batch_workspace_size": (st, [ctypes.c_int, ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_size_t)]),
         "mfh_batch_create": (st, [ctypes.c_int, ctypes.POINTER(_P), _P, ctypes.c_size_t, _P,
@@ -427,10 +428,12 @@ class Problem:
         return x
 
 
-def dense_inverse(a, stream=None):
+def dense_inverse(a, stream=None, static=False):
     """The coarse level's pivoted dense inverse on a symmetric FP64 device
     matrix: returns (A^-1, number of negative eigenvalues); `a` is left
-    unchanged (the library works on a copy)."""
+    unchanged (the library works on a copy).  static=True calls the
+    allocation-free entry point (n <= 2048, work arrays in the library's
+    static device array)."""
     if not isinstance(a, torch.Tensor) or a.dim() != 2 or a.shape[0] != a.shape[1]:
         raise ValueError("a: expected a square 2-D torch tensor")
     n = a.shape[0]
@@ -441,6 +444,11 @@ def dense_inverse(a, stream=None):
     inv = torch.empty_like(a)
     stream = torch.cuda.current_stream(a.device) if stream is None else stream
     neg = ctypes.c_int()
+    if static:
+        with torch.cuda.device(a.device):
+            _check(lib().mfh_dense_inverse_static(_ptr(work_a), _ptr(inv), n, ctypes.c_void_p(stream.cuda_stream),
+                                                  ctypes.byref(neg)))
+        return inv, neg.value
     size = ctypes.c_size_t()
     _check(lib().mfh_dense_inverse_workspace(n, ctypes.byref(size)))
     ws = torch.empty(size.value + 256, dtype=torch.uint8, device=a.device)
