@@ -104,8 +104,10 @@ def time_vmult(P, x, y, steps, warmup, cold=False, flush=None):
     HIP event pair on the library's stream around all of them (the step time);
     a second pass brackets every call with its own event pair (per-call
     durations for the median and minimum; a pair costs a few microseconds, so
-    it stays out of the step time).  cold: a 512 MB buffer is rewritten before
-    every call, which evicts the working set from the caches."""
+    it stays out of the step time).  cold: a 512 MB buffer is read (summed)
+    before every call, which evicts the working set from the caches; a
+    rewritten buffer would also leave dirty lines whose write-back the timed
+    call would pay."""
     import torch
     for _ in range(warmup):
         P.tangent_vmult(x, y)
@@ -114,14 +116,14 @@ def time_vmult(P, x, y, steps, warmup, cold=False, flush=None):
     e0.record(P.stream)
     for _ in range(steps):
         if cold:
-            flush.add_(1.0)
+            flush.sum()
         P.tangent_vmult(x, y)
     e1.record(P.stream)
     torch.cuda.synchronize()
     pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     for b, e in pairs:
         if cold:
-            flush.add_(1.0)
+            flush.sum()
         b.record(P.stream)
         P.tangent_vmult(x, y)
         e.record(P.stream)
@@ -704,7 +706,7 @@ def main(argv=None):
     u = torch.as_tensor(w["u"], device="cuda")
     x64 = torch.as_tensor(w["x"], device="cuda")
     x32 = x64.float()
-    flush = torch.zeros(128 * 1024 * 1024, dtype=torch.float32, device="cuda")   # 512 MB > MALL
+    flush = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device="cuda")   # 512 MB > MALL, read to flush
     if a.calibrate_copy:
         src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
