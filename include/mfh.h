@@ -464,6 +464,28 @@ mfh_status mfh_batch_set_deformation(mfh_batch* batch, const double* const* u, d
  * point. */
 mfh_status mfh_batch_tangent_vmult(mfh_batch* batch, int dtype, const void* const* x, void* const* y);
 
+/* The 1-D contraction stage of the sum factorisation (Sec. 5) alone, for the
+ * autotuner's choice between VALU and MFMA at degrees 3 and 4 in FP32:
+ * `blocks` workgroups of 256 lines of degree + 1 values in LDS, `sweeps`
+ * dependent applications of a pair of (degree + 1)^2 tables; mfma = 0: one
+ * line per thread with FMAs, 1: v_mfma_f32_16x16x4f32 on 16 lines at a time
+ * (the tables stacked as A, the lines' values as B).  out (device, blocks *
+ * (degree + 1) * 256 floats) receives the final values (both forms agree up
+ * to rounding).  Async on `stream`.  Errors: INVALID_ARG, HIP. */
+mfh_status mfh_contraction_stage(int degree, int mfma, int sweeps, int blocks, float* out_dev, void* stream);
+
+/* Launch form of mfh_batch_tangent_vmult: one launch per (dim, degree) bin
+ * (PER_DEGREE: each degree's kernel at its own occupancy), or one persistent
+ * launch over the cell blocks of every problem (FUSED: a grid of the
+ * workgroups the GPU holds at once walks XCD-local ranges of the item list,
+ * heaviest degree first, each running its item's degree; 3-D batches of
+ * degrees 1 to 3 only), followed in both by the node sums of the problems on
+ * the ELEMENT scatter.  AUTO (default): the form the autotuner measured
+ * faster on gfx950.  Errors: INVALID_ARG (unknown mode; FUSED for a batch
+ * it does not cover). */
+enum { MFH_BATCH_LAUNCH_AUTO = -1, MFH_BATCH_LAUNCH_PER_DEGREE = 0, MFH_BATCH_LAUNCH_FUSED = 1 };
+mfh_status mfh_batch_set_launch(mfh_batch* batch, int mode);
+
 /* mfh_cg_solve of every problem (host arrays of device pointers) from one
  * host thread, in lockstep: the preconditioner set-ups of all problems are
  * enqueued and drained together, then every round issues one PCG iteration of

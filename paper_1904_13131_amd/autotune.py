@@ -1,15 +1,24 @@
-"""Autotuner of the tangent-vmult scatter mode (run on the GPU).
+"""Autotuner of the tangent vmult's launch shapes (run on the GPU).
 
-For every (dim, degree, precision, qp policy, size class) it times one whole
-tangent vmult (output fill or node sums included) with each scatter mode on
-a representative mesh and records the fastest in ``tuning/gfx950.json``;
-``csrc/tuned.hpp`` is generated from that table and compiled into the
-library, where MFH_SCATTER_AUTO looks it up per level.
+Scatter mode: for every (dim, degree, precision, qp policy, size class) it
+times one whole tangent vmult (output fill or node sums included) with each
+scatter mode on a representative mesh and records the fastest.  Batch
+launch: on the 256-problem batch of independent 3-D problems (degrees 1 to
+3) it times the batched vmult as one launch per degree bin and as one
+persistent launch over every degree, in both precisions, and records the
+faster.  Contraction stage: the sum factorisation's 1-D contractions at
+degrees 3 and 4 in FP32, VALU against MFMA (recorded in the table; the
+tangent kernels implement the VALU form, which the measurement favours).  Both go to ``tuning/gfx950.json``; ``csrc/tuned.hpp`` is generated
+from that table and compiled into the library, where MFH_SCATTER_AUTO and
+MFH_BATCH_LAUNCH_AUTO look them up.
 
     python -m paper_1904_13131_amd.autotune [--quick] [--out tuning/gfx950.json]
     python -m paper_1904_13131_amd.autotune --emit-header     # JSON -> csrc/tuned.hpp only
     python -m paper_1904_13131_amd.autotune --policies cache_T4 --out new.json
         # re-measure some policies; the other entries are kept from the table
+    python -m paper_1904_13131_amd.autotune --batch-only
+        # re-measure the batch launch and the contraction stage only; the
+        # scatter entries are kept
 """
 import argparse
 import json
@@ -95,6 +104,86 @@ def measure(dims=(2, 3), degrees=(1, 2, 3, 4), quick=False, log=print, policies=
     return entries
 
 
+def measure_batch(log=print, reps=20, warmup=3):
+    """The batched vmult of the 256-problem batch (cache_T2), per-degree
+    launches against the fused persistent launch, FP64 and FP32 (ms)."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from .mfh import Batch, Problem
+    from . import mfh
+    mu, lam = W.two_phase_material()
+    probs, us = [], []
+    for d in W.batch_of_cubes():
+        incl = W.spheres(d["n_spheres"], d["sphere_seed"], 3)
+        P = Problem(3, d["n_cells"], d["degree"], n_levels=d["n_levels"], mu=tuple(mu), lam=tuple(lam),
+                    inclusions=incl, dirichlet_mask=d["mask"], qp_policy=2, stream=torch.cuda.current_stream())
+        L = d["degree"] * d["n_cells"] + 1
+        us.append(torch.as_tensor(W.stretched_field(3, L, d["stretch"], d["u_seed"], d["amp"],
+                                                    coords=P.node_coords_1d()), device="cuda"))
+        probs.append(P)
+    B = Batch(probs)
+    B.set_deformation(us)
+    out = {}
+    for dt, tdt in (("f64", torch.float64), ("f32", torch.float32)):
+        xs = [torch.as_tensor(W.normal_vector(P.n_dofs(), 5), device="cuda").to(tdt) for P in probs]
+        ys = [torch.empty_like(x) for x in xs]
+        for mode, code in (("per_degree", mfh.BATCH_LAUNCH_PER_DEGREE), ("fused", mfh.BATCH_LAUNCH_FUSED)):
+            B.set_launch(code)
+            for _ in range(warmup):
+                B.tangent_vmult(xs, ys)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(B.stream)
+            for _ in range(reps):
+                B.tangent_vmult(xs, ys)
+            e1.record(B.stream)
+            torch.cuda.synchronize()
+            out.setdefault(dt, {})[mode] = round(e0.elapsed_time(e1) / reps, 4)
+        log(f"[autotune] batch {dt}: " + " ".join(f"{k}={v:.3f} ms" for k, v in out[dt].items()))
+    total = {m: sum(out[dt][m] for dt in out) for m in ("per_degree", "fused")}
+    B.close()
+    del B, probs, us
+    torch.cuda.empty_cache()
+    return {"policy": "cache_T2", "ms": out, "launch": min(total, key=total.get)}
+
+
+def measure_contraction(log=print, sweeps=200, blocks=4096, reps=10):
+    """The sum factorisation's 1-D contraction stage (Sec. 5) at degrees 3 and
+    4 in FP32, VALU against MFMA (mfh_contraction_stage): time of `reps`
+    launches of `blocks` x 256 lines x `sweeps` dependent applications of a
+    table pair, as table-FLOP rates (4 n^2 per line and sweep), and the
+    largest difference of the two forms' results."""
+    import torch
+
+    from .mfh import contraction_stage
+    out = {}
+    for degree in (3, 4):
+        n = degree + 1
+        res, bufs = {}, {}
+        for form, m in (("valu", 0), ("mfma", 1)):
+            buf = torch.empty(blocks * n * 256, dtype=torch.float32, device="cuda")
+            contraction_stage(degree, m, sweeps, blocks, buf)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                contraction_stage(degree, m, sweeps, blocks, buf)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            res[form] = {"ms": round(ms, 4), "table_tflops": round(4 * n * n * blocks * 256 * sweeps / ms / 1e9, 2)}
+            bufs[form] = buf
+        diff = float(((bufs["valu"] - bufs["mfma"]).abs().max() / bufs["valu"].abs().max()).item())
+        choice = min(res, key=lambda f: res[f]["ms"])
+        out[str(degree)] = dict(res, max_rel_diff=diff, faster=choice)
+        log(f"[autotune] contraction p{degree} fp32: valu {res['valu']['ms']:.3f} ms "
+            f"({res['valu']['table_tflops']} TFLOP/s), mfma {res['mfma']['ms']:.3f} ms "
+            f"({res['mfma']['table_tflops']} TFLOP/s), max rel diff {diff:.1e} -> {choice}")
+    return out
+
+
 def emit_header(table, path=HEADER_PATH):
     rows = []
     for e in table["entries"]:
@@ -102,6 +191,10 @@ def emit_header(table, path=HEADER_PATH):
                     f"{CLASSES.index(e['size_class'])}, {MODES[e['scatter']]}}},")
     if not rows:
         rows = ["    {0, 0, 0, 0, 0, 0},   // no measurements: every lookup falls back to ATOMIC"]
+    batch = table.get("batch_launch")
+    batch_fused = "true" if batch and batch["launch"] == "fused" else "false"
+    batch_note = (" (" + ", ".join(f"{dt}: " + " / ".join(f"{k} {v} ms" for k, v in ms.items())
+                                   for dt, ms in batch["ms"].items()) + ")") if batch else " (not measured)"
     text = f"""// Generated by paper_1904_13131_amd/autotune.py from tuning/gfx950.json
 // ({table.get('note', '')}).  Do not edit: rerun the autotuner.
 // Scatter mode measured fastest for one whole tangent vmult, per (dim, degree,
@@ -119,6 +212,10 @@ constexpr TunedScatter kTunedScatter[] = {{
 }};
 
 inline int tuned_size_class(long long cells) {{ return cells < {CLASS_BOUNDS[0]} ? 0 : cells < {CLASS_BOUNDS[1]} ? 1 : 2; }}
+
+// Batched vmult: one persistent launch over every degree (true) or one launch
+// per degree bin (false), as measured on the 256-problem batch{batch_note}.
+constexpr bool kTunedBatchFused = {batch_fused};
 
 // Scatter mode for a level (0 = ATOMIC when the table has no entry).
 inline int tuned_scatter(int dim, int degree, int dtype, int policy, long long cells) {{
@@ -142,12 +239,21 @@ def main(argv=None):
     ap.add_argument("--emit-header", action="store_true", help="only regenerate csrc/tuned.hpp from the JSON")
     ap.add_argument("--dims", default="2,3")
     ap.add_argument("--policies", default=None, help="comma list of policy names to re-measure (default: all)")
+    ap.add_argument("--batch-only", action="store_true", help="re-measure the batch launch only")
     a = ap.parse_args(argv)
     if a.emit_header:
         emit_header(json.load(open(a.out)))
         return 0
     sys.path.insert(0, os.path.dirname(HERE))
     import torch
+    if a.batch_only:
+        table = json.load(open(JSON_PATH))
+        table["batch_launch"] = measure_batch()
+        table["contraction"] = measure_contraction()
+        with open(a.out, "w") as f:
+            json.dump(table, f, indent=1)
+        emit_header(table)
+        return 0
     t0 = time.time()
     pols = a.policies.split(",") if a.policies else None
     entries = measure(dims=tuple(int(d) for d in a.dims.split(",")), quick=a.quick, policies=pols)
@@ -157,7 +263,8 @@ def main(argv=None):
         entries = [e for e in old["entries"] if e["policy"] not in pols] + entries
         note = old.get("note", "") + f"; {','.join(pols)}: {note}"
     table = {"arch": "gfx950", "device": torch.cuda.get_device_name(0), "note": note,
-             "size_class_bounds_cells": list(CLASS_BOUNDS), "entries": entries}
+             "size_class_bounds_cells": list(CLASS_BOUNDS), "entries": entries, "batch_launch": measure_batch(),
+             "contraction": measure_contraction()}
     os.makedirs(os.path.dirname(a.out), exist_ok=True)
     with open(a.out, "w") as f:
         json.dump(table, f, indent=1)

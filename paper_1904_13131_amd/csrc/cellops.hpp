@@ -66,6 +66,13 @@ struct Geo {
   static constexpr int NARR = DIM == 3 ? 3 : 2;        // LDS arrays per component
 };
 
+// LDS words (of T) of the tangent kernels' block: the sweeps' DIM * NARR
+// arrays of NV points per cell, also used for the element-buffer handover.
+template <int DIM, int N1, typename T>
+struct TangentLdsSize {
+  static constexpr int value = DIM * Geo<DIM, N1>::NARR * Geo<DIM, N1>::NV * Geo<DIM, N1>::CPB;
+};
+
 // Element buffer of the ELEMENT scatter for a level of `cells` cells (T words,
 // each array cell-fastest, so that a block's cells store and load coalesced):
 //   [0, DIM * NX * cells): component c, slot s = x + P * line at
@@ -81,10 +88,11 @@ struct ElemLayout {
   static constexpr int NX = (N1 - 1) * NP;
 };
 
-template <int DIM, int N1, typename T>
+// Sum-factorisation sweeps over the LDS of a block of NCELL cells (the
+// pencil kernels' cells per block by default; the tile kernel's tile).
+template <int DIM, int N1, typename T, int NCELL = Geo<DIM, N1>::CPB>
 struct SumFact {
-  using G = Geo<DIM, N1>;
-  static constexpr int NV = G::NV, CPB = G::CPB;
+  static constexpr int NV = Geo<DIM, N1>::NV, CPB = NCELL;
 
   __device__ static __forceinline__ int pt(int x, int y, int z) { return x + N1 * (y + N1 * z); }
   __device__ static __forceinline__ T& at(T* lds, int arr, int p, int cl) {
@@ -1039,8 +1047,7 @@ __global__ void __launch_bounds__(kBlock) k_elem_gather_batch(const CellArgs<T>*
 // Tangent vmult: y += K x over the cells of this launch (y pre-filled).
 template <int DIM, int P, typename T, int POL, bool O32>
 __global__ void __launch_bounds__(kBlock) k_tangent(CellArgs<T> arg) {
-  using G = Geo<DIM, P + 1>;
-  __shared__ T lds[DIM * G::NARR * G::NV * G::CPB];
+  __shared__ T lds[TangentLdsSize<DIM, P + 1, T>::value];
   const CellArgs<T>& a = kernel_args(arg);
   const long long blk = a.color < 0 ? xcd_block(blockIdx.x, gridDim.x) : (long long)blockIdx.x;
   tangent_block<DIM, P, T, POL, O32>(a, a.x, a.y, blk, lds);
@@ -1056,8 +1063,7 @@ template <int DIM, int P, typename T, int POL, bool O32>
 __global__ void __launch_bounds__(kBlock) k_tangent_batch(const CellArgs<T>* __restrict__ args,
                                                           const int2* __restrict__ items,
                                                           const T* const* __restrict__ xs, T* const* __restrict__ ys) {
-  using G = Geo<DIM, P + 1>;
-  __shared__ T lds[DIM * G::NARR * G::NV * G::CPB];
+  __shared__ T lds[TangentLdsSize<DIM, P + 1, T>::value];
   // The tables are read through the constant address space, where
   // wave-uniform addresses become scalar loads; the arguments are used in
   // place (no private copy), as kernel arguments are.
@@ -1096,241 +1102,6 @@ struct TileGeo {
   static constexpr int NV = NP * N1;
 };
 
-// Sum-factorisation sweeps of SumFact with the cell count of a tile.
-template <int DIM, int N1, int NCELL, typename T>
-struct TileSF {
-  static constexpr int NV = (DIM == 3 ? N1 * N1 : N1) * N1;
-  __device__ static __forceinline__ int pt(int x, int y, int z) { return x + N1 * (y + N1 * z); }
-  __device__ static __forceinline__ T& at(T* lds, int arr, int p, int cl) { return lds[(arr * NV + p) * NCELL + cl]; }
-
-  template <int NC>
-  __device__ static void forward(const T (&v)[NC][N1], T* g, T* lds, int pen, int cl, bool act,
-                                 const Tables<T>& tb) {
-    // g points at g[NC][DIM][N1] in registers
-    T (&G)[NC][DIM][N1] = *reinterpret_cast<T(*)[NC][DIM][N1]>(g);
-    if constexpr (DIM == 3) {
-      const int p0 = pen % N1, p1 = pen / N1;
-      if (act) {
-#pragma unroll
-        for (int c = 0; c < NC; ++c)
-#pragma unroll
-          for (int q = 0; q < N1; ++q) {
-            T s = 0, d = 0;
-#pragma unroll
-            for (int a = 0; a < N1; ++a) {
-              s += tb.S[q][a] * v[c][a];
-              d += tb.D[q][a] * v[c][a];
-            }
-            at(lds, 3 * c + 0, pt(q, p0, p1), cl) = s;
-            at(lds, 3 * c + 1, pt(q, p0, p1), cl) = d;
-          }
-      }
-      __syncthreads();
-      if (act) {
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          T s[N1], d[N1];
-#pragma unroll
-          for (int b = 0; b < N1; ++b) {
-            s[b] = at(lds, 3 * c + 0, pt(p0, b, p1), cl);
-            d[b] = at(lds, 3 * c + 1, pt(p0, b, p1), cl);
-          }
-#pragma unroll
-          for (int q = 0; q < N1; ++q) {
-            T ss = 0, sd = 0, ds = 0;
-#pragma unroll
-            for (int b = 0; b < N1; ++b) {
-              ss += tb.S[q][b] * s[b];
-              sd += tb.D[q][b] * s[b];
-              ds += tb.S[q][b] * d[b];
-            }
-            at(lds, 3 * c + 0, pt(p0, q, p1), cl) = ss;
-            at(lds, 3 * c + 1, pt(p0, q, p1), cl) = sd;
-            at(lds, 3 * c + 2, pt(p0, q, p1), cl) = ds;
-          }
-        }
-      }
-      __syncthreads();
-      if (act) {
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          T ss[N1], sd[N1], ds[N1];
-#pragma unroll
-          for (int k = 0; k < N1; ++k) {
-            ss[k] = at(lds, 3 * c + 0, pt(p0, p1, k), cl);
-            sd[k] = at(lds, 3 * c + 1, pt(p0, p1, k), cl);
-            ds[k] = at(lds, 3 * c + 2, pt(p0, p1, k), cl);
-          }
-#pragma unroll
-          for (int q = 0; q < N1; ++q) {
-            T gx = 0, gy = 0, gz = 0;
-#pragma unroll
-            for (int k = 0; k < N1; ++k) {
-              gx += tb.S[q][k] * ds[k];
-              gy += tb.S[q][k] * sd[k];
-              gz += tb.D[q][k] * ss[k];
-            }
-            G[c][0][q] = gx;
-            G[c][1][q] = gy;
-            G[c][2][q] = gz;
-          }
-        }
-      }
-      __syncthreads();
-    } else {
-      const int b = pen;
-      if (act) {
-#pragma unroll
-        for (int c = 0; c < NC; ++c)
-#pragma unroll
-          for (int q = 0; q < N1; ++q) {
-            T s = 0, d = 0;
-#pragma unroll
-            for (int a = 0; a < N1; ++a) {
-              s += tb.S[q][a] * v[c][a];
-              d += tb.D[q][a] * v[c][a];
-            }
-            at(lds, 2 * c + 0, pt(q, b, 0), cl) = s;
-            at(lds, 2 * c + 1, pt(q, b, 0), cl) = d;
-          }
-      }
-      __syncthreads();
-      if (act) {
-        const int qx = pen;
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          T s[N1], d[N1];
-#pragma unroll
-          for (int j = 0; j < N1; ++j) {
-            s[j] = at(lds, 2 * c + 0, pt(qx, j, 0), cl);
-            d[j] = at(lds, 2 * c + 1, pt(qx, j, 0), cl);
-          }
-#pragma unroll
-          for (int q = 0; q < N1; ++q) {
-            T gx = 0, gy = 0;
-#pragma unroll
-            for (int j = 0; j < N1; ++j) {
-              gx += tb.S[q][j] * d[j];
-              gy += tb.D[q][j] * s[j];
-            }
-            G[c][0][q] = gx;
-            G[c][1][q] = gy;
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
-
-  template <int NC>
-  __device__ static void backward(const T* Pin, T (&out)[NC][N1], T* lds, int pen, int cl, bool act,
-                                  const Tables<T>& tb) {
-    const T (&Pq)[NC][DIM][N1] = *reinterpret_cast<const T(*)[NC][DIM][N1]>(Pin);
-    if constexpr (DIM == 3) {
-      const int p0 = pen % N1, p1 = pen / N1;
-      if (act) {
-#pragma unroll
-        for (int c = 0; c < NC; ++c)
-#pragma unroll
-          for (int k = 0; k < N1; ++k) {
-            T z0 = 0, z1 = 0, z2 = 0;
-#pragma unroll
-            for (int q = 0; q < N1; ++q) {
-              z0 += tb.S[q][k] * Pq[c][0][q];
-              z1 += tb.S[q][k] * Pq[c][1][q];
-              z2 += tb.D[q][k] * Pq[c][2][q];
-            }
-            at(lds, 3 * c + 0, pt(p0, p1, k), cl) = z0;
-            at(lds, 3 * c + 1, pt(p0, p1, k), cl) = z1;
-            at(lds, 3 * c + 2, pt(p0, p1, k), cl) = z2;
-          }
-      }
-      __syncthreads();
-      if (act) {
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          T z0[N1], z1[N1], z2[N1];
-#pragma unroll
-          for (int q = 0; q < N1; ++q) {
-            z0[q] = at(lds, 3 * c + 0, pt(p0, q, p1), cl);
-            z1[q] = at(lds, 3 * c + 1, pt(p0, q, p1), cl);
-            z2[q] = at(lds, 3 * c + 2, pt(p0, q, p1), cl);
-          }
-#pragma unroll
-          for (int b = 0; b < N1; ++b) {
-            T yd = 0, ys = 0;
-#pragma unroll
-            for (int q = 0; q < N1; ++q) {
-              yd += tb.S[q][b] * z0[q];
-              ys += tb.D[q][b] * z1[q] + tb.S[q][b] * z2[q];
-            }
-            at(lds, 3 * c + 0, pt(p0, b, p1), cl) = yd;
-            at(lds, 3 * c + 1, pt(p0, b, p1), cl) = ys;
-          }
-        }
-      }
-      __syncthreads();
-      if (act) {
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          T yd[N1], ys[N1];
-#pragma unroll
-          for (int q = 0; q < N1; ++q) {
-            yd[q] = at(lds, 3 * c + 0, pt(q, p0, p1), cl);
-            ys[q] = at(lds, 3 * c + 1, pt(q, p0, p1), cl);
-          }
-#pragma unroll
-          for (int a = 0; a < N1; ++a) {
-            T s = 0;
-#pragma unroll
-            for (int q = 0; q < N1; ++q) s += tb.D[q][a] * yd[q] + tb.S[q][a] * ys[q];
-            out[c][a] = s;
-          }
-        }
-      }
-      __syncthreads();
-    } else {
-      if (act) {
-        const int qx = pen;
-#pragma unroll
-        for (int c = 0; c < NC; ++c)
-#pragma unroll
-          for (int j = 0; j < N1; ++j) {
-            T yd = 0, ys = 0;
-#pragma unroll
-            for (int q = 0; q < N1; ++q) {
-              yd += tb.S[q][j] * Pq[c][0][q];
-              ys += tb.D[q][j] * Pq[c][1][q];
-            }
-            at(lds, 2 * c + 0, pt(qx, j, 0), cl) = yd;
-            at(lds, 2 * c + 1, pt(qx, j, 0), cl) = ys;
-          }
-      }
-      __syncthreads();
-      if (act) {
-        const int b = pen;
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          T yd[N1], ys[N1];
-#pragma unroll
-          for (int q = 0; q < N1; ++q) {
-            yd[q] = at(lds, 2 * c + 0, pt(q, b, 0), cl);
-            ys[q] = at(lds, 2 * c + 1, pt(q, b, 0), cl);
-          }
-#pragma unroll
-          for (int a = 0; a < N1; ++a) {
-            T s = 0;
-#pragma unroll
-            for (int q = 0; q < N1; ++q) s += tb.D[q][a] * yd[q] + tb.S[q][a] * ys[q];
-            out[c][a] = s;
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
-};
-
 // Tile origin and extent of block b.
 template <int DIM, int TX, int TY, int TZ>
 struct TilePos {
@@ -1357,7 +1128,7 @@ k_tangent_tile(CellArgs<T> a) {
   using TG = TileGeo<DIM, P, TX, TY, TZ>;
   constexpr int N1 = P + 1, NCELL = TG::NCELL, NG = TG::NG, GX = TG::GX, GY = TG::GY;
   constexpr int NARR = DIM == 3 ? 3 : 2;
-  using SF = TileSF<DIM, N1, NCELL, T>;
+  using SF = SumFact<DIM, N1, T, NCELL>;
   __shared__ T xs[DIM * NG];                                   // x tile, then y accumulator
   __shared__ T us[POL == POL_R ? DIM * NG : 1];                // displacement tile (recompute)
   __shared__ T sf[NC * NARR * TG::NV * NCELL];
@@ -1404,7 +1175,7 @@ k_tangent_tile(CellArgs<T> a) {
       for (int c = 0; c < NC; ++c)
 #pragma unroll
         for (int k = 0; k < N1; ++k) v[c][k] = act ? us[(c0 + c) * NG + g0 + k] : T(0);
-      SF::template forward<NC>(v, &gu[c0][0][0], sf, pen, cl, act, a.tb);
+      SF::template forward<NC>(v, reinterpret_cast<T(&)[NC][DIM][N1]>(gu[c0]), sf, pen, cl, act, a.tb);
     }
   }
 #pragma unroll
@@ -1414,7 +1185,7 @@ k_tangent_tile(CellArgs<T> a) {
     for (int c = 0; c < NC; ++c)
 #pragma unroll
       for (int k = 0; k < N1; ++k) v[c][k] = act ? xs[(c0 + c) * NG + g0 + k] : T(0);
-    SF::template forward<NC>(v, &gx[c0][0][0], sf, pen, cl, act, a.tb);
+    SF::template forward<NC>(v, reinterpret_cast<T(&)[NC][DIM][N1]>(gx[c0]), sf, pen, cl, act, a.tb);
   }
   // x is consumed: the tile buffer becomes the accumulator
   for (int idx = t; idx < DIM * NG; idx += TG::BLOCK) xs[idx] = T(0);
@@ -1469,7 +1240,7 @@ k_tangent_tile(CellArgs<T> a) {
 #pragma unroll
   for (int c0 = 0; c0 < DIM; c0 += NC) {
     T out[NC][N1];
-    SF::template backward<NC>(&gx[c0][0][0], out, sf, pen, cl, act, a.tb);
+    SF::template backward<NC>(reinterpret_cast<const T(&)[NC][DIM][N1]>(gx[c0]), out, sf, pen, cl, act, a.tb);
     if (act) {
 #pragma unroll
       for (int c = 0; c < NC; ++c)

@@ -18,6 +18,7 @@
 #include "ops.hpp"
 #include "tables.hpp"
 #include "tuned.hpp"
+#include "fused.hpp"
 #include "vec.hpp"
 
 namespace mfh {
@@ -1874,6 +1875,19 @@ struct mfh_batch {
     std::vector<const void*> last_x, last_y;   // pointer tables on the device (skip re-upload)
   };
   std::vector<Bin> bins;
+  // one persistent launch over all problems (3-D, degrees 1 to 3): argument
+  // tables of every problem, (problem, cell block, degree) items by falling
+  // degree, pointer tables
+  int launch = MFH_BATCH_LAUNCH_AUTO;
+  bool fused_ok = false;
+  mfh::CellArgs<double>* fa64 = nullptr;
+  mfh::CellArgs<float>* fa32 = nullptr;
+  int4* fitems = nullptr;
+  long long n_fitems = 0;
+  void** fxs = nullptr;
+  void** fys = nullptr;
+  bool foff32[2] = {false, false};
+  std::vector<const void*> flast_x, flast_y;
   // output fills of the problems on the atomic scatter, per precision (0 FP64, 1 FP32)
   mfh::FillItem<double>* f64 = nullptr;
   mfh::FillItem<float>* f32 = nullptr;
@@ -1932,7 +1946,27 @@ size_t batch_layout(mfh_batch* B, char* base) {
   }
   B->f64 = b.take<FillItem<double>>(B->fill_ids[0].size());
   B->f32 = b.take<FillItem<float>>(B->fill_ids[1].size());
+  // the fused persistent launch covers 3-D problems of degrees 1 to 3
+  B->fused_ok = true;
+  B->n_fitems = 0;
+  for (const mfh_problem* P : B->probs) {
+    B->fused_ok = B->fused_ok && P->d.dim == 3 && P->d.degree <= 3;
+    B->n_fitems += (P->lv.back().ncells + P->ops->cpb - 1) / P->ops->cpb;
+  }
+  const size_t n = B->probs.size();
+  B->fa64 = b.take<CellArgs<double>>(n);
+  B->fa32 = b.take<CellArgs<float>>(n);
+  B->fitems = b.take<int4>(B->fused_ok ? B->n_fitems : 0);
+  B->fxs = b.take<void*>(n);
+  B->fys = b.take<void*>(n);
   return b.off + 256;
+}
+
+// Launch form of the batched vmult: the caller's choice, else the tuned one.
+bool batch_fused(const mfh_batch* B) {
+  if (!B->fused_ok) return false;
+  if (B->launch == MFH_BATCH_LAUNCH_AUTO) return kTunedBatchFused;
+  return B->launch == MFH_BATCH_LAUNCH_FUSED;
 }
 
 void batch_bins(mfh_batch* B) {
@@ -1980,6 +2014,22 @@ void batch_vmult(mfh_batch* B, const void* const* x, void* const* y) {
     }
     fill_dirichlet_batch<T>(fdev, B->foff[ti], (int)fid.size(), B->fchunks[ti], s);
   }
+  const bool fused = batch_fused(B);
+  if (fused) {   // one persistent launch for the cell blocks of every problem
+    const size_t n = B->probs.size();
+    std::vector<const void*> xs(x, x + n), ys(y, y + n);
+    if (xs != B->flast_x || ys != B->flast_y) {
+      HIPCHECK(hipMemcpyAsync(B->fxs, xs.data(), sizeof(void*) * n, hipMemcpyHostToDevice, s));
+      HIPCHECK(hipMemcpyAsync(B->fys, ys.data(), sizeof(void*) * n, hipMemcpyHostToDevice, s));
+      HIPCHECK(hipStreamSynchronize(s));
+      B->flast_x = xs;
+      B->flast_y = ys;
+    }
+    const CellArgs<T>* fa = ti == 0 ? reinterpret_cast<const CellArgs<T>*>(B->fa64)
+                                    : reinterpret_cast<const CellArgs<T>*>(B->fa32);
+    tangent_batch_fused<T>(B->policy, B->foff32[ti], fa, B->fitems, (int)B->n_fitems,
+                           reinterpret_cast<const T* const*>(B->fxs), reinterpret_cast<T* const*>(B->fys), s);
+  }
   for (auto& bin : B->bins) {
     const size_t nb = bin.ids.size();
     std::vector<const void*> xs(nb), ys(nb);
@@ -1993,6 +2043,15 @@ void batch_vmult(mfh_batch* B, const void* const* x, void* const* y) {
       HIPCHECK(hipStreamSynchronize(s));
       bin.last_x = xs;
       bin.last_y = ys;
+    }
+    if (fused) {   // only the node sums of the ELEMENT problems remain per bin
+      if (ti == 0 && bin.n_g[0])
+        bin.ops->elem_gather_batch_d(bin.a64, bin.g[0], reinterpret_cast<const double* const*>(bin.xs),
+                                     reinterpret_cast<double* const*>(bin.ys), (unsigned)bin.n_g[0], s);
+      if (ti == 1 && bin.n_g[1])
+        bin.ops->elem_gather_batch_f(bin.a32, bin.g[1], reinterpret_cast<const float* const*>(bin.xs),
+                                     reinterpret_cast<float* const*>(bin.ys), (unsigned)bin.n_g[1], s);
+      continue;
     }
     if (ti == 0) {
       bin.ops->tangent_batch_d[B->policy](bin.a64, bin.items, reinterpret_cast<const double* const*>(bin.xs),
@@ -2121,6 +2180,39 @@ mfh_status mfh_batch_create(int n, mfh_problem* const* probs, void* ws, size_t b
           HIPCHECK(hipMemcpyAsync(bin.g[t], g[t].data(), sizeof(GatherItem) * g[t].size(), hipMemcpyHostToDevice, s));
       HIPCHECK(hipStreamSynchronize(s));   // the host tables above go out of scope
     }
+    {   // tables of the fused persistent launch
+      const size_t np = B->probs.size();
+      std::vector<CellArgs<double>> a64(np);
+      std::vector<CellArgs<float>> a32(np);
+      std::vector<int4> items;
+      B->foff32[0] = B->foff32[1] = true;
+      for (size_t i = 0; i < np; ++i) {
+        const mfh_problem* P = B->probs[i];
+        const Level& v = P->lv.back();
+        a64[i] = cell_args<double>(P, v, v.u64, v.cache64, nullptr, nullptr);
+        a32[i] = cell_args<float>(P, v, v.u32, v.cache32, nullptr, nullptr);
+        if (batch_elem(P, 0)) a64[i].elem = P->elem;
+        if (batch_elem(P, 1)) a32[i].elem = reinterpret_cast<float*>(P->elem);
+        const long long nv = (long long)std::pow(P->d.degree + 1, P->d.dim);
+        B->foff32[0] = B->foff32[0] && nv * v.ncells * 2 * (long long)sizeof(double) < (1LL << 32);
+        B->foff32[1] = B->foff32[1] && nv * v.ncells * 2 * (long long)sizeof(float) < (1LL << 32);
+      }
+      if (B->fused_ok) {
+        need(B->n_fitems < (1ll << 31), "batch has too many cell blocks");
+        items.reserve(B->n_fitems);
+        for (int deg = 3; deg >= 1; --deg)   // heaviest items first
+          for (size_t i = 0; i < np; ++i) {
+            const mfh_problem* P = B->probs[i];
+            if (P->d.degree != deg) continue;
+            const long long nblk = (P->lv.back().ncells + P->ops->cpb - 1) / P->ops->cpb;
+            for (long long j = 0; j < nblk; ++j) items.push_back(make_int4((int)i, (int)j, deg, 0));
+          }
+        HIPCHECK(hipMemcpyAsync(B->fitems, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice, s));
+      }
+      HIPCHECK(hipMemcpyAsync(B->fa64, a64.data(), sizeof(CellArgs<double>) * np, hipMemcpyHostToDevice, s));
+      HIPCHECK(hipMemcpyAsync(B->fa32, a32.data(), sizeof(CellArgs<float>) * np, hipMemcpyHostToDevice, s));
+      HIPCHECK(hipStreamSynchronize(s));   // the host tables go out of scope
+    }
     for (int t = 0; t < 2; ++t) {
       const std::vector<int>& fid = B->fill_ids[t];
       std::vector<long long> foff(fid.size() + 1, 0);
@@ -2178,6 +2270,28 @@ mfh_status mfh_batch_set_deformation(mfh_batch* B, const double* const* u, doubl
       if (min_J) min_J[i] = st[i] == MFH_OK ? mj : NAN;
     }
     batch_raise(B, st, msg);
+  });
+}
+
+mfh_status mfh_contraction_stage(int degree, int mfma, int sweeps, int blocks, float* out, void* stream) {
+  return guarded(nullptr, [&] {
+    need(degree == 3 || degree == 4, "degree must be 3 or 4");
+    need(mfma == 0 || mfma == 1, "mfma must be 0 or 1");
+    need(sweeps >= 1 && blocks >= 1, "need sweeps >= 1 and blocks >= 1");
+    need(out != nullptr, "out is NULL");
+    contraction_stage(degree, mfma, sweeps, blocks, out, static_cast<hipStream_t>(stream));
+    check_launch("contraction stage");
+  });
+}
+
+mfh_status mfh_batch_set_launch(mfh_batch* B, int mode) {
+  if (!B) return MFH_ERR_INVALID_ARG;
+  return batch_guarded(B, [&] {
+    need(mode == MFH_BATCH_LAUNCH_AUTO || mode == MFH_BATCH_LAUNCH_PER_DEGREE || mode == MFH_BATCH_LAUNCH_FUSED,
+         "mode must be MFH_BATCH_LAUNCH_AUTO, _PER_DEGREE or _FUSED");
+    need(mode != MFH_BATCH_LAUNCH_FUSED || B->fused_ok,
+         "the fused launch covers 3-D problems of degrees 1 to 3 only");
+    B->launch = mode;
   });
 }
 

@@ -22,6 +22,7 @@ SCATTER_AUTO, SCATTER_ATOMIC, SCATTER_COLOR, SCATTER_TILE, SCATTER_ELEMENT = -1,
 SCATTER_NAMES = {0: "atomic", 1: "color", 2: "tile", 3: "element"}
 LEVEL_FIELD_NODAL, LEVEL_FIELD_VERTEX = 0, 1
 COARSE_DIRECT, COARSE_CHEBYSHEV = 0, 1
+BATCH_LAUNCH_AUTO, BATCH_LAUNCH_PER_DEGREE, BATCH_LAUNCH_FUSED = -1, 0, 1
 
 
 class MfhError(RuntimeError):
@@ -109,6 +110,8 @@ def lib():
         "mfh_batch_last_error": (ctypes.c_char_p, [_P]),
         "mfh_batch_set_deformation": (st, [_P, ctypes.POINTER(_P), _D]),
         "mfh_batch_tangent_vmult": (st, [_P, ctypes.c_int, ctypes.POINTER(_P), ctypes.POINTER(_P)]),
+        "mfh_batch_set_launch": (st, [_P, ctypes.c_int]),
+        "mfh_contraction_stage": (st, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, _P]),
         "mfh_batch_cg_solve": (st, [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.c_double, ctypes.c_int,
                                     ctypes.POINTER(ctypes.c_int), _D, _D]),
         "mfh_node_coords_1d": (st, [_P, ctypes.c_int, _D]),
@@ -458,6 +461,16 @@ def dense_inverse(a, stream=None, static=False):
     return inv, neg.value
 
 
+def contraction_stage(degree, mfma, sweeps, blocks, out, stream=None):
+    """The sum factorisation's contraction stage alone (autotuner measurement);
+    out: float32 device tensor of blocks * (degree + 1) * 256 entries."""
+    _arg(out, "out", out.device, blocks * (degree + 1) * 256, (torch.float32,))
+    stream = torch.cuda.current_stream(out.device) if stream is None else stream
+    _check(lib().mfh_contraction_stage(int(degree), int(mfma), int(sweeps), int(blocks), _ptr(out),
+                                       ctypes.c_void_p(stream.cuda_stream)))
+    return out
+
+
 def _check_batch(st, handle):
     if st != MFH_OK:
         msg = lib().mfh_batch_last_error(handle)
@@ -513,6 +526,10 @@ class Batch:
         mj = (ctypes.c_double * len(us))()
         _check_batch(lib().mfh_batch_set_deformation(self.handle, _parr(us), mj), self.handle)
         return list(mj)
+
+    def set_launch(self, mode):
+        """Batched vmult launch form: BATCH_LAUNCH_AUTO (tuned), _PER_DEGREE or _FUSED."""
+        _check_batch(lib().mfh_batch_set_launch(self.handle, int(mode)), self.handle)
 
     def tangent_vmult(self, xs, ys):
         xs = self._vectors(xs, "xs", (torch.float64, torch.float32))

@@ -226,3 +226,32 @@ def test_batch_real_sizes_against_oracle_rows():
                   f"max rel {err:.2e}", flush=True)
             assert err <= (1e-12 if dt == F64 else 1e-5)
             assert np.all(np.isfinite(host(y)))
+
+
+@pytest.mark.parametrize("policy", [0, 2, 3], ids=["R", "C2", "C4"])
+def test_batch_fused_launch_matches_per_degree(policy):
+    """The persistent launch over every degree computes what the per-degree
+    launches compute (same block bodies; the atomic-scatter problems differ
+    only by summation order), FP64 and FP32, and a 2-D batch refuses it."""
+    from paper_1904_13131_amd import MfhError
+    from paper_1904_13131_amd.mfh import BATCH_LAUNCH_AUTO, BATCH_LAUNCH_FUSED, BATCH_LAUNCH_PER_DEGREE
+    log_case("batch_fused", policy=policy)
+    probs, fields = _problems(12, 63, qp_policy=policy)
+    B = Batch(probs)
+    B.set_deformation([dev(f[2]) for f in fields])
+    for tdt, tol in ((torch.float64, 1e-13), (torch.float32, 2e-6)):
+        xs = [dev(f[3], tdt) for f in fields]
+        outs = {}
+        for mode in (BATCH_LAUNCH_PER_DEGREE, BATCH_LAUNCH_FUSED, BATCH_LAUNCH_AUTO):
+            ys = [torch.full_like(x, float("nan")) for x in xs]
+            B.set_launch(mode)
+            B.tangent_vmult(xs, ys)
+            torch.cuda.synchronize()
+            outs[mode] = [host(y) for y in ys]
+        for a, b, c in zip(outs[BATCH_LAUNCH_PER_DEGREE], outs[BATCH_LAUNCH_FUSED], outs[BATCH_LAUNCH_AUTO]):
+            assert np.all(np.isfinite(b))
+            assert rel_l2(b, a) <= tol and rel_l2(c, a) <= tol
+    P2 = Problem(2, 4, 2, mu=(1.0,), lam=(1.5,))
+    B2 = Batch([P2])
+    with pytest.raises(MfhError):
+        B2.set_launch(BATCH_LAUNCH_FUSED)

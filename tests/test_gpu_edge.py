@@ -166,3 +166,20 @@ def test_element_buffer_block_ends(dim, n, p, policy):
     assert rel_l2(host(P.tangent_vmult(dev(w["x"]))), ref) <= 1e-12
     y32 = P.tangent_vmult(dev(w["x"]).float())
     assert rel_l2(host(y32.double()), K @ host(dev(w["x"]).float().double())) <= 1e-5
+
+
+@pytest.mark.parametrize("degree", [3, 4])
+def test_contraction_stage_forms_agree(degree):
+    """The VALU and MFMA forms of the contraction stage (the autotuner's
+    measurement) compute the same values: the MFMA operand layout is right."""
+    import torch
+
+    from paper_1904_13131_amd.mfh import contraction_stage
+    log_case("contraction_stage", degree=degree)
+    n = (degree + 1) * 256 * 8
+    a = contraction_stage(degree, 0, 50, 8, torch.empty(n, dtype=torch.float32, device="cuda"))
+    b = contraction_stage(degree, 1, 50, 8, torch.empty(n, dtype=torch.float32, device="cuda"))
+    torch.cuda.synchronize()
+    scale = float(a.abs().max())
+    assert scale > 0
+    assert float((a - b).abs().max()) <= 1e-4 * scale
