@@ -994,10 +994,13 @@ __device__ __forceinline__ void elem_gather_node(const CellArgs<T>& a, const T* 
         const int e0 = ex0 + eyz, e1 = qx - 1 + eyz;
         const bool on1 = on && shared && (unsigned)e1 % (unsigned)CPB == (unsigned)(CPB - 1);
         const long long i0 = (long long)(last ? line : rx + P * line) * a.ncells + e0;
-        const T v0 = (last ? ob : eb)[on ? i0 : 0];                             // in bounds for every lane
-        const T v1 = ob[on1 ? (long long)line * a.ncells + e1 : 0];
-        v[c][2 * s] = on ? v0 : T(0);
-        v[c][2 * s + 1] = on1 ? v1 : T(0);
+        // only the entries that exist are loaded (the others read as zero, so
+        // the fixed summation order below is kept)
+        T v0 = T(0), v1 = T(0);
+        if (on) v0 = (last ? ob : eb)[i0];
+        if (on1) v1 = ob[(long long)line * a.ncells + e1];
+        v[c][2 * s] = v0;
+        v[c][2 * s + 1] = v1;
       }
   }
 #pragma unroll
