@@ -377,16 +377,21 @@ mfh_status mfh_chebyshev(mfh_problem* problem, int level, const void* f_dev, voi
 
 /* The coarse level's dense direct solver (the exact FP64 coarse solve that
  * replaces the paper's Chebyshev coarse iteration, Sec. 7) on a caller's
- * matrix: symmetric block Gauss-Jordan with symmetric pivoting (each block of
- * 64 takes the unswept indices of largest |diagonal| of the current Schur
- * complement and is inverted with Bunch-Kaufman 1x1/2x2 pivots), for any
- * nonsingular symmetric matrix, definite or not.
- * a_dev: n x n FP64 row-major symmetric matrix (device), overwritten by the
- * inverse in the pivoted basis; inv_dev: receives A^-1 in the original order
- * (device, n x n, must not overlap a_dev); work_dev: at least
+ * matrix, for any nonsingular symmetric matrix, definite or not: block
+ * Gauss-Jordan in plain diagonal order first, kept when every pivot is
+ * positive and above 1e-12 max |A_ii| (A positive definite: no element
+ * growth without exchanges); otherwise symmetric block Gauss-Jordan with
+ * symmetric pivoting (each block of 64 takes the unswept indices of largest
+ * |diagonal| of the current Schur complement and is inverted with
+ * Bunch-Kaufman 1x1/2x2 pivots).  The choice is made on the device.
+ * a_dev: n x n FP64 row-major symmetric matrix (device), work space of the
+ * pivoted pass: unchanged when the plain pass is kept, else overwritten
+ * by the inverse in the pivoted basis; inv_dev: receives A^-1 in the original
+ * order (device, n x n, must not overlap a_dev); work_dev: at least
  * mfh_dense_inverse_workspace(n) bytes of device memory, 256-byte aligned;
  * stream: HIP stream (NULL: default).  *negative receives the number of
- * negative eigenvalues of A (Sylvester: signs of the 1x1 and 2x2 pivots).
+ * negative eigenvalues of A (Sylvester: signs of the kept pass's 1x1 and 2x2
+ * pivots).
  * 1 <= n <= 20000.  Synchronises.  Errors: INVALID_ARG, WORKSPACE, NOT_SPD
  * (numerically singular: a pivot, or a 2x2 pivot's determinant against its
  * largest entry, at most 1e-12 max |A_ii| or not finite), HIP. */

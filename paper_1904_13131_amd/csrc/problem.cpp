@@ -135,8 +135,8 @@ struct mfh_problem {
   int* dof_of = nullptr;             // free index -> dof
   int* dof_perm = nullptr;           // position in the pivoted coarse inverse -> dof
   int* gj_sw = nullptr;              // exchange pairs of a block step
-  double* gj_key = nullptr;          // |diagonal| of the unswept positions
   double* Kinv = nullptr;
+  double* Kc = nullptr;              // the assembled coarse tangent (kept for the inverse's acceptance test)
   double *gj_P = nullptr, *gj_C = nullptr, *gj_R = nullptr, *crf = nullptr, *czf = nullptr;
   int* flag = nullptr;
   double* elem = nullptr;            // element buffer of the ELEMENT scatter (finest level size)
@@ -385,14 +385,14 @@ size_t layout(mfh_problem* P, char* base) {
   P->dof_of = b.take<int>(std::max<long long>(1, P->nf));
   P->dof_perm = b.take<int>(std::max<long long>(1, P->nf));
   P->gj_sw = b.take<int>(1 + 4 * 64);
-  P->gj_key = b.take<double>(std::max<long long>(1, P->nf));
   P->Kinv = b.take<double>((size_t)P->nf * P->nf);
+  P->Kc = b.take<double>((size_t)P->nf * P->nf);
   P->gj_P = b.take<double>(64 * 64);
   P->gj_C = b.take<double>((size_t)P->nf * 64);
   P->gj_R = b.take<double>((size_t)P->nf * 64);
   P->crf = b.take<double>(std::max<long long>(1, P->nf));
   P->czf = b.take<double>(std::max<long long>(1, P->nf));
-  P->flag = b.take<int>(2);
+  P->flag = b.take<int>(3);
   if (d.coarse_solver == MFH_COARSE_CHEBYSHEV) {
     const long long n0 = P->lv[0].ndofs;
     for (double** q : {&P->cc_dinv, &P->cc_b, &P->cc_x, &P->cc_t, &P->cc_d}) *q = b.take<double>(n0);
@@ -933,17 +933,18 @@ void setup_enqueue(mfh_problem* P) {
     reciprocal<double>(P->lv[0].diag64, P->cc_dinv, P->lv[0].ndofs, s);
     if (P->eig_fresh) coarse_lanczos_enqueue(P, P->hist);
   }
-  // coarse level (direct solver): dense FP64 tangent on free DoFs, inverted in place
+  // coarse level (direct solver): dense FP64 tangent on free DoFs and its inverse
+  // (kept in the pivoted basis when the pivoted pass runs; dof_perm maps it)
   Level& c = P->lv[0];
   const long long nf = P->nf;
-  fill<int>(P->flag, 0, 2, s);
+  fill<int>(P->flag, 0, 3, s);
   if (nf && !cheb_coarse) {
-    fill<double>(P->Kinv, 0.0, nf * nf, s);
+    fill<double>(P->Kc, 0.0, nf * nf, s);
     CellArgs<double> a = cell_args<double>(P, c, c.u64, nullptr, nullptr, nullptr);
-    P->ops->coarse_assemble(a, P->fmap, nf, P->Kinv, (unsigned)c.ncells, s);
+    P->ops->coarse_assemble(a, P->fmap, nf, P->Kc, (unsigned)c.ncells, s);
     HIPCHECK(hipMemcpyAsync(P->dof_perm, P->dof_of, sizeof(int) * nf, hipMemcpyDeviceToDevice, s));
-    const DenseInvWork w{P->gj_P, P->gj_C, P->gj_R, P->gj_key, P->sc + SC_TMP, P->gj_sw, P->flag};
-    dense_inverse(P->Kinv, nf, P->dof_perm, w, kSingularTol, s);
+    const DenseInvWork w{P->gj_P, P->gj_C, P->gj_R, P->sc + SC_TMP, P->gj_sw, P->flag};
+    dense_inverse(P->Kc, P->Kinv, nf, P->dof_perm, w, kSingularTol, false, s);
   }
   check_launch("coarse inverse");
 }
@@ -1718,12 +1719,11 @@ size_t dense_inverse_layout(long long n, char* base, mfh::DenseInvWork* w, int**
   double* Pinv = b.take<double>(64 * 64);
   double* C = b.take<double>((size_t)n * 64);
   double* R = b.take<double>((size_t)n * 64);
-  double* key = b.take<double>((size_t)n);
   double* scale = b.take<double>(1);
   int* pm = b.take<int>((size_t)n);
   int* sw = b.take<int>(1 + 4 * 64);
-  int* flag = b.take<int>(2);
-  if (w) *w = mfh::DenseInvWork{Pinv, C, R, key, scale, sw, flag};
+  int* flag = b.take<int>(3);
+  if (w) *w = mfh::DenseInvWork{Pinv, C, R, scale, sw, flag};
   if (perm) *perm = pm;
   return b.off + 256;
 }
@@ -1746,10 +1746,9 @@ void dense_inverse_run(double* a, double* inv, long long n, char* work, hipStrea
   mfh::DenseInvWork w{};
   int* perm = nullptr;
   dense_inverse_layout(n, work, &w, &perm);
-  mfh::fill<int>(w.flag, 0, 2, s);
+  mfh::fill<int>(w.flag, 0, 3, s);
   mfh::iota(perm, n, s);
-  mfh::dense_inverse(a, n, perm, w, mfh::kSingularTol, s);
-  mfh::unpermute(a, perm, n, inv, s);
+  mfh::dense_inverse(a, inv, n, perm, w, mfh::kSingularTol, true, s);
   int flag[2];
   HIPCHECK(hipMemcpyAsync(flag, w.flag, sizeof flag, hipMemcpyDeviceToHost, s));
   HIPCHECK(hipStreamSynchronize(s));

@@ -412,8 +412,13 @@ __global__ void k_material_bits(uint32_t* __restrict__ bits, long long ncells, i
 
 constexpr int kGJ = 64;
 
-// Coarse inverse by symmetric block Gauss-Jordan with Bunch-Kaufman pivoting.
-// Each block step chooses its (up to) 64 pivots on the current Schur
+// Coarse inverse by symmetric block Gauss-Jordan.  A plain pass (diagonal
+// pivots in order) runs first and is kept when all its pivots are positive
+// and above the singularity threshold (a positive definite matrix, for which
+// elimination without exchanges is stable).  Otherwise the pass with
+// Bunch-Kaufman pivoting described next runs; its launches are gated on the
+// device by the plain pass's verdict, so no host round trip decides between
+// them.  Each block step of the pivoted pass chooses its (up to) 64 pivots on the current Schur
 // complement of the unswept positions [k0, n) (the update kernels keep those
 // entries current): the unswept index k of largest |diagonal|, lambda = the
 // largest off-diagonal |entry| of its column (row r); k alone when |a_kk| >=
@@ -446,6 +451,8 @@ __device__ __forceinline__ void wave_argmax(double& v, int& i) {
 __device__ __forceinline__ double mag(double x) { return isfinite(x) ? fabs(x) : INFINITY; }   // non-finite first
 
 constexpr int kSel = 1024;   // threads of the pivot-choice kernel
+constexpr int kPerMax = (kGJMaxFree + kSel - 1) / kSel;   // positions per thread at the largest size
+constexpr int kKeepMax = 5;   // up to this many positions per thread, a formed column also stays in registers
 
 // Block-wide argmax over kSel threads; every thread gets the result.
 __device__ __forceinline__ void block_argmax(double& v, int& i, double* sv, int* si) {
@@ -471,27 +478,18 @@ __device__ __forceinline__ void block_argmax(double& v, int& i, double* sv, int*
   __syncthreads();
 }
 
-// Largest |entry| of vector c over unswept positions other than `skip`.
-__device__ __forceinline__ void col_absmax(const double* c, int m, int skip, const unsigned* taken, double* sv,
-                                           int* si, double& v, int& i) {
-  v = -1.0;
-  i = 0x7fffffff;
-  for (int q = threadIdx.x; q < m; q += kSel)
-    if (q != skip && !((taken[q >> 5] >> (q & 31)) & 1u)) {
-      const double a = mag(c[q]);
-      if (a > v) {
-        v = a;
-        i = q;
-      }
-    }
-  block_argmax(v, i, sv, si);
-}
-
 // Column k (position relative to k0) of the current Schur complement into
 // V[slot]: row k of the matrix at the step's start (the unswept block is
-// symmetric) minus the updates of the pivot groups chosen so far.
-__device__ void form_column(const double* __restrict__ A, long long n, long long k0, int m, int k, double* V,
-                            int slot, int ng, const int* gs, const int* gn, const double (*einv)[3], double* wk) {
+// symmetric) minus the updates of the pivot groups chosen so far.  Thread t
+// handles positions q = t + j kSel (j < KP) and, when KP <= kKeepMax, keeps
+// its entries in cq[j].  Returns to every thread the column's diagonal entry
+// ckk and the largest |entry| lam over the unswept positions other than k
+// (own bit j of tk set: swept), at position r (lam = -1 when there is none).
+template <int KP>
+__device__ __forceinline__ void form_column(const double* __restrict__ A, long long n, long long k0, int m, int k, double* V,
+                            int slot, int ng, const int* gs, const int* gn, const double (*einv)[3], double* wk,
+                            unsigned tk, double* sv, int* si, double* bc, double (&cq)[KP], double& ckk,
+                            double& lam, int& r) {
   const int t = threadIdx.x;
   if (t < ng) {
     const int s0 = gs[t];
@@ -505,62 +503,92 @@ __device__ void form_column(const double* __restrict__ A, long long n, long long
   }
   __syncthreads();
   const int nv = ng > 0 ? gs[ng - 1] + gn[ng - 1] : 0;
-  for (int q = t; q < m; q += kSel) {
-    double c = A[(k0 + k) * n + k0 + q];
-    for (int v = 0; v < nv; ++v) c -= V[(long long)v * m + q] * wk[v];
-    V[(long long)slot * m + q] = c;
+  const double* arow = A + (k0 + k) * n + k0;
+  double* vs = V + (long long)slot * m;
+  double best = -1.0;
+  int bi = 0x7fffffff;
+#pragma unroll
+  for (int j = 0; j < KP; ++j) {
+    const int q = t + j * kSel;
+    if (q < m) {
+      double c = arow[q];
+#pragma unroll 8
+      for (int u = 0; u < nv; ++u) c -= V[(long long)u * m + q] * wk[u];
+      vs[q] = c;
+      if constexpr (KP <= kKeepMax) cq[j] = c;
+      if (q == k) {
+        bc[0] = c;
+      } else if (!((tk >> j) & 1u)) {
+        const double a = mag(c);
+        if (a > best) {
+          best = a;
+          bi = q;
+        }
+      }
+    }
   }
-  __syncthreads();
+  block_argmax(best, bi, sv, si);   // its barriers also publish bc[0] and vs
+  ckk = bc[0];
+  lam = best;
+  r = bi;
 }
 
 // Chooses the block's pivots (see above) and writes the exchange and the
 // pivot list: sw[0] = number of exchange pairs q, sw[1 + i] / sw[1 + kGJ + i]
 // = window / outside position of pair i, sw[1 + 2 kGJ + t] = window-relative
 // position of pivot t (after the exchange), sw[1 + 3 kGJ + t] = 1 (1x1 pivot),
-// 2 / 3 (first / second index of a 2x2 pivot).  dcur: n - k0 doubles, V: nb
-// vectors of n - k0 doubles (scratch).  One workgroup of kSel threads.
+// 2 / 3 (first / second index of a 2x2 pivot).  V: nb vectors of n - k0
+// doubles (scratch).  One workgroup of kSel threads; thread t keeps the
+// current Schur-complement diagonal of its positions t + j kSel (j < KP,
+// KP kSel >= n - k0) in registers, and their swept flags in tk.
+template <int KP>
 __global__ void __launch_bounds__(kSel) k_gj_choose(const double* __restrict__ A, long long n, long long k0, int nb,
-                                                    double* __restrict__ dcur, double* __restrict__ V,
-                                                    int* __restrict__ sw) {
-  __shared__ unsigned taken[kGJMaxFree / 32];
+                                                    double* __restrict__ V, int* __restrict__ sw,
+                                                    const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;   // pivoted pass not needed
   __shared__ double sv[kSel / 64 + 1];
   __shared__ int si[kSel / 64 + 1];
   __shared__ double wk[kGJ];
   __shared__ double einv[kGJ][3];
+  __shared__ double bc[1];
   __shared__ int gs[kGJ], gn[kGJ];
   __shared__ int sel[kGJ], kind[kGJ];
   const double alpha = 0.6403882032022076;   // (1 + sqrt(17)) / 8
   const int t = threadIdx.x;
   const int m = (int)(n - k0);
-  for (int w = t; w < (m + 31) / 32; w += kSel) taken[w] = 0u;
-  for (int q = t; q < m; q += kSel) dcur[q] = A[(k0 + q) * n + k0 + q];
-  __syncthreads();
+  double dq[KP], cq[KP];
+  unsigned tk = 0u;
+  double best = -1.0;
+  int k = 0x7fffffff;
+#pragma unroll
+  for (int j = 0; j < KP; ++j) {
+    const int q = t + j * kSel;
+    dq[j] = 0.0;
+    cq[j] = 0.0;
+    if (q < m) {
+      dq[j] = A[(k0 + q) * n + k0 + q];
+      const double a = mag(dq[j]);
+      if (a > best) {
+        best = a;
+        k = q;
+      }
+    }
+  }
+  block_argmax(best, k, sv, si);   // m > 0 unswept positions: k is one of them
   int cnt = 0, ng = 0;
   while (cnt < nb) {
-    double akk = -1.0;
-    int k = 0x7fffffff;
-    for (int q = t; q < m; q += kSel)
-      if (!((taken[q >> 5] >> (q & 31)) & 1u)) {
-        const double a = mag(dcur[q]);
-        if (a > akk) {
-          akk = a;
-          k = q;
-        }
-      }
-    block_argmax(akk, k, sv, si);   // m - cnt > 0 unswept positions: k is one of them
-    form_column(A, n, k0, m, k, V, cnt, ng, gs, gn, einv, wk);
-    double lam;
-    int r;
-    col_absmax(V + (long long)cnt * m, m, k, taken, sv, si, lam, r);
+    double ckk, lam, sig, crr;
+    int r, ri;
+    form_column<KP>(A, n, k0, m, k, V, cnt, ng, gs, gn, einv, wk, tk, sv, si, bc, cq, ckk, lam, r);
+    const double akk = mag(ckk);
+    double p = ckk;     // 1x1 pivot value
     int pk = k, two = 0;
+    bool in_regs = true;   // cq holds the column in slot cnt
     if (lam > 0.0 && akk < alpha * lam) {
-      form_column(A, n, k0, m, r, V, cnt + (cnt + 1 < nb ? 1 : 0), ng, gs, gn, einv, wk);
+      const int slot_r = cnt + (cnt + 1 < nb ? 1 : 0);
       // (at the last slot column r overwrites column k: only r's diagonal and sigma are needed)
-      const double* cr = V + (long long)(cnt + (cnt + 1 < nb ? 1 : 0)) * m;
-      double sig;
-      int ri;
-      col_absmax(cr, m, r, taken, sv, si, sig, ri);
-      const double arr = mag(cr[r]);
+      form_column<KP>(A, n, k0, m, r, V, slot_r, ng, gs, gn, einv, wk, tk, sv, si, bc, cq, crr, sig, ri);
+      const double arr = mag(crr);
       if (akk * sig >= alpha * lam * lam) {
         pk = k;
       } else if (arr >= alpha * sig) {
@@ -571,31 +599,35 @@ __global__ void __launch_bounds__(kSel) k_gj_choose(const double* __restrict__ A
         pk = arr > akk ? r : k;   // last slot: no room for a 2x2 pivot
       }
       if (!two && (pk == r) != (cnt + 1 >= nb)) {   // bring the chosen column into slot cnt
-        form_column(A, n, k0, m, pk, V, cnt, ng, gs, gn, einv, wk);
+        double c2, l2;
+        int r2;
+        form_column<KP>(A, n, k0, m, pk, V, cnt, ng, gs, gn, einv, wk, tk, sv, si, bc, cq, c2, l2, r2);
+        p = c2;
+      } else if (!two && pk == r) {   // last slot: column r already sits in slot cnt (and in cq)
+        p = crr;
+      } else {   // column k in slot cnt but cq holds column r, or a 2x2 pivot
+        in_regs = false;
       }
     }
-    // record the group and update the diagonal of the unswept positions
+    // record the group (read by the next form_column after the barriers below)
     const double* c0 = V + (long long)cnt * m;
+    const double* c1 = V + (long long)(cnt + 1) * m;
+    double e00 = 0.0, e01 = 0.0, e11 = 0.0;
     if (!two) {
-      const double p = c0[pk];
-      const double ip = 1.0 / p;
-      for (int q = t; q < m; q += kSel) dcur[q] -= c0[q] * c0[q] * ip;
+      e00 = 1.0 / p;
       if (t == 0) {
         gs[ng] = cnt;
         gn[ng] = 1;
-        einv[ng][0] = ip;
+        einv[ng][0] = e00;
         sel[cnt] = pk;
         kind[cnt] = 1;
-        taken[pk >> 5] |= 1u << (pk & 31);
       }
-      ++cnt;
     } else {
-      const double* c1 = V + (long long)(cnt + 1) * m;
-      const double a = c0[k], b = c0[r], c = c1[r];
+      const double a = ckk, b = c0[r], c = crr;
       const double det = a * c - b * b;
-      const double e00 = c / det, e01 = -b / det, e11 = a / det;
-      for (int q = t; q < m; q += kSel)
-        dcur[q] -= e00 * c0[q] * c0[q] + 2.0 * e01 * c0[q] * c1[q] + e11 * c1[q] * c1[q];
+      e00 = c / det;
+      e01 = -b / det;
+      e11 = a / det;
       if (t == 0) {
         gs[ng] = cnt;
         gn[ng] = 2;
@@ -606,17 +638,40 @@ __global__ void __launch_bounds__(kSel) k_gj_choose(const double* __restrict__ A
         kind[cnt] = 2;
         sel[cnt + 1] = r;
         kind[cnt + 1] = 3;
-        taken[k >> 5] |= 1u << (k & 31);
-        taken[r >> 5] |= 1u << (r & 31);
       }
-      cnt += 2;
     }
+    // update the diagonal of the unswept positions and choose the next k
+    best = -1.0;
+    int kn = 0x7fffffff;
+#pragma unroll
+    for (int j = 0; j < KP; ++j) {
+      const int q = t + j * kSel;
+      if (q < m) {
+        if (q == pk || (two && (q == k || q == r))) tk |= 1u << j;
+        if (!((tk >> j) & 1u)) {
+          if (!two) {
+            const double v = KP <= kKeepMax && in_regs ? cq[j] : c0[q];
+            dq[j] -= v * v * e00;
+          } else {
+            const double v0 = c0[q], v1 = c1[q];
+            dq[j] -= e00 * v0 * v0 + 2.0 * e01 * v0 * v1 + e11 * v1 * v1;
+          }
+          const double a = mag(dq[j]);
+          if (a > best) {
+            best = a;
+            kn = q;
+          }
+        }
+      }
+    }
+    cnt += two ? 2 : 1;
     ++ng;
-    __syncthreads();
+    block_argmax(best, kn, sv, si);   // no unswept position left: kn unused (the loop ends)
+    k = kn;
   }
+  __shared__ bool in_window[kGJ];
+  __shared__ int wpos[kGJ];
   if (t == 0) {   // exchange pairs: window positions not chosen <-> chosen positions outside
-    bool in_window[kGJ];
-    int wpos[kGJ];
     for (int w = 0; w < nb; ++w) in_window[w] = false;
     for (int c = 0; c < nb; ++c)
       if (sel[c] < nb) in_window[sel[c]] = true;
@@ -641,7 +696,9 @@ __global__ void __launch_bounds__(kSel) k_gj_choose(const double* __restrict__ A
 
 // Symmetric exchange of the pairs of sw: rows first (this kernel), then
 // columns and the permutation (k_gj_swap_cols), as two launches.
-__global__ void k_gj_swap_rows(double* __restrict__ A, long long n, const int* __restrict__ sw) {
+__global__ void k_gj_swap_rows(double* __restrict__ A, long long n, const int* __restrict__ sw,
+                               const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;   // pivoted pass not needed
   const int q = sw[0];
   const long long total = (long long)q * n;
   for (long long g = blockIdx.x * (long long)kVB + threadIdx.x; g < total; g += (long long)gridDim.x * kVB) {
@@ -655,7 +712,9 @@ __global__ void k_gj_swap_rows(double* __restrict__ A, long long n, const int* _
   }
 }
 
-__global__ void k_gj_swap_cols(double* __restrict__ A, long long n, const int* __restrict__ sw, int* __restrict__ perm) {
+__global__ void k_gj_swap_cols(double* __restrict__ A, long long n, const int* __restrict__ sw, int* __restrict__ perm,
+                               const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;   // pivoted pass not needed
   const int q = sw[0];
   const long long total = (long long)q * n;
   for (long long g = blockIdx.x * (long long)kVB + threadIdx.x; g < total; g += (long long)gridDim.x * kVB) {
@@ -682,16 +741,21 @@ __global__ void k_gj_swap_cols(double* __restrict__ A, long long n, const int* _
 // most tol * scale[0] in magnitude (numerically singular).
 __global__ void __launch_bounds__(256) k_gj_pivot(double* __restrict__ A, long long n, long long k0, int nb,
                                                   double* __restrict__ Pinv, int* flag, const double* scale,
-                                                  double tol, const int* __restrict__ sw) {
+                                                  double tol, const int* __restrict__ sw,
+                                                  const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;   // pivoted pass not needed
   __shared__ double M[kGJ][kGJ + 1];
   __shared__ double colk[kGJ], rowk[kGJ], colr[kGJ], rowr[kGJ];
+  __shared__ int pos[kGJ], kind[kGJ];   // the pivot list, read at every step
   // thread t owns column j = t % kGJ of rows t / kGJ + 4 r (256 threads)
   constexpr int kRows = 256 / kGJ;
   const int t = threadIdx.x;
   const int j = t % kGJ, i0 = t / kGJ;
   const double thr = tol * scale[0];
-  const int* pos = sw + 1 + 2 * kGJ;
-  const int* kind = sw + 1 + 3 * kGJ;
+  if (t < nb) {
+    pos[t] = sw[1 + 2 * kGJ + t];
+    kind[t] = sw[1 + 3 * kGJ + t];
+  }
   if (j < nb)
     for (int i = i0; i < nb; i += kRows) M[i][j] = A[(k0 + i) * n + k0 + j];
   __syncthreads();
@@ -766,7 +830,8 @@ __global__ void __launch_bounds__(256) k_gj_pivot(double* __restrict__ A, long l
 }
 
 // scale[0] = max_i |A[i][i]|
-__global__ void k_diag_absmax(const double* __restrict__ A, long long n, double* scale) {
+__global__ void k_diag_absmax(const double* __restrict__ A, long long n, double* scale, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;   // pivoted pass not needed
   __shared__ double sh[kVB];
   double m = 0;
   for (long long i = threadIdx.x; i < n; i += kVB) m = fmax(m, fabs(A[i * n + i]));
@@ -781,7 +846,8 @@ __global__ void k_diag_absmax(const double* __restrict__ A, long long n, double*
 
 // R[t][j] = sum_s Pinv[t][s] A[k0+s][j]
 __global__ void k_gj_rowpanel(const double* __restrict__ A, long long n, long long k0, int nb,
-                              const double* __restrict__ Pinv, double* __restrict__ R) {
+                              const double* __restrict__ Pinv, double* __restrict__ R, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;   // pivoted pass not needed
   const long long total = (long long)nb * n;
   for (long long g = blockIdx.x * (long long)kVB + threadIdx.x; g < total; g += (long long)gridDim.x * kVB) {
     const int t = (int)(g / n);
@@ -793,7 +859,9 @@ __global__ void k_gj_rowpanel(const double* __restrict__ A, long long n, long lo
 }
 
 // Cb[i][t] = A[i][k0+t]
-__global__ void k_gj_colpanel(const double* __restrict__ A, long long n, long long k0, int nb, double* __restrict__ Cb) {
+__global__ void k_gj_colpanel(const double* __restrict__ A, long long n, long long k0, int nb, double* __restrict__ Cb,
+                              const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;   // pivoted pass not needed
   const long long total = (long long)nb * n;
   for (long long g = blockIdx.x * (long long)kVB + threadIdx.x; g < total; g += (long long)gridDim.x * kVB) {
     const long long i = g / nb;
@@ -804,7 +872,9 @@ __global__ void k_gj_colpanel(const double* __restrict__ A, long long n, long lo
 
 // A[i][j] -= sum_t Cb[i][t] R[t][j]   for i, j outside the pivot block
 __global__ void __launch_bounds__(256) k_gj_update(double* __restrict__ A, long long n, long long k0, int nb,
-                                                   const double* __restrict__ Cb, const double* __restrict__ R) {
+                                                   const double* __restrict__ Cb, const double* __restrict__ R,
+                                                   const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;   // pivoted pass not needed
   const long long bi = blockIdx.y, bj = blockIdx.x;
   const long long kb = k0 / kGJ;
   if (bi == kb || bj == kb) return;
@@ -845,7 +915,8 @@ __global__ void __launch_bounds__(256) k_gj_update(double* __restrict__ A, long 
 
 // Column k block: A[i][k0+t] = -sum_s Cb[i][s] Pinv[s][t] (i outside), Pinv inside.
 __global__ void k_gj_fincol(double* __restrict__ A, long long n, long long k0, int nb, const double* __restrict__ Cb,
-                            const double* __restrict__ Pinv) {
+                            const double* __restrict__ Pinv, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;   // pivoted pass not needed
   const long long total = (long long)nb * n;
   for (long long g = blockIdx.x * (long long)kVB + threadIdx.x; g < total; g += (long long)gridDim.x * kVB) {
     const long long i = g / nb;
@@ -862,13 +933,47 @@ __global__ void k_gj_fincol(double* __restrict__ A, long long n, long long k0, i
 }
 
 // Row k block: A[k0+t][j] = R[t][j] for j outside the pivot block.
-__global__ void k_gj_finrow(double* __restrict__ A, long long n, long long k0, int nb, const double* __restrict__ R) {
+__global__ void k_gj_finrow(double* __restrict__ A, long long n, long long k0, int nb, const double* __restrict__ R,
+                            const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;   // pivoted pass not needed
   const long long total = (long long)nb * n;
   for (long long g = blockIdx.x * (long long)kVB + threadIdx.x; g < total; g += (long long)gridDim.x * kVB) {
     const int t = (int)(g / n);
     const long long j = g - (long long)t * n;
     if (j >= k0 && j < k0 + nb) continue;
     A[(k0 + t) * n + j] = R[g];
+  }
+}
+
+// Pivot list of a block step without pivoting: the window's diagonal in order.
+__global__ void k_gj_plain_order(int* __restrict__ sw, int nb) {
+  const int t = threadIdx.x;
+  if (t == 0) sw[0] = 0;
+  if (t < nb) {
+    sw[1 + 2 * kGJ + t] = t;
+    sw[1 + 3 * kGJ + t] = 1;
+  }
+}
+
+// dst = src (n entries) when the gate is open.
+__global__ void k_copy_gated(const double* __restrict__ src, double* __restrict__ dst, long long n,
+                             const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;   // pivoted pass not needed
+  for (long long g = blockIdx.x * (long long)kVB + threadIdx.x; g < n; g += (long long)gridDim.x * kVB) dst[g] = src[g];
+}
+
+// Accepts the plain pass when every pivot was positive and above the
+// singularity threshold: the matrix is then positive definite (Sylvester) and
+// elimination without exchanges is stable (no element growth).  Otherwise
+// sets flag[2], the gate of the pivoted pass, and clears the plain pass's
+// pivot flags.
+__global__ void k_plain_decide(int* __restrict__ flag) {
+  if (threadIdx.x != 0) return;
+  const bool ok = flag[0] == 0 && flag[1] == 0;
+  flag[2] = ok ? 0 : 1;
+  if (!ok) {
+    flag[0] = 0;
+    flag[1] = 0;
   }
 }
 
@@ -1022,55 +1127,84 @@ void material_bits(uint32_t* bits, long long ncells, int N, int dim, int n1, con
                      h, incl, nincl, nwords);
 }
 
-void gj_choose_block(double* A, long long n, long long k0, int nb, double* key, double* V, int* sw, int* perm,
-                     hipStream_t s) {
-  hipLaunchKernelGGL(k_gj_choose, dim3(1), dim3(kSel), 0, s, A, n, k0, nb, key, V, sw);
-  hipLaunchKernelGGL(k_gj_swap_rows, dim3(grid_for((long long)kGJ * n)), dim3(kVB), 0, s, A, n, sw);
-  hipLaunchKernelGGL(k_gj_swap_cols, dim3(grid_for((long long)kGJ * n)), dim3(kVB), 0, s, A, n, sw, perm);
-}
-void gj_pivot(double* A, long long n, long long k0, int nb, double* Pinv, int* flag, const double* scale, double tol,
-              const int* sw, hipStream_t s) {
-  hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(256), 0, s, A, n, k0, nb, Pinv, flag, scale, tol, sw);
-}
-void diag_absmax(const double* A, long long n, double* scale, hipStream_t s) {
-  hipLaunchKernelGGL(k_diag_absmax, dim3(1), dim3(kVB), 0, s, A, n, scale);
-}
-void gj_panels(const double* A, long long n, long long k0, int nb, const double* Pinv, double* Cb, double* R,
-               hipStream_t s) {
-  hipLaunchKernelGGL(k_gj_rowpanel, dim3(grid_for((long long)nb * n)), dim3(kVB), 0, s, A, n, k0, nb, Pinv, R);
-  hipLaunchKernelGGL(k_gj_colpanel, dim3(grid_for((long long)nb * n)), dim3(kVB), 0, s, A, n, k0, nb, Cb);
-}
-void gj_update(double* A, long long n, long long k0, int nb, const double* Cb, const double* R, hipStream_t s) {
-  const unsigned nt = (unsigned)((n + kGJ - 1) / kGJ);
-  hipLaunchKernelGGL(k_gj_update, dim3(nt, nt), dim3(256), 0, s, A, n, k0, nb, Cb, R);
-}
-void gj_finish(double* A, long long n, long long k0, int nb, const double* Cb, const double* R, const double* Pinv,
-               hipStream_t s) {
-  hipLaunchKernelGGL(k_gj_fincol, dim3(grid_for((long long)nb * n)), dim3(kVB), 0, s, A, n, k0, nb, Cb, Pinv);
-  hipLaunchKernelGGL(k_gj_finrow, dim3(grid_for((long long)nb * n)), dim3(kVB), 0, s, A, n, k0, nb, R);
-}
-void dense_inverse(double* A, long long n, int* perm, const DenseInvWork& w, double tol, hipStream_t s) {
-  diag_absmax(A, n, w.scale, s);
-  for (long long k0 = 0; k0 < n; k0 += kGJ) {
-    const int nb = (int)std::min<long long>(kGJ, n - k0);
-    gj_choose_block(A, n, k0, nb, w.key, w.C, w.sw, perm, s);
-    gj_pivot(A, n, k0, nb, w.Pinv, w.flag, w.scale, tol, w.sw, s);
-    gj_panels(A, n, k0, nb, w.Pinv, w.C, w.R, s);
-    gj_update(A, n, k0, nb, w.C, w.R, s);
-    gj_finish(A, n, k0, nb, w.C, w.R, w.Pinv, s);
-  }
-}
 __global__ void k_unpermute(const double* __restrict__ A, const int* __restrict__ perm, long long n,
-                            double* __restrict__ out) {
+                            double* __restrict__ out, const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;   // pivoted pass not needed
   const long long total = n * n;
   for (long long g = blockIdx.x * (long long)kVB + threadIdx.x; g < total; g += (long long)gridDim.x * kVB) {
     const long long i = g / n, j = g - i * n;
     out[(long long)perm[i] * n + perm[j]] = A[g];
   }
 }
-void unpermute(const double* A, const int* perm, long long n, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_unpermute, dim3(grid_for(n * n)), dim3(kVB), 0, s, A, perm, n, out);
+void gj_choose_block(double* A, long long n, long long k0, int nb, double* V, int* sw, int* perm, const int* gate,
+                     hipStream_t s) {
+  const long long m = n - k0;
+  if (m <= 2 * kSel)
+    hipLaunchKernelGGL(k_gj_choose<2>, dim3(1), dim3(kSel), 0, s, A, n, k0, nb, V, sw, gate);
+  else if (m <= 5 * kSel)
+    hipLaunchKernelGGL(k_gj_choose<5>, dim3(1), dim3(kSel), 0, s, A, n, k0, nb, V, sw, gate);
+  else if (m <= 10 * kSel)
+    hipLaunchKernelGGL(k_gj_choose<10>, dim3(1), dim3(kSel), 0, s, A, n, k0, nb, V, sw, gate);
+  else
+    hipLaunchKernelGGL(k_gj_choose<kPerMax>, dim3(1), dim3(kSel), 0, s, A, n, k0, nb, V, sw, gate);
+  hipLaunchKernelGGL(k_gj_swap_rows, dim3(grid_for((long long)kGJ * n)), dim3(kVB), 0, s, A, n, sw, gate);
+  hipLaunchKernelGGL(k_gj_swap_cols, dim3(grid_for((long long)kGJ * n)), dim3(kVB), 0, s, A, n, sw, perm, gate);
 }
+void gj_pivot(double* A, long long n, long long k0, int nb, double* Pinv, int* flag, const double* scale, double tol,
+              const int* sw, const int* gate, hipStream_t s) {
+  hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(256), 0, s, A, n, k0, nb, Pinv, flag, scale, tol, sw, gate);
+}
+void diag_absmax(const double* A, long long n, double* scale, const int* gate, hipStream_t s) {
+  hipLaunchKernelGGL(k_diag_absmax, dim3(1), dim3(kVB), 0, s, A, n, scale, gate);
+}
+void gj_panels(const double* A, long long n, long long k0, int nb, const double* Pinv, double* Cb, double* R,
+               const int* gate, hipStream_t s) {
+  hipLaunchKernelGGL(k_gj_rowpanel, dim3(grid_for((long long)nb * n)), dim3(kVB), 0, s, A, n, k0, nb, Pinv, R, gate);
+  hipLaunchKernelGGL(k_gj_colpanel, dim3(grid_for((long long)nb * n)), dim3(kVB), 0, s, A, n, k0, nb, Cb, gate);
+}
+void gj_update(double* A, long long n, long long k0, int nb, const double* Cb, const double* R, const int* gate,
+               hipStream_t s) {
+  const unsigned nt = (unsigned)((n + kGJ - 1) / kGJ);
+  hipLaunchKernelGGL(k_gj_update, dim3(nt, nt), dim3(256), 0, s, A, n, k0, nb, Cb, R, gate);
+}
+void gj_finish(double* A, long long n, long long k0, int nb, const double* Cb, const double* R, const double* Pinv,
+               const int* gate, hipStream_t s) {
+  hipLaunchKernelGGL(k_gj_fincol, dim3(grid_for((long long)nb * n)), dim3(kVB), 0, s, A, n, k0, nb, Cb, Pinv, gate);
+  hipLaunchKernelGGL(k_gj_finrow, dim3(grid_for((long long)nb * n)), dim3(kVB), 0, s, A, n, k0, nb, R, gate);
+}
+// Block Gauss-Jordan sweeps over A in place: pivoted (Bunch-Kaufman choice,
+// exchanges, perm following) or in plain diagonal order; every launch of the
+// pivoted form is gated.
+void gj_blocks(double* A, long long n, int* perm, const DenseInvWork& w, double tol, bool pivoted, const int* gate,
+               hipStream_t s) {
+  diag_absmax(A, n, w.scale, gate, s);
+  for (long long k0 = 0; k0 < n; k0 += kGJ) {
+    const int nb = (int)std::min<long long>(kGJ, n - k0);
+    if (pivoted)
+      gj_choose_block(A, n, k0, nb, w.C, w.sw, perm, gate, s);
+    else
+      hipLaunchKernelGGL(k_gj_plain_order, dim3(1), dim3(kGJ), 0, s, w.sw, nb);
+    gj_pivot(A, n, k0, nb, w.Pinv, w.flag, w.scale, tol, w.sw, gate, s);
+    gj_panels(A, n, k0, nb, w.Pinv, w.C, w.R, gate, s);
+    gj_update(A, n, k0, nb, w.C, w.R, gate, s);
+    gj_finish(A, n, k0, nb, w.C, w.R, w.Pinv, gate, s);
+  }
+}
+void dense_inverse(double* A, double* X, long long n, int* perm, const DenseInvWork& w, double tol, bool natural,
+                   hipStream_t s) {
+  // plain pass on a copy in X, accepted on the device
+  hipLaunchKernelGGL(k_copy_gated, dim3(grid_for(n * n)), dim3(kVB), 0, s, A, X, n * n, nullptr);
+  gj_blocks(X, n, perm, w, tol, false, nullptr, s);
+  hipLaunchKernelGGL(k_plain_decide, dim3(1), dim3(64), 0, s, w.flag);
+  // pivoted pass on A, run only when the plain one was rejected
+  const int* gate = w.flag + 2;
+  gj_blocks(A, n, perm, w, tol, true, gate, s);
+  if (natural)
+    hipLaunchKernelGGL(k_unpermute, dim3(grid_for(n * n)), dim3(kVB), 0, s, A, perm, n, X, gate);
+  else
+    hipLaunchKernelGGL(k_copy_gated, dim3(grid_for(n * n)), dim3(kVB), 0, s, A, X, n * n, gate);
+}
+
 __global__ void k_iota(int* __restrict__ v, long long n) {
   for (long long g = blockIdx.x * (long long)kVB + threadIdx.x; g < n; g += (long long)gridDim.x * kVB) v[g] = (int)g;
 }

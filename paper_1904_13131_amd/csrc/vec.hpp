@@ -109,38 +109,46 @@ void dirichlet_delta(const double* u, double* dg, const Lattice& lt, const doubl
 void material_bits(uint32_t* bits, long long ncells, int N, int dim, int n1, const Tables<double>& tb, double h,
                    const double* incl, int nincl, int nwords, hipStream_t s);
 
-// Coarse direct solve: in-place block Gauss-Jordan inverse of a symmetric
-// nonsingular matrix (no pivoting).  flag[0]: singular pivot met; flag[1]:
-// number of negative pivots (the inertia of the matrix).
-void diag_absmax(const double* A, long long n, double* scale, hipStream_t s);
-// Work arrays of the pivoted dense inverse: Pinv 64 x 64, C and R n x 64,
-// key n, sw 1 + 4 * 64 ints, flag 2 ints (zeroed by the caller), scale 1.
+// Coarse direct solve (dense FP64 inverse of a symmetric nonsingular matrix).
+// Work arrays: Pinv 64 x 64, C and R n x 64, sw 1 + 4 * 64 ints, flag 3 ints
+// (zeroed by the caller), scale 1.
 struct DenseInvWork {
-  double *Pinv, *C, *R, *key, *scale;
+  double *Pinv, *C, *R, *scale;
   int *sw, *flag;
 };
-// In-place inverse of the symmetric n x n matrix A (row-major) in a permuted
-// basis: A <- (Q A Q^T)^-1 with perm <- Q perm (perm[i] = original index of
-// position i; the caller initialises it).  flag[0] = numerically singular
-// (pivot magnitude <= tol * max |A_ii|), flag[1] += negative eigenvalues.
-void dense_inverse(double* A, long long n, int* perm, const DenseInvWork& w, double tol, hipStream_t s);
-// out[perm[i]][perm[j]] = A[i][j]; v[i] = i
-void unpermute(const double* A, const int* perm, long long n, double* out, hipStream_t s);
+// X <- A^-1 for the symmetric n x n matrix A (row-major).  First block
+// Gauss-Jordan in plain diagonal order on a copy in X, kept (decided on the
+// device, without a host round trip) when every pivot is positive and above
+// tol * max |A_ii|, i.e. A is positive definite; A and perm are then left
+// unchanged.  Otherwise (flag[2] = 1) the pivoted pass inverts A in place in a
+// permuted basis, A <- (Q A Q^T)^-1 with perm <- Q perm (perm[i] = original
+// index of position i; the caller initialises it), and X receives that
+// inverse in the original order (natural) or as it is, in the permuted basis
+// (!natural, perm then maps its positions).  flag[0] = numerically singular,
+// flag[1] = negative eigenvalues (Sylvester: the signs of the pivots).
+void dense_inverse(double* A, double* X, long long n, int* perm, const DenseInvWork& w, double tol, bool natural,
+                   hipStream_t s);
 void iota(int* v, long long n, hipStream_t s);
 // Most free coarse DoFs the pivoted inverse handles (LDS bitmap of the pivot choice).
 constexpr int kGJMaxFree = 20480;
-// Chooses a block step's pivots (Bunch-Kaufman on the current Schur
-// complement) and exchanges them into [k0, k0 + nb); perm (free index -> DoF)
-// follows.  key: n doubles, V: 64 n doubles of scratch; sw: 1 + 4 * 64 ints
-// (exchange pairs and the pivot list that gj_pivot follows).
-void gj_choose_block(double* A, long long n, long long k0, int nb, double* key, double* V, int* sw, int* perm,
+// Block steps of dense_inverse.  gate: NULL, or a device flag that lets the
+// launches run only when it is nonzero.  gj_choose_block chooses a block
+// step's pivots (Bunch-Kaufman on the current Schur complement) and exchanges
+// them into [k0, k0 + nb); perm (free index -> DoF) follows.  V: 64 n doubles
+// of scratch; sw: 1 + 4 * 64 ints (exchange pairs and the pivot list that
+// gj_pivot follows).
+void gj_choose_block(double* A, long long n, long long k0, int nb, double* V, int* sw, int* perm, const int* gate,
                      hipStream_t s);
 void gj_pivot(double* A, long long n, long long k0, int nb, double* Pinv, int* flag, const double* scale, double tol,
-              const int* sw, hipStream_t s);
+              const int* sw, const int* gate, hipStream_t s);
+void diag_absmax(const double* A, long long n, double* scale, const int* gate, hipStream_t s);
 void gj_panels(const double* A, long long n, long long k0, int nb, const double* Pinv, double* Cb, double* R,
+               const int* gate, hipStream_t s);
+void gj_update(double* A, long long n, long long k0, int nb, const double* Cb, const double* R, const int* gate,
                hipStream_t s);
-void gj_update(double* A, long long n, long long k0, int nb, const double* Cb, const double* R, hipStream_t s);
 void gj_finish(double* A, long long n, long long k0, int nb, const double* Cb, const double* R, const double* Pinv,
+               const int* gate, hipStream_t s);
+void gj_blocks(double* A, long long n, int* perm, const DenseInvWork& w, double tol, bool pivoted, const int* gate,
                hipStream_t s);
 // z[dof_of[f]] = sum_g Kinv[f][g] r[dof_of[g]]  (z pre-zeroed)
 template <typename T> void coarse_apply(const double* Kinv, long long nf, const int* dof_of, const T* r, double* rf,

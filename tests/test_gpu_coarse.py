@@ -1,8 +1,9 @@
 """GPU tests of the coarse level's dense direct solver (the exact FP64 coarse
-solve of the V-cycle) on matrices with known inverses and inertia: symmetric
-pivoting handles zero leading minors and indefinite matrices; the negative
-pivot count equals the number of negative eigenvalues (Sylvester's law of
-inertia); singular matrices are reported."""
+solve of the V-cycle) on matrices with known inverses and inertia: the plain
+pass where it is accurate, symmetric pivoting where it is not (zero or small
+leading minors, saddle-point matrices); the negative pivot count equals the
+number of negative eigenvalues (Sylvester's law of inertia); singular
+matrices are reported."""
 import numpy as np
 import pytest
 import torch
@@ -47,6 +48,9 @@ CASES = {
 A = _sym(150, 7)
 A[0, 0] = 1e-14                      # a leading 1x1 minor that is not zero, only tiny
 CASES["tiny_first_pivot_150"] = A
+A = _sym(150, 7)
+A[0, 0] = 1e-9                       # above the singularity threshold: the plain pass
+CASES["small_first_pivot_150"] = A   # grows entries ~1e9 and must be rejected
 
 
 @pytest.mark.parametrize("name", list(CASES))
