@@ -119,6 +119,12 @@ enum {
   MFH_SCATTER_ELEMENT = 3
 };
 
+/* Tile shape of the TILE scatter: two shapes (cells per axis) are compiled
+ * for every dimension, degree and precision; AUTO takes the one the
+ * autotuner measured faster for the level (same table as the scatter mode),
+ * 0 or 1 forces one.  mfh_tile_shape reports the shape a level uses. */
+enum { MFH_TILE_SHAPE_AUTO = -1 };
+
 /* Displacement the coarser level operators are linearised about (Sec. 6
  * restricts the fine displacement to every level without saying how):
  * NODAL interpolates the finer level's field at the coarser support points,
@@ -168,14 +174,14 @@ typedef struct {
   int law;                   /* MFH_LAW_*                                                 */
   const double* mu2;         /* host [n_materials] second-invariant moduli >= 0 (law
                                 MOONEY_RIVLIN; ignored, may be NULL, otherwise)           */
+  int tile_shape;            /* MFH_TILE_SHAPE_AUTO, 0 or 1 (TILE scatter only)          */
 } mfh_desc;
 
 /* Fills *desc with the paper's solver settings (degree 4, 2 steps, 30
- * iterations, [0.6, 1.2]), RECOMPUTE, AUTO scatter, F32 V-cycle, NODAL level
- * fields, DIRECT coarse solve, eigenvalue estimates at every linearisation,
- * the Neo-Hookean law;
- * geometry fields
- * are zeroed and must be set by the caller. */
+ * iterations, [0.6, 1.2]), RECOMPUTE, AUTO scatter and tile shape, F32
+ * V-cycle, NODAL level fields, DIRECT coarse solve, eigenvalue estimates at
+ * every linearisation, the Neo-Hookean law; geometry fields are zeroed and
+ * must be set by the caller. */
 void mfh_desc_defaults(mfh_desc* desc);
 
 /* Device bytes the problem needs.  Errors: MFH_ERR_INVALID_ARG. */
@@ -339,6 +345,13 @@ mfh_status mfh_external_force(mfh_problem* problem, const double* face_traction,
  * descriptor's mode, or the tuned choice under MFH_SCATTER_AUTO) into *mode.
  * Host only.  Errors: INVALID_ARG. */
 mfh_status mfh_scatter_mode(const mfh_problem* problem, int level, int dtype, int* mode);
+
+/* The TILE scatter's tile shape on `level` in precision dtype (the
+ * descriptor's, or the tuned one under MFH_TILE_SHAPE_AUTO) into *shape (0 or
+ * 1) and its cells per axis into cells[0..2] (cells[2] = 1 in 2-D).  Reported
+ * whatever the scatter mode; it is used only when the level runs TILE.  Host
+ * only.  Errors: INVALID_ARG. */
+mfh_status mfh_tile_shape(const mfh_problem* problem, int level, int dtype, int* shape, int* cells);
 
 /* Coordinates of the support points along one axis of `level` (all axes
  * are alike): the L = degree * N + 1 lattice positions in [0, 1], the

@@ -5,6 +5,10 @@
 
 namespace mfh {
 
+struct TileShape {
+  int tx, ty, tz;
+};
+
 struct OpFns {
   // tangent vmult per policy (0 R, 1 CF, 2 C2, 3 C4)
   void (*tangent_d[4])(const CellArgs<double>&, unsigned grid, hipStream_t);
@@ -14,10 +18,11 @@ struct OpFns {
   void (*qpdata_d[4])(const CellArgs<double>&, double* cache, unsigned grid, hipStream_t);
   void (*qpdata_f[4])(const CellArgs<double>&, float* cache, unsigned grid, hipStream_t);
   void (*diag)(const CellArgs<double>&, hipStream_t);   // adds into a.y
-  // tile variant of the tangent vmult (atomic scatter only); grid = tiles(N)
-  void (*tangent_tile_d[4])(const CellArgs<double>&, unsigned grid, hipStream_t);
-  void (*tangent_tile_f[4])(const CellArgs<float>&, unsigned grid, hipStream_t);
-  long long (*tiles[2])(int N);   // [0] double, [1] float
+  // tile variant of the tangent vmult per tile shape [shape][policy]; grid = tiles[dtype][shape](N)
+  void (*tangent_tile_d[2][4])(const CellArgs<double>&, unsigned grid, hipStream_t);
+  void (*tangent_tile_f[2][4])(const CellArgs<float>&, unsigned grid, hipStream_t);
+  long long (*tiles[2][2])(int N);   // [0] double, [1] float
+  TileShape tile_shape[2][2];        // cells per axis of each shape, [dtype][shape]
   // batched vmult over problems of this (dim, degree): one workgroup per (problem, cell block) item
   // (max_cells: the largest cell count of the bin's problems)
   void (*tangent_batch_d[4])(const CellArgs<double>* args, const int2* items, const double* const* xs,

@@ -8,47 +8,72 @@
 
 namespace mfh {
 
-// Tile shape (cells per axis) and components per sweep batch of the tile kernel,
-// per dimension, degree and precision.  A tile uses cells x (pencils per cell)
-// threads; the FP64 kernels hold about 2x the registers of the FP32 ones, so
-// their tiles stay within 256 threads (two resident blocks per CU).
-template <int DIM, int P, typename T>
+// Tile shapes (cells per axis) and components per sweep batch of the tile
+// kernel, per dimension, degree and precision: two shapes each, the tuned
+// table (or the descriptor's tile_shape) picks one per level.  A tile uses
+// cells x (pencils per cell) threads, rounded up to whole wavefronts; shape 0
+// keeps FP64 tiles within 256 threads (two resident blocks per CU, FP64
+// kernels hold about 2x the registers of FP32 ones), shape 1 is the
+// alternative: larger tiles (fewer tile faces, hence fewer atomics) where the
+// LDS allows, smaller ones where shape 0 is already large.
+template <int DIM, int P, typename T, int V>
 struct TileCfg;
-#define MFH_TILE(D, P, T, X, Y, Z, C) \
-  template <> struct TileCfg<D, P, T> { static constexpr int TX = X, TY = Y, TZ = Z, NC = C; };
-MFH_TILE(3, 1, double, 4, 4, 4, 3)
-MFH_TILE(3, 1, float, 4, 4, 4, 3)
-MFH_TILE(3, 2, double, 3, 3, 3, 3)
-MFH_TILE(3, 2, float, 4, 4, 2, 3)
-MFH_TILE(3, 3, double, 2, 2, 4, 1)
-MFH_TILE(3, 3, float, 2, 2, 4, 3)
-MFH_TILE(3, 4, double, 2, 2, 2, 1)
-MFH_TILE(3, 4, float, 2, 2, 2, 1)
-MFH_TILE(2, 1, double, 16, 8, 1, 2)
-MFH_TILE(2, 1, float, 16, 8, 1, 2)
-MFH_TILE(2, 2, double, 16, 5, 1, 2)
-MFH_TILE(2, 2, float, 16, 5, 1, 2)
-MFH_TILE(2, 3, double, 8, 8, 1, 2)
-MFH_TILE(2, 3, float, 8, 8, 1, 2)
-MFH_TILE(2, 4, double, 8, 6, 1, 2)
-MFH_TILE(2, 4, float, 8, 6, 1, 2)
+#define MFH_TILE(D, P, T, V, X, Y, Z, C) \
+  template <> struct TileCfg<D, P, T, V> { static constexpr int TX = X, TY = Y, TZ = Z, NC = C; };
+MFH_TILE(3, 1, double, 0, 4, 4, 4, 3)
+MFH_TILE(3, 1, double, 1, 8, 4, 2, 3)
+MFH_TILE(3, 1, float, 0, 4, 4, 4, 3)
+MFH_TILE(3, 1, float, 1, 8, 8, 2, 3)
+MFH_TILE(3, 2, double, 0, 3, 3, 3, 3)
+MFH_TILE(3, 2, double, 1, 4, 4, 2, 3)
+MFH_TILE(3, 2, float, 0, 4, 4, 2, 3)
+MFH_TILE(3, 2, float, 1, 3, 3, 3, 3)
+MFH_TILE(3, 3, double, 0, 2, 2, 4, 1)
+MFH_TILE(3, 3, double, 1, 4, 2, 2, 1)
+MFH_TILE(3, 3, float, 0, 2, 2, 4, 3)
+MFH_TILE(3, 3, float, 1, 2, 2, 2, 3)
+MFH_TILE(3, 4, double, 0, 2, 2, 2, 1)
+MFH_TILE(3, 4, double, 1, 4, 2, 2, 1)
+MFH_TILE(3, 4, float, 0, 2, 2, 2, 1)
+MFH_TILE(3, 4, float, 1, 2, 2, 2, 3)
+MFH_TILE(2, 1, double, 0, 16, 8, 1, 2)
+MFH_TILE(2, 1, double, 1, 16, 16, 1, 2)
+MFH_TILE(2, 1, float, 0, 16, 8, 1, 2)
+MFH_TILE(2, 1, float, 1, 16, 16, 1, 2)
+MFH_TILE(2, 2, double, 0, 16, 5, 1, 2)
+MFH_TILE(2, 2, double, 1, 8, 8, 1, 2)
+MFH_TILE(2, 2, float, 0, 16, 5, 1, 2)
+MFH_TILE(2, 2, float, 1, 8, 8, 1, 2)
+MFH_TILE(2, 3, double, 0, 8, 8, 1, 2)
+MFH_TILE(2, 3, double, 1, 16, 4, 1, 2)
+MFH_TILE(2, 3, float, 0, 8, 8, 1, 2)
+MFH_TILE(2, 3, float, 1, 16, 4, 1, 2)
+MFH_TILE(2, 4, double, 0, 8, 6, 1, 2)
+MFH_TILE(2, 4, double, 1, 8, 4, 1, 2)
+MFH_TILE(2, 4, float, 0, 8, 6, 1, 2)
+MFH_TILE(2, 4, float, 1, 8, 4, 1, 2)
 #undef MFH_TILE
 
 template <int DIM, int P>
 struct OpInst {
-  template <typename T, int POL>
+  template <typename T, int POL, int V>
   static void tangent_tile(const CellArgs<T>& a, unsigned grid, hipStream_t s) {
-    using TC = TileCfg<DIM, P, T>;
+    using TC = TileCfg<DIM, P, T, V>;
     using TGeo = TileGeo<DIM, P, TC::TX, TC::TY, TC::TZ>;
     hipLaunchKernelGGL((k_tangent_tile<DIM, P, T, POL, TC::TX, TC::TY, TC::TZ, TC::NC>), dim3(grid),
                        dim3(TGeo::BLOCK), 0, s, a);
   }
-  template <typename T>
+  template <typename T, int V>
   static long long tiles(int N) {
-    using TC = TileCfg<DIM, P, T>;
+    using TC = TileCfg<DIM, P, T, V>;
     const long long tx = (N + TC::TX - 1) / TC::TX, ty = (N + TC::TY - 1) / TC::TY;
     const long long tz = DIM == 3 ? (N + TC::TZ - 1) / TC::TZ : 1;
     return tx * ty * tz;
+  }
+  template <typename T, int V>
+  static constexpr TileShape shape() {
+    using TC = TileCfg<DIM, P, T, V>;
+    return TileShape{TC::TX, TC::TY, DIM == 3 ? TC::TZ : 1};
   }
   // 32-bit lane offsets (see lane_load) when every per-lane offset of a level
   // with `cells` cells fits, including those into arrays of T pairs
@@ -136,11 +161,16 @@ struct OpInst {
         {&qpdata<double, POL_R>, &qpdata<double, POL_CF>, &qpdata<double, POL_C2>, &qpdata<double, POL_C4>},
         {&qpdata<float, POL_R>, &qpdata<float, POL_CF>, &qpdata<float, POL_C2>, &qpdata<float, POL_C4>},
         &diag,
-        {&tangent_tile<double, POL_R>, &tangent_tile<double, POL_CF>, &tangent_tile<double, POL_C2>,
-         &tangent_tile<double, POL_C4>},
-        {&tangent_tile<float, POL_R>, &tangent_tile<float, POL_CF>, &tangent_tile<float, POL_C2>,
-         &tangent_tile<float, POL_C4>},
-        {&tiles<double>, &tiles<float>},
+        {{&tangent_tile<double, POL_R, 0>, &tangent_tile<double, POL_CF, 0>, &tangent_tile<double, POL_C2, 0>,
+          &tangent_tile<double, POL_C4, 0>},
+         {&tangent_tile<double, POL_R, 1>, &tangent_tile<double, POL_CF, 1>, &tangent_tile<double, POL_C2, 1>,
+          &tangent_tile<double, POL_C4, 1>}},
+        {{&tangent_tile<float, POL_R, 0>, &tangent_tile<float, POL_CF, 0>, &tangent_tile<float, POL_C2, 0>,
+          &tangent_tile<float, POL_C4, 0>},
+         {&tangent_tile<float, POL_R, 1>, &tangent_tile<float, POL_CF, 1>, &tangent_tile<float, POL_C2, 1>,
+          &tangent_tile<float, POL_C4, 1>}},
+        {{&tiles<double, 0>, &tiles<double, 1>}, {&tiles<float, 0>, &tiles<float, 1>}},
+        {{shape<double, 0>(), shape<double, 1>()}, {shape<float, 0>(), shape<float, 1>()}},
         {&tangent_batch<double, POL_R>, &tangent_batch<double, POL_CF>, &tangent_batch<double, POL_C2>,
          &tangent_batch<double, POL_C4>},
         {&tangent_batch<float, POL_R>, &tangent_batch<float, POL_CF>, &tangent_batch<float, POL_C2>,

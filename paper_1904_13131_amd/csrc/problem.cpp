@@ -213,6 +213,7 @@ void validate(const mfh_desc* d) {
       if (!(d->mu2[m] >= 0) || !std::isfinite(d->mu2[m])) bad("mu2 must be finite and >= 0");
   }
   if (d->scatter < MFH_SCATTER_AUTO || d->scatter > MFH_SCATTER_ELEMENT) bad("bad scatter mode");
+  if (d->tile_shape < MFH_TILE_SHAPE_AUTO || d->tile_shape > 1) bad("bad tile shape");
   if (d->vcycle_dtype != MFH_F32 && d->vcycle_dtype != MFH_F64) bad("bad vcycle_dtype");
   if (d->cheb_degree < 1 || d->cheb_degree > 16) bad("cheb_degree must be 1..16");
   if (d->n_smooth < 1 || d->n_smooth > 8) bad("n_smooth must be 1..8");
@@ -326,6 +327,13 @@ void build_host(mfh_problem* P) {
 int scatter_mode(const mfh_problem* P, const Level& v, int t) {
   if (P->d.scatter != MFH_SCATTER_AUTO) return P->d.scatter;
   return tuned_scatter(P->d.dim, P->d.degree, t, P->d.qp_policy, v.ncells);
+}
+
+// Tile shape of the TILE scatter on a level: the descriptor's, or with
+// MFH_TILE_SHAPE_AUTO the faster of the two measured for the level.
+int tile_shape(const mfh_problem* P, const Level& v, int t) {
+  if (P->d.tile_shape != MFH_TILE_SHAPE_AUTO) return P->d.tile_shape;
+  return tuned_tile(P->d.dim, P->d.degree, t, P->d.qp_policy, v.ncells);
 }
 
 size_t layout(mfh_problem* P, char* base) {
@@ -467,8 +475,8 @@ struct Sel<double> {
   static void run(const OpFns* o, int pol, const CellArgs<double>& a, unsigned g, hipStream_t s) {
     o->tangent_d[pol](a, g, s);
   }
-  static void run_tile(const OpFns* o, int pol, const CellArgs<double>& a, unsigned g, hipStream_t s) {
-    o->tangent_tile_d[pol](a, g, s);
+  static void run_tile(const OpFns* o, int shape, int pol, const CellArgs<double>& a, unsigned g, hipStream_t s) {
+    o->tangent_tile_d[shape][pol](a, g, s);
   }
   static void elem_gather(const OpFns* o, const CellArgs<double>& a, hipStream_t s) { o->elem_gather_d(a, s); }
   static void elem_gather_cheb(const OpFns* o, const CellArgs<double>& a, const ChebOut<double>& c, hipStream_t s) {
@@ -483,8 +491,8 @@ struct Sel<float> {
   static void run(const OpFns* o, int pol, const CellArgs<float>& a, unsigned g, hipStream_t s) {
     o->tangent_f[pol](a, g, s);
   }
-  static void run_tile(const OpFns* o, int pol, const CellArgs<float>& a, unsigned g, hipStream_t s) {
-    o->tangent_tile_f[pol](a, g, s);
+  static void run_tile(const OpFns* o, int shape, int pol, const CellArgs<float>& a, unsigned g, hipStream_t s) {
+    o->tangent_tile_f[shape][pol](a, g, s);
   }
   static void elem_gather(const OpFns* o, const CellArgs<float>& a, hipStream_t s) { o->elem_gather_f(a, s); }
   static void elem_gather_cheb(const OpFns* o, const CellArgs<float>& a, const ChebOut<float>& c, hipStream_t s) {
@@ -532,7 +540,8 @@ void vmult(mfh_problem* P, int l, const T* x, T* y, int mask_in = 1) {
   timer_mark(P);
   if (mode == MFH_SCATTER_TILE) {
     const int ti = std::is_same<T, double>::value ? 0 : 1;
-    Sel<T>::run_tile(P->ops, P->d.qp_policy, a, (unsigned)P->ops->tiles[ti](v.N), P->stream);
+    const int ts = tile_shape(P, v, ti);
+    Sel<T>::run_tile(P->ops, ts, P->d.qp_policy, a, (unsigned)P->ops->tiles[ti][ts](v.N), P->stream);
   } else if (mode == MFH_SCATTER_ATOMIC) {
     Sel<T>::run(P->ops, P->d.qp_policy, a, (unsigned)((v.ncells + cpb - 1) / cpb), P->stream);
   } else {
@@ -1205,6 +1214,7 @@ void mfh_desc_defaults(mfh_desc* d) {
   d->coarse_solver = MFH_COARSE_DIRECT;
   d->eig_refresh = 1;
   d->law = MFH_LAW_NEO_HOOKE;
+  d->tile_shape = MFH_TILE_SHAPE_AUTO;
 }
 
 mfh_status mfh_workspace_size(const mfh_desc* desc, size_t* bytes) {
@@ -1599,6 +1609,21 @@ mfh_status mfh_scatter_mode(const mfh_problem* P, int level, int dtype, int* mod
     need(mode != nullptr, "mode is NULL");
     need(dtype == MFH_F64 || dtype == MFH_F32, "dtype must be MFH_F64 or MFH_F32");
     *mode = scatter_mode(P, P->lv[level], dtype == MFH_F64 ? 0 : 1);
+  });
+}
+
+mfh_status mfh_tile_shape(const mfh_problem* P, int level, int dtype, int* shape, int* cells) {
+  if (!P) return MFH_ERR_INVALID_ARG;
+  return guarded(const_cast<mfh_problem*>(P), [&] {
+    check_level(P, level);
+    need(shape != nullptr && cells != nullptr, "NULL argument");
+    need(dtype == MFH_F64 || dtype == MFH_F32, "dtype must be MFH_F64 or MFH_F32");
+    const int t = dtype == MFH_F64 ? 0 : 1;
+    *shape = tile_shape(P, P->lv[level], t);
+    const TileShape& ts = P->ops->tile_shape[t][*shape];
+    cells[0] = ts.tx;
+    cells[1] = ts.ty;
+    cells[2] = ts.tz;
   });
 }
 

@@ -50,14 +50,21 @@ def _oracle(name):
     return _ORACLE[name]
 
 
-@pytest.mark.parametrize("scatter", [0, 1, 2, 3, -1], ids=["atomic", "color", "tile", "elem", "auto"])
+# (scatter mode, tile shape): both compiled tile shapes of the TILE scatter
+SCATTERS64 = [(0, -1), (1, -1), (2, 0), (2, 1), (3, -1), (-1, -1)]
+SCATTERS32 = [(0, -1), (2, 0), (2, 1), (3, -1), (-1, -1)]
+IDS64 = ["atomic", "color", "tile0", "tile1", "elem", "auto"]
+IDS32 = ["atomic", "tile0", "tile1", "elem", "auto"]
+
+
+@pytest.mark.parametrize("scatter,tile", SCATTERS64, ids=IDS64)
 @pytest.mark.parametrize("policy", [0, 1, 2, 3], ids=["R", "CF", "C2", "C4"])
 @pytest.mark.parametrize("name", list(CASES))
-def test_vmult_fp64(name, policy, scatter):
-    log_case("vmult_fp64", name=name, policy=policy, scatter=scatter)
+def test_vmult_fp64(name, policy, scatter, tile):
+    log_case("vmult_fp64", name=name, policy=policy, scatter=scatter, tile=tile)
     w = CASES[name]
     _, _, _, K, _ = _oracle(name)
-    P = device_problem(w, qp_policy=policy, scatter=scatter)
+    P = device_problem(w, qp_policy=policy, scatter=scatter, tile_shape=tile)
     mj = P.set_deformation(dev(w["u"]))
     assert mj > 0
     y = host(P.tangent_vmult(dev(w["x"])))
@@ -65,19 +72,37 @@ def test_vmult_fp64(name, policy, scatter):
     assert rel_l2(y, want) <= 1e-12 and rel_max(y, want) <= 1e-12
 
 
-@pytest.mark.parametrize("scatter", [0, 2, 3, -1], ids=["atomic", "tile", "elem", "auto"])
+@pytest.mark.parametrize("scatter,tile", SCATTERS32, ids=IDS32)
 @pytest.mark.parametrize("policy", [0, 1, 2, 3], ids=["R", "CF", "C2", "C4"])
 @pytest.mark.parametrize("name", list(CASES))
-def test_vmult_fp32(name, policy, scatter):
-    log_case("vmult_fp32", name=name, policy=policy, scatter=scatter)
+def test_vmult_fp32(name, policy, scatter, tile):
+    log_case("vmult_fp32", name=name, policy=policy, scatter=scatter, tile=tile)
     w = CASES[name]
     _, _, _, K, _ = _oracle(name)
-    P = device_problem(w, qp_policy=policy, scatter=scatter)
+    P = device_problem(w, qp_policy=policy, scatter=scatter, tile_shape=tile)
     P.set_deformation(dev(w["u"]))
     x32 = w["x"].astype(np.float32)
     y = host(P.tangent_vmult(dev(x32, torch.float32)))
     want = K @ x32.astype(np.float64)
     assert rel_l2(y, want) <= 1e-5 and rel_max(y, want) <= 1e-5
+
+
+def test_tile_shapes_reported():
+    """The two compiled tile shapes of a level, forced or tuned, as reported
+    by mfh_tile_shape: shape 0 of 3-D Q2 FP64 is 3 x 3 x 3 cells."""
+    from paper_1904_13131_amd import F32, F64
+    log_case("tile_shapes")
+    w = CASES["3d_q2"]
+    seen = set()
+    for tile in (0, 1):
+        P = device_problem(w, scatter=2, tile_shape=tile)
+        for dt in (F64, F32):
+            shape, cells = P.tile_shape(dtype=dt)
+            assert shape == tile and len(cells) == 3 and min(cells) >= 1
+            seen.add((dt, cells))
+    assert (F64, (3, 3, 3)) in seen and len(seen) == 4
+    P = device_problem(w, scatter=2)
+    assert P.tile_shape()[0] in (0, 1)
 
 
 @pytest.mark.parametrize("scatter", [0, 1], ids=["atomic", "color"])
