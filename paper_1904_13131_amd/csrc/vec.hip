@@ -734,21 +734,24 @@ __global__ void k_gj_swap_cols(double* __restrict__ A, long long n, const int* _
   }
 }
 
-// Inverts the symmetric pivot block [k0, k0 + nb) in LDS by Gauss-Jordan
-// sweeps in the order and grouping k_gj_choose recorded (sw).  flag[1]
-// accumulates the negative eigenvalues of the pivots; flag[0] is set when a
-// pivot (or a 2x2 determinant against its largest entry) is not finite or at
-// most tol * scale[0] in magnitude (numerically singular).
-__global__ void __launch_bounds__(256) k_gj_pivot(double* __restrict__ A, long long n, long long k0, int nb,
+// Inverts the symmetric pivot block [k0, k0 + nb) by Gauss-Jordan sweeps
+// (the block held in registers) in the order and grouping k_gj_choose
+// recorded (sw).  flag[1] accumulates the negative eigenvalues of the pivots;
+// flag[0] is set when a pivot (or a 2x2 determinant against its largest
+// entry) is not finite or at most tol * scale[0] in magnitude (numerically
+// singular).
+constexpr int kPivT = 1024;   // threads of the pivot-block kernel
+__global__ void __launch_bounds__(kPivT) k_gj_pivot(double* __restrict__ A, long long n, long long k0, int nb,
                                                   double* __restrict__ Pinv, int* flag, const double* scale,
                                                   double tol, const int* __restrict__ sw,
                                                   const int* __restrict__ gate) {
   if (gate && *gate == 0) return;   // pivoted pass not needed
-  __shared__ double M[kGJ][kGJ + 1];
-  __shared__ double colk[kGJ], rowk[kGJ], colr[kGJ], rowr[kGJ];
-  __shared__ int pos[kGJ], kind[kGJ];   // the pivot list, read at every step
-  // thread t owns column j = t % kGJ of rows t / kGJ + 4 r (256 threads)
-  constexpr int kRows = 256 / kGJ;
+  // thread t keeps column j = t % kGJ of rows i0 + kGroups r (i0 = t / kGJ,
+  // r < kPerT) in registers; each step broadcasts the pivot rows and columns
+  // through LDS (double-buffered, one barrier per step)
+  constexpr int kGroups = kPivT / kGJ, kPerT = kGJ / kGroups;
+  __shared__ double bc[2][4][kGJ];      // [buffer][col k, row k, col r, row r][index]
+  __shared__ int pos[kGJ], kind[kGJ];   // the pivot list
   const int t = threadIdx.x;
   const int j = t % kGJ, i0 = t / kGJ;
   const double thr = tol * scale[0];
@@ -756,73 +759,90 @@ __global__ void __launch_bounds__(256) k_gj_pivot(double* __restrict__ A, long l
     pos[t] = sw[1 + 2 * kGJ + t];
     kind[t] = sw[1 + 3 * kGJ + t];
   }
-  if (j < nb)
-    for (int i = i0; i < nb; i += kRows) M[i][j] = A[(k0 + i) * n + k0 + j];
+  double m[kPerT];
+#pragma unroll
+  for (int r = 0; r < kPerT; ++r) {
+    const int i = i0 + kGroups * r;
+    m[r] = (i < nb && j < nb) ? A[(k0 + i) * n + k0 + j] : 0.0;
+  }
   __syncthreads();
   bool bad = false;   // pivot checks of thread 0, written once at the end
   int neg = 0;
+  int buf = 0;
   for (int step = 0; step < nb;) {
     const int k = pos[step];
-    if (kind[step] == 1) {   // 1x1 pivot
-      if (t < nb) {
-        colk[t] = M[t][k];
-        rowk[t] = M[k][t];
+    const bool two = kind[step] != 1;
+    const int r2 = two ? pos[step + 1] : k;
+    double* ck = bc[buf][0];
+    double* rk = bc[buf][1];
+    double* cr = bc[buf][2];
+    double* rr = bc[buf][3];
+    // publish column k (and r) from the threads owning it, row k (and r) likewise
+    if (j == k || (two && j == r2)) {
+      double* dst = j == k ? ck : cr;
+#pragma unroll
+      for (int r = 0; r < kPerT; ++r) dst[i0 + kGroups * r] = m[r];
+    }
+    if (i0 == (k % kGroups) || (two && i0 == (r2 % kGroups))) {
+      double vk = 0.0, vr = 0.0;
+#pragma unroll
+      for (int r = 0; r < kPerT; ++r) {
+        vk = r == k / kGroups ? m[r] : vk;
+        vr = r == r2 / kGroups ? m[r] : vr;
       }
-      __syncthreads();
-      const double p = rowk[k];
+      if (i0 == (k % kGroups)) rk[j] = vk;
+      if (two && i0 == (r2 % kGroups)) rr[j] = vr;
+    }
+    __syncthreads();
+    if (!two) {   // 1x1 pivot
+      const double p = rk[k];
       if (t == 0) {
         bad = bad || !(fabs(p) > thr) || !isfinite(p);
         neg += p < 0.0 ? 1 : 0;
       }
       const double pinv = 1.0 / p;
-      if (j < nb) {
-        const double rj = rowk[j] * pinv;
-        for (int i = i0; i < nb; i += kRows) {
-          if (i == k)
-            M[i][j] = j == k ? pinv : rj;
-          else if (j == k)
-            M[i][j] = -colk[i] * pinv;
-          else
-            M[i][j] -= colk[i] * rj;
-        }
+      // branch-free (selects), so that m stays in place in registers
+      const double rj = rk[j] * pinv;
+      const double rowv = j == k ? pinv : rj;
+#pragma unroll
+      for (int r = 0; r < kPerT; ++r) {
+        const int i = i0 + kGroups * r;
+        const double ci = ck[i];
+        const double v = i == k ? rowv : (j == k ? -ci * pinv : m[r] - ci * rj);
+        m[r] = (i < nb && j < nb) ? v : m[r];
       }
       step += 1;
     } else {   // 2x2 pivot {k, r}: E = [[a, b], [b, c]]
-      const int r = pos[step + 1];
-      if (t < nb) {
-        colk[t] = M[t][k];
-        rowk[t] = M[k][t];
-        colr[t] = M[t][r];
-        rowr[t] = M[r][t];
-      }
-      __syncthreads();
-      const double a = rowk[k], b = rowk[r], c = rowr[r];
+      const double a = rk[k], b = rk[r2], c = rr[r2];
       const double det = a * c - b * b;
       if (t == 0) {
         bad = bad || !(fabs(det) > thr * fmax(fabs(b), fmax(fabs(a), fabs(c)))) || !isfinite(det);
         neg += det < 0.0 ? 1 : (a + c < 0.0 ? 2 : 0);
       }
       const double e00 = c / det, e01 = -b / det, e11 = a / det;   // E^-1
-      if (j < nb) {
-        const bool jb = j == k || j == r;
-        const double rk = e00 * rowk[j] + e01 * rowr[j];   // (E^-1 M_Bj)_k
-        const double rr = e01 * rowk[j] + e11 * rowr[j];   // (E^-1 M_Bj)_r
-        const double ek = j == k ? e00 : e01, er = j == k ? e01 : e11;   // column j of E^-1
-        for (int i = i0; i < nb; i += kRows) {
-          if (i == k || i == r)
-            M[i][j] = jb ? (i == k ? ek : er) : (i == k ? rk : rr);
-          else if (jb)
-            M[i][j] = -(colk[i] * ek + colr[i] * er);
-          else
-            M[i][j] -= colk[i] * rk + colr[i] * rr;
-        }
+      const bool jb = j == k || j == r2;
+      const double sk = e00 * rk[j] + e01 * rr[j];   // (E^-1 M_Bj)_k
+      const double sr = e01 * rk[j] + e11 * rr[j];   // (E^-1 M_Bj)_r
+      const double ek = j == k ? e00 : e01, er = j == k ? e01 : e11;   // column j of E^-1
+#pragma unroll
+      for (int r = 0; r < kPerT; ++r) {
+        const int i = i0 + kGroups * r;
+        const double ci = ck[i], di = cr[i];
+        const double inb = jb ? (i == k ? ek : er) : (i == k ? sk : sr);
+        const double v = (i == k || i == r2) ? inb : (jb ? -(ci * ek + di * er) : m[r] - (ci * sk + di * sr));
+        m[r] = (i < nb && j < nb) ? v : m[r];
       }
       step += 2;
     }
-    __syncthreads();
+    buf ^= 1;   // the next step writes the other buffer; the one after waits behind its barrier
   }
-  if (j < nb)
-    for (int i = i0; i < nb; i += kRows) Pinv[i * nb + j] = M[i][j];
+  if (j < nb) {
+#pragma unroll
+    for (int r = 0; r < kPerT; ++r) {
+      const int i = i0 + kGroups * r;
+      if (i < nb) Pinv[i * nb + j] = m[r];
+    }
+  }
   if (t == 0) {
     if (bad) flag[0] = 1;
     flag[1] += neg;
@@ -1152,7 +1172,7 @@ void gj_choose_block(double* A, long long n, long long k0, int nb, double* V, in
 }
 void gj_pivot(double* A, long long n, long long k0, int nb, double* Pinv, int* flag, const double* scale, double tol,
               const int* sw, const int* gate, hipStream_t s) {
-  hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(256), 0, s, A, n, k0, nb, Pinv, flag, scale, tol, sw, gate);
+  hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(kPivT), 0, s, A, n, k0, nb, Pinv, flag, scale, tol, sw, gate);
 }
 void diag_absmax(const double* A, long long n, double* scale, const int* gate, hipStream_t s) {
   hipLaunchKernelGGL(k_diag_absmax, dim3(1), dim3(kVB), 0, s, A, n, scale, gate);
