@@ -89,6 +89,7 @@ Band<float> DevBand::get<float>() const { return {nout, nin, K, start, v32}; }
 struct Level {
   int N = 0, L = 0;
   long long nn = 0, ndofs = 0, ncells = 0;
+  long long csr_nnz = -1;      // nonzeros of the level's CSR pattern (computed on first request)
   double h = 0;
   Lattice lt{};
   int nwords = 0;
@@ -1322,9 +1323,10 @@ mfh_status mfh_csr_size(mfh_problem* P, int level, long long* n_rows, long long*
   return guarded(P, [&] {
     check_level(P, level);
     need(n_rows && nnz, "n_rows/nnz is NULL");
-    const Level& v = P->lv[level];
+    Level& v = P->lv[level];
+    if (v.csr_nnz < 0) v.csr_nnz = csr_row_ptr(P, v).back();   // O(rows) on the host: once per level
     *n_rows = v.ndofs;
-    *nnz = csr_row_ptr(P, v).back();
+    *nnz = v.csr_nnz;
   });
 }
 
