@@ -620,6 +620,31 @@ def batch_bench(policy=2, steps=20, warmup=3, n=256, solve=True):
         print(f"[bench] batch vmult {name}: {ms_b:.3f} ms ({total / (ms_b * 1e-3):.3e} DoF/s), "
               f"one launch per problem {ms_l:.3f} ms", file=sys.stderr, flush=True)
         del ys
+    # the same batch linearised about random smooth deformations (amplitude
+    # 0.025-0.1, read literally; tangents may be indefinite: vmult only)
+    ul = [torch.as_tensor(W.batch_literal_field(d, coords=P.node_coords_1d()), device="cuda")
+          for d, P in zip(descs, probs)]
+    mjl = B.set_deformation(ul)
+    lit = {"min_J": min(mjl)}
+    for name, xs in (("f64", x64), ("f32", [x.float() for x in x64])):
+        ys = [torch.empty_like(x) for x in xs]
+        for _ in range(warmup):
+            B.tangent_vmult(xs, ys)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            B.tangent_vmult(xs, ys)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_b = e0.elapsed_time(e1) / steps
+        lit[f"vmult_{name}"] = {"batched_ms": ms_b, "batched_dofs_per_s": total / (ms_b * 1e-3)}
+        print(f"[bench] batch vmult {name}, random smooth deformations: {ms_b:.3f} ms "
+              f"({total / (ms_b * 1e-3):.3e} DoF/s), min J {min(mjl):.3f}", file=sys.stderr, flush=True)
+        del ys
+    out["random_smooth_linearisation"] = lit
+    del ul
+    B.set_deformation(us)
     if not solve:
         B.close()
         for P in probs:

@@ -175,6 +175,15 @@ def stretched_field(dim, L, stretch, seed, amp, coords=None):
     return u
 
 
+def batch_literal_field(desc, coords=None):
+    """The batch problem's displacement read literally as a random smooth
+    deformation: ``sine_field`` (kmax 1) of amplitude 1.25 * stretch, i.e.
+    max |u| in [0.025, 0.1] over the batch.  Such states can make the tangent
+    indefinite (no CG solve), which a vmult does not mind."""
+    L = desc["degree"] * desc["n_cells"] + 1
+    return sine_field(3, L, desc["u_seed"] + 1, 1.25 * desc["stretch"], kmax=1, coords=coords)
+
+
 def batch_fields(desc, coords=None):
     """(inclusions, u, x) of one problem of the batch; ``coords`` are the support
     points along an axis of its finest level."""
