@@ -125,6 +125,14 @@ enum {
  * 0 or 1 forces one.  mfh_tile_shape reports the shape a level uses. */
 enum { MFH_TILE_SHAPE_AUTO = -1 };
 
+/* Cells per workgroup of the tangent vmult's pencil kernels (ATOMIC, COLOR,
+ * ELEMENT): two lengths are compiled for every dimension and degree (0: the
+ * length that keeps the most FP64 blocks resident, 1: about half of it, or
+ * for 3-D Q4 the ten cells 256 threads hold); AUTO takes the one the
+ * autotuner measured faster with the level's scatter mode, 0 or 1 forces one.
+ * mfh_cell_block reports the choice of a level. */
+enum { MFH_CELL_BLOCK_AUTO = -1 };
+
 /* Displacement the coarser level operators are linearised about (Sec. 6
  * restricts the fine displacement to every level without saying how):
  * NODAL interpolates the finer level's field at the coarser support points,
@@ -175,11 +183,12 @@ typedef struct {
   const double* mu2;         /* host [n_materials] second-invariant moduli >= 0 (law
                                 MOONEY_RIVLIN; ignored, may be NULL, otherwise)           */
   int tile_shape;            /* MFH_TILE_SHAPE_AUTO, 0 or 1 (TILE scatter only)          */
+  int cell_block;            /* MFH_CELL_BLOCK_AUTO, 0 or 1 (tangent vmult, pencil modes)  */
 } mfh_desc;
 
 /* Fills *desc with the paper's solver settings (degree 4, 2 steps, 30
- * iterations, [0.6, 1.2]), RECOMPUTE, AUTO scatter and tile shape, F32
- * V-cycle, NODAL level fields, DIRECT coarse solve, eigenvalue estimates at
+ * iterations, [0.6, 1.2]), RECOMPUTE, AUTO scatter, tile shape and cell
+ * block, F32 V-cycle, NODAL level fields, DIRECT coarse solve, eigenvalue estimates at
  * every linearisation, the Neo-Hookean law; geometry fields are zeroed and
  * must be set by the caller. */
 void mfh_desc_defaults(mfh_desc* desc);
@@ -352,6 +361,11 @@ mfh_status mfh_scatter_mode(const mfh_problem* problem, int level, int dtype, in
  * whatever the scatter mode; it is used only when the level runs TILE.  Host
  * only.  Errors: INVALID_ARG. */
 mfh_status mfh_tile_shape(const mfh_problem* problem, int level, int dtype, int* shape, int* cells);
+
+/* The cell-block variant (0 or 1) the tangent vmult's pencil kernels use on
+ * `level` in precision dtype into *variant and its cells per workgroup into
+ * *cells.  Host only.  Errors: INVALID_ARG. */
+mfh_status mfh_cell_block(const mfh_problem* problem, int level, int dtype, int* variant, int* cells);
 
 /* Coordinates of the support points along one axis of `level` (all axes
  * are alike): the L = degree * N + 1 lattice positions in [0, 1], the

@@ -1,10 +1,12 @@
 """Autotuner of the tangent vmult's launch shapes (run on the GPU).
 
-Scatter mode and tile shape: for every (dim, degree, precision, qp policy,
-size class) it times one whole tangent vmult (output fill or node sums
-included) with each scatter mode on a representative mesh, the TILE mode
-with each of its two compiled tile shapes, and records the fastest mode and
-the faster tile shape (used whenever TILE runs).  Batch
+Scatter mode, tile shape and cells per block: for every (dim, degree,
+precision, qp policy, size class) it times one whole tangent vmult (output
+fill or node sums included) on a representative mesh with each scatter mode,
+the TILE mode with each of its two compiled tile shapes and the pencil-kernel
+modes (ATOMIC, ELEMENT, COLOR) with each of their two compiled cell-block
+lengths, and records the fastest mode with its cell-block length, and the
+faster tile shape (used whenever TILE runs).  Batch
 launch: on the 256-problem batch of independent 3-D problems (degrees 1 to
 3) it times the batched vmult as one launch per degree bin and as one
 persistent launch over every degree, in both precisions, and records the
@@ -84,11 +86,14 @@ def measure(dims=(2, 3), degrees=(1, 2, 3, 4), quick=False, log=print, policies=
                     if policies is not None and pname not in policies:
                         continue
                     times = {dt: {} for dt in DTYPES}
-                    modes = ["atomic", "tile0", "tile1", "element"] + (["color"] if cls == "large" else [])
+                    pencil = ["atomic", "element"] + (["color"] if cls == "large" else [])
+                    modes = [m + b for m in pencil for b in ("", "/b1")] + ["tile0", "tile1"]
                     for mname in modes:
                         tile = int(mname[4]) if mname.startswith("tile") else -1
+                        cb = 1 if mname.endswith("/b1") else 0
+                        base = "tile" if tile >= 0 else mname.split("/")[0]
                         P = Problem(dim, N, degree, mu=tuple(mu), lam=tuple(lam), inclusions=incl, qp_policy=pol,
-                                    scatter=MODES[mname[:4] if tile >= 0 else mname], tile_shape=tile)
+                                    scatter=MODES[base], tile_shape=tile, cell_block=cb)
                         L = degree * N + 1
                         u = W.sine_field(dim, L, 4, 0.02, kmax=1, coords=P.node_coords_1d())
                         P.set_deformation(torch.as_tensor(u, device="cuda"))
@@ -100,9 +105,11 @@ def measure(dims=(2, 3), degrees=(1, 2, 3, 4), quick=False, log=print, policies=
                     for dt in DTYPES:
                         best = min(times[dt], key=times[dt].get)
                         tile = 0 if times[dt]["tile0"] <= times[dt]["tile1"] else 1
+                        scatter = "tile" if best.startswith("tile") else best.split("/")[0]
                         entries.append(dict(dim=dim, degree=degree, dtype=dt, policy=pname, size_class=cls,
-                                            cells=N ** dim, scatter="tile" if best.startswith("tile") else best,
-                                            tile=tile, us={k: round(v, 2) for k, v in times[dt].items()}))
+                                            cells=N ** dim, scatter=scatter, tile=tile,
+                                            cell_block=1 if best.endswith("/b1") else 0,
+                                            us={k: round(v, 2) for k, v in times[dt].items()}))
                         log(f"[autotune] d{dim} p{degree} {cls:6s} N={N:3d} {pname:9s} {dt}: "
                             + " ".join(f"{k}={v:7.1f}" for k, v in times[dt].items()) + f" -> {best}")
     return entries
@@ -192,9 +199,10 @@ def emit_header(table, path=HEADER_PATH):
     rows = []
     for e in table["entries"]:
         rows.append(f"    {{{e['dim']}, {e['degree']}, {DTYPES[e['dtype']]}, {POLICIES[e['policy']]}, "
-                    f"{CLASSES.index(e['size_class'])}, {MODES[e['scatter']]}, {e.get('tile', 0)}}},")
+                    f"{CLASSES.index(e['size_class'])}, {MODES[e['scatter']]}, {e.get('tile', 0)}, "
+                    f"{e.get('cell_block', 0)}}},")
     if not rows:
-        rows = ["    {0, 0, 0, 0, 0, 0, 0},   // no measurements: every lookup falls back to ATOMIC, tile shape 0"]
+        rows = ["    {0, 0, 0, 0, 0, 0, 0, 0},   // no measurements: every lookup falls back to ATOMIC, shapes 0"]
     batch = table.get("batch_launch")
     batch_fused = "true" if batch and batch["launch"] == "fused" else "false"
     batch_note = (" (" + ", ".join(f"{dt}: " + " / ".join(f"{k} {v} ms" for k, v in ms.items())
@@ -202,14 +210,15 @@ def emit_header(table, path=HEADER_PATH):
     text = f"""// Generated by paper_1904_13131_amd/autotune.py from tuning/gfx950.json
 // ({table.get('note', '')}).  Do not edit: rerun the autotuner.
 // Scatter mode measured fastest for one whole tangent vmult, per (dim, degree,
-// precision 0 = FP64 / 1 = FP32, qp policy, size class of the level's cells),
-// and the faster of the TILE mode's two tile shapes.
+// precision 0 = FP64 / 1 = FP32, qp policy, size class of the level's cells)
+// with the cell-block variant of the pencil kernels it was fastest with, and
+// the faster of the TILE mode's two tile shapes.
 #pragma once
 
 namespace mfh {{
 
 struct TunedScatter {{
-  signed char dim, degree, dtype, policy, size_class, scatter, tile;
+  signed char dim, degree, dtype, policy, size_class, scatter, tile, cell_block;
 }};
 
 constexpr TunedScatter kTunedScatter[] = {{
@@ -241,6 +250,12 @@ inline int tuned_scatter(int dim, int degree, int dtype, int policy, long long c
 inline int tuned_tile(int dim, int degree, int dtype, int policy, long long cells) {{
   const TunedScatter* e = tuned_entry(dim, degree, dtype, policy, cells);
   return e ? e->tile : 0;
+}}
+
+// Cell-block variant of the pencil kernels for a level (0 when the table has no entry).
+inline int tuned_cell_block(int dim, int degree, int dtype, int policy, long long cells) {{
+  const TunedScatter* e = tuned_entry(dim, degree, dtype, policy, cells);
+  return e ? e->cell_block : 0;
 }}
 
 }}  // namespace mfh

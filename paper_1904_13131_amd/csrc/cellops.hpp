@@ -66,11 +66,25 @@ struct Geo {
   static constexpr int NARR = DIM == 3 ? 3 : 2;        // LDS arrays per component
 };
 
+// Cells per block of the tangent vmult's pencil kernels, two variants that
+// the tuned table chooses between per level: V = 0 the length above; V = 1 a
+// second one (about half, so two-wave blocks; 3-D Q4 the full 10 cells that
+// 256 threads hold).  The element scatter's node-sum kernel must be launched
+// with the same variant, as it locates the cell-block ends.
+template <int DIM, int N1, int V>
+struct CellBlock {
+  static constexpr int NP = Geo<DIM, N1>::NP;
+  static constexpr int value = V == 0 ? Geo<DIM, N1>::CPB : DIM == 3 && N1 == 5 ? 10 : DIM == 3 && N1 == 3 ? 14
+                                                                                               : kBlock / NP / 2;
+  static constexpr int threads = (value * NP + 63) / 64 * 64;
+  static_assert(value * NP <= kBlock, "a cell block fits the block's threads");
+};
+
 // LDS words (of T) of the tangent kernels' block: the sweeps' DIM * NARR
 // arrays of NV points per cell, also used for the element-buffer handover.
-template <int DIM, int N1, typename T>
+template <int DIM, int N1, typename T, int CPB = Geo<DIM, N1>::CPB>
 struct TangentLdsSize {
-  static constexpr int value = DIM * Geo<DIM, N1>::NARR * Geo<DIM, N1>::NV * Geo<DIM, N1>::CPB;
+  static constexpr int value = DIM * Geo<DIM, N1>::NARR * Geo<DIM, N1>::NV * CPB;
 };
 
 // Element buffer of the ELEMENT scatter for a level of `cells` cells (T words,
@@ -794,17 +808,17 @@ __device__ __forceinline__ int material_of(const CellArgs<T>& a, long long e, in
 // Tangent vmult body for cell block `blk` of one level: y += K x over the
 // block's cells (y pre-filled).  Shared by the single-problem kernel and the
 // batched work-list kernel.
-template <int DIM, int P, typename T, int POL, bool O32>
+template <int DIM, int P, typename T, int POL, bool O32, int CPB = Geo<DIM, P + 1>::CPB>
 __device__ __forceinline__ void tangent_block(const CellArgs<T>& a, const T* __restrict__ x, T* __restrict__ y,
                                               long long blk, T* lds) {
   constexpr int N1 = P + 1;
   using G = Geo<DIM, N1>;
-  using SF = SumFact<DIM, N1, T>;
+  using SF = SumFact<DIM, N1, T, CPB>;
   constexpr int NW = CacheWords<DIM, POL>::value;
 
   const int t = threadIdx.x;
-  const int cl = t % G::CPB, pen = t / G::CPB;
-  const long long lin = blk * G::CPB + cl;
+  const int cl = t % CPB, pen = t / CPB;
+  const long long lin = blk * CPB + cl;
   const bool act = pen < G::NP && lin < a.nlaunch;
   CellPos<DIM, N1> cp;
   cp.init(a, act ? lin : 0, act ? pen : 0);
@@ -891,13 +905,13 @@ __device__ __forceinline__ void tangent_block(const CellArgs<T>& a, const T* __r
     const int line = DIM == 3 ? p0 + N1 * p1 : p0;
     if (act) {
 #pragma unroll
-      for (int c = 0; c < DIM; ++c) lds[(c * G::NP + line) * G::CPB + cl] = out[c][N1 - 1];
+      for (int c = 0; c < DIM; ++c) lds[(c * G::NP + line) * CPB + cl] = out[c][N1 - 1];
     }
     __syncthreads();
     if (act) {
       if (cl > 0 && !cp.first_i) {
 #pragma unroll
-        for (int c = 0; c < DIM; ++c) out[c][0] += lds[(c * G::NP + line) * G::CPB + cl - 1];
+        for (int c = 0; c < DIM; ++c) out[c][0] += lds[(c * G::NP + line) * CPB + cl - 1];
       }
       const long long lane_e = (long long)(P * line) * a.ncells + cp.e;
       const unsigned lane_eb = O32 ? (unsigned)lane_e * (unsigned)sizeof(T) : 0u;
@@ -906,7 +920,7 @@ __device__ __forceinline__ void tangent_block(const CellArgs<T>& a, const T* __r
 #pragma unroll
         for (int k = 0; k < P; ++k)
           lane_store<O32>(a.elem + ((long long)c * EL::NX + k) * a.ncells, lane_e, lane_eb, out[c][k]);
-      if (cl + 1 == G::CPB || cp.last_i || lin + 1 >= a.nlaunch) {
+      if (cl + 1 == CPB || cp.last_i || lin + 1 >= a.nlaunch) {
         const long long lane_o = (long long)line * a.ncells + cp.e;
         const unsigned lane_ob = O32 ? (unsigned)lane_o * (unsigned)sizeof(T) : 0u;
 #pragma unroll
@@ -920,7 +934,7 @@ __device__ __forceinline__ void tangent_block(const CellArgs<T>& a, const T* __r
     // over and let one lane add the sum, saving a third of the atomics.
     const int lane = t & 63;
     const bool from_prev = act && cl > 0 && lane > 0 && !cp.first_i;
-    const bool to_next = act && cl + 1 < G::CPB && lane < 63 && lin + 1 < a.nlaunch && !cp.last_i;
+    const bool to_next = act && cl + 1 < CPB && lane < 63 && lin + 1 < a.nlaunch && !cp.last_i;
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
       const T v = __shfl_up(out[c][N1 - 1], 1);
@@ -943,11 +957,10 @@ __device__ __forceinline__ void tangent_block(const CellArgs<T>& a, const T* __r
 // plane and all its components (the loads are in flight together);
 // blockIdx.y is the plane k.  j = t / L comes from a multiply-high by
 // magic = ceil(2^32 / L), exact for t < L^2 while L^3 < 2^32.
-template <int DIM, int P, typename T, typename Out>
+template <int DIM, int P, typename T, typename Out, int CPB = Geo<DIM, P + 1>::CPB>
 __device__ __forceinline__ void elem_gather_node(const CellArgs<T>& a, const T* __restrict__ x, const Out& out,
                                                  int t, int k, unsigned magic) {
   constexpr int N1 = P + 1;
-  constexpr int CPB = Geo<DIM, N1>::CPB;
   using EL = ElemLayout<DIM, N1>;
   const int N = a.N, L = a.L;
   if (t >= L * L) return;
@@ -1014,18 +1027,19 @@ __device__ __forceinline__ void elem_gather_node(const CellArgs<T>& a, const T* 
   }
 }
 
-template <int DIM, int P, typename T>
+template <int DIM, int P, typename T, int CPB>
 __global__ void __launch_bounds__(kBlock) k_elem_gather(CellArgs<T> arg, unsigned magic) {
   const CellArgs<T>& a = kernel_args(arg);
-  elem_gather_node<DIM, P, T>(a, a.x, StoreOut<T>{a.y}, blockIdx.x * kBlock + threadIdx.x, blockIdx.y, magic);
+  elem_gather_node<DIM, P, T, StoreOut<T>, CPB>(a, a.x, StoreOut<T>{a.y}, blockIdx.x * kBlock + threadIdx.x,
+                                                 blockIdx.y, magic);
 }
 
 // Node sums fused with one Chebyshev step (the smoother's vmult on a level
 // with the ELEMENT scatter).
-template <int DIM, int P, typename T>
+template <int DIM, int P, typename T, int CPB>
 __global__ void __launch_bounds__(kBlock) k_elem_gather_cheb(CellArgs<T> arg, unsigned magic, ChebOut<T> out) {
   const CellArgs<T>& a = kernel_args(arg);
-  elem_gather_node<DIM, P, T>(a, a.x, out, blockIdx.x * kBlock + threadIdx.x, blockIdx.y, magic);
+  elem_gather_node<DIM, P, T, ChebOut<T>, CPB>(a, a.x, out, blockIdx.x * kBlock + threadIdx.x, blockIdx.y, magic);
 }
 
 // Batched second pass: one workgroup per item (problem, plane k, block of the
@@ -1048,12 +1062,12 @@ __global__ void __launch_bounds__(kBlock) k_elem_gather_batch(const CellArgs<T>*
 }
 
 // Tangent vmult: y += K x over the cells of this launch (y pre-filled).
-template <int DIM, int P, typename T, int POL, bool O32>
+template <int DIM, int P, typename T, int POL, bool O32, int CPB>
 __global__ void __launch_bounds__(kBlock) k_tangent(CellArgs<T> arg) {
-  __shared__ T lds[TangentLdsSize<DIM, P + 1, T>::value];
+  __shared__ T lds[TangentLdsSize<DIM, P + 1, T, CPB>::value];
   const CellArgs<T>& a = kernel_args(arg);
   const long long blk = a.color < 0 ? xcd_block(blockIdx.x, gridDim.x) : (long long)blockIdx.x;
-  tangent_block<DIM, P, T, POL, O32>(a, a.x, a.y, blk, lds);
+  tangent_block<DIM, P, T, POL, O32, CPB>(a, a.x, a.y, blk, lds);
 }
 
 // Batched tangent vmult over many independent problems of one degree: one

@@ -10,9 +10,9 @@ struct TileShape {
 };
 
 struct OpFns {
-  // tangent vmult per policy (0 R, 1 CF, 2 C2, 3 C4)
-  void (*tangent_d[4])(const CellArgs<double>&, unsigned grid, hipStream_t);
-  void (*tangent_f[4])(const CellArgs<float>&, unsigned grid, hipStream_t);
+  // tangent vmult per cell-block variant and policy (0 R, 1 CF, 2 C2, 3 C4); grid = ceil(cells / cpb[variant])
+  void (*tangent_d[2][4])(const CellArgs<double>&, unsigned grid, hipStream_t);
+  void (*tangent_f[2][4])(const CellArgs<float>&, unsigned grid, hipStream_t);
   void (*residual)(const CellArgs<double>&, unsigned grid, hipStream_t);
   // quadrature data (min J and the policy cache in double / float)
   void (*qpdata_d[4])(const CellArgs<double>&, double* cache, unsigned grid, hipStream_t);
@@ -29,22 +29,22 @@ struct OpFns {
                              double* const* ys, unsigned n_items, long long max_cells, hipStream_t);
   void (*tangent_batch_f[4])(const CellArgs<float>* args, const int2* items, const float* const* xs,
                              float* const* ys, unsigned n_items, long long max_cells, hipStream_t);
-  // second pass of the ELEMENT scatter
-  void (*elem_gather_d)(const CellArgs<double>&, hipStream_t);
-  void (*elem_gather_f)(const CellArgs<float>&, hipStream_t);
+  // second pass of the ELEMENT scatter, per cell-block variant of the cell kernel that wrote the buffer
+  void (*elem_gather_d[2])(const CellArgs<double>&, hipStream_t);
+  void (*elem_gather_f[2])(const CellArgs<float>&, hipStream_t);
   void (*elem_gather_batch_d)(const CellArgs<double>* args, const GatherItem* items, const double* const* xs,
                               double* const* ys, unsigned n_items, hipStream_t);
   void (*elem_gather_batch_f)(const CellArgs<float>* args, const GatherItem* items, const float* const* xs,
                               float* const* ys, unsigned n_items, hipStream_t);
   // node sums fused with one Chebyshev step (ELEMENT levels of the smoother)
-  void (*elem_gather_cheb_d)(const CellArgs<double>&, const ChebOut<double>&, hipStream_t);
-  void (*elem_gather_cheb_f)(const CellArgs<float>&, const ChebOut<float>&, hipStream_t);
+  void (*elem_gather_cheb_d[2])(const CellArgs<double>&, const ChebOut<double>&, hipStream_t);
+  void (*elem_gather_cheb_f[2])(const CellArgs<float>&, const ChebOut<float>&, hipStream_t);
   void (*coarse_assemble)(const CellArgs<double>&, const int* fmap, long long nf, double* K,
                           unsigned grid, hipStream_t);
   // element tangents added into the CSR values of K_c (pattern of the lattice)
   void (*csr_assemble)(const CellArgs<double>&, const long long* row_ptr, double* val, unsigned grid,
                        hipStream_t);
-  int cpb;        // cells per block of the pencil kernels
+  int cpb[2];     // cells per block of the tangent vmult's variants ([0]: the other pencil kernels' length too)
   int cache_words[4];
 };
 

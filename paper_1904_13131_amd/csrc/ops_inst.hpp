@@ -81,12 +81,13 @@ struct OpInst {
   static bool off32(long long cells) {
     return (long long)Geo<DIM, P + 1>::NV * cells * 2 * (long long)sizeof(T) < (1LL << 32);
   }
-  template <typename T, int POL>
+  template <typename T, int POL, int V>
   static void tangent(const CellArgs<T>& a, unsigned grid, hipStream_t s) {
+    using CB = CellBlock<DIM, P + 1, V>;
     if (off32<T>(a.ncells))
-      hipLaunchKernelGGL((k_tangent<DIM, P, T, POL, true>), dim3(grid), dim3(kBlock), 0, s, a);
+      hipLaunchKernelGGL((k_tangent<DIM, P, T, POL, true, CB::value>), dim3(grid), dim3(CB::threads), 0, s, a);
     else
-      hipLaunchKernelGGL((k_tangent<DIM, P, T, POL, false>), dim3(grid), dim3(kBlock), 0, s, a);
+      hipLaunchKernelGGL((k_tangent<DIM, P, T, POL, false, CB::value>), dim3(grid), dim3(CB::threads), 0, s, a);
   }
   template <typename T, int POL>
   static void tangent_batch(const CellArgs<T>* args, const int2* items, const T* const* xs, T* const* ys,
@@ -103,19 +104,21 @@ struct OpInst {
                                 unsigned n_items, hipStream_t s) {
     hipLaunchKernelGGL((k_elem_gather_batch<DIM, P, T>), dim3(n_items), dim3(kBlock), 0, s, args, items, xs, ys);
   }
-  template <typename T>
+  template <typename T, int V>
   static void elem_gather(const CellArgs<T>& a, hipStream_t s) {
     const unsigned plane = (unsigned)a.L * (unsigned)a.L;
     const unsigned magic = (unsigned)((((unsigned long long)1 << 32) + (unsigned)a.L - 1) / (unsigned)a.L);
     const dim3 grid((plane + kBlock - 1) / kBlock, DIM == 3 ? a.L : 1, 1);
-    hipLaunchKernelGGL((k_elem_gather<DIM, P, T>), grid, dim3(kBlock), 0, s, a, magic);
+    hipLaunchKernelGGL((k_elem_gather<DIM, P, T, CellBlock<DIM, P + 1, V>::value>), grid, dim3(kBlock), 0, s, a,
+                       magic);
   }
-  template <typename T>
+  template <typename T, int V>
   static void elem_gather_cheb(const CellArgs<T>& a, const ChebOut<T>& out, hipStream_t s) {
     const unsigned plane = (unsigned)a.L * (unsigned)a.L;
     const unsigned magic = (unsigned)((((unsigned long long)1 << 32) + (unsigned)a.L - 1) / (unsigned)a.L);
     const dim3 grid((plane + kBlock - 1) / kBlock, DIM == 3 ? a.L : 1, 1);
-    hipLaunchKernelGGL((k_elem_gather_cheb<DIM, P, T>), grid, dim3(kBlock), 0, s, a, magic, out);
+    hipLaunchKernelGGL((k_elem_gather_cheb<DIM, P, T, CellBlock<DIM, P + 1, V>::value>), grid, dim3(kBlock), 0, s,
+                       a, magic, out);
   }
   static void residual(const CellArgs<double>& a, unsigned grid, hipStream_t s) {
     hipLaunchKernelGGL((k_residual<DIM, P>), dim3(grid), dim3(kBlock), 0, s, a);
@@ -155,8 +158,14 @@ struct OpInst {
   }
   static const OpFns* table() {
     static const OpFns t = {
-        {&tangent<double, POL_R>, &tangent<double, POL_CF>, &tangent<double, POL_C2>, &tangent<double, POL_C4>},
-        {&tangent<float, POL_R>, &tangent<float, POL_CF>, &tangent<float, POL_C2>, &tangent<float, POL_C4>},
+        {{&tangent<double, POL_R, 0>, &tangent<double, POL_CF, 0>, &tangent<double, POL_C2, 0>,
+          &tangent<double, POL_C4, 0>},
+         {&tangent<double, POL_R, 1>, &tangent<double, POL_CF, 1>, &tangent<double, POL_C2, 1>,
+          &tangent<double, POL_C4, 1>}},
+        {{&tangent<float, POL_R, 0>, &tangent<float, POL_CF, 0>, &tangent<float, POL_C2, 0>,
+          &tangent<float, POL_C4, 0>},
+         {&tangent<float, POL_R, 1>, &tangent<float, POL_CF, 1>, &tangent<float, POL_C2, 1>,
+          &tangent<float, POL_C4, 1>}},
         &residual,
         {&qpdata<double, POL_R>, &qpdata<double, POL_CF>, &qpdata<double, POL_C2>, &qpdata<double, POL_C4>},
         {&qpdata<float, POL_R>, &qpdata<float, POL_CF>, &qpdata<float, POL_C2>, &qpdata<float, POL_C4>},
@@ -175,15 +184,15 @@ struct OpInst {
          &tangent_batch<double, POL_C4>},
         {&tangent_batch<float, POL_R>, &tangent_batch<float, POL_CF>, &tangent_batch<float, POL_C2>,
          &tangent_batch<float, POL_C4>},
-        &elem_gather<double>,
-        &elem_gather<float>,
+        {&elem_gather<double, 0>, &elem_gather<double, 1>},
+        {&elem_gather<float, 0>, &elem_gather<float, 1>},
         &elem_gather_batch<double>,
         &elem_gather_batch<float>,
-        &elem_gather_cheb<double>,
-        &elem_gather_cheb<float>,
+        {&elem_gather_cheb<double, 0>, &elem_gather_cheb<double, 1>},
+        {&elem_gather_cheb<float, 0>, &elem_gather_cheb<float, 1>},
         &coarse_assemble,
         &csr_assemble,
-        Geo<DIM, P + 1>::CPB,
+        {CellBlock<DIM, P + 1, 0>::value, CellBlock<DIM, P + 1, 1>::value},
         {CacheWords<DIM, POL_R>::value, CacheWords<DIM, POL_CF>::value, CacheWords<DIM, POL_C2>::value,
          CacheWords<DIM, POL_C4>::value},
     };

@@ -215,6 +215,7 @@ void validate(const mfh_desc* d) {
   }
   if (d->scatter < MFH_SCATTER_AUTO || d->scatter > MFH_SCATTER_ELEMENT) bad("bad scatter mode");
   if (d->tile_shape < MFH_TILE_SHAPE_AUTO || d->tile_shape > 1) bad("bad tile shape");
+  if (d->cell_block < MFH_CELL_BLOCK_AUTO || d->cell_block > 1) bad("bad cell block");
   if (d->vcycle_dtype != MFH_F32 && d->vcycle_dtype != MFH_F64) bad("bad vcycle_dtype");
   if (d->cheb_degree < 1 || d->cheb_degree > 16) bad("cheb_degree must be 1..16");
   if (d->n_smooth < 1 || d->n_smooth > 8) bad("n_smooth must be 1..8");
@@ -337,6 +338,13 @@ int tile_shape(const mfh_problem* P, const Level& v, int t) {
   return tuned_tile(P->d.dim, P->d.degree, t, P->d.qp_policy, v.ncells);
 }
 
+// Cell-block variant of the tangent vmult's pencil kernels on a level: the
+// descriptor's, or with MFH_CELL_BLOCK_AUTO the tuned one.
+int cell_block(const mfh_problem* P, const Level& v, int t) {
+  if (P->d.cell_block != MFH_CELL_BLOCK_AUTO) return P->d.cell_block;
+  return tuned_cell_block(P->d.dim, P->d.degree, t, P->d.qp_policy, v.ncells);
+}
+
 size_t layout(mfh_problem* P, char* base) {
   const mfh_desc& d = P->d;
   Bump b;
@@ -366,7 +374,7 @@ size_t layout(mfh_problem* P, char* base) {
   const Level& top = P->lv.back();
   P->incl_dev = b.take<double>((size_t)std::max(1, d.n_inclusions) * (d.dim + 2));
   P->sc = b.take<double>(SC_COUNT);
-  P->part = b.take<double>((size_t)std::max<long long>(kRedBlocks, top.ncells / P->ops->cpb + 16));
+  P->part = b.take<double>((size_t)std::max<long long>(kRedBlocks, top.ncells / P->ops->cpb[0] + 16));
   P->minj = b.take<double>(P->lv.size());
   P->hist = b.take<double>(2 * (size_t)d.eig_iters * P->lv.size() + 2);
   // transfer intermediates: dim * Lf^(dim-1) * Lc entries of up to 8 bytes
@@ -473,15 +481,18 @@ template <>
 struct Sel<double> {
   static const double* u(const Level& v) { return v.u64; }
   static const double* cache(const Level& v) { return v.cache64; }
-  static void run(const OpFns* o, int pol, const CellArgs<double>& a, unsigned g, hipStream_t s) {
-    o->tangent_d[pol](a, g, s);
+  static void run(const OpFns* o, int cb, int pol, const CellArgs<double>& a, unsigned g, hipStream_t s) {
+    o->tangent_d[cb][pol](a, g, s);
   }
   static void run_tile(const OpFns* o, int shape, int pol, const CellArgs<double>& a, unsigned g, hipStream_t s) {
     o->tangent_tile_d[shape][pol](a, g, s);
   }
-  static void elem_gather(const OpFns* o, const CellArgs<double>& a, hipStream_t s) { o->elem_gather_d(a, s); }
-  static void elem_gather_cheb(const OpFns* o, const CellArgs<double>& a, const ChebOut<double>& c, hipStream_t s) {
-    o->elem_gather_cheb_d(a, c, s);
+  static void elem_gather(const OpFns* o, int cb, const CellArgs<double>& a, hipStream_t s) {
+    o->elem_gather_d[cb](a, s);
+  }
+  static void elem_gather_cheb(const OpFns* o, int cb, const CellArgs<double>& a, const ChebOut<double>& c,
+                               hipStream_t s) {
+    o->elem_gather_cheb_d[cb](a, c, s);
   }
   static Band<double> band(const DevBand& b) { return b.get<double>(); }
 };
@@ -489,15 +500,18 @@ template <>
 struct Sel<float> {
   static const float* u(const Level& v) { return v.u32; }
   static const float* cache(const Level& v) { return v.cache32; }
-  static void run(const OpFns* o, int pol, const CellArgs<float>& a, unsigned g, hipStream_t s) {
-    o->tangent_f[pol](a, g, s);
+  static void run(const OpFns* o, int cb, int pol, const CellArgs<float>& a, unsigned g, hipStream_t s) {
+    o->tangent_f[cb][pol](a, g, s);
   }
   static void run_tile(const OpFns* o, int shape, int pol, const CellArgs<float>& a, unsigned g, hipStream_t s) {
     o->tangent_tile_f[shape][pol](a, g, s);
   }
-  static void elem_gather(const OpFns* o, const CellArgs<float>& a, hipStream_t s) { o->elem_gather_f(a, s); }
-  static void elem_gather_cheb(const OpFns* o, const CellArgs<float>& a, const ChebOut<float>& c, hipStream_t s) {
-    o->elem_gather_cheb_f(a, c, s);
+  static void elem_gather(const OpFns* o, int cb, const CellArgs<float>& a, hipStream_t s) {
+    o->elem_gather_f[cb](a, s);
+  }
+  static void elem_gather_cheb(const OpFns* o, int cb, const CellArgs<float>& a, const ChebOut<float>& c,
+                               hipStream_t s) {
+    o->elem_gather_cheb_f[cb](a, c, s);
   }
   static Band<float> band(const DevBand& b) { return b.get<float>(); }
 };
@@ -527,30 +541,31 @@ void vmult(mfh_problem* P, int l, const T* x, T* y, int mask_in = 1) {
   const Level& v = P->lv[l];
   CellArgs<T> a = cell_args<T>(P, v, Sel<T>::u(v), Sel<T>::cache(v), x, y);
   a.mask_in = mask_in;
-  const int cpb = P->ops->cpb;
-  const int mode = scatter_mode(P, v, std::is_same<T, double>::value ? 0 : 1);
+  const int ti = std::is_same<T, double>::value ? 0 : 1;
+  const int cb = cell_block(P, v, ti);
+  const int cpb = P->ops->cpb[cb];
+  const int mode = scatter_mode(P, v, ti);
   if (mode == MFH_SCATTER_ELEMENT) {   // cell kernel into the element buffer, then the node sums
     a.elem = reinterpret_cast<T*>(P->elem);
     timer_mark(P);
-    Sel<T>::run(P->ops, P->d.qp_policy, a, (unsigned)((v.ncells + cpb - 1) / cpb), P->stream);
-    Sel<T>::elem_gather(P->ops, a, P->stream);
+    Sel<T>::run(P->ops, cb, P->d.qp_policy, a, (unsigned)((v.ncells + cpb - 1) / cpb), P->stream);
+    Sel<T>::elem_gather(P->ops, cb, a, P->stream);
     timer_mark(P);
     return;
   }
   fill_dirichlet<T>(y, mask_in ? x : nullptr, v.ndofs, v.lt, P->stream);
   timer_mark(P);
   if (mode == MFH_SCATTER_TILE) {
-    const int ti = std::is_same<T, double>::value ? 0 : 1;
     const int ts = tile_shape(P, v, ti);
     Sel<T>::run_tile(P->ops, ts, P->d.qp_policy, a, (unsigned)P->ops->tiles[ti][ts](v.N), P->stream);
   } else if (mode == MFH_SCATTER_ATOMIC) {
-    Sel<T>::run(P->ops, P->d.qp_policy, a, (unsigned)((v.ncells + cpb - 1) / cpb), P->stream);
+    Sel<T>::run(P->ops, cb, P->d.qp_policy, a, (unsigned)((v.ncells + cpb - 1) / cpb), P->stream);
   } else {
     for (int color = 0; color < (1 << P->d.dim); ++color) {
       a.color = color;
       a.nlaunch = color_count(v.N, P->d.dim, color);
       if (!a.nlaunch) continue;
-      Sel<T>::run(P->ops, P->d.qp_policy, a, (unsigned)((a.nlaunch + cpb - 1) / cpb), P->stream);
+      Sel<T>::run(P->ops, cb, P->d.qp_policy, a, (unsigned)((a.nlaunch + cpb - 1) / cpb), P->stream);
     }
   }
   timer_mark(P);
@@ -568,10 +583,11 @@ bool vmult_cheb(mfh_problem* P, int l, const T* f, const T* dinv, T* d, T* x, T 
   CellArgs<T> a = cell_args<T>(P, v, Sel<T>::u(v), Sel<T>::cache(v), x, nullptr);
   a.mask_in = 1;
   a.elem = reinterpret_cast<T*>(P->elem);
-  const int cpb = P->ops->cpb;
+  const int cb = cell_block(P, v, std::is_same<T, double>::value ? 0 : 1);
+  const int cpb = P->ops->cpb[cb];
   timer_mark(P);
-  Sel<T>::run(P->ops, P->d.qp_policy, a, (unsigned)((v.ncells + cpb - 1) / cpb), P->stream);
-  Sel<T>::elem_gather_cheb(P->ops, a, ChebOut<T>{f, dinv, d, x, cd, cr}, P->stream);
+  Sel<T>::run(P->ops, cb, P->d.qp_policy, a, (unsigned)((v.ncells + cpb - 1) / cpb), P->stream);
+  Sel<T>::elem_gather_cheb(P->ops, cb, a, ChebOut<T>{f, dinv, d, x, cd, cr}, P->stream);
   timer_mark(P);
   return true;
 }
@@ -580,7 +596,7 @@ void residual(mfh_problem* P, const double* u, double* r) {
   const Level& v = P->lv.back();
   fill_dirichlet<double>(r, nullptr, v.ndofs, v.lt, P->stream);
   CellArgs<double> a = cell_args<double>(P, v, u, nullptr, nullptr, r);
-  const int cpb = P->ops->cpb;
+  const int cpb = P->ops->cpb[0];
   if (P->d.scatter != MFH_SCATTER_COLOR) {
     P->ops->residual(a, (unsigned)((v.ncells + cpb - 1) / cpb), P->stream);
   } else {
@@ -868,7 +884,7 @@ void setdef_enqueue(mfh_problem* P, const double* u) {
   HIPCHECK(hipMemcpyAsync(top.u64, u, sizeof(double) * top.ndofs, hipMemcpyDeviceToDevice, s));
   for (int l = nl - 1; l >= 1; --l) interpolate_down(P, l);
   const int pol = d.qp_policy;
-  const int cpb = P->ops->cpb;
+  const int cpb = P->ops->cpb[0];
   for (int l = 0; l < nl; ++l) {
     Level& v = P->lv[l];
     cast<double, float>(v.u64, v.u32, v.ndofs, s);
@@ -1216,6 +1232,7 @@ void mfh_desc_defaults(mfh_desc* d) {
   d->eig_refresh = 1;
   d->law = MFH_LAW_NEO_HOOKE;
   d->tile_shape = MFH_TILE_SHAPE_AUTO;
+  d->cell_block = MFH_CELL_BLOCK_AUTO;
 }
 
 mfh_status mfh_workspace_size(const mfh_desc* desc, size_t* bytes) {
@@ -1629,6 +1646,17 @@ mfh_status mfh_tile_shape(const mfh_problem* P, int level, int dtype, int* shape
   });
 }
 
+mfh_status mfh_cell_block(const mfh_problem* P, int level, int dtype, int* variant, int* cells) {
+  if (!P) return MFH_ERR_INVALID_ARG;
+  return guarded(const_cast<mfh_problem*>(P), [&] {
+    check_level(P, level);
+    need(variant != nullptr && cells != nullptr, "NULL argument");
+    need(dtype == MFH_F64 || dtype == MFH_F32, "dtype must be MFH_F64 or MFH_F32");
+    *variant = cell_block(P, P->lv[level], dtype == MFH_F64 ? 0 : 1);
+    *cells = P->ops->cpb[*variant];
+  });
+}
+
 mfh_status mfh_node_coords_1d(mfh_problem* P, int level, double* x) {
   if (!P) return MFH_ERR_INVALID_ARG;
   return guarded(P, [&] {
@@ -1954,7 +1982,7 @@ size_t batch_layout(mfh_batch* B, char* base) {
     bin.n_g[0] = bin.n_g[1] = 0;
     for (int i : bin.ids) {
       const mfh_problem* P = B->probs[i];
-      bin.n_items += (P->lv.back().ncells + P->ops->cpb - 1) / P->ops->cpb;
+      bin.n_items += (P->lv.back().ncells + P->ops->cpb[0] - 1) / P->ops->cpb[0];
       bin.max_cells = std::max(bin.max_cells, P->lv.back().ncells);
       for (int t = 0; t < 2; ++t)
         if (batch_elem(P, t)) bin.n_g[t] += gather_blocks(P);
@@ -1977,7 +2005,7 @@ size_t batch_layout(mfh_batch* B, char* base) {
   B->n_fitems = 0;
   for (const mfh_problem* P : B->probs) {
     B->fused_ok = B->fused_ok && P->d.dim == 3 && P->d.degree <= 3;
-    B->n_fitems += (P->lv.back().ncells + P->ops->cpb - 1) / P->ops->cpb;
+    B->n_fitems += (P->lv.back().ncells + P->ops->cpb[0] - 1) / P->ops->cpb[0];
   }
   const size_t n = B->probs.size();
   B->fa64 = b.take<CellArgs<double>>(n);
@@ -2187,7 +2215,7 @@ mfh_status mfh_batch_create(int n, mfh_problem* const* probs, void* ws, size_t b
         a32[k] = cell_args<float>(P, v, v.u32, v.cache32, nullptr, nullptr);
         if (batch_elem(P, 0)) a64[k].elem = P->elem;
         if (batch_elem(P, 1)) a32[k].elem = reinterpret_cast<float*>(P->elem);
-        const long long nblk = (v.ncells + P->ops->cpb - 1) / P->ops->cpb;
+        const long long nblk = (v.ncells + P->ops->cpb[0] - 1) / P->ops->cpb[0];
         for (long long j = 0; j < nblk; ++j) items.push_back(make_int2((int)k, (int)j));
         const unsigned L = (unsigned)v.L;
         const unsigned magic = (unsigned)((((unsigned long long)1 << 32) + L - 1) / L);
@@ -2230,7 +2258,7 @@ mfh_status mfh_batch_create(int n, mfh_problem* const* probs, void* ws, size_t b
           for (size_t i = 0; i < np; ++i) {
             const mfh_problem* P = B->probs[i];
             if (P->d.degree != deg) continue;
-            const long long nblk = (P->lv.back().ncells + P->ops->cpb - 1) / P->ops->cpb;
+            const long long nblk = (P->lv.back().ncells + P->ops->cpb[0] - 1) / P->ops->cpb[0];
             for (long long j = 0; j < nblk; ++j) items.push_back(make_int4((int)i, (int)j, deg, 0));
           }
         HIPCHECK(hipMemcpyAsync(B->fitems, items.data(), sizeof(int4) * items.size(), hipMemcpyHostToDevice, s));

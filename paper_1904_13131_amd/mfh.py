@@ -43,6 +43,7 @@ class Desc(ctypes.Structure):
         ("eig_iters", ctypes.c_int), ("cheb_lo", ctypes.c_double), ("cheb_hi", ctypes.c_double),
         ("level_field", ctypes.c_int), ("coarse_solver", ctypes.c_int), ("eig_refresh", ctypes.c_int),
         ("law", ctypes.c_int), ("mu2", ctypes.POINTER(ctypes.c_double)), ("tile_shape", ctypes.c_int),
+        ("cell_block", ctypes.c_int),
     ]
 
 
@@ -118,6 +119,8 @@ def lib():
         "mfh_scatter_mode": (st, [_P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
         "mfh_tile_shape": (st, [_P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                 ctypes.POINTER(ctypes.c_int)]),
+        "mfh_cell_block": (st, [_P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                ctypes.POINTER(ctypes.c_int)]),
         "mfh_timer_enable": (st, [_P, ctypes.c_int]),
         "mfh_timer_read": (st, [_P, _D, ctypes.POINTER(ctypes.c_longlong)]),
         "mfh_csr_size": (st, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong)]),
@@ -146,7 +149,7 @@ def _darr(vals):
 def make_desc(dim, n_cells, degree, n_levels=1, mu=(1.0,), lam=(1.5,), inclusions=(), dirichlet_mask=0,
               qp_policy=QP_RECOMPUTE, scatter=SCATTER_AUTO, vcycle_dtype=F32, cheb_degree=4, n_smooth=2,
               eig_iters=30, cheb_lo=0.6, cheb_hi=1.2, level_field=0, coarse_solver=0, eig_refresh=1,
-              law=LAW_NEO_HOOKE, mu2=None, tile_shape=-1):
+              law=LAW_NEO_HOOKE, mu2=None, tile_shape=-1, cell_block=-1):
     """Builds an mfh_desc; the returned tuple keeps the host arrays alive."""
     d = Desc()
     lib().mfh_desc_defaults(ctypes.byref(d))
@@ -169,6 +172,7 @@ def make_desc(dim, n_cells, degree, n_levels=1, mu=(1.0,), lam=(1.5,), inclusion
     d.coarse_solver, d.eig_refresh = coarse_solver, eig_refresh
     d.law = law
     d.tile_shape = tile_shape
+    d.cell_block = cell_block
     mu2_a = _darr(mu2 if mu2 is not None else [0.0] * len(mu))
     d.mu2 = ctypes.cast(mu2_a, _D)
     return d, (mu_a, lam_a, inc_a, mu2_a)
@@ -364,6 +368,13 @@ class Problem:
         _check(lib().mfh_tile_shape(self.handle, level % self.n_levels, dtype, ctypes.byref(shape), cells),
                self.handle)
         return shape.value, tuple(cells)
+
+    def cell_block(self, level=-1, dtype=F64):
+        """Cell-block variant of the tangent vmult's pencil kernels on a level: (variant, cells per workgroup)."""
+        v, cells = ctypes.c_int(), ctypes.c_int()
+        _check(lib().mfh_cell_block(self.handle, level % self.n_levels, dtype, ctypes.byref(v), ctypes.byref(cells)),
+               self.handle)
+        return v.value, cells.value
 
     def node_coords_1d(self, level=-1):
         """Support-point coordinates along one axis (numpy array of L values)."""

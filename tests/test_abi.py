@@ -58,7 +58,7 @@ def test_workspace_size_on_host():
     dict(cheb_degree=0), dict(n_smooth=0), dict(eig_iters=0), dict(cheb_lo=1.3, cheb_hi=1.2),
     dict(dirichlet_mask=1 << 18), dict(level_field=2), dict(coarse_solver=2), dict(eig_refresh=-1), dict(inclusions=[((0.5, 0.5, 0.5), 0.2, 2)]),
     dict(law=2), dict(law=1, qp_policy=2, mu2=(0.3, 30.0)), dict(law=1, qp_policy=3, mu2=(-0.3, 30.0)),
-    dict(law=1, qp_policy=3, mu2=(float("nan"), 30.0)), dict(tile_shape=2), dict(tile_shape=-2),
+    dict(law=1, qp_policy=3, mu2=(float("nan"), 30.0)), dict(tile_shape=2), dict(tile_shape=-2), dict(cell_block=2), dict(cell_block=-2),
 ])
 def test_invalid_descriptors_rejected(bad):
     from paper_1904_13131_amd import MfhError, workspace_size

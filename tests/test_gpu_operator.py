@@ -50,21 +50,23 @@ def _oracle(name):
     return _ORACLE[name]
 
 
-# (scatter mode, tile shape): both compiled tile shapes of the TILE scatter
-SCATTERS64 = [(0, -1), (1, -1), (2, 0), (2, 1), (3, -1), (-1, -1)]
-SCATTERS32 = [(0, -1), (2, 0), (2, 1), (3, -1), (-1, -1)]
-IDS64 = ["atomic", "color", "tile0", "tile1", "elem", "auto"]
-IDS32 = ["atomic", "tile0", "tile1", "elem", "auto"]
+# (scatter mode, tile shape, cell block): both compiled tile shapes of the
+# TILE scatter, both cell-block lengths of the pencil-kernel modes
+SCATTERS64 = [(0, -1, 0), (0, -1, 1), (1, -1, 0), (1, -1, 1), (2, 0, 0), (2, 1, 0), (3, -1, 0), (3, -1, 1),
+              (-1, -1, -1)]
+SCATTERS32 = [(0, -1, 0), (0, -1, 1), (2, 0, 0), (2, 1, 0), (3, -1, 0), (3, -1, 1), (-1, -1, -1)]
+IDS64 = ["atomic", "atomic_b1", "color", "color_b1", "tile0", "tile1", "elem", "elem_b1", "auto"]
+IDS32 = ["atomic", "atomic_b1", "tile0", "tile1", "elem", "elem_b1", "auto"]
 
 
-@pytest.mark.parametrize("scatter,tile", SCATTERS64, ids=IDS64)
+@pytest.mark.parametrize("scatter,tile,cb", SCATTERS64, ids=IDS64)
 @pytest.mark.parametrize("policy", [0, 1, 2, 3], ids=["R", "CF", "C2", "C4"])
 @pytest.mark.parametrize("name", list(CASES))
-def test_vmult_fp64(name, policy, scatter, tile):
-    log_case("vmult_fp64", name=name, policy=policy, scatter=scatter, tile=tile)
+def test_vmult_fp64(name, policy, scatter, tile, cb):
+    log_case("vmult_fp64", name=name, policy=policy, scatter=scatter, tile=tile, cell_block=cb)
     w = CASES[name]
     _, _, _, K, _ = _oracle(name)
-    P = device_problem(w, qp_policy=policy, scatter=scatter, tile_shape=tile)
+    P = device_problem(w, qp_policy=policy, scatter=scatter, tile_shape=tile, cell_block=cb)
     mj = P.set_deformation(dev(w["u"]))
     assert mj > 0
     y = host(P.tangent_vmult(dev(w["x"])))
@@ -72,14 +74,14 @@ def test_vmult_fp64(name, policy, scatter, tile):
     assert rel_l2(y, want) <= 1e-12 and rel_max(y, want) <= 1e-12
 
 
-@pytest.mark.parametrize("scatter,tile", SCATTERS32, ids=IDS32)
+@pytest.mark.parametrize("scatter,tile,cb", SCATTERS32, ids=IDS32)
 @pytest.mark.parametrize("policy", [0, 1, 2, 3], ids=["R", "CF", "C2", "C4"])
 @pytest.mark.parametrize("name", list(CASES))
-def test_vmult_fp32(name, policy, scatter, tile):
-    log_case("vmult_fp32", name=name, policy=policy, scatter=scatter, tile=tile)
+def test_vmult_fp32(name, policy, scatter, tile, cb):
+    log_case("vmult_fp32", name=name, policy=policy, scatter=scatter, tile=tile, cell_block=cb)
     w = CASES[name]
     _, _, _, K, _ = _oracle(name)
-    P = device_problem(w, qp_policy=policy, scatter=scatter, tile_shape=tile)
+    P = device_problem(w, qp_policy=policy, scatter=scatter, tile_shape=tile, cell_block=cb)
     P.set_deformation(dev(w["u"]))
     x32 = w["x"].astype(np.float32)
     y = host(P.tangent_vmult(dev(x32, torch.float32)))
@@ -103,6 +105,22 @@ def test_tile_shapes_reported():
     assert (F64, (3, 3, 3)) in seen and len(seen) == 4
     P = device_problem(w, scatter=2)
     assert P.tile_shape()[0] in (0, 1)
+
+
+def test_cell_blocks_reported():
+    """Cells per workgroup of the two cell-block variants (3-D Q2: 27 and 14,
+    3-D Q4: 8 and 10), forced and tuned, as reported by mfh_cell_block."""
+    from paper_1904_13131_amd import F32, F64
+    log_case("cell_blocks")
+    for name, want in (("3d_q2", (27, 14)), ("3d_q4_clamp", (8, 10))):
+        w = CASES[name]
+        for cb in (0, 1):
+            P = device_problem(w, scatter=3, cell_block=cb)
+            for dt in (F64, F32):
+                assert P.cell_block(dtype=dt) == (cb, want[cb])
+        P = device_problem(w)
+        v, cells = P.cell_block()
+        assert cells == want[v]
 
 
 @pytest.mark.parametrize("scatter", [0, 1], ids=["atomic", "color"])
