@@ -1,6 +1,8 @@
 // Vector, transfer and coarse-solve kernels.
 #include "vec.hpp"
 
+#include <stdexcept>
+
 namespace mfh {
 
 namespace {
@@ -205,34 +207,44 @@ __global__ void k_reciprocal(const double* __restrict__ in, TO* __restrict__ out
     out[i] = (TO)(1.0 / in[i]);
 }
 
-template <typename T>
+// One output entry per thread: blockIdx.y = (component, index along axis 2)
+// of the output, the x threads run over its axis-0 x axis-1 plane, so the
+// only per-thread division is by the plane's row length (32-bit; the launch
+// checks that plane and component sizes fit).  KB > 0: the band width as a
+// compile-time constant (loads of the band unrolled and in flight together);
+// KB = 0: any width.
+template <typename T, int KB>
 __global__ void k_sweep(const T* __restrict__ in, T* __restrict__ out, SweepArgs<T> a) {
-  int m[3] = {a.n[0], a.n[1], a.n[2]};
-  m[a.axis] = a.band.nout;
-  const long long per = (long long)m[0] * m[1] * m[2];
-  const long long total = per * a.comps;
-  for (long long g = blockIdx.x * (long long)kVB + threadIdx.x; g < total; g += (long long)gridDim.x * kVB) {
-    const int c = (int)(g / per);
-    long long r = g - c * per;
-    int idx[3];
-    idx[0] = (int)(r % m[0]);
-    r /= m[0];
-    idx[1] = (int)(r % m[1]);
-    idx[2] = (int)(r / m[1]);
-    const int o = idx[a.axis];
-    const int st = a.band.start[o];
-    long long stride = 1;
-    for (int k = 0; k < a.axis; ++k) stride *= a.n[k];
-    idx[a.axis] = st;
-    const long long ib = c * a.in_cs + idx[0] + (long long)a.n[0] * (idx[1] + (long long)a.n[1] * idx[2]);
-    const T* v = a.band.vals + (long long)o * a.band.K;
-    T s = 0;
-    for (int k = 0; k < a.band.K; ++k) s += v[k] * in[ib + k * stride];
-    idx[a.axis] = o;
-    const long long ob = c * a.out_cs + idx[0] + (long long)m[0] * (idx[1] + (long long)m[1] * idx[2]);
-    if (a.mask && constrained_dof(a.lt, c * a.lt.nn + (ob - c * a.out_cs))) s = T(0);
-    out[ob] = a.add ? out[ob] + s : s;
+  const unsigned m0 = a.axis == 0 ? a.band.nout : a.n[0];
+  const unsigned m1 = a.axis == 1 ? a.band.nout : a.n[1];
+  const unsigned m2 = a.axis == 2 ? a.band.nout : a.n[2];
+  const unsigned t = blockIdx.x * kVB + threadIdx.x;
+  if (t >= m0 * m1) return;
+  const unsigned c = blockIdx.y / m2, i2 = blockIdx.y - c * m2;
+  const unsigned i1 = t / m0, i0 = t - i1 * m0;
+  const unsigned o = a.axis == 0 ? i0 : a.axis == 1 ? i1 : i2;
+  const unsigned st = (unsigned)a.band.start[o];
+  const unsigned j0 = a.axis == 0 ? st : i0, j1 = a.axis == 1 ? st : i1, j2 = a.axis == 2 ? st : i2;
+  const unsigned n0 = a.n[0], n1 = a.n[1];
+  const unsigned stride = a.axis == 0 ? 1u : a.axis == 1 ? n0 : n0 * n1;
+  const T* src = in + c * a.in_cs + (j0 + n0 * (j1 + n1 * j2));
+  const T* v = a.band.vals + (long long)o * a.band.K;
+  T s = 0;
+  if constexpr (KB > 0) {
+    T w[KB], x[KB];
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+      w[k] = v[k];
+      x[k] = src[k * stride];
+    }
+#pragma unroll
+    for (int k = 0; k < KB; ++k) s += w[k] * x[k];
+  } else {
+    for (int k = 0; k < a.band.K; ++k) s += v[k] * src[k * stride];
   }
+  const long long ob = c * a.out_cs + (i0 + m0 * (i1 + m1 * i2));
+  if (a.mask && (node_faces((int)i0, (int)i1, (int)i2, a.lt.L, a.lt.dim) & a.lt.fmask[c])) s = T(0);
+  out[ob] = a.add ? out[ob] + s : s;
 }
 
 struct FaceVals {
@@ -1103,8 +1115,23 @@ void reciprocal(const double* in, TO* out, long long n, hipStream_t s) {
 }
 template <typename T>
 void sweep(const T* in, T* out, const SweepArgs<T>& a, hipStream_t s) {
-  long long m = (long long)a.n[0] * a.n[1] * a.n[2] / a.n[a.axis] * a.band.nout * a.comps;
-  hipLaunchKernelGGL(k_sweep<T>, dim3(grid_for(m)), dim3(kVB), 0, s, in, out, a);
+  const long long m0 = a.axis == 0 ? a.band.nout : a.n[0], m1 = a.axis == 1 ? a.band.nout : a.n[1];
+  const long long m2 = a.axis == 2 ? a.band.nout : a.n[2];
+  const long long in_per = (long long)a.n[0] * a.n[1] * a.n[2];
+  if (m0 * m1 >= (1LL << 31) || in_per >= (1LL << 32) || m0 * m1 * m2 >= (1LL << 32) || m2 * a.comps > 65535)
+    throw std::runtime_error("transfer sweep: lattice too large for the 32-bit sweep indices");
+  const dim3 grid((unsigned)((m0 * m1 + kVB - 1) / kVB), (unsigned)(m2 * a.comps));
+  switch (a.band.K) {
+#define MFH_SWEEP_K(K) \
+  case K:              \
+    hipLaunchKernelGGL((k_sweep<T, K>), grid, dim3(kVB), 0, s, in, out, a); \
+    break;
+    MFH_SWEEP_K(1) MFH_SWEEP_K(2) MFH_SWEEP_K(3) MFH_SWEEP_K(4) MFH_SWEEP_K(5)
+    MFH_SWEEP_K(6) MFH_SWEEP_K(7) MFH_SWEEP_K(8) MFH_SWEEP_K(9)
+#undef MFH_SWEEP_K
+    default:
+      hipLaunchKernelGGL((k_sweep<T, 0>), grid, dim3(kVB), 0, s, in, out, a);
+  }
 }
 
 void set_dirichlet(double* u, const Lattice& lt, const double* fv, double scale, long long n, hipStream_t s) {
