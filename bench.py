@@ -41,11 +41,11 @@ POLICIES = {0: "recompute", 1: "cache_F", 2: "cache_T2", 3: "cache_T4"}
 # rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by a 256 MiB device copy (reads
 # x2.0, writes x1.0; profiles/tangent_vmult_q2_32cube_hbm_counters.md); valid
 # only for the kernel source they were taken on.
-TRAFFIC_SOURCE_SHA = "15507b890b1bcd8a"
-TRAFFIC = {"recompute/f64/element": 58799276, "cache_F/f64/element": 116143558,
-           "cache_T2/f64/element": 123006089, "cache_T4/f64/element": 349121758,
-           "recompute/f32/element": 32041522, "cache_F/f32/element": 60378434,
-           "cache_T2/f32/element": 63752107, "cache_T4/f32/element": 173375393}
+TRAFFIC_SOURCE_SHA = "96b5c976ad8ec479"
+TRAFFIC = {"recompute/f64/element": 58785859, "cache_F/f64/element": 116122789,
+           "cache_T2/f64/element": 123013800, "cache_T4/f64/element": 348990304,
+           "recompute/f32/element": 32024088, "cache_F/f32/element": 60367087,
+           "cache_T2/f32/element": 63740867, "cache_T4/f32/element": 173326784}
 
 QP_FLOPS_3D = {0: 261, 1: 255, 2: 170, 3: 246}
 QP_FLOPS_2D = {0: 100, 1: 98, 2: 55, 3: 71}
