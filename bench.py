@@ -424,6 +424,39 @@ def _q4_problem(n_cells, n_levels, level_field):
                    dirichlet_mask=W.clamp_bottom_top(3), qp_policy=2, vcycle_dtype=F32, level_field=level_field)
 
 
+def _q4_reach(n_cells, n_levels, cg_max_it, coarse_solver=0, fp64_vcycle=False, budget_s=30.0, strain=-0.2):
+    """The config-5 body at another resolution: one Newton solve over the five
+    load steps towards `strain`, within a wall-time budget; how far it gets
+    and why it stops."""
+    import torch
+
+    import workloads as W
+    from paper_1904_13131_amd import F32, F64, Problem, lib
+    mu, lam = W.two_phase_material()
+    P = Problem(3, n_cells, 4, n_levels=n_levels, mu=tuple(mu), lam=tuple(lam), inclusions=W.spheres(200, 7),
+                dirichlet_mask=W.clamp_bottom_top(3), qp_policy=2, vcycle_dtype=F64 if fp64_vcycle else F32,
+                coarse_solver=coarse_solver)
+    u = torch.zeros(P.n_dofs(), dtype=torch.float64, device="cuda")
+    fv = np.zeros((6, 3))
+    fv[5][2] = strain
+    t0 = time.perf_counter()
+    recs, st = P.newton_solve(u, fv, n_steps=5, cg_max_it=cg_max_it, raise_on_error=False, max_seconds=budget_s)
+    why = lib().mfh_last_error(P.handle).decode() if st != 0 else ""
+    out = {"mesh": f"{n_cells}^3 Q4", "levels": n_levels,
+           "preconditioner": "Chebyshev solver on the one level" if coarse_solver else "GMG, direct coarse solve",
+           "vcycle": "f64" if fp64_vcycle else "f32", "cg_max_it": cg_max_it, "status": int(st), "stop_reason": why,
+           "strain_reached": _converged_fraction(recs) * strain, "newton_steps": len(recs),
+           "max_cg_iters": max([r["cg_iters"] for r in recs] or [0]),
+           "max_coarse_negative": max([r["coarse_negative"] for r in recs] or [0]),
+           "wall_s": round(time.perf_counter() - t0, 2)}
+    print(f"[bench] q4 body {out['mesh']}, {n_levels} level(s), {out['preconditioner']}, CG cap {cg_max_it}: "
+          f"{out['strain_reached']:.2%} of -20 %, status {st} ({why[:80]})", file=sys.stderr, flush=True)
+    P.close()
+    del P
+    torch.cuda.empty_cache()
+    return out
+
+
 def _converged_fraction(recs, du_tol=1e-5, r_tol=1e-8):
     """Largest load fraction whose increment converged, from the Newton records
     (an increment's records share its load fraction, with rising step numbers)."""
@@ -550,6 +583,12 @@ def q4_48cube_bench(n_cells=48, n_levels=5, n_steps=5, steps=10, newton=True, bu
     if newton:
         out["newton"] = [_q4_newton(n_cells, n_levels, -0.2, n_steps, 0, budget_s=budget_s),
                          _q4_newton(n_cells, n_levels, +0.2, n_steps, 1, budget_s=budget_s)]
+        # the same body and compression at coarser resolutions: where the load
+        # path ends with the multigrid preconditioner, and where the body's
+        # own tangent gives out (one level, no coarse displacements)
+        out["resolution_study"] = [_q4_reach(4, 2, 3000, fp64_vcycle=True),
+                                   _q4_reach(12, 3, 3000),
+                                   _q4_reach(12, 1, 2000, coarse_solver=1, fp64_vcycle=True)]
     return out
 
 
