@@ -1,8 +1,9 @@
 """The allocation-free dense inverse (mfh_dense_inverse_static, for callers
 that cannot allocate device memory) against the workspace entry point
-(mfh_dense_inverse), through the C ABI: two calls in a row on one GPU, the
-second with a smaller matrix (the static work arrays keep the first call's
-contents), plus the size limit."""
+(mfh_dense_inverse), through the C ABI: calls in a row on one GPU, each
+with a smaller matrix than the one before (the static work arrays keep the
+previous call's contents), indefinite ones (pivoted pass) and a positive
+definite one (plain pass), plus the size limit."""
 import ctypes
 
 import numpy as np
@@ -14,20 +15,22 @@ from tests.gpu_helpers import host, log_case, requires_gpu
 pytestmark = [pytest.mark.gpu, requires_gpu]
 
 
-def _sym(n, seed):
+def _sym(n, seed, definite=False):
     rng = np.random.default_rng(seed)
     q, _ = np.linalg.qr(rng.standard_normal((n, n)))
-    eigs = rng.uniform(0.5, 2.0, n) * rng.choice([-1.0, 1.0], n)
-    A = (q * eigs) @ q.T
-    A[: n // 4, : n // 4] = 0.0            # zero leading block: pivoting needed
+    eigs = rng.uniform(0.5, 2.0, n)
+    if definite:                           # the plain pass is kept
+        return (q * eigs) @ q.T
+    A = (q * (eigs * rng.choice([-1.0, 1.0], n))) @ q.T
+    A[: n // 4, : n // 4] = 0.0            # zero leading block: the pivoted pass runs
     return A
 
 
 def test_static_dense_inverse_matches_workspace_entry():
     from paper_1904_13131_amd import dense_inverse
-    for n, seed in ((1000, 1), (301, 2)):
-        log_case("dense_inverse_static", n=n)
-        A = torch.as_tensor(_sym(n, seed), device="cuda")
+    for n, seed, definite in ((1000, 1, False), (301, 2, False), (200, 3, True)):
+        log_case("dense_inverse_static", n=n, definite=definite)
+        A = torch.as_tensor(_sym(n, seed, definite), device="cuda")
         ref, neg_ref = dense_inverse(A)
         got, neg = dense_inverse(A, static=True)
         r, g = host(ref), host(got)
