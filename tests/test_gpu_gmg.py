@@ -34,6 +34,12 @@ LAMBDA_TOL = 1e-13
 # linear map evaluated in FP32 (unit roundoff 6e-8) through up to 16 operator
 # applications per level and three levels.
 VCYCLE_F32_TOL = 2e-5
+# FP64 V-cycle with its own Lanczos estimates and the Chebyshev coarse solver:
+# the interval starts at the coarse run's smallest Ritz value, which rounding
+# alone moves far (one-ulp perturbations of the oracle's own products move
+# its V-cycle by up to 6e-6:
+# test_oracle_gmg.py::test_chebyshev_coarse_own_estimate_sensitivity).
+CHEB_OWN_TOL = 1e-4
 
 
 def _fix_intervals(P, H):
@@ -164,15 +170,17 @@ def test_vcycle_fp64_own_estimates(name):
     oracle to 1e-12: the largest Ritz values agree to rounding (LAMBDA_TOL).
     The Chebyshev coarse solver also takes the smallest Ritz value of the
     coarse run, which 30 steps leave far from converged and sensitive to the
-    summation order, and its degree-40 polynomial amplifies that (measured
-    5.9e-9); on the oracle's estimates it agrees to 1e-12 (above)."""
+    summation order, and its polynomial (degree 94 here) amplifies that
+    (measured 5.9e-9 and 1.2e-7 in two runs whose coarse products summed in
+    different orders; CHEB_OWN_TOL); on the oracle's estimates it agrees to
+    1e-12 (above)."""
     log_case("vcycle_f64_own", name=name)
     c, mu, lam, incl, mask, H, u, b = _setup(name)
     P = _device(name, F64)
     z, zw = host(P.gmg_vcycle(dev(b))), H.vcycle(b)
     dl = max(abs(P.level_lambda_max(l) - H.lam_max[l]) / H.lam_max[l] for l in range(1, c["n_levels"]))
     print(f"[vcycle_f64_own] {name}: lambda rel {dl:.2e}, vcycle rel {rel_l2(z, zw):.2e}", flush=True)
-    assert rel_l2(z, zw) <= (1e-7 if c.get("coarse") == "chebyshev" else 1e-12)
+    assert rel_l2(z, zw) <= (CHEB_OWN_TOL if c.get("coarse") == "chebyshev" else 1e-12)
 
 
 @pytest.mark.parametrize("name", list(HIER))

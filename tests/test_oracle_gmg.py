@@ -210,6 +210,47 @@ def test_chebyshev_coarse_solver():
     assert rel <= 1e-8
 
 
+def test_chebyshev_coarse_own_estimate_sensitivity():
+    """The Chebyshev coarse solver (Sec. 7) starts its interval at the smallest
+    Ritz value of the coarse level's 30-step CG-Lanczos run, which is far from
+    converged: perturbing every product of that run by one unit in the last
+    place (a change of summation order does as much) moves it by 1e-7 to
+    2e-4 and the whole V-cycle by 4e-9 to 6e-6 on the 3-D Q2 hierarchy of the
+    device comparison (two coarse cells, three levels, three spheres), while
+    the largest Ritz value stays within 1e-15.  So a device V-cycle with its
+    own estimates cannot match the oracle's to 1e-12 in this configuration;
+    the device test holds it to 1e-4 and the shared-interval one to 1e-12."""
+    mu, lam = W.two_phase_material()
+    mat = fe.Material(mu, lam, W.spheres(3, 3, 3))
+    H = gmg.Hierarchy(3, 2, 2, 3, mat, W.clamp_bottom_top(3), coarse_solver="chebyshev")
+    fine = H.meshes[-1]
+    u = W.sine_field(3, fine.L, 4, 0.01, kmax=1)
+    u[H.cons[-1]] = 0.0
+    H.set_deformation(u)
+    b = W.normal_vector(fine.n_dofs, 5)
+    b[H.cons[-1]] = 0.0
+    z0 = H.vcycle(b)
+    lmin0, lmax0 = H.lam_min0, H.lam_max[0]
+    A, m = H.A[0], H.meshes[0]
+    rg = np.random.default_rng(1)
+    dz, dmin, dmax = [], [], []
+    for _ in range(12):
+        def apply(v):
+            y = A @ v
+            return y * (1.0 + 2.0 ** -52 * rg.choice([-1.0, 1.0], size=y.shape))
+        lmax, _ = gmg.lanczos_lambda_max(apply, H.dinv[0], gmg.eig_start_vector(m.n_dofs, H.cons[0]), H.eig_iters)
+        lmin = gmg.lanczos_lambda_max.last_min
+        H.interval[0] = (lmin, H.cheb_hi * lmax)
+        H.coarse_degree = gmg.chebyshev_solver_degree(lmin, H.cheb_hi * lmax, gmg.COARSE_REDUCTION)
+        z = H.vcycle(b)
+        dz.append(np.linalg.norm(z - z0) / np.linalg.norm(z0))
+        dmin.append(abs(lmin - lmin0) / lmin0)
+        dmax.append(abs(lmax - lmax0) / lmax0)
+    assert max(dmax) <= 1e-14
+    assert max(dmin) >= 1e-8 and max(dz) >= 1e-9     # far above rounding
+    assert max(dz) <= 1e-4                          # the device test's bar
+
+
 def _spd(n, eigs, seed):
     q, _ = np.linalg.qr(np.random.default_rng(seed).standard_normal((n, n)))
     return (q * np.asarray(eigs, dtype=np.float64)) @ q.T
