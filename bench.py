@@ -41,11 +41,11 @@ POLICIES = {0: "recompute", 1: "cache_F", 2: "cache_T2", 3: "cache_T4"}
 # rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled by a 256 MiB device copy (reads
 # x2.0, writes x1.0; profiles/tangent_vmult_q2_32cube_hbm_counters.md); valid
 # only for the kernel source they were taken on.
-TRAFFIC_SOURCE_SHA = "96b5c976ad8ec479"
-TRAFFIC = {"recompute/f64/element": 58785859, "cache_F/f64/element": 116122789,
-           "cache_T2/f64/element": 123013800, "cache_T4/f64/element": 348990304,
-           "recompute/f32/element": 32024088, "cache_F/f32/element": 60367087,
-           "cache_T2/f32/element": 63740867, "cache_T4/f32/element": 173326784}
+TRAFFIC_SOURCE_SHA = "100930e8fd80cb5a"
+TRAFFIC = {"recompute/f64/element": 58784664, "cache_F/f64/element": 116125656,
+           "cache_T2/f64/element": 123012254, "cache_T4/f64/element": 348807387,
+           "recompute/f32/element": 32022950, "cache_F/f32/element": 60365742,
+           "cache_T2/f32/element": 63739593, "cache_T4/f32/element": 173464575}
 
 QP_FLOPS_3D = {0: 261, 1: 255, 2: 170, 3: 246}
 QP_FLOPS_2D = {0: 100, 1: 98, 2: 55, 3: 71}

@@ -102,11 +102,86 @@ struct ElemLayout {
   static constexpr int NX = (N1 - 1) * NP;
 };
 
+// Even-odd form of the 1-D products.  The support and Gauss points are
+// symmetric about the cell centre, so S and S^T are centro-symmetric
+// (M[n-1-r][n-1-c] = M[r][c]) and D and D^T skew (= -M[r][c]).  A line v is
+// folded into e[c] = v[c] + v[n-1-c], o[c] = v[c] - v[n-1-c] (c < h = n/2)
+// and, for odd n, its middle value vm; products are accumulated as P and Q
+// with y[r] = P[r] + Q[r], y[n-1-r] = P[r] - Q[r] (r < h), y[h] = P[h]: a
+// symmetric M adds its even half times e and its middle column times vm to
+// P and its odd half times o to Q, a skew M its odd half times o to P and its
+// even half times e and middle column times vm to Q.  At n = 5 one product
+// takes 13 (symmetric) or 12 (skew) multiply-adds instead of 25, plus four
+// additions to fold each input line and four to unfold each output line,
+// shared by the products of a sweep.
+template <int N1, typename T>
+struct EvenOdd {
+  static constexpr int H = N1 / 2, NPQ = H + (N1 & 1);
+  struct Fold {
+    T e[H], o[H], m;
+  };
+  struct Acc {
+    T P[NPQ], Q[H];
+    __device__ Acc() {
+#pragma unroll
+      for (int r = 0; r < NPQ; ++r) P[r] = 0;
+#pragma unroll
+      for (int r = 0; r < H; ++r) Q[r] = 0;
+    }
+  };
+  __device__ static __forceinline__ Fold fold(const T (&v)[N1]) {
+    Fold f;
+#pragma unroll
+    for (int c = 0; c < H; ++c) {
+      f.e[c] = v[c] + v[N1 - 1 - c];
+      f.o[c] = v[c] - v[N1 - 1 - c];
+    }
+    f.m = (N1 & 1) ? v[H] : T(0);
+    return f;
+  }
+  // acc += M v for M = S, D, S^T, D^T (M = 0..3; 1 and 3 are skew)
+  template <int M>
+  __device__ static __forceinline__ void add(Acc& acc, const Fold& f, const Tables<T>& tb) {
+    constexpr bool skew = M & 1;
+#pragma unroll
+    for (int r = 0; r < NPQ; ++r)
+#pragma unroll
+      for (int c = 0; c < H; ++c) acc.P[r] += tb.eo[M][skew ? 1 : 0][r][c] * (skew ? f.o[c] : f.e[c]);
+#pragma unroll
+    for (int r = 0; r < H; ++r)
+#pragma unroll
+      for (int c = 0; c < H; ++c) acc.Q[r] += tb.eo[M][skew ? 0 : 1][r][c] * (skew ? f.e[c] : f.o[c]);
+    if constexpr (N1 & 1) {
+      if constexpr (skew) {
+#pragma unroll
+        for (int r = 0; r < H; ++r) acc.Q[r] += tb.mid[M][r] * f.m;
+      } else {
+#pragma unroll
+        for (int r = 0; r < NPQ; ++r) acc.P[r] += tb.mid[M][r] * f.m;
+      }
+    }
+  }
+  __device__ static __forceinline__ void unfold(const Acc& acc, T (&y)[N1]) {
+#pragma unroll
+    for (int r = 0; r < H; ++r) {
+      y[r] = acc.P[r] + acc.Q[r];
+      y[N1 - 1 - r] = acc.P[r] - acc.Q[r];
+    }
+    if constexpr (N1 & 1) y[H] = acc.P[H];
+  }
+};
+
 // Sum-factorisation sweeps over the LDS of a block of NCELL cells (the
-// pencil kernels' cells per block by default; the tile kernel's tile).
+// pencil kernels' cells per block by default; the tile kernel's tile).  In
+// 3-D from n = 4 the sweeps take the even-odd form (EvenOdd): measured
+// 3-11 % faster vmults at Q4 and 2-8 % at Q3 (except Q3 FP64 with cached
+// F^-1, within noise), no gain at Q2, where a product of 9 multiply-adds
+// becomes 7 or 6 plus the folds.
 template <int DIM, int N1, typename T, int NCELL = Geo<DIM, N1>::CPB>
 struct SumFact {
   static constexpr int NV = Geo<DIM, N1>::NV, CPB = NCELL;
+  static constexpr bool kEO = DIM == 3 && N1 >= 4;
+  using EO = EvenOdd<N1, T>;
 
   __device__ static __forceinline__ int pt(int x, int y, int z) { return x + N1 * (y + N1 * z); }
   __device__ static __forceinline__ T& at(T* lds, int arr, int p, int cl) {
@@ -119,7 +194,9 @@ struct SumFact {
   template <int NC>
   __device__ static void forward(const T (&v)[NC][N1], T (&g)[NC][DIM][N1], T* lds,
                                  int pen, int cl, bool act, const Tables<T>& tb) {
-    if constexpr (DIM == 3) {
+    if constexpr (kEO) {
+      forward_eo<NC>(v, g, lds, pen, cl, act, tb);
+    } else if constexpr (DIM == 3) {
       const int p0 = pen % N1, p1 = pen / N1;
       if (act) {   // x-sweep: line (b, c) = (p0, p1)
 #pragma unroll
@@ -239,7 +316,9 @@ struct SumFact {
   template <int NC>
   __device__ static void backward(const T (&P)[NC][DIM][N1], T (&out)[NC][N1], T* lds,
                                   int pen, int cl, bool act, const Tables<T>& tb) {
-    if constexpr (DIM == 3) {
+    if constexpr (kEO) {
+      backward_eo<NC>(P, out, lds, pen, cl, act, tb);
+    } else if constexpr (DIM == 3) {
       const int p0 = pen % N1, p1 = pen / N1;
       if (act) {   // z: line (qx, qy)
 #pragma unroll
@@ -341,6 +420,150 @@ struct SumFact {
       }
       __syncthreads();
     }
+  }
+
+  // 3-D sweeps in the even-odd form: the same products, stages and LDS
+  // traffic as the direct form above.
+  template <int NC>
+  __device__ static void forward_eo(const T (&v)[NC][N1], T (&g)[NC][DIM][N1], T* lds,
+                                    int pen, int cl, bool act, const Tables<T>& tb) {
+    const int p0 = pen % N1, p1 = pen / N1;
+    if (act) {   // x-sweep: line (b, c) = (p0, p1)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const typename EO::Fold f = EO::fold(v[c]);
+        typename EO::Acc as, ad;
+        EO::template add<0>(as, f, tb);
+        EO::template add<1>(ad, f, tb);
+        T s[N1], d[N1];
+        EO::unfold(as, s);
+        EO::unfold(ad, d);
+#pragma unroll
+        for (int q = 0; q < N1; ++q) {
+          at(lds, 3 * c + 0, pt(q, p0, p1), cl) = s[q];
+          at(lds, 3 * c + 1, pt(q, p0, p1), cl) = d[q];
+        }
+      }
+    }
+    __syncthreads();
+    if (act) {   // y-sweep: line (qx, c) = (p0, p1)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        T s[N1], d[N1];
+#pragma unroll
+        for (int b = 0; b < N1; ++b) {
+          s[b] = at(lds, 3 * c + 0, pt(p0, b, p1), cl);
+          d[b] = at(lds, 3 * c + 1, pt(p0, b, p1), cl);
+        }
+        const typename EO::Fold fs = EO::fold(s), fd = EO::fold(d);
+        typename EO::Acc ass, asd, ads;
+        EO::template add<0>(ass, fs, tb);   // S_y S_x
+        EO::template add<1>(asd, fs, tb);   // D_y S_x
+        EO::template add<0>(ads, fd, tb);   // S_y D_x
+        T ss[N1], sd[N1], ds[N1];
+        EO::unfold(ass, ss);
+        EO::unfold(asd, sd);
+        EO::unfold(ads, ds);
+#pragma unroll
+        for (int q = 0; q < N1; ++q) {
+          at(lds, 3 * c + 0, pt(p0, q, p1), cl) = ss[q];
+          at(lds, 3 * c + 1, pt(p0, q, p1), cl) = sd[q];
+          at(lds, 3 * c + 2, pt(p0, q, p1), cl) = ds[q];
+        }
+      }
+    }
+    __syncthreads();
+    if (act) {   // z-sweep: line (qx, qy) = (p0, p1)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        T ss[N1], sd[N1], ds[N1];
+#pragma unroll
+        for (int k = 0; k < N1; ++k) {
+          ss[k] = at(lds, 3 * c + 0, pt(p0, p1, k), cl);
+          sd[k] = at(lds, 3 * c + 1, pt(p0, p1, k), cl);
+          ds[k] = at(lds, 3 * c + 2, pt(p0, p1, k), cl);
+        }
+        const typename EO::Fold fss = EO::fold(ss), fsd = EO::fold(sd), fds = EO::fold(ds);
+        typename EO::Acc ax, ay, az;
+        EO::template add<0>(ax, fds, tb);
+        EO::template add<0>(ay, fsd, tb);
+        EO::template add<1>(az, fss, tb);
+        EO::unfold(ax, g[c][0]);
+        EO::unfold(ay, g[c][1]);
+        EO::unfold(az, g[c][2]);
+      }
+    }
+    __syncthreads();
+  }
+
+  template <int NC>
+  __device__ static void backward_eo(const T (&P)[NC][DIM][N1], T (&out)[NC][N1], T* lds,
+                                     int pen, int cl, bool act, const Tables<T>& tb) {
+    const int p0 = pen % N1, p1 = pen / N1;
+    if (act) {   // z: line (qx, qy)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const typename EO::Fold f0 = EO::fold(P[c][0]), f1 = EO::fold(P[c][1]), f2 = EO::fold(P[c][2]);
+        typename EO::Acc a0, a1, a2;
+        EO::template add<2>(a0, f0, tb);
+        EO::template add<2>(a1, f1, tb);
+        EO::template add<3>(a2, f2, tb);
+        T z0[N1], z1[N1], z2[N1];
+        EO::unfold(a0, z0);
+        EO::unfold(a1, z1);
+        EO::unfold(a2, z2);
+#pragma unroll
+        for (int k = 0; k < N1; ++k) {
+          at(lds, 3 * c + 0, pt(p0, p1, k), cl) = z0[k];
+          at(lds, 3 * c + 1, pt(p0, p1, k), cl) = z1[k];
+          at(lds, 3 * c + 2, pt(p0, p1, k), cl) = z2[k];
+        }
+      }
+    }
+    __syncthreads();
+    if (act) {   // y: line (qx, c)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        T z0[N1], z1[N1], z2[N1];
+#pragma unroll
+        for (int q = 0; q < N1; ++q) {
+          z0[q] = at(lds, 3 * c + 0, pt(p0, q, p1), cl);
+          z1[q] = at(lds, 3 * c + 1, pt(p0, q, p1), cl);
+          z2[q] = at(lds, 3 * c + 2, pt(p0, q, p1), cl);
+        }
+        const typename EO::Fold f0 = EO::fold(z0), f1 = EO::fold(z1), f2 = EO::fold(z2);
+        typename EO::Acc ad, as;
+        EO::template add<2>(ad, f0, tb);   // still needs D_x
+        EO::template add<3>(as, f1, tb);   // still needs S_x
+        EO::template add<2>(as, f2, tb);
+        T yd[N1], ys[N1];
+        EO::unfold(ad, yd);
+        EO::unfold(as, ys);
+#pragma unroll
+        for (int b = 0; b < N1; ++b) {
+          at(lds, 3 * c + 0, pt(p0, b, p1), cl) = yd[b];
+          at(lds, 3 * c + 1, pt(p0, b, p1), cl) = ys[b];
+        }
+      }
+    }
+    __syncthreads();
+    if (act) {   // x: line (b, c)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        T yd[N1], ys[N1];
+#pragma unroll
+        for (int q = 0; q < N1; ++q) {
+          yd[q] = at(lds, 3 * c + 0, pt(q, p0, p1), cl);
+          ys[q] = at(lds, 3 * c + 1, pt(q, p0, p1), cl);
+        }
+        const typename EO::Fold fd = EO::fold(yd), fs = EO::fold(ys);
+        typename EO::Acc a;
+        EO::template add<3>(a, fd, tb);
+        EO::template add<2>(a, fs, tb);
+        EO::unfold(a, out[c]);
+      }
+    }
+    __syncthreads();
   }
 };
 

@@ -19,6 +19,11 @@ struct Tables {
   T D[kMaxN1][kMaxN1];
   T w[kMaxN1];
   T xg[kMaxN1];   // Gauss points on [0,1]
+  // Even-odd halves of M = S, D, S^T, D^T (index 0..3; n = p + 1, h = n / 2):
+  // eo[M][0][r][c] = (M[r][c] + M[r][n-1-c]) / 2, eo[M][1][r][c] =
+  // (M[r][c] - M[r][n-1-c]) / 2 for c < h, r <= h; mid[M][r] = M[r][h].
+  T eo[4][2][kMaxN1][kMaxN1 / 2];
+  T mid[4][kMaxN1];
 };
 
 // Everything a cell kernel needs about one level, by value.

@@ -102,6 +102,17 @@ Tables<double> make_tables(int p) {
     t.w[q] = w[q];
     t.xg[q] = xg[q];
   }
+  const int n = p + 1, h = n / 2;
+  for (int M = 0; M < 4; ++M) {
+    auto m = [&](int r, int c) { return M == 0 ? t.S[r][c] : M == 1 ? t.D[r][c] : M == 2 ? t.S[c][r] : t.D[c][r]; };
+    for (int r = 0; r <= h && r < n; ++r) {
+      for (int c = 0; c < h; ++c) {
+        t.eo[M][0][r][c] = 0.5 * (m(r, c) + m(r, n - 1 - c));
+        t.eo[M][1][r][c] = 0.5 * (m(r, c) - m(r, n - 1 - c));
+      }
+      t.mid[M][r] = m(r, h);
+    }
+  }
   return t;
 }
 
@@ -115,6 +126,12 @@ Tables<float> to_float(const Tables<double>& t) {
     f.w[i] = (float)t.w[i];
     f.xg[i] = (float)t.xg[i];
   }
+  for (int M = 0; M < 4; ++M)
+    for (int r = 0; r < kMaxN1; ++r) {
+      for (int c = 0; c < kMaxN1 / 2; ++c)
+        for (int k = 0; k < 2; ++k) f.eo[M][k][r][c] = (float)t.eo[M][k][r][c];
+      f.mid[M][r] = (float)t.mid[M][r];
+    }
   return f;
 }
 
