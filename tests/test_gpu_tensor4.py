@@ -128,7 +128,6 @@ def test_mr_gmg(name):
     from paper_1904_13131_amd import F32, F64
     log_case("mr_gmg", name=name)
     c, H, u, b, w = _hier(name)
-    tol = 1e-5 if c["coarse"] else 1e-12
     for vdt in (F64, F32):
         P = _problem(w, n_levels=c["n_levels"], vcycle_dtype=vdt, coarse_solver=c["coarse"])
         P.set_deformation(dev(u))
@@ -137,7 +136,15 @@ def test_mr_gmg(name):
                 assert rel_l2(host(P.level_diagonal(l)), H.A[l].diagonal()) <= 1e-12
             for l in range(1, c["n_levels"]):
                 assert abs(P.level_lambda_max(l) - H.lam_max[l]) <= 1e-8 * H.lam_max[l]
-            assert rel_l2(host(P.gmg_vcycle(dev(b))), H.vcycle(b)) <= tol
+            # the V-cycle on the oracle's intervals: the Chebyshev coarse
+            # solver's lower end (the coarse run's smallest Ritz value) is
+            # too sensitive to rounding to compare own estimates tightly
+            # (test_oracle_gmg.py::test_chebyshev_coarse_own_estimate_sensitivity)
+            for l in range(1, c["n_levels"]):
+                P.set_level_eigenvalues(l, H.lam_max[l])
+            if c["coarse"]:
+                P.set_level_eigenvalues(0, H.lam_max[0], H.lam_min0)
+            assert rel_l2(host(P.gmg_vcycle(dev(b))), H.vcycle(b)) <= 1e-12
         x, it, rel, _ = P.cg_solve(dev(b), rtol=1e-8, max_it=200)
         xh = host(x)
         assert rel <= 1e-8
