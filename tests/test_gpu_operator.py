@@ -5,8 +5,9 @@ operators, through the C ABI.
 Bar: relative l2 error <= 1e-12 in FP64 and <= 1e-5 in FP32 (x rounded to
 FP32 first), for every quadrature-point policy and both scatter modes.  The
 small cases span several blocks of cells with a ragged last block; the full
-size of the 32^3 Q2 workload (823,875 DoFs) is checked on sampled rows that the
-oracle computes one by one, plus identities that hold at any size.
+size of the 32^3 Q2 workload (823,875 DoFs) and of the 48^3 Q4 benchmark body
+(21,567,171 DoFs) is checked on sampled rows that the oracle computes one by
+one, plus identities that hold at any size.
 """
 import numpy as np
 import pytest
@@ -241,3 +242,55 @@ def test_q2_32cube_tangent_is_derivative_of_device_residual():
     print(f"[q2_32cube_fd] rel {err:.2e}", flush=True)
     # truncation error O(eps^2) times the third derivative, rounding O(1e-16 / eps)
     assert err <= 1e-8
+
+
+# ---- full size: 48^3 Q4 with 200 spheres, 21,567,171 DoFs ----------------------------
+
+_C4 = {}
+
+
+def _q4_48cube():
+    """The 48^3 Q4 body (200 spheres, seed 7, bottom and top clamped) at a
+    smooth state, with sampled rows that the oracle computes one by one:
+    random rows plus nodes shared by 1, 2, 4 and 8 cells and constrained ones."""
+    if not _C4:
+        w = W.problem(3, 48, 4, n_spheres=200, sphere_seed=7, u_seed=4, u_amp=0.02, u_kmax=1, x_seed=5,
+                      mask=CLAMP3)
+        mesh, mat, cons = oracle_problem(w)
+        rng = np.random.default_rng(19)
+        rows = rng.choice(mesh.n_dofs, 100, replace=False)
+        L = mesh.L
+        node = lambda i, j, k: i + L * (j + L * k)
+        extra = [node(4, 4, 4), node(4, 2, 7), node(8, 8, 3), node(1, 2, 3), node(0, 96, 96),
+                 node(L - 1, L - 1, 100), node(50, 60, 0), node(L - 1, 0, L - 1)]
+        extra += [mesh.n_nodes + e for e in extra[:4]] + [2 * mesh.n_nodes + e for e in extra[:4]]
+        rows = np.unique(np.concatenate([rows, extra]))
+        _C4.update(w=w, mesh=mesh, mat=mat, cons=cons, rows=rows,
+                   ref=fe.vmult_rows(mesh, mat, w["u"], w["x"], rows, constrained=cons),
+                   ref32=fe.vmult_rows(mesh, mat, w["u"], w["x"].astype(np.float32).astype(np.float64), rows,
+                                       constrained=cons),
+                   rres=fe.residual_rows(mesh, mat, w["u"], rows, constrained=cons))
+    return _C4
+
+
+@pytest.mark.parametrize("policy", [0, 2], ids=["R", "C2"])
+def test_q4_48cube_sampled_rows(policy):
+    """The finest level of the Q4 benchmark at its real size (even-odd sweeps,
+    8-cell blocks, element scatter): FP64 rows to 1e-12 of the largest entry,
+    FP32 to 1e-5, residual rows to 1e-12."""
+    c = _q4_48cube()
+    w = c["w"]
+    log_case("q4_48cube_rows", policy=policy, n_dofs=c["mesh"].n_dofs)
+    P = device_problem(w, qp_policy=policy)
+    P.set_deformation(dev(w["u"]))
+    y = host(P.tangent_vmult(dev(w["x"])))
+    scale = np.abs(c["ref"]).max()
+    err = np.abs(y[c["rows"]] - c["ref"]).max() / scale
+    y32 = host(P.tangent_vmult(dev(w["x"].astype(np.float32), torch.float32)))
+    err32 = np.linalg.norm(y32[c["rows"]] - c["ref32"]) / np.linalg.norm(c["ref32"])
+    r = host(P.residual(dev(w["u"])))
+    rscale = max(np.abs(c["rres"]).max(), 1e-300)
+    errr = np.abs(r[c["rows"]] - c["rres"]).max() / rscale
+    print(f"[q4_48cube_rows] policy {policy}: fp64 {err:.2e} fp32 {err32:.2e} residual {errr:.2e}", flush=True)
+    assert err <= 1e-12 and err32 <= 1e-5 and errr <= 1e-12
+    P.close()
