@@ -5,9 +5,10 @@ operators, through the C ABI.
 Bar: relative l2 error <= 1e-12 in FP64 and <= 1e-5 in FP32 (x rounded to
 FP32 first), for every quadrature-point policy and both scatter modes.  The
 small cases span several blocks of cells with a ragged last block; the full
-size of the 32^3 Q2 workload (823,875 DoFs) and of the 48^3 Q4 benchmark body
-(21,567,171 DoFs) is checked on sampled rows that the oracle computes one by
-one, plus identities that hold at any size.
+size of the 32^3 Q2 workload (823,875 DoFs), of the 64^3 Q2 Newton level
+(6,440,067 DoFs) and of the 48^3 Q4 benchmark body (21,567,171 DoFs) is
+checked on sampled rows that the oracle computes one by one, plus identities
+that hold at any size.
 """
 import numpy as np
 import pytest
@@ -324,4 +325,34 @@ def test_q4_48cube_tangent_is_derivative_of_device_residual():
         errs.append(rel_l2(fd[free], kv[free]))
     print(f"[q4_48cube_fd] rel {errs[0]:.2e} (step 4e-6), {errs[1]:.2e} (step 1e-6)", flush=True)
     assert errs[1] <= 0.1 * errs[0] and errs[1] <= 5e-8
+    P.close()
+
+
+def test_q2_64cube_sampled_rows():
+    """The finest level of the Newton benchmark at its real size (64^3 Q2,
+    6,440,067 DoFs, 20 spheres, bottom and top clamped) on sampled rows:
+    cached-F^-1 vmult FP64 to 1e-12 of the largest entry, FP32 to 1e-5,
+    residual to 1e-12."""
+    w = W.problem(3, 64, 2, n_spheres=20, sphere_seed=3, u_seed=4, u_amp=0.1, u_kmax=1, x_seed=5, mask=CLAMP3)
+    mesh, mat, cons = oracle_problem(w)
+    rng = np.random.default_rng(23)
+    L = mesh.L
+    node = lambda i, j, k: i + L * (j + L * k)
+    extra = [node(2, 2, 2), node(64, 63, 1), node(128, 128, 64), node(7, 0, 0), node(0, 5, 128)]
+    rows = np.unique(np.concatenate([rng.choice(mesh.n_dofs, 100, replace=False), extra,
+                                     [mesh.n_nodes + e for e in extra], [2 * mesh.n_nodes + e for e in extra]]))
+    log_case("q2_64cube_rows", n_dofs=mesh.n_dofs)
+    ref = fe.vmult_rows(mesh, mat, w["u"], w["x"], rows, constrained=cons)
+    ref32 = fe.vmult_rows(mesh, mat, w["u"], w["x"].astype(np.float32).astype(np.float64), rows, constrained=cons)
+    rres = fe.residual_rows(mesh, mat, w["u"], rows, constrained=cons)
+    P = device_problem(w, qp_policy=2)
+    P.set_deformation(dev(w["u"]))
+    y = host(P.tangent_vmult(dev(w["x"])))
+    err = np.abs(y[rows] - ref).max() / np.abs(ref).max()
+    y32 = host(P.tangent_vmult(dev(w["x"].astype(np.float32), torch.float32)))
+    err32 = np.linalg.norm(y32[rows] - ref32) / np.linalg.norm(ref32)
+    r = host(P.residual(dev(w["u"])))
+    errr = np.abs(r[rows] - rres).max() / np.abs(rres).max()
+    print(f"[q2_64cube_rows] fp64 {err:.2e} fp32 {err32:.2e} residual {errr:.2e}", flush=True)
+    assert err <= 1e-12 and err32 <= 1e-5 and errr <= 1e-12
     P.close()
