@@ -536,3 +536,30 @@ def test_newton_q2_16cube_matches_oracle_golden():
           flush=True)
     assert err <= 1e-8
     assert abs(np.linalg.norm(uh) - g["u_norm"]) <= 1e-8 * g["u_norm"]
+
+
+@pytest.mark.parametrize("n_fine,degree,n_levels,spheres,seed", [(64, 2, 5, 20, 3), (24, 4, 4, 200, 7)],
+                         ids=["q2_64cube", "q4_24cube"])
+def test_level_displacements_full_size(n_fine, degree, n_levels, spheres, seed):
+    """The benchmark hierarchies at large size (the Newton benchmark's 64^3 Q2
+    fine level with levels 4^3 .. 64^3; the 200-sphere Q4 body at 24^3 with
+    levels 3^3 .. 24^3, where the support points do not nest and every
+    coarse value is a weighted sum of fine ones; bottom and top clamped): the
+    device's level displacements (nodal interpolation, Sec. 6) agree with the
+    oracle's Kronecker-product interpolation on every level to 1e-13."""
+    from paper_1904_13131_amd import Problem
+    mask = W.clamp_bottom_top(3)
+    w = W.problem(3, n_fine, degree, n_spheres=spheres, sphere_seed=seed, u_seed=4, u_amp=0.1 if degree == 2 else 0.02,
+                  u_kmax=1, x_seed=5, mask=mask)
+    mat = fe.Material(w["mu"], w["lam"], w["inclusions"])
+    H = gmg.Hierarchy(3, n_fine >> (n_levels - 1), degree, n_levels, mat, mask)
+    log_case("level_displacements_full", n_dofs=H.meshes[-1].n_dofs, degree=degree)
+    us = H.level_displacements(w["u"])
+    P = Problem(3, n_fine, degree, n_levels=n_levels, mu=tuple(w["mu"]), lam=tuple(w["lam"]),
+                inclusions=w["inclusions"], dirichlet_mask=mask, qp_policy=2)
+    P.set_deformation(dev(w["u"]))
+    for l in range(n_levels):
+        err = rel_l2(host(P.level_displacement(l)), us[l])
+        print(f"[level_displacements_full] Q{degree} level {l}: rel {err:.2e}", flush=True)
+        assert err <= 1e-13
+    P.close()
