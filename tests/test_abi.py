@@ -184,3 +184,13 @@ def test_binding_checks_levels_faces_and_batches():
         B.tangent_vmult([ok, ok], [ok.float(), ok.float()])
     with pytest.raises(ValueError, match="entries"):
         B.cg_solve([ok, ok], [ok, torch.zeros(80, dtype=torch.float64)])
+
+
+def test_c_client_compiles_and_links(tmp_path):
+    """include/mfh.h is plain C: a C99 client (tests/c_client.c) compiles with
+    -Wall -Wextra -Werror and links against the library and the HIP runtime
+    alone (no Python, no torch)."""
+    from tests.c_client_build import build_client
+    _lib()
+    exe = build_client(str(tmp_path))
+    assert os.path.exists(exe)
