@@ -106,7 +106,8 @@ enum { MFH_LAW_NEO_HOOKE = 0, MFH_LAW_MOONEY_RIVLIN = 1 };
  * x-neighbours in one cell block already summed, and a second kernel sums
  * the remaining contributions of every node in a fixed order and writes each
  * output entry once: deterministic, no atomics, no separate output fill; the
- * workspace grows by dim * (p+1)^dim * cells of the finest level doubles).  AUTO takes, for every level and precision, the mode measured
+ * workspace grows by dim * (p+1)^dim * cells of the finest level doubles).
+ * AUTO takes, for every level and precision, the mode measured
  * fastest on gfx950 for the problem's dimension, degree, qp policy and the
  * level's cell count (a table built by the package's autotuner and compiled
  * into the library).  The choice affects tangent_vmult only; all other cell
@@ -233,7 +234,8 @@ mfh_status mfh_tangent_vmult(mfh_problem* problem, int level, int dtype,
 
 /* Sizes of the CSR form of a level's constrained tangent K_c (the matrix of
  * eq. algebraic_tangent with the constraints of Sec. 3), the operator of the
- * matrix-based approach that Sec. 4 and Sec. 7.1 compare against.  n_rows = dim * nodes, DoF numbering as the vectors.
+ * matrix-based approach that Sec. 4 and Sec. 7.1 compare against.
+ * n_rows = dim * nodes, DoF numbering as the vectors.
  * A free row lists every DoF of the cells that hold its node, component-major
  * and by ascending node index within a component (constrained columns stay as
  * stored zeros); a constrained row holds its diagonal only.  Host outputs, no
